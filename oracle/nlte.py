@@ -1,0 +1,101 @@
+"""Two-level-atom Lambda iteration on the oracle side (FP64, numpy + the C sweep).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Follows Sect. 2.1: the line source function of a two-level atom under complete
+redistribution is S_L = (1 - eps) Jbar + eps B (Eq. 3 with the profile-weighted
+mean intensity Jbar), J = Lambda[S] is one formal solution over all rays (Eq.
+4), and the plain Lambda iteration alternates the two until the largest
+relative change of S_L drops below a tolerance (about 1e-3, Sect. 3.3).
+
+With a grey continuum of opacity chi_c and thermal source B beside the line of
+opacity chi_L phi_lambda, the total opacity and source at each wavelength are
+chi = chi_c + chi_L phi and S = (chi_L phi S_L + chi_c B) / chi. The profile
+weights satisfy sum_lambda wlam * phi = 1 at every site (the caller normalises
+them), so S_L = B is an exact fixed point of an isothermal, thermalised box.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from . import fs_voronoi
+
+
+def assemble(chi_c, chi_L, phi, B, S_L):
+    """Total opacity and source [n, nl] from the continuum and the line (Sect. 2.1, Eq. 3)."""
+    chi = chi_c[:, None] + chi_L[:, None] * phi
+    S = (chi_L[:, None] * phi * S_L[:, None] + chi_c[:, None] * B[:, None]) / chi
+    return chi, S
+
+
+def jbar(phi, wlam, J):
+    """Profile-weighted mean intensity sum_lambda wlam phi J."""
+    return np.sum(wlam[None, :] * phi * J, axis=1)
+
+
+def lambda_step(grid, dirs, ray_w, sel, chi_c, chi_L, phi, wlam, B, eps, S_L, I_top=None):
+    """One Lambda iteration: returns (S_L new, max relative change)."""
+    chi, S = assemble(chi_c, chi_L, phi, B, S_L)
+    nl = phi.shape[1]
+    Ib = np.repeat(B[:, None], nl, axis=1)
+    It = None if I_top is None else np.repeat(np.asarray(I_top)[:, None], nl, axis=1)
+    J = fs_voronoi(grid, dirs, ray_w, sel, chi, S, Ib, I_top=It)
+    S_new = (1.0 - eps) * jbar(phi, wlam, J) + eps * B
+    dS = float(np.max(np.abs(S_new - S_L) / np.abs(S_L)))
+    return S_new, dS
+
+
+def lambda_iterate(grid, dirs, ray_w, sel, chi_c, chi_L, phi, wlam, B, eps, max_iter=1000, tol=1e-3,
+                   S_start=None, I_top=None):
+    """Plain Lambda iteration from S_L = B (or ``S_start``) until max dS/S < tol.
+
+    Returns (S_L, history of dS, number of iterations done, converged flag).
+    """
+    S_L = np.array(B if S_start is None else S_start, dtype=np.float64)
+    hist = []
+    for it in range(max_iter):
+        S_L, dS = lambda_step(grid, dirs, ray_w, sel, chi_c, chi_L, phi, wlam, B, eps, S_L, I_top)
+        hist.append(dS)
+        if not np.isfinite(dS):
+            raise FloatingPointError("non-finite source-function change")
+        if dS < tol:
+            return S_L, np.array(hist), it + 1, True
+    return S_L, np.array(hist), max_iter, False
+
+
+def dense_fixed_point(grid, dirs, ray_w, sel, chi_c, chi_L, phi, wlam, B, eps, I_top=None, groups=None):
+    """Fixed point of the Lambda iteration by a dense linear solve.
+
+    For fixed opacities Jbar is affine in S_L: Jbar = M S_L + c. c is Jbar at
+    S_L = 0, column j of M is Jbar(e_j) - c (one formal solution per column).
+    ``groups`` (optional list of index arrays) ties sites that share one
+    unknown, e.g. the sites of one plane of a horizontally uniform column.
+    Solves (1 - (1 - eps) M) S = (1 - eps) c + eps B.
+    """
+    n = grid.n
+    nl = phi.shape[1]
+    Ib = np.repeat(B[:, None], nl, axis=1)
+    It = None if I_top is None else np.repeat(np.asarray(I_top)[:, None], nl, axis=1)
+
+    def jb(S_L):
+        chi, S = assemble(chi_c, chi_L, phi, B, S_L)
+        return jbar(phi, wlam, fs_voronoi(grid, dirs, ray_w, sel, chi, S, Ib, I_top=It))
+
+    if groups is None:
+        groups = [np.array([i]) for i in range(n)]
+    m = len(groups)
+    c = jb(np.zeros(n))
+    M = np.empty((m, m))
+    rep = np.array([g[0] for g in groups])
+    for j, gidx in enumerate(groups):
+        e = np.zeros(n)
+        e[gidx] = 1.0
+        M[:, j] = (jb(e) - c)[rep]
+    A = np.eye(m) - (1.0 - eps) * M
+    rhs = (1.0 - eps) * c[rep] + eps * B[rep]
+    sol = np.linalg.solve(A, rhs)
+    S = np.empty(n)
+    for j, gidx in enumerate(groups):
+        S[gidx] = sol[j]
+    return S

@@ -1,0 +1,200 @@
+"""Input generators: quadrature, atmosphere recipe, Voronoi neighbour lists and lattices.
+
+The Voronoi adjacency is pinned by an independent brute-force definition (a
+linear programme per site pair: do the two cells share a face of positive area
+inside the box?), by the mean degree of Poisson-Voronoi cells, 2 + 48 pi^2/35
+= 15.5355 (the paper quotes 15.54, Sect. 2.5), and by exact lattice results.
+"""
+
+import numpy as np
+import pytest
+from scipy.integrate import quad
+from scipy.optimize import linprog
+
+import synth
+from synth.atmosphere import MM, KM
+
+
+def test_quadrature_moments():
+    dirs, w = synth.gauss_legendre_quadrature()
+    assert dirs.shape == (24, 3)
+    assert abs(w.sum() - 1.0) < 1e-15
+    assert np.allclose(np.linalg.norm(dirs, axis=1), 1.0, atol=1e-15)
+    # GL(3) on [0,1] integrates mu^2 exactly: angle mean of mu^2 is 1/3
+    assert abs(np.sum(w * dirs[:, 2] ** 2) - 1.0 / 3.0) < 1e-15
+    assert np.allclose(np.sum(w[:, None] * dirs, axis=0), 0.0, atol=1e-15)
+    mus = np.unique(np.round(np.abs(dirs[:, 2]), 12))
+    assert np.allclose(mus, [0.5 - np.sqrt(0.15), 0.5, 0.5 + np.sqrt(0.15)], atol=1e-12)
+    # no ray along the x or y axis
+    assert np.all(np.abs(dirs[:, 0]) > 0.1) and np.all(np.abs(dirs[:, 1]) > 0.1)
+
+
+def test_temperature_and_density_recipe():
+    assert abs(synth.T0_of_z(-0.5 * MM) - 6500.0) < 1.0
+    assert abs(synth.T0_of_z(0.5 * MM) - 4241.0) < 1.0
+    assert abs(synth.T0_of_z(2.5 * MM) - 4200.0) < 1e-9
+    assert abs(synth.rho_of_z(0.0) - 3e-4) < 1e-18
+    assert abs(synth.rho_of_z(150 * KM) - 3e-4 / np.e) < 1e-15
+
+
+def test_kappa0_normalises_tau_to_one_at_z0():
+    kappa0, _, _ = synth.kappa0_and_density()
+    box = synth.BoxSpec()
+
+    def g(z):
+        return kappa0 * synth.rho_of_z(z) ** 2 * synth.T0_of_z(z) ** 9
+
+    inside, _ = quad(g, 0.0, box.hi[2], limit=400, epsabs=0, epsrel=1e-12)
+    tail = g(box.hi[2]) * 150 * KM / 2.0
+    assert abs(inside + tail - 1.0) < 1e-7
+    # chi(0) of the recipe
+    assert 1.5e-5 < g(0.0) < 1.8e-5
+
+
+def test_horizontal_field_statistics():
+    f = synth.horizontal_field(3)
+    assert abs(f.mean()) < 1e-12 and abs(f.std() - 1.0) < 1e-12
+    # correlation at one correlation length ~ exp(-1/2) (loose: finite box)
+    lag = int(round(256 / 6.0))
+    c = np.mean(f * np.roll(f, lag, axis=0))
+    assert 0.35 < c < 0.85
+
+
+def test_rejection_sampling_follows_target_density():
+    _, zt, ft = synth.kappa0_and_density()
+    xyz = synth.sample_sites(200000, seed=5)
+    box = synth.BoxSpec()
+    assert np.all(xyz >= np.asarray(box.lo)) and np.all(xyz <= np.asarray(box.hi))
+    hist, edges = np.histogram(xyz[:, 2], bins=30, range=(box.lo[2], box.hi[2]))
+    mids = 0.5 * (edges[1:] + edges[:-1])
+    expect = np.interp(mids, zt, ft)
+    expect = expect / expect.sum() * hist.sum()
+    chi2 = np.sum((hist - expect) ** 2 / expect)
+    assert chi2 < 80  # 29 dof
+
+
+def _face_lp(P, i, k_img, others, lo, hi, clip_xy):
+    """Largest slack t with a point x on the bisector of P[i] and k_img, strictly
+    closer to both than to every point in ``others`` and inside the box by t."""
+    a = P[i]
+    b = k_img
+    A_ub, b_ub = [], []
+    for c in others:
+        A_ub.append(np.r_[2 * (c - a), 1.0])
+        b_ub.append(c @ c - a @ a)
+    dims = [0, 1, 2] if clip_xy else [2]
+    for d in dims:
+        e = np.zeros(4); e[d] = -1; e[3] = 1; A_ub.append(e); b_ub.append(-lo[d])
+        e = np.zeros(4); e[d] = 1; e[3] = 1; A_ub.append(e); b_ub.append(hi[d])
+    A_eq = [np.r_[2 * (b - a), 0.0]]
+    b_eq = [b @ b - a @ a]
+    res = linprog(c=[0, 0, 0, -1], A_ub=np.array(A_ub), b_ub=np.array(b_ub), A_eq=np.array(A_eq),
+                  b_eq=np.array(b_eq), bounds=[(None, None)] * 3 + [(None, 1.0)], method="highs")
+    return -res.fun if res.status == 0 else -np.inf
+
+
+def _wall_lp(P, i, others, lo, hi, zwall, clip_xy):
+    """Largest slack t with a point of cell i on the plane z = zwall."""
+    a = P[i]
+    A_ub, b_ub = [], []
+    for c in others:
+        A_ub.append(np.r_[2 * (c - a), 1.0])
+        b_ub.append(c @ c - a @ a)
+    if clip_xy:
+        for d in (0, 1):
+            e = np.zeros(4); e[d] = -1; e[3] = 1; A_ub.append(e); b_ub.append(-lo[d])
+            e = np.zeros(4); e[d] = 1; e[3] = 1; A_ub.append(e); b_ub.append(hi[d])
+    A_eq = [np.array([0, 0, 1.0, 0])]
+    res = linprog(c=[0, 0, 0, -1], A_ub=np.array(A_ub), b_ub=np.array(b_ub), A_eq=np.array(A_eq),
+                  b_eq=[zwall], bounds=[(None, None)] * 3 + [(None, 1.0)], method="highs")
+    return -res.fun if res.status == 0 else -np.inf
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_voronoi_adjacency_brute_force(periodic):
+    rng = np.random.default_rng(11 + periodic)
+    n = 24 if periodic else 40
+    lo = np.zeros(3)
+    hi = np.array([1.0, 1.2, 0.9])
+    P = lo + rng.random((n, 3)) * (hi - lo)
+    g = synth.voronoi_neighbours(P, lo, hi, periodic_xy=periodic, margin_spacings=10.0)
+    assert synth.check_symmetric(g)
+    L = hi - lo
+    shifts = [(sx, sy) for sx in (-1, 0, 1) for sy in (-1, 0, 1)] if periodic else [(0, 0)]
+    imgs = {s: P + np.array([s[0] * L[0], s[1] * L[1], 0.0]) for s in shifts}
+    got = set()
+    for i in range(n):
+        for e in range(g.nbr_ptr[i], g.nbr_ptr[i + 1]):
+            got.add((i, int(g.nbr_idx[e]), int(g.nbr_shift[e, 0]), int(g.nbr_shift[e, 1])))
+    want = set()
+    for i in range(n):
+        for s in shifts:
+            for k in range(n):
+                if k == i and s == (0, 0):
+                    continue
+                others = [imgs[t][j] for t in shifts for j in range(n) if not (t == s and j == k)
+                          and not (t == (0, 0) and j == i)]
+                if _face_lp(P, i, imgs[s][k], others, lo, hi, clip_xy=not periodic) > 1e-9:
+                    want.add((i, k, s[0], s[1]))
+    assert got == want
+    for i in range(n):
+        others = [imgs[t][j] for t in shifts for j in range(n) if not (t == (0, 0) and j == i)]
+        bot = _wall_lp(P, i, others, lo, hi, lo[2], clip_xy=not periodic) > 1e-9
+        top = _wall_lp(P, i, others, lo, hi, hi[2], clip_xy=not periodic) > 1e-9
+        assert bool(g.wall[i] & 1) == bot and bool(g.wall[i] & 2) == top, i
+
+
+def test_voronoi_adjacency_does_not_depend_on_margin():
+    atm = synth.make_atmosphere(3000, seed=17)
+    g1 = synth.voronoi_neighbours(atm.xyz, atm.box.lo, atm.box.hi, margin_spacings=4.0)
+    g2 = synth.voronoi_neighbours(atm.xyz, atm.box.lo, atm.box.hi, margin_spacings=8.0)
+    assert np.array_equal(g1.nbr_ptr, g2.nbr_ptr)
+    assert np.array_equal(g1.nbr_idx, g2.nbr_idx)
+    assert np.array_equal(g1.nbr_shift, g2.nbr_shift)
+    assert np.array_equal(g1.wall, g2.wall)
+
+
+def test_poisson_voronoi_mean_degree():
+    # interior cells of a uniform random box: theory 2 + 48 pi^2 / 35 (paper: 15.54)
+    rng = np.random.default_rng(2)
+    P = rng.random((30000, 3))
+    g = synth.voronoi_neighbours(P, [0, 0, 0], [1, 1, 1])
+    far = (P[:, 2] > 0.2) & (P[:, 2] < 0.8)
+    deg = g.degrees()[far]
+    theory = 2.0 + 48.0 * np.pi**2 / 35.0
+    assert abs(theory - 15.5355) < 1e-4
+    sem = deg.std() / np.sqrt(len(deg))
+    assert abs(deg.mean() - theory) < 4 * sem
+
+
+def test_recipe_grid_degree_and_walls():
+    atm = synth.make_atmosphere(16384, seed=1041)
+    g = synth.voronoi_neighbours(atm.xyz, atm.box.lo, atm.box.hi)
+    assert synth.check_symmetric(g)
+    assert 14.8 < g.m / g.n < 15.5
+    assert 700 < np.count_nonzero(g.wall & 1) < 1100
+    assert 700 < np.count_nonzero(g.wall & 2) < 1100
+    # every non-wall cell has a neighbour strictly below and strictly above
+    src = np.repeat(np.arange(g.n), np.diff(g.nbr_ptr))
+    dz = g.xyz[src, 2] - g.xyz[g.nbr_idx, 2]
+    has_below = np.zeros(g.n, bool); has_below[src[dz > 0]] = True
+    has_above = np.zeros(g.n, bool); has_above[src[dz < 0]] = True
+    assert np.all(has_below | (g.wall & 1 > 0))
+    assert np.all(has_above | (g.wall & 2 > 0))
+
+
+def test_lattice_neighbours():
+    z = np.array([0.0, 0.3, 1.0, 1.1, 2.0])
+    g = synth.lattice_grid(4, 3, z, dx=0.5, dy=0.7)
+    assert synth.check_symmetric(g)
+    deg = g.degrees()
+    nz = len(z)
+    iz = np.arange(g.n) // 12
+    assert np.all(deg[(iz > 0) & (iz < nz - 1)] == 6)
+    assert np.all(deg[(iz == 0) | (iz == nz - 1)] == 5)
+    assert np.all((g.wall & 1) == (iz == 0))
+    assert np.all(((g.wall >> 1) & 1) == (iz == nz - 1))
+    # a 2-wide periodic direction gives the same neighbour twice with different shifts
+    g2 = synth.lattice_grid(2, 2, z)
+    assert synth.check_symmetric(g2)
+    assert np.all(g2.degrees()[6:14] == 6)

@@ -1,0 +1,214 @@
+"""Benchmark: site*ray*wavelength updates per second of the formal solution on a
+262,144-site Voronoi grid (64 wavelengths 400-900 nm, 24 rays), one GPU.
+
+One step = grey LTE source assembly (chi = kappa0 rho^2 T^9, S = B_lambda(T))
++ the FP32 formal solution of all 24 rays, level step by level step, captured
+in a HIP graph + the angle quadrature of J (double accumulation) + the
+emergent-intensity gather. Inputs (T, rho) are resident on the GPU before the
+timed region. The grid, its quadrature and the per-ray schedules are built
+once, outside the timed region.
+
+Printed as one JSON line with, besides the headline value:
+  roofline     the sweep kernel's algorithmic bytes per launch over its mean
+               launch time (HIP events on the library's stream), vs 8 TB/s;
+  fp64_plain   the plain FP64 GPU path (one launch per ray and level) and the
+               FP32-batched speed-up over it;
+  cpu_baseline the FP64 CPU oracle timed on this host on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--sites N] [--no-cpu]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def sweep_bytes_per_update(nl: int, fp: int) -> float:
+    """Algorithmic HBM bytes of the sweep kernel per site*ray*wavelength update:
+    read S_i and chi_i, write I_i (3 * fp bytes), plus the per-(ray, site) sweep
+    record (16 B of indices + 4 * fp bytes of weights and lengths) shared by
+    the nl wavelengths. Upwind gathers are not counted (served on chip in the
+    ideal streaming model)."""
+    return 3.0 * fp + (16.0 + 4.0 * fp) / nl
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--sites", type=int, default=262144)
+    ap.add_argument("--nl", type=int, default=64)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    import paper_2306_01041_amd
+    import synth
+
+    v = paper_2306_01041_amd.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = "cuda:0"
+    seed = 1041
+    nl = args.nl
+    lam = np.linspace(400e-9, 900e-9, nl)
+
+    t0 = time.time()
+    atm = synth.make_atmosphere(args.sites, seed=seed)
+    g = synth.voronoi_neighbours(atm.xyz, atm.box.lo, atm.box.hi)
+    dirs, w = synth.gauss_legendre_quadrature()
+    R = len(dirs)
+    log(f"grid {g.n} sites, {g.m / g.n:.2f} neighbours/site, built in {time.time() - t0:.1f} s")
+
+    ctx = v.Context(0)
+    stream = torch.cuda.current_stream()
+    G = v.Grid.from_synth(ctx, g)
+    t0 = time.time()
+    G.set_rays(dirs, w, 7.0)
+    info = G.info()
+    setup_s = time.time() - t0
+    log(f"rays set in {setup_s:.2f} s: {info}")
+
+    T = torch.as_tensor(atm.T, device=dev)
+    rho = torch.as_tensor(atm.rho, device=dev)
+    f32 = torch.float32
+    chi = torch.empty((g.n, nl), dtype=f32, device=dev)
+    S = torch.empty_like(chi)
+    J = torch.empty_like(chi)
+    off, _ = G.emergent_index()
+    em = torch.empty((int(off[-1]), nl), dtype=f32, device=dev)
+
+    def step():
+        v.lte_continuum(G, lam, atm.kappa0, T, rho, chi, S)
+        v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_GRAPH)
+        v.emergent_gather(G, em)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("warm-up done")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    updates = g.n * R * nl
+    value = updates / (ms_step * 1e-3)
+    log(f"FP32 graph step {ms_step:.3f} ms -> {value:.3e} updates/s")
+
+    # roofline of the dominant kernel: eager batched launches with HIP events on the library's stream
+    ctx.profile_reset()
+    ctx.set_profiling(True)
+    nprof = 3
+    for _ in range(nprof):
+        v.lte_continuum(G, lam, atm.kappa0, T, rho, chi, S)
+        v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_BATCHED)
+    sw_ms, sw_launches, sw_units = ctx.profile(0)
+    jr_ms, jr_launches, jr_units = ctx.profile(1)
+    ctx.set_profiling(False)
+    torch.cuda.synchronize()
+    bpu = sweep_bytes_per_update(nl, 4)
+    avg_launch_ms = sw_ms / sw_launches
+    bytes_per_launch = bpu * sw_units / sw_launches
+    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+    jr_bytes = (4.0 + 4.0 / R) * jr_units  # read every ray's I once, write J once
+    log(f"sweep: {sw_launches // nprof} launches/step, mean {avg_launch_ms * 1e3:.1f} us, "
+        f"{achieved:.0f} GB/s algorithmic; J reduction {jr_ms / jr_launches:.3f} ms "
+        f"({jr_bytes / jr_launches / (jr_ms / jr_launches * 1e-3) / 1e9:.0f} GB/s)")
+
+    # plain FP64 GPU path
+    fp64 = None
+    if not args.no_fp64:
+        f64 = torch.float64
+        chi64 = torch.empty((g.n, nl), dtype=f64, device=dev)
+        S64 = torch.empty_like(chi64)
+        J64 = torch.empty_like(chi64)
+        v.lte_continuum(G, lam, atm.kappa0, T, rho, chi64, S64)
+        v.formal_solution(G, chi64, S64, J64, exec_mode=v.VRT_EXEC_PLAIN)
+        torch.cuda.synchronize()
+        k64 = 3
+        t0 = time.perf_counter()
+        for _ in range(k64):
+            v.lte_continuum(G, lam, atm.kappa0, T, rho, chi64, S64)
+            v.formal_solution(G, chi64, S64, J64, exec_mode=v.VRT_EXEC_PLAIN)
+        torch.cuda.synchronize()
+        ms64 = (time.perf_counter() - t0) * 1e3 / k64
+        # error of the FP32 path against the FP64 GPU path on this workload
+        jerr = float(((J.double() - J64).abs() / J64.abs()).max().item())
+        fp64 = {"ms_per_step": round(ms64, 3), "value": updates / (ms64 * 1e-3),
+                "speedup_fp32_batched": round(ms64 / ms_step, 2), "fp32_vs_fp64_max_rel_err_J": jerr}
+        log(f"FP64 plain step {ms64:.2f} ms; FP32 graph speed-up {ms64 / ms_step:.1f}x; FP32 J err {jerr:.2e}")
+        del chi64, S64, J64
+
+    # CPU oracle on a bounded sample: all sites and rays, every other wavelength
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+
+        lam_s = lam[::2]
+        chi_o, S_o = oracle.lte(lam_s, atm.kappa0, atm.T, atm.rho)
+        sel = oracle.select(g, dirs)
+        t0 = time.perf_counter()
+        oracle.fs_voronoi(g, dirs, w, sel, chi_o, S_o, S_o)
+        dt = time.perf_counter() - t0
+        cpu = {"value": g.n * R * len(lam_s) / dt, "unit": "site*ray*lambda updates/s",
+               "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"one FP64 formal solution: {g.n} sites x {R} rays x {len(lam_s)} of the {nl} "
+                         f"wavelengths ({dt:.1f} s)"}
+        log(f"CPU oracle {cpu['value']:.3e} updates/s on {cpu['cores']} threads")
+
+    out = {
+        "metric": "site*ray*lambda updates/s, FP32 batched formal solution (vs FP64 plain) + %HBM roofline",
+        "value": value,
+        "unit": "site*ray*lambda updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded Bifrost-like stratified atmosphere, rejection-sampled Voronoi sites)",
+        "config": {"workload": f"LTE continuum formal solution, Voronoi grid {g.n} sites, {nl} wavelengths "
+                               f"400-900 nm, {R} rays, FP32 sweeps with FP64 J accumulation",
+                   "sites": g.n, "rays": R, "wavelengths": nl, "levels_max": info["max_levels"],
+                   "launches_per_step": sw_launches // nprof + 1},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "sweep_kernel<float,64>", "bytes_per_update": round(bpu, 4),
+                     "mean_launch_us": round(avg_launch_ms * 1e3, 2)},
+        "whole_step_effective_GBs": round(updates * (20.0 + 20.0 / nl) / (ms_step * 1e-3) / 1e9, 1),
+        "fp64_plain": fp64,
+        "cpu_baseline": cpu,
+        "setup_s": round(setup_s, 3),
+    }
+    print(json.dumps(out))
+    G.close()
+    ctx.close()
+    del stream
+
+
+if __name__ == "__main__":
+    main()

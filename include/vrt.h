@@ -1,0 +1,212 @@
+/*
+ * vrt.h -- C ABI of the MI355X (gfx950) formal-solution library.
+ *
+ * The library solves the time-independent radiative transfer equation
+ * dI/dtau = S - I along every ray of a fixed angle quadrature, on an
+ * irregular (Voronoi) grid or on a regular grid, and integrates the
+ * intensities over angle to the mean intensity J (Udnaes & Pereira 2023,
+ * Sect. 2.1, Eq. 1, 2 and 4). On a Voronoi grid the intensity at a site is
+ * carried along the two Delaunay lines closest to the ray direction and
+ * weighted by w_j = v_j^r / (v_1^r + v_2^r) (Sect. 2.5, Eq. 5 and 6); along
+ * each line the source function is taken as linear (Sect. 2.5). On a regular
+ * grid short characteristics with bilinear interpolation in the upwind
+ * horizontal plane are used (Sect. 2.6). A two-level-atom Lambda iteration,
+ * S_L = (1 - eps) Jbar + eps B (Sect. 2.1, Eq. 3), runs on top.
+ *
+ * Conventions shared by every entry point:
+ *   - Status codes: every function returns vrt_status (0 = success, 1 = a
+ *     warning with valid outputs, negative = error). No C++ exception crosses
+ *     the ABI. After an error, vrt_ctx_last_error() returns a message that
+ *     stays valid until the next call on the same context.
+ *   - Host vs device pointers: arguments documented "host" are read or written
+ *     by the CPU before the call returns. Arguments documented "device" are
+ *     HIP device allocations (for instance torch tensors on the context's
+ *     GPU); the library only enqueues work on the context's stream, so the
+ *     caller must keep them alive until that stream has completed.
+ *   - Layout: per-(site, wavelength) arrays are C-contiguous [site][lambda]
+ *     with lambda fastest, in the caller's site order. Per-ray intensities are
+ *     [ray][site][lambda]. Sizes are int64, indices int32 (n < 2^31).
+ *   - Precision: VRT_F64 arrays are double, VRT_F32 arrays are float.
+ *   - Ownership: the caller owns every buffer it passes; host geometry is
+ *     copied when a grid is created. A context owns its grids' schedules,
+ *     scratch memory and captured HIP graphs; destroying a grid or the
+ *     context frees them. One context must not be used from two host threads
+ *     at once; separate contexts are independent.
+ */
+#ifndef VRT_H
+#define VRT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t vrt_status;
+
+#define VRT_OK 0
+#define VRT_W_NOT_CONVERGED 1 /* iteration cap reached; outputs valid */
+#define VRT_E_ARG (-1)        /* null pointer, bad size or bad enum */
+#define VRT_E_GRID (-2)       /* malformed neighbour lists, walls or geometry */
+#define VRT_E_DAG (-3)        /* the upwind graph of a ray is not acyclic */
+#define VRT_E_HIP (-4)        /* a HIP runtime call failed */
+#define VRT_E_NOMEM (-5)      /* device or host allocation failed */
+#define VRT_E_NUMERIC (-6)    /* NaN, Inf or negative opacity; NaN source change */
+#define VRT_E_STATE (-7)      /* call out of order (e.g. no rays set yet) */
+
+typedef enum { VRT_F64 = 0, VRT_F32 = 1 } vrt_prec;
+
+/* How a formal solution is launched.
+ * PLAIN:   one kernel per (ray, level) of the upwind schedule, rays in turn.
+ * BATCHED: one kernel per level step with all rays in flight together.
+ * GRAPH:   BATCHED, captured once into a HIP graph and replayed. */
+typedef enum { VRT_EXEC_PLAIN = 0, VRT_EXEC_BATCHED = 1, VRT_EXEC_GRAPH = 2 } vrt_exec;
+
+typedef struct vrt_ctx_s *vrt_ctx;
+typedef struct vrt_grid_s *vrt_grid;
+
+/* Library version string (static storage). */
+const char *vrt_version(void);
+
+/* Human-readable name of a status code (static storage). */
+const char *vrt_status_string(vrt_status s);
+
+/* Host-only check of Voronoi grid geometry (Sect. 2.4: cells, neighbours,
+ * Delaunay lines). Checks that nbr_ptr is non-decreasing from 0 to m, that
+ * every neighbour index is in [0, n), that shifts are in {-1, 0, 1} (and 0 when
+ * not periodic), that no site is its own neighbour with a zero shift, that the
+ * lists are symmetric (i -> (k, s) implies k -> (i, -s)), that wall flags use
+ * only bits 0 and 1, and that sites lie inside [lo, hi]. Runs no GPU code.
+ * msg (host, may be NULL) receives up to msg_len bytes describing the first
+ * problem found. Returns VRT_OK or VRT_E_GRID / VRT_E_ARG. */
+vrt_status vrt_validate_voronoi(int64_t n, const double *xyz, const int64_t *nbr_ptr,
+                                const int32_t *nbr_idx, const int8_t *nbr_shift,
+                                const uint8_t *wall, const double lo[3], const double hi[3],
+                                uint32_t periodic_xy, char *msg, int64_t msg_len);
+
+/* Create a context on HIP device `device`, enqueuing on `stream` (a
+ * hipStream_t; NULL = the device's null stream). */
+vrt_status vrt_ctx_create(int32_t device, void *stream, vrt_ctx *out);
+void vrt_ctx_destroy(vrt_ctx ctx);
+const char *vrt_ctx_last_error(vrt_ctx ctx);
+/* Switch the stream later calls enqueue on (drops captured graphs). */
+vrt_status vrt_ctx_set_stream(vrt_ctx ctx, void *stream);
+/* Block until all work the context has enqueued has finished. */
+vrt_status vrt_ctx_synchronize(vrt_ctx ctx);
+
+/* Kernel timing. While profiling is on, formal solutions launched with
+ * VRT_EXEC_PLAIN or VRT_EXEC_BATCHED record a pair of HIP events on the
+ * context stream around every kernel (graph replays are not instrumented).
+ * vrt_ctx_profile() waits for the recorded events and returns the totals of
+ * one kernel class since the last reset:
+ *   kernel 0 = Voronoi sweep, 1 = angle quadrature of J, 2 = regular-grid sweep;
+ *   ms = summed kernel time, launches = number of launches, units = summed
+ *   site * ray * wavelength updates (for kernel 1: site * wavelength outputs
+ *   times rays). Any output pointer may be NULL (host). */
+vrt_status vrt_ctx_set_profiling(vrt_ctx ctx, int32_t on);
+vrt_status vrt_ctx_profile(vrt_ctx ctx, int32_t kernel, double *ms, int64_t *launches, int64_t *units);
+vrt_status vrt_ctx_profile_reset(vrt_ctx ctx);
+
+/* Voronoi grid (Sect. 2.4, 2.5). All pointers host; copied.
+ *   xyz       [n][3] site positions (m).
+ *   nbr_ptr   [n+1], nbr_idx [m]: CSR neighbour lists (Voronoi cells sharing a face).
+ *   nbr_shift [m][2] periodic image of the neighbour, in {-1,0,1}: the image of
+ *             site k adjacent to i sits at r_k + (sx*Lx, sy*Ly, 0). May be NULL
+ *             when periodic_xy is 0.
+ *   wall      [n]: bit 0 = the cell touches the bottom wall z = lo[2], bit 1 =
+ *             the top wall z = hi[2]. Sites whose cell touches the upwind wall
+ *             of a ray are that ray's boundary sites (rays start at the bottom
+ *             or top boundary, Sect. 2.5).
+ *   lo, hi    box corners; the periods are Lx = hi[0]-lo[0], Ly = hi[1]-lo[1].
+ * Runs vrt_validate_voronoi first and returns its status on failure. */
+vrt_status vrt_grid_create_voronoi(vrt_ctx ctx, int64_t n, const double *xyz,
+                                   const int64_t *nbr_ptr, const int32_t *nbr_idx,
+                                   const int8_t *nbr_shift, const uint8_t *wall,
+                                   const double lo[3], const double hi[3], uint32_t periodic_xy,
+                                   vrt_grid *out);
+
+/* Regular grid for short characteristics (Sect. 2.6). Points (i*dx, j*dy,
+ * z[k]), periodic in x and y with periods nx*dx and ny*dy; z (host [nz]) is
+ * strictly increasing. Site index = (k*ny + j)*nx + i. */
+vrt_status vrt_grid_create_regular(vrt_ctx ctx, int32_t nx, int32_t ny, int32_t nz, double dx,
+                                   double dy, const double *z, vrt_grid *out);
+
+void vrt_grid_destroy(vrt_grid grid);
+
+/* Set the angle quadrature (Sect. 2.5: a fixed quadrature of directions).
+ *   dir [n_rays][3] unit vectors (host), none horizontal; w [n_rays] weights
+ *   (host), positive, summing to 1 within 1e-12, so J = sum_r w_r I_r.
+ *   r_exp: exponent r of the line weights (Eq. 6); the paper uses 7.
+ * On a Voronoi grid this selects, on the GPU, the two upwind Delaunay lines of
+ * every (ray, site) (Eq. 5-6), builds each ray's level schedule (a site's
+ * level is one more than the largest level of the sites it reads from;
+ * boundary sites have level 0), orders sites by (level, index) and packs the
+ * per-(ray, site) records in sweep order. Blocks until done. Returns
+ * VRT_E_GRID if a non-boundary site has no neighbour upwind in height,
+ * VRT_E_DAG if a schedule does not close. */
+vrt_status vrt_grid_set_rays(vrt_grid grid, int32_t n_rays, const double *dir, const double *w,
+                             double r_exp);
+
+/* Sizes of a grid: number of sites, rays, the largest level count over rays
+ * (number of planes on a regular grid) and the number of (ray, site) pairs
+ * that fell back to the best z-upwind line because no neighbour lay ahead of
+ * the ray. Any output pointer may be NULL (host). */
+vrt_status vrt_grid_info(vrt_grid grid, int64_t *n_sites, int32_t *n_rays, int32_t *max_levels,
+                         int64_t *n_fallback);
+
+/* Copy one ray's upwind selection and schedule to the host (all [n] unless
+ * stated; any pointer may be NULL):
+ *   k1, k2   chosen upwind sites (-1 = none; both -1 at boundary sites),
+ *   w1       weight of k1 (k2 gets 1 - w1), ds1, ds2 Delaunay line lengths,
+ *   level    level of each site, order sites sorted by (level, index),
+ *   level_ptr [n_levels + 1] first position of each level in order,
+ *   n_levels number of levels. Voronoi grids only. Blocks. */
+vrt_status vrt_grid_schedule(vrt_grid grid, int32_t ray, int32_t *k1, int32_t *k2, double *w1,
+                             double *ds1, double *ds2, int32_t *level, int32_t *order,
+                             int32_t *level_ptr, int32_t *n_levels);
+
+/* Grey LTE continuum (Sect. 2.1 with S = B; opacity recipe of the synthetic
+ * atmosphere): chi = kappa0 * rho^2 * T^9 at every wavelength and
+ * S = B_lambda(T), the Planck function in kW m^-2 nm^-1 sr^-1.
+ *   lambda_m (host [n_lambda]) wavelengths in metres; T, rho (device [n],
+ *   double); chi, S (device [n][n_lambda], prec). Enqueued, not blocking. */
+vrt_status vrt_lte_continuum(vrt_grid grid, vrt_prec prec, int32_t n_lambda,
+                             const double *lambda_m, double kappa0, const double *T,
+                             const double *rho, void *chi, void *S);
+
+/* Formal solution for every ray and wavelength and the mean intensity
+ * J = sum_r w_r I_r (Sect. 2.1, Eq. 2 and 4; Sect. 2.5, Eq. 5).
+ *   chi, S     device [n][n_lambda] opacity (m^-1, >= 0) and source function.
+ *   I_bottom   device [n][n_lambda] intensity entering at the bottom boundary
+ *              on upward rays; NULL = S (thermalised boundary).
+ *   I_top      device [n][n_lambda] entering at the top on downward rays;
+ *              NULL = 0.
+ *   J          device [n][n_lambda] output; accumulated in double precision.
+ *   I_rays     device [n_rays][n][n_lambda] output of every ray's intensity,
+ *              or NULL to keep it in library-owned scratch.
+ * All arrays use `prec`. Enqueued on the context stream, not blocking. With
+ * VRT_EXEC_GRAPH the launch sequence is captured on first use for each set of
+ * pointers and replayed afterwards. */
+vrt_status vrt_formal_solution(vrt_grid grid, vrt_prec prec, vrt_exec exec, int32_t n_lambda,
+                               const void *chi, const void *S, const void *I_bottom,
+                               const void *I_top, void *J, void *I_rays);
+
+/* Emergent intensities (Sect. 2.5: rays leave through the far boundary):
+ * for each ray, the sites whose cell touches the downwind z-wall (the top
+ * wall for upward rays). offsets (host [n_rays+1]) and sites (host
+ * [offsets[n_rays]]) describe the lists; either may be NULL to query sizes
+ * (offsets alone). Voronoi and regular grids. Blocks. */
+vrt_status vrt_grid_emergent_index(vrt_grid grid, int64_t *offsets, int32_t *sites);
+
+/* Gather the emergent intensities of the last formal solution into out
+ * (device [offsets[n_rays]][n_lambda], prec), ray by ray in the order of
+ * vrt_grid_emergent_index. I_rays is the array given to that formal solution,
+ * or NULL if it used library scratch. Enqueued. */
+vrt_status vrt_emergent_gather(vrt_grid grid, vrt_prec prec, int32_t n_lambda, const void *I_rays,
+                               void *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VRT_H */

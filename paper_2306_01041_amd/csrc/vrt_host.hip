@@ -1,0 +1,749 @@
+// C ABI of the formal-solution library: contexts, grids, validation, the
+// construction of per-ray sweep schedules on the GPU, and the launch
+// sequences of the formal solution (plain, batched, or captured into a HIP
+// graph). Every entry point converts internal errors into a status code and a
+// message on the context; no exception crosses the ABI.
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+
+#include "vrt_internal.h"
+
+using vrt::DevBuf;
+using vrt::Error;
+
+namespace {
+
+constexpr const char *kVersion = "vrt 0.1.0 (gfx950)";
+
+template <typename F> vrt_status guarded(vrt_ctx ctx, F &&f) {
+  try {
+    if (ctx) {
+      ctx->err.clear();
+      VRT_HIP(hipSetDevice(ctx->device));
+    }
+    return f();
+  } catch (const Error &e) {
+    if (ctx) ctx->err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    if (ctx) ctx->err = "host allocation failed";
+    return VRT_E_NOMEM;
+  } catch (const std::exception &e) {
+    if (ctx) ctx->err = e.what();
+    return VRT_E_HIP;
+  }
+}
+
+void fail(vrt_status code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+void fail(vrt_status code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  throw Error(code, buf);
+}
+
+template <typename T> void upload(DevBuf &d, const T *h, size_t count, hipStream_t s) {
+  d.alloc(count * sizeof(T));
+  if (count) VRT_HIP(hipMemcpyAsync(d.p, h, count * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+// Host-side geometry checks (reading of Sect. 2.4: a Voronoi diagram's
+// neighbour relation is symmetric and each shared face is one entry on each
+// side). Returns an empty string when the grid is well formed.
+std::string check_voronoi(int64_t n, const double *xyz, const int64_t *ptr, const int32_t *idx, const int8_t *shift,
+                          const uint8_t *wall, const double lo[3], const double hi[3], bool periodic) {
+  char buf[256];
+  if (n < 0) return "negative site count";
+  if (n > 0 && (!xyz || !ptr || !wall)) return "null xyz, nbr_ptr or wall";
+  if (n >= (int64_t(1) << 31)) return "more than 2^31 - 1 sites";
+  if (ptr && ptr[0] != 0) return "nbr_ptr[0] must be 0";
+  for (int d = 0; d < 3; ++d)
+    if (!(hi[d] > lo[d])) return "box must satisfy hi > lo in every dimension";
+  int64_t m = n > 0 ? ptr[n] : 0;
+  if (m > 0 && !idx) return "null nbr_idx";
+  if (periodic && m > 0 && !shift) return "periodic grid needs nbr_shift";
+  for (int64_t i = 0; i < n; ++i) {
+    if (ptr[i + 1] < ptr[i]) {
+      snprintf(buf, sizeof buf, "nbr_ptr decreases at site %lld", (long long)i);
+      return buf;
+    }
+    if (wall[i] & ~3u) {
+      snprintf(buf, sizeof buf, "wall flag of site %lld uses bits other than 0 and 1", (long long)i);
+      return buf;
+    }
+    for (int d = 0; d < 3; ++d) {
+      const double v = xyz[3 * i + d];
+      if (!std::isfinite(v) || v < lo[d] || v > hi[d]) {
+        snprintf(buf, sizeof buf, "site %lld lies outside the box", (long long)i);
+        return buf;
+      }
+    }
+  }
+  // per-row sorted copies of (k, sx, sy) to look up reverse entries
+  struct Ent {
+    int32_t k;
+    int8_t sx, sy;
+    bool operator<(const Ent &o) const { return std::tie(k, sx, sy) < std::tie(o.k, o.sx, o.sy); }
+    bool operator==(const Ent &o) const { return k == o.k && sx == o.sx && sy == o.sy; }
+  };
+  std::vector<Ent> ent((size_t)m);
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) {
+      const int32_t k = idx[e];
+      const int8_t sx = shift ? shift[2 * e] : 0, sy = shift ? shift[2 * e + 1] : 0;
+      if (k < 0 || k >= n) {
+        snprintf(buf, sizeof buf, "neighbour index %d of site %lld out of range", k, (long long)i);
+        return buf;
+      }
+      if (sx < -1 || sx > 1 || sy < -1 || sy > 1) {
+        snprintf(buf, sizeof buf, "shift of entry %lld not in {-1,0,1}", (long long)e);
+        return buf;
+      }
+      if (!periodic && (sx || sy)) {
+        snprintf(buf, sizeof buf, "non-zero shift on a non-periodic grid (entry %lld)", (long long)e);
+        return buf;
+      }
+      if (k == i && sx == 0 && sy == 0) {
+        snprintf(buf, sizeof buf, "site %lld lists itself without a periodic shift", (long long)i);
+        return buf;
+      }
+      ent[(size_t)e] = Ent{k, sx, sy};
+    }
+    std::sort(ent.begin() + ptr[i], ent.begin() + ptr[i + 1]);
+    if (std::adjacent_find(ent.begin() + ptr[i], ent.begin() + ptr[i + 1]) != ent.begin() + ptr[i + 1]) {
+      snprintf(buf, sizeof buf, "site %lld lists a neighbour twice", (long long)i);
+      return buf;
+    }
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) {
+      const Ent rev{(int32_t)i, (int8_t)-ent[(size_t)e].sx, (int8_t)-ent[(size_t)e].sy};
+      const int32_t k = ent[(size_t)e].k;
+      if (!std::binary_search(ent.begin() + ptr[k], ent.begin() + ptr[k + 1], rev)) {
+        snprintf(buf, sizeof buf, "neighbour lists are not symmetric: %lld lists %d but not the reverse",
+                 (long long)i, k);
+        return buf;
+      }
+    }
+  }
+  return "";
+}
+
+template <typename T> const typename vrt::RecOf<T>::type *records(vrt_grid g);
+template <> const vrt::RecF32 *records<float>(vrt_grid g) { return g->d_rf32.as<vrt::RecF32>(); }
+template <> const vrt::RecF64 *records<double>(vrt_grid g) { return g->d_rf64.as<vrt::RecF64>(); }
+
+void build_emergent_index(vrt_grid g) {
+  g->em_off.assign((size_t)g->R + 1, 0);
+  g->em_site.clear();
+  std::vector<int32_t> ray_of;
+  for (int32_t r = 0; r < g->R; ++r) {
+    const bool up = g->h_dirs[3 * r + 2] > 0.0;
+    if (g->kind == 0) {
+      const uint8_t bit = up ? 2 : 1;  // downwind wall
+      for (int64_t i = 0; i < g->n; ++i)
+        if (g->h_wall[(size_t)i] & bit) {
+          g->em_site.push_back((int32_t)i);
+          ray_of.push_back(r);
+        }
+    } else {
+      const int64_t plane = (int64_t)g->nx * g->ny;
+      const int64_t k = up ? g->nz - 1 : 0;
+      for (int64_t p = 0; p < plane; ++p) {
+        g->em_site.push_back((int32_t)(k * plane + p));
+        ray_of.push_back(r);
+      }
+    }
+    g->em_off[(size_t)r + 1] = (int64_t)g->em_site.size();
+  }
+  upload(g->d_em_site, g->em_site.data(), g->em_site.size(), g->ctx->stream);
+  upload(g->d_em_ray, ray_of.data(), ray_of.size(), g->ctx->stream);
+  VRT_HIP(hipStreamSynchronize(g->ctx->stream));
+}
+
+void set_rays_voronoi(vrt_grid g) {
+  hipStream_t s = g->ctx->stream;
+  const int64_t n = g->n;
+  const int32_t R = g->R;
+  const int64_t RN = (int64_t)R * n;
+  g->d_k1.alloc(RN * 4);
+  g->d_k2.alloc(RN * 4);
+  g->d_w1.alloc(RN * 8);
+  g->d_ds1.alloc(RN * 8);
+  g->d_ds2.alloc(RN * 8);
+  g->d_level.alloc(RN * 4);
+  g->d_order.alloc(RN * 4);
+
+  // upwind selection (Eq. 5-6)
+  DevBuf d_misc;
+  d_misc.alloc(sizeof(unsigned long long) * (size_t)R + 64 + 4 * 16);
+  auto *d_nfb = d_misc.as<unsigned long long>();
+  auto *d_bad = reinterpret_cast<int32_t *>(d_nfb + R);
+  auto *d_flags = d_bad + 4;  // 16 relaxation flags
+  VRT_HIP(hipMemsetAsync(d_nfb, 0, sizeof(unsigned long long) * (size_t)R, s));
+  const int32_t big = 0x7fffffff;
+  VRT_HIP(hipMemcpyAsync(d_bad, &big, 4, hipMemcpyHostToDevice, s));
+  const double Lx = g->periodic ? g->hi[0] - g->lo[0] : 0.0;
+  const double Ly = g->periodic ? g->hi[1] - g->lo[1] : 0.0;
+  vrt::launch_select(s, n, R, g->d_xyz.as<double>(), g->d_ptr.as<int64_t>(), g->d_idx.as<int32_t>(),
+                     g->d_shift.as<int8_t>(), g->d_wall.as<uint8_t>(), Lx, Ly, g->d_dirs.as<double>(), g->r_exp,
+                     g->d_k1.as<int32_t>(), g->d_k2.as<int32_t>(), g->d_w1.as<double>(), g->d_ds1.as<double>(),
+                     g->d_ds2.as<double>(), d_nfb, d_bad);
+  std::vector<unsigned long long> nfb((size_t)R);
+  int32_t bad = 0;
+  VRT_HIP(hipMemcpyAsync(nfb.data(), d_nfb, sizeof(unsigned long long) * (size_t)R, hipMemcpyDeviceToHost, s));
+  VRT_HIP(hipMemcpyAsync(&bad, d_bad, 4, hipMemcpyDeviceToHost, s));
+  VRT_HIP(hipStreamSynchronize(s));
+  if (bad != big)
+    fail(VRT_E_GRID, "site %d is not a boundary site of some ray but has no neighbour upwind in height", bad);
+  g->n_fallback = 0;
+  for (auto v : nfb) g->n_fallback += (int64_t)v;
+
+  // levels by monotone relaxation, 16 passes between checks
+  int32_t *level = g->d_level.as<int32_t>();
+  vrt::launch_level_fill(s, RN, level);
+  int64_t passes = 0;
+  for (;;) {
+    VRT_HIP(hipMemsetAsync(d_flags, 0, 4 * 16, s));
+    for (int b = 0; b < 16; ++b)
+      vrt::launch_level_relax(s, n, R, g->d_k1.as<int32_t>(), g->d_k2.as<int32_t>(), level, d_flags + b);
+    int32_t flags[16];
+    VRT_HIP(hipMemcpyAsync(flags, d_flags, sizeof flags, hipMemcpyDeviceToHost, s));
+    VRT_HIP(hipStreamSynchronize(s));
+    passes += 16;
+    if (flags[15] == 0) break;
+    if (passes > n + 32) fail(VRT_E_DAG, "level relaxation did not converge: the upwind graph has a cycle");
+  }
+  int32_t lmax = 0;
+  VRT_HIP(hipMemsetAsync(d_flags, 0, 4, s));
+  vrt::launch_level_max(s, RN, level, d_flags);
+  VRT_HIP(hipMemcpyAsync(&lmax, d_flags, 4, hipMemcpyDeviceToHost, s));
+  VRT_HIP(hipStreamSynchronize(s));
+  const int32_t Lmax = lmax + 1;
+
+  // stable counting sort by (level, site index)
+  const int64_t tile = 256;
+  const int64_t ntiles = (n + tile - 1) / tile;
+  DevBuf d_cnt, d_tot, d_lp, d_nl;
+  d_cnt.alloc((size_t)R * Lmax * ntiles * 4);
+  d_tot.alloc((size_t)R * Lmax * 8);
+  d_lp.alloc((size_t)R * (Lmax + 1) * 4);
+  d_nl.alloc((size_t)R * 4);
+  VRT_HIP(hipMemsetAsync(d_cnt.p, 0, (size_t)R * Lmax * ntiles * 4, s));
+  vrt::launch_level_count(s, n, R, Lmax, tile, level, d_cnt.as<int32_t>());
+  vrt::launch_level_scan(s, R, Lmax, ntiles, d_cnt.as<int32_t>(), d_tot.as<int64_t>());
+  vrt::launch_level_ptr(s, R, Lmax, d_tot.as<int64_t>(), d_lp.as<int32_t>(), d_nl.as<int32_t>());
+  vrt::launch_level_scatter(s, n, R, Lmax, tile, level, d_lp.as<int32_t>(), d_cnt.as<int32_t>(),
+                            g->d_order.as<int32_t>());
+  std::vector<int32_t> lp((size_t)R * (Lmax + 1));
+  g->n_levels.assign((size_t)R, 0);
+  VRT_HIP(hipMemcpyAsync(lp.data(), d_lp.p, lp.size() * 4, hipMemcpyDeviceToHost, s));
+  VRT_HIP(hipMemcpyAsync(g->n_levels.data(), d_nl.p, (size_t)R * 4, hipMemcpyDeviceToHost, s));
+  VRT_HIP(hipStreamSynchronize(s));
+  g->level_ptr.assign((size_t)R, {});
+  for (int32_t r = 0; r < R; ++r) {
+    const int32_t L = g->n_levels[(size_t)r];
+    g->level_ptr[(size_t)r].assign(lp.begin() + (int64_t)r * (Lmax + 1), lp.begin() + (int64_t)r * (Lmax + 1) + L + 1);
+    if (g->level_ptr[(size_t)r].back() != n) fail(VRT_E_DAG, "schedule of ray %d does not cover every site", r);
+  }
+
+  // step-major record layout: step s holds level s of ray 0, 1, ..., R-1
+  g->n_steps = n > 0 ? *std::max_element(g->n_levels.begin(), g->n_levels.end()) : 0;
+  const int32_t NS = g->n_steps;
+  g->seg_off.assign((size_t)NS * R, 0);
+  g->seg_cnt.assign((size_t)NS * R, 0);
+  g->step_ptr.assign((size_t)NS + 1, 0);
+  int64_t acc = 0;
+  for (int32_t st = 0; st < NS; ++st) {
+    g->step_ptr[(size_t)st] = acc;
+    for (int32_t r = 0; r < R; ++r) {
+      const auto &p = g->level_ptr[(size_t)r];
+      const int64_t c = st < g->n_levels[(size_t)r] ? (int64_t)p[(size_t)st + 1] - p[(size_t)st] : 0;
+      g->seg_off[(size_t)st * R + r] = acc;
+      g->seg_cnt[(size_t)st * R + r] = c;
+      acc += c;
+    }
+  }
+  g->step_ptr[(size_t)NS] = acc;
+  g->n_rec = acc;
+  DevBuf d_seg;
+  upload(d_seg, g->seg_off.data(), g->seg_off.size(), s);
+  g->d_ri.alloc((size_t)RN * sizeof(int4));
+  g->d_rf32.alloc((size_t)RN * sizeof(vrt::RecF32));
+  g->d_rf64.alloc((size_t)RN * sizeof(vrt::RecF64));
+  vrt::launch_pack(s, n, R, Lmax, g->d_order.as<int32_t>(), level, d_lp.as<int32_t>(), d_seg.as<int64_t>(),
+                   g->d_k1.as<int32_t>(), g->d_k2.as<int32_t>(), g->d_w1.as<double>(), g->d_ds1.as<double>(),
+                   g->d_ds2.as<double>(), g->d_dirs.as<double>(), g->d_ri.as<int4>(), g->d_rf32.as<vrt::RecF32>(),
+                   g->d_rf64.as<vrt::RecF64>());
+  VRT_HIP(hipStreamSynchronize(s));
+}
+
+template <typename T> T *intensity_buffer(vrt_grid g, int32_t nl, void *I_rays) {
+  if (I_rays) return static_cast<T *>(I_rays);
+  const size_t bytes = (size_t)g->R * (size_t)g->n * (size_t)nl * sizeof(T);
+  if (bytes > g->d_Iscr.bytes) {
+    g->drop_graphs();  // captured launches may point into the old scratch
+    g->d_Iscr.alloc(bytes);
+  }
+  return g->d_Iscr.as<T>();
+}
+
+// Runs one launch, bracketed by timing events when the context profiles
+// (never inside a graph capture: `timed` is false there).
+template <typename F> void timed_launch(vrt_ctx ctx, hipStream_t s, bool timed, int kernel, int64_t units, F &&launch) {
+  if (!timed) {
+    launch();
+    return;
+  }
+  vrt_ctx_s::Timed t{kernel, nullptr, nullptr, units};
+  VRT_HIP(hipEventCreate(&t.start));
+  VRT_HIP(hipEventCreate(&t.stop));
+  VRT_HIP(hipEventRecord(t.start, s));
+  launch();
+  VRT_HIP(hipEventRecord(t.stop, s));
+  ctx->pending.push_back(t);
+}
+
+template <typename T>
+void enqueue_fs(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *chi, const T *S, const T *Ib,
+                const T *It, T *J, T *I) {
+  const int32_t R = g->R;
+  const int64_t n = g->n;
+  vrt_ctx ctx = g->ctx;
+  const bool tm = ctx->profiling && ex != VRT_EXEC_GRAPH && s == ctx->stream;
+  if (g->kind == 0) {
+    const int4 *ri = g->d_ri.as<int4>();
+    const auto *rf = records<T>(g);
+    auto sweep = [&](int64_t b, int64_t c) {
+      if (c <= 0) return;
+      timed_launch(ctx, s, tm, 0, c * nl, [&] { vrt::launch_sweep<T>(s, ri, rf, b, c, nl, n, chi, S, Ib, It, I); });
+    };
+    if (ex == VRT_EXEC_PLAIN) {
+      for (int32_t r = 0; r < R; ++r)
+        for (int32_t st = 0; st < g->n_levels[(size_t)r]; ++st)
+          sweep(g->seg_off[(size_t)st * R + r], g->seg_cnt[(size_t)st * R + r]);
+    } else {
+      for (int32_t st = 0; st < g->n_steps; ++st)
+        sweep(g->step_ptr[(size_t)st], g->step_ptr[(size_t)st + 1] - g->step_ptr[(size_t)st]);
+    }
+  } else {
+    const double *z = g->d_z.as<double>(), *dirs = g->d_dirs.as<double>();
+    const int64_t plane = (int64_t)g->nx * g->ny;
+    auto planes = [&](int32_t st, int32_t rb, int32_t rc) {
+      timed_launch(ctx, s, tm, 2, plane * rc * nl, [&] {
+        vrt::launch_regular<T>(s, st, rb, rc, g->nx, g->ny, g->nz, g->dx, g->dy, z, dirs, nl, chi, S, Ib, It, I);
+      });
+    };
+    if (ex == VRT_EXEC_PLAIN) {
+      for (int32_t r = 0; r < R; ++r)
+        for (int32_t st = 0; st < g->nz; ++st) planes(st, r, 1);
+    } else {
+      for (int32_t st = 0; st < g->nz; ++st) planes(st, 0, R);
+    }
+  }
+  timed_launch(ctx, s, tm, 1, (int64_t)R * n * nl,
+               [&] { vrt::launch_jreduce<T>(s, I, R, n * nl, g->d_w.as<double>(), J); });
+}
+
+template <typename T>
+void formal_solution(vrt_grid g, vrt_exec ex, int32_t nl, const void *chi_, const void *S_, const void *Ib_,
+                     const void *It_, void *J_, void *Ir_) {
+  const T *chi = static_cast<const T *>(chi_), *S = static_cast<const T *>(S_);
+  const T *Ib = Ib_ ? static_cast<const T *>(Ib_) : S;
+  const T *It = static_cast<const T *>(It_);
+  T *J = static_cast<T *>(J_);
+  T *I = intensity_buffer<T>(g, nl, Ir_);
+  vrt_ctx ctx = g->ctx;
+  if (ex != VRT_EXEC_GRAPH) {
+    enqueue_fs<T>(g, ctx->stream, ex, nl, chi, S, Ib, It, J, I);
+  } else {
+    const vrt_grid_s::GraphKey key{sizeof(T), nl, chi, S, Ib, It, J, I};
+    auto it = g->graphs.find(key);
+    if (it == g->graphs.end()) {
+      if (!ctx->capture_stream) VRT_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+      hipStream_t cs = ctx->capture_stream;
+      VRT_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      hipGraph_t graph = nullptr;
+      try {
+        enqueue_fs<T>(g, cs, VRT_EXEC_BATCHED, nl, chi, S, Ib, It, J, I);
+      } catch (...) {
+        (void)hipStreamEndCapture(cs, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+      }
+      VRT_HIP(hipStreamEndCapture(cs, &graph));
+      hipGraphExec_t exec = nullptr;
+      hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      VRT_HIP(e);
+      it = g->graphs.emplace(key, exec).first;
+    }
+    VRT_HIP(hipGraphLaunch(it->second, ctx->stream));
+  }
+  g->last_I = I;
+}
+
+bool valid_prec(vrt_prec p) { return p == VRT_F64 || p == VRT_F32; }
+
+}  // namespace
+
+void vrt_ctx_s::drain_profile() {
+  for (auto &t : pending) {
+    VRT_HIP(hipEventSynchronize(t.stop));
+    float ms = 0.0f;
+    VRT_HIP(hipEventElapsedTime(&ms, t.start, t.stop));
+    prof_ms[t.kernel] += ms;
+    prof_launches[t.kernel] += 1;
+    prof_units[t.kernel] += t.units;
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  pending.clear();
+}
+
+void vrt_grid_s::drop_graphs() {
+  for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+  graphs.clear();
+}
+
+extern "C" {
+
+const char *vrt_version(void) { return kVersion; }
+
+const char *vrt_status_string(vrt_status s) {
+  switch (s) {
+    case VRT_OK: return "ok";
+    case VRT_W_NOT_CONVERGED: return "not converged";
+    case VRT_E_ARG: return "invalid argument";
+    case VRT_E_GRID: return "invalid grid";
+    case VRT_E_DAG: return "upwind graph is not acyclic";
+    case VRT_E_HIP: return "HIP error";
+    case VRT_E_NOMEM: return "out of memory";
+    case VRT_E_NUMERIC: return "numerical error";
+    case VRT_E_STATE: return "call out of order";
+    default: return "unknown status";
+  }
+}
+
+vrt_status vrt_validate_voronoi(int64_t n, const double *xyz, const int64_t *nbr_ptr, const int32_t *nbr_idx,
+                                const int8_t *nbr_shift, const uint8_t *wall, const double lo[3], const double hi[3],
+                                uint32_t periodic_xy, char *msg, int64_t msg_len) {
+  try {
+    if (!lo || !hi || (n > 0 && !nbr_ptr)) {
+      if (msg && msg_len > 0) snprintf(msg, (size_t)msg_len, "null argument");
+      return VRT_E_ARG;
+    }
+    const std::string err = check_voronoi(n, xyz, nbr_ptr, nbr_idx, nbr_shift, wall, lo, hi, periodic_xy != 0);
+    if (msg && msg_len > 0) snprintf(msg, (size_t)msg_len, "%s", err.c_str());
+    return err.empty() ? VRT_OK : VRT_E_GRID;
+  } catch (...) {
+    if (msg && msg_len > 0) snprintf(msg, (size_t)msg_len, "host allocation failed");
+    return VRT_E_NOMEM;
+  }
+}
+
+vrt_status vrt_ctx_create(int32_t device, void *stream, vrt_ctx *out) {
+  if (!out) return VRT_E_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return VRT_E_ARG;
+  auto *c = new (std::nothrow) vrt_ctx_s;
+  if (!c) return VRT_E_NOMEM;
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(stream);
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return VRT_E_HIP;
+  }
+  *out = c;
+  return VRT_OK;
+}
+
+void vrt_ctx_destroy(vrt_ctx ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  try {
+    ctx->drain_profile();
+  } catch (...) {
+  }
+  if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+  delete ctx;
+}
+
+const char *vrt_ctx_last_error(vrt_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+vrt_status vrt_ctx_set_stream(vrt_ctx ctx, void *stream) {
+  if (!ctx) return VRT_E_ARG;
+  return guarded(ctx, [&] {
+    ctx->stream = static_cast<hipStream_t>(stream);
+    return VRT_OK;
+  });
+}
+
+vrt_status vrt_ctx_set_profiling(vrt_ctx ctx, int32_t on) {
+  if (!ctx) return VRT_E_ARG;
+  return guarded(ctx, [&] {
+    ctx->profiling = on != 0;
+    return VRT_OK;
+  });
+}
+
+vrt_status vrt_ctx_profile(vrt_ctx ctx, int32_t kernel, double *ms, int64_t *launches, int64_t *units) {
+  if (!ctx) return VRT_E_ARG;
+  return guarded(ctx, [&] {
+    if (kernel < 0 || kernel > 2) fail(VRT_E_ARG, "kernel class %d not in 0..2", kernel);
+    ctx->drain_profile();
+    if (ms) *ms = ctx->prof_ms[kernel];
+    if (launches) *launches = ctx->prof_launches[kernel];
+    if (units) *units = ctx->prof_units[kernel];
+    return VRT_OK;
+  });
+}
+
+vrt_status vrt_ctx_profile_reset(vrt_ctx ctx) {
+  if (!ctx) return VRT_E_ARG;
+  return guarded(ctx, [&] {
+    ctx->drain_profile();
+    for (int k = 0; k < 3; ++k) {
+      ctx->prof_ms[k] = 0.0;
+      ctx->prof_launches[k] = 0;
+      ctx->prof_units[k] = 0;
+    }
+    return VRT_OK;
+  });
+}
+
+vrt_status vrt_ctx_synchronize(vrt_ctx ctx) {
+  if (!ctx) return VRT_E_ARG;
+  return guarded(ctx, [&] {
+    VRT_HIP(hipStreamSynchronize(ctx->stream));
+    return VRT_OK;
+  });
+}
+
+vrt_status vrt_grid_create_voronoi(vrt_ctx ctx, int64_t n, const double *xyz, const int64_t *nbr_ptr,
+                                   const int32_t *nbr_idx, const int8_t *nbr_shift, const uint8_t *wall,
+                                   const double lo[3], const double hi[3], uint32_t periodic_xy, vrt_grid *out) {
+  if (!ctx || !out) return VRT_E_ARG;
+  *out = nullptr;
+  return guarded(ctx, [&] {
+    if (!lo || !hi || n < 0 || (n > 0 && (!xyz || !nbr_ptr || !wall))) fail(VRT_E_ARG, "null argument or n < 0");
+    const std::string err = check_voronoi(n, xyz, nbr_ptr, nbr_idx, nbr_shift, wall, lo, hi, periodic_xy != 0);
+    if (!err.empty()) throw Error(VRT_E_GRID, err);
+    std::unique_ptr<vrt_grid_s> g(new vrt_grid_s);
+    g->ctx = ctx;
+    g->kind = 0;
+    g->n = n;
+    g->m = n > 0 ? nbr_ptr[n] : 0;
+    g->periodic = periodic_xy != 0;
+    for (int d = 0; d < 3; ++d) {
+      g->lo[d] = lo[d];
+      g->hi[d] = hi[d];
+    }
+    hipStream_t s = ctx->stream;
+    std::vector<int8_t> zero;
+    upload(g->d_xyz, xyz, (size_t)n * 3, s);
+    upload(g->d_ptr, nbr_ptr, (size_t)n + 1, s);
+    upload(g->d_idx, nbr_idx, (size_t)g->m, s);
+    if (nbr_shift) {
+      upload(g->d_shift, nbr_shift, (size_t)g->m * 2, s);
+    } else {
+      zero.assign((size_t)g->m * 2, 0);
+      upload(g->d_shift, zero.data(), zero.size(), s);
+    }
+    upload(g->d_wall, wall, (size_t)n, s);
+    g->h_wall.assign(wall, wall + n);
+    VRT_HIP(hipStreamSynchronize(s));
+    *out = g.release();
+    return VRT_OK;
+  });
+}
+
+vrt_status vrt_grid_create_regular(vrt_ctx ctx, int32_t nx, int32_t ny, int32_t nz, double dx, double dy,
+                                   const double *z, vrt_grid *out) {
+  if (!ctx || !out) return VRT_E_ARG;
+  *out = nullptr;
+  return guarded(ctx, [&] {
+    if (nx <= 0 || ny <= 0 || nz <= 0 || !z || !(dx > 0) || !(dy > 0)) fail(VRT_E_ARG, "bad regular grid size");
+    if ((int64_t)nx * ny * nz >= (int64_t(1) << 31)) fail(VRT_E_ARG, "more than 2^31 - 1 points");
+    for (int32_t k = 1; k < nz; ++k)
+      if (!(z[k] > z[k - 1])) fail(VRT_E_GRID, "z must be strictly increasing (index %d)", k);
+    std::unique_ptr<vrt_grid_s> g(new vrt_grid_s);
+    g->ctx = ctx;
+    g->kind = 1;
+    g->nx = nx;
+    g->ny = ny;
+    g->nz = nz;
+    g->dx = dx;
+    g->dy = dy;
+    g->n = (int64_t)nx * ny * nz;
+    g->h_z.assign(z, z + nz);
+    upload(g->d_z, z, (size_t)nz, ctx->stream);
+    VRT_HIP(hipStreamSynchronize(ctx->stream));
+    *out = g.release();
+    return VRT_OK;
+  });
+}
+
+void vrt_grid_destroy(vrt_grid g) {
+  if (!g) return;
+  (void)hipSetDevice(g->ctx->device);
+  (void)hipStreamSynchronize(g->ctx->stream);
+  g->drop_graphs();
+  delete g;
+}
+
+vrt_status vrt_grid_set_rays(vrt_grid g, int32_t n_rays, const double *dir, const double *w, double r_exp) {
+  if (!g) return VRT_E_ARG;
+  return guarded(g->ctx, [&] {
+    if (n_rays <= 0 || !dir || !w || !std::isfinite(r_exp) || r_exp <= 0)
+      fail(VRT_E_ARG, "need n_rays > 0, directions, weights and a positive exponent");
+    double sum = 0.0;
+    for (int32_t r = 0; r < n_rays; ++r) {
+      const double a = dir[3 * r], b = dir[3 * r + 1], c = dir[3 * r + 2];
+      const double nrm = std::sqrt(a * a + b * b + c * c);
+      if (!(std::fabs(nrm - 1.0) < 1e-12)) fail(VRT_E_ARG, "direction %d is not a unit vector", r);
+      if (!(c != 0.0)) fail(VRT_E_ARG, "direction %d is horizontal", r);
+      if (!(w[r] > 0.0) || !std::isfinite(w[r])) fail(VRT_E_ARG, "weight %d is not positive", r);
+      sum += w[r];
+    }
+    if (!(std::fabs(sum - 1.0) < 1e-12)) fail(VRT_E_ARG, "ray weights sum to %.17g, not 1", sum);
+    g->drop_graphs();
+    g->R = n_rays;
+    g->r_exp = r_exp;
+    g->h_dirs.assign(dir, dir + 3 * (size_t)n_rays);
+    g->h_w.assign(w, w + n_rays);
+    upload(g->d_dirs, dir, 3 * (size_t)n_rays, g->ctx->stream);
+    upload(g->d_w, w, (size_t)n_rays, g->ctx->stream);
+    g->d_Iscr.release();
+    if (g->kind == 0) {
+      set_rays_voronoi(g);
+    } else {
+      g->n_steps = g->nz;
+      g->n_levels.assign((size_t)n_rays, g->nz);
+    }
+    build_emergent_index(g);
+    return VRT_OK;
+  });
+}
+
+vrt_status vrt_grid_info(vrt_grid g, int64_t *n_sites, int32_t *n_rays, int32_t *max_levels, int64_t *n_fallback) {
+  if (!g) return VRT_E_ARG;
+  if (n_sites) *n_sites = g->n;
+  if (n_rays) *n_rays = g->R;
+  if (max_levels) *max_levels = g->n_steps;
+  if (n_fallback) *n_fallback = g->n_fallback;
+  return VRT_OK;
+}
+
+vrt_status vrt_grid_schedule(vrt_grid g, int32_t ray, int32_t *k1, int32_t *k2, double *w1, double *ds1, double *ds2,
+                             int32_t *level, int32_t *order, int32_t *level_ptr, int32_t *n_levels) {
+  if (!g) return VRT_E_ARG;
+  return guarded(g->ctx, [&] {
+    if (g->kind != 0) fail(VRT_E_ARG, "schedules exist on Voronoi grids only");
+    if (g->R == 0) fail(VRT_E_STATE, "rays not set");
+    if (ray < 0 || ray >= g->R) fail(VRT_E_ARG, "ray %d out of range", ray);
+    hipStream_t s = g->ctx->stream;
+    const size_t off = (size_t)ray * (size_t)g->n;
+    auto dl = [&](void *h, const DevBuf &d, size_t esz) {
+      if (h && g->n) VRT_HIP(hipMemcpyAsync(h, (const char *)d.p + off * esz, (size_t)g->n * esz, hipMemcpyDeviceToHost, s));
+    };
+    dl(k1, g->d_k1, 4);
+    dl(k2, g->d_k2, 4);
+    dl(w1, g->d_w1, 8);
+    dl(ds1, g->d_ds1, 8);
+    dl(ds2, g->d_ds2, 8);
+    dl(level, g->d_level, 4);
+    dl(order, g->d_order, 4);
+    VRT_HIP(hipStreamSynchronize(s));
+    const auto &lp = g->level_ptr[(size_t)ray];
+    if (level_ptr) std::copy(lp.begin(), lp.end(), level_ptr);
+    if (n_levels) *n_levels = g->n_levels[(size_t)ray];
+    return VRT_OK;
+  });
+}
+
+vrt_status vrt_lte_continuum(vrt_grid g, vrt_prec prec, int32_t n_lambda, const double *lambda_m, double kappa0,
+                             const double *T, const double *rho, void *chi, void *S) {
+  if (!g) return VRT_E_ARG;
+  return guarded(g->ctx, [&] {
+    if (!valid_prec(prec) || n_lambda <= 0 || !lambda_m || !(g->n == 0 || (T && rho && chi && S)))
+      fail(VRT_E_ARG, "bad LTE arguments");
+    for (int32_t l = 0; l < n_lambda; ++l)
+      if (!(lambda_m[l] > 0.0)) fail(VRT_E_ARG, "wavelength %d is not positive", l);
+    hipStream_t s = g->ctx->stream;
+    // the wavelength table is cached on the device; a new table waits for
+    // earlier work that may still read the old one, then is copied synchronously
+    if (g->h_lam.size() != (size_t)n_lambda || !std::equal(g->h_lam.begin(), g->h_lam.end(), lambda_m)) {
+      VRT_HIP(hipStreamSynchronize(s));
+      g->d_lam.alloc((size_t)n_lambda * sizeof(double));
+      VRT_HIP(hipMemcpy(g->d_lam.p, lambda_m, (size_t)n_lambda * sizeof(double), hipMemcpyHostToDevice));
+      g->h_lam.assign(lambda_m, lambda_m + n_lambda);
+    }
+    if (prec == VRT_F32)
+      vrt::launch_lte<float>(s, g->n, n_lambda, g->d_lam.as<double>(), kappa0, T, rho, static_cast<float *>(chi),
+                             static_cast<float *>(S));
+    else
+      vrt::launch_lte<double>(s, g->n, n_lambda, g->d_lam.as<double>(), kappa0, T, rho, static_cast<double *>(chi),
+                              static_cast<double *>(S));
+    return VRT_OK;
+  });
+}
+
+vrt_status vrt_formal_solution(vrt_grid g, vrt_prec prec, vrt_exec exec, int32_t n_lambda, const void *chi,
+                               const void *S, const void *I_bottom, const void *I_top, void *J, void *I_rays) {
+  if (!g) return VRT_E_ARG;
+  return guarded(g->ctx, [&] {
+    if (!valid_prec(prec) || (exec != VRT_EXEC_PLAIN && exec != VRT_EXEC_BATCHED && exec != VRT_EXEC_GRAPH))
+      fail(VRT_E_ARG, "bad precision or execution mode");
+    if (n_lambda <= 0) fail(VRT_E_ARG, "n_lambda must be positive");
+    if (g->R == 0) fail(VRT_E_STATE, "rays not set");
+    if (g->n > 0 && (!chi || !S || !J)) fail(VRT_E_ARG, "chi, S and J are required");
+    if (g->n == 0) return VRT_OK;
+    if (prec == VRT_F32)
+      formal_solution<float>(g, exec, n_lambda, chi, S, I_bottom, I_top, J, I_rays);
+    else
+      formal_solution<double>(g, exec, n_lambda, chi, S, I_bottom, I_top, J, I_rays);
+    return VRT_OK;
+  });
+}
+
+vrt_status vrt_grid_emergent_index(vrt_grid g, int64_t *offsets, int32_t *sites) {
+  if (!g) return VRT_E_ARG;
+  if (g->R == 0) {
+    g->ctx->err = "rays not set";
+    return VRT_E_STATE;
+  }
+  if (offsets) std::copy(g->em_off.begin(), g->em_off.end(), offsets);
+  if (sites) std::copy(g->em_site.begin(), g->em_site.end(), sites);
+  return VRT_OK;
+}
+
+vrt_status vrt_emergent_gather(vrt_grid g, vrt_prec prec, int32_t n_lambda, const void *I_rays, void *out) {
+  if (!g) return VRT_E_ARG;
+  return guarded(g->ctx, [&] {
+    if (!valid_prec(prec) || n_lambda <= 0) fail(VRT_E_ARG, "bad precision or n_lambda");
+    if (g->R == 0) fail(VRT_E_STATE, "rays not set");
+    const void *I = I_rays ? I_rays : g->last_I;
+    if (!I) fail(VRT_E_STATE, "no formal solution has run");
+    const int64_t total = g->em_off.back();
+    if (total > 0 && !out) fail(VRT_E_ARG, "null output");
+    if (prec == VRT_F32)
+      vrt::launch_emergent<float>(g->ctx->stream, total, n_lambda, g->n, g->d_em_ray.as<int32_t>(),
+                                  g->d_em_site.as<int32_t>(), static_cast<const float *>(I), static_cast<float *>(out));
+    else
+      vrt::launch_emergent<double>(g->ctx->stream, total, n_lambda, g->n, g->d_em_ray.as<int32_t>(),
+                                   g->d_em_site.as<int32_t>(), static_cast<const double *>(I),
+                                   static_cast<double *>(out));
+    return VRT_OK;
+  });
+}
+
+}  // extern "C"

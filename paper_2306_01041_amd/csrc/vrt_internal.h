@@ -1,0 +1,201 @@
+// Internal declarations of the gfx950 formal-solution library: grid and
+// context state, per-(ray, site) sweep records, and the host-side launchers
+// that each kernel file exports.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/vrt.h"
+
+namespace vrt {
+
+// An error carrying a status code; caught at the C ABI boundary.
+struct Error : std::runtime_error {
+  vrt_status code;
+  Error(vrt_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define VRT_HIP(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      throw ::vrt::Error(VRT_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Floating-point part of one sweep record. The integer part is an int4:
+// x = site, y = first upwind site (-1 at boundary sites), z = second upwind
+// site (-1 if none), w = 2 * ray + (1 if the ray points up).
+struct RecF32 {
+  float w1, ds1, ds2, pad;
+};
+struct RecF64 {
+  double w1, ds1, ds2, pad;
+};
+
+template <typename T> struct RecOf;
+template <> struct RecOf<float> { using type = RecF32; };
+template <> struct RecOf<double> { using type = RecF64; };
+
+// Device buffer with RAII release.
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(size_t b) {
+    if (b <= bytes && p) return;
+    release();
+    if (b == 0) b = 16;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      p = nullptr;
+      throw Error(VRT_E_NOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed: " + hipGetErrorString(e));
+    }
+    bytes = b;
+  }
+  template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
+}  // namespace vrt
+
+struct vrt_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t capture_stream = nullptr;
+  std::string err;
+
+  // kernel timing (eager launches only)
+  struct Timed {
+    int kernel;
+    hipEvent_t start, stop;
+    int64_t units;
+  };
+  bool profiling = false;
+  std::vector<Timed> pending;
+  double prof_ms[3] = {0, 0, 0};
+  int64_t prof_launches[3] = {0, 0, 0};
+  int64_t prof_units[3] = {0, 0, 0};
+  void drain_profile();
+};
+
+struct vrt_grid_s {
+  vrt_ctx ctx = nullptr;
+  int kind = 0;  // 0 Voronoi, 1 regular
+  int64_t n = 0;
+
+  // Voronoi geometry
+  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  bool periodic = false;
+  int64_t m = 0;
+  vrt::DevBuf d_xyz, d_ptr, d_idx, d_shift, d_wall;
+  std::vector<uint8_t> h_wall;
+
+  // regular geometry
+  int32_t nx = 0, ny = 0, nz = 0;
+  double dx = 0, dy = 0;
+  std::vector<double> h_z;
+  vrt::DevBuf d_z;
+
+  // quadrature
+  int32_t R = 0;
+  std::vector<double> h_dirs, h_w;
+  double r_exp = 7.0;
+  vrt::DevBuf d_dirs, d_w;
+
+  // Voronoi selection and schedule, [R][n] in caller site order
+  vrt::DevBuf d_k1, d_k2, d_w1, d_ds1, d_ds2, d_level, d_order;
+  std::vector<int32_t> n_levels;               // per ray
+  std::vector<std::vector<int32_t>> level_ptr;  // per ray, [n_levels + 1]
+  int64_t n_fallback = 0;
+
+  // sweep records in step-major order: step s holds level s of ray 0, 1, ...
+  int32_t n_steps = 0;
+  int64_t n_rec = 0;
+  vrt::DevBuf d_ri, d_rf32, d_rf64;
+  std::vector<int64_t> step_ptr;  // [n_steps + 1]
+  std::vector<int64_t> seg_off;   // [n_steps][R]: first record of (step, ray)
+  std::vector<int64_t> seg_cnt;   // [n_steps][R]
+
+  // emergent index
+  std::vector<int64_t> em_off;
+  std::vector<int32_t> em_site;
+  vrt::DevBuf d_em_ray, d_em_site;
+
+  // wavelength table of the LTE helper
+  std::vector<double> h_lam;
+  vrt::DevBuf d_lam;
+
+  // scratch for per-ray intensities when the caller passes none
+  vrt::DevBuf d_Iscr;
+  const void *last_I = nullptr;
+
+  // captured launch sequences, keyed by (prec, n_lambda, pointers)
+  using GraphKey = std::tuple<int, int32_t, const void *, const void *, const void *, const void *, void *, void *>;
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  void drop_graphs();
+};
+
+namespace vrt {
+
+// ---- k_select.hip
+void launch_select(hipStream_t s, int64_t n, int32_t R, const double *xyz, const int64_t *ptr,
+                   const int32_t *idx, const int8_t *shift, const uint8_t *wall, double Lx, double Ly,
+                   const double *dirs, double r_exp, int32_t *k1, int32_t *k2, double *w1, double *ds1,
+                   double *ds2, unsigned long long *n_fallback, int32_t *bad_site);
+
+// ---- k_schedule.hip
+void launch_level_fill(hipStream_t s, int64_t total, int32_t *level);
+void launch_level_relax(hipStream_t s, int64_t n, int32_t R, const int32_t *k1, const int32_t *k2,
+                        int32_t *level, int32_t *changed);
+void launch_level_count(hipStream_t s, int64_t n, int32_t R, int32_t Lmax, int64_t tile,
+                        const int32_t *level, int32_t *cnt);
+void launch_level_scan(hipStream_t s, int32_t R, int32_t Lmax, int64_t ntiles, int32_t *cnt,
+                       int64_t *totals);
+void launch_level_ptr(hipStream_t s, int32_t R, int32_t Lmax, const int64_t *totals, int32_t *level_ptr,
+                      int32_t *n_levels);
+void launch_level_scatter(hipStream_t s, int64_t n, int32_t R, int32_t Lmax, int64_t tile,
+                          const int32_t *level, const int32_t *level_ptr, int32_t *cnt, int32_t *order);
+void launch_level_max(hipStream_t s, int64_t total, const int32_t *level, int32_t *out_max);
+void launch_pack(hipStream_t s, int64_t n, int32_t R, int32_t Lmax, const int32_t *order,
+                 const int32_t *level, const int32_t *level_ptr, const int64_t *seg_off,
+                 const int32_t *k1, const int32_t *k2, const double *w1, const double *ds1,
+                 const double *ds2, const double *dirs, int4 *ri, RecF32 *rf32, RecF64 *rf64);
+
+// ---- k_sweep.hip
+template <typename T>
+void launch_sweep(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *rf, int64_t rec_begin,
+                  int64_t rec_count, int32_t nl, int64_t n, const T *chi, const T *S, const T *Ibot,
+                  const T *Itop, T *I);
+template <typename T>
+void launch_jreduce(hipStream_t s, const T *I, int32_t R, int64_t nn, const double *w, T *J);
+template <typename T>
+void launch_emergent(hipStream_t s, int64_t total, int32_t nl, int64_t n, const int32_t *em_ray,
+                     const int32_t *em_site, const T *I, T *out);
+
+// ---- k_source.hip
+template <typename T>
+void launch_lte(hipStream_t s, int64_t n, int32_t nl, const double *lam, double kappa0, const double *T_,
+                const double *rho, T *chi, T *S);
+
+// ---- k_regular.hip
+template <typename T>
+void launch_regular(hipStream_t s, int32_t step, int32_t ray_begin, int32_t ray_count, int32_t nx,
+                    int32_t ny, int32_t nz, double dx, double dy, const double *z, const double *dirs,
+                    int32_t nl, const T *chi, const T *S, const T *Ibot, const T *Itop, T *I);
+
+}  // namespace vrt

@@ -1,0 +1,319 @@
+"""ctypes binding of ``libvrt.so`` (declared in ``include/vrt.h``).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels. Host arrays are numpy; device arrays are torch tensors on the
+context's GPU (used for memory and streams, never for arithmetic here). The
+functions keep the C names; small classes own the context and grid handles.
+
+Importing this module fails loudly when the library has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvrt.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2306_01041_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+VRT_OK = 0
+VRT_W_NOT_CONVERGED = 1
+VRT_E_ARG = -1
+VRT_E_GRID = -2
+VRT_E_DAG = -3
+VRT_E_HIP = -4
+VRT_E_NOMEM = -5
+VRT_E_NUMERIC = -6
+VRT_E_STATE = -7
+
+VRT_F64 = 0
+VRT_F32 = 1
+VRT_EXEC_PLAIN = 0
+VRT_EXEC_BATCHED = 1
+VRT_EXEC_GRAPH = 2
+
+_vp = ctypes.c_void_p
+_d = ctypes.POINTER(ctypes.c_double)
+_i32 = ctypes.POINTER(ctypes.c_int32)
+_i64 = ctypes.POINTER(ctypes.c_int64)
+_i8 = ctypes.POINTER(ctypes.c_int8)
+_u8 = ctypes.POINTER(ctypes.c_uint8)
+_st = ctypes.c_int32
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+vrt_version = _sig("vrt_version", ctypes.c_char_p, [])
+vrt_status_string = _sig("vrt_status_string", ctypes.c_char_p, [_st])
+vrt_validate_voronoi = _sig("vrt_validate_voronoi", _st, [ctypes.c_int64, _d, _i64, _i32, _i8, _u8, _d, _d,
+                                                          ctypes.c_uint32, ctypes.c_char_p, ctypes.c_int64])
+vrt_ctx_create = _sig("vrt_ctx_create", _st, [ctypes.c_int32, _vp, ctypes.POINTER(_vp)])
+vrt_ctx_destroy = _sig("vrt_ctx_destroy", None, [_vp])
+vrt_ctx_last_error = _sig("vrt_ctx_last_error", ctypes.c_char_p, [_vp])
+vrt_ctx_set_stream = _sig("vrt_ctx_set_stream", _st, [_vp, _vp])
+vrt_ctx_synchronize = _sig("vrt_ctx_synchronize", _st, [_vp])
+vrt_ctx_set_profiling = _sig("vrt_ctx_set_profiling", _st, [_vp, ctypes.c_int32])
+vrt_ctx_profile = _sig("vrt_ctx_profile", _st, [_vp, ctypes.c_int32, _d, _i64, _i64])
+vrt_ctx_profile_reset = _sig("vrt_ctx_profile_reset", _st, [_vp])
+vrt_grid_create_voronoi = _sig("vrt_grid_create_voronoi", _st, [_vp, ctypes.c_int64, _d, _i64, _i32, _i8, _u8, _d,
+                                                                _d, ctypes.c_uint32, ctypes.POINTER(_vp)])
+vrt_grid_create_regular = _sig("vrt_grid_create_regular", _st, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                                ctypes.c_double, ctypes.c_double, _d,
+                                                                ctypes.POINTER(_vp)])
+vrt_grid_destroy = _sig("vrt_grid_destroy", None, [_vp])
+vrt_grid_set_rays = _sig("vrt_grid_set_rays", _st, [_vp, ctypes.c_int32, _d, _d, ctypes.c_double])
+vrt_grid_info = _sig("vrt_grid_info", _st, [_vp, _i64, _i32, _i32, _i64])
+vrt_grid_schedule = _sig("vrt_grid_schedule", _st, [_vp, ctypes.c_int32, _i32, _i32, _d, _d, _d, _i32, _i32, _i32,
+                                                    _i32])
+vrt_lte_continuum = _sig("vrt_lte_continuum", _st, [_vp, ctypes.c_int32, ctypes.c_int32, _d, ctypes.c_double, _vp,
+                                                    _vp, _vp, _vp])
+vrt_formal_solution = _sig("vrt_formal_solution", _st, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
+                                                        _vp, _vp, _vp, _vp])
+vrt_grid_emergent_index = _sig("vrt_grid_emergent_index", _st, [_vp, _i64, _i32])
+vrt_emergent_gather = _sig("vrt_emergent_gather", _st, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp])
+
+EXPORTED = [n for n in dir() if n.startswith("vrt_")]
+
+
+class VrtError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{vrt_status_string(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+def _p(a, t):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+def _dev(t):
+    """Device pointer of a torch tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("device arrays must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _prec_of(t):
+    import torch
+
+    if t.dtype == torch.float64:
+        return VRT_F64
+    if t.dtype == torch.float32:
+        return VRT_F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def validate_voronoi(n, xyz, nbr_ptr, nbr_idx, nbr_shift, wall, lo, hi, periodic_xy=True):
+    """Host-only geometry check; returns (status, message)."""
+    buf = ctypes.create_string_buffer(512)
+    keep = [None if a is None else np.ascontiguousarray(a, dt) for a, dt in
+            ((xyz, np.float64), (nbr_ptr, np.int64), (nbr_idx, np.int32), (nbr_shift, np.int8), (wall, np.uint8),
+             (lo, np.float64), (hi, np.float64))]
+    ptrs = [None if a is None else _p(a, t) for a, t in zip(keep, (_d, _i64, _i32, _i8, _u8, _d, _d))]
+    st = vrt_validate_voronoi(int(n), *ptrs, 1 if periodic_xy else 0, buf, 512)
+    return st, buf.value.decode()
+
+
+class Context:
+    """A library context on one GPU, enqueuing on a HIP stream (default: torch's current stream)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self._stream_obj = stream
+        h = _vp()
+        st = vrt_ctx_create(int(device), _vp(stream.cuda_stream), ctypes.byref(h))
+        if st != VRT_OK:
+            raise VrtError(st, "vrt_ctx_create failed")
+        self.handle = h
+        self.device = device
+
+    def check(self, st):
+        if st < 0:
+            raise VrtError(st, vrt_ctx_last_error(self.handle).decode())
+        return st
+
+    def set_stream(self, stream):
+        self._stream_obj = stream
+        self.check(vrt_ctx_set_stream(self.handle, _vp(stream.cuda_stream)))
+
+    def synchronize(self):
+        self.check(vrt_ctx_synchronize(self.handle))
+
+    def set_profiling(self, on: bool):
+        self.check(vrt_ctx_set_profiling(self.handle, 1 if on else 0))
+
+    def profile(self, kernel: int):
+        """(ms, launches, units) summed over instrumented launches of a kernel class."""
+        ms = ctypes.c_double()
+        nl = ctypes.c_int64()
+        un = ctypes.c_int64()
+        self.check(vrt_ctx_profile(self.handle, int(kernel), ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(un)))
+        return ms.value, nl.value, un.value
+
+    def profile_reset(self):
+        self.check(vrt_ctx_profile_reset(self.handle))
+
+    def close(self):
+        if self.handle:
+            vrt_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Grid:
+    """A Voronoi or regular grid handle with its quadrature and schedules."""
+
+    def __init__(self, ctx: Context, handle, kind: str):
+        self.ctx = ctx
+        self.handle = handle
+        self.kind = kind
+
+    @classmethod
+    def voronoi(cls, ctx: Context, xyz, nbr_ptr, nbr_idx, nbr_shift, wall, lo, hi, periodic_xy=True):
+        xyz = np.ascontiguousarray(xyz, np.float64)
+        ptr = np.ascontiguousarray(nbr_ptr, np.int64)
+        idx = np.ascontiguousarray(nbr_idx, np.int32)
+        sh = None if nbr_shift is None else np.ascontiguousarray(nbr_shift, np.int8)
+        wall = np.ascontiguousarray(wall, np.uint8)
+        lo = np.ascontiguousarray(lo, np.float64)
+        hi = np.ascontiguousarray(hi, np.float64)
+        h = _vp()
+        ctx.check(vrt_grid_create_voronoi(ctx.handle, xyz.shape[0], _p(xyz, _d), _p(ptr, _i64), _p(idx, _i32),
+                                          _p(sh, _i8), _p(wall, _u8), _p(lo, _d), _p(hi, _d),
+                                          1 if periodic_xy else 0, ctypes.byref(h)))
+        return cls(ctx, h, "voronoi")
+
+    @classmethod
+    def from_synth(cls, ctx: Context, g):
+        return cls.voronoi(ctx, g.xyz, g.nbr_ptr, g.nbr_idx, g.nbr_shift, g.wall, g.lo, g.hi, g.periodic_xy)
+
+    @classmethod
+    def regular(cls, ctx: Context, nx, ny, z, dx, dy):
+        z = np.ascontiguousarray(z, np.float64)
+        h = _vp()
+        ctx.check(vrt_grid_create_regular(ctx.handle, int(nx), int(ny), len(z), float(dx), float(dy), _p(z, _d),
+                                          ctypes.byref(h)))
+        return cls(ctx, h, "regular")
+
+    def set_rays(self, dirs, w, r_exp: float = 7.0):
+        dirs = np.ascontiguousarray(dirs, np.float64)
+        w = np.ascontiguousarray(w, np.float64)
+        self.ctx.check(vrt_grid_set_rays(self.handle, dirs.shape[0], _p(dirs, _d), _p(w, _d), float(r_exp)))
+
+    def info(self):
+        n = ctypes.c_int64()
+        r = ctypes.c_int32()
+        L = ctypes.c_int32()
+        fb = ctypes.c_int64()
+        self.ctx.check(vrt_grid_info(self.handle, ctypes.byref(n), ctypes.byref(r), ctypes.byref(L), ctypes.byref(fb)))
+        return dict(n_sites=n.value, n_rays=r.value, max_levels=L.value, n_fallback=fb.value)
+
+    def schedule(self, ray: int):
+        n = self.info()["n_sites"]
+        k1 = np.empty(n, np.int32)
+        k2 = np.empty(n, np.int32)
+        w1 = np.empty(n, np.float64)
+        d1 = np.empty(n, np.float64)
+        d2 = np.empty(n, np.float64)
+        lev = np.empty(n, np.int32)
+        order = np.empty(n, np.int32)
+        lp = np.empty(n + 1, np.int32)
+        nl = ctypes.c_int32()
+        self.ctx.check(vrt_grid_schedule(self.handle, int(ray), _p(k1, _i32), _p(k2, _i32), _p(w1, _d), _p(d1, _d),
+                                         _p(d2, _d), _p(lev, _i32), _p(order, _i32), _p(lp, _i32), ctypes.byref(nl)))
+        return dict(k1=k1, k2=k2, w1=w1, ds1=d1, ds2=d2, level=lev, order=order, level_ptr=lp[: nl.value + 1].copy(),
+                    n_levels=nl.value)
+
+    def emergent_index(self):
+        R = self.info()["n_rays"]
+        off = np.empty(R + 1, np.int64)
+        self.ctx.check(vrt_grid_emergent_index(self.handle, _p(off, _i64), None))
+        sites = np.empty(int(off[-1]), np.int32)
+        self.ctx.check(vrt_grid_emergent_index(self.handle, _p(off, _i64), _p(sites, _i32)))
+        return off, sites
+
+    def close(self):
+        if self.handle:
+            vrt_grid_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _need(t, shape, dtype, name):
+    """Host-side guard: a device tensor of exactly this shape and dtype, contiguous, on a GPU."""
+    if t is None:
+        return
+    if not getattr(t, "is_cuda", False):
+        raise ValueError(f"{name} must be a GPU tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def lte_continuum(grid: Grid, lam, kappa0, T, rho, chi, S):
+    """chi = kappa0 rho^2 T^9, S = B_lambda(T) into device tensors chi, S [n, nl] (their dtype sets the precision)."""
+    import torch
+
+    lam = np.ascontiguousarray(np.atleast_1d(lam), np.float64)
+    n = grid.info()["n_sites"]
+    _need(T, (n,), torch.float64, "T")
+    _need(rho, (n,), torch.float64, "rho")
+    _need(chi, (n, len(lam)), chi.dtype, "chi")
+    _need(S, (n, len(lam)), chi.dtype, "S")
+    grid.ctx.check(vrt_lte_continuum(grid.handle, _prec_of(chi), len(lam), _p(lam, _d), float(kappa0), _dev(T),
+                                     _dev(rho), _dev(chi), _dev(S)))
+
+
+def formal_solution(grid: Grid, chi, S, J, I_bottom=None, I_top=None, I_rays=None, exec_mode=VRT_EXEC_BATCHED):
+    """Formal solution of every ray and J (device tensors [n, nl]; I_rays [R, n, nl] optional)."""
+    inf = grid.info()
+    n, R = inf["n_sites"], inf["n_rays"]
+    if chi.dim() != 2:
+        raise ValueError("chi must be [n_sites, n_lambda]")
+    nl = chi.shape[1]
+    for t, name in ((chi, "chi"), (S, "S"), (J, "J"), (I_bottom, "I_bottom"), (I_top, "I_top")):
+        _need(t, (n, nl), chi.dtype, name)
+    _need(I_rays, (R, n, nl), chi.dtype, "I_rays")
+    grid.ctx.check(vrt_formal_solution(grid.handle, _prec_of(chi), int(exec_mode), int(nl), _dev(chi), _dev(S),
+                                       _dev(I_bottom), _dev(I_top), _dev(J), _dev(I_rays)))
+
+
+def emergent_gather(grid: Grid, out, I_rays=None):
+    """Emergent intensities of the last formal solution into out [total, nl] (see Grid.emergent_index)."""
+    inf = grid.info()
+    off, _ = grid.emergent_index()
+    if out.dim() != 2:
+        raise ValueError("out must be [n_emergent, n_lambda]")
+    nl = out.shape[1]
+    _need(out, (int(off[-1]), nl), out.dtype, "out")
+    _need(I_rays, (inf["n_rays"], inf["n_sites"], nl), out.dtype, "I_rays")
+    grid.ctx.check(vrt_emergent_gather(grid.handle, _prec_of(out), int(nl), _dev(I_rays), _dev(out)))

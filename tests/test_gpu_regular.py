@@ -1,0 +1,92 @@
+"""GPU parity of the regular-grid short-characteristics solver (Sect. 2.6)
+against the FP64 oracle, and of a lattice Voronoi grid against it for
+vertical rays."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import flush, relerr, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def v():
+    import paper_2306_01041_amd
+
+    return paper_2306_01041_amd.load()
+
+
+@pytest.fixture(scope="module")
+def ctx(v):
+    c = v.Context(0)
+    yield c
+    c.close()
+
+
+def _case(nx, ny, nz, nl, seed):
+    rng = np.random.default_rng(seed)
+    z = np.cumsum(np.r_[0.0, rng.uniform(0.05, 0.2, nz - 1)])
+    n = nx * ny * nz
+    chi = 10 ** rng.uniform(-1, 1.3, (n, nl))
+    S = rng.uniform(0.5, 5.0, (n, nl))
+    Ib = rng.uniform(0.5, 5.0, (n, nl))
+    return z, chi, S, Ib
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("mode", ["PLAIN", "GRAPH"])
+@pytest.mark.parametrize("nl", [1, 5, 70])
+def test_regular_matches_oracle(v, ctx, prec, mode, nl):
+    flush(f"regular prec={prec} mode={mode} nl={nl}")
+    nx, ny, nz = 16, 12, 21
+    z, chi, S, Ib = _case(nx, ny, nz, nl, nl)
+    dirs, w = synth.gauss_legendre_quadrature()
+    Jo, Io = oracle.fs_regular(nx, ny, z, 0.11, 0.13, dirs, w, chi, S, Ib, keep_I=True)
+    G = v.Grid.regular(ctx, nx, ny, z, 0.11, 0.13)
+    G.set_rays(dirs, w)
+    d = torch.float64 if prec == "f64" else torch.float32
+    J = torch.empty((nx * ny * nz, nl), dtype=d, device="cuda:0")
+    I = torch.empty((len(dirs), nx * ny * nz, nl), dtype=d, device="cuda:0")
+    v.formal_solution(G, to_dev(chi, d), to_dev(S, d), J, I_bottom=to_dev(Ib, d), I_rays=I,
+                      exec_mode=getattr(v, "VRT_EXEC_" + mode))
+    torch.cuda.synchronize()
+    tol = 1e-12 if prec == "f64" else 1e-5
+    eJ = relerr(J.cpu().numpy(), Jo)
+    flush(f"  J err {eJ:.2e}")
+    assert eJ <= tol
+    assert relerr(I.cpu().numpy(), Io) <= (tol if prec == "f64" else 1e-4)
+    off, sites = G.emergent_index()
+    em = torch.empty((int(off[-1]), nl), dtype=d, device="cuda:0")
+    v.emergent_gather(G, em, I_rays=I)
+    torch.cuda.synchronize()
+    emh = em.cpu().numpy()
+    for r in range(len(dirs)):
+        assert relerr(emh[off[r]:off[r + 1]], Io[r, sites[off[r]:off[r + 1]]]) <= (tol if prec == "f64" else 1e-4)
+    G.close()
+
+
+def test_lattice_voronoi_equals_regular_vertical_rays(v, ctx):
+    flush("lattice vs regular")
+    nx, ny, nz, nl = 8, 6, 15, 3
+    z, chi, S, Ib = _case(nx, ny, nz, nl, 77)
+    dirs, w = synth.vertical_quadrature()
+    g = synth.lattice_grid(nx, ny, z, dx=0.3, dy=0.2)
+    d = torch.float64
+    Gv = v.Grid.from_synth(ctx, g)
+    Gv.set_rays(dirs, w)
+    Gr = v.Grid.regular(ctx, nx, ny, z, 0.3, 0.2)
+    Gr.set_rays(dirs, w)
+    Jv = torch.empty((g.n, nl), dtype=d, device="cuda:0")
+    Jr = torch.empty_like(Jv)
+    args = (to_dev(chi, d), to_dev(S, d))
+    v.formal_solution(Gv, *args, Jv, I_bottom=to_dev(Ib, d))
+    v.formal_solution(Gr, *args, Jr, I_bottom=to_dev(Ib, d))
+    torch.cuda.synchronize()
+    assert relerr(Jv.cpu().numpy(), Jr.cpu().numpy()) <= 1e-13
+    Gv.close()
+    Gr.close()

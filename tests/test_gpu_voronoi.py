@@ -1,0 +1,257 @@
+"""GPU parity of the Voronoi-grid path against the FP64 oracle.
+
+Integer outputs (upwind sites, levels, sweep order) must be bit-identical;
+FP64 intensities and J agree to 1e-12 relative; the FP32 sweep agrees with
+the FP64 oracle to 1e-5 relative on J (its inputs are the FP64 fields rounded
+to single precision). Every case runs through the C ABI.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import flush, recipe_grid, relerr, to_dev, wavelengths
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def v():
+    import paper_2306_01041_amd
+
+    return paper_2306_01041_amd.load()
+
+
+@pytest.fixture(scope="module")
+def ctx(v):
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = v.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def quad():
+    return synth.gauss_legendre_quadrature()
+
+
+@pytest.fixture(scope="module")
+def grids():
+    return {n: recipe_grid(n, seed=1041 + n) for n in (1000, 16384)}
+
+
+def _gpu_grid(v, ctx, g, dirs, w):
+    G = v.Grid.from_synth(ctx, g)
+    G.set_rays(dirs, w, 7.0)
+    return G
+
+
+@pytest.mark.parametrize("n", [1000, 16384])
+def test_selection_and_schedule_bit_exact(v, ctx, quad, grids, n):
+    flush(f"selection n={n}")
+    atm, g = grids[n]
+    dirs, w = quad
+    G = _gpu_grid(v, ctx, g, dirs, w)
+    sel = oracle.select(g, dirs)
+    lev, order, ptrs, nlev = oracle.levels(g, dirs, sel)
+    info = G.info()
+    assert info["n_fallback"] == int(sel.n_fallback.sum())
+    assert info["max_levels"] == int(nlev.max())
+    for r in range(len(dirs)):
+        s = G.schedule(r)
+        assert np.array_equal(s["k1"], sel.k1[r]), r
+        assert np.array_equal(s["k2"], sel.k2[r]), r
+        assert relerr(s["w1"], sel.w1[r]) <= 1e-13
+        assert relerr(s["ds1"], sel.ds1[r]) <= 1e-15
+        assert relerr(s["ds2"], sel.ds2[r]) <= 1e-15
+        assert np.array_equal(s["level"], lev[r])
+        assert np.array_equal(s["order"], order[r])
+        assert np.array_equal(s["level_ptr"], ptrs[r])
+    G.close()
+
+
+def _fields(atm, nl, seed):
+    """Grey LTE-like opacity with a per-wavelength random modulation, so the
+    wavelength lanes are not all equal."""
+    lam = wavelengths(nl)
+    chi, S = oracle.lte(lam, atm.kappa0, atm.T, atm.rho)
+    rng = np.random.default_rng(seed)
+    chi = chi * rng.uniform(0.5, 2.0, size=(1, nl))
+    return chi, S
+
+
+@pytest.mark.parametrize("nl", [1, 3, 37, 101])
+@pytest.mark.parametrize("mode", ["PLAIN", "BATCHED", "GRAPH"])
+def test_fp64_formal_solution_matches_oracle(v, ctx, quad, grids, nl, mode):
+    flush(f"fp64 fs nl={nl} mode={mode}")
+    atm, g = grids[1000]
+    dirs, w = quad
+    G = _gpu_grid(v, ctx, g, dirs, w)
+    sel = oracle.select(g, dirs)
+    chi, S = _fields(atm, nl, nl)
+    Ib = S * 1.1
+    It = S * 0.01
+    Jo, Io = oracle.fs_voronoi(g, dirs, w, sel, chi, S, Ib, I_top=It, keep_I=True)
+    d = torch.float64
+    J = torch.empty((g.n, nl), dtype=d, device="cuda:0")
+    I = torch.empty((len(dirs), g.n, nl), dtype=d, device="cuda:0")
+    args = (to_dev(chi, d), to_dev(S, d), J)
+    ib, it = to_dev(Ib, d), to_dev(It, d)
+    ex = getattr(v, "VRT_EXEC_" + mode)
+    for rep in range(2 if mode == "GRAPH" else 1):
+        v.formal_solution(G, *args, I_bottom=ib, I_top=it, I_rays=I, exec_mode=ex)
+        torch.cuda.synchronize()
+        assert relerr(I.cpu().numpy(), Io) <= 1e-12
+        assert relerr(J.cpu().numpy(), Jo) <= 1e-12
+    G.close()
+
+
+def test_c0_lte_continuum_fp64(v, ctx, quad, grids):
+    flush("c0 lte fp64")
+    atm, g = grids[16384]
+    dirs, w = quad
+    G = _gpu_grid(v, ctx, g, dirs, w)
+    lam = np.array([500e-9])
+    d = torch.float64
+    T = to_dev(atm.T, d)
+    rho = to_dev(atm.rho, d)
+    chi = torch.empty((g.n, 1), dtype=d, device="cuda:0")
+    S = torch.empty_like(chi)
+    v.lte_continuum(G, lam, atm.kappa0, T, rho, chi, S)
+    chi_o, S_o = oracle.lte(lam, atm.kappa0, atm.T, atm.rho)
+    torch.cuda.synchronize()
+    assert relerr(chi.cpu().numpy(), chi_o) <= 1e-14
+    assert relerr(S.cpu().numpy(), S_o) <= 1e-14
+    sel = oracle.select(g, dirs)
+    Jo, Io = oracle.fs_voronoi(g, dirs, w, sel, chi_o, S_o, S_o, keep_I=True)
+    J = torch.empty_like(chi)
+    I = torch.empty((len(dirs), g.n, 1), dtype=d, device="cuda:0")
+    v.formal_solution(G, chi, S, J, I_rays=I, exec_mode=v.VRT_EXEC_GRAPH)
+    torch.cuda.synchronize()
+    assert relerr(J.cpu().numpy(), Jo) <= 1e-12
+    assert relerr(I.cpu().numpy(), Io) <= 1e-12
+    off, sites = G.emergent_index()
+    want_sites = oracle.emergent_sites(g, dirs)
+    for r in range(len(dirs)):
+        assert np.array_equal(sites[off[r]:off[r + 1]], want_sites[r])
+    em = torch.empty((int(off[-1]), 1), dtype=d, device="cuda:0")
+    v.emergent_gather(G, em, I_rays=None)  # from the library's record of the last solution
+    torch.cuda.synchronize()
+    emh = em.cpu().numpy()
+    for r in range(len(dirs)):
+        assert relerr(emh[off[r]:off[r + 1]], Io[r, want_sites[r]]) <= 1e-12
+    G.close()
+
+
+@pytest.mark.parametrize("nl", [1, 64])
+def test_fp32_batched_matches_fp64_oracle(v, ctx, quad, grids, nl):
+    flush(f"fp32 vs oracle nl={nl}")
+    atm, g = grids[16384]
+    dirs, w = quad
+    G = _gpu_grid(v, ctx, g, dirs, w)
+    lam = wavelengths(nl)
+    chi_o, S_o = oracle.lte(lam, atm.kappa0, atm.T, atm.rho)
+    sel = oracle.select(g, dirs)
+    Jo, Io = oracle.fs_voronoi(g, dirs, w, sel, chi_o, S_o, S_o, keep_I=True)
+    f = torch.float32
+    chi = torch.empty((g.n, nl), dtype=f, device="cuda:0")
+    S = torch.empty_like(chi)
+    v.lte_continuum(G, lam, atm.kappa0, to_dev(atm.T, torch.float64), to_dev(atm.rho, torch.float64), chi, S)
+    J = torch.empty_like(chi)
+    I = torch.empty((len(dirs), g.n, nl), dtype=f, device="cuda:0")
+    v.formal_solution(G, chi, S, J, I_rays=I, exec_mode=v.VRT_EXEC_GRAPH)
+    torch.cuda.synchronize()
+    eJ = relerr(J.cpu().numpy(), Jo)
+    eI = relerr(I.cpu().numpy(), Io)
+    flush(f"  fp32 max rel err J {eJ:.3e} I {eI:.3e}")
+    assert eJ <= 1e-5
+    assert eI <= 1e-4
+    G.close()
+
+
+def test_graph_replays_match_eager(v, ctx, quad, grids):
+    """A captured launch sequence replayed several times, with eager work and
+    synchronisations between replays, reproduces the eager result bit for bit."""
+    flush("graph replay")
+    atm, g = grids[16384]
+    dirs, w = quad
+    G = _gpu_grid(v, ctx, g, dirs, w)
+    chi_o, S_o = _fields(atm, 8, 3)
+    f = torch.float32
+    chi, S = to_dev(chi_o, f), to_dev(S_o, f)
+    J0 = torch.empty_like(chi)
+    v.formal_solution(G, chi, S, J0, exec_mode=v.VRT_EXEC_BATCHED)
+    torch.cuda.synchronize()
+    ref = J0.cpu().numpy().copy()
+    J = torch.empty_like(chi)
+    for rep in range(4):
+        J.fill_(-1.0)
+        v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_GRAPH)
+        torch.cuda.synchronize()
+        assert np.array_equal(J.cpu().numpy(), ref), rep
+        # eager work in between
+        v.formal_solution(G, chi, S, J0, exec_mode=v.VRT_EXEC_PLAIN)
+        torch.cuda.synchronize()
+        assert np.array_equal(J0.cpu().numpy(), ref)
+    G.close()
+
+
+def test_tiny_lattice_and_fallback_grids(v, ctx, quad):
+    flush("tiny lattice")
+    dirs, w = quad
+    g = synth.lattice_grid(2, 2, [0.0, 0.4, 1.0])
+    G = _gpu_grid(v, ctx, g, dirs, w)
+    sel = oracle.select(g, dirs)
+    rng = np.random.default_rng(0)
+    chi = rng.uniform(0.1, 2.0, (g.n, 2))
+    S = rng.uniform(0.5, 3.0, (g.n, 2))
+    Jo = oracle.fs_voronoi(g, dirs, w, sel, chi, S, S)
+    d = torch.float64
+    J = torch.empty((g.n, 2), dtype=d, device="cuda:0")
+    v.formal_solution(G, to_dev(chi, d), to_dev(S, d), J, exec_mode=v.VRT_EXEC_BATCHED)
+    torch.cuda.synchronize()
+    assert relerr(J.cpu().numpy(), Jo) <= 1e-13
+    for r in range(len(dirs)):
+        s = G.schedule(r)
+        assert np.array_equal(s["k1"], sel.k1[r])
+    G.close()
+
+
+def test_determinism(v, ctx, quad, grids):
+    flush("determinism")
+    atm, g = grids[1000]
+    dirs, w = quad
+    G = _gpu_grid(v, ctx, g, dirs, w)
+    chi_o, S_o = _fields(atm, 64, 9)
+    f = torch.float32
+    chi, S = to_dev(chi_o, f), to_dev(S_o, f)
+    out = []
+    for mode in (v.VRT_EXEC_PLAIN, v.VRT_EXEC_BATCHED, v.VRT_EXEC_GRAPH, v.VRT_EXEC_BATCHED):
+        J = torch.empty_like(chi)
+        v.formal_solution(G, chi, S, J, exec_mode=mode)
+        torch.cuda.synchronize()
+        out.append(J.cpu().numpy())
+    for o in out[1:]:
+        assert np.array_equal(o, out[0])
+    G.close()
+
+
+def test_errors_do_not_launch(v, ctx, quad, grids):
+    atm, g = grids[1000]
+    G = v.Grid.from_synth(ctx, g)
+    chi = torch.zeros((g.n, 1), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(v.VrtError) as e:
+        v.formal_solution(G, chi, chi, chi)
+    assert e.value.status == v.VRT_E_STATE
+    dirs, w = quad
+    with pytest.raises(v.VrtError) as e:
+        G.set_rays(dirs, w * 2.0)
+    assert e.value.status == v.VRT_E_ARG
+    bad = dirs.copy()
+    bad[0] = [1.0, 0.0, 0.0]
+    with pytest.raises(v.VrtError):
+        G.set_rays(bad, w)
+    G.close()

@@ -56,7 +56,21 @@ def main():
     ap.add_argument("--nl", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU baseline")
+    ap.add_argument("--mode", choices=["graph", "batched"], default="graph",
+                    help="launch the timed steps from a captured graph or eagerly")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of this many MiB (to scale HBM counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+
+        a = torch.ones(args.copy_calibration * (1 << 20) // 4, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": a.numel() * 4, "launches": 3}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -98,10 +112,16 @@ def main():
     off, _ = G.emergent_index()
     em = torch.empty((int(off[-1]), nl), dtype=f32, device=dev)
 
+    mode = v.VRT_EXEC_GRAPH if args.mode == "graph" else v.VRT_EXEC_BATCHED
+
     def step():
         v.lte_continuum(G, lam, atm.kappa0, T, rho, chi, S)
-        v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_GRAPH)
+        v.formal_solution(G, chi, S, J, exec_mode=mode)
         v.emergent_gather(G, em)
+
+    v.lte_continuum(G, lam, atm.kappa0, T, rho, chi, S)
+    tuning = v.autotune(G, chi, S, J, reps=5)
+    log(f"autotune: {tuning}")
 
     for _ in range(args.warmup):
         step()
@@ -115,7 +135,7 @@ def main():
     ms_step = (t1 - t0) * 1e3 / args.steps
     updates = g.n * R * nl
     value = updates / (ms_step * 1e-3)
-    log(f"FP32 graph step {ms_step:.3f} ms -> {value:.3e} updates/s")
+    log(f"FP32 {args.mode} step {ms_step:.3f} ms -> {value:.3e} updates/s")
 
     # roofline of the dominant kernel: eager batched launches with HIP events on the library's stream
     ctx.profile_reset()
@@ -161,22 +181,25 @@ def main():
         log(f"FP64 plain step {ms64:.2f} ms; FP32 graph speed-up {ms64 / ms_step:.1f}x; FP32 J err {jerr:.2e}")
         del chi64, S64, J64
 
-    # CPU oracle on a bounded sample: all sites and rays, every other wavelength
+    # CPU oracle on a bounded sample: the same formal solution (all sites, rays and
+    # wavelengths), repeated until about 10 s of host time have been spent
     cpu = None
     if not args.no_cpu:
         import oracle
 
-        lam_s = lam[::2]
-        chi_o, S_o = oracle.lte(lam_s, atm.kappa0, atm.T, atm.rho)
+        chi_o, S_o = oracle.lte(lam, atm.kappa0, atm.T, atm.rho)
         sel = oracle.select(g, dirs)
-        t0 = time.perf_counter()
-        oracle.fs_voronoi(g, dirs, w, sel, chi_o, S_o, S_o)
-        dt = time.perf_counter() - t0
-        cpu = {"value": g.n * R * len(lam_s) / dt, "unit": "site*ray*lambda updates/s",
+        reps, dt = 0, 0.0
+        while reps < 4 and dt < 10.0:
+            t0 = time.perf_counter()
+            oracle.fs_voronoi(g, dirs, w, sel, chi_o, S_o, S_o)
+            dt += time.perf_counter() - t0
+            reps += 1
+        cpu = {"value": reps * updates / dt, "unit": "site*ray*lambda updates/s",
                "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": f"one FP64 formal solution: {g.n} sites x {R} rays x {len(lam_s)} of the {nl} "
-                         f"wavelengths ({dt:.1f} s)"}
-        log(f"CPU oracle {cpu['value']:.3e} updates/s on {cpu['cores']} threads")
+               "sample": f"{reps} FP64 formal solution(s) of the full workload ({g.n} sites x {R} rays x {nl} "
+                         f"wavelengths), {dt:.1f} s"}
+        log(f"CPU oracle {cpu['value']:.3e} updates/s on {cpu['cores']} threads ({dt:.1f} s)")
 
     out = {
         "metric": "site*ray*lambda updates/s, FP32 batched formal solution (vs FP64 plain) + %HBM roofline",
@@ -203,6 +226,7 @@ def main():
         "fp64_plain": fp64,
         "cpu_baseline": cpu,
         "setup_s": round(setup_s, 3),
+        "tuning": tuning,
     }
     print(json.dumps(out))
     G.close()

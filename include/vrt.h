@@ -147,6 +147,30 @@ void vrt_grid_destroy(vrt_grid grid);
 vrt_status vrt_grid_set_rays(vrt_grid grid, int32_t n_rays, const double *dir, const double *w,
                              double r_exp);
 
+/* Launch and layout knobs of a grid (used by the autotuner; defaults in brackets).
+ *   VRT_TUNE_RECORD_ORDER  order of the records inside one (level, ray)
+ *                          segment: 0 = site index, 1 = Morton order of the
+ *                          sites' horizontal position [1]. Takes effect at the
+ *                          next vrt_grid_set_rays.
+ *   VRT_TUNE_XCD_CHUNKS    0 = plain block order; k > 0 = hand each of k
+ *                          consecutive chunks of a launch's records to one of
+ *                          k accelerator dies, so neighbouring records share a
+ *                          die's L2 [8].
+ * Returns VRT_E_ARG for an unknown knob or value. Drops captured graphs. */
+#define VRT_TUNE_RECORD_ORDER 1
+#define VRT_TUNE_XCD_CHUNKS 2
+vrt_status vrt_grid_tune(vrt_grid grid, int32_t knob, int64_t value);
+
+/* Autotuner: times every combination of the knobs above (record order x
+ * {0, 8} XCD chunks) on a formal solution with the given arguments (as for
+ * vrt_formal_solution with VRT_EXEC_GRAPH), `reps` replays each after one
+ * warm-up, keeps the fastest setting on the grid and writes a one-line JSON
+ * report (host, may be NULL) of every candidate's mean time in ms. Re-packs
+ * the sweep records when the record order changes. Blocks. */
+vrt_status vrt_grid_autotune(vrt_grid grid, vrt_prec prec, int32_t n_lambda, const void *chi,
+                             const void *S, const void *I_bottom, const void *I_top, void *J,
+                             void *I_rays, int32_t reps, char *report, int64_t report_len);
+
 /* Sizes of a grid: number of sites, rays, the largest level count over rays
  * (number of planes on a regular grid) and the number of (ray, site) pairs
  * that fell back to the best z-upwind line because no neighbour lay ahead of

@@ -9,9 +9,11 @@
 // and are bounded by the longest path, so a pass without change is the fixed
 // point; concurrent reads of a neighbour being updated only delay that pass.
 // The order (level, site index) is a stable counting sort: each thread owns a
-// tile of consecutive site indices, counts levels inside it, an exclusive
-// scan over (level, tile) gives every tile's first slot per level, and the
-// tiles scatter their sites in index order.
+// tile of consecutive visiting positions, counts levels inside it, an
+// exclusive scan over (level, tile) gives every tile's first slot per level,
+// and the tiles scatter their sites in visiting order. Visiting the sites in
+// index order gives the (level, index) order; visiting them through another
+// permutation (e.g. a space-filling curve) orders each level by it instead.
 
 #include "vrt_internal.h"
 
@@ -52,14 +54,18 @@ __global__ void level_max_kernel(int64_t total, const int32_t *__restrict__ leve
 
 // cnt layout: [R][Lmax][ntiles]
 __global__ void level_count_kernel(int64_t n, int32_t R, int32_t Lmax, int64_t tile, int64_t ntiles,
-                                   const int32_t *__restrict__ level, int32_t *__restrict__ cnt) {
+                                   const int32_t *__restrict__ level, int32_t *__restrict__ cnt,
+                                   const int32_t *__restrict__ visit) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)R * ntiles) return;
   const int32_t r = (int32_t)(t / ntiles);
   const int64_t tl = t - (int64_t)r * ntiles;
   const int64_t i0 = tl * tile, i1 = (i0 + tile < n) ? i0 + tile : n;
   int32_t *c = cnt + (int64_t)r * Lmax * ntiles + tl;
-  for (int64_t i = i0; i < i1; ++i) c[(int64_t)level[(int64_t)r * n + i] * ntiles] += 1;
+  for (int64_t j = i0; j < i1; ++j) {
+    const int64_t i = visit ? visit[j] : j;
+    c[(int64_t)level[(int64_t)r * n + i] * ntiles] += 1;
+  }
 }
 
 // one thread per (ray, level): exclusive scan over tiles, level total out
@@ -96,7 +102,8 @@ __global__ void level_ptr_kernel(int32_t R, int32_t Lmax, const int64_t *__restr
 
 __global__ void level_scatter_kernel(int64_t n, int32_t R, int32_t Lmax, int64_t tile, int64_t ntiles,
                                      const int32_t *__restrict__ level, const int32_t *__restrict__ level_ptr,
-                                     int32_t *__restrict__ cnt, int32_t *__restrict__ order) {
+                                     int32_t *__restrict__ cnt, int32_t *__restrict__ order,
+                                     const int32_t *__restrict__ visit) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)R * ntiles) return;
   const int32_t r = (int32_t)(t / ntiles);
@@ -104,7 +111,8 @@ __global__ void level_scatter_kernel(int64_t n, int32_t R, int32_t Lmax, int64_t
   const int64_t i0 = tl * tile, i1 = (i0 + tile < n) ? i0 + tile : n;
   int32_t *c = cnt + (int64_t)r * Lmax * ntiles + tl;
   const int32_t *lp = level_ptr + (int64_t)r * (Lmax + 1);
-  for (int64_t i = i0; i < i1; ++i) {
+  for (int64_t j = i0; j < i1; ++j) {
+    const int64_t i = visit ? visit[j] : j;
     const int32_t l = level[(int64_t)r * n + i];
     const int64_t slot = (int64_t)lp[l] + c[(int64_t)l * ntiles];
     c[(int64_t)l * ntiles] += 1;
@@ -165,12 +173,12 @@ void launch_level_max(hipStream_t s, int64_t total, const int32_t *level, int32_
 }
 
 void launch_level_count(hipStream_t s, int64_t n, int32_t R, int32_t Lmax, int64_t tile, const int32_t *level,
-                        int32_t *cnt) {
+                        int32_t *cnt, const int32_t *visit) {
   const int64_t ntiles = (n + tile - 1) / tile;
   const int64_t total = (int64_t)R * ntiles;
   if (total == 0) return;
   hipLaunchKernelGGL(level_count_kernel, dim3(nblocks(total, 64)), dim3(64), 0, s, n, R, Lmax, tile, ntiles,
-                     level, cnt);
+                     level, cnt, visit);
   VRT_HIP(hipGetLastError());
 }
 
@@ -189,12 +197,12 @@ void launch_level_ptr(hipStream_t s, int32_t R, int32_t Lmax, const int64_t *tot
 }
 
 void launch_level_scatter(hipStream_t s, int64_t n, int32_t R, int32_t Lmax, int64_t tile, const int32_t *level,
-                          const int32_t *level_ptr, int32_t *cnt, int32_t *order) {
+                          const int32_t *level_ptr, int32_t *cnt, int32_t *order, const int32_t *visit) {
   const int64_t ntiles = (n + tile - 1) / tile;
   const int64_t total = (int64_t)R * ntiles;
   if (total == 0) return;
   hipLaunchKernelGGL(level_scatter_kernel, dim3(nblocks(total, 64)), dim3(64), 0, s, n, R, Lmax, tile, ntiles,
-                     level, level_ptr, cnt, order);
+                     level, level_ptr, cnt, order, visit);
   VRT_HIP(hipGetLastError());
 }
 

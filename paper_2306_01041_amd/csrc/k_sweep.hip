@@ -21,17 +21,48 @@
 
 namespace {
 
-template <typename T, int C>
+// Lane-vector of V elements (16-byte loads and stores when V > 1).
+template <typename T, int V> struct Lane {
+  typedef T type __attribute__((ext_vector_type(V)));
+  static __device__ __forceinline__ type load(const T *p) { return *reinterpret_cast<const type *>(p); }
+  static __device__ __forceinline__ void store(T *p, const type &v) { *reinterpret_cast<type *>(p) = v; }
+  static __device__ __forceinline__ T get(const type &v, int k) { return v[k]; }
+  static __device__ __forceinline__ void set(type &v, int k, T x) { v[k] = x; }
+};
+template <typename T> struct Lane<T, 1> {
+  typedef T type;
+  static __device__ __forceinline__ type load(const T *p) { return *p; }
+  static __device__ __forceinline__ void store(T *p, const type &v) { *p = v; }
+  static __device__ __forceinline__ T get(const type &v, int) { return v; }
+  static __device__ __forceinline__ void set(type &v, int, T x) { v = x; }
+};
+
+// Workgroups are handed to the accelerator dies (XCDs) round-robin. With
+// k > 1 chunks, block b is renumbered so that die (b mod k) works on the
+// (b mod k)-th contiguous chunk of the launch's records: records that are
+// neighbours in the (spatially sorted) record order share a die and its L2.
+__device__ __forceinline__ int64_t chunked_block(int32_t k) {
+  const int64_t b = blockIdx.x, nb = gridDim.x;
+  if (k <= 1 || nb < k) return b;
+  const int64_t x = b % k, j = b / k, per = nb / k, rem = nb % k;
+  return x * per + (x < rem ? x : rem) + j;
+}
+
+// C lanes per record, V consecutive wavelengths per lane (nl is a multiple of V).
+template <typename T, int C, int V>
 __global__ __launch_bounds__(256) void sweep_kernel(const int4 *__restrict__ ri,
                                                     const typename vrt::RecOf<T>::type *__restrict__ rf,
                                                     int64_t rec_begin, int64_t rec_count, int32_t nl, int64_t n,
                                                     const T *__restrict__ chi, const T *__restrict__ S,
-                                                    const T *__restrict__ Ibot, const T *__restrict__ Itop, T *I) {
+                                                    const T *__restrict__ Ibot, const T *__restrict__ Itop, T *I,
+                                                    int32_t xcd_chunks) {
+  using L = Lane<T, V>;
+  using VT = typename L::type;
   constexpr int SPW = 64 / C;
   const int lane = threadIdx.x & 63;
-  const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int64_t wave = chunked_block(xcd_chunks) * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const int64_t rec = wave * SPW + lane / C;
-  const int l0 = lane % C;
+  const int l0 = (lane % C) * V;
   if (rec >= rec_count) return;
   const int4 q = ri[rec_begin + rec];
   const int32_t site = q.x, k1 = q.y, k2 = q.z;
@@ -40,41 +71,69 @@ __global__ __launch_bounds__(256) void sweep_kernel(const int4 *__restrict__ ri,
   T *Iray = I + (int64_t)ray * n * nl;
   const int64_t bi = (int64_t)site * nl;
   if (k1 < 0) {
-    for (int l = l0; l < nl; l += C) {
-      T v = T(0);
-      if (up) v = Ibot[bi + l];
-      else if (Itop) v = Itop[bi + l];
-      Iray[bi + l] = v;
+    for (int l = l0; l < nl; l += C * V) {
+      VT v;
+      if (up) v = L::load(Ibot + bi + l);
+      else if (Itop) v = L::load(Itop + bi + l);
+      else v = VT(T(0));
+      L::store(Iray + bi + l, v);
     }
     return;
   }
   const auto f = rf[rec_begin + rec];
   const T w1 = f.w1, w2 = T(1) - f.w1;
   const T h1 = T(0.5) * f.ds1, h2 = T(0.5) * f.ds2;
+  const bool two = k2 >= 0;
   const int64_t b1 = (int64_t)k1 * nl;
-  const int64_t b2 = (int64_t)(k2 >= 0 ? k2 : k1) * nl;
-  for (int l = l0; l < nl; l += C) {
-    const T ci = chi[bi + l], si = S[bi + l];
-    T E, pu, p0;
-    vrt::Seg<T>::weights((chi[b1 + l] + ci) * h1, E, pu, p0);
-    const T Ia = E * Iray[b1 + l] + pu * S[b1 + l] + p0 * si;
-    T Iv = Ia;
-    if (k2 >= 0) {
-      vrt::Seg<T>::weights((chi[b2 + l] + ci) * h2, E, pu, p0);
-      const T Ib = E * Iray[b2 + l] + pu * S[b2 + l] + p0 * si;
-      Iv = w1 * Ia + w2 * Ib;
+  const int64_t b2 = (int64_t)(two ? k2 : k1) * nl;
+  for (int l = l0; l < nl; l += C * V) {
+    const VT ci = L::load(chi + bi + l), si = L::load(S + bi + l);
+    const VT c1 = L::load(chi + b1 + l), s1 = L::load(S + b1 + l), u1 = L::load(Iray + b1 + l);
+    VT c2, s2, u2;
+    if (two) {
+      c2 = L::load(chi + b2 + l);
+      s2 = L::load(S + b2 + l);
+      u2 = L::load(Iray + b2 + l);
     }
-    Iray[bi + l] = Iv;
+    VT out;
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      const T cik = L::get(ci, k), sik = L::get(si, k);
+      T E, pu, p0;
+      vrt::Seg<T>::weights((L::get(c1, k) + cik) * h1, E, pu, p0);
+      T Iv = E * L::get(u1, k) + pu * L::get(s1, k) + p0 * sik;
+      if (two) {
+        vrt::Seg<T>::weights((L::get(c2, k) + cik) * h2, E, pu, p0);
+        const T Ib = E * L::get(u2, k) + pu * L::get(s2, k) + p0 * sik;
+        Iv = w1 * Iv + w2 * Ib;
+      }
+      L::set(out, k, Iv);
+    }
+    L::store(Iray + bi + l, out);
   }
 }
 
-template <typename T>
+// J = sum_r w_r I_r with double accumulation (ray order fixed); V elements per thread.
+template <typename T, int V>
 __global__ __launch_bounds__(256) void jreduce_kernel(const T *__restrict__ I, int32_t R, int64_t nn,
                                                       const double *__restrict__ w, T *__restrict__ J) {
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nn; t += (int64_t)gridDim.x * blockDim.x) {
-    double acc = 0.0;
-    for (int32_t r = 0; r < R; ++r) acc += w[r] * (double)I[(int64_t)r * nn + t];
-    J[t] = (T)acc;
+  using L = Lane<T, V>;
+  using VT = typename L::type;
+  const int64_t nv = nn / V;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nv; t += (int64_t)gridDim.x * blockDim.x) {
+    double acc[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) acc[k] = 0.0;
+    for (int32_t r = 0; r < R; ++r) {
+      const VT x = L::load(I + (int64_t)r * nn + t * V);
+      const double wr = w[r];
+#pragma unroll
+      for (int k = 0; k < V; ++k) acc[k] += wr * (double)L::get(x, k);
+    }
+    VT out;
+#pragma unroll
+    for (int k = 0; k < V; ++k) L::set(out, k, (T)acc[k]);
+    L::store(J + t * V, out);
   }
 }
 
@@ -88,15 +147,34 @@ __global__ void emergent_kernel(int64_t total, int32_t nl, int64_t n, const int3
   out[t] = I[((int64_t)em_ray[e] * n + em_site[e]) * nl + l];
 }
 
-template <typename T, int C>
+template <typename T, int C, int V>
 void launch_c(hipStream_t s, const int4 *ri, const typename vrt::RecOf<T>::type *rf, int64_t b, int64_t c, int32_t nl,
-              int64_t n, const T *chi, const T *S, const T *Ibot, const T *Itop, T *I) {
+              int64_t n, const T *chi, const T *S, const T *Ibot, const T *Itop, T *I, int32_t xc) {
   constexpr int SPW = 64 / C;
   const int64_t waves = (c + SPW - 1) / SPW;
   const int64_t blocks = (waves + 3) / 4;
-  hipLaunchKernelGGL((sweep_kernel<T, C>), dim3((unsigned)blocks), dim3(256), 0, s, ri, rf, b, c, nl, n, chi, S,
-                     Ibot, Itop, I);
+  hipLaunchKernelGGL((sweep_kernel<T, C, V>), dim3((unsigned)blocks), dim3(256), 0, s, ri, rf, b, c, nl, n, chi, S,
+                     Ibot, Itop, I, xc);
 }
+
+// lanes per record for m lane-vectors per row: the smallest power of two >= m, at most 64
+template <typename T, int V>
+void launch_v(hipStream_t s, const int4 *ri, const typename vrt::RecOf<T>::type *rf, int64_t b, int64_t c, int32_t nl,
+              int64_t n, const T *chi, const T *S, const T *Ibot, const T *Itop, T *I, int32_t xc) {
+  const int32_t m = nl / V;
+  if (m >= 33) launch_c<T, 64, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc);
+  else if (m >= 17) launch_c<T, 32, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc);
+  else if (m >= 9) launch_c<T, 16, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc);
+  else if (m >= 5) launch_c<T, 8, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc);
+  else if (m >= 3) launch_c<T, 4, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc);
+  else if (m == 2) launch_c<T, 2, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc);
+  else launch_c<T, 1, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc);
+}
+
+// 16-byte lane vectors when the row length allows (and rows then stay 16-byte aligned)
+template <typename T> constexpr int kVec = 16 / sizeof(T);
+
+inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 }  // namespace
 
@@ -105,24 +183,27 @@ namespace vrt {
 template <typename T>
 void launch_sweep(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *rf, int64_t rec_begin,
                   int64_t rec_count, int32_t nl, int64_t n, const T *chi, const T *S, const T *Ibot, const T *Itop,
-                  T *I) {
+                  T *I, int32_t xcd_chunks) {
   if (rec_count <= 0) return;
-  if (nl >= 33) launch_c<T, 64>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I);
-  else if (nl >= 17) launch_c<T, 32>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I);
-  else if (nl >= 9) launch_c<T, 16>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I);
-  else if (nl >= 5) launch_c<T, 8>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I);
-  else if (nl >= 3) launch_c<T, 4>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I);
-  else if (nl == 2) launch_c<T, 2>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I);
-  else launch_c<T, 1>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I);
+  const bool aligned = aligned16(chi) && aligned16(S) && aligned16(Ibot) && aligned16(Itop) && aligned16(I);
+  if (aligned && nl % kVec<T> == 0)
+    launch_v<T, kVec<T>>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I, xcd_chunks);
+  else
+    launch_v<T, 1>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I, xcd_chunks);
   VRT_HIP(hipGetLastError());
 }
 
 template <typename T>
 void launch_jreduce(hipStream_t s, const T *I, int32_t R, int64_t nn, const double *w, T *J) {
   if (nn == 0) return;
-  int64_t blocks = (nn + 255) / 256;
+  const bool vec = nn % kVec<T> == 0 && aligned16(I) && aligned16(J);
+  const int64_t items = vec ? nn / kVec<T> : nn;
+  int64_t blocks = (items + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(jreduce_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, I, R, nn, w, J);
+  if (vec)
+    hipLaunchKernelGGL((jreduce_kernel<T, kVec<T>>), dim3((unsigned)blocks), dim3(256), 0, s, I, R, nn, w, J);
+  else
+    hipLaunchKernelGGL((jreduce_kernel<T, 1>), dim3((unsigned)blocks), dim3(256), 0, s, I, R, nn, w, J);
   VRT_HIP(hipGetLastError());
 }
 
@@ -137,9 +218,9 @@ void launch_emergent(hipStream_t s, int64_t total, int32_t nl, int64_t n, const 
 }
 
 template void launch_sweep<float>(hipStream_t, const int4 *, const RecF32 *, int64_t, int64_t, int32_t, int64_t,
-                                  const float *, const float *, const float *, const float *, float *);
+                                  const float *, const float *, const float *, const float *, float *, int32_t);
 template void launch_sweep<double>(hipStream_t, const int4 *, const RecF64 *, int64_t, int64_t, int32_t, int64_t,
-                                   const double *, const double *, const double *, const double *, double *);
+                                   const double *, const double *, const double *, const double *, double *, int32_t);
 template void launch_jreduce<float>(hipStream_t, const float *, int32_t, int64_t, const double *, float *);
 template void launch_jreduce<double>(hipStream_t, const double *, int32_t, int64_t, const double *, double *);
 template void launch_emergent<float>(hipStream_t, int64_t, int32_t, int64_t, const int32_t *, const int32_t *,

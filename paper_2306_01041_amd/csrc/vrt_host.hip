@@ -237,11 +237,42 @@ void set_rays_voronoi(vrt_grid g) {
   d_lp.alloc((size_t)R * (Lmax + 1) * 4);
   d_nl.alloc((size_t)R * 4);
   VRT_HIP(hipMemsetAsync(d_cnt.p, 0, (size_t)R * Lmax * ntiles * 4, s));
-  vrt::launch_level_count(s, n, R, Lmax, tile, level, d_cnt.as<int32_t>());
+  vrt::launch_level_count(s, n, R, Lmax, tile, level, d_cnt.as<int32_t>(), nullptr);
   vrt::launch_level_scan(s, R, Lmax, ntiles, d_cnt.as<int32_t>(), d_tot.as<int64_t>());
   vrt::launch_level_ptr(s, R, Lmax, d_tot.as<int64_t>(), d_lp.as<int32_t>(), d_nl.as<int32_t>());
   vrt::launch_level_scatter(s, n, R, Lmax, tile, level, d_lp.as<int32_t>(), d_cnt.as<int32_t>(),
-                            g->d_order.as<int32_t>());
+                            g->d_order.as<int32_t>(), nullptr);
+  // sweep records: the same levels, each level visited along a space-filling
+  // curve of the horizontal position, so neighbouring records share upwind sites
+  DevBuf d_rec_order, d_visit;
+  const int32_t *rec_order = g->d_order.as<int32_t>();
+  if (g->record_order == 1 && n > 1) {
+    std::vector<uint64_t> key((size_t)n);
+    const std::vector<double> &xyz = g->h_xyz;
+    const double Lx = g->hi[0] - g->lo[0], Ly = g->hi[1] - g->lo[1];
+    for (int64_t i = 0; i < n; ++i) {
+      auto q = [](double v) {
+        double f = std::floor(v * 65536.0);
+        return (uint32_t)std::min(65535.0, std::max(0.0, f));
+      };
+      const uint32_t ux = q((xyz[3 * i] - g->lo[0]) / Lx), uy = q((xyz[3 * i + 1] - g->lo[1]) / Ly);
+      uint64_t m = 0;
+      for (int b = 0; b < 16; ++b) m |= (uint64_t)((ux >> b) & 1u) << (2 * b) | (uint64_t)((uy >> b) & 1u) << (2 * b + 1);
+      key[(size_t)i] = (m << 31) | (uint64_t)i;
+    }
+    std::sort(key.begin(), key.end());
+    std::vector<int32_t> visit((size_t)n);
+    for (int64_t i = 0; i < n; ++i) visit[(size_t)i] = (int32_t)(key[(size_t)i] & 0x7fffffffu);
+    upload(d_visit, visit.data(), visit.size(), s);
+    d_rec_order.alloc((size_t)RN * 4);
+    VRT_HIP(hipMemsetAsync(d_cnt.p, 0, (size_t)R * Lmax * ntiles * 4, s));
+    vrt::launch_level_count(s, n, R, Lmax, tile, level, d_cnt.as<int32_t>(), d_visit.as<int32_t>());
+    vrt::launch_level_scan(s, R, Lmax, ntiles, d_cnt.as<int32_t>(), d_tot.as<int64_t>());
+    vrt::launch_level_scatter(s, n, R, Lmax, tile, level, d_lp.as<int32_t>(), d_cnt.as<int32_t>(),
+                              d_rec_order.as<int32_t>(), d_visit.as<int32_t>());
+    rec_order = d_rec_order.as<int32_t>();
+    VRT_HIP(hipStreamSynchronize(s));  // visit lives in host memory until the copy is done
+  }
   std::vector<int32_t> lp((size_t)R * (Lmax + 1));
   g->n_levels.assign((size_t)R, 0);
   VRT_HIP(hipMemcpyAsync(lp.data(), d_lp.p, lp.size() * 4, hipMemcpyDeviceToHost, s));
@@ -278,7 +309,7 @@ void set_rays_voronoi(vrt_grid g) {
   g->d_ri.alloc((size_t)RN * sizeof(int4));
   g->d_rf32.alloc((size_t)RN * sizeof(vrt::RecF32));
   g->d_rf64.alloc((size_t)RN * sizeof(vrt::RecF64));
-  vrt::launch_pack(s, n, R, Lmax, g->d_order.as<int32_t>(), level, d_lp.as<int32_t>(), d_seg.as<int64_t>(),
+  vrt::launch_pack(s, n, R, Lmax, rec_order, level, d_lp.as<int32_t>(), d_seg.as<int64_t>(),
                    g->d_k1.as<int32_t>(), g->d_k2.as<int32_t>(), g->d_w1.as<double>(), g->d_ds1.as<double>(),
                    g->d_ds2.as<double>(), g->d_dirs.as<double>(), g->d_ri.as<int4>(), g->d_rf32.as<vrt::RecF32>(),
                    g->d_rf64.as<vrt::RecF64>());
@@ -321,9 +352,11 @@ void enqueue_fs(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *chi
   if (g->kind == 0) {
     const int4 *ri = g->d_ri.as<int4>();
     const auto *rf = records<T>(g);
+    const int32_t xc = g->xcd_chunks;
     auto sweep = [&](int64_t b, int64_t c) {
       if (c <= 0) return;
-      timed_launch(ctx, s, tm, 0, c * nl, [&] { vrt::launch_sweep<T>(s, ri, rf, b, c, nl, n, chi, S, Ib, It, I); });
+      timed_launch(ctx, s, tm, 0, c * nl,
+                   [&] { vrt::launch_sweep<T>(s, ri, rf, b, c, nl, n, chi, S, Ib, It, I, xc); });
     };
     if (ex == VRT_EXEC_PLAIN) {
       for (int32_t r = 0; r < R; ++r)
@@ -560,6 +593,7 @@ vrt_status vrt_grid_create_voronoi(vrt_ctx ctx, int64_t n, const double *xyz, co
     }
     upload(g->d_wall, wall, (size_t)n, s);
     g->h_wall.assign(wall, wall + n);
+    g->h_xyz.assign(xyz, xyz + 3 * n);
     VRT_HIP(hipStreamSynchronize(s));
     *out = g.release();
     return VRT_OK;
@@ -630,6 +664,91 @@ vrt_status vrt_grid_set_rays(vrt_grid g, int32_t n_rays, const double *dir, cons
       g->n_levels.assign((size_t)n_rays, g->nz);
     }
     build_emergent_index(g);
+    return VRT_OK;
+  });
+}
+
+vrt_status vrt_grid_tune(vrt_grid g, int32_t knob, int64_t value) {
+  if (!g) return VRT_E_ARG;
+  return guarded(g->ctx, [&] {
+    if (knob == VRT_TUNE_RECORD_ORDER) {
+      if (value != 0 && value != 1) fail(VRT_E_ARG, "record order must be 0 or 1");
+      g->record_order = (int)value;
+    } else if (knob == VRT_TUNE_XCD_CHUNKS) {
+      if (value < 0 || value > 64) fail(VRT_E_ARG, "XCD chunk count must be in 0..64");
+      g->xcd_chunks = (int)value;
+    } else {
+      fail(VRT_E_ARG, "unknown tuning knob %d", knob);
+    }
+    g->drop_graphs();
+    return VRT_OK;
+  });
+}
+
+vrt_status vrt_grid_autotune(vrt_grid g, vrt_prec prec, int32_t n_lambda, const void *chi, const void *S,
+                             const void *I_bottom, const void *I_top, void *J, void *I_rays, int32_t reps, char *report,
+                             int64_t report_len) {
+  if (!g) return VRT_E_ARG;
+  return guarded(g->ctx, [&] {
+    if (!valid_prec(prec) || n_lambda <= 0 || reps <= 0) fail(VRT_E_ARG, "bad autotune arguments");
+    if (g->R == 0) fail(VRT_E_STATE, "rays not set");
+    if (g->n == 0 || g->kind != 0) return VRT_OK;
+    hipStream_t s = g->ctx->stream;
+    hipEvent_t e0, e1;
+    VRT_HIP(hipEventCreate(&e0));
+    VRT_HIP(hipEventCreate(&e1));
+    std::string rep = "{\"candidates\": [";
+    double best = 1e300;
+    int best_order = g->record_order, best_xcd = g->xcd_chunks;
+    bool first = true;
+    for (int order = 0; order <= 1; ++order) {
+      if (order != g->record_order || first) {
+        g->record_order = order;
+        g->drop_graphs();
+        set_rays_voronoi(g);
+      }
+      for (int xcd : {0, 8}) {
+        g->xcd_chunks = xcd;
+        g->drop_graphs();
+        auto run = [&] {
+          if (prec == VRT_F32)
+            formal_solution<float>(g, VRT_EXEC_GRAPH, n_lambda, chi, S, I_bottom, I_top, J, I_rays);
+          else
+            formal_solution<double>(g, VRT_EXEC_GRAPH, n_lambda, chi, S, I_bottom, I_top, J, I_rays);
+        };
+        run();  // capture + warm-up
+        VRT_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r) run();
+        VRT_HIP(hipEventRecord(e1, s));
+        VRT_HIP(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        VRT_HIP(hipEventElapsedTime(&ms, e0, e1));
+        const double mean = ms / reps;
+        char buf[128];
+        snprintf(buf, sizeof buf, "%s{\"record_order\": %d, \"xcd_chunks\": %d, \"ms\": %.5f}", first ? "" : ", ",
+                 order, xcd, mean);
+        rep += buf;
+        first = false;
+        if (mean < best) {
+          best = mean;
+          best_order = order;
+          best_xcd = xcd;
+        }
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best_order != g->record_order) {
+      g->record_order = best_order;
+      set_rays_voronoi(g);
+    }
+    g->xcd_chunks = best_xcd;
+    g->drop_graphs();
+    char buf[160];
+    snprintf(buf, sizeof buf, "], \"chosen\": {\"record_order\": %d, \"xcd_chunks\": %d, \"ms\": %.5f}}", best_order,
+             best_xcd, best);
+    rep += buf;
+    if (report && report_len > 0) snprintf(report, (size_t)report_len, "%s", rep.c_str());
     return VRT_OK;
   });
 }

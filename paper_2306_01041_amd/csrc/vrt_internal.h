@@ -104,6 +104,7 @@ struct vrt_grid_s {
   int64_t m = 0;
   vrt::DevBuf d_xyz, d_ptr, d_idx, d_shift, d_wall;
   std::vector<uint8_t> h_wall;
+  std::vector<double> h_xyz;
 
   // regular geometry
   int32_t nx = 0, ny = 0, nz = 0;
@@ -140,6 +141,10 @@ struct vrt_grid_s {
   std::vector<double> h_lam;
   vrt::DevBuf d_lam;
 
+  // tuning knobs
+  int record_order = 1;  // 0 site index, 1 Morton (x, y) within a level
+  int xcd_chunks = 8;    // 0 = plain block order
+
   // scratch for per-ray intensities when the caller passes none
   vrt::DevBuf d_Iscr;
   const void *last_I = nullptr;
@@ -163,13 +168,14 @@ void launch_level_fill(hipStream_t s, int64_t total, int32_t *level);
 void launch_level_relax(hipStream_t s, int64_t n, int32_t R, const int32_t *k1, const int32_t *k2,
                         int32_t *level, int32_t *changed);
 void launch_level_count(hipStream_t s, int64_t n, int32_t R, int32_t Lmax, int64_t tile,
-                        const int32_t *level, int32_t *cnt);
+                        const int32_t *level, int32_t *cnt, const int32_t *visit);
 void launch_level_scan(hipStream_t s, int32_t R, int32_t Lmax, int64_t ntiles, int32_t *cnt,
                        int64_t *totals);
 void launch_level_ptr(hipStream_t s, int32_t R, int32_t Lmax, const int64_t *totals, int32_t *level_ptr,
                       int32_t *n_levels);
 void launch_level_scatter(hipStream_t s, int64_t n, int32_t R, int32_t Lmax, int64_t tile,
-                          const int32_t *level, const int32_t *level_ptr, int32_t *cnt, int32_t *order);
+                          const int32_t *level, const int32_t *level_ptr, int32_t *cnt, int32_t *order,
+                          const int32_t *visit);
 void launch_level_max(hipStream_t s, int64_t total, const int32_t *level, int32_t *out_max);
 void launch_pack(hipStream_t s, int64_t n, int32_t R, int32_t Lmax, const int32_t *order,
                  const int32_t *level, const int32_t *level_ptr, const int64_t *seg_off,
@@ -180,7 +186,7 @@ void launch_pack(hipStream_t s, int64_t n, int32_t R, int32_t Lmax, const int32_
 template <typename T>
 void launch_sweep(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *rf, int64_t rec_begin,
                   int64_t rec_count, int32_t nl, int64_t n, const T *chi, const T *S, const T *Ibot,
-                  const T *Itop, T *I);
+                  const T *Itop, T *I, int32_t xcd_chunks);
 template <typename T>
 void launch_jreduce(hipStream_t s, const T *I, int32_t R, int64_t nn, const double *w, T *J);
 template <typename T>

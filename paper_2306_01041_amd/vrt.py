@@ -33,6 +33,9 @@ VRT_E_NOMEM = -5
 VRT_E_NUMERIC = -6
 VRT_E_STATE = -7
 
+VRT_TUNE_RECORD_ORDER = 1
+VRT_TUNE_XCD_CHUNKS = 2
+
 VRT_F64 = 0
 VRT_F32 = 1
 VRT_EXEC_PLAIN = 0
@@ -74,6 +77,9 @@ vrt_grid_create_regular = _sig("vrt_grid_create_regular", _st, [_vp, ctypes.c_in
                                                                 ctypes.POINTER(_vp)])
 vrt_grid_destroy = _sig("vrt_grid_destroy", None, [_vp])
 vrt_grid_set_rays = _sig("vrt_grid_set_rays", _st, [_vp, ctypes.c_int32, _d, _d, ctypes.c_double])
+vrt_grid_tune = _sig("vrt_grid_tune", _st, [_vp, ctypes.c_int32, ctypes.c_int64])
+vrt_grid_autotune = _sig("vrt_grid_autotune", _st, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp,
+                                                    _vp, ctypes.c_int32, ctypes.c_char_p, ctypes.c_int64])
 vrt_grid_info = _sig("vrt_grid_info", _st, [_vp, _i64, _i32, _i32, _i64])
 vrt_grid_schedule = _sig("vrt_grid_schedule", _st, [_vp, ctypes.c_int32, _i32, _i32, _d, _d, _d, _i32, _i32, _i32,
                                                     _i32])
@@ -221,6 +227,9 @@ class Grid:
         w = np.ascontiguousarray(w, np.float64)
         self.ctx.check(vrt_grid_set_rays(self.handle, dirs.shape[0], _p(dirs, _d), _p(w, _d), float(r_exp)))
 
+    def tune(self, knob: int, value: int):
+        self.ctx.check(vrt_grid_tune(self.handle, int(knob), int(value)))
+
     def info(self):
         n = ctypes.c_int64()
         r = ctypes.c_int32()
@@ -317,3 +326,19 @@ def emergent_gather(grid: Grid, out, I_rays=None):
     _need(out, (int(off[-1]), nl), out.dtype, "out")
     _need(I_rays, (inf["n_rays"], inf["n_sites"], nl), out.dtype, "I_rays")
     grid.ctx.check(vrt_emergent_gather(grid.handle, _prec_of(out), int(nl), _dev(I_rays), _dev(out)))
+
+
+def autotune(grid: Grid, chi, S, J, I_bottom=None, I_top=None, I_rays=None, reps: int = 5):
+    """Time the grid's launch/layout knobs on this formal solution, keep the fastest; returns the report dict."""
+    import json
+
+    inf = grid.info()
+    n, R = inf["n_sites"], inf["n_rays"]
+    nl = chi.shape[1]
+    for t, name in ((chi, "chi"), (S, "S"), (J, "J"), (I_bottom, "I_bottom"), (I_top, "I_top")):
+        _need(t, (n, nl), chi.dtype, name)
+    _need(I_rays, (R, n, nl), chi.dtype, "I_rays")
+    buf = ctypes.create_string_buffer(4096)
+    grid.ctx.check(vrt_grid_autotune(grid.handle, _prec_of(chi), int(nl), _dev(chi), _dev(S), _dev(I_bottom),
+                                     _dev(I_top), _dev(J), _dev(I_rays), int(reps), buf, 4096))
+    return json.loads(buf.value.decode() or "{}")

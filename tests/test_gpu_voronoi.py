@@ -255,3 +255,41 @@ def test_errors_do_not_launch(v, ctx, quad, grids):
     with pytest.raises(v.VrtError):
         G.set_rays(bad, w)
     G.close()
+
+
+def test_tuning_knobs_do_not_change_results(v, ctx, quad, grids):
+    """Record order and die-chunk mapping only reorder independent work: the
+    results are bit-identical for every setting, and the autotuner reports
+    every candidate and keeps one of them."""
+    flush("tuning knobs")
+    atm, g = grids[16384]
+    dirs, w = quad
+    chi_o, S_o = _fields(atm, 64, 5)
+    f = torch.float32
+    chi, S = to_dev(chi_o, f), to_dev(S_o, f)
+    ref = None
+    for order in (0, 1):
+        for xcd in (0, 3, 8):
+            G = v.Grid.from_synth(ctx, g)
+            G.tune(v.VRT_TUNE_RECORD_ORDER, order)
+            G.tune(v.VRT_TUNE_XCD_CHUNKS, xcd)
+            G.set_rays(dirs, w)
+            J = torch.empty_like(chi)
+            v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_GRAPH)
+            torch.cuda.synchronize()
+            out = J.cpu().numpy()
+            if ref is None:
+                ref = out
+            assert np.array_equal(out, ref), (order, xcd)
+            G.close()
+    G = _gpu_grid(v, ctx, g, dirs, w)
+    J = torch.empty_like(chi)
+    rep = v.autotune(G, chi, S, J, reps=2)
+    assert len(rep["candidates"]) == 4
+    assert rep["chosen"]["ms"] == min(c["ms"] for c in rep["candidates"])
+    v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_GRAPH)
+    torch.cuda.synchronize()
+    assert np.array_equal(J.cpu().numpy(), ref)
+    with pytest.raises(v.VrtError):
+        G.tune(99, 1)
+    G.close()

@@ -47,6 +47,25 @@ def sweep_bytes_per_update(nl: int, fp: int) -> float:
     return 3.0 * fp + (16.0 + 4.0 * fp) / nl
 
 
+def counter_traffic(nl, n, mode):
+    """HBM bytes per sweep launch measured by rocprofv3 counters (FETCH_SIZE x
+    its copy-kernel calibration + WRITE_SIZE), read from the committed profile
+    summary, or None when that summary was taken on another workload or on
+    kernel sources that have changed since."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "sweep_kernel_c1_counters.json")
+    if mode == "persistent" or nl != 64 or n != 262144 or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in ("paper_2306_01041_amd/csrc/k_sweep.hip", "paper_2306_01041_amd/csrc/segment.h"):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest()[:16] != rec.get("source_sha256_16"):
+        return None
+    return rec["sweep_bytes_per_launch"]["total"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -56,8 +75,8 @@ def main():
     ap.add_argument("--nl", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU baseline")
-    ap.add_argument("--mode", choices=["graph", "batched"], default="graph",
-                    help="launch the timed steps from a captured graph or eagerly")
+    ap.add_argument("--mode", choices=["auto", "graph", "batched", "persistent"], default="auto",
+                    help="launch mode of the timed steps (auto: the faster of graph and persistent)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (to scale HBM counters) and exit")
     args = ap.parse_args()
@@ -112,7 +131,21 @@ def main():
     off, _ = G.emergent_index()
     em = torch.empty((int(off[-1]), nl), dtype=f32, device=dev)
 
-    mode = v.VRT_EXEC_GRAPH if args.mode == "graph" else v.VRT_EXEC_BATCHED
+    modes = {"graph": v.VRT_EXEC_GRAPH, "batched": v.VRT_EXEC_BATCHED, "persistent": v.VRT_EXEC_PERSISTENT}
+    mode_times = {}
+    if args.mode == "auto":
+        for name in ("graph", "persistent"):
+            for _ in range(2):
+                v.formal_solution(G, chi, S, J, exec_mode=modes[name])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                v.formal_solution(G, chi, S, J, exec_mode=modes[name])
+            G.device_status()
+            mode_times[name] = (time.perf_counter() - t0) * 1e3 / 5
+        args.mode = min(mode_times, key=mode_times.get)
+        log(f"launch modes (ms per formal solution): {mode_times} -> {args.mode}")
+    mode = modes[args.mode]
 
     def step():
         v.lte_continuum(G, lam, atm.kappa0, T, rho, chi, S)
@@ -132,30 +165,43 @@ def main():
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    G.device_status()
     ms_step = (t1 - t0) * 1e3 / args.steps
     updates = g.n * R * nl
     value = updates / (ms_step * 1e-3)
     log(f"FP32 {args.mode} step {ms_step:.3f} ms -> {value:.3e} updates/s")
 
-    # roofline of the dominant kernel: eager batched launches with HIP events on the library's stream
+    # roofline of the dominant kernel (the sweep): HIP events on the library's
+    # stream around the formal solution as launched in the timed steps, minus the
+    # angle-quadrature kernel timed on its own (one launch), over the sweep launches
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    nprof = 10
+    ev0.record(stream)
+    for _ in range(nprof):
+        v.formal_solution(G, chi, S, J, exec_mode=mode)
+    ev1.record(stream)
+    ev1.synchronize()
+    fs_ms = ev0.elapsed_time(ev1) / nprof
     ctx.profile_reset()
     ctx.set_profiling(True)
-    nprof = 3
-    for _ in range(nprof):
-        v.lte_continuum(G, lam, atm.kappa0, T, rho, chi, S)
+    for _ in range(3):
         v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_BATCHED)
-    sw_ms, sw_launches, sw_units = ctx.profile(0)
+    sw_ms_ev, sw_launches, sw_units = ctx.profile(0)
     jr_ms, jr_launches, jr_units = ctx.profile(1)
     ctx.set_profiling(False)
     torch.cuda.synchronize()
+    jr_one = jr_ms / jr_launches
+    launches = sw_launches // 3 if args.mode != "persistent" else 1
+    sweep_ms = fs_ms - jr_one
     bpu = sweep_bytes_per_update(nl, 4)
-    avg_launch_ms = sw_ms / sw_launches
-    bytes_per_launch = bpu * sw_units / sw_launches
+    avg_launch_ms = sweep_ms / launches
+    bytes_per_launch = bpu * updates / launches
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
-    jr_bytes = (4.0 + 4.0 / R) * jr_units  # read every ray's I once, write J once
-    log(f"sweep: {sw_launches // nprof} launches/step, mean {avg_launch_ms * 1e3:.1f} us, "
-        f"{achieved:.0f} GB/s algorithmic; J reduction {jr_ms / jr_launches:.3f} ms "
-        f"({jr_bytes / jr_launches / (jr_ms / jr_launches * 1e-3) / 1e9:.0f} GB/s)")
+    jr_bytes = (4.0 + 4.0 / R) * jr_units / jr_launches  # read every ray's I once, write J once
+    traffic = counter_traffic(nl, g.n, args.mode)
+    log(f"sweep: {launches} launches/step, {sweep_ms:.3f} ms, mean {avg_launch_ms * 1e3:.2f} us/launch, "
+        f"{achieved:.0f} GB/s algorithmic (counters: {traffic}); J quadrature {jr_one:.3f} ms "
+        f"({jr_bytes / (jr_one * 1e-3) / 1e9:.0f} GB/s)")
 
     # plain FP64 GPU path
     fp64 = None
@@ -213,15 +259,20 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
+        "launch_mode": args.mode,
+        "mode_ms": mode_times,
         "data": "synthetic (seeded Bifrost-like stratified atmosphere, rejection-sampled Voronoi sites)",
         "config": {"workload": f"LTE continuum formal solution, Voronoi grid {g.n} sites, {nl} wavelengths "
                                f"400-900 nm, {R} rays, FP32 sweeps with FP64 J accumulation",
-                   "sites": g.n, "rays": R, "wavelengths": nl, "levels_max": info["max_levels"],
-                   "launches_per_step": sw_launches // nprof + 1},
+                   "sites": g.n, "rays": R, "wavelengths": nl, "levels_max": info["max_levels"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "sweep_kernel<float,64>", "bytes_per_update": round(bpu, 4),
-                     "mean_launch_us": round(avg_launch_ms * 1e3, 2)},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic),
+                     "algorithmic_bytes_per_launch": round(bytes_per_launch),
+                     "kernel": ("persistent_sweep_kernel<float,16,4>" if args.mode == "persistent"
+                                else "sweep_kernel<float,16,4>"), "bytes_per_update": round(bpu, 4),
+                     "mean_launch_us": round(avg_launch_ms * 1e3, 2), "launches_per_step": launches,
+                     "sweep_ms_per_step": round(sweep_ms, 4), "j_quadrature_ms": round(jr_one, 4)},
         "whole_step_effective_GBs": round(updates * (20.0 + 20.0 / nl) / (ms_step * 1e-3) / 1e9, 1),
         "fp64_plain": fp64,
         "cpu_baseline": cpu,

@@ -53,14 +53,24 @@ typedef int32_t vrt_status;
 #define VRT_E_NOMEM (-5)      /* device or host allocation failed */
 #define VRT_E_NUMERIC (-6)    /* NaN, Inf or negative opacity; NaN source change */
 #define VRT_E_STATE (-7)      /* call out of order (e.g. no rays set yet) */
+#define VRT_E_TIMEOUT (-8)    /* a bounded device-side wait gave up; outputs invalid */
 
 typedef enum { VRT_F64 = 0, VRT_F32 = 1 } vrt_prec;
 
 /* How a formal solution is launched.
- * PLAIN:   one kernel per (ray, level) of the upwind schedule, rays in turn.
- * BATCHED: one kernel per level step with all rays in flight together.
- * GRAPH:   BATCHED, captured once into a HIP graph and replayed. */
-typedef enum { VRT_EXEC_PLAIN = 0, VRT_EXEC_BATCHED = 1, VRT_EXEC_GRAPH = 2 } vrt_exec;
+ * PLAIN:      one kernel per (ray, level) of the upwind schedule, rays in turn.
+ * BATCHED:    one kernel per level step with all rays in flight together.
+ * GRAPH:      BATCHED, captured once into a HIP graph and replayed.
+ * PERSISTENT: one cooperative kernel for all rays and levels; each site waits
+ *             for the completion stamps of its upwind sites (Voronoi grids;
+ *             regular grids fall back to GRAPH). Check vrt_grid_device_status
+ *             after synchronising to learn whether a bounded wait gave up. */
+typedef enum {
+  VRT_EXEC_PLAIN = 0,
+  VRT_EXEC_BATCHED = 1,
+  VRT_EXEC_GRAPH = 2,
+  VRT_EXEC_PERSISTENT = 3
+} vrt_exec;
 
 typedef struct vrt_ctx_s *vrt_ctx;
 typedef struct vrt_grid_s *vrt_grid;
@@ -159,6 +169,12 @@ vrt_status vrt_grid_set_rays(vrt_grid grid, int32_t n_rays, const double *dir, c
  * Returns VRT_E_ARG for an unknown knob or value. Drops captured graphs. */
 #define VRT_TUNE_RECORD_ORDER 1
 #define VRT_TUNE_XCD_CHUNKS 2
+/*   VRT_TUNE_SPIN_CAP       bound on the polls of one wait in the persistent
+ *                           sweep [2^22]; a wait that exceeds it gives up.
+ *   VRT_TUNE_PERSIST_BLOCKS cap on the persistent sweep's workgroups
+ *                           [0 = as many as can be resident]. */
+#define VRT_TUNE_SPIN_CAP 3
+#define VRT_TUNE_PERSIST_BLOCKS 4
 vrt_status vrt_grid_tune(vrt_grid grid, int32_t knob, int64_t value);
 
 /* Autotuner: times every combination of the knobs above (record order x
@@ -214,6 +230,11 @@ vrt_status vrt_lte_continuum(vrt_grid grid, vrt_prec prec, int32_t n_lambda,
 vrt_status vrt_formal_solution(vrt_grid grid, vrt_prec prec, vrt_exec exec, int32_t n_lambda,
                                const void *chi, const void *S, const void *I_bottom,
                                const void *I_top, void *J, void *I_rays);
+
+/* Wait for the context stream, then report and clear the grid's device error
+ * flag: VRT_OK, or VRT_E_TIMEOUT if a bounded wait of a persistent sweep gave
+ * up since the last check (the outputs of that solution are invalid). */
+vrt_status vrt_grid_device_status(vrt_grid grid);
 
 /* Emergent intensities (Sect. 2.5: rays leave through the far boundary):
  * for each ray, the sites whose cell touches the downwind z-wall (the top

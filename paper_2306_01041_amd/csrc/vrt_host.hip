@@ -342,6 +342,37 @@ template <typename F> void timed_launch(vrt_ctx ctx, hipStream_t s, bool timed, 
   ctx->pending.push_back(t);
 }
 
+// Wave items of the persistent sweep for `spw` records per wave: every level
+// step is cut separately, so no item holds two levels of one ray.
+const vrt::PersistItems &persistent_items(vrt_grid g, int32_t spw) {
+  auto it = g->persist_items.find(spw);
+  if (it != g->persist_items.end()) return *it->second;
+  std::vector<int64_t> rec;
+  std::vector<int32_t> cnt;
+  for (int32_t st = 0; st < g->n_steps; ++st) {
+    const int64_t b = g->step_ptr[(size_t)st], e = g->step_ptr[(size_t)st + 1];
+    for (int64_t r = b; r < e; r += spw) {
+      rec.push_back(r);
+      cnt.push_back((int32_t)std::min<int64_t>(spw, e - r));
+    }
+  }
+  std::unique_ptr<vrt::PersistItems> p(new vrt::PersistItems);
+  p->spw = spw;
+  p->n_items = (int64_t)rec.size();
+  upload(p->rec, rec.data(), rec.size(), g->ctx->stream);
+  upload(p->cnt, cnt.data(), cnt.size(), g->ctx->stream);
+  if (!g->d_flags.p) {
+    g->d_flags.alloc((size_t)g->R * (size_t)g->n * 4);
+    VRT_HIP(hipMemsetAsync(g->d_flags.p, 0, (size_t)g->R * (size_t)g->n * 4, g->ctx->stream));
+    g->d_epoch.alloc(16);
+    VRT_HIP(hipMemsetAsync(g->d_epoch.p, 0, 16, g->ctx->stream));
+  }
+  VRT_HIP(hipStreamSynchronize(g->ctx->stream));  // host tables are local
+  auto &ref = *p;
+  g->persist_items.emplace(spw, std::move(p));
+  return ref;
+}
+
 template <typename T>
 void enqueue_fs(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *chi, const T *S, const T *Ib,
                 const T *It, T *J, T *I) {
@@ -349,7 +380,16 @@ void enqueue_fs(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *chi
   const int64_t n = g->n;
   vrt_ctx ctx = g->ctx;
   const bool tm = ctx->profiling && ex != VRT_EXEC_GRAPH && s == ctx->stream;
-  if (g->kind == 0) {
+  if (g->kind == 0 && ex == VRT_EXEC_PERSISTENT) {
+    const bool aligned = vrt::al16(chi) && vrt::al16(S) && vrt::al16(Ib) && vrt::al16(It) && vrt::al16(I);
+    const vrt::PersistItems &items = persistent_items(g, vrt::persistent_records_per_wave(nl, sizeof(T), aligned));
+    int32_t *ep = g->d_epoch.as<int32_t>();
+    vrt::launch_epoch(s, ep);
+    timed_launch(ctx, s, tm, 0, g->n_rec * nl, [&] {
+      vrt::launch_persistent_sweep<T>(s, items, g->persist_max_blocks, g->d_ri.as<int4>(), records<T>(g), nl, n, chi,
+                                      S, Ib, It, I, g->d_flags.as<int32_t>(), ep, ep + 1, g->spin_cap);
+    });
+  } else if (g->kind == 0) {
     const int4 *ri = g->d_ri.as<int4>();
     const auto *rf = records<T>(g);
     const int32_t xc = g->xcd_chunks;
@@ -394,6 +434,7 @@ void formal_solution(vrt_grid g, vrt_exec ex, int32_t nl, const void *chi_, cons
   T *J = static_cast<T *>(J_);
   T *I = intensity_buffer<T>(g, nl, Ir_);
   vrt_ctx ctx = g->ctx;
+  if (ex == VRT_EXEC_PERSISTENT && g->kind != 0) ex = VRT_EXEC_GRAPH;
   if (ex != VRT_EXEC_GRAPH) {
     enqueue_fs<T>(g, ctx->stream, ex, nl, chi, S, Ib, It, J, I);
   } else {
@@ -461,6 +502,7 @@ const char *vrt_status_string(vrt_status s) {
     case VRT_E_NOMEM: return "out of memory";
     case VRT_E_NUMERIC: return "numerical error";
     case VRT_E_STATE: return "call out of order";
+    case VRT_E_TIMEOUT: return "device wait timed out";
     default: return "unknown status";
   }
 }
@@ -650,6 +692,9 @@ vrt_status vrt_grid_set_rays(vrt_grid g, int32_t n_rays, const double *dir, cons
     }
     if (!(std::fabs(sum - 1.0) < 1e-12)) fail(VRT_E_ARG, "ray weights sum to %.17g, not 1", sum);
     g->drop_graphs();
+    g->persist_items.clear();
+    g->d_flags.release();
+    g->d_epoch.release();
     g->R = n_rays;
     g->r_exp = r_exp;
     g->h_dirs.assign(dir, dir + 3 * (size_t)n_rays);
@@ -677,6 +722,12 @@ vrt_status vrt_grid_tune(vrt_grid g, int32_t knob, int64_t value) {
     } else if (knob == VRT_TUNE_XCD_CHUNKS) {
       if (value < 0 || value > 64) fail(VRT_E_ARG, "XCD chunk count must be in 0..64");
       g->xcd_chunks = (int)value;
+    } else if (knob == VRT_TUNE_SPIN_CAP) {
+      if (value < 0) fail(VRT_E_ARG, "spin cap must be non-negative");
+      g->spin_cap = value;
+    } else if (knob == VRT_TUNE_PERSIST_BLOCKS) {
+      if (value < 0 || value > (int64_t(1) << 20)) fail(VRT_E_ARG, "bad persistent block cap");
+      g->persist_max_blocks = (int32_t)value;
     } else {
       fail(VRT_E_ARG, "unknown tuning knob %d", knob);
     }
@@ -820,7 +871,8 @@ vrt_status vrt_formal_solution(vrt_grid g, vrt_prec prec, vrt_exec exec, int32_t
                                const void *S, const void *I_bottom, const void *I_top, void *J, void *I_rays) {
   if (!g) return VRT_E_ARG;
   return guarded(g->ctx, [&] {
-    if (!valid_prec(prec) || (exec != VRT_EXEC_PLAIN && exec != VRT_EXEC_BATCHED && exec != VRT_EXEC_GRAPH))
+    if (!valid_prec(prec) || (exec != VRT_EXEC_PLAIN && exec != VRT_EXEC_BATCHED && exec != VRT_EXEC_GRAPH &&
+                              exec != VRT_EXEC_PERSISTENT))
       fail(VRT_E_ARG, "bad precision or execution mode");
     if (n_lambda <= 0) fail(VRT_E_ARG, "n_lambda must be positive");
     if (g->R == 0) fail(VRT_E_STATE, "rays not set");
@@ -830,6 +882,20 @@ vrt_status vrt_formal_solution(vrt_grid g, vrt_prec prec, vrt_exec exec, int32_t
       formal_solution<float>(g, exec, n_lambda, chi, S, I_bottom, I_top, J, I_rays);
     else
       formal_solution<double>(g, exec, n_lambda, chi, S, I_bottom, I_top, J, I_rays);
+    return VRT_OK;
+  });
+}
+
+vrt_status vrt_grid_device_status(vrt_grid g) {
+  if (!g) return VRT_E_ARG;
+  return guarded(g->ctx, [&] {
+    VRT_HIP(hipStreamSynchronize(g->ctx->stream));
+    if (!g->d_epoch.p) return VRT_OK;
+    int32_t err = 0;
+    VRT_HIP(hipMemcpy(&err, g->d_epoch.as<int32_t>() + 1, 4, hipMemcpyDeviceToHost));
+    if (err == 0) return VRT_OK;
+    VRT_HIP(hipMemset(g->d_epoch.as<int32_t>() + 1, 0, 4));
+    fail(VRT_E_TIMEOUT, "a bounded wait of the persistent sweep gave up (spin cap %lld)", (long long)g->spin_cap);
     return VRT_OK;
   });
 }

@@ -71,6 +71,25 @@ struct DevBuf {
   template <typename T> T *as() const { return static_cast<T *>(p); }
 };
 
+// lanes per record for m lane-vectors per row: the smallest power of two >= m, at most 64
+inline int lanes_per_record(int32_t m) {
+  if (m >= 33) return 64;
+  if (m >= 17) return 32;
+  if (m >= 9) return 16;
+  if (m >= 5) return 8;
+  if (m >= 3) return 4;
+  if (m == 2) return 2;
+  return 1;
+}
+
+// Wave items of the persistent sweep for one records-per-wave width: item i
+// covers records [rec[i], rec[i] + cnt[i]) inside one level step.
+struct PersistItems {
+  int32_t spw = 0;
+  int64_t n_items = 0;
+  DevBuf rec, cnt;
+};
+
 }  // namespace vrt
 
 struct vrt_ctx_s {
@@ -149,6 +168,13 @@ struct vrt_grid_s {
   vrt::DevBuf d_Iscr;
   const void *last_I = nullptr;
 
+  // persistent sweep state: per-(ray, site) epoch stamps, the epoch, a device
+  // error flag (a bounded wait gave up) and wave-item tables by width
+  vrt::DevBuf d_flags, d_epoch;
+  std::map<int32_t, std::unique_ptr<vrt::PersistItems>> persist_items;
+  int32_t persist_max_blocks = 0;  // 0 = as many as can be resident
+  int64_t spin_cap = int64_t(1) << 22;
+
   // captured launch sequences, keyed by (prec, n_lambda, pointers)
   using GraphKey = std::tuple<int, int32_t, const void *, const void *, const void *, const void *, void *, void *>;
   std::map<GraphKey, hipGraphExec_t> graphs;
@@ -197,6 +223,16 @@ void launch_emergent(hipStream_t s, int64_t total, int32_t nl, int64_t n, const 
 template <typename T>
 void launch_lte(hipStream_t s, int64_t n, int32_t nl, const double *lam, double kappa0, const double *T_,
                 const double *rho, T *chi, T *S);
+
+// ---- k_persist.hip
+void launch_epoch(hipStream_t s, int32_t *epoch);
+int32_t persistent_records_per_wave(int32_t nl, int elem_bytes, bool aligned);
+bool al16(const void *p);
+template <typename T>
+void launch_persistent_sweep(hipStream_t s, const PersistItems &items, int32_t max_blocks, const int4 *ri,
+                             const typename RecOf<T>::type *rf, int32_t nl, int64_t n, const T *chi, const T *S,
+                             const T *Ibot, const T *Itop, T *I, int32_t *flags, const int32_t *epoch, int32_t *err,
+                             int64_t spin_cap);
 
 // ---- k_regular.hip
 template <typename T>

@@ -32,15 +32,19 @@ VRT_E_HIP = -4
 VRT_E_NOMEM = -5
 VRT_E_NUMERIC = -6
 VRT_E_STATE = -7
+VRT_E_TIMEOUT = -8
 
 VRT_TUNE_RECORD_ORDER = 1
 VRT_TUNE_XCD_CHUNKS = 2
+VRT_TUNE_SPIN_CAP = 3
+VRT_TUNE_PERSIST_BLOCKS = 4
 
 VRT_F64 = 0
 VRT_F32 = 1
 VRT_EXEC_PLAIN = 0
 VRT_EXEC_BATCHED = 1
 VRT_EXEC_GRAPH = 2
+VRT_EXEC_PERSISTENT = 3
 
 _vp = ctypes.c_void_p
 _d = ctypes.POINTER(ctypes.c_double)
@@ -87,6 +91,7 @@ vrt_lte_continuum = _sig("vrt_lte_continuum", _st, [_vp, ctypes.c_int32, ctypes.
                                                     _vp, _vp, _vp])
 vrt_formal_solution = _sig("vrt_formal_solution", _st, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
                                                         _vp, _vp, _vp, _vp])
+vrt_grid_device_status = _sig("vrt_grid_device_status", _st, [_vp])
 vrt_grid_emergent_index = _sig("vrt_grid_emergent_index", _st, [_vp, _i64, _i32])
 vrt_emergent_gather = _sig("vrt_emergent_gather", _st, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp])
 
@@ -253,6 +258,10 @@ class Grid:
                                          _p(d2, _d), _p(lev, _i32), _p(order, _i32), _p(lp, _i32), ctypes.byref(nl)))
         return dict(k1=k1, k2=k2, w1=w1, ds1=d1, ds2=d2, level=lev, order=order, level_ptr=lp[: nl.value + 1].copy(),
                     n_levels=nl.value)
+
+    def device_status(self):
+        """Synchronise and raise VrtError(VRT_E_TIMEOUT) if a bounded device wait gave up."""
+        self.ctx.check(vrt_grid_device_status(self.handle))
 
     def emergent_index(self):
         R = self.info()["n_rays"]

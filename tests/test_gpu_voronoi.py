@@ -84,7 +84,7 @@ def _fields(atm, nl, seed):
 
 
 @pytest.mark.parametrize("nl", [1, 3, 37, 101])
-@pytest.mark.parametrize("mode", ["PLAIN", "BATCHED", "GRAPH"])
+@pytest.mark.parametrize("mode", ["PLAIN", "BATCHED", "GRAPH", "PERSISTENT"])
 def test_fp64_formal_solution_matches_oracle(v, ctx, quad, grids, nl, mode):
     flush(f"fp64 fs nl={nl} mode={mode}")
     atm, g = grids[1000]
@@ -101,9 +101,9 @@ def test_fp64_formal_solution_matches_oracle(v, ctx, quad, grids, nl, mode):
     args = (to_dev(chi, d), to_dev(S, d), J)
     ib, it = to_dev(Ib, d), to_dev(It, d)
     ex = getattr(v, "VRT_EXEC_" + mode)
-    for rep in range(2 if mode == "GRAPH" else 1):
+    for rep in range(2 if mode in ("GRAPH", "PERSISTENT") else 1):
         v.formal_solution(G, *args, I_bottom=ib, I_top=it, I_rays=I, exec_mode=ex)
-        torch.cuda.synchronize()
+        G.device_status()
         assert relerr(I.cpu().numpy(), Io) <= 1e-12
         assert relerr(J.cpu().numpy(), Jo) <= 1e-12
     G.close()
@@ -292,4 +292,55 @@ def test_tuning_knobs_do_not_change_results(v, ctx, quad, grids):
     assert np.array_equal(J.cpu().numpy(), ref)
     with pytest.raises(v.VrtError):
         G.tune(99, 1)
+    G.close()
+
+
+@pytest.mark.parametrize("nl", [1, 64, 101])
+def test_persistent_fp32_matches_graph_bitwise(v, ctx, quad, grids, nl):
+    """The persistent dataflow sweep performs the same arithmetic per record as
+    the level-synchronous launches, so its results are bit-identical."""
+    flush(f"persistent fp32 nl={nl}")
+    atm, g = grids[16384]
+    dirs, w = quad
+    G = _gpu_grid(v, ctx, g, dirs, w)
+    chi_o, S_o = _fields(atm, nl, 11)
+    f = torch.float32
+    chi, S = to_dev(chi_o, f), to_dev(S_o, f)
+    Jg = torch.empty_like(chi)
+    v.formal_solution(G, chi, S, Jg, exec_mode=v.VRT_EXEC_GRAPH)
+    torch.cuda.synchronize()
+    ref = Jg.cpu().numpy()
+    for rep in range(3):
+        J = torch.full_like(chi, -1.0)
+        v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_PERSISTENT)
+        G.device_status()
+        assert np.array_equal(J.cpu().numpy(), ref), rep
+    G.close()
+
+
+def test_persistent_bounded_wait_reports_timeout(v, ctx, quad, grids):
+    """A spin bound of zero polls makes the first unmet wait give up: the kernel
+    still drains, the device status reports a timeout once, and the next
+    solution with the normal bound is correct again."""
+    flush("persistent timeout path")
+    atm, g = grids[16384]
+    dirs, w = quad
+    G = _gpu_grid(v, ctx, g, dirs, w)
+    chi_o, S_o = _fields(atm, 8, 12)
+    f = torch.float32
+    chi, S = to_dev(chi_o, f), to_dev(S_o, f)
+    Jg = torch.empty_like(chi)
+    v.formal_solution(G, chi, S, Jg, exec_mode=v.VRT_EXEC_GRAPH)
+    torch.cuda.synchronize()
+    G.tune(v.VRT_TUNE_SPIN_CAP, 0)
+    J = torch.empty_like(chi)
+    v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_PERSISTENT)
+    with pytest.raises(v.VrtError) as e:
+        G.device_status()
+    assert e.value.status == v.VRT_E_TIMEOUT
+    G.device_status()  # cleared
+    G.tune(v.VRT_TUNE_SPIN_CAP, 1 << 22)
+    v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_PERSISTENT)
+    G.device_status()
+    assert np.array_equal(J.cpu().numpy(), Jg.cpu().numpy())
     G.close()

@@ -231,6 +231,31 @@ vrt_status vrt_formal_solution(vrt_grid grid, vrt_prec prec, vrt_exec exec, int3
                                const void *chi, const void *S, const void *I_bottom,
                                const void *I_top, void *J, void *I_rays);
 
+/* Two-level-atom Lambda iteration (Sect. 2.1, Eq. 3 and 4; stop rule near
+ * 1e-3, Sect. 3.3) with a grey continuum beside the line:
+ *   chi_lambda = chi_cont + chi_line phi_lambda,
+ *   S_lambda   = (chi_line phi_lambda S_line + chi_cont B) / chi_lambda,
+ *   Jbar       = sum_lambda wlam_lambda phi_lambda J_lambda,
+ *   S_line    <- (1 - eps) Jbar + eps B,
+ * repeated until max_i |dS_line| / |S_line| < tol or max_iter iterations. The
+ * bottom boundary of upward rays is thermalised (I = B), the top is empty.
+ * The formal solutions run in `sweep_prec` with `exec` (VRT_EXEC_GRAPH
+ * captures one iteration and replays it); assembly, Jbar, the update and the
+ * convergence test are double precision.
+ *   wlam      host [n_lambda] quadrature weights of the profile.
+ *   phi       device [n][n_lambda] double, profile with sum_l wlam phi = 1.
+ *   chi_line, chi_cont, B   device [n] double.
+ *   S_line    device [n] double: start value in, final value out.
+ *   dS_hist   host [max_iter] or NULL: the change after each iteration.
+ *   n_iter    host: iterations done.
+ * Blocks (one small device-to-host read per iteration). Returns VRT_OK when
+ * converged, VRT_W_NOT_CONVERGED at the cap, VRT_E_NUMERIC on a non-finite
+ * change. Voronoi and regular grids. */
+vrt_status vrt_two_level_solve(vrt_grid grid, vrt_prec sweep_prec, vrt_exec exec, int32_t n_lambda,
+                               const double *wlam, const double *phi, const double *chi_line,
+                               const double *chi_cont, const double *B, double eps, int32_t max_iter,
+                               double tol, double *S_line, double *dS_hist, int32_t *n_iter);
+
 /* Wait for the context stream, then report and clear the grid's device error
  * flag: VRT_OK, or VRT_E_TIMEOUT if a bounded wait of a persistent sweep gave
  * up since the last check (the outputs of that solution are invalid). */

@@ -373,9 +373,10 @@ const vrt::PersistItems &persistent_items(vrt_grid g, int32_t spw) {
   return ref;
 }
 
+// The sweeps of every ray (no angle quadrature).
 template <typename T>
-void enqueue_fs(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *chi, const T *S, const T *Ib,
-                const T *It, T *J, T *I) {
+void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *chi, const T *S, const T *Ib,
+                   const T *It, T *I) {
   const int32_t R = g->R;
   const int64_t n = g->n;
   vrt_ctx ctx = g->ctx;
@@ -421,8 +422,116 @@ void enqueue_fs(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *chi
       for (int32_t st = 0; st < g->nz; ++st) planes(st, 0, R);
     }
   }
+}
+
+template <typename T>
+void enqueue_fs(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *chi, const T *S, const T *Ib,
+                const T *It, T *J, T *I) {
+  enqueue_sweep<T>(g, s, ex, nl, chi, S, Ib, It, I);
+  vrt_ctx ctx = g->ctx;
+  const bool tm = ctx->profiling && ex != VRT_EXEC_GRAPH && s == ctx->stream;
+  const int32_t R = g->R;
+  const int64_t n = g->n;
   timed_launch(ctx, s, tm, 1, (int64_t)R * n * nl,
                [&] { vrt::launch_jreduce<T>(s, I, R, n * nl, g->d_w.as<double>(), J); });
+}
+
+// One Lambda iteration without the host read: reset the max-change word,
+// assemble chi and S from S_line, sweep every ray, then Jbar and the update.
+template <typename T>
+void enqueue_lambda_step(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const double *phi, const double *chi_L,
+                         const double *chi_c, const double *B, double eps, double *S_L, T *I) {
+  T *chi = g->d_nchi.as<T>(), *S = g->d_nS.as<T>(), *Ib = g->d_nIb.as<T>();
+  auto *dS = g->d_dS.as<unsigned long long>();
+  vrt::launch_zero_u64(s, dS);
+  vrt::launch_nlte_assemble<T>(s, g->n, nl, phi, chi_L, chi_c, B, S_L, chi, S);
+  enqueue_sweep<T>(g, s, ex == VRT_EXEC_GRAPH ? VRT_EXEC_BATCHED : ex, nl, chi, S, Ib, nullptr, I);
+  vrt::launch_line_update<T>(s, g->n, nl, g->R, I, g->d_w.as<double>(), g->d_wlam.as<double>(), phi, B, eps, S_L,
+                             dS);
+}
+
+template <typename T>
+vrt_status two_level_solve(vrt_grid g, vrt_exec ex, int32_t nl, const double *wlam, const double *phi,
+                           const double *chi_L, const double *chi_c, const double *B, double eps, int32_t max_iter,
+                           double tol, double *S_L, double *hist, int32_t *n_iter) {
+  vrt_ctx ctx = g->ctx;
+  hipStream_t s = ctx->stream;
+  const size_t nn = (size_t)g->n * (size_t)nl;
+  T *I = intensity_buffer<T>(g, nl, nullptr);
+  if (g->d_nchi.bytes < nn * sizeof(T) || g->d_wlam.bytes < (size_t)nl * 8) {
+    if (g->nlte_graph) {
+      (void)hipGraphExecDestroy(g->nlte_graph);
+      g->nlte_graph = nullptr;
+    }
+  }
+  g->d_nchi.alloc(nn * sizeof(T));
+  g->d_nS.alloc(nn * sizeof(T));
+  g->d_nIb.alloc(nn * sizeof(T));
+  g->d_dS.alloc(8);
+  if (!g->h_dS) VRT_HIP(hipHostMalloc((void **)&g->h_dS, 8, hipHostMallocDefault));
+  VRT_HIP(hipStreamSynchronize(s));  // earlier work may still read the old profile weights
+  g->d_wlam.alloc((size_t)nl * 8);
+  VRT_HIP(hipMemcpy(g->d_wlam.p, wlam, (size_t)nl * 8, hipMemcpyHostToDevice));
+  vrt::launch_broadcast<T>(s, g->n, nl, B, g->d_nIb.as<T>());
+  const int pexec = ex == VRT_EXEC_PERSISTENT && g->kind == 0 ? 1 : 0;
+  if (ex == VRT_EXEC_GRAPH || (ex == VRT_EXEC_PERSISTENT && g->kind != 0)) {
+    const auto key = std::make_tuple((int)sizeof(T), nl, (const void *)phi, (const void *)chi_L,
+                                     (const void *)chi_c, (const void *)B, (const void *)S_L, eps, pexec);
+    if (!g->nlte_graph || g->nlte_key != key) {
+      if (g->nlte_graph) (void)hipGraphExecDestroy(g->nlte_graph);
+      g->nlte_graph = nullptr;
+      if (!ctx->capture_stream) VRT_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+      hipStream_t cs = ctx->capture_stream;
+      VRT_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      hipGraph_t graph = nullptr;
+      try {
+        enqueue_lambda_step<T>(g, cs, VRT_EXEC_GRAPH, nl, phi, chi_L, chi_c, B, eps, S_L, I);
+      } catch (...) {
+        (void)hipStreamEndCapture(cs, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+      }
+      VRT_HIP(hipStreamEndCapture(cs, &graph));
+      hipError_t e = hipGraphInstantiate(&g->nlte_graph, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      VRT_HIP(e);
+      g->nlte_key = key;
+    }
+  }
+  int32_t it = 0;
+  vrt_status st = VRT_W_NOT_CONVERGED;
+  for (; it < max_iter; ++it) {
+    if (g->nlte_graph && (ex == VRT_EXEC_GRAPH || (ex == VRT_EXEC_PERSISTENT && g->kind != 0)))
+      VRT_HIP(hipGraphLaunch(g->nlte_graph, s));
+    else
+      enqueue_lambda_step<T>(g, s, ex, nl, phi, chi_L, chi_c, B, eps, S_L, I);
+    VRT_HIP(hipMemcpyAsync(g->h_dS, g->d_dS.p, 8, hipMemcpyDeviceToHost, s));
+    VRT_HIP(hipStreamSynchronize(s));
+    if (pexec) {
+      int32_t err = 0;
+      VRT_HIP(hipMemcpy(&err, g->d_epoch.as<int32_t>() + 1, 4, hipMemcpyDeviceToHost));
+      if (err) {
+        VRT_HIP(hipMemset(g->d_epoch.as<int32_t>() + 1, 0, 4));
+        if (n_iter) *n_iter = it + 1;
+        fail(VRT_E_TIMEOUT, "a bounded wait of the persistent sweep gave up at iteration %d", it + 1);
+      }
+    }
+    double d;
+    std::memcpy(&d, g->h_dS, 8);
+    if (hist) hist[it] = d;
+    if (!std::isfinite(d)) {
+      if (n_iter) *n_iter = it + 1;
+      fail(VRT_E_NUMERIC, "non-finite source-function change at iteration %d", it + 1);
+    }
+    if (d < tol) {
+      ++it;
+      st = VRT_OK;
+      break;
+    }
+  }
+  if (n_iter) *n_iter = it;
+  g->last_I = I;
+  return st;
 }
 
 template <typename T>
@@ -485,6 +594,8 @@ void vrt_ctx_s::drain_profile() {
 void vrt_grid_s::drop_graphs() {
   for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
   graphs.clear();
+  if (nlte_graph) (void)hipGraphExecDestroy(nlte_graph);
+  nlte_graph = nullptr;
 }
 
 extern "C" {
@@ -673,6 +784,7 @@ void vrt_grid_destroy(vrt_grid g) {
   (void)hipSetDevice(g->ctx->device);
   (void)hipStreamSynchronize(g->ctx->stream);
   g->drop_graphs();
+  if (g->h_dS) (void)hipHostFree(g->h_dS);
   delete g;
 }
 
@@ -883,6 +995,28 @@ vrt_status vrt_formal_solution(vrt_grid g, vrt_prec prec, vrt_exec exec, int32_t
     else
       formal_solution<double>(g, exec, n_lambda, chi, S, I_bottom, I_top, J, I_rays);
     return VRT_OK;
+  });
+}
+
+vrt_status vrt_two_level_solve(vrt_grid g, vrt_prec prec, vrt_exec exec, int32_t n_lambda, const double *wlam,
+                               const double *phi, const double *chi_line, const double *chi_cont, const double *B,
+                               double eps, int32_t max_iter, double tol, double *S_line, double *dS_hist,
+                               int32_t *n_iter) {
+  if (!g) return VRT_E_ARG;
+  return guarded(g->ctx, [&]() -> vrt_status {
+    if (!valid_prec(prec) || n_lambda <= 0 || !wlam || max_iter < 0 || !(tol >= 0.0) || !(eps >= 0.0 && eps <= 1.0))
+      fail(VRT_E_ARG, "bad two-level arguments");
+    if (exec != VRT_EXEC_PLAIN && exec != VRT_EXEC_BATCHED && exec != VRT_EXEC_GRAPH && exec != VRT_EXEC_PERSISTENT)
+      fail(VRT_E_ARG, "bad execution mode");
+    if (g->R == 0) fail(VRT_E_STATE, "rays not set");
+    if (n_iter) *n_iter = 0;
+    if (g->n == 0 || max_iter == 0) return max_iter == 0 ? VRT_W_NOT_CONVERGED : VRT_OK;
+    if (!phi || !chi_line || !chi_cont || !B || !S_line) fail(VRT_E_ARG, "null device array");
+    if (prec == VRT_F32)
+      return two_level_solve<float>(g, exec, n_lambda, wlam, phi, chi_line, chi_cont, B, eps, max_iter, tol, S_line,
+                                    dS_hist, n_iter);
+    return two_level_solve<double>(g, exec, n_lambda, wlam, phi, chi_line, chi_cont, B, eps, max_iter, tol, S_line,
+                                   dS_hist, n_iter);
   });
 }
 

@@ -175,6 +175,14 @@ struct vrt_grid_s {
   int32_t persist_max_blocks = 0;  // 0 = as many as can be resident
   int64_t spin_cap = int64_t(1) << 22;
 
+  // two-level iteration scratch: chi, S, I_bottom in the sweep precision, the
+  // profile weights, the max-change word and its pinned host copy
+  vrt::DevBuf d_nchi, d_nS, d_nIb, d_wlam, d_dS;
+  unsigned long long *h_dS = nullptr;
+  hipGraphExec_t nlte_graph = nullptr;
+  std::tuple<int, int32_t, const void *, const void *, const void *, const void *, const void *, double, int>
+      nlte_key{};
+
   // captured launch sequences, keyed by (prec, n_lambda, pointers)
   using GraphKey = std::tuple<int, int32_t, const void *, const void *, const void *, const void *, void *, void *>;
   std::map<GraphKey, hipGraphExec_t> graphs;
@@ -233,6 +241,17 @@ void launch_persistent_sweep(hipStream_t s, const PersistItems &items, int32_t m
                              const typename RecOf<T>::type *rf, int32_t nl, int64_t n, const T *chi, const T *S,
                              const T *Ibot, const T *Itop, T *I, int32_t *flags, const int32_t *epoch, int32_t *err,
                              int64_t spin_cap);
+
+// ---- k_nlte.hip
+template <typename T>
+void launch_nlte_assemble(hipStream_t s, int64_t n, int32_t nl, const double *phi, const double *chi_L,
+                          const double *chi_c, const double *B, const double *S_L, T *chi, T *S);
+template <typename T> void launch_broadcast(hipStream_t s, int64_t n, int32_t nl, const double *v, T *out);
+void launch_zero_u64(hipStream_t s, unsigned long long *p);
+template <typename T>
+void launch_line_update(hipStream_t s, int64_t n, int32_t nl, int32_t R, const T *I, const double *w,
+                        const double *wlam, const double *phi, const double *B, double eps, double *S_L,
+                        unsigned long long *dS_bits);
 
 // ---- k_regular.hip
 template <typename T>

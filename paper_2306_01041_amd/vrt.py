@@ -91,6 +91,9 @@ vrt_lte_continuum = _sig("vrt_lte_continuum", _st, [_vp, ctypes.c_int32, ctypes.
                                                     _vp, _vp, _vp])
 vrt_formal_solution = _sig("vrt_formal_solution", _st, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
                                                         _vp, _vp, _vp, _vp])
+vrt_two_level_solve = _sig("vrt_two_level_solve", _st, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _d, _vp,
+                                                        _vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,
+                                                        ctypes.c_double, _vp, _d, _i32])
 vrt_grid_device_status = _sig("vrt_grid_device_status", _st, [_vp])
 vrt_grid_emergent_index = _sig("vrt_grid_emergent_index", _st, [_vp, _i64, _i32])
 vrt_emergent_gather = _sig("vrt_emergent_gather", _st, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp])
@@ -351,3 +354,28 @@ def autotune(grid: Grid, chi, S, J, I_bottom=None, I_top=None, I_rays=None, reps
     grid.ctx.check(vrt_grid_autotune(grid.handle, _prec_of(chi), int(nl), _dev(chi), _dev(S), _dev(I_bottom),
                                      _dev(I_top), _dev(J), _dev(I_rays), int(reps), buf, 4096))
     return json.loads(buf.value.decode() or "{}")
+
+
+def two_level_solve(grid: Grid, wlam, phi, chi_line, chi_cont, B, eps, S_line, max_iter=1000, tol=1e-3,
+                    sweep_dtype=None, exec_mode=VRT_EXEC_GRAPH):
+    """Lambda iteration of the two-level line; S_line (device float64 [n]) is updated in place.
+
+    Returns (status, n_iter, dS history as numpy). status is VRT_OK or VRT_W_NOT_CONVERGED.
+    """
+    import torch
+
+    sweep_dtype = torch.float32 if sweep_dtype is None else sweep_dtype
+    inf = grid.info()
+    n = inf["n_sites"]
+    wlam = np.ascontiguousarray(wlam, np.float64)
+    nl = len(wlam)
+    _need(phi, (n, nl), torch.float64, "phi")
+    for t, name in ((chi_line, "chi_line"), (chi_cont, "chi_cont"), (B, "B"), (S_line, "S_line")):
+        _need(t, (n,), torch.float64, name)
+    hist = np.zeros(max(int(max_iter), 1), np.float64)
+    it = ctypes.c_int32()
+    prec = VRT_F32 if sweep_dtype == torch.float32 else VRT_F64
+    st = grid.ctx.check(vrt_two_level_solve(grid.handle, prec, int(exec_mode), nl, _p(wlam, _d), _dev(phi),
+                                            _dev(chi_line), _dev(chi_cont), _dev(B), float(eps), int(max_iter),
+                                            float(tol), _dev(S_line), _p(hist, _d), ctypes.byref(it)))
+    return st, it.value, hist[: it.value].copy()

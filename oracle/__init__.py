@@ -70,6 +70,10 @@ def lib():
         L.orc_dplanck_dT.restype = ctypes.c_double
         L.orc_lte.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, ctypes.c_double, _d, _d, _d, _d]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_fs_voronoi_vjp.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _d, _d, _d, _i32, _i32,
+                                         _d, _d, _d, _d, _d, _d, _d, _d, _d, _d, _d, _d]
+        L.orc_fs_voronoi_vjp.restype = ctypes.c_int
+        L.orc_lte_vjp.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, ctypes.c_double, _d, _d, _d, _d, _d, _d, _d]
         _lib = L
     return _lib
 
@@ -240,3 +244,63 @@ def emergent_sites(grid, dirs):
         bit = 2 if d[2] > 0 else 1
         out.append(np.nonzero(np.asarray(grid.wall) & bit)[0].astype(np.int32))
     return out
+
+
+# ----------------------------------------------------------------------------
+# reverse-mode derivatives
+# ----------------------------------------------------------------------------
+
+def fs_voronoi_vjp(grid, dirs, ray_w, sel: Selection, chi, S, I, dL_dI=None, dL_dJ=None):
+    """(dL/dchi, dL/dS, dL/dI_bottom, dL/dI_top), each [n, nl], for the forward
+    intensities I [R, n, nl] of ``fs_voronoi(..., keep_I=True)``."""
+    dirs = _c(dirs, np.float64)
+    ray_w = _c(ray_w, np.float64)
+    chi = _c(chi, np.float64)
+    S = _c(S, np.float64)
+    I = _c(I, np.float64)
+    R, n, nl = I.shape
+    gI = None if dL_dI is None else _c(dL_dI, np.float64)
+    gJ = None if dL_dJ is None else _c(dL_dJ, np.float64)
+    out = [np.empty((n, nl), np.float64) for _ in range(4)]
+    st = lib().orc_fs_voronoi_vjp(n, R, nl, _p(_c(grid.xyz, np.float64), _d), _p(dirs, _d), _p(ray_w, _d),
+                                  _p(sel.k1, _i32), _p(sel.k2, _i32), _p(sel.w1, _d), _p(sel.ds1, _d),
+                                  _p(sel.ds2, _d), _p(chi, _d), _p(S, _d), _p(I, _d), _p(gI, _d), _p(gJ, _d),
+                                  *[_p(o, _d) for o in out])
+    if st != 0:
+        raise MemoryError("orc_fs_voronoi_vjp failed")
+    return tuple(out)
+
+
+def lte_vjp(lam, kappa0, T, rho, g_chi, g_S, g_Ib=None):
+    """(dL/dT, dL/drho) [n] through chi = kappa0 rho^2 T^9 and S = I_bottom = B_lambda(T)."""
+    lam = _c(np.atleast_1d(lam), np.float64)
+    T = _c(T, np.float64)
+    rho = _c(rho, np.float64)
+    n = len(T)
+    gT = np.empty(n, np.float64)
+    gr = np.empty(n, np.float64)
+    lib().orc_lte_vjp(n, len(lam), _p(lam, _d), float(kappa0), _p(T, _d), _p(rho, _d),
+                      _p(_c(g_chi, np.float64), _d), _p(_c(g_S, np.float64), _d),
+                      None if g_Ib is None else _p(_c(g_Ib, np.float64), _d), _p(gT, _d), _p(gr, _d))
+    return gT, gr
+
+
+def emergent_loss(grid, dirs, ray_w, sel, lam, kappa0, T, rho, target=None):
+    """L = sum over upward rays and their top-wall sites of (I - target)^2 for the
+    grey LTE continuum, with its gradient (dL/dT, dL/drho) by the reverse sweep.
+    target: dict ray -> [sites, nl] array (None: zero)."""
+    chi, S = lte(lam, kappa0, T, rho)
+    J, I = fs_voronoi(grid, dirs, ray_w, sel, chi, S, S, keep_I=True)
+    em = emergent_sites(grid, dirs)
+    gI = np.zeros_like(I)
+    L = 0.0
+    for r in range(len(dirs)):
+        if dirs[r, 2] <= 0:
+            continue
+        tr = 0.0 if target is None else target[r]
+        d = I[r, em[r]] - tr
+        L += float(np.sum(d * d))
+        gI[r, em[r]] = 2.0 * d
+    g_chi, g_S, g_Ib, _ = fs_voronoi_vjp(grid, dirs, ray_w, sel, chi, S, I, dL_dI=gI)
+    gT, gr = lte_vjp(lam, kappa0, T, rho, g_chi, g_S, g_Ib)
+    return L, gT, gr, I

@@ -459,3 +459,87 @@ void orc_lte(int64_t n, int32_t nl, const double *lam, double kappa0, const doub
         }
     }
 }
+
+/* ---------------------------------------------------------------------------
+ * Reverse (adjoint) sweep of the Voronoi formal solution: given dL/dI for
+ * every ray, site and wavelength (dL_dI, [R][n][nl], may be NULL) and dL/dJ
+ * ([n][nl], may be NULL; J = sum_r w_r I_r), accumulate dL/dchi, dL/dS,
+ * dL/dI_bottom and dL/dI_top ([n][nl] each, overwritten). I is the forward
+ * intensity [R][n][nl]. Written in scatter form: sites are visited in the
+ * exact reverse of the forward sweep order, and each site's adjoint is pushed
+ * to the quantities its forward update read:
+ *   I_i = sum_j w_j (E_j I_kj + Psi_u,j S_kj + Psi_0,j S_i),
+ *   x_j = (chi_kj + chi_i) ds_j / 2.
+ * ------------------------------------------------------------------------- */
+int orc_fs_voronoi_vjp(int64_t n, int32_t n_rays, int32_t nl, const double *xyz, const double *dirs,
+                       const double *ray_w, const int32_t *k1, const int32_t *k2, const double *w1,
+                       const double *ds1, const double *ds2, const double *chi, const double *S, const double *I,
+                       const double *dL_dI, const double *dL_dJ, double *g_chi, double *g_S, double *g_Ib,
+                       double *g_It) {
+    const int64_t nn = n * (int64_t)nl;
+    for (int64_t q = 0; q < nn; ++q) { g_chi[q] = 0.0; g_S[q] = 0.0; g_Ib[q] = 0.0; g_It[q] = 0.0; }
+    double *Ibar = (double *)malloc(sizeof(double) * (size_t)(nn > 0 ? nn : 1));
+    int64_t *hz = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!Ibar || !hz) { free(Ibar); free(hz); return -5; }
+    for (int32_t r = 0; r < n_rays; ++r) {
+        const double nz = dirs[3 * r + 2];
+        const int32_t *K1 = k1 + (int64_t)r * n, *K2 = k2 + (int64_t)r * n;
+        const double *W1 = w1 + (int64_t)r * n, *D1 = ds1 + (int64_t)r * n, *D2 = ds2 + (int64_t)r * n;
+        const double *Ir = I + (int64_t)r * nn;
+        for (int64_t q = 0; q < nn; ++q) {
+            Ibar[q] = dL_dI ? dL_dI[(int64_t)r * nn + q] : 0.0;
+            if (dL_dJ) Ibar[q] += ray_w[r] * dL_dJ[q];
+        }
+        orc_height_order(n, xyz, nz > 0.0 ? 1.0 : -1.0, hz);
+        for (int64_t p = n - 1; p >= 0; --p) {
+            const int64_t i = hz[p];
+            if (K1[i] < 0) {
+                double *gb = nz > 0.0 ? g_Ib : g_It;
+                for (int32_t l = 0; l < nl; ++l) gb[i * nl + l] += Ibar[i * nl + l];
+                continue;
+            }
+            for (int j = 0; j < 2; ++j) {
+                const int64_t k = j == 0 ? K1[i] : K2[i];
+                if (k < 0) continue;
+                const double w = (K2[i] < 0) ? 1.0 : (j == 0 ? W1[i] : 1.0 - W1[i]);
+                const double ds = j == 0 ? D1[i] : D2[i];
+                for (int32_t l = 0; l < nl; ++l) {
+                    const double gi = Ibar[i * nl + l] * w;
+                    if (gi == 0.0) continue;
+                    const double x = 0.5 * (chi[k * nl + l] + chi[i * nl + l]) * ds;
+                    double E, pu, p0, dpu, dp0;
+                    orc_psi(x, &E, &pu, &p0);
+                    orc_dpsi(x, &dpu, &dp0);
+                    Ibar[k * nl + l] += gi * E;
+                    g_S[k * nl + l] += gi * pu;
+                    g_S[i * nl + l] += gi * p0;
+                    const double xbar = gi * (-E * Ir[k * nl + l] + dpu * S[k * nl + l] + dp0 * S[i * nl + l]);
+                    g_chi[k * nl + l] += 0.5 * ds * xbar;
+                    g_chi[i * nl + l] += 0.5 * ds * xbar;
+                }
+            }
+        }
+    }
+    free(Ibar);
+    free(hz);
+    return 0;
+}
+
+/* Chain rule of the grey LTE continuum to temperature and density:
+ *   chi = kappa0 rho^2 T^9  ->  dchi/dT = 9 chi / T,  dchi/drho = 2 chi / rho,
+ *   S = I_bottom = B_lambda(T) ->  dB/dT.
+ * g_T, g_rho [n] receive sum over wavelengths. */
+void orc_lte_vjp(int64_t n, int32_t nl, const double *lam, double kappa0, const double *T, const double *rho,
+                 const double *g_chi, const double *g_S, const double *g_Ib, double *g_T, double *g_rho) {
+    for (int64_t i = 0; i < n; ++i) {
+        const double c = kappa0 * rho[i] * rho[i] * pow(T[i], 9.0);
+        double gt = 0.0, gr = 0.0;
+        for (int32_t l = 0; l < nl; ++l) {
+            const int64_t q = i * nl + l;
+            gt += g_chi[q] * 9.0 * c / T[i] + (g_S[q] + (g_Ib ? g_Ib[q] : 0.0)) * orc_dplanck_dT(lam[l], T[i]);
+            gr += g_chi[q] * 2.0 * c / rho[i];
+        }
+        g_T[i] = gt;
+        g_rho[i] = gr;
+    }
+}

@@ -231,6 +231,49 @@ vrt_status vrt_formal_solution(vrt_grid grid, vrt_prec prec, vrt_exec exec, int3
                                const void *chi, const void *S, const void *I_bottom,
                                const void *I_top, void *J, void *I_rays);
 
+/* Reverse-mode derivative (vector-Jacobian product) of vrt_formal_solution on
+ * a Voronoi grid, for gradients of a misfit of the intensities (Sect. 2.1 Eq.
+ * 2, Sect. 2.5 Eq. 5 differentiated by hand). Given
+ *   dL_dI   device [n_rays][n][n_lambda], dL/dI of every ray (may be NULL),
+ *   dL_dJ   device [n][n_lambda], dL/dJ (may be NULL; at least one of the two),
+ * and the forward inputs chi, S, I_bottom (NULL = S), I_top (NULL = 0) and
+ * I_rays (device [n_rays][n][n_lambda], the forward intensities; NULL = the
+ * library recomputes them), writes dL/dchi, dL/dS, dL/dI_bottom and
+ * dL/dI_top (device [n][n_lambda] each; any may be NULL). When the forward
+ * solution used I_bottom = S, the total sensitivity to S is dL_dS +
+ * dL_dIbottom. Upwind selection and weights depend on geometry only, so no
+ * derivative flows through them. The reverse sweep walks the level steps
+ * downwards with each site gathering from the sites that read it (no atomics);
+ * sums over rays are double precision.
+ *   ray_group  0 = all rays at once; g > 0 = g rays at a time, recomputing
+ *              their forward intensities when I_rays is NULL, so the scratch
+ *              memory scales with g instead of n_rays (checkpointing by ray
+ *              group, for memory-bound cases).
+ * Enqueued, not blocking. */
+vrt_status vrt_formal_solution_vjp(vrt_grid grid, vrt_prec prec, int32_t n_lambda, const void *chi,
+                                   const void *S, const void *I_bottom, const void *I_top,
+                                   const void *I_rays, const void *dL_dI, const void *dL_dJ,
+                                   void *dL_dchi, void *dL_dS, void *dL_dIbottom, void *dL_dItop,
+                                   int32_t ray_group);
+
+/* Adjoint of vrt_emergent_gather: writes dL_dI (device [n_rays][n][n_lambda])
+ * with dL_dIem (device, layout of vrt_emergent_gather's output) at the
+ * emergent rows and zero elsewhere. Enqueued. */
+vrt_status vrt_emergent_scatter(vrt_grid grid, vrt_prec prec, int32_t n_lambda, const void *dL_dIem,
+                                void *dL_dI);
+
+/* Adjoint of vrt_lte_continuum (with I_bottom = S = B_lambda(T)):
+ *   dL/dT   = sum_lambda dL/dchi 9 chi / T + (dL/dS + dL/dI_bottom) dB/dT,
+ *   dL/drho = sum_lambda dL/dchi 2 chi / rho,
+ * summed over wavelengths in double precision. dL_dchi, dL_dS, dL_dIbottom
+ * (may be NULL) are device [n][n_lambda] in `prec`; T, rho, dL_dT, dL_drho
+ * are device [n] double. kappa0 is a constant of the recipe, not
+ * differentiated. Enqueued. */
+vrt_status vrt_lte_continuum_vjp(vrt_grid grid, vrt_prec prec, int32_t n_lambda,
+                                 const double *lambda_m, double kappa0, const double *T,
+                                 const double *rho, const void *dL_dchi, const void *dL_dS,
+                                 const void *dL_dIbottom, double *dL_dT, double *dL_drho);
+
 /* Two-level-atom Lambda iteration (Sect. 2.1, Eq. 3 and 4; stop rule near
  * 1e-3, Sect. 3.3) with a grey continuum beside the line:
  *   chi_lambda = chi_cont + chi_line phi_lambda,

@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void sweep_kernel(const int4 *__restrict__ ri,
                                                     int64_t rec_begin, int64_t rec_count, int32_t nl, int64_t n,
                                                     const T *__restrict__ chi, const T *__restrict__ S,
                                                     const T *__restrict__ Ibot, const T *__restrict__ Itop, T *I,
-                                                    int32_t xcd_chunks) {
+                                                    int32_t xcd_chunks, int32_t ray0) {
   using L = Lane<T, V>;
   using VT = typename L::type;
   constexpr int SPW = 64 / C;
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256) void sweep_kernel(const int4 *__restrict__ ri,
   const int32_t site = q.x, k1 = q.y, k2 = q.z;
   const int32_t ray = q.w >> 1;
   const bool up = (q.w & 1) != 0;
-  T *Iray = I + (int64_t)ray * n * nl;
+  T *Iray = I + (int64_t)(ray - ray0) * n * nl;
   const int64_t bi = (int64_t)site * nl;
   if (k1 < 0) {
     for (int l = l0; l < nl; l += C * V) {
@@ -149,26 +149,26 @@ __global__ void emergent_kernel(int64_t total, int32_t nl, int64_t n, const int3
 
 template <typename T, int C, int V>
 void launch_c(hipStream_t s, const int4 *ri, const typename vrt::RecOf<T>::type *rf, int64_t b, int64_t c, int32_t nl,
-              int64_t n, const T *chi, const T *S, const T *Ibot, const T *Itop, T *I, int32_t xc) {
+              int64_t n, const T *chi, const T *S, const T *Ibot, const T *Itop, T *I, int32_t xc, int32_t ray0) {
   constexpr int SPW = 64 / C;
   const int64_t waves = (c + SPW - 1) / SPW;
   const int64_t blocks = (waves + 3) / 4;
   hipLaunchKernelGGL((sweep_kernel<T, C, V>), dim3((unsigned)blocks), dim3(256), 0, s, ri, rf, b, c, nl, n, chi, S,
-                     Ibot, Itop, I, xc);
+                     Ibot, Itop, I, xc, ray0);
 }
 
 // lanes per record for m lane-vectors per row: the smallest power of two >= m, at most 64
 template <typename T, int V>
 void launch_v(hipStream_t s, const int4 *ri, const typename vrt::RecOf<T>::type *rf, int64_t b, int64_t c, int32_t nl,
-              int64_t n, const T *chi, const T *S, const T *Ibot, const T *Itop, T *I, int32_t xc) {
+              int64_t n, const T *chi, const T *S, const T *Ibot, const T *Itop, T *I, int32_t xc, int32_t ray0) {
   const int32_t m = nl / V;
-  if (m >= 33) launch_c<T, 64, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc);
-  else if (m >= 17) launch_c<T, 32, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc);
-  else if (m >= 9) launch_c<T, 16, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc);
-  else if (m >= 5) launch_c<T, 8, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc);
-  else if (m >= 3) launch_c<T, 4, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc);
-  else if (m == 2) launch_c<T, 2, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc);
-  else launch_c<T, 1, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc);
+  if (m >= 33) launch_c<T, 64, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0);
+  else if (m >= 17) launch_c<T, 32, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0);
+  else if (m >= 9) launch_c<T, 16, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0);
+  else if (m >= 5) launch_c<T, 8, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0);
+  else if (m >= 3) launch_c<T, 4, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0);
+  else if (m == 2) launch_c<T, 2, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0);
+  else launch_c<T, 1, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0);
 }
 
 // 16-byte lane vectors when the row length allows (and rows then stay 16-byte aligned)
@@ -183,13 +183,13 @@ namespace vrt {
 template <typename T>
 void launch_sweep(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *rf, int64_t rec_begin,
                   int64_t rec_count, int32_t nl, int64_t n, const T *chi, const T *S, const T *Ibot, const T *Itop,
-                  T *I, int32_t xcd_chunks) {
+                  T *I, int32_t xcd_chunks, int32_t ray0) {
   if (rec_count <= 0) return;
   const bool aligned = aligned16(chi) && aligned16(S) && aligned16(Ibot) && aligned16(Itop) && aligned16(I);
   if (aligned && nl % kVec<T> == 0)
-    launch_v<T, kVec<T>>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I, xcd_chunks);
+    launch_v<T, kVec<T>>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I, xcd_chunks, ray0);
   else
-    launch_v<T, 1>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I, xcd_chunks);
+    launch_v<T, 1>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I, xcd_chunks, ray0);
   VRT_HIP(hipGetLastError());
 }
 
@@ -218,9 +218,11 @@ void launch_emergent(hipStream_t s, int64_t total, int32_t nl, int64_t n, const 
 }
 
 template void launch_sweep<float>(hipStream_t, const int4 *, const RecF32 *, int64_t, int64_t, int32_t, int64_t,
-                                  const float *, const float *, const float *, const float *, float *, int32_t);
+                                  const float *, const float *, const float *, const float *, float *, int32_t,
+                                  int32_t);
 template void launch_sweep<double>(hipStream_t, const int4 *, const RecF64 *, int64_t, int64_t, int32_t, int64_t,
-                                   const double *, const double *, const double *, const double *, double *, int32_t);
+                                   const double *, const double *, const double *, const double *, double *, int32_t,
+                                   int32_t);
 template void launch_jreduce<float>(hipStream_t, const float *, int32_t, int64_t, const double *, float *);
 template void launch_jreduce<double>(hipStream_t, const double *, int32_t, int64_t, const double *, double *);
 template void launch_emergent<float>(hipStream_t, int64_t, int32_t, int64_t, const int32_t *, const int32_t *,

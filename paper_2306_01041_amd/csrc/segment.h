@@ -5,7 +5,9 @@
 // Below x = 1/2 both come from their power series
 //   Psi_0 = sum_{n>=1} (-1)^(n+1) x^n/(n+1)!,  Psi_u = sum_{n>=1} (-1)^(n+1) n x^n/(n+1)!,
 // which removes the 0/0 at x = 0 and the cancellation of the closed form at
-// small x. Shared by the Voronoi, regular-grid and reverse sweeps.
+// small x. The reverse sweep also needs the derivatives: dPsi_0/dx = Psi_u / x
+// (whose series is the Psi_u series divided by x) and dPsi_u/dx = e^-x -
+// dPsi_0/dx. Shared by the Voronoi, regular-grid and reverse sweeps.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -17,6 +19,11 @@ template <typename T> struct Seg;
 template <> struct Seg<float> {
   // ten terms: truncation below 1e-12 relative for x < 1/2
   static __device__ __forceinline__ void weights(float x, float &E, float &pu, float &p0) {
+    float d0;
+    weights(x, E, pu, p0, d0);
+  }
+  // also d0 = dPsi_0/dx = Psi_u / x (then dPsi_u/dx = e^-x - d0)
+  static __device__ __forceinline__ void weights(float x, float &E, float &pu, float &p0, float &d0) {
     if (x < 0.5f) {
       // Psi_0 = sum_{n>=1} (-1)^(n+1) x^n/(n+1)!, Psi_u = sum (-1)^(n+1) n x^n/(n+1)!
       const float a = 1.0f / 39916800.0f;  // 1/11!
@@ -42,12 +49,14 @@ template <> struct Seg<float> {
       su = su * x + 0.5f;
       p0 = s0 * x;
       pu = su * x;
+      d0 = su;
       E = expf(-x);
     } else {
       E = expf(-x);
       const float r = (1.0f - E) / x;
       p0 = 1.0f - r;
       pu = r - E;
+      d0 = pu / x;
     }
   }
 };
@@ -62,6 +71,10 @@ __host__ __device__ constexpr double inv_factorial(int m) {
 template <> struct Seg<double> {
   // eighteen terms: truncation below 1e-21 relative for x < 1/2
   static __device__ __forceinline__ void weights(double x, double &E, double &pu, double &p0) {
+    double d0;
+    weights(x, E, pu, p0, d0);
+  }
+  static __device__ __forceinline__ void weights(double x, double &E, double &pu, double &p0, double &d0) {
     if (x < 0.5) {
       double s0 = 0.0, su = 0.0;
 #pragma unroll
@@ -72,12 +85,14 @@ template <> struct Seg<double> {
       }
       p0 = s0 * x;
       pu = su * x;
+      d0 = su;
       E = exp(-x);
     } else {
       E = exp(-x);
       const double r = -expm1(-x) / x;
       p0 = 1.0 - r;
       pu = r - E;
+      d0 = pu / x;
     }
   }
 };

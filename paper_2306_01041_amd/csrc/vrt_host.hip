@@ -397,7 +397,7 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
     auto sweep = [&](int64_t b, int64_t c) {
       if (c <= 0) return;
       timed_launch(ctx, s, tm, 0, c * nl,
-                   [&] { vrt::launch_sweep<T>(s, ri, rf, b, c, nl, n, chi, S, Ib, It, I, xc); });
+                   [&] { vrt::launch_sweep<T>(s, ri, rf, b, c, nl, n, chi, S, Ib, It, I, xc, 0); });
     };
     if (ex == VRT_EXEC_PLAIN) {
       for (int32_t r = 0; r < R; ++r)
@@ -434,6 +434,127 @@ void enqueue_fs(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *chi
   const int64_t n = g->n;
   timed_launch(ctx, s, tm, 1, (int64_t)R * n * nl,
                [&] { vrt::launch_jreduce<T>(s, I, R, n * nl, g->d_w.as<double>(), J); });
+}
+
+// Per-ray dependents lists: for every site k, the sites d whose forward update
+// read k, in increasing d (then line) order, with the weight and length of
+// that line. Built on the host from the selection, once per quadrature.
+void build_dependents(vrt_grid g) {
+  if (g->deps_built) return;
+  const int64_t n = g->n;
+  const int32_t R = g->R;
+  const size_t RN = (size_t)R * (size_t)n;
+  hipStream_t s = g->ctx->stream;
+  std::vector<int32_t> k1(RN), k2(RN);
+  std::vector<double> w1(RN), d1(RN), d2(RN);
+  VRT_HIP(hipMemcpyAsync(k1.data(), g->d_k1.p, RN * 4, hipMemcpyDeviceToHost, s));
+  VRT_HIP(hipMemcpyAsync(k2.data(), g->d_k2.p, RN * 4, hipMemcpyDeviceToHost, s));
+  VRT_HIP(hipMemcpyAsync(w1.data(), g->d_w1.p, RN * 8, hipMemcpyDeviceToHost, s));
+  VRT_HIP(hipMemcpyAsync(d1.data(), g->d_ds1.p, RN * 8, hipMemcpyDeviceToHost, s));
+  VRT_HIP(hipMemcpyAsync(d2.data(), g->d_ds2.p, RN * 8, hipMemcpyDeviceToHost, s));
+  VRT_HIP(hipStreamSynchronize(s));
+  std::vector<int64_t> ptr((size_t)R * (size_t)(n + 1), 0);
+  int64_t total = 0;
+  for (int32_t r = 0; r < R; ++r) {
+    int64_t *p = ptr.data() + (size_t)r * (size_t)(n + 1);
+    const size_t o = (size_t)r * (size_t)n;
+    for (int64_t d = 0; d < n; ++d) {
+      if (k1[o + d] >= 0) p[k1[o + d] + 1]++;
+      if (k2[o + d] >= 0) p[k2[o + d] + 1]++;
+    }
+    p[0] = total;
+    for (int64_t k = 0; k < n; ++k) p[k + 1] += p[k];
+    total = p[n];
+  }
+  std::vector<int32_t> site((size_t)total);
+  std::vector<vrt::RecF32> r32((size_t)total);
+  std::vector<vrt::RecF64> r64((size_t)total);
+  std::vector<int64_t> cur(ptr);
+  for (int32_t r = 0; r < R; ++r) {
+    int64_t *c = cur.data() + (size_t)r * (size_t)(n + 1);
+    const size_t o = (size_t)r * (size_t)n;
+    for (int64_t d = 0; d < n; ++d) {
+      const bool two = k2[o + d] >= 0;
+      for (int j = 0; j < 2; ++j) {
+        const int32_t k = j == 0 ? k1[o + d] : k2[o + d];
+        if (k < 0) continue;
+        const double w = two ? (j == 0 ? w1[o + d] : 1.0 - w1[o + d]) : 1.0;
+        const double ds = j == 0 ? d1[o + d] : d2[o + d];
+        const int64_t t = c[k]++;
+        site[(size_t)t] = (int32_t)d;
+        r32[(size_t)t] = vrt::RecF32{(float)w, (float)ds, 0.0f, 0.0f};
+        r64[(size_t)t] = vrt::RecF64{w, ds, 0.0, 0.0};
+      }
+    }
+  }
+  upload(g->d_dep_ptr, ptr.data(), ptr.size(), s);
+  upload(g->d_dep_site, site.data(), site.size(), s);
+  upload(g->d_dep_rf32, r32.data(), r32.size(), s);
+  upload(g->d_dep_rf64, r64.data(), r64.size(), s);
+  VRT_HIP(hipStreamSynchronize(s));
+  g->deps_built = true;
+}
+
+template <typename T> const typename vrt::RecOf<T>::type *dep_records(vrt_grid g);
+template <> const vrt::RecF32 *dep_records<float>(vrt_grid g) { return g->d_dep_rf32.as<vrt::RecF32>(); }
+template <> const vrt::RecF64 *dep_records<double>(vrt_grid g) { return g->d_dep_rf64.as<vrt::RecF64>(); }
+
+// Reverse sweep over ray groups of `group` rays: the forward intensities come
+// from I_rays when given, else each group's are recomputed first; the group's
+// adjoint contributions are summed into double accumulators.
+template <typename T>
+void formal_solution_vjp(vrt_grid g, int32_t nl, const T *chi, const T *S, const T *Ib, const T *It,
+                         const T *I_rays, const T *gI, const T *gJ, T *o_chi, T *o_S, T *o_Ib, T *o_It,
+                         int32_t group) {
+  build_dependents(g);
+  hipStream_t s = g->ctx->stream;
+  const int64_t n = g->n;
+  const int32_t R = g->R;
+  const int64_t nn = n * nl;
+  if (group <= 0 || group > R) group = R;
+  const size_t gbytes = (size_t)group * (size_t)nn * sizeof(T);
+  if (!I_rays) g->d_vI.alloc(gbytes);
+  g->d_vIbar.alloc(gbytes);
+  g->d_vSbar.alloc(gbytes);
+  g->d_vCbar.alloc(gbytes);
+  g->d_vacc.alloc((size_t)nn * 4 * sizeof(double));
+  double *acc = g->d_vacc.as<double>();
+  vrt::launch_fill_zero<double>(s, nn * 4, acc);
+  T *Ibar = g->d_vIbar.as<T>(), *Sbar = g->d_vSbar.as<T>(), *Cbar = g->d_vCbar.as<T>();
+  const int4 *ri = g->d_ri.as<int4>();
+  const auto *rf = records<T>(g);
+  for (int32_t r0 = 0; r0 < R; r0 += group) {
+    const int32_t gc = std::min(group, R - r0);
+    auto seg = [&](int32_t st, int64_t &b, int64_t &c) {
+      b = g->seg_off[(size_t)st * R + r0];
+      const int32_t rl = r0 + gc - 1;
+      c = g->seg_off[(size_t)st * R + rl] + g->seg_cnt[(size_t)st * R + rl] - b;
+    };
+    const T *Ifw;
+    if (I_rays) {
+      Ifw = I_rays + (size_t)r0 * (size_t)nn;
+    } else {
+      T *Iw = g->d_vI.as<T>();
+      for (int32_t st = 0; st < g->n_steps; ++st) {
+        int64_t b, c;
+        seg(st, b, c);
+        vrt::launch_sweep<T>(s, ri, rf, b, c, nl, n, chi, S, Ib, It, Iw, g->xcd_chunks, r0);
+      }
+      Ifw = Iw;
+    }
+    for (int32_t st = g->n_steps - 1; st >= 0; --st) {
+      int64_t b, c;
+      seg(st, b, c);
+      vrt::launch_reverse<T>(s, ri, rf, b, c, nl, n, r0, g->d_dep_ptr.as<int64_t>(), g->d_dep_site.as<int32_t>(),
+                             dep_records<T>(g), chi, S, Ifw, gI, gJ, g->d_w.as<double>(), Ibar, Sbar, Cbar);
+    }
+    vrt::launch_reverse_reduce<T>(s, n, nl, r0, gc, g->d_dirs.as<double>(), g->d_wall.as<uint8_t>(), Ibar, Sbar,
+                                  Cbar, acc, acc + nn, acc + 2 * nn, acc + 3 * nn);
+  }
+  vrt::launch_to_prec<T>(s, nn, acc, o_chi);
+  vrt::launch_to_prec<T>(s, nn, acc + nn, o_S);
+  vrt::launch_to_prec<T>(s, nn, acc + 2 * nn, o_Ib);
+  vrt::launch_to_prec<T>(s, nn, acc + 3 * nn, o_It);
 }
 
 // One Lambda iteration without the host read: reset the max-change word,
@@ -549,6 +670,11 @@ void formal_solution(vrt_grid g, vrt_exec ex, int32_t nl, const void *chi_, cons
   } else {
     const vrt_grid_s::GraphKey key{sizeof(T), nl, chi, S, Ib, It, J, I};
     auto it = g->graphs.find(key);
+    if (it == g->graphs.end() && g->graphs.size() >= 8) {
+      // bounded cache: callers that pass fresh buffers every time would otherwise grow it without end
+      for (auto &kv : g->graphs) (void)hipGraphExecDestroy(kv.second);
+      g->graphs.clear();
+    }
     if (it == g->graphs.end()) {
       if (!ctx->capture_stream) VRT_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
       hipStream_t cs = ctx->capture_stream;
@@ -807,6 +933,7 @@ vrt_status vrt_grid_set_rays(vrt_grid g, int32_t n_rays, const double *dir, cons
     g->persist_items.clear();
     g->d_flags.release();
     g->d_epoch.release();
+    g->deps_built = false;
     g->R = n_rays;
     g->r_exp = r_exp;
     g->h_dirs.assign(dir, dir + 3 * (size_t)n_rays);
@@ -1017,6 +1144,83 @@ vrt_status vrt_two_level_solve(vrt_grid g, vrt_prec prec, vrt_exec exec, int32_t
                                     dS_hist, n_iter);
     return two_level_solve<double>(g, exec, n_lambda, wlam, phi, chi_line, chi_cont, B, eps, max_iter, tol, S_line,
                                    dS_hist, n_iter);
+  });
+}
+
+vrt_status vrt_formal_solution_vjp(vrt_grid g, vrt_prec prec, int32_t n_lambda, const void *chi, const void *S,
+                                   const void *I_bottom, const void *I_top, const void *I_rays, const void *dL_dI,
+                                   const void *dL_dJ, void *dL_dchi, void *dL_dS, void *dL_dIbottom, void *dL_dItop,
+                                   int32_t ray_group) {
+  if (!g) return VRT_E_ARG;
+  return guarded(g->ctx, [&] {
+    if (!valid_prec(prec) || n_lambda <= 0 || ray_group < 0) fail(VRT_E_ARG, "bad precision, n_lambda or ray group");
+    if (g->kind != 0) fail(VRT_E_ARG, "the reverse sweep exists for Voronoi grids only");
+    if (g->R == 0) fail(VRT_E_STATE, "rays not set");
+    if (g->n == 0) return VRT_OK;
+    if (!chi || !S) fail(VRT_E_ARG, "chi and S are required");
+    if (!dL_dI && !dL_dJ) fail(VRT_E_ARG, "give dL_dI, dL_dJ or both");
+    if (prec == VRT_F32) {
+      using T = float;
+      const T *ib = I_bottom ? (const T *)I_bottom : (const T *)S;
+      formal_solution_vjp<T>(g, n_lambda, (const T *)chi, (const T *)S, ib, (const T *)I_top, (const T *)I_rays,
+                             (const T *)dL_dI, (const T *)dL_dJ, (T *)dL_dchi, (T *)dL_dS, (T *)dL_dIbottom,
+                             (T *)dL_dItop, ray_group);
+    } else {
+      using T = double;
+      const T *ib = I_bottom ? (const T *)I_bottom : (const T *)S;
+      formal_solution_vjp<T>(g, n_lambda, (const T *)chi, (const T *)S, ib, (const T *)I_top, (const T *)I_rays,
+                             (const T *)dL_dI, (const T *)dL_dJ, (T *)dL_dchi, (T *)dL_dS, (T *)dL_dIbottom,
+                             (T *)dL_dItop, ray_group);
+    }
+    return VRT_OK;
+  });
+}
+
+vrt_status vrt_emergent_scatter(vrt_grid g, vrt_prec prec, int32_t n_lambda, const void *dL_dIem, void *dL_dI) {
+  if (!g) return VRT_E_ARG;
+  return guarded(g->ctx, [&] {
+    if (!valid_prec(prec) || n_lambda <= 0) fail(VRT_E_ARG, "bad precision or n_lambda");
+    if (g->R == 0) fail(VRT_E_STATE, "rays not set");
+    const int64_t total = g->em_off.back();
+    const int64_t full = (int64_t)g->R * g->n * n_lambda;
+    if (full > 0 && !dL_dI) fail(VRT_E_ARG, "null output");
+    if (total > 0 && !dL_dIem) fail(VRT_E_ARG, "null input");
+    hipStream_t s = g->ctx->stream;
+    if (prec == VRT_F32) {
+      vrt::launch_fill_zero<float>(s, full, (float *)dL_dI);
+      vrt::launch_emergent_scatter<float>(s, total, n_lambda, g->n, g->d_em_ray.as<int32_t>(),
+                                          g->d_em_site.as<int32_t>(), (const float *)dL_dIem, (float *)dL_dI);
+    } else {
+      vrt::launch_fill_zero<double>(s, full, (double *)dL_dI);
+      vrt::launch_emergent_scatter<double>(s, total, n_lambda, g->n, g->d_em_ray.as<int32_t>(),
+                                           g->d_em_site.as<int32_t>(), (const double *)dL_dIem, (double *)dL_dI);
+    }
+    return VRT_OK;
+  });
+}
+
+vrt_status vrt_lte_continuum_vjp(vrt_grid g, vrt_prec prec, int32_t n_lambda, const double *lambda_m, double kappa0,
+                                 const double *T, const double *rho, const void *dL_dchi, const void *dL_dS,
+                                 const void *dL_dIbottom, double *dL_dT, double *dL_drho) {
+  if (!g) return VRT_E_ARG;
+  return guarded(g->ctx, [&] {
+    if (!valid_prec(prec) || n_lambda <= 0 || !lambda_m) fail(VRT_E_ARG, "bad LTE adjoint arguments");
+    if (g->n == 0) return VRT_OK;
+    if (!T || !rho || !dL_dchi || !dL_dS || !dL_dT || !dL_drho) fail(VRT_E_ARG, "null device array");
+    hipStream_t s = g->ctx->stream;
+    if (g->h_lam.size() != (size_t)n_lambda || !std::equal(g->h_lam.begin(), g->h_lam.end(), lambda_m)) {
+      VRT_HIP(hipStreamSynchronize(s));
+      g->d_lam.alloc((size_t)n_lambda * sizeof(double));
+      VRT_HIP(hipMemcpy(g->d_lam.p, lambda_m, (size_t)n_lambda * sizeof(double), hipMemcpyHostToDevice));
+      g->h_lam.assign(lambda_m, lambda_m + n_lambda);
+    }
+    if (prec == VRT_F32)
+      vrt::launch_lte_vjp<float>(s, g->n, n_lambda, g->d_lam.as<double>(), kappa0, T, rho, (const float *)dL_dchi,
+                                 (const float *)dL_dS, (const float *)dL_dIbottom, dL_dT, dL_drho);
+    else
+      vrt::launch_lte_vjp<double>(s, g->n, n_lambda, g->d_lam.as<double>(), kappa0, T, rho, (const double *)dL_dchi,
+                                  (const double *)dL_dS, (const double *)dL_dIbottom, dL_dT, dL_drho);
+    return VRT_OK;
   });
 }
 

@@ -183,6 +183,12 @@ struct vrt_grid_s {
   std::tuple<int, int32_t, const void *, const void *, const void *, const void *, const void *, double, int>
       nlte_key{};
 
+  // reverse sweep: per-ray dependents lists (absolute offsets [R][n+1], the
+  // dependent site, and the weight and length of the line it reads), scratch
+  vrt::DevBuf d_dep_ptr, d_dep_site, d_dep_rf32, d_dep_rf64;
+  bool deps_built = false;
+  vrt::DevBuf d_vI, d_vIbar, d_vSbar, d_vCbar, d_vacc;
+
   // captured launch sequences, keyed by (prec, n_lambda, pointers)
   using GraphKey = std::tuple<int, int32_t, const void *, const void *, const void *, const void *, void *, void *>;
   std::map<GraphKey, hipGraphExec_t> graphs;
@@ -217,10 +223,11 @@ void launch_pack(hipStream_t s, int64_t n, int32_t R, int32_t Lmax, const int32_
                  const double *ds2, const double *dirs, int4 *ri, RecF32 *rf32, RecF64 *rf64);
 
 // ---- k_sweep.hip
+// I holds the rays from ray0 on (ray r writes I + (r - ray0) * n * nl)
 template <typename T>
 void launch_sweep(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *rf, int64_t rec_begin,
                   int64_t rec_count, int32_t nl, int64_t n, const T *chi, const T *S, const T *Ibot,
-                  const T *Itop, T *I, int32_t xcd_chunks);
+                  const T *Itop, T *I, int32_t xcd_chunks, int32_t ray0);
 template <typename T>
 void launch_jreduce(hipStream_t s, const T *I, int32_t R, int64_t nn, const double *w, T *J);
 template <typename T>
@@ -252,6 +259,25 @@ template <typename T>
 void launch_line_update(hipStream_t s, int64_t n, int32_t nl, int32_t R, const T *I, const double *w,
                         const double *wlam, const double *phi, const double *B, double eps, double *S_L,
                         unsigned long long *dS_bits);
+
+// ---- k_adjoint.hip
+template <typename T>
+void launch_reverse(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *rf, int64_t rec_begin,
+                    int64_t rec_count, int32_t nl, int64_t n, int32_t ray0, const int64_t *dep_ptr,
+                    const int32_t *dep_site, const typename RecOf<T>::type *dep_rec, const T *chi, const T *S,
+                    const T *I, const T *gI, const T *gJ, const double *ray_w, T *Ibar, T *Sbar, T *Cbar);
+template <typename T>
+void launch_reverse_reduce(hipStream_t s, int64_t n, int32_t nl, int32_t ray0, int32_t group, const double *dirs,
+                           const uint8_t *wall, const T *Ibar, const T *Sbar, const T *Cbar, double *acc_chi,
+                           double *acc_S, double *acc_Ib, double *acc_It);
+template <typename T> void launch_to_prec(hipStream_t s, int64_t nn, const double *a, T *out);
+template <typename T> void launch_fill_zero(hipStream_t s, int64_t count, T *p);
+template <typename T>
+void launch_emergent_scatter(hipStream_t s, int64_t total, int32_t nl, int64_t n, const int32_t *em_ray,
+                             const int32_t *em_site, const T *g_em, T *gI);
+template <typename T>
+void launch_lte_vjp(hipStream_t s, int64_t n, int32_t nl, const double *lam, double kappa0, const double *T_,
+                    const double *rho, const T *g_chi, const T *g_S, const T *g_Ib, double *g_T, double *g_rho);
 
 // ---- k_regular.hip
 template <typename T>

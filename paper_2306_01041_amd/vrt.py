@@ -94,6 +94,12 @@ vrt_formal_solution = _sig("vrt_formal_solution", _st, [_vp, ctypes.c_int32, cty
 vrt_two_level_solve = _sig("vrt_two_level_solve", _st, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _d, _vp,
                                                         _vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,
                                                         ctypes.c_double, _vp, _d, _i32])
+vrt_formal_solution_vjp = _sig("vrt_formal_solution_vjp", _st, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp,
+                                                                _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                                                ctypes.c_int32])
+vrt_emergent_scatter = _sig("vrt_emergent_scatter", _st, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp])
+vrt_lte_continuum_vjp = _sig("vrt_lte_continuum_vjp", _st, [_vp, ctypes.c_int32, ctypes.c_int32, _d, ctypes.c_double,
+                                                            _vp, _vp, _vp, _vp, _vp, _vp, _vp])
 vrt_grid_device_status = _sig("vrt_grid_device_status", _st, [_vp])
 vrt_grid_emergent_index = _sig("vrt_grid_emergent_index", _st, [_vp, _i64, _i32])
 vrt_emergent_gather = _sig("vrt_emergent_gather", _st, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp])
@@ -379,3 +385,111 @@ def two_level_solve(grid: Grid, wlam, phi, chi_line, chi_cont, B, eps, S_line, m
                                             _dev(chi_line), _dev(chi_cont), _dev(B), float(eps), int(max_iter),
                                             float(tol), _dev(S_line), _p(hist, _d), ctypes.byref(it)))
     return st, it.value, hist[: it.value].copy()
+
+
+def formal_solution_vjp(grid: Grid, chi, S, dL_dI=None, dL_dJ=None, I_bottom=None, I_top=None, I_rays=None,
+                        ray_group: int = 0):
+    """(dL/dchi, dL/dS, dL/dI_bottom, dL/dI_top) as new device tensors [n, nl]."""
+    import torch
+
+    inf = grid.info()
+    n, R = inf["n_sites"], inf["n_rays"]
+    nl = chi.shape[1]
+    for t, name in ((chi, "chi"), (S, "S"), (dL_dJ, "dL_dJ"), (I_bottom, "I_bottom"), (I_top, "I_top")):
+        _need(t, (n, nl), chi.dtype, name)
+    _need(I_rays, (R, n, nl), chi.dtype, "I_rays")
+    _need(dL_dI, (R, n, nl), chi.dtype, "dL_dI")
+    outs = [torch.empty((n, nl), dtype=chi.dtype, device=chi.device) for _ in range(4)]
+    grid.ctx.check(vrt_formal_solution_vjp(grid.handle, _prec_of(chi), int(nl), _dev(chi), _dev(S), _dev(I_bottom),
+                                           _dev(I_top), _dev(I_rays), _dev(dL_dI), _dev(dL_dJ),
+                                           *[_dev(o) for o in outs], int(ray_group)))
+    return tuple(outs)
+
+
+def emergent_scatter(grid: Grid, dL_dIem, dL_dI):
+    inf = grid.info()
+    off, _ = grid.emergent_index()
+    nl = dL_dIem.shape[1]
+    _need(dL_dIem, (int(off[-1]), nl), dL_dIem.dtype, "dL_dIem")
+    _need(dL_dI, (inf["n_rays"], inf["n_sites"], nl), dL_dIem.dtype, "dL_dI")
+    grid.ctx.check(vrt_emergent_scatter(grid.handle, _prec_of(dL_dIem), int(nl), _dev(dL_dIem), _dev(dL_dI)))
+
+
+def lte_continuum_vjp(grid: Grid, lam, kappa0, T, rho, dL_dchi, dL_dS, dL_dIbottom=None):
+    """(dL/dT, dL/drho) as new float64 device tensors [n]."""
+    import torch
+
+    lam = np.ascontiguousarray(np.atleast_1d(lam), np.float64)
+    n = grid.info()["n_sites"]
+    _need(T, (n,), torch.float64, "T")
+    _need(rho, (n,), torch.float64, "rho")
+    for t, name in ((dL_dchi, "dL_dchi"), (dL_dS, "dL_dS"), (dL_dIbottom, "dL_dIbottom")):
+        _need(t, (n, len(lam)), dL_dchi.dtype, name)
+    gT = torch.empty((n,), dtype=torch.float64, device=T.device)
+    gr = torch.empty_like(gT)
+    grid.ctx.check(vrt_lte_continuum_vjp(grid.handle, _prec_of(dL_dchi), len(lam), _p(lam, _d), float(kappa0),
+                                         _dev(T), _dev(rho), _dev(dL_dchi), _dev(dL_dS), _dev(dL_dIbottom),
+                                         _dev(gT), _dev(gr)))
+    return gT, gr
+
+
+def _make_lte_emergent():
+    import torch
+
+    class LTEEmergent(torch.autograd.Function):
+        """Emergent intensities of the grey LTE continuum as a differentiable
+        function of per-site temperature and density (float64 [n] each).
+
+        Forward: chi, S = lte_continuum(T, rho); formal solution; emergent
+        gather. Backward: emergent scatter, the hand-written reverse sweep
+        (vrt_formal_solution_vjp) and the LTE chain rule; every step runs in
+        the library's kernels."""
+
+        @staticmethod
+        def forward(fctx, T, rho, grid, lam, kappa0, dtype, keep_intensities, ray_group):
+            inf = grid.info()
+            n, R = inf["n_sites"], inf["n_rays"]
+            lam = np.ascontiguousarray(np.atleast_1d(lam), np.float64)
+            nl = len(lam)
+            dev = T.device
+            chi = torch.empty((n, nl), dtype=dtype, device=dev)
+            S = torch.empty_like(chi)
+            J = torch.empty_like(chi)
+            I = torch.empty((R, n, nl), dtype=dtype, device=dev) if keep_intensities else None
+            lte_continuum(grid, lam, kappa0, T, rho, chi, S)
+            formal_solution(grid, chi, S, J, I_rays=I, exec_mode=VRT_EXEC_BATCHED)
+            off, _ = grid.emergent_index()
+            em = torch.empty((int(off[-1]), nl), dtype=dtype, device=dev)
+            emergent_gather(grid, em, I_rays=I)
+            fctx.grid, fctx.lam, fctx.kappa0, fctx.ray_group = grid, lam, kappa0, ray_group
+            fctx.I = I
+            fctx.save_for_backward(T, rho, chi, S)
+            return em
+
+        @staticmethod
+        def backward(fctx, g_em):
+            T, rho, chi, S = fctx.saved_tensors
+            grid = fctx.grid
+            inf = grid.info()
+            gI = torch.empty((inf["n_rays"], inf["n_sites"], chi.shape[1]), dtype=chi.dtype, device=chi.device)
+            emergent_scatter(grid, g_em.contiguous().to(chi.dtype), gI)
+            g_chi, g_S, g_Ib, _ = formal_solution_vjp(grid, chi, S, dL_dI=gI, I_rays=fctx.I,
+                                                      ray_group=fctx.ray_group)
+            gT, gr = lte_continuum_vjp(grid, fctx.lam, fctx.kappa0, T, rho, g_chi, g_S, g_Ib)
+            return gT, gr, None, None, None, None, None, None
+
+    return LTEEmergent
+
+
+_LTE_EMERGENT = None
+
+
+def lte_emergent(T, rho, grid: Grid, lam, kappa0, dtype=None, keep_intensities=True, ray_group=0):
+    """Differentiable emergent intensities [n_emergent, nl] (see LTEEmergent)."""
+    import torch
+
+    global _LTE_EMERGENT
+    if _LTE_EMERGENT is None:
+        _LTE_EMERGENT = _make_lte_emergent()
+    return _LTE_EMERGENT.apply(T, rho, grid, lam, kappa0, torch.float32 if dtype is None else dtype,
+                               keep_intensities, ray_group)

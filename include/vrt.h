@@ -299,6 +299,29 @@ vrt_status vrt_two_level_solve(vrt_grid grid, vrt_prec sweep_prec, vrt_exec exec
                                const double *chi_cont, const double *B, double eps, int32_t max_iter,
                                double tol, double *S_line, double *dS_hist, int32_t *n_iter);
 
+/* Many independent atmospheres solved as one batch (Sect. 3: the method is
+ * applied per snapshot; a batch of uneven snapshots shares every launch).
+ * The grid is the disjoint union of the atmospheres, atmosphere a owning
+ * sites [atm_ptr[a], atm_ptr[a+1]) (host [n_atm+1], from 0 to n, not
+ * decreasing; empty atmospheres allowed). No site may select an upwind
+ * neighbour in another atmosphere (checked on the device: VRT_E_GRID).
+ * The iteration is that of vrt_two_level_solve applied to each atmosphere on
+ * its own: the change max |dS_line| / |S_line| is taken per atmosphere, and an
+ * atmosphere that has converged keeps its S_line while the others go on, so
+ * its result equals a solve of that atmosphere alone.
+ *   dS_hist  host [max_iter][n_atm] or NULL: the change of each atmosphere
+ *            after each iteration, -1 once it has stopped.
+ *   n_iter   host [n_atm], required: iterations done per atmosphere.
+ * Other arguments as vrt_two_level_solve. Voronoi grids when n_atm > 1.
+ * Returns VRT_OK when every atmosphere converged, VRT_W_NOT_CONVERGED if any
+ * reached the cap, VRT_E_NUMERIC on a non-finite change. Blocks. */
+vrt_status vrt_two_level_solve_batched(vrt_grid grid, vrt_prec sweep_prec, vrt_exec exec,
+                                       int32_t n_lambda, const double *wlam, const double *phi,
+                                       const double *chi_line, const double *chi_cont,
+                                       const double *B, double eps, int32_t max_iter, double tol,
+                                       double *S_line, int32_t n_atm, const int64_t *atm_ptr,
+                                       double *dS_hist, int32_t *n_iter);
+
 /* Wait for the context stream, then report and clear the grid's device error
  * flag: VRT_OK, or VRT_E_TIMEOUT if a bounded wait of a persistent sweep gave
  * up since the last check (the outputs of that solution are invalid). */

@@ -8,7 +8,8 @@
 //   Jbar = sum_lambda wlam phi sum_r w_r I_r
 // in double precision straight from the per-ray intensities (J per wavelength
 // never goes to memory), updates S_L <- (1 - eps) Jbar + eps B in double
-// precision and max-reduces |dS_L| / |S_L| for the convergence test.
+// precision and max-reduces |dS_L| / |S_L| for the convergence test, per
+// atmosphere when several independent atmospheres are solved as one grid.
 
 #include "vrt_internal.h"
 
@@ -37,28 +38,56 @@ __global__ void broadcast_kernel(int64_t n, int32_t nl, const double *__restrict
   out[t] = (T)v[t / nl];
 }
 
-__global__ void zero_u64_kernel(unsigned long long *p) { *p = 0ull; }
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+__global__ void zero_u64_array_kernel(int32_t count, unsigned long long *p) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) p[t] = 0ull;
 }
 
-// One wavefront per site (grid-stride over sites), lanes over wavelengths.
+// atmosphere holding site i: the largest a with atm_ptr[a] <= i (empty
+// atmospheres are skipped because a later one starts at the same offset)
+__device__ __forceinline__ int32_t atm_of(int64_t i, int32_t n_atm, const int64_t *atm_ptr) {
+  int32_t lo = 0, hi = n_atm - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) / 2;
+    if (atm_ptr[mid] <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// One wavefront per site, lanes over wavelengths; each wave walks a contiguous
+// chunk of sites. Sites of atmosphere a are [atm_ptr[a], atm_ptr[a+1]); a wave
+// keeps the running maximum change of the atmosphere it is in and flushes it
+// with one atomic when it leaves that atmosphere. Inactive (converged)
+// atmospheres keep their S_line.
 template <typename T>
 __global__ __launch_bounds__(256) void line_update_kernel(int64_t n, int32_t nl, int32_t R, const T *__restrict__ I,
                                                           const double *__restrict__ w,
                                                           const double *__restrict__ wlam,
                                                           const double *__restrict__ phi,
                                                           const double *__restrict__ B, double eps,
-                                                          double *__restrict__ S_L, unsigned long long *dS_bits) {
+                                                          double *__restrict__ S_L, int32_t n_atm,
+                                                          const int64_t *__restrict__ atm_ptr,
+                                                          const int32_t *__restrict__ active,
+                                                          unsigned long long *dS_bits) {
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  const int64_t chunk = (n + waves - 1) / waves;
+  const int64_t i0 = wave * chunk, i1 = (i0 + chunk < n) ? i0 + chunk : n;
+  if (i0 >= i1) return;
   const int64_t nn = n * nl;
+  int32_t atm = atm_of(i0, n_atm, atm_ptr);
   double dmax = 0.0;
-  for (int64_t i = wave; i < n; i += waves) {
+  bool any = false;
+  for (int64_t i = i0; i < i1; ++i) {
+    while (i >= atm_ptr[atm + 1]) {
+      if (any && lane == 0) atomicMax(&dS_bits[atm], (unsigned long long)__double_as_longlong(dmax));
+      dmax = 0.0;
+      any = false;
+      ++atm;
+    }
+    if (!active[atm]) continue;
     double acc = 0.0;
     for (int l = lane; l < nl; l += 64) {
       const int64_t q = i * nl + l;
@@ -66,24 +95,31 @@ __global__ __launch_bounds__(256) void line_update_kernel(int64_t n, int32_t nl,
       for (int32_t r = 0; r < R; ++r) j += w[r] * (double)I[(int64_t)r * nn + q];
       acc += wlam[l] * phi[q] * j;
     }
-    const double jbar = wave_sum(acc);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
     const double s_old = S_L[i];
-    const double s_new = (1.0 - eps) * jbar + eps * B[i];
+    const double s_new = (1.0 - eps) * acc + eps * B[i];
     const double d = fabs(s_new - s_old) / fabs(s_old);
     // NaN compares false: keep it so the host sees a non-finite change
     dmax = (d > dmax || d != d) ? d : dmax;
+    any = true;
     if (lane == 0) S_L[i] = s_new;
   }
-  // block maximum, then one atomic per block; non-negative doubles order like
-  // their bit patterns and NaN sorts above +inf
-  __shared__ double wmax[4];
-  if (lane == 0) wmax[threadIdx.x >> 6] = dmax;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double m = wmax[0];
-    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = (wmax[k] > m || wmax[k] != wmax[k]) ? wmax[k] : m;
-    atomicMax(dS_bits, (unsigned long long)__double_as_longlong(m));
-  }
+  // non-negative doubles order like their bit patterns; NaN sorts above +inf
+  if (any && lane == 0) atomicMax(&dS_bits[atm], (unsigned long long)__double_as_longlong(dmax));
+}
+
+__global__ void check_partition_kernel(int64_t n, int32_t R, const int32_t *__restrict__ k1,
+                                       const int32_t *__restrict__ k2, int32_t n_atm,
+                                       const int64_t *__restrict__ atm_ptr, int32_t *bad) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * R) return;
+  const int64_t i = t % n;
+  const int32_t a = atm_of(i, n_atm, atm_ptr);
+  const int64_t lo = atm_ptr[a], hi = atm_ptr[a + 1];
+  const int32_t u = k1[t], v = k2[t];
+  const bool out = (u >= 0 && (u < lo || u >= hi)) || (v >= 0 && (v < lo || v >= hi));
+  if (out) atomicOr(bad, 1);
 }
 
 inline unsigned nb(int64_t work, int bs) { return (unsigned)((work + bs - 1) / bs); }
@@ -107,20 +143,28 @@ template <typename T> void launch_broadcast(hipStream_t s, int64_t n, int32_t nl
   VRT_HIP(hipGetLastError());
 }
 
-void launch_zero_u64(hipStream_t s, unsigned long long *p) {
-  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, s, p);
+void launch_zero_u64(hipStream_t s, int32_t count, unsigned long long *p) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(zero_u64_array_kernel, dim3(nb(count, 256)), dim3(256), 0, s, count, p);
+  VRT_HIP(hipGetLastError());
+}
+
+void launch_check_partition(hipStream_t s, int64_t n, int32_t R, const int32_t *k1, const int32_t *k2, int32_t n_atm,
+                            const int64_t *atm_ptr, int32_t *bad) {
+  if (n * R == 0) return;
+  hipLaunchKernelGGL(check_partition_kernel, dim3(nb(n * R, 256)), dim3(256), 0, s, n, R, k1, k2, n_atm, atm_ptr, bad);
   VRT_HIP(hipGetLastError());
 }
 
 template <typename T>
 void launch_line_update(hipStream_t s, int64_t n, int32_t nl, int32_t R, const T *I, const double *w,
                         const double *wlam, const double *phi, const double *B, double eps, double *S_L,
-                        unsigned long long *dS_bits) {
+                        int32_t n_atm, const int64_t *atm_ptr, const int32_t *active, unsigned long long *dS_bits) {
   if (n == 0) return;
   int64_t blocks = (n + 3) / 4;
   if (blocks > 8192) blocks = 8192;
   hipLaunchKernelGGL(line_update_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, n, nl, R, I, w, wlam, phi, B,
-                     eps, S_L, dS_bits);
+                     eps, S_L, n_atm, atm_ptr, active, dS_bits);
   VRT_HIP(hipGetLastError());
 }
 
@@ -131,10 +175,10 @@ template void launch_nlte_assemble<double>(hipStream_t, int64_t, int32_t, const 
 template void launch_broadcast<float>(hipStream_t, int64_t, int32_t, const double *, float *);
 template void launch_broadcast<double>(hipStream_t, int64_t, int32_t, const double *, double *);
 template void launch_line_update<float>(hipStream_t, int64_t, int32_t, int32_t, const float *, const double *,
-                                        const double *, const double *, const double *, double, double *,
-                                        unsigned long long *);
+                                        const double *, const double *, const double *, double, double *, int32_t,
+                                        const int64_t *, const int32_t *, unsigned long long *);
 template void launch_line_update<double>(hipStream_t, int64_t, int32_t, int32_t, const double *, const double *,
-                                         const double *, const double *, const double *, double, double *,
-                                         unsigned long long *);
+                                         const double *, const double *, const double *, double, double *, int32_t,
+                                         const int64_t *, const int32_t *, unsigned long long *);
 
 }  // namespace vrt

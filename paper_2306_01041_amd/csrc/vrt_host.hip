@@ -557,48 +557,81 @@ void formal_solution_vjp(vrt_grid g, int32_t nl, const T *chi, const T *S, const
   vrt::launch_to_prec<T>(s, nn, acc + 3 * nn, o_It);
 }
 
-// One Lambda iteration without the host read: reset the max-change word,
-// assemble chi and S from S_line, sweep every ray, then Jbar and the update.
+// One Lambda iteration without the host read: reset the per-atmosphere
+// max-change words, assemble chi and S from S_line, sweep every ray, then Jbar
+// and the update of the active atmospheres.
 template <typename T>
 void enqueue_lambda_step(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const double *phi, const double *chi_L,
-                         const double *chi_c, const double *B, double eps, double *S_L, T *I) {
+                         const double *chi_c, const double *B, double eps, double *S_L, T *I, int32_t n_atm) {
   T *chi = g->d_nchi.as<T>(), *S = g->d_nS.as<T>(), *Ib = g->d_nIb.as<T>();
   auto *dS = g->d_dS.as<unsigned long long>();
-  vrt::launch_zero_u64(s, dS);
+  vrt::launch_zero_u64(s, n_atm, dS);
   vrt::launch_nlte_assemble<T>(s, g->n, nl, phi, chi_L, chi_c, B, S_L, chi, S);
   enqueue_sweep<T>(g, s, ex == VRT_EXEC_GRAPH ? VRT_EXEC_BATCHED : ex, nl, chi, S, Ib, nullptr, I);
   vrt::launch_line_update<T>(s, g->n, nl, g->R, I, g->d_w.as<double>(), g->d_wlam.as<double>(), phi, B, eps, S_L,
-                             dS);
+                             n_atm, g->d_atm_ptr.as<int64_t>(), g->d_active.as<int32_t>(), dS);
 }
 
+// Lambda iteration of n_atm independent atmospheres stored as one grid:
+// atmosphere a owns sites [atm_ptr[a], atm_ptr[a+1]). Each is tested for
+// convergence on its own and stops updating its S_line once converged, so its
+// iterates are those of a solve of that atmosphere alone. hist is
+// [max_iter][n_atm] (-1 where an atmosphere had stopped), n_iter [n_atm].
 template <typename T>
 vrt_status two_level_solve(vrt_grid g, vrt_exec ex, int32_t nl, const double *wlam, const double *phi,
                            const double *chi_L, const double *chi_c, const double *B, double eps, int32_t max_iter,
-                           double tol, double *S_L, double *hist, int32_t *n_iter) {
+                           double tol, double *S_L, int32_t n_atm, const int64_t *atm_ptr, double *hist,
+                           int32_t *n_iter) {
   vrt_ctx ctx = g->ctx;
   hipStream_t s = ctx->stream;
   const size_t nn = (size_t)g->n * (size_t)nl;
   T *I = intensity_buffer<T>(g, nl, nullptr);
-  if (g->d_nchi.bytes < nn * sizeof(T) || g->d_wlam.bytes < (size_t)nl * 8) {
-    if (g->nlte_graph) {
-      (void)hipGraphExecDestroy(g->nlte_graph);
-      g->nlte_graph = nullptr;
-    }
-  }
+  VRT_HIP(hipStreamSynchronize(s));  // earlier work may still read the buffers replaced below
   g->d_nchi.alloc(nn * sizeof(T));
   g->d_nS.alloc(nn * sizeof(T));
   g->d_nIb.alloc(nn * sizeof(T));
-  g->d_dS.alloc(8);
-  if (!g->h_dS) VRT_HIP(hipHostMalloc((void **)&g->h_dS, 8, hipHostMallocDefault));
-  VRT_HIP(hipStreamSynchronize(s));  // earlier work may still read the old profile weights
+  g->d_dS.alloc((size_t)n_atm * 8);
+  g->d_atm_ptr.alloc((size_t)(n_atm + 1) * 8);
+  g->d_active.alloc((size_t)n_atm * 4 + 4);  // the last word is the partition-check flag
+  if (g->h_dS_cap < n_atm) {
+    if (g->h_dS) (void)hipHostFree(g->h_dS);
+    if (g->h_active) (void)hipHostFree(g->h_active);
+    g->h_dS = nullptr;
+    g->h_active = nullptr;
+    g->h_dS_cap = 0;
+    VRT_HIP(hipHostMalloc((void **)&g->h_dS, (size_t)n_atm * 8, hipHostMallocDefault));
+    VRT_HIP(hipHostMalloc((void **)&g->h_active, (size_t)n_atm * 4 + 4, hipHostMallocDefault));
+    g->h_dS_cap = n_atm;
+  }
   g->d_wlam.alloc((size_t)nl * 8);
   VRT_HIP(hipMemcpy(g->d_wlam.p, wlam, (size_t)nl * 8, hipMemcpyHostToDevice));
+  VRT_HIP(hipMemcpy(g->d_atm_ptr.p, atm_ptr, (size_t)(n_atm + 1) * 8, hipMemcpyHostToDevice));
+  int32_t *active = g->h_active;
+  for (int32_t a = 0; a < n_atm; ++a) active[a] = 1;
+  active[n_atm] = 0;
+  int32_t *d_bad = g->d_active.as<int32_t>() + n_atm;
+  VRT_HIP(hipMemcpy(g->d_active.p, active, (size_t)n_atm * 4 + 4, hipMemcpyHostToDevice));
+  if (n_atm > 1) {
+    vrt::launch_check_partition(s, g->n, g->R, g->d_k1.as<int32_t>(), g->d_k2.as<int32_t>(), n_atm,
+                                g->d_atm_ptr.as<int64_t>(), d_bad);
+    int32_t bad = 0;
+    VRT_HIP(hipMemcpyAsync(&bad, d_bad, 4, hipMemcpyDeviceToHost, s));
+    VRT_HIP(hipStreamSynchronize(s));
+    if (bad) fail(VRT_E_GRID, "a site reads an upwind neighbour in another atmosphere");
+  }
   vrt::launch_broadcast<T>(s, g->n, nl, B, g->d_nIb.as<T>());
   const int pexec = ex == VRT_EXEC_PERSISTENT && g->kind == 0 ? 1 : 0;
-  if (ex == VRT_EXEC_GRAPH || (ex == VRT_EXEC_PERSISTENT && g->kind != 0)) {
+  const bool use_graph = ex == VRT_EXEC_GRAPH || (ex == VRT_EXEC_PERSISTENT && g->kind != 0);
+  if (use_graph) {
     const auto key = std::make_tuple((int)sizeof(T), nl, (const void *)phi, (const void *)chi_L,
-                                     (const void *)chi_c, (const void *)B, (const void *)S_L, eps, pexec);
-    if (!g->nlte_graph || g->nlte_key != key) {
+                                     (const void *)chi_c, (const void *)B, (const void *)S_L, eps, pexec, n_atm,
+                                     (const void *)g->d_atm_ptr.p, (const void *)g->d_active.p,
+                                     (const void *)g->d_dS.p);
+    // the graph also bakes in the scratch pointers, which the allocations above may have moved
+    const bool same = g->nlte_graph && g->nlte_key == key && g->nlte_scratch[0] == g->d_nchi.p &&
+                      g->nlte_scratch[1] == g->d_nS.p && g->nlte_scratch[2] == g->d_nIb.p &&
+                      g->nlte_scratch[3] == (const void *)I && g->nlte_scratch[4] == g->d_wlam.p;
+    if (!same) {
       if (g->nlte_graph) (void)hipGraphExecDestroy(g->nlte_graph);
       g->nlte_graph = nullptr;
       if (!ctx->capture_stream) VRT_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
@@ -606,7 +639,7 @@ vrt_status two_level_solve(vrt_grid g, vrt_exec ex, int32_t nl, const double *wl
       VRT_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
       hipGraph_t graph = nullptr;
       try {
-        enqueue_lambda_step<T>(g, cs, VRT_EXEC_GRAPH, nl, phi, chi_L, chi_c, B, eps, S_L, I);
+        enqueue_lambda_step<T>(g, cs, VRT_EXEC_GRAPH, nl, phi, chi_L, chi_c, B, eps, S_L, I, n_atm);
       } catch (...) {
         (void)hipStreamEndCapture(cs, &graph);
         if (graph) (void)hipGraphDestroy(graph);
@@ -617,42 +650,53 @@ vrt_status two_level_solve(vrt_grid g, vrt_exec ex, int32_t nl, const double *wl
       (void)hipGraphDestroy(graph);
       VRT_HIP(e);
       g->nlte_key = key;
+      g->nlte_scratch[0] = g->d_nchi.p;
+      g->nlte_scratch[1] = g->d_nS.p;
+      g->nlte_scratch[2] = g->d_nIb.p;
+      g->nlte_scratch[3] = I;
+      g->nlte_scratch[4] = g->d_wlam.p;
     }
   }
-  int32_t it = 0;
-  vrt_status st = VRT_W_NOT_CONVERGED;
-  for (; it < max_iter; ++it) {
-    if (g->nlte_graph && (ex == VRT_EXEC_GRAPH || (ex == VRT_EXEC_PERSISTENT && g->kind != 0)))
+  for (int32_t a = 0; a < n_atm; ++a) n_iter[a] = 0;
+  int32_t n_active = n_atm;
+  for (int32_t it = 0; it < max_iter && n_active > 0; ++it) {
+    if (use_graph)
       VRT_HIP(hipGraphLaunch(g->nlte_graph, s));
     else
-      enqueue_lambda_step<T>(g, s, ex, nl, phi, chi_L, chi_c, B, eps, S_L, I);
-    VRT_HIP(hipMemcpyAsync(g->h_dS, g->d_dS.p, 8, hipMemcpyDeviceToHost, s));
+      enqueue_lambda_step<T>(g, s, ex, nl, phi, chi_L, chi_c, B, eps, S_L, I, n_atm);
+    VRT_HIP(hipMemcpyAsync(g->h_dS, g->d_dS.p, (size_t)n_atm * 8, hipMemcpyDeviceToHost, s));
     VRT_HIP(hipStreamSynchronize(s));
     if (pexec) {
       int32_t err = 0;
       VRT_HIP(hipMemcpy(&err, g->d_epoch.as<int32_t>() + 1, 4, hipMemcpyDeviceToHost));
       if (err) {
         VRT_HIP(hipMemset(g->d_epoch.as<int32_t>() + 1, 0, 4));
-        if (n_iter) *n_iter = it + 1;
         fail(VRT_E_TIMEOUT, "a bounded wait of the persistent sweep gave up at iteration %d", it + 1);
       }
     }
-    double d;
-    std::memcpy(&d, g->h_dS, 8);
-    if (hist) hist[it] = d;
-    if (!std::isfinite(d)) {
-      if (n_iter) *n_iter = it + 1;
-      fail(VRT_E_NUMERIC, "non-finite source-function change at iteration %d", it + 1);
+    bool changed = false;
+    for (int32_t a = 0; a < n_atm; ++a) {
+      double d = -1.0;
+      if (active[a]) {
+        std::memcpy(&d, g->h_dS + a, 8);
+        n_iter[a] = it + 1;
+        if (!std::isfinite(d)) {
+          if (hist) hist[(size_t)it * n_atm + a] = d;
+          fail(VRT_E_NUMERIC, "non-finite source-function change in atmosphere %d at iteration %d", a, it + 1);
+        }
+        if (d < tol) {
+          active[a] = 0;
+          --n_active;
+          changed = true;
+        }
+      }
+      if (hist) hist[(size_t)it * n_atm + a] = d;
     }
-    if (d < tol) {
-      ++it;
-      st = VRT_OK;
-      break;
-    }
+    if (changed && n_active > 0)
+      VRT_HIP(hipMemcpyAsync(g->d_active.p, active, (size_t)n_atm * 4, hipMemcpyHostToDevice, s));
   }
-  if (n_iter) *n_iter = it;
   g->last_I = I;
-  return st;
+  return n_active == 0 ? VRT_OK : VRT_W_NOT_CONVERGED;
 }
 
 template <typename T>
@@ -911,6 +955,7 @@ void vrt_grid_destroy(vrt_grid g) {
   (void)hipStreamSynchronize(g->ctx->stream);
   g->drop_graphs();
   if (g->h_dS) (void)hipHostFree(g->h_dS);
+  if (g->h_active) (void)hipHostFree(g->h_active);
   delete g;
 }
 
@@ -1125,25 +1170,60 @@ vrt_status vrt_formal_solution(vrt_grid g, vrt_prec prec, vrt_exec exec, int32_t
   });
 }
 
+static vrt_status two_level_entry(vrt_grid g, vrt_prec prec, vrt_exec exec, int32_t n_lambda, const double *wlam,
+                                  const double *phi, const double *chi_line, const double *chi_cont, const double *B,
+                                  double eps, int32_t max_iter, double tol, double *S_line, int32_t n_atm,
+                                  const int64_t *atm_ptr, double *dS_hist, int32_t *n_iter) {
+  if (!valid_prec(prec) || n_lambda <= 0 || !wlam || max_iter < 0 || !(tol >= 0.0) || !(eps >= 0.0 && eps <= 1.0))
+    fail(VRT_E_ARG, "bad two-level arguments");
+  if (exec != VRT_EXEC_PLAIN && exec != VRT_EXEC_BATCHED && exec != VRT_EXEC_GRAPH && exec != VRT_EXEC_PERSISTENT)
+    fail(VRT_E_ARG, "bad execution mode");
+  if (n_atm <= 0 || !atm_ptr || !n_iter) fail(VRT_E_ARG, "bad atmosphere partition");
+  if (atm_ptr[0] != 0 || atm_ptr[n_atm] != g->n) fail(VRT_E_ARG, "atmosphere offsets must run from 0 to n");
+  for (int32_t a = 0; a < n_atm; ++a)
+    if (atm_ptr[a + 1] < atm_ptr[a]) fail(VRT_E_ARG, "atmosphere offsets must not decrease");
+  if (n_atm > 1 && g->kind != 0) fail(VRT_E_ARG, "several atmospheres need a Voronoi grid");
+  if (g->R == 0) fail(VRT_E_STATE, "rays not set");
+  for (int32_t a = 0; a < n_atm; ++a) n_iter[a] = 0;
+  if (g->n == 0 || max_iter == 0) return max_iter == 0 ? VRT_W_NOT_CONVERGED : VRT_OK;
+  if (!phi || !chi_line || !chi_cont || !B || !S_line) fail(VRT_E_ARG, "null device array");
+  if (prec == VRT_F32)
+    return two_level_solve<float>(g, exec, n_lambda, wlam, phi, chi_line, chi_cont, B, eps, max_iter, tol, S_line,
+                                  n_atm, atm_ptr, dS_hist, n_iter);
+  return two_level_solve<double>(g, exec, n_lambda, wlam, phi, chi_line, chi_cont, B, eps, max_iter, tol, S_line,
+                                 n_atm, atm_ptr, dS_hist, n_iter);
+}
+
 vrt_status vrt_two_level_solve(vrt_grid g, vrt_prec prec, vrt_exec exec, int32_t n_lambda, const double *wlam,
                                const double *phi, const double *chi_line, const double *chi_cont, const double *B,
                                double eps, int32_t max_iter, double tol, double *S_line, double *dS_hist,
                                int32_t *n_iter) {
   if (!g) return VRT_E_ARG;
   return guarded(g->ctx, [&]() -> vrt_status {
-    if (!valid_prec(prec) || n_lambda <= 0 || !wlam || max_iter < 0 || !(tol >= 0.0) || !(eps >= 0.0 && eps <= 1.0))
-      fail(VRT_E_ARG, "bad two-level arguments");
-    if (exec != VRT_EXEC_PLAIN && exec != VRT_EXEC_BATCHED && exec != VRT_EXEC_GRAPH && exec != VRT_EXEC_PERSISTENT)
-      fail(VRT_E_ARG, "bad execution mode");
-    if (g->R == 0) fail(VRT_E_STATE, "rays not set");
-    if (n_iter) *n_iter = 0;
-    if (g->n == 0 || max_iter == 0) return max_iter == 0 ? VRT_W_NOT_CONVERGED : VRT_OK;
-    if (!phi || !chi_line || !chi_cont || !B || !S_line) fail(VRT_E_ARG, "null device array");
-    if (prec == VRT_F32)
-      return two_level_solve<float>(g, exec, n_lambda, wlam, phi, chi_line, chi_cont, B, eps, max_iter, tol, S_line,
-                                    dS_hist, n_iter);
-    return two_level_solve<double>(g, exec, n_lambda, wlam, phi, chi_line, chi_cont, B, eps, max_iter, tol, S_line,
-                                   dS_hist, n_iter);
+    const int64_t ptr[2] = {0, g->n};
+    int32_t it = 0;
+    vrt_status st = VRT_OK;
+    try {
+      st = two_level_entry(g, prec, exec, n_lambda, wlam, phi, chi_line, chi_cont, B, eps, max_iter, tol, S_line, 1,
+                           ptr, dS_hist, &it);
+    } catch (...) {
+      if (n_iter) *n_iter = it;
+      throw;
+    }
+    if (n_iter) *n_iter = it;
+    return st;
+  });
+}
+
+vrt_status vrt_two_level_solve_batched(vrt_grid g, vrt_prec prec, vrt_exec exec, int32_t n_lambda,
+                                       const double *wlam, const double *phi, const double *chi_line,
+                                       const double *chi_cont, const double *B, double eps, int32_t max_iter,
+                                       double tol, double *S_line, int32_t n_atm, const int64_t *atm_ptr,
+                                       double *dS_hist, int32_t *n_iter) {
+  if (!g) return VRT_E_ARG;
+  return guarded(g->ctx, [&]() -> vrt_status {
+    return two_level_entry(g, prec, exec, n_lambda, wlam, phi, chi_line, chi_cont, B, eps, max_iter, tol, S_line,
+                           n_atm, atm_ptr, dS_hist, n_iter);
   });
 }
 

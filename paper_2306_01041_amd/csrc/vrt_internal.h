@@ -177,11 +177,15 @@ struct vrt_grid_s {
 
   // two-level iteration scratch: chi, S, I_bottom in the sweep precision, the
   // profile weights, the max-change word and its pinned host copy
-  vrt::DevBuf d_nchi, d_nS, d_nIb, d_wlam, d_dS;
-  unsigned long long *h_dS = nullptr;
+  vrt::DevBuf d_nchi, d_nS, d_nIb, d_wlam, d_dS, d_atm_ptr, d_active;
+  unsigned long long *h_dS = nullptr;  // pinned, [n_atm]
+  int32_t *h_active = nullptr;         // pinned, [n_atm]
+  int32_t h_dS_cap = 0;
   hipGraphExec_t nlte_graph = nullptr;
-  std::tuple<int, int32_t, const void *, const void *, const void *, const void *, const void *, double, int>
+  std::tuple<int, int32_t, const void *, const void *, const void *, const void *, const void *, double, int, int32_t,
+             const void *, const void *, const void *>
       nlte_key{};
+  const void *nlte_scratch[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 
   // reverse sweep: per-ray dependents lists (absolute offsets [R][n+1], the
   // dependent site, and the weight and length of the line it reads), scratch
@@ -254,11 +258,14 @@ template <typename T>
 void launch_nlte_assemble(hipStream_t s, int64_t n, int32_t nl, const double *phi, const double *chi_L,
                           const double *chi_c, const double *B, const double *S_L, T *chi, T *S);
 template <typename T> void launch_broadcast(hipStream_t s, int64_t n, int32_t nl, const double *v, T *out);
-void launch_zero_u64(hipStream_t s, unsigned long long *p);
+void launch_zero_u64(hipStream_t s, int32_t count, unsigned long long *p);
+// sets *bad to 1 if a selected upwind neighbour of a site lies in another atmosphere
+void launch_check_partition(hipStream_t s, int64_t n, int32_t R, const int32_t *k1, const int32_t *k2, int32_t n_atm,
+                            const int64_t *atm_ptr, int32_t *bad);
 template <typename T>
 void launch_line_update(hipStream_t s, int64_t n, int32_t nl, int32_t R, const T *I, const double *w,
                         const double *wlam, const double *phi, const double *B, double eps, double *S_L,
-                        unsigned long long *dS_bits);
+                        int32_t n_atm, const int64_t *atm_ptr, const int32_t *active, unsigned long long *dS_bits);
 
 // ---- k_adjoint.hip
 template <typename T>

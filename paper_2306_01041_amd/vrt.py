@@ -94,6 +94,10 @@ vrt_formal_solution = _sig("vrt_formal_solution", _st, [_vp, ctypes.c_int32, cty
 vrt_two_level_solve = _sig("vrt_two_level_solve", _st, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _d, _vp,
                                                         _vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,
                                                         ctypes.c_double, _vp, _d, _i32])
+vrt_two_level_solve_batched = _sig("vrt_two_level_solve_batched", _st,
+                                   [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _d, _vp, _vp, _vp, _vp,
+                                    ctypes.c_double, ctypes.c_int32, ctypes.c_double, _vp, ctypes.c_int32, _i64, _d,
+                                    _i32])
 vrt_formal_solution_vjp = _sig("vrt_formal_solution_vjp", _st, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp,
                                                                 _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                                                 ctypes.c_int32])
@@ -385,6 +389,37 @@ def two_level_solve(grid: Grid, wlam, phi, chi_line, chi_cont, B, eps, S_line, m
                                             _dev(chi_line), _dev(chi_cont), _dev(B), float(eps), int(max_iter),
                                             float(tol), _dev(S_line), _p(hist, _d), ctypes.byref(it)))
     return st, it.value, hist[: it.value].copy()
+
+
+def two_level_solve_batched(grid: Grid, atm_ptr, wlam, phi, chi_line, chi_cont, B, eps, S_line, max_iter=1000,
+                            tol=1e-3, sweep_dtype=None, exec_mode=VRT_EXEC_GRAPH):
+    """Lambda iteration of independent atmospheres stored as one grid (atmosphere a owns
+    sites atm_ptr[a]:atm_ptr[a+1]); each converges and freezes on its own.
+
+    Returns (status, n_iter per atmosphere, dS history [iterations, n_atm] with -1 after
+    an atmosphere stopped).
+    """
+    import torch
+
+    sweep_dtype = torch.float32 if sweep_dtype is None else sweep_dtype
+    n = grid.info()["n_sites"]
+    ptr = np.ascontiguousarray(atm_ptr, np.int64)
+    n_atm = len(ptr) - 1
+    if n_atm < 1:
+        raise ValueError("atm_ptr needs at least two entries")
+    wlam = np.ascontiguousarray(wlam, np.float64)
+    nl = len(wlam)
+    _need(phi, (n, nl), torch.float64, "phi")
+    for t, name in ((chi_line, "chi_line"), (chi_cont, "chi_cont"), (B, "B"), (S_line, "S_line")):
+        _need(t, (n,), torch.float64, name)
+    hist = np.zeros((max(int(max_iter), 1), n_atm), np.float64)
+    its = np.zeros(n_atm, np.int32)
+    prec = VRT_F32 if sweep_dtype == torch.float32 else VRT_F64
+    st = grid.ctx.check(vrt_two_level_solve_batched(grid.handle, prec, int(exec_mode), nl, _p(wlam, _d), _dev(phi),
+                                                    _dev(chi_line), _dev(chi_cont), _dev(B), float(eps),
+                                                    int(max_iter), float(tol), _dev(S_line), n_atm, _p(ptr, _i64),
+                                                    _p(hist, _d), _p(its, _i32)))
+    return st, its, hist[: int(its.max(initial=0))].copy()
 
 
 def formal_solution_vjp(grid: Grid, chi, S, dL_dI=None, dL_dJ=None, I_bottom=None, I_top=None, I_rays=None,

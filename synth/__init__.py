@@ -21,7 +21,7 @@ from .atmosphere import (
     sample_sites,
     make_atmosphere,
 )
-from .voronoi import VoronoiGrid, voronoi_neighbours, lattice_grid, check_symmetric
+from .voronoi import VoronoiGrid, voronoi_neighbours, lattice_grid, check_symmetric, concat_grids
 
 __all__ = [
     "gauss_legendre_quadrature",
@@ -38,4 +38,14 @@ __all__ = [
     "voronoi_neighbours",
     "lattice_grid",
     "check_symmetric",
+    "concat_grids",
+    "batch_sizes",
 ]
+
+
+def batch_sizes(n_atm: int, lo: int, hi: int, seed: int):
+    """Atmosphere sizes drawn log-uniformly in [lo, hi] (rounded), seeded."""
+    import numpy as _np
+
+    rng = _np.random.Generator(_np.random.PCG64(seed))
+    return [int(round(_np.exp(rng.uniform(_np.log(lo), _np.log(hi))))) for _ in range(n_atm)]

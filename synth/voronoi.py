@@ -241,3 +241,27 @@ def lattice_grid(nx: int, ny: int, z, dx: float = 1.0, dy: float = 1.0, x0: floa
     hi = np.array([x0 + (nx - 0.5) * dx, y0 + (ny - 0.5) * dy, Lz1])
     return VoronoiGrid(xyz=xyz, nbr_ptr=ptr, nbr_idx=idx, nbr_shift=shift, wall=wall,
                        lo=lo, hi=hi, periodic_xy=periodic_xy)
+
+
+def concat_grids(grids):
+    """Disjoint union of Voronoi grids that share one box: sites of grid j are
+    renumbered by the number of sites before it; no neighbour list crosses
+    between grids. Returns (union grid, site offsets [len(grids) + 1])."""
+    grids = list(grids)
+    if not grids:
+        raise ValueError("no grids")
+    lo, hi = grids[0].lo, grids[0].hi
+    for g in grids:
+        if not (np.allclose(g.lo, lo) and np.allclose(g.hi, hi)) or g.periodic_xy != grids[0].periodic_xy:
+            raise ValueError("grids of a batch must share one box")
+    off = np.zeros(len(grids) + 1, np.int64)
+    off[1:] = np.cumsum([g.n for g in grids])
+    eoff = np.zeros(len(grids) + 1, np.int64)
+    eoff[1:] = np.cumsum([g.m for g in grids])
+    xyz = np.concatenate([g.xyz for g in grids])
+    ptr = np.concatenate([[0]] + [g.nbr_ptr[1:] + eoff[j] for j, g in enumerate(grids)]).astype(np.int64)
+    idx = np.concatenate([g.nbr_idx.astype(np.int64) + off[j] for j, g in enumerate(grids)]).astype(np.int32)
+    shift = np.concatenate([g.nbr_shift for g in grids]).astype(np.int8)
+    wall = np.concatenate([g.wall for g in grids]).astype(np.uint8)
+    return VoronoiGrid(xyz=xyz, nbr_ptr=ptr, nbr_idx=idx, nbr_shift=shift, wall=wall, lo=np.asarray(lo),
+                       hi=np.asarray(hi), periodic_xy=grids[0].periodic_xy), off

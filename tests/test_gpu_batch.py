@@ -1,0 +1,165 @@
+"""GPU parity of the batched two-level Lambda iteration: several independent
+atmospheres of uneven size stored as one grid (Sect. 3 applies the method per
+snapshot; a batch shares every launch).
+
+Each atmosphere converges and freezes on its own, so its result must equal a
+solve of that atmosphere alone: against the oracle's standalone iteration
+(count, history and S_line to 1e-12 with double-precision sweeps), and
+bit for bit against standalone GPU solves with single-precision sweeps.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import flush, relerr, to_dev
+from oracle import nlte as onl
+from synth.nlte import LAMBDA0_NM, line_setup
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SIZES = [300, 1100, 150, 700, 2000]
+EPS, TOL = 1e-2, 1e-3
+
+
+@pytest.fixture(scope="module")
+def v():
+    import paper_2306_01041_amd
+
+    return paper_2306_01041_amd.load()
+
+
+@pytest.fixture(scope="module")
+def ctx(v):
+    c = v.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def batch():
+    atms = [synth.make_atmosphere(n, seed=200 + k) for k, n in enumerate(SIZES)]
+    grids = [synth.voronoi_neighbours(a.xyz, a.box.lo, a.box.hi) for a in atms]
+    U, off = synth.concat_grids(grids)
+    T = np.concatenate([a.T for a in atms])
+    rho = np.concatenate([a.rho for a in atms])
+    line = line_setup(T, rho, n_lambda=21)
+    dirs, w = synth.gauss_legendre_quadrature()
+    # one continuum constant for the whole batch (a recipe constant, not a result)
+    return dict(grids=grids, U=U, off=np.asarray(off, np.int64), T=T, rho=rho, line=line, dirs=dirs, w=w,
+                kappa0=atms[0].kappa0, lam0=np.array([LAMBDA0_NM * 1e-9]))
+
+
+def _grid(v, ctx, g, b):
+    G = v.Grid.from_synth(ctx, g)
+    G.set_rays(b["dirs"], b["w"])
+    return G
+
+
+def _continuum(v, G, b, sl):
+    d = torch.float64
+    n = sl.stop - sl.start
+    chi_c = torch.empty((n, 1), dtype=d, device="cuda:0")
+    B = torch.empty_like(chi_c)
+    v.lte_continuum(G, b["lam0"], b["kappa0"], to_dev(b["T"][sl], d), to_dev(b["rho"][sl], d), chi_c, B)
+    return chi_c[:, 0].contiguous(), B[:, 0].contiguous()
+
+
+def _solve_batched(v, ctx, b, dt, mode):
+    G = _grid(v, ctx, b["U"], b)
+    chi_c, B = _continuum(v, G, b, slice(0, b["U"].n))
+    line = b["line"]
+    d = torch.float64
+    S = B.clone()
+    st, its, hist = v.two_level_solve_batched(G, b["off"], line.wlam, to_dev(line.phi, d), to_dev(line.chi_line, d),
+                                              chi_c, B, EPS, S, max_iter=500, tol=TOL, sweep_dtype=dt,
+                                              exec_mode=getattr(v, "VRT_EXEC_" + mode))
+    torch.cuda.synchronize()
+    G.close()
+    return st, its, hist, S.cpu().numpy()
+
+
+@pytest.mark.parametrize("mode", ["GRAPH", "BATCHED"])
+def test_batch_matches_standalone_oracle(v, ctx, batch, mode):
+    flush(f"batch f64 {mode} sizes={SIZES}")
+    st, its, hist, S = _solve_batched(v, ctx, batch, torch.float64, mode)
+    assert st == v.VRT_OK
+    line, off = batch["line"], batch["off"]
+    chi_c, B = oracle.lte(batch["lam0"], batch["kappa0"], batch["T"], batch["rho"])
+    for a, g in enumerate(batch["grids"]):
+        sl = slice(off[a], off[a + 1])
+        sel = oracle.select(g, batch["dirs"])
+        S_o, h_o, nit_o, ok = onl.lambda_iterate(g, batch["dirs"], batch["w"], sel, chi_c[sl, 0], line.chi_line[sl],
+                                                 line.phi[sl], line.wlam, B[sl, 0], EPS, max_iter=500, tol=TOL)
+        flush(f"  atmosphere {a} ({g.n} sites): {its[a]} iterations, oracle {nit_o}")
+        assert ok and its[a] == nit_o
+        assert relerr(S[sl], S_o) <= 1e-12
+        assert np.max(np.abs(hist[: its[a], a] - h_o)) <= 1e-11
+        assert np.all(hist[its[a]:, a] == -1.0)
+    assert len(set(its.tolist())) > 1  # the atmospheres stop at different iterations
+
+
+def test_batch_equals_standalone_gpu_solves_bitwise(v, ctx, batch):
+    flush("batch f32 vs standalone f32 solves")
+    st, its, hist, S = _solve_batched(v, ctx, batch, torch.float32, "GRAPH")
+    assert st == v.VRT_OK
+    line, off = batch["line"], batch["off"]
+    d = torch.float64
+    for a, g in enumerate(batch["grids"]):
+        sl = slice(off[a], off[a + 1])
+        G = _grid(v, ctx, g, batch)
+        chi_c, B = _continuum(v, G, batch, sl)
+        S1 = B.clone()
+        st1, nit1, h1 = v.two_level_solve(G, line.wlam, to_dev(line.phi[sl], d), to_dev(line.chi_line[sl], d), chi_c,
+                                          B, EPS, S1, max_iter=500, tol=TOL, sweep_dtype=torch.float32)
+        torch.cuda.synchronize()
+        G.close()
+        assert st1 == v.VRT_OK and nit1 == its[a]
+        assert np.array_equal(S1.cpu().numpy(), S[sl])
+        assert np.array_equal(h1, hist[: its[a], a])
+
+
+def test_empty_atmosphere_and_cap(v, ctx, batch):
+    """An empty atmosphere stops at once with change 0; a cap below every count
+    leaves all active and reports not converged."""
+    flush("batch empty atmosphere and cap")
+    U, off = batch["U"], batch["off"]
+    ptr = np.array([0, off[1], off[1], U.n], np.int64)
+    # the second range holds atmospheres 1..4, which are mutually independent too
+    G = _grid(v, ctx, U, batch)
+    chi_c, B = _continuum(v, G, batch, slice(0, U.n))
+    line = batch["line"]
+    d = torch.float64
+    S = B.clone()
+    st, its, hist = v.two_level_solve_batched(G, ptr, line.wlam, to_dev(line.phi, d), to_dev(line.chi_line, d),
+                                              chi_c, B, EPS, S, max_iter=3, tol=TOL, sweep_dtype=torch.float32)
+    assert st == v.VRT_W_NOT_CONVERGED
+    assert its.tolist() == [3, 1, 3]
+    assert hist[0, 1] == 0.0 and np.all(hist[1:, 1] == -1.0)
+    assert np.all(hist[:, 0] > TOL) and np.all(hist[:, 2] > TOL)
+    G.close()
+
+
+def test_partition_errors(v, ctx, batch):
+    flush("batch partition errors")
+    U, off = batch["U"], batch["off"]
+    G = _grid(v, ctx, U, batch)
+    chi_c, B = _continuum(v, G, batch, slice(0, U.n))
+    line = batch["line"]
+    d = torch.float64
+    args = (line.wlam, to_dev(line.phi, d), to_dev(line.chi_line, d), chi_c, B, EPS, B.clone())
+    # splitting an atmosphere leaves sites whose upwind neighbours lie across the cut
+    with pytest.raises(v.VrtError) as e:
+        v.two_level_solve_batched(G, [0, off[1] // 2, U.n], *args, max_iter=2)
+    assert e.value.status == v.VRT_E_GRID
+    for bad in ([0, off[1], U.n - 1], [0, off[2], off[1], U.n], [1, U.n]):
+        with pytest.raises(v.VrtError) as e:
+            v.two_level_solve_batched(G, bad, *args, max_iter=2)
+        assert e.value.status == v.VRT_E_ARG
+    # the grid still works after the errors
+    st, its, _ = v.two_level_solve_batched(G, off, *args, max_iter=1, tol=0.0)
+    assert st == v.VRT_W_NOT_CONVERGED and np.all(its == 1)
+    G.close()

@@ -198,3 +198,30 @@ def test_lattice_neighbours():
     g2 = synth.lattice_grid(2, 2, z)
     assert synth.check_symmetric(g2)
     assert np.all(g2.degrees()[6:14] == 6)
+
+
+def test_concat_grids_is_a_disjoint_union():
+    gs = []
+    for n, seed in ((60, 3), (200, 4)):
+        atm = synth.make_atmosphere(n, seed=seed)
+        gs.append(synth.voronoi_neighbours(atm.xyz, atm.box.lo, atm.box.hi))
+    gs.append(gs[0])
+    U, off = synth.concat_grids(gs)
+    assert list(off) == [0, gs[0].n, gs[0].n + gs[1].n, U.n] and U.n == sum(g.n for g in gs)
+    assert U.m == sum(g.m for g in gs)
+    assert synth.check_symmetric(U)
+    for a, g in enumerate(gs):
+        for i in range(g.n):
+            j = off[a] + i
+            nb = U.nbr_idx[U.nbr_ptr[j] : U.nbr_ptr[j + 1]]
+            assert np.array_equal(nb, g.nbr_idx[g.nbr_ptr[i] : g.nbr_ptr[i + 1]] + off[a])
+            assert np.array_equal(U.nbr_shift[U.nbr_ptr[j] : U.nbr_ptr[j + 1]], g.nbr_shift[g.nbr_ptr[i] : g.nbr_ptr[i + 1]])
+        assert np.array_equal(U.xyz[off[a] : off[a + 1]], g.xyz) and np.array_equal(U.wall[off[a] : off[a + 1]], g.wall)
+
+
+def test_batch_sizes_are_seeded_and_in_range():
+    s = synth.batch_sizes(48, 32768, 524288, seed=1041)
+    assert s == synth.batch_sizes(48, 32768, 524288, seed=1041)
+    assert len(s) == 48 and min(s) >= 32768 and max(s) <= 524288
+    # log-uniform: about half below the geometric mean of the bounds
+    assert 14 <= sum(x < np.sqrt(32768 * 524288) for x in s) <= 34

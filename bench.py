@@ -13,6 +13,9 @@ Printed as one JSON line with, besides the headline value:
                launch time (HIP events on the library's stream), vs 8 TB/s;
   fp64_plain   the plain FP64 GPU path (one launch per ray and level) and the
                FP32-batched speed-up over it;
+  adjoint      forward and reverse-sweep times of the differentiable emergent
+               intensity (32 wavelengths 500-700 nm on the same grid) and
+               their ratio;
   cpu_baseline the FP64 CPU oracle timed on this host on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--sites N] [--no-cpu]
@@ -75,6 +78,7 @@ def main():
     ap.add_argument("--nl", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU baseline")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing")
     ap.add_argument("--mode", choices=["auto", "graph", "batched", "persistent"], default="auto",
                     help="launch mode of the timed steps (auto: the faster of graph and persistent)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -227,6 +231,50 @@ def main():
         log(f"FP64 plain step {ms64:.2f} ms; FP32 graph speed-up {ms64 / ms_step:.1f}x; FP32 J err {jerr:.2e}")
         del chi64, S64, J64
 
+    # adjoint of the LTE formal solution (same grid, 32 wavelengths 500-700 nm):
+    # forward = continuum + formal solution keeping per-ray intensities + emergent
+    # gather; backward = emergent scatter + reverse sweep + LTE chain rule
+    adjoint = None
+    if not args.no_adjoint:
+        nl4 = 32
+        lam4 = np.linspace(500e-9, 700e-9, nl4)
+        rng = np.random.Generator(np.random.PCG64(seed + 1))
+        T_tgt = torch.as_tensor(atm.T * (1.0 + 0.02 * rng.standard_normal(g.n)), device=dev)
+        with torch.no_grad():
+            target = v.lte_emergent(T_tgt, rho, G, lam4, atm.kappa0)
+        Tq = T.clone().requires_grad_(True)
+        rq = rho.clone().requires_grad_(True)
+
+        def fwd():
+            em4 = v.lte_emergent(Tq, rq, G, lam4, atm.kappa0)
+            return ((em4.double() - target.double()) ** 2).sum()
+
+        for _ in range(2):
+            fwd().backward()
+        torch.cuda.synchronize()
+        fw_ms = bw_ms = 0.0
+        k4 = 5
+        for _ in range(k4):
+            Tq.grad = rq.grad = None
+            t0 = time.perf_counter()
+            L = fwd()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            L.backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            fw_ms += (t1 - t0) * 1e3 / k4
+            bw_ms += (t2 - t1) * 1e3 / k4
+        u4 = g.n * R * nl4
+        adjoint = {"workload": f"adjoint of the LTE formal solution, {g.n} sites, {nl4} wavelengths 500-700 nm, "
+                               f"{R} rays, FP32 sweeps, FP64 ray accumulation, loss sum (I_em - I_target)^2",
+                   "forward_ms": round(fw_ms, 3), "adjoint_ms": round(bw_ms, 3),
+                   "adjoint_over_forward": round(bw_ms / fw_ms, 3),
+                   "forward_updates_per_s": u4 / (fw_ms * 1e-3), "adjoint_updates_per_s": u4 / (bw_ms * 1e-3),
+                   "grad_finite": bool(torch.isfinite(Tq.grad).all() and torch.isfinite(rq.grad).all())}
+        log(f"adjoint: forward {fw_ms:.3f} ms, backward {bw_ms:.3f} ms, ratio {bw_ms / fw_ms:.2f}")
+        del Tq, rq, target, T_tgt
+
     # CPU oracle on a bounded sample: the same formal solution (all sites, rays and
     # wavelengths), repeated until about 10 s of host time have been spent
     cpu = None
@@ -248,7 +296,8 @@ def main():
         log(f"CPU oracle {cpu['value']:.3e} updates/s on {cpu['cores']} threads ({dt:.1f} s)")
 
     out = {
-        "metric": "site*ray*lambda updates/s, FP32 batched formal solution (vs FP64 plain) + %HBM roofline",
+        "metric": "site*ray*lambda updates/s, FP32 batched formal solution (vs FP64 plain) + %HBM roofline; "
+                  "adjoint/fwd",
         "value": value,
         "unit": "site*ray*lambda updates/s",
         "n_gpus": 1,
@@ -275,6 +324,7 @@ def main():
                      "sweep_ms_per_step": round(sweep_ms, 4), "j_quadrature_ms": round(jr_one, 4)},
         "whole_step_effective_GBs": round(updates * (20.0 + 20.0 / nl) / (ms_step * 1e-3) / 1e9, 1),
         "fp64_plain": fp64,
+        "adjoint": adjoint,
         "cpu_baseline": cpu,
         "setup_s": round(setup_s, 3),
         "tuning": tuning,

@@ -97,6 +97,8 @@ vrt_status vrt_validate_voronoi(int64_t n, const double *xyz, const int64_t *nbr
 /* Create a context on HIP device `device`, enqueuing on `stream` (a
  * hipStream_t; NULL = the device's null stream). */
 vrt_status vrt_ctx_create(int32_t device, void *stream, vrt_ctx *out);
+/* Destroys the context and every grid still alive on it (their handles
+ * become invalid). */
 void vrt_ctx_destroy(vrt_ctx ctx);
 const char *vrt_ctx_last_error(vrt_ctx ctx);
 /* Switch the stream later calls enqueue on (drops captured graphs). */
@@ -141,6 +143,8 @@ vrt_status vrt_grid_create_voronoi(vrt_ctx ctx, int64_t n, const double *xyz,
 vrt_status vrt_grid_create_regular(vrt_ctx ctx, int32_t nx, int32_t ny, int32_t nz, double dx,
                                    double dy, const double *z, vrt_grid *out);
 
+/* Drains the context stream and frees the grid. Must not be called after its
+ * context was destroyed (that already freed it). */
 void vrt_grid_destroy(vrt_grid grid);
 
 /* Set the angle quadrature (Sect. 2.5: a fixed quadrature of directions).
@@ -169,6 +173,19 @@ vrt_status vrt_grid_set_rays(vrt_grid grid, int32_t n_rays, const double *dir, c
  * Returns VRT_E_ARG for an unknown knob or value. Drops captured graphs. */
 #define VRT_TUNE_RECORD_ORDER 1
 #define VRT_TUNE_XCD_CHUNKS 2
+/*   VRT_TUNE_RAY_AFFINITY   1 = every ray's records run on one die for the
+ *                           whole sweep (rays dealt to the 8 dies in
+ *                           serpentine order of their level counts), so a
+ *                           level reads the rows its predecessor wrote through
+ *                           the same L2; overrides VRT_TUNE_XCD_CHUNKS in
+ *                           batched and graph sweeps [0]. */
+#define VRT_TUNE_RAY_AFFINITY 5
+/*   VRT_TUNE_CHAINS         1..8: split the rays of a batched or graph sweep
+ *                           into this many contiguous ranges, each swept on a
+ *                           stream of its own (forked from and joined to the
+ *                           context stream), so the launch latency of one
+ *                           range overlaps the work of the others [1]. */
+#define VRT_TUNE_CHAINS 6
 /*   VRT_TUNE_SPIN_CAP       bound on the polls of one wait in the persistent
  *                           sweep [2^22]; a wait that exceeds it gives up.
  *   VRT_TUNE_PERSIST_BLOCKS cap on the persistent sweep's workgroups
@@ -177,8 +194,8 @@ vrt_status vrt_grid_set_rays(vrt_grid grid, int32_t n_rays, const double *dir, c
 #define VRT_TUNE_PERSIST_BLOCKS 4
 vrt_status vrt_grid_tune(vrt_grid grid, int32_t knob, int64_t value);
 
-/* Autotuner: times every combination of the knobs above (record order x
- * {0, 8} XCD chunks) on a formal solution with the given arguments (as for
+/* Autotuner: times launch layouts (record order x a fixed list of {die
+ * chunks, ray affinity, chains} settings) on a formal solution with the given arguments (as for
  * vrt_formal_solution with VRT_EXEC_GRAPH), `reps` replays each after one
  * warm-up, keeps the fastest setting on the grid and writes a one-line JSON
  * report (host, may be NULL) of every candidate's mean time in ms. Re-packs

@@ -48,6 +48,25 @@ __device__ __forceinline__ int64_t chunked_block(int32_t k) {
   return x * per + (x < rem ? x : rem) + j;
 }
 
+// Ray affinity: each ray is assigned to one die for the whole sweep, so the
+// rows a level writes are read by the next level through the same die's L2.
+// The launch of one step passes that step's table xtab[die][k] = {first
+// record, running record count} over the k < xk segments of the die's rays;
+// block b works for die b mod 8. Returns the record of this lane, or -1.
+__device__ __forceinline__ int64_t affinity_record(const int64_t *__restrict__ xtab, int32_t xk, int spw, int lane,
+                                                   int c) {
+  const int x = blockIdx.x & (vrt::kDies - 1);
+  const int64_t j = ((int64_t)(blockIdx.x / vrt::kDies) * (blockDim.x >> 6) + (threadIdx.x >> 6)) * spw + lane / c;
+  const int64_t *t = xtab + (int64_t)x * xk * 2;
+  int64_t prev = 0;
+  for (int32_t k = 0; k < xk; ++k) {
+    const int64_t cum = t[2 * k + 1];
+    if (j < cum) return t[2 * k] + (j - prev);
+    prev = cum;
+  }
+  return -1;
+}
+
 // C lanes per record, V consecutive wavelengths per lane (nl is a multiple of V).
 template <typename T, int C, int V>
 __global__ __launch_bounds__(256) void sweep_kernel(const int4 *__restrict__ ri,
@@ -55,16 +74,24 @@ __global__ __launch_bounds__(256) void sweep_kernel(const int4 *__restrict__ ri,
                                                     int64_t rec_begin, int64_t rec_count, int32_t nl, int64_t n,
                                                     const T *__restrict__ chi, const T *__restrict__ S,
                                                     const T *__restrict__ Ibot, const T *__restrict__ Itop, T *I,
-                                                    int32_t xcd_chunks, int32_t ray0) {
+                                                    int32_t xcd_chunks, int32_t ray0,
+                                                    const int64_t *__restrict__ xtab, int32_t xk) {
   using L = Lane<T, V>;
   using VT = typename L::type;
   constexpr int SPW = 64 / C;
   const int lane = threadIdx.x & 63;
-  const int64_t wave = chunked_block(xcd_chunks) * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int64_t rec = wave * SPW + lane / C;
   const int l0 = (lane % C) * V;
-  if (rec >= rec_count) return;
-  const int4 q = ri[rec_begin + rec];
+  int64_t rec;
+  if (xtab) {
+    rec = affinity_record(xtab, xk, SPW, lane, C);
+    if (rec < 0) return;
+  } else {
+    const int64_t wave = chunked_block(xcd_chunks) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t r = wave * SPW + lane / C;
+    if (r >= rec_count) return;
+    rec = rec_begin + r;
+  }
+  const int4 q = ri[rec];
   const int32_t site = q.x, k1 = q.y, k2 = q.z;
   const int32_t ray = q.w >> 1;
   const bool up = (q.w & 1) != 0;
@@ -80,7 +107,7 @@ __global__ __launch_bounds__(256) void sweep_kernel(const int4 *__restrict__ ri,
     }
     return;
   }
-  const auto f = rf[rec_begin + rec];
+  const auto f = rf[rec];
   const T w1 = f.w1, w2 = T(1) - f.w1;
   const T h1 = T(0.5) * f.ds1, h2 = T(0.5) * f.ds2;
   const bool two = k2 >= 0;
@@ -147,28 +174,32 @@ __global__ void emergent_kernel(int64_t total, int32_t nl, int64_t n, const int3
   out[t] = I[((int64_t)em_ray[e] * n + em_site[e]) * nl + l];
 }
 
+// With a ray-affinity table, c is the largest record count of one die and the
+// grid holds that many records for every die.
 template <typename T, int C, int V>
 void launch_c(hipStream_t s, const int4 *ri, const typename vrt::RecOf<T>::type *rf, int64_t b, int64_t c, int32_t nl,
-              int64_t n, const T *chi, const T *S, const T *Ibot, const T *Itop, T *I, int32_t xc, int32_t ray0) {
+              int64_t n, const T *chi, const T *S, const T *Ibot, const T *Itop, T *I, int32_t xc, int32_t ray0,
+              const int64_t *xtab, int32_t xk) {
   constexpr int SPW = 64 / C;
   const int64_t waves = (c + SPW - 1) / SPW;
-  const int64_t blocks = (waves + 3) / 4;
+  const int64_t blocks = xtab ? (int64_t)vrt::kDies * ((waves + 3) / 4) : (waves + 3) / 4;
   hipLaunchKernelGGL((sweep_kernel<T, C, V>), dim3((unsigned)blocks), dim3(256), 0, s, ri, rf, b, c, nl, n, chi, S,
-                     Ibot, Itop, I, xc, ray0);
+                     Ibot, Itop, I, xc, ray0, xtab, xk);
 }
 
 // lanes per record for m lane-vectors per row: the smallest power of two >= m, at most 64
 template <typename T, int V>
 void launch_v(hipStream_t s, const int4 *ri, const typename vrt::RecOf<T>::type *rf, int64_t b, int64_t c, int32_t nl,
-              int64_t n, const T *chi, const T *S, const T *Ibot, const T *Itop, T *I, int32_t xc, int32_t ray0) {
+              int64_t n, const T *chi, const T *S, const T *Ibot, const T *Itop, T *I, int32_t xc, int32_t ray0,
+              const int64_t *xtab, int32_t xk) {
   const int32_t m = nl / V;
-  if (m >= 33) launch_c<T, 64, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0);
-  else if (m >= 17) launch_c<T, 32, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0);
-  else if (m >= 9) launch_c<T, 16, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0);
-  else if (m >= 5) launch_c<T, 8, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0);
-  else if (m >= 3) launch_c<T, 4, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0);
-  else if (m == 2) launch_c<T, 2, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0);
-  else launch_c<T, 1, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0);
+  if (m >= 33) launch_c<T, 64, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk);
+  else if (m >= 17) launch_c<T, 32, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk);
+  else if (m >= 9) launch_c<T, 16, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk);
+  else if (m >= 5) launch_c<T, 8, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk);
+  else if (m >= 3) launch_c<T, 4, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk);
+  else if (m == 2) launch_c<T, 2, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk);
+  else launch_c<T, 1, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk);
 }
 
 // 16-byte lane vectors when the row length allows (and rows then stay 16-byte aligned)
@@ -183,13 +214,13 @@ namespace vrt {
 template <typename T>
 void launch_sweep(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *rf, int64_t rec_begin,
                   int64_t rec_count, int32_t nl, int64_t n, const T *chi, const T *S, const T *Ibot, const T *Itop,
-                  T *I, int32_t xcd_chunks, int32_t ray0) {
+                  T *I, int32_t xcd_chunks, int32_t ray0, const int64_t *xtab, int32_t xk) {
   if (rec_count <= 0) return;
   const bool aligned = aligned16(chi) && aligned16(S) && aligned16(Ibot) && aligned16(Itop) && aligned16(I);
   if (aligned && nl % kVec<T> == 0)
-    launch_v<T, kVec<T>>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I, xcd_chunks, ray0);
+    launch_v<T, kVec<T>>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I, xcd_chunks, ray0, xtab, xk);
   else
-    launch_v<T, 1>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I, xcd_chunks, ray0);
+    launch_v<T, 1>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I, xcd_chunks, ray0, xtab, xk);
   VRT_HIP(hipGetLastError());
 }
 
@@ -219,10 +250,10 @@ void launch_emergent(hipStream_t s, int64_t total, int32_t nl, int64_t n, const 
 
 template void launch_sweep<float>(hipStream_t, const int4 *, const RecF32 *, int64_t, int64_t, int32_t, int64_t,
                                   const float *, const float *, const float *, const float *, float *, int32_t,
-                                  int32_t);
+                                  int32_t, const int64_t *, int32_t);
 template void launch_sweep<double>(hipStream_t, const int4 *, const RecF64 *, int64_t, int64_t, int32_t, int64_t,
                                    const double *, const double *, const double *, const double *, double *, int32_t,
-                                   int32_t);
+                                   int32_t, const int64_t *, int32_t);
 template void launch_jreduce<float>(hipStream_t, const float *, int32_t, int64_t, const double *, float *);
 template void launch_jreduce<double>(hipStream_t, const double *, int32_t, int64_t, const double *, double *);
 template void launch_emergent<float>(hipStream_t, int64_t, int32_t, int64_t, const int32_t *, const int32_t *,

@@ -168,6 +168,50 @@ void build_emergent_index(vrt_grid g) {
   VRT_HIP(hipStreamSynchronize(g->ctx->stream));
 }
 
+// Ray-affinity tables: rays sorted by their number of levels (most first, then
+// index) are dealt to the dies in serpentine order, so every die gets a mix of
+// long and short sweeps; per step, each die's records are the (level, ray)
+// segments of its rays.
+void build_affinity(vrt_grid g) {
+  const int32_t R = g->R, NS = g->n_steps, D = vrt::kDies;
+  std::vector<int32_t> by((size_t)R);
+  for (int32_t r = 0; r < R; ++r) by[(size_t)r] = r;
+  std::stable_sort(by.begin(), by.end(),
+                   [&](int32_t a, int32_t b) { return g->n_levels[(size_t)a] > g->n_levels[(size_t)b]; });
+  g->ray_die.assign((size_t)R, 0);
+  std::vector<std::vector<int32_t>> rays_of((size_t)D);
+  for (int32_t p = 0; p < R; ++p) {
+    const int32_t round = p / D, pos = p % D;
+    const int32_t die = (round % 2 == 0) ? pos : D - 1 - pos;
+    g->ray_die[(size_t)by[(size_t)p]] = die;
+  }
+  for (int32_t r = 0; r < R; ++r) rays_of[(size_t)g->ray_die[(size_t)r]].push_back(r);
+  int32_t xk = 1;
+  for (const auto &v : rays_of) xk = std::max<int32_t>(xk, (int32_t)v.size());
+  g->xk = xk;
+  std::vector<int64_t> tab((size_t)std::max(NS, 1) * D * xk * 2, 0);
+  g->xmax.assign((size_t)NS, 0);
+  for (int32_t st = 0; st < NS; ++st) {
+    for (int32_t x = 0; x < D; ++x) {
+      int64_t *t = tab.data() + ((size_t)st * D + x) * xk * 2;
+      int64_t cum = 0;
+      const auto &v = rays_of[(size_t)x];
+      for (int32_t k = 0; k < xk; ++k) {
+        if (k < (int32_t)v.size()) {
+          const int32_t r = v[(size_t)k];
+          t[2 * k] = g->seg_off[(size_t)st * R + r];
+          cum += g->seg_cnt[(size_t)st * R + r];
+        }
+        t[2 * k + 1] = cum;  // unused slots repeat the total
+      }
+      g->xmax[(size_t)st] = std::max(g->xmax[(size_t)st], cum);
+    }
+  }
+  upload(g->d_xtab, tab.data(), tab.size(), g->ctx->stream);
+  VRT_HIP(hipStreamSynchronize(g->ctx->stream));  // the host table is local
+}
+
+
 void set_rays_voronoi(vrt_grid g) {
   hipStream_t s = g->ctx->stream;
   const int64_t n = g->n;
@@ -304,6 +348,7 @@ void set_rays_voronoi(vrt_grid g) {
   }
   g->step_ptr[(size_t)NS] = acc;
   g->n_rec = acc;
+  build_affinity(g);
   DevBuf d_seg;
   upload(d_seg, g->seg_off.data(), g->seg_off.size(), s);
   g->d_ri.alloc((size_t)RN * sizeof(int4));
@@ -344,6 +389,15 @@ template <typename F> void timed_launch(vrt_ctx ctx, hipStream_t s, bool timed, 
 
 // Wave items of the persistent sweep for `spw` records per wave: every level
 // step is cut separately, so no item holds two levels of one ray.
+// per-(ray, site) epoch stamps and the epoch / device-error words
+void ensure_flags(vrt_grid g) {
+  if (g->d_flags.p) return;
+  g->d_flags.alloc((size_t)g->R * (size_t)g->n * 4);
+  VRT_HIP(hipMemsetAsync(g->d_flags.p, 0, (size_t)g->R * (size_t)g->n * 4, g->ctx->stream));
+  g->d_epoch.alloc(16);
+  VRT_HIP(hipMemsetAsync(g->d_epoch.p, 0, 16, g->ctx->stream));
+}
+
 const vrt::PersistItems &persistent_items(vrt_grid g, int32_t spw) {
   auto it = g->persist_items.find(spw);
   if (it != g->persist_items.end()) return *it->second;
@@ -361,12 +415,7 @@ const vrt::PersistItems &persistent_items(vrt_grid g, int32_t spw) {
   p->n_items = (int64_t)rec.size();
   upload(p->rec, rec.data(), rec.size(), g->ctx->stream);
   upload(p->cnt, cnt.data(), cnt.size(), g->ctx->stream);
-  if (!g->d_flags.p) {
-    g->d_flags.alloc((size_t)g->R * (size_t)g->n * 4);
-    VRT_HIP(hipMemsetAsync(g->d_flags.p, 0, (size_t)g->R * (size_t)g->n * 4, g->ctx->stream));
-    g->d_epoch.alloc(16);
-    VRT_HIP(hipMemsetAsync(g->d_epoch.p, 0, 16, g->ctx->stream));
-  }
+  ensure_flags(g);
   VRT_HIP(hipStreamSynchronize(g->ctx->stream));  // host tables are local
   auto &ref = *p;
   g->persist_items.emplace(spw, std::move(p));
@@ -403,6 +452,40 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
       for (int32_t r = 0; r < R; ++r)
         for (int32_t st = 0; st < g->n_levels[(size_t)r]; ++st)
           sweep(g->seg_off[(size_t)st * R + r], g->seg_cnt[(size_t)st * R + r]);
+    } else if (g->ray_affinity) {
+      const int64_t *xt = g->d_xtab.as<int64_t>();
+      const size_t per = (size_t)vrt::kDies * g->xk * 2;
+      for (int32_t st = 0; st < g->n_steps; ++st) {
+        const int64_t c = g->xmax[(size_t)st];
+        if (c <= 0) continue;
+        const int64_t units = (g->step_ptr[(size_t)st + 1] - g->step_ptr[(size_t)st]) * nl;
+        timed_launch(ctx, s, tm, 0, units, [&] {
+          vrt::launch_sweep<T>(s, ri, rf, 0, c, nl, n, chi, S, Ib, It, I, 0, 0, xt + per * st, g->xk);
+        });
+      }
+    } else if (g->chains > 1 && R > 1) {
+      // rays never read each other's intensities: split them into K contiguous
+      // ranges, each swept level by level on a stream of its own, so one
+      // chain's launch latency overlaps the other chains' work
+      const int32_t K = std::min<int32_t>(g->chains, R);
+      ctx->ensure_aux(K - 1);
+      VRT_HIP(hipEventRecord(ctx->fork_ev, s));
+      for (int32_t c = 1; c < K; ++c) VRT_HIP(hipStreamWaitEvent(ctx->aux[(size_t)c - 1], ctx->fork_ev, 0));
+      for (int32_t st = 0; st < g->n_steps; ++st) {
+        for (int32_t c = 0; c < K; ++c) {
+          const int32_t r0 = (int32_t)((int64_t)c * R / K), r1 = (int32_t)((int64_t)(c + 1) * R / K);
+          const int64_t b = g->seg_off[(size_t)st * R + r0];
+          const int64_t e = g->seg_off[(size_t)st * R + r1 - 1] + g->seg_cnt[(size_t)st * R + r1 - 1];
+          if (e <= b) continue;
+          hipStream_t sc = c == 0 ? s : ctx->aux[(size_t)c - 1];
+          timed_launch(ctx, sc, tm, 0, (e - b) * nl,
+                       [&] { vrt::launch_sweep<T>(sc, ri, rf, b, e - b, nl, n, chi, S, Ib, It, I, xc, 0); });
+        }
+      }
+      for (int32_t c = 1; c < K; ++c) {
+        VRT_HIP(hipEventRecord(ctx->join_ev[(size_t)c - 1], ctx->aux[(size_t)c - 1]));
+        VRT_HIP(hipStreamWaitEvent(s, ctx->join_ev[(size_t)c - 1], 0));
+      }
     } else {
       for (int32_t st = 0; st < g->n_steps; ++st)
         sweep(g->step_ptr[(size_t)st], g->step_ptr[(size_t)st + 1] - g->step_ptr[(size_t)st]);
@@ -745,7 +828,29 @@ void formal_solution(vrt_grid g, vrt_exec ex, int32_t nl, const void *chi_, cons
 
 bool valid_prec(vrt_prec p) { return p == VRT_F64 || p == VRT_F32; }
 
+// frees a grid whose context is still alive (the context's stream is drained first)
+void free_grid(vrt_grid g) {
+  (void)hipSetDevice(g->ctx->device);
+  (void)hipStreamSynchronize(g->ctx->stream);
+  g->drop_graphs();
+  if (g->h_dS) (void)hipHostFree(g->h_dS);
+  if (g->h_active) (void)hipHostFree(g->h_active);
+  delete g;
+}
+
 }  // namespace
+
+void vrt_ctx_s::ensure_aux(int k) {
+  if (!fork_ev) VRT_HIP(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
+  while ((int)aux.size() < k) {
+    hipStream_t a = nullptr;
+    VRT_HIP(hipStreamCreateWithFlags(&a, hipStreamNonBlocking));
+    aux.push_back(a);
+    hipEvent_t e = nullptr;
+    VRT_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    join_ev.push_back(e);
+  }
+}
 
 void vrt_ctx_s::drain_profile() {
   for (auto &t : pending) {
@@ -824,12 +929,17 @@ vrt_status vrt_ctx_create(int32_t device, void *stream, vrt_ctx *out) {
 
 void vrt_ctx_destroy(vrt_ctx ctx) {
   if (!ctx) return;
+  for (vrt_grid g : ctx->grids) free_grid(g);
+  ctx->grids.clear();
   (void)hipSetDevice(ctx->device);
   try {
     ctx->drain_profile();
   } catch (...) {
   }
   if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+  for (hipStream_t a : ctx->aux) (void)hipStreamDestroy(a);
+  for (hipEvent_t e : ctx->join_ev) (void)hipEventDestroy(e);
+  if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
   delete ctx;
 }
 
@@ -918,6 +1028,7 @@ vrt_status vrt_grid_create_voronoi(vrt_ctx ctx, int64_t n, const double *xyz, co
     g->h_wall.assign(wall, wall + n);
     g->h_xyz.assign(xyz, xyz + 3 * n);
     VRT_HIP(hipStreamSynchronize(s));
+    ctx->grids.insert(g.get());
     *out = g.release();
     return VRT_OK;
   });
@@ -944,6 +1055,7 @@ vrt_status vrt_grid_create_regular(vrt_ctx ctx, int32_t nx, int32_t ny, int32_t 
     g->h_z.assign(z, z + nz);
     upload(g->d_z, z, (size_t)nz, ctx->stream);
     VRT_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->grids.insert(g.get());
     *out = g.release();
     return VRT_OK;
   });
@@ -951,12 +1063,8 @@ vrt_status vrt_grid_create_regular(vrt_ctx ctx, int32_t nx, int32_t ny, int32_t 
 
 void vrt_grid_destroy(vrt_grid g) {
   if (!g) return;
-  (void)hipSetDevice(g->ctx->device);
-  (void)hipStreamSynchronize(g->ctx->stream);
-  g->drop_graphs();
-  if (g->h_dS) (void)hipHostFree(g->h_dS);
-  if (g->h_active) (void)hipHostFree(g->h_active);
-  delete g;
+  g->ctx->grids.erase(g);
+  free_grid(g);
 }
 
 vrt_status vrt_grid_set_rays(vrt_grid g, int32_t n_rays, const double *dir, const double *w, double r_exp) {
@@ -1006,6 +1114,12 @@ vrt_status vrt_grid_tune(vrt_grid g, int32_t knob, int64_t value) {
     } else if (knob == VRT_TUNE_XCD_CHUNKS) {
       if (value < 0 || value > 64) fail(VRT_E_ARG, "XCD chunk count must be in 0..64");
       g->xcd_chunks = (int)value;
+    } else if (knob == VRT_TUNE_RAY_AFFINITY) {
+      if (value != 0 && value != 1) fail(VRT_E_ARG, "ray affinity must be 0 or 1");
+      g->ray_affinity = (int)value;
+    } else if (knob == VRT_TUNE_CHAINS) {
+      if (value < 1 || value > 8) fail(VRT_E_ARG, "chain count must be in 1..8");
+      g->chains = (int)value;
     } else if (knob == VRT_TUNE_SPIN_CAP) {
       if (value < 0) fail(VRT_E_ARG, "spin cap must be non-negative");
       g->spin_cap = value;
@@ -1034,7 +1148,10 @@ vrt_status vrt_grid_autotune(vrt_grid g, vrt_prec prec, int32_t n_lambda, const 
     VRT_HIP(hipEventCreate(&e1));
     std::string rep = "{\"candidates\": [";
     double best = 1e300;
-    int best_order = g->record_order, best_xcd = g->xcd_chunks;
+    int best_order = g->record_order, best_xcd = g->xcd_chunks, best_aff = g->ray_affinity, best_ch = g->chains;
+    // (die chunks, ray affinity, chains) per record order; split chains are
+    // not candidates: kernels on separate queues were measured not to overlap
+    static const int cands[][3] = {{0, 0, 1}, {8, 0, 1}, {0, 1, 1}};
     bool first = true;
     for (int order = 0; order <= 1; ++order) {
       if (order != g->record_order || first) {
@@ -1042,8 +1159,11 @@ vrt_status vrt_grid_autotune(vrt_grid g, vrt_prec prec, int32_t n_lambda, const 
         g->drop_graphs();
         set_rays_voronoi(g);
       }
-      for (int xcd : {0, 8}) {
+      for (const auto &cd : cands) {
+        const int xcd = cd[0], aff = cd[1], ch = cd[2];
         g->xcd_chunks = xcd;
+        g->ray_affinity = aff;
+        g->chains = ch;
         g->drop_graphs();
         auto run = [&] {
           if (prec == VRT_F32)
@@ -1060,14 +1180,17 @@ vrt_status vrt_grid_autotune(vrt_grid g, vrt_prec prec, int32_t n_lambda, const 
         VRT_HIP(hipEventElapsedTime(&ms, e0, e1));
         const double mean = ms / reps;
         char buf[128];
-        snprintf(buf, sizeof buf, "%s{\"record_order\": %d, \"xcd_chunks\": %d, \"ms\": %.5f}", first ? "" : ", ",
-                 order, xcd, mean);
+        snprintf(buf, sizeof buf,
+                 "%s{\"record_order\": %d, \"xcd_chunks\": %d, \"ray_affinity\": %d, \"chains\": %d, \"ms\": %.5f}",
+                 first ? "" : ", ", order, xcd, aff, ch, mean);
         rep += buf;
         first = false;
         if (mean < best) {
           best = mean;
           best_order = order;
           best_xcd = xcd;
+          best_aff = aff;
+          best_ch = ch;
         }
       }
     }
@@ -1078,10 +1201,14 @@ vrt_status vrt_grid_autotune(vrt_grid g, vrt_prec prec, int32_t n_lambda, const 
       set_rays_voronoi(g);
     }
     g->xcd_chunks = best_xcd;
+    g->ray_affinity = best_aff;
+    g->chains = best_ch;
     g->drop_graphs();
-    char buf[160];
-    snprintf(buf, sizeof buf, "], \"chosen\": {\"record_order\": %d, \"xcd_chunks\": %d, \"ms\": %.5f}}", best_order,
-             best_xcd, best);
+    char buf[240];
+    snprintf(buf, sizeof buf,
+             "], \"chosen\": {\"record_order\": %d, \"xcd_chunks\": %d, \"ray_affinity\": %d, \"chains\": %d, "
+             "\"ms\": %.5f}}",
+             best_order, best_xcd, best_aff, best_ch, best);
     rep += buf;
     if (report && report_len > 0) snprintf(report, (size_t)report_len, "%s", rep.c_str());
     return VRT_OK;

@@ -7,6 +7,7 @@
 
 #include <cstdint>
 #include <map>
+#include <set>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -71,6 +72,9 @@ struct DevBuf {
   template <typename T> T *as() const { return static_cast<T *>(p); }
 };
 
+// accelerator dies (XCDs) of the GPU; workgroups are dealt to them round-robin
+constexpr int kDies = 8;
+
 // lanes per record for m lane-vectors per row: the smallest power of two >= m, at most 64
 inline int lanes_per_record(int32_t m) {
   if (m >= 33) return 64;
@@ -89,6 +93,8 @@ struct PersistItems {
   int64_t n_items = 0;
   DevBuf rec, cnt;
 };
+
+
 
 }  // namespace vrt
 
@@ -110,6 +116,17 @@ struct vrt_ctx_s {
   int64_t prof_launches[3] = {0, 0, 0};
   int64_t prof_units[3] = {0, 0, 0};
   void drain_profile();
+
+  // auxiliary streams (default priority) for sweeps split into independent
+  // chains of rays, with the events that fork them from and join them to
+  // the context stream
+  std::vector<hipStream_t> aux;
+  hipEvent_t fork_ev = nullptr;
+  std::vector<hipEvent_t> join_ev;
+  void ensure_aux(int k);
+
+  // live grids of this context, destroyed with it
+  std::set<vrt_grid_s *> grids;
 };
 
 struct vrt_grid_s {
@@ -163,6 +180,15 @@ struct vrt_grid_s {
   // tuning knobs
   int record_order = 1;  // 0 site index, 1 Morton (x, y) within a level
   int xcd_chunks = 8;    // 0 = plain block order
+  int ray_affinity = 0;  // 1: each ray's records always run on the same die
+  int chains = 1;        // independent launch chains (streams) a sweep is split into
+
+  // ray-affinity tables: ray_die[r], and per step [kDies][xk][2] = {first
+  // record, running count} over the segments of each die's rays
+  std::vector<int32_t> ray_die;
+  int32_t xk = 0;
+  std::vector<int64_t> xmax;  // [n_steps]: largest record count of one die
+  vrt::DevBuf d_xtab;
 
   // scratch for per-ray intensities when the caller passes none
   vrt::DevBuf d_Iscr;
@@ -227,11 +253,14 @@ void launch_pack(hipStream_t s, int64_t n, int32_t R, int32_t Lmax, const int32_
                  const double *ds2, const double *dirs, int4 *ri, RecF32 *rf32, RecF64 *rf64);
 
 // ---- k_sweep.hip
-// I holds the rays from ray0 on (ray r writes I + (r - ray0) * n * nl)
+// I holds the rays from ray0 on (ray r writes I + (r - ray0) * n * nl). With
+// xtab (one step's ray-affinity table [kDies][xk][2]), rec_count is the
+// largest record count of one die and rec_begin is unused.
 template <typename T>
 void launch_sweep(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *rf, int64_t rec_begin,
                   int64_t rec_count, int32_t nl, int64_t n, const T *chi, const T *S, const T *Ibot,
-                  const T *Itop, T *I, int32_t xcd_chunks, int32_t ray0);
+                  const T *Itop, T *I, int32_t xcd_chunks, int32_t ray0, const int64_t *xtab = nullptr,
+                  int32_t xk = 0);
 template <typename T>
 void launch_jreduce(hipStream_t s, const T *I, int32_t R, int64_t nn, const double *w, T *J);
 template <typename T>

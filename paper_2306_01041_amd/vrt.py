@@ -38,6 +38,8 @@ VRT_TUNE_RECORD_ORDER = 1
 VRT_TUNE_XCD_CHUNKS = 2
 VRT_TUNE_SPIN_CAP = 3
 VRT_TUNE_PERSIST_BLOCKS = 4
+VRT_TUNE_RAY_AFFINITY = 5
+VRT_TUNE_CHAINS = 6
 
 VRT_F64 = 0
 VRT_F32 = 1
@@ -285,9 +287,10 @@ class Grid:
         return off, sites
 
     def close(self):
-        if self.handle:
+        # a destroyed context has already freed its grids
+        if self.handle and self.ctx.handle:
             vrt_grid_destroy(self.handle)
-            self.handle = None
+        self.handle = None
 
     def __del__(self):
         try:

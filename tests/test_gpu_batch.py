@@ -82,7 +82,7 @@ def _solve_batched(v, ctx, b, dt, mode):
     return st, its, hist, S.cpu().numpy()
 
 
-@pytest.mark.parametrize("mode", ["GRAPH", "BATCHED"])
+@pytest.mark.parametrize("mode", ["GRAPH", "BATCHED", "PERSISTENT"])
 def test_batch_matches_standalone_oracle(v, ctx, batch, mode):
     flush(f"batch f64 {mode} sizes={SIZES}")
     st, its, hist, S = _solve_batched(v, ctx, batch, torch.float64, mode)

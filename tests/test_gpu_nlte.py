@@ -60,7 +60,8 @@ def _gpu_inputs(v, ctx, case):
 
 
 @pytest.mark.parametrize("eps", [1e-2, 1e-4])
-@pytest.mark.parametrize("prec,mode", [("f64", "PLAIN"), ("f64", "GRAPH"), ("f32", "GRAPH"), ("f32", "BATCHED")])
+@pytest.mark.parametrize("prec,mode", [("f64", "PLAIN"), ("f64", "GRAPH"), ("f32", "GRAPH"), ("f32", "BATCHED"),
+                                       ("f32", "PERSISTENT")])
 def test_iterates_match_oracle(v, ctx, case, eps, prec, mode):
     flush(f"nlte eps={eps} prec={prec} mode={mode}")
     G, chi_c, B = _gpu_inputs(v, ctx, case)

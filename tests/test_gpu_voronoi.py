@@ -172,13 +172,16 @@ def test_fp32_batched_matches_fp64_oracle(v, ctx, quad, grids, nl):
     G.close()
 
 
-def test_graph_replays_match_eager(v, ctx, quad, grids):
-    """A captured launch sequence replayed several times, with eager work and
-    synchronisations between replays, reproduces the eager result bit for bit."""
-    flush("graph replay")
+@pytest.mark.parametrize("chains", [1, 3])
+def test_graph_replays_match_eager(v, ctx, quad, grids, chains):
+    """A captured launch sequence (with forked streams when the rays are split
+    into chains) replayed several times, with eager work and synchronisations
+    between replays, reproduces the eager result bit for bit."""
+    flush(f"graph replay chains={chains}")
     atm, g = grids[16384]
     dirs, w = quad
     G = _gpu_grid(v, ctx, g, dirs, w)
+    G.tune(v.VRT_TUNE_CHAINS, chains)
     chi_o, S_o = _fields(atm, 8, 3)
     f = torch.float32
     chi, S = to_dev(chi_o, f), to_dev(S_o, f)
@@ -269,10 +272,12 @@ def test_tuning_knobs_do_not_change_results(v, ctx, quad, grids):
     chi, S = to_dev(chi_o, f), to_dev(S_o, f)
     ref = None
     for order in (0, 1):
-        for xcd in (0, 3, 8):
+        for xcd, aff, ch in ((0, 0, 1), (3, 0, 1), (8, 0, 1), (8, 1, 1), (8, 0, 2), (0, 0, 3), (8, 0, 5)):
             G = v.Grid.from_synth(ctx, g)
             G.tune(v.VRT_TUNE_RECORD_ORDER, order)
             G.tune(v.VRT_TUNE_XCD_CHUNKS, xcd)
+            G.tune(v.VRT_TUNE_RAY_AFFINITY, aff)
+            G.tune(v.VRT_TUNE_CHAINS, ch)
             G.set_rays(dirs, w)
             J = torch.empty_like(chi)
             v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_GRAPH)
@@ -280,12 +285,12 @@ def test_tuning_knobs_do_not_change_results(v, ctx, quad, grids):
             out = J.cpu().numpy()
             if ref is None:
                 ref = out
-            assert np.array_equal(out, ref), (order, xcd)
+            assert np.array_equal(out, ref), (order, xcd, aff, ch)
             G.close()
     G = _gpu_grid(v, ctx, g, dirs, w)
     J = torch.empty_like(chi)
     rep = v.autotune(G, chi, S, J, reps=2)
-    assert len(rep["candidates"]) == 4
+    assert len(rep["candidates"]) == 6
     assert rep["chosen"]["ms"] == min(c["ms"] for c in rep["candidates"])
     v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_GRAPH)
     torch.cuda.synchronize()
@@ -344,3 +349,45 @@ def test_persistent_bounded_wait_reports_timeout(v, ctx, quad, grids):
     G.device_status()
     assert np.array_equal(J.cpu().numpy(), Jg.cpu().numpy())
     G.close()
+
+
+@pytest.mark.parametrize("n_mu,n_phi", [(1, 3), (2, 5)])
+def test_ray_affinity_and_chains_with_uneven_rays(v, ctx, grids, n_mu, n_phi):
+    """6 and 20 rays leave dies with different numbers of rays (or none) and
+    chains with different numbers of rays: the affinity tables and the chain
+    ranges must still cover every record once; the intensities of every ray
+    equal those of the plain block order bit for bit."""
+    flush(f"ray affinity n_mu={n_mu} n_phi={n_phi}")
+    atm, g = grids[16384]
+    dirs, w = synth.gauss_legendre_quadrature(n_mu=n_mu, n_phi=n_phi)
+    chi_o, S_o = _fields(atm, 8, 3)
+    f = torch.float32
+    chi, S = to_dev(chi_o, f), to_dev(S_o, f)
+    outs = []
+    for aff, ch, mode in ((0, 1, "BATCHED"), (1, 1, "BATCHED"), (0, 4, "BATCHED"), (0, 1, "PERSISTENT")):
+        G = v.Grid.from_synth(ctx, g)
+        G.tune(v.VRT_TUNE_RAY_AFFINITY, aff)
+        G.tune(v.VRT_TUNE_CHAINS, ch)
+        G.set_rays(dirs, w)
+        J = torch.empty_like(chi)
+        I = torch.full((len(dirs), g.n, 8), float("nan"), dtype=f, device="cuda:0")
+        v.formal_solution(G, chi, S, J, I_rays=I, exec_mode=getattr(v, "VRT_EXEC_" + mode))
+        G.device_status()
+        outs.append(I.cpu().numpy())
+        G.close()
+    for o in outs[1:]:
+        assert np.all(np.isfinite(o))
+        assert np.array_equal(outs[0], o)
+
+
+def test_grid_outliving_its_context(v, quad, grids):
+    """Destroying a context frees its grids; closing such a grid afterwards is
+    a no-op (no use of the freed context)."""
+    flush("grid outliving context")
+    atm, g = grids[1000]
+    dirs, w = quad
+    c = v.Context(0)
+    G = _gpu_grid(v, c, g, dirs, w)
+    c.close()
+    G.close()
+    assert G.handle is None

@@ -186,6 +186,12 @@ vrt_status vrt_grid_set_rays(vrt_grid grid, int32_t n_rays, const double *dir, c
  *                           context stream), so the launch latency of one
  *                           range overlaps the work of the others [1]. */
 #define VRT_TUNE_CHAINS 6
+/*   VRT_TUNE_LANE_BYTES     16 or 32: bytes of a [site][lambda] row each lane
+ *                           moves per access in the level-synchronous sweep
+ *                           (32 halves the lanes per record and doubles the
+ *                           records per wavefront when the row length and the
+ *                           arrays' alignment allow it) [16]. */
+#define VRT_TUNE_LANE_BYTES 8
 /*   VRT_TUNE_SPIN_CAP       bound on the polls of one wait in the persistent
  *                           sweep [2^22]; a wait that exceeds it gives up.
  *   VRT_TUNE_PERSIST_BLOCKS cap on the persistent sweep's workgroups

@@ -69,13 +69,12 @@ __device__ __forceinline__ int64_t affinity_record(const int64_t *__restrict__ x
 
 // C lanes per record, V consecutive wavelengths per lane (nl is a multiple of V).
 template <typename T, int C, int V>
-__global__ __launch_bounds__(256) void sweep_kernel(const int4 *__restrict__ ri,
-                                                    const typename vrt::RecOf<T>::type *__restrict__ rf,
-                                                    int64_t rec_begin, int64_t rec_count, int32_t nl, int64_t n,
-                                                    const T *__restrict__ chi, const T *__restrict__ S,
-                                                    const T *__restrict__ Ibot, const T *__restrict__ Itop, T *I,
-                                                    int32_t xcd_chunks, int32_t ray0,
-                                                    const int64_t *__restrict__ xtab, int32_t xk) {
+__device__ __forceinline__ void sweep_body(const int4 *__restrict__ ri,
+                                           const typename vrt::RecOf<T>::type *__restrict__ rf, int64_t rec_begin,
+                                           int64_t rec_count, int32_t nl, int64_t n, const T *__restrict__ chi,
+                                           const T *__restrict__ S, const T *__restrict__ Ibot,
+                                           const T *__restrict__ Itop, T *I, int32_t xcd_chunks, int32_t ray0,
+                                           const int64_t *__restrict__ xtab, int32_t xk) {
   using L = Lane<T, V>;
   using VT = typename L::type;
   constexpr int SPW = 64 / C;
@@ -140,6 +139,29 @@ __global__ __launch_bounds__(256) void sweep_kernel(const int4 *__restrict__ ri,
   }
 }
 
+// Single precision with lanes of at most 16 bytes: the body fits 64
+// registers, so 8 wavefronts per SIMD stay resident (more gathers in flight
+// per compute unit).
+template <typename T, int C, int V>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void sweep_kernel(
+    const int4 *__restrict__ ri, const typename vrt::RecOf<T>::type *__restrict__ rf, int64_t rec_begin,
+    int64_t rec_count, int32_t nl, int64_t n, const T *__restrict__ chi, const T *__restrict__ S,
+    const T *__restrict__ Ibot, const T *__restrict__ Itop, T *I, int32_t xcd_chunks, int32_t ray0,
+    const int64_t *__restrict__ xtab, int32_t xk) {
+  sweep_body<T, C, V>(ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I, xcd_chunks, ray0, xtab, xk);
+}
+
+// Double precision, or 32-byte lanes (twice the records per wavefront): more
+// registers per wavefront, no occupancy bound
+template <typename T, int C, int V>
+__global__ __launch_bounds__(256) void sweep_kernel_wide(
+    const int4 *__restrict__ ri, const typename vrt::RecOf<T>::type *__restrict__ rf, int64_t rec_begin,
+    int64_t rec_count, int32_t nl, int64_t n, const T *__restrict__ chi, const T *__restrict__ S,
+    const T *__restrict__ Ibot, const T *__restrict__ Itop, T *I, int32_t xcd_chunks, int32_t ray0,
+    const int64_t *__restrict__ xtab, int32_t xk) {
+  sweep_body<T, C, V>(ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I, xcd_chunks, ray0, xtab, xk);
+}
+
 // J = sum_r w_r I_r with double accumulation (ray order fixed); V elements per thread.
 template <typename T, int V>
 __global__ __launch_bounds__(256) void jreduce_kernel(const T *__restrict__ I, int32_t R, int64_t nn,
@@ -183,8 +205,12 @@ void launch_c(hipStream_t s, const int4 *ri, const typename vrt::RecOf<T>::type 
   constexpr int SPW = 64 / C;
   const int64_t waves = (c + SPW - 1) / SPW;
   const int64_t blocks = xtab ? (int64_t)vrt::kDies * ((waves + 3) / 4) : (waves + 3) / 4;
-  hipLaunchKernelGGL((sweep_kernel<T, C, V>), dim3((unsigned)blocks), dim3(256), 0, s, ri, rf, b, c, nl, n, chi, S,
-                     Ibot, Itop, I, xc, ray0, xtab, xk);
+  if constexpr (sizeof(T) != 4 || V * sizeof(T) > 16)
+    hipLaunchKernelGGL((sweep_kernel_wide<T, C, V>), dim3((unsigned)blocks), dim3(256), 0, s, ri, rf, b, c, nl, n, chi,
+                       S, Ibot, Itop, I, xc, ray0, xtab, xk);
+  else
+    hipLaunchKernelGGL((sweep_kernel<T, C, V>), dim3((unsigned)blocks), dim3(256), 0, s, ri, rf, b, c, nl, n, chi, S,
+                       Ibot, Itop, I, xc, ray0, xtab, xk);
 }
 
 // lanes per record for m lane-vectors per row: the smallest power of two >= m, at most 64
@@ -206,6 +232,7 @@ void launch_v(hipStream_t s, const int4 *ri, const typename vrt::RecOf<T>::type 
 template <typename T> constexpr int kVec = 16 / sizeof(T);
 
 inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+inline bool aligned32p(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 31u) == 0; }
 
 }  // namespace
 
@@ -214,10 +241,14 @@ namespace vrt {
 template <typename T>
 void launch_sweep(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *rf, int64_t rec_begin,
                   int64_t rec_count, int32_t nl, int64_t n, const T *chi, const T *S, const T *Ibot, const T *Itop,
-                  T *I, int32_t xcd_chunks, int32_t ray0, const int64_t *xtab, int32_t xk) {
+                  T *I, int32_t xcd_chunks, int32_t ray0, const int64_t *xtab, int32_t xk, int32_t lane_bytes) {
   if (rec_count <= 0) return;
   const bool aligned = aligned16(chi) && aligned16(S) && aligned16(Ibot) && aligned16(Itop) && aligned16(I);
-  if (aligned && nl % kVec<T> == 0)
+  const bool aligned32 = aligned32p(chi) && aligned32p(S) && aligned32p(Ibot) && aligned32p(Itop) && aligned32p(I);
+  if (lane_bytes == 32 && aligned32 && nl % (2 * kVec<T>) == 0)
+    launch_v<T, 2 * kVec<T>>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I, xcd_chunks, ray0, xtab,
+                             xk);
+  else if (aligned && nl % kVec<T> == 0)
     launch_v<T, kVec<T>>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I, xcd_chunks, ray0, xtab, xk);
   else
     launch_v<T, 1>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I, xcd_chunks, ray0, xtab, xk);
@@ -250,10 +281,10 @@ void launch_emergent(hipStream_t s, int64_t total, int32_t nl, int64_t n, const 
 
 template void launch_sweep<float>(hipStream_t, const int4 *, const RecF32 *, int64_t, int64_t, int32_t, int64_t,
                                   const float *, const float *, const float *, const float *, float *, int32_t,
-                                  int32_t, const int64_t *, int32_t);
+                                  int32_t, const int64_t *, int32_t, int32_t);
 template void launch_sweep<double>(hipStream_t, const int4 *, const RecF64 *, int64_t, int64_t, int32_t, int64_t,
                                    const double *, const double *, const double *, const double *, double *, int32_t,
-                                   int32_t, const int64_t *, int32_t);
+                                   int32_t, const int64_t *, int32_t, int32_t);
 template void launch_jreduce<float>(hipStream_t, const float *, int32_t, int64_t, const double *, float *);
 template void launch_jreduce<double>(hipStream_t, const double *, int32_t, int64_t, const double *, double *);
 template void launch_emergent<float>(hipStream_t, int64_t, int32_t, int64_t, const int32_t *, const int32_t *,

@@ -445,8 +445,9 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
     const int32_t xc = g->xcd_chunks;
     auto sweep = [&](int64_t b, int64_t c) {
       if (c <= 0) return;
-      timed_launch(ctx, s, tm, 0, c * nl,
-                   [&] { vrt::launch_sweep<T>(s, ri, rf, b, c, nl, n, chi, S, Ib, It, I, xc, 0); });
+      timed_launch(ctx, s, tm, 0, c * nl, [&] {
+        vrt::launch_sweep<T>(s, ri, rf, b, c, nl, n, chi, S, Ib, It, I, xc, 0, nullptr, 0, g->lane_bytes);
+      });
     };
     if (ex == VRT_EXEC_PLAIN) {
       for (int32_t r = 0; r < R; ++r)
@@ -460,7 +461,7 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
         if (c <= 0) continue;
         const int64_t units = (g->step_ptr[(size_t)st + 1] - g->step_ptr[(size_t)st]) * nl;
         timed_launch(ctx, s, tm, 0, units, [&] {
-          vrt::launch_sweep<T>(s, ri, rf, 0, c, nl, n, chi, S, Ib, It, I, 0, 0, xt + per * st, g->xk);
+          vrt::launch_sweep<T>(s, ri, rf, 0, c, nl, n, chi, S, Ib, It, I, 0, 0, xt + per * st, g->xk, g->lane_bytes);
         });
       }
     } else if (g->chains > 1 && R > 1) {
@@ -479,7 +480,10 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
           if (e <= b) continue;
           hipStream_t sc = c == 0 ? s : ctx->aux[(size_t)c - 1];
           timed_launch(ctx, sc, tm, 0, (e - b) * nl,
-                       [&] { vrt::launch_sweep<T>(sc, ri, rf, b, e - b, nl, n, chi, S, Ib, It, I, xc, 0); });
+                       [&] {
+                         vrt::launch_sweep<T>(sc, ri, rf, b, e - b, nl, n, chi, S, Ib, It, I, xc, 0, nullptr, 0,
+                                              g->lane_bytes);
+                       });
         }
       }
       for (int32_t c = 1; c < K; ++c) {
@@ -1120,6 +1124,9 @@ vrt_status vrt_grid_tune(vrt_grid g, int32_t knob, int64_t value) {
     } else if (knob == VRT_TUNE_CHAINS) {
       if (value < 1 || value > 8) fail(VRT_E_ARG, "chain count must be in 1..8");
       g->chains = (int)value;
+    } else if (knob == VRT_TUNE_LANE_BYTES) {
+      if (value != 16 && value != 32) fail(VRT_E_ARG, "lane bytes must be 16 or 32");
+      g->lane_bytes = (int)value;
     } else if (knob == VRT_TUNE_SPIN_CAP) {
       if (value < 0) fail(VRT_E_ARG, "spin cap must be non-negative");
       g->spin_cap = value;
@@ -1148,10 +1155,12 @@ vrt_status vrt_grid_autotune(vrt_grid g, vrt_prec prec, int32_t n_lambda, const 
     VRT_HIP(hipEventCreate(&e1));
     std::string rep = "{\"candidates\": [";
     double best = 1e300;
-    int best_order = g->record_order, best_xcd = g->xcd_chunks, best_aff = g->ray_affinity, best_ch = g->chains;
-    // (die chunks, ray affinity, chains) per record order; split chains are
-    // not candidates: kernels on separate queues were measured not to overlap
-    static const int cands[][3] = {{0, 0, 1}, {8, 0, 1}, {0, 1, 1}};
+    int best_order = g->record_order, best_xcd = g->xcd_chunks, best_aff = g->ray_affinity, best_ch = g->chains,
+        best_lb = g->lane_bytes;
+    // (die chunks, ray affinity, chains, lane bytes) per record order; split
+    // chains are not candidates: kernels on separate queues were measured not
+    // to overlap
+    static const int cands[][4] = {{0, 0, 1, 16}, {8, 0, 1, 16}, {0, 1, 1, 16}, {8, 0, 1, 32}, {0, 1, 1, 32}};
     bool first = true;
     for (int order = 0; order <= 1; ++order) {
       if (order != g->record_order || first) {
@@ -1160,10 +1169,11 @@ vrt_status vrt_grid_autotune(vrt_grid g, vrt_prec prec, int32_t n_lambda, const 
         set_rays_voronoi(g);
       }
       for (const auto &cd : cands) {
-        const int xcd = cd[0], aff = cd[1], ch = cd[2];
+        const int xcd = cd[0], aff = cd[1], ch = cd[2], lb = cd[3];
         g->xcd_chunks = xcd;
         g->ray_affinity = aff;
         g->chains = ch;
+        g->lane_bytes = lb;
         g->drop_graphs();
         auto run = [&] {
           if (prec == VRT_F32)
@@ -1181,8 +1191,9 @@ vrt_status vrt_grid_autotune(vrt_grid g, vrt_prec prec, int32_t n_lambda, const 
         const double mean = ms / reps;
         char buf[128];
         snprintf(buf, sizeof buf,
-                 "%s{\"record_order\": %d, \"xcd_chunks\": %d, \"ray_affinity\": %d, \"chains\": %d, \"ms\": %.5f}",
-                 first ? "" : ", ", order, xcd, aff, ch, mean);
+                 "%s{\"record_order\": %d, \"xcd_chunks\": %d, \"ray_affinity\": %d, \"chains\": %d, "
+                 "\"lane_bytes\": %d, \"ms\": %.5f}",
+                 first ? "" : ", ", order, xcd, aff, ch, lb, mean);
         rep += buf;
         first = false;
         if (mean < best) {
@@ -1191,6 +1202,7 @@ vrt_status vrt_grid_autotune(vrt_grid g, vrt_prec prec, int32_t n_lambda, const 
           best_xcd = xcd;
           best_aff = aff;
           best_ch = ch;
+          best_lb = lb;
         }
       }
     }
@@ -1203,12 +1215,13 @@ vrt_status vrt_grid_autotune(vrt_grid g, vrt_prec prec, int32_t n_lambda, const 
     g->xcd_chunks = best_xcd;
     g->ray_affinity = best_aff;
     g->chains = best_ch;
+    g->lane_bytes = best_lb;
     g->drop_graphs();
-    char buf[240];
+    char buf[260];
     snprintf(buf, sizeof buf,
              "], \"chosen\": {\"record_order\": %d, \"xcd_chunks\": %d, \"ray_affinity\": %d, \"chains\": %d, "
-             "\"ms\": %.5f}}",
-             best_order, best_xcd, best_aff, best_ch, best);
+             "\"lane_bytes\": %d, \"ms\": %.5f}}",
+             best_order, best_xcd, best_aff, best_ch, best_lb, best);
     rep += buf;
     if (report && report_len > 0) snprintf(report, (size_t)report_len, "%s", rep.c_str());
     return VRT_OK;

@@ -182,6 +182,7 @@ struct vrt_grid_s {
   int xcd_chunks = 8;    // 0 = plain block order
   int ray_affinity = 0;  // 1: each ray's records always run on the same die
   int chains = 1;        // independent launch chains (streams) a sweep is split into
+  int lane_bytes = 16;   // bytes of a row each lane moves per access (16 or 32)
 
   // ray-affinity tables: ray_die[r], and per step [kDies][xk][2] = {first
   // record, running count} over the segments of each die's rays
@@ -260,7 +261,7 @@ template <typename T>
 void launch_sweep(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *rf, int64_t rec_begin,
                   int64_t rec_count, int32_t nl, int64_t n, const T *chi, const T *S, const T *Ibot,
                   const T *Itop, T *I, int32_t xcd_chunks, int32_t ray0, const int64_t *xtab = nullptr,
-                  int32_t xk = 0);
+                  int32_t xk = 0, int32_t lane_bytes = 16);
 template <typename T>
 void launch_jreduce(hipStream_t s, const T *I, int32_t R, int64_t nn, const double *w, T *J);
 template <typename T>

@@ -272,12 +272,14 @@ def test_tuning_knobs_do_not_change_results(v, ctx, quad, grids):
     chi, S = to_dev(chi_o, f), to_dev(S_o, f)
     ref = None
     for order in (0, 1):
-        for xcd, aff, ch in ((0, 0, 1), (3, 0, 1), (8, 0, 1), (8, 1, 1), (8, 0, 2), (0, 0, 3), (8, 0, 5)):
+        for xcd, aff, ch, lb in ((0, 0, 1, 16), (3, 0, 1, 16), (8, 0, 1, 16), (8, 1, 1, 16), (8, 0, 2, 16),
+                                 (0, 0, 3, 16), (8, 0, 5, 16), (8, 0, 1, 32), (8, 1, 1, 32)):
             G = v.Grid.from_synth(ctx, g)
             G.tune(v.VRT_TUNE_RECORD_ORDER, order)
             G.tune(v.VRT_TUNE_XCD_CHUNKS, xcd)
             G.tune(v.VRT_TUNE_RAY_AFFINITY, aff)
             G.tune(v.VRT_TUNE_CHAINS, ch)
+            G.tune(v.VRT_TUNE_LANE_BYTES, lb)
             G.set_rays(dirs, w)
             J = torch.empty_like(chi)
             v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_GRAPH)
@@ -285,12 +287,12 @@ def test_tuning_knobs_do_not_change_results(v, ctx, quad, grids):
             out = J.cpu().numpy()
             if ref is None:
                 ref = out
-            assert np.array_equal(out, ref), (order, xcd, aff, ch)
+            assert np.array_equal(out, ref), (order, xcd, aff, ch, lb)
             G.close()
     G = _gpu_grid(v, ctx, g, dirs, w)
     J = torch.empty_like(chi)
     rep = v.autotune(G, chi, S, J, reps=2)
-    assert len(rep["candidates"]) == 6
+    assert len(rep["candidates"]) == 10
     assert rep["chosen"]["ms"] == min(c["ms"] for c in rep["candidates"])
     v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_GRAPH)
     torch.cuda.synchronize()

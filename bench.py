@@ -79,6 +79,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU baseline")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the grid's default launch layout (for profiler runs that average over dispatches)")
     ap.add_argument("--mode", choices=["auto", "graph", "batched", "persistent"], default="auto",
                     help="launch mode of the timed steps (auto: the faster of graph and persistent)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -157,7 +159,7 @@ def main():
         v.emergent_gather(G, em)
 
     v.lte_continuum(G, lam, atm.kappa0, T, rho, chi, S)
-    tuning = v.autotune(G, chi, S, J, reps=5)
+    tuning = None if args.no_autotune else v.autotune(G, chi, S, J, reps=5)
     log(f"autotune: {tuning}")
 
     for _ in range(args.warmup):

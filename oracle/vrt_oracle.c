@@ -491,11 +491,19 @@ int orc_fs_voronoi_vjp(int64_t n, int32_t n_rays, int32_t nl, const double *xyz,
             if (dL_dJ) Ibar[q] += ray_w[r] * dL_dJ[q];
         }
         orc_height_order(n, xyz, nz > 0.0 ? 1.0 : -1.0, hz);
-        for (int64_t p = n - 1; p >= 0; --p) {
+        /* wavelengths never mix: each thread takes a contiguous range of them and
+         * walks the sites in the same order, so every sum is formed in the same
+         * order as by a single thread */
+        const int nth = orc_num_threads();
+        const int32_t chunks = nl < nth ? nl : nth;
+#pragma omp parallel for schedule(static, 1) num_threads(nth)
+        for (int32_t c = 0; c < chunks; ++c) {
+          const int32_t l0 = (int32_t)((int64_t)c * nl / chunks), l1 = (int32_t)((int64_t)(c + 1) * nl / chunks);
+          for (int64_t p = n - 1; p >= 0; --p) {
             const int64_t i = hz[p];
             if (K1[i] < 0) {
                 double *gb = nz > 0.0 ? g_Ib : g_It;
-                for (int32_t l = 0; l < nl; ++l) gb[i * nl + l] += Ibar[i * nl + l];
+                for (int32_t l = l0; l < l1; ++l) gb[i * nl + l] += Ibar[i * nl + l];
                 continue;
             }
             for (int j = 0; j < 2; ++j) {
@@ -503,7 +511,7 @@ int orc_fs_voronoi_vjp(int64_t n, int32_t n_rays, int32_t nl, const double *xyz,
                 if (k < 0) continue;
                 const double w = (K2[i] < 0) ? 1.0 : (j == 0 ? W1[i] : 1.0 - W1[i]);
                 const double ds = j == 0 ? D1[i] : D2[i];
-                for (int32_t l = 0; l < nl; ++l) {
+                for (int32_t l = l0; l < l1; ++l) {
                     const double gi = Ibar[i * nl + l] * w;
                     if (gi == 0.0) continue;
                     const double x = 0.5 * (chi[k * nl + l] + chi[i * nl + l]) * ds;
@@ -518,6 +526,7 @@ int orc_fs_voronoi_vjp(int64_t n, int32_t n_rays, int32_t nl, const double *xyz,
                     g_chi[i * nl + l] += 0.5 * ds * xbar;
                 }
             }
+          }
         }
     }
     free(Ibar);

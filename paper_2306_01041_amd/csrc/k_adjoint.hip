@@ -9,7 +9,8 @@
 //   Ibar_k = seed_k + sum_d a_d E_d,          a_d = Ibar_d w_d
 //   Sbar_k = sum_d a_d Psi_u,d + sum_own_j Ibar_k w_j Psi_0,j
 //   chibar_k = sum_d a_d (-E_d I_k + Psi_u,d' S_k + Psi_0,d' S_d) ds_d / 2
-//            + sum_own_j Ibar_k w_j (-E_j I_kj + Psi_u,j' S_kj + Psi_0,j' S_k) ds_j / 2.
+//            + sum_own_j Ibar_k w_j (-E_j I_kj + Psi_u,j' S_kj + Psi_0,j' S_k) ds_j / 2
+// (the brackets are evaluated in the cancellation-free form of dI_dx below).
 // Dependents sit at higher levels, so walking the level steps downwards makes
 // every Ibar_d final before it is read; each site writes only its own entries
 // (no atomics, deterministic). Per-ray contributions are summed over rays in
@@ -35,6 +36,17 @@ template <typename T> struct ALane<T, 1> {
   static __device__ __forceinline__ T get(const type &v, int) { return v; }
   static __device__ __forceinline__ void set(type &v, int, T x) { v = x; }
 };
+
+// Derivative of one segment's intensity I = E I_u + Psi_u S_u + Psi_0 S_d with
+// respect to its optical depth x. With Psi_u' = E - Psi_0' (Psi_u + Psi_0 =
+// 1 - E) it is -E (I_u - S_u) + Psi_0' (S_d - S_u): no cancellation where
+// the intensity has thermalised (I_u ~ S_u ~ S_d), and the differences and
+// products are formed in double precision from the stored values.
+template <typename T>
+__device__ __forceinline__ T dI_dx(T E, T dp0, T Iu, T Su, T Sd) {
+  const double dI = (double)Iu - (double)Su, dS = (double)Sd - (double)Su;
+  return (T)(-(double)E * dI + (double)dp0 * dS);
+}
 
 // C lanes per record, V wavelengths per lane. Scratch arrays (I, Ibar, Sbar,
 // Cbar) hold the rays [ray0, ray0 + group) of the current ray group.
@@ -89,11 +101,10 @@ __global__ __launch_bounds__(256) void reverse_kernel(
       for (int e = 0; e < V; ++e) {
         T E, pu, p0, dp0;
         vrt::Seg<T>::weights((L::get(ck, e) + L::get(cd, e)) * hd, E, pu, p0, dp0);
-        const T dpu = E - dp0;
         const T a = L::get(ad_, e) * wd;
         L::set(ib, e, L::get(ib, e) + a * E);
         L::set(sb, e, L::get(sb, e) + a * pu);
-        const T xb = a * (-E * L::get(ik, e) + dpu * L::get(sk, e) + dp0 * L::get(sd, e));
+        const T xb = a * dI_dx(E, dp0, L::get(ik, e), L::get(sk, e), L::get(sd, e));
         L::set(cb, e, L::get(cb, e) + xb * hd);
       }
     }
@@ -109,10 +120,9 @@ __global__ __launch_bounds__(256) void reverse_kernel(
         for (int e = 0; e < V; ++e) {
           T E, pu, p0, dp0;
           vrt::Seg<T>::weights((L::get(cu, e) + L::get(ck, e)) * h, E, pu, p0, dp0);
-          const T dpu = E - dp0;
           const T a = L::get(ib, e) * w;
           L::set(sb, e, L::get(sb, e) + a * p0);
-          const T xb = a * (-E * L::get(iu, e) + dpu * L::get(su, e) + dp0 * L::get(sk, e));
+          const T xb = a * dI_dx(E, dp0, L::get(iu, e), L::get(su, e), L::get(sk, e));
           L::set(cb, e, L::get(cb, e) + xb * h);
         }
       }

@@ -485,21 +485,32 @@ def _make_lte_emergent():
         the library's kernels."""
 
         @staticmethod
-        def forward(fctx, T, rho, grid, lam, kappa0, dtype, keep_intensities, ray_group):
+        def forward(fctx, T, rho, grid, lam, kappa0, dtype, keep_intensities, ray_group, emergent_dtype):
             inf = grid.info()
             n, R = inf["n_sites"], inf["n_rays"]
             lam = np.ascontiguousarray(np.atleast_1d(lam), np.float64)
             nl = len(lam)
             dev = T.device
-            chi = torch.empty((n, nl), dtype=dtype, device=dev)
-            S = torch.empty_like(chi)
-            J = torch.empty_like(chi)
-            I = torch.empty((R, n, nl), dtype=dtype, device=dev) if keep_intensities else None
-            lte_continuum(grid, lam, kappa0, T, rho, chi, S)
-            formal_solution(grid, chi, S, J, I_rays=I, exec_mode=VRT_EXEC_BATCHED)
+            fdt = dtype if emergent_dtype is None else emergent_dtype
+            mixed = fdt != dtype
+            # the sweep whose emergent intensities are returned (precision fdt)
+            chi_f = torch.empty((n, nl), dtype=fdt, device=dev)
+            S_f = torch.empty_like(chi_f)
+            J = torch.empty_like(chi_f)
+            I = torch.empty((R, n, nl), dtype=fdt, device=dev) if keep_intensities and not mixed else None
+            lte_continuum(grid, lam, kappa0, T, rho, chi_f, S_f)
+            formal_solution(grid, chi_f, S_f, J, I_rays=I, exec_mode=VRT_EXEC_BATCHED)
             off, _ = grid.emergent_index()
-            em = torch.empty((int(off[-1]), nl), dtype=dtype, device=dev)
+            em = torch.empty((int(off[-1]), nl), dtype=fdt, device=dev)
             emergent_gather(grid, em, I_rays=I)
+            if mixed:
+                # the reverse sweep runs in `dtype` on fields of that precision; it
+                # recomputes its own forward intensities ray group by ray group
+                chi = torch.empty((n, nl), dtype=dtype, device=dev)
+                S = torch.empty_like(chi)
+                lte_continuum(grid, lam, kappa0, T, rho, chi, S)
+            else:
+                chi, S = chi_f, S_f
             fctx.grid, fctx.lam, fctx.kappa0, fctx.ray_group = grid, lam, kappa0, ray_group
             fctx.I = I
             fctx.save_for_backward(T, rho, chi, S)
@@ -515,7 +526,7 @@ def _make_lte_emergent():
             g_chi, g_S, g_Ib, _ = formal_solution_vjp(grid, chi, S, dL_dI=gI, I_rays=fctx.I,
                                                       ray_group=fctx.ray_group)
             gT, gr = lte_continuum_vjp(grid, fctx.lam, fctx.kappa0, T, rho, g_chi, g_S, g_Ib)
-            return gT, gr, None, None, None, None, None, None
+            return gT, gr, None, None, None, None, None, None, None
 
     return LTEEmergent
 
@@ -523,12 +534,21 @@ def _make_lte_emergent():
 _LTE_EMERGENT = None
 
 
-def lte_emergent(T, rho, grid: Grid, lam, kappa0, dtype=None, keep_intensities=True, ray_group=0):
-    """Differentiable emergent intensities [n_emergent, nl] (see LTEEmergent)."""
+def lte_emergent(T, rho, grid: Grid, lam, kappa0, dtype=None, keep_intensities=True, ray_group=0,
+                 emergent_dtype=None):
+    """Differentiable emergent intensities [n_emergent, nl] (see LTEEmergent).
+
+    dtype is the precision of the sweeps (float32 by default). With
+    emergent_dtype=torch.float64 and float32 sweeps, the returned intensities
+    come from a double-precision forward sweep, so that a misfit whose residuals
+    are small against the intensities is formed accurately; the reverse sweep
+    still runs in single precision (it recomputes its own single-precision
+    forward intensities).
+    """
     import torch
 
     global _LTE_EMERGENT
     if _LTE_EMERGENT is None:
         _LTE_EMERGENT = _make_lte_emergent()
     return _LTE_EMERGENT.apply(T, rho, grid, lam, kappa0, torch.float32 if dtype is None else dtype,
-                               keep_intensities, ray_group)
+                               keep_intensities, ray_group, emergent_dtype)

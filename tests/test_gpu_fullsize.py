@@ -1,0 +1,268 @@
+"""Parity at the full workload sizes, in the launch configuration the benchmark
+times (FP32 sweeps, graph-launched, default launch layout):
+
+* 262,144-site Voronoi grid, 64 wavelengths 400-900 nm, 24 rays: J and the
+  emergent intensities against the FP64 oracle (FP32 1e-5 on J), and the plain
+  FP64 GPU path against it (1e-12);
+* the regular 128 x 128 x 256 grid: every 16th of the 64 wavelengths against
+  the oracle at full grid size, and all 64 in FP32 against the FP64 GPU path;
+* the adjoint of the emergent intensity (32 wavelengths 500-700 nm, FP32
+  sweeps with FP64 accumulation, and FP64): against central differences of
+  the FP64 forward on 64 random sites each for T and rho, and against the
+  oracle's gradient;
+* one two-level Lambda iteration on the 1,048,576-site grid with the
+  101-point line, against the oracle's iteration.
+
+Each case prints what it is about to run and the errors it finds.
+"""
+
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import flush, relerr, to_dev
+from oracle import nlte as onl
+from synth.nlte import LAMBDA0_NM, line_setup
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SEED = 1041
+MM = 1e6
+
+
+@pytest.fixture(scope="module")
+def v():
+    import paper_2306_01041_amd
+
+    return paper_2306_01041_amd.load()
+
+
+@pytest.fixture(scope="module")
+def ctx(v):
+    c = v.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def c1():
+    t0 = time.time()
+    atm = synth.make_atmosphere(262144, seed=SEED)
+    g = synth.voronoi_neighbours(atm.xyz, atm.box.lo, atm.box.hi)
+    dirs, w = synth.gauss_legendre_quadrature()
+    sel = oracle.select(g, dirs)
+    flush(f"262k grid and oracle selection built in {time.time() - t0:.1f} s")
+    return atm, g, dirs, w, sel
+
+
+def test_c1_voronoi_full_size(v, ctx, c1):
+    atm, g, dirs, w, sel = c1
+    nl = 64
+    lam = np.linspace(400e-9, 900e-9, nl)
+    flush("c1 voronoi: oracle FP64 formal solution (262,144 sites x 24 rays x 64 wavelengths)")
+    chi_o, S_o = oracle.lte(lam, atm.kappa0, atm.T, atm.rho)
+    t0 = time.time()
+    Jo, Io = oracle.fs_voronoi(g, dirs, w, sel, chi_o, S_o, S_o, keep_I=True)
+    flush(f"  oracle done in {time.time() - t0:.1f} s")
+    em_sites = oracle.emergent_sites(g, dirs)
+    Iem_o = [Io[r, em_sites[r]] for r in range(len(dirs))]
+    del Io
+    G = v.Grid.from_synth(ctx, g)
+    G.set_rays(dirs, w)
+    T, rho = to_dev(atm.T, torch.float64), to_dev(atm.rho, torch.float64)
+    for dt, tol_J, tol_I in ((torch.float32, 1e-5, 1e-4), (torch.float64, 1e-12, 1e-12)):
+        flush(f"  GPU {dt}")
+        chi = torch.empty((g.n, nl), dtype=dt, device="cuda:0")
+        S = torch.empty_like(chi)
+        J = torch.empty_like(chi)
+        v.lte_continuum(G, lam, atm.kappa0, T, rho, chi, S)
+        mode = v.VRT_EXEC_GRAPH if dt == torch.float32 else v.VRT_EXEC_PLAIN
+        v.formal_solution(G, chi, S, J, exec_mode=mode)
+        off, sites = G.emergent_index()
+        em = torch.empty((int(off[-1]), nl), dtype=dt, device="cuda:0")
+        v.emergent_gather(G, em)
+        torch.cuda.synchronize()
+        eJ = relerr(J.cpu().numpy(), Jo)
+        emh = em.cpu().numpy()
+        eI = max(relerr(emh[off[r]:off[r + 1]], Iem_o[r]) for r in range(len(dirs)))
+        flush(f"    max rel err J {eJ:.3e}, emergent I {eI:.3e}")
+        assert eJ <= tol_J
+        assert eI <= tol_I
+        for r in range(len(dirs)):
+            assert np.array_equal(sites[off[r]:off[r + 1]], em_sites[r])
+        del chi, S, J, em
+    G.close()
+
+
+def test_c1_regular_full_size(v, ctx):
+    nx = ny = 128
+    nz = 256
+    box = synth.BoxSpec()
+    dx = (box.hi[0] - box.lo[0]) / nx
+    dy = (box.hi[1] - box.lo[1]) / ny
+    z = box.lo[2] + (box.hi[2] - box.lo[2]) * np.arange(nz) / (nz - 1)
+    X, Y, Z = np.meshgrid(box.lo[0] + dx * np.arange(nx), box.lo[1] + dy * np.arange(ny), z, indexing="xy")
+    # site index (k * ny + j) * nx + i
+    xyz = np.stack([X.transpose(2, 0, 1).ravel(), Y.transpose(2, 0, 1).ravel(), Z.transpose(2, 0, 1).ravel()], 1)
+    atm = synth.make_atmosphere(len(xyz), seed=SEED, xyz=xyz)
+    dirs, w = synth.gauss_legendre_quadrature()
+    nl = 64
+    lam = np.linspace(400e-9, 900e-9, nl)
+    G = v.Grid.regular(ctx, nx, ny, z, dx, dy)
+    G.set_rays(dirs, w)
+    T, rho = to_dev(atm.T, torch.float64), to_dev(atm.rho, torch.float64)
+    out = {}
+    for dt in (torch.float32, torch.float64):
+        flush(f"c1 regular 128x128x256, 64 wavelengths, GPU {dt}")
+        chi = torch.empty((len(xyz), nl), dtype=dt, device="cuda:0")
+        S = torch.empty_like(chi)
+        J = torch.empty_like(chi)
+        v.lte_continuum(G, lam, atm.kappa0, T, rho, chi, S)
+        v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_GRAPH if dt == torch.float32 else v.VRT_EXEC_PLAIN)
+        torch.cuda.synchronize()
+        out[dt] = J.cpu().numpy()
+        del chi, S, J
+    e32 = relerr(out[torch.float32], out[torch.float64])
+    flush(f"  FP32 vs FP64 GPU: max rel err J {e32:.3e}")
+    assert e32 <= 1e-5
+    # the oracle on every 16th wavelength (4 of 64) at the full grid size
+    pick = np.arange(0, nl, 16)
+    flush("  oracle FP64 regular sweep, 4 wavelengths")
+    chi_o, S_o = oracle.lte(lam[pick], atm.kappa0, atm.T, atm.rho)
+    t0 = time.time()
+    Jo = oracle.fs_regular(nx, ny, z, dx, dy, dirs, w, chi_o, S_o, S_o)
+    flush(f"  oracle done in {time.time() - t0:.1f} s")
+    e64 = relerr(out[torch.float64][:, pick], Jo)
+    flush(f"  FP64 GPU vs oracle: max rel err J {e64:.3e}")
+    assert e64 <= 1e-12
+    assert relerr(out[torch.float32][:, pick], Jo) <= 1e-5
+    G.close()
+
+
+def test_c4_adjoint_full_size(v, ctx, c1):
+    """Three pipelines: FP64 sweeps; FP32 sweeps; FP32 sweeps with the emergent
+    intensities of the misfit from an FP64 forward sweep. The FP32 reverse sweep
+    itself is accurate to ~1e-7, but with FP32 emergent intensities the misfit
+    residuals (a few tenths of a percent of the intensity) carry the forward
+    sweep's ~1e-6 rounding, which reaches the gradient as a few 1e-5 normwise."""
+    atm, g, dirs, w, sel = c1
+    nl = 32
+    lam = np.linspace(500e-9, 700e-9, nl)
+    rng = np.random.Generator(np.random.PCG64(SEED + 1))
+    T_tgt = atm.T * (1.0 + 0.02 * rng.standard_normal(g.n))
+    G = v.Grid.from_synth(ctx, g)
+    G.set_rays(dirs, w)
+    off, _ = G.emergent_index()
+    up = np.concatenate([np.arange(off[r], off[r + 1]) for r in range(len(dirs)) if dirs[r, 2] > 0])
+    up_t = torch.as_tensor(up, device="cuda:0")
+    T = to_dev(atm.T, torch.float64)
+    rho = to_dev(atm.rho, torch.float64)
+    f32, f64 = torch.float32, torch.float64
+
+    def loss(Tq, rq, dtype, target, emergent_dtype=None):
+        em = v.lte_emergent(Tq, rq, G, lam, atm.kappa0, dtype=dtype, emergent_dtype=emergent_dtype)
+        return ((em.double()[up_t] - target) ** 2).sum()
+
+    with torch.no_grad():
+        tgt64 = v.lte_emergent(to_dev(T_tgt, f64), rho, G, lam, atm.kappa0, dtype=f64).double()[up_t]
+    grads = {}
+    for name, dt, edt in (("f64", f64, None), ("f32", f32, None), ("f32+em64", f32, f64)):
+        flush(f"c4 adjoint, GPU {name}")
+        Tq = T.clone().requires_grad_(True)
+        rq = rho.clone().requires_grad_(True)
+        L = loss(Tq, rq, dt, tgt64, edt)
+        L.backward()
+        grads[name] = (Tq.grad.cpu().numpy(), rq.grad.cpu().numpy(), float(L.detach()))
+    gT64, gr64, L64 = grads["f64"]
+    norms = {}
+    for name in ("f32", "f32+em64"):
+        gT, gr, _ = grads[name]
+        norms[name] = (np.linalg.norm(gT - gT64) / np.linalg.norm(gT64), np.linalg.norm(gr - gr64) / np.linalg.norm(gr64))
+    flush(f"  normwise against the FP64 adjoint (T, rho): {norms}")
+
+    # central differences of the FP64 forward, for T and for rho on 64 random
+    # sites each among those the loss responds to (|dL/dq| at least 1e-3 of its
+    # largest value; elsewhere the change of L drowns in rounding)
+    worst = {name: {"T": 0.0, "rho": 0.0} for name in grads}
+    rng = np.random.Generator(np.random.PCG64(SEED + 2))
+    with torch.no_grad():
+        for which, base, col in (("T", T, 0), ("rho", rho, 1)):
+            g64 = grads["f64"][col]
+            cand = np.nonzero(np.abs(g64) >= 1e-3 * np.abs(g64).max())[0]
+            flush(f"  central differences in {which} on 64 of {len(cand)} responsive sites")
+            for i in rng.choice(cand, 64, replace=False):
+                h = 1e-5 * float(base[i])
+                vals = []
+                for sgn in (1.0, -1.0):
+                    p = base.clone()
+                    p[i] += sgn * h
+                    Tq, rq = (p, rho) if which == "T" else (T, p)
+                    vals.append(float(loss(Tq, rq, f64, tgt64)))
+                fd = (vals[0] - vals[1]) / (2 * h)
+                for name in grads:
+                    gi = grads[name][col][i]
+                    worst[name][which] = max(worst[name][which], abs(gi - fd) / abs(fd))
+    flush(f"  adjoint vs central differences, max rel err: {worst}")
+
+    flush("  oracle gradient (FP64, 262,144 sites x 32 wavelengths)")
+    t0 = time.time()
+    em_sites = oracle.emergent_sites(g, dirs)
+    _, _, _, It = oracle.emergent_loss(g, dirs, w, sel, lam, atm.kappa0, T_tgt, atm.rho)
+    target = {r: It[r, em_sites[r]] for r in range(len(dirs)) if dirs[r, 2] > 0}
+    del It
+    Lo, gTo, gro, _ = oracle.emergent_loss(g, dirs, w, sel, lam, atm.kappa0, atm.T, atm.rho, target)
+    flush(f"  oracle done in {time.time() - t0:.1f} s; loss GPU {L64:.6e} oracle {Lo:.6e}")
+    vs_oracle = {name: (np.linalg.norm(grads[name][0] - gTo) / np.linalg.norm(gTo),
+                        np.linalg.norm(grads[name][1] - gro) / np.linalg.norm(gro)) for name in grads}
+    flush(f"  GPU vs oracle gradient, normwise (T, rho): {vs_oracle}")
+    G.close()
+    assert abs(L64 - Lo) <= 1e-10 * abs(Lo)
+    assert max(vs_oracle["f64"]) <= 1e-10
+    # the 1e-4 target against central differences, with FP64 and with FP32 sweeps
+    assert max(worst["f64"].values()) <= 1e-4
+    assert max(worst["f32+em64"].values()) <= 1e-4
+    assert max(vs_oracle["f32+em64"]) <= 1e-5
+    # FP32 emergent intensities in the misfit: bounded by the forward rounding
+    assert max(norms["f32"]) <= 1e-4
+    assert max(worst["f32"].values()) <= 2e-3
+
+
+def test_c2_one_iteration_full_size(v, ctx):
+    flush("c2: 1,048,576-site grid")
+    t0 = time.time()
+    atm = synth.make_atmosphere(1048576, seed=SEED)
+    g = synth.voronoi_neighbours(atm.xyz, atm.box.lo, atm.box.hi)
+    dirs, w = synth.gauss_legendre_quadrature()
+    line = line_setup(atm.T, atm.rho, n_lambda=101)
+    lam0 = np.array([LAMBDA0_NM * 1e-9])
+    flush(f"  grid and line built in {time.time() - t0:.1f} s")
+    eps = 1e-4
+    G = v.Grid.from_synth(ctx, g)
+    G.set_rays(dirs, w)
+    d = torch.float64
+    chi_c = torch.empty((g.n, 1), dtype=d, device="cuda:0")
+    B = torch.empty_like(chi_c)
+    v.lte_continuum(G, lam0, atm.kappa0, to_dev(atm.T, d), to_dev(atm.rho, d), chi_c, B)
+    chi_c, B = chi_c[:, 0].contiguous(), B[:, 0].contiguous()
+    S = B.clone()
+    st, nit, hist = v.two_level_solve(G, line.wlam, to_dev(line.phi, d), to_dev(line.chi_line, d), chi_c, B, eps, S,
+                                      max_iter=1, tol=0.0, sweep_dtype=torch.float32)
+    torch.cuda.synchronize()
+    G.close()
+    flush("  oracle FP64 iteration (1,048,576 sites x 24 rays x 101 wavelengths)")
+    t0 = time.time()
+    chi_co, B_o = oracle.lte(lam0, atm.kappa0, atm.T, atm.rho)
+    sel = oracle.select(g, dirs)
+    S_o, hist_o, _, _ = onl.lambda_iterate(g, dirs, w, sel, chi_co[:, 0], line.chi_line, line.phi, line.wlam,
+                                           B_o[:, 0], eps, max_iter=1, tol=0.0)
+    flush(f"  oracle done in {time.time() - t0:.1f} s")
+    e = relerr(S.cpu().numpy(), S_o)
+    flush(f"  S_line after one iteration: max rel err {e:.3e}; change GPU {hist[0]:.6e} oracle {hist_o[0]:.6e}")
+    assert nit == 1 and st == v.VRT_W_NOT_CONVERGED
+    assert e <= 1e-5
+    assert abs(hist[0] - hist_o[0]) <= 3e-5

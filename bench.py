@@ -81,6 +81,11 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the grid's default launch layout (for profiler runs that average over dispatches)")
+    ap.add_argument("--workload", choices=["c1", "c2", "c3"], default="c1",
+                    help="c1: the formal solution (default line); c2: the two-level Lambda iteration on 1,048,576 "
+                         "sites; c3: 48 atmospheres of 32,768-524,288 sites solved as one batch")
+    ap.add_argument("--max-iter", type=int, default=None,
+                    help="iteration cap of the c2/c3 Lambda iterations (default 1000 for c2, 100 for c3)")
     ap.add_argument("--mode", choices=["auto", "graph", "batched", "persistent"], default="auto",
                     help="launch mode of the timed steps (auto: the faster of graph and persistent)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -99,6 +104,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload != "c1":
+        run_lambda(args)
+        return
 
     import torch
 
@@ -345,6 +353,153 @@ def main():
     G.close()
     ctx.close()
     del stream
+
+
+def _make_grid(args):
+    """One seeded atmosphere, its Voronoi grid and its line profile (module
+    level, for the process pool)."""
+    import synth
+    from synth.nlte import line_setup
+
+    n, seed = args
+    atm = synth.make_atmosphere(n, seed=seed)
+    g = synth.voronoi_neighbours(atm.xyz, atm.box.lo, atm.box.hi)
+    line = line_setup(atm.T, atm.rho, n_lambda=101)
+    return atm, g, line
+
+
+def run_lambda(args):
+    """Two-level Lambda iteration on 1,048,576 sites (c2) or on a batch of 48
+    atmospheres of 32,768-524,288 sites (c3): 101 line wavelengths, 24 rays,
+    eps = 1e-4, FP32 sweeps, FP64 line update, graph-captured iterations, to
+    max |dS|/S < 1e-3. Reports the time per iteration, the iteration counts,
+    the formal solution's share of an iteration and its update rate."""
+    import multiprocessing as mp
+
+    import torch
+
+    import paper_2306_01041_amd
+    import synth
+    from synth.nlte import LAMBDA0_NM
+
+    v = paper_2306_01041_amd.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = "cuda:0"
+    seed = 1041
+    t0 = time.time()
+    if args.workload == "c2":
+        jobs = [(1048576, seed)]
+    else:
+        # atmosphere j of the batch uses seed + 1 + j
+        jobs = [(n, seed + 1 + j) for j, n in enumerate(synth.batch_sizes(48, 32768, 524288, seed))]
+    with mp.get_context("spawn").Pool(min(16, len(jobs))) as pool:
+        made = []
+        for k, r in enumerate(pool.imap(_make_grid, jobs)):
+            made.append(r)
+            log(f"atmosphere {k + 1}/{len(jobs)}: {r[1].n} sites")
+    atms = [m[0] for m in made]
+    grids = [m[1] for m in made]
+    lines = [m[2] for m in made]
+    del made
+    U, off = synth.concat_grids(grids) if len(grids) > 1 else (grids[0], np.array([0, grids[0].n], np.int64))
+    T = np.concatenate([a.T for a in atms])
+    rho = np.concatenate([a.rho for a in atms])
+    nl = 101
+    wlam = lines[0].wlam
+    phi = torch.empty((U.n, nl), dtype=torch.float64, device=dev)
+    for j, ln in enumerate(lines):
+        phi[off[j]:off[j + 1]].copy_(torch.as_tensor(ln.phi))
+    chi_L = torch.as_tensor(np.concatenate([ln.chi_line for ln in lines]), device=dev)
+    del lines
+    dirs, w = synth.gauss_legendre_quadrature()
+    R = len(dirs)
+    log(f"{len(grids)} atmosphere(s), {U.n} sites, inputs built in {time.time() - t0:.1f} s")
+
+    ctx = v.Context(0)
+    G = v.Grid.from_synth(ctx, U)
+    t0 = time.time()
+    G.set_rays(dirs, w)
+    setup_s = time.time() - t0
+    info = G.info()
+    log(f"rays set in {setup_s:.2f} s: {info}")
+    d = torch.float64
+    lam0 = np.array([LAMBDA0_NM * 1e-9])
+    # one continuum constant for the batch (a recipe constant)
+    chi_c = torch.empty((U.n, 1), dtype=d, device=dev)
+    B = torch.empty_like(chi_c)
+    v.lte_continuum(G, lam0, atms[0].kappa0, torch.as_tensor(T, device=dev), torch.as_tensor(rho, device=dev),
+                    chi_c, B)
+    chi_c, B = chi_c[:, 0].contiguous(), B[:, 0].contiguous()
+    eps = 1e-4
+
+    # the formal solution alone, on the fields of the first iteration, in the
+    # library's own layout inside the iteration: rows padded to 104 entries
+    # (16-byte multiples) with the continuum in the padding; only the 101 line
+    # wavelengths count as updates
+    f32 = torch.float32
+    S_L = B.clone()
+    ld = (nl + 3) // 4 * 4
+    chi = torch.empty((U.n, ld), dtype=f32, device=dev)
+    S = torch.empty_like(chi)
+    chi[:, :nl] = chi_c[:, None] + chi_L[:, None] * phi
+    S[:, :nl] = (chi_L[:, None] * phi * S_L[:, None] + chi_c[:, None] * B[:, None]) / (chi_c[:, None] +
+                                                                                   chi_L[:, None] * phi)
+    chi[:, nl:] = chi_c[:, None]
+    S[:, nl:] = B[:, None]
+    J = torch.empty_like(chi)
+    for _ in range(2):
+        v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_GRAPH)
+    torch.cuda.synchronize()
+    k = 5
+    t1 = time.perf_counter()
+    for _ in range(k):
+        v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_GRAPH)
+    torch.cuda.synchronize()
+    fs_ms = (time.perf_counter() - t1) * 1e3 / k
+    del chi, S, J
+    updates = U.n * R * nl
+    log(f"formal solution {fs_ms:.3f} ms -> {updates / (fs_ms * 1e-3):.3e} updates/s")
+
+    # the iteration to convergence (or the cap)
+    max_iter = args.max_iter if args.max_iter is not None else (1000 if args.workload == "c2" else 100)
+    log(f"Lambda iteration, at most {max_iter} iterations")
+    t1 = time.perf_counter()
+    st, its, hist = v.two_level_solve_batched(G, off, wlam, phi, chi_L, chi_c, B, eps, S_L,
+                                              max_iter=max_iter, tol=1e-3, sweep_dtype=f32)
+    torch.cuda.synchronize()
+    total_s = time.perf_counter() - t1
+    n_iter = int(np.max(its))
+    it_ms = total_s * 1e3 / max(n_iter, 1)
+    log(f"Lambda iteration: status {st}, iterations {np.min(its)}..{n_iter}, {it_ms:.3f} ms per iteration, "
+        f"{total_s:.2f} s in total")
+    out = {
+        "metric": "site*ray*lambda updates/s of the formal solution inside the two-level Lambda iteration",
+        "value": updates / (fs_ms * 1e-3),
+        "unit": "site*ray*lambda updates/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f32",
+        "data": "synthetic (seeded Bifrost-like stratified atmospheres, rejection-sampled Voronoi sites)",
+        "config": {"workload": ("two-level Lambda iteration, " +
+                                (f"{U.n} sites" if len(grids) == 1 else
+                                 f"{len(grids)} atmospheres, {U.n} sites in total") +
+                                f", {nl} line wavelengths, {R} rays, eps {eps}, FP32 sweeps, FP64 update"),
+                   "sites": U.n, "atmospheres": len(grids), "wavelengths": nl, "rays": R,
+                   "levels_max": info["max_levels"]},
+        "formal_solution_ms": round(fs_ms, 3),
+        "ms_per_iteration": round(it_ms, 3),
+        "formal_solution_share": round(fs_ms / it_ms, 3),
+        "iterations": {"min": int(np.min(its)), "max": n_iter, "median": float(np.median(its)), "cap": max_iter},
+        "converged": bool(st == v.VRT_OK),
+        "atmospheres_converged": int(np.sum(its < max_iter) + np.sum((its == max_iter) & (hist[-1] < 1e-3))),
+        "final_change": {"min": float(np.min(hist[-1])), "max": float(np.max(hist[-1]))},
+        "solve_s": round(total_s, 3),
+        "setup_s": round(setup_s, 3),
+        "whole_step_effective_GBs": round(updates * (20.0 + 20.0 / nl) / (fs_ms * 1e-3) / 1e9, 1),
+    }
+    print(json.dumps(out))
+    G.close()
+    ctx.close()
 
 
 if __name__ == "__main__":

@@ -360,7 +360,9 @@ vrt_status vrt_grid_emergent_index(vrt_grid grid, int64_t *offsets, int32_t *sit
 /* Gather the emergent intensities of the last formal solution into out
  * (device [offsets[n_rays]][n_lambda], prec), ray by ray in the order of
  * vrt_grid_emergent_index. I_rays is the array given to that formal solution,
- * or NULL if it used library scratch. Enqueued. */
+ * or NULL if it used library scratch (the last vrt_formal_solution or
+ * two-level solve on this grid; then prec and n_lambda must be those of that
+ * solution, else VRT_E_ARG). Enqueued. */
 vrt_status vrt_emergent_gather(vrt_grid grid, vrt_prec prec, int32_t n_lambda, const void *I_rays,
                                void *out);
 

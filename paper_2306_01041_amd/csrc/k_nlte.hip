@@ -15,27 +15,36 @@
 
 namespace {
 
+// Rows of chi and S have ld >= nl entries; the ld - nl padding entries take
+// the continuum alone (finite values the sweep may carry but nothing reads).
 template <typename T>
-__global__ __launch_bounds__(256) void nlte_assemble_kernel(int64_t n, int32_t nl, const double *__restrict__ phi,
+__global__ __launch_bounds__(256) void nlte_assemble_kernel(int64_t n, int32_t nl, int32_t ld,
+                                                            const double *__restrict__ phi,
                                                             const double *__restrict__ chi_L,
                                                             const double *__restrict__ chi_c,
                                                             const double *__restrict__ B,
                                                             const double *__restrict__ S_L, T *__restrict__ chi,
                                                             T *__restrict__ S) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n * nl) return;
-  const int64_t i = t / nl;
-  const double lo = chi_L[i] * phi[t];
+  if (t >= n * ld) return;
+  const int64_t i = t / ld;
+  const int32_t l = (int32_t)(t - i * ld);
+  if (l >= nl) {
+    chi[t] = (T)chi_c[i];
+    S[t] = (T)B[i];
+    return;
+  }
+  const double lo = chi_L[i] * phi[i * nl + l];
   const double c = chi_c[i] + lo;
   chi[t] = (T)c;
   S[t] = (T)((lo * S_L[i] + chi_c[i] * B[i]) / c);
 }
 
 template <typename T>
-__global__ void broadcast_kernel(int64_t n, int32_t nl, const double *__restrict__ v, T *__restrict__ out) {
+__global__ void broadcast_kernel(int64_t n, int32_t ld, const double *__restrict__ v, T *__restrict__ out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n * nl) return;
-  out[t] = (T)v[t / nl];
+  if (t >= n * ld) return;
+  out[t] = (T)v[t / ld];
 }
 
 __global__ void zero_u64_array_kernel(int32_t count, unsigned long long *p) {
@@ -60,8 +69,10 @@ __device__ __forceinline__ int32_t atm_of(int64_t i, int32_t n_atm, const int64_
 // keeps the running maximum change of the atmosphere it is in and flushes it
 // with one atomic when it leaves that atmosphere. Inactive (converged)
 // atmospheres keep their S_line.
+// I rows have ld >= nl entries (only the first nl are line wavelengths).
 template <typename T>
-__global__ __launch_bounds__(256) void line_update_kernel(int64_t n, int32_t nl, int32_t R, const T *__restrict__ I,
+__global__ __launch_bounds__(256) void line_update_kernel(int64_t n, int32_t nl, int32_t ld, int32_t R,
+                                                          const T *__restrict__ I,
                                                           const double *__restrict__ w,
                                                           const double *__restrict__ wlam,
                                                           const double *__restrict__ phi,
@@ -76,7 +87,7 @@ __global__ __launch_bounds__(256) void line_update_kernel(int64_t n, int32_t nl,
   const int64_t chunk = (n + waves - 1) / waves;
   const int64_t i0 = wave * chunk, i1 = (i0 + chunk < n) ? i0 + chunk : n;
   if (i0 >= i1) return;
-  const int64_t nn = n * nl;
+  const int64_t nn = n * ld;
   int32_t atm = atm_of(i0, n_atm, atm_ptr);
   double dmax = 0.0;
   bool any = false;
@@ -90,10 +101,10 @@ __global__ __launch_bounds__(256) void line_update_kernel(int64_t n, int32_t nl,
     if (!active[atm]) continue;
     double acc = 0.0;
     for (int l = lane; l < nl; l += 64) {
-      const int64_t q = i * nl + l;
+      const int64_t q = i * ld + l;
       double j = 0.0;
       for (int32_t r = 0; r < R; ++r) j += w[r] * (double)I[(int64_t)r * nn + q];
-      acc += wlam[l] * phi[q] * j;
+      acc += wlam[l] * phi[i * nl + l] * j;
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
@@ -129,17 +140,17 @@ inline unsigned nb(int64_t work, int bs) { return (unsigned)((work + bs - 1) / b
 namespace vrt {
 
 template <typename T>
-void launch_nlte_assemble(hipStream_t s, int64_t n, int32_t nl, const double *phi, const double *chi_L,
+void launch_nlte_assemble(hipStream_t s, int64_t n, int32_t nl, int32_t ld, const double *phi, const double *chi_L,
                           const double *chi_c, const double *B, const double *S_L, T *chi, T *S) {
-  if (n * nl == 0) return;
-  hipLaunchKernelGGL(nlte_assemble_kernel<T>, dim3(nb(n * nl, 256)), dim3(256), 0, s, n, nl, phi, chi_L, chi_c, B,
-                     S_L, chi, S);
+  if (n * ld == 0) return;
+  hipLaunchKernelGGL(nlte_assemble_kernel<T>, dim3(nb(n * ld, 256)), dim3(256), 0, s, n, nl, ld, phi, chi_L, chi_c,
+                     B, S_L, chi, S);
   VRT_HIP(hipGetLastError());
 }
 
-template <typename T> void launch_broadcast(hipStream_t s, int64_t n, int32_t nl, const double *v, T *out) {
-  if (n * nl == 0) return;
-  hipLaunchKernelGGL(broadcast_kernel<T>, dim3(nb(n * nl, 256)), dim3(256), 0, s, n, nl, v, out);
+template <typename T> void launch_broadcast(hipStream_t s, int64_t n, int32_t ld, const double *v, T *out) {
+  if (n * ld == 0) return;
+  hipLaunchKernelGGL(broadcast_kernel<T>, dim3(nb(n * ld, 256)), dim3(256), 0, s, n, ld, v, out);
   VRT_HIP(hipGetLastError());
 }
 
@@ -157,27 +168,29 @@ void launch_check_partition(hipStream_t s, int64_t n, int32_t R, const int32_t *
 }
 
 template <typename T>
-void launch_line_update(hipStream_t s, int64_t n, int32_t nl, int32_t R, const T *I, const double *w,
+void launch_line_update(hipStream_t s, int64_t n, int32_t nl, int32_t ld, int32_t R, const T *I, const double *w,
                         const double *wlam, const double *phi, const double *B, double eps, double *S_L,
                         int32_t n_atm, const int64_t *atm_ptr, const int32_t *active, unsigned long long *dS_bits) {
   if (n == 0) return;
   int64_t blocks = (n + 3) / 4;
   if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(line_update_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, n, nl, R, I, w, wlam, phi, B,
-                     eps, S_L, n_atm, atm_ptr, active, dS_bits);
+  hipLaunchKernelGGL(line_update_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, n, nl, ld, R, I, w, wlam, phi,
+                     B, eps, S_L, n_atm, atm_ptr, active, dS_bits);
   VRT_HIP(hipGetLastError());
 }
 
-template void launch_nlte_assemble<float>(hipStream_t, int64_t, int32_t, const double *, const double *,
+template void launch_nlte_assemble<float>(hipStream_t, int64_t, int32_t, int32_t, const double *, const double *,
                                           const double *, const double *, const double *, float *, float *);
-template void launch_nlte_assemble<double>(hipStream_t, int64_t, int32_t, const double *, const double *,
+template void launch_nlte_assemble<double>(hipStream_t, int64_t, int32_t, int32_t, const double *, const double *,
                                            const double *, const double *, const double *, double *, double *);
 template void launch_broadcast<float>(hipStream_t, int64_t, int32_t, const double *, float *);
 template void launch_broadcast<double>(hipStream_t, int64_t, int32_t, const double *, double *);
-template void launch_line_update<float>(hipStream_t, int64_t, int32_t, int32_t, const float *, const double *,
+template void launch_line_update<float>(hipStream_t, int64_t, int32_t, int32_t, int32_t, const float *,
+                                        const double *,
                                         const double *, const double *, const double *, double, double *, int32_t,
                                         const int64_t *, const int32_t *, unsigned long long *);
-template void launch_line_update<double>(hipStream_t, int64_t, int32_t, int32_t, const double *, const double *,
+template void launch_line_update<double>(hipStream_t, int64_t, int32_t, int32_t, int32_t, const double *,
+                                         const double *,
                                          const double *, const double *, const double *, double, double *, int32_t,
                                          const int64_t *, const int32_t *, unsigned long long *);
 

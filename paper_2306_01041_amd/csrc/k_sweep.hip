@@ -186,14 +186,15 @@ __global__ __launch_bounds__(256) void jreduce_kernel(const T *__restrict__ I, i
   }
 }
 
+// I rows have ld >= nl entries; out rows have nl.
 template <typename T>
-__global__ void emergent_kernel(int64_t total, int32_t nl, int64_t n, const int32_t *__restrict__ em_ray,
+__global__ void emergent_kernel(int64_t total, int32_t nl, int32_t ld, int64_t n, const int32_t *__restrict__ em_ray,
                                 const int32_t *__restrict__ em_site, const T *__restrict__ I, T *__restrict__ out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= total * nl) return;
   const int64_t e = t / nl;
   const int32_t l = (int32_t)(t - e * nl);
-  out[t] = I[((int64_t)em_ray[e] * n + em_site[e]) * nl + l];
+  out[t] = I[((int64_t)em_ray[e] * n + em_site[e]) * ld + l];
 }
 
 // With a ray-affinity table, c is the largest record count of one die and the
@@ -270,12 +271,12 @@ void launch_jreduce(hipStream_t s, const T *I, int32_t R, int64_t nn, const doub
 }
 
 template <typename T>
-void launch_emergent(hipStream_t s, int64_t total, int32_t nl, int64_t n, const int32_t *em_ray,
+void launch_emergent(hipStream_t s, int64_t total, int32_t nl, int32_t ld, int64_t n, const int32_t *em_ray,
                      const int32_t *em_site, const T *I, T *out) {
   const int64_t work = total * nl;
   if (work == 0) return;
-  hipLaunchKernelGGL(emergent_kernel<T>, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, total, nl, n, em_ray,
-                     em_site, I, out);
+  hipLaunchKernelGGL(emergent_kernel<T>, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, total, nl, ld, n,
+                     em_ray, em_site, I, out);
   VRT_HIP(hipGetLastError());
 }
 
@@ -287,9 +288,9 @@ template void launch_sweep<double>(hipStream_t, const int4 *, const RecF64 *, in
                                    int32_t, const int64_t *, int32_t, int32_t);
 template void launch_jreduce<float>(hipStream_t, const float *, int32_t, int64_t, const double *, float *);
 template void launch_jreduce<double>(hipStream_t, const double *, int32_t, int64_t, const double *, double *);
-template void launch_emergent<float>(hipStream_t, int64_t, int32_t, int64_t, const int32_t *, const int32_t *,
-                                     const float *, float *);
-template void launch_emergent<double>(hipStream_t, int64_t, int32_t, int64_t, const int32_t *, const int32_t *,
-                                      const double *, double *);
+template void launch_emergent<float>(hipStream_t, int64_t, int32_t, int32_t, int64_t, const int32_t *,
+                                     const int32_t *, const float *, float *);
+template void launch_emergent<double>(hipStream_t, int64_t, int32_t, int32_t, int64_t, const int32_t *,
+                                      const int32_t *, const double *, double *);
 
 }  // namespace vrt

@@ -647,16 +647,20 @@ void formal_solution_vjp(vrt_grid g, int32_t nl, const T *chi, const T *S, const
 // One Lambda iteration without the host read: reset the per-atmosphere
 // max-change words, assemble chi and S from S_line, sweep every ray, then Jbar
 // and the update of the active atmospheres.
+// The library's own chi, S, I_bottom and intensity rows have ld >= nl entries
+// (16-byte multiples, so the sweep moves whole vectors); the padding lanes
+// carry the continuum and are never read back.
 template <typename T>
-void enqueue_lambda_step(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const double *phi, const double *chi_L,
-                         const double *chi_c, const double *B, double eps, double *S_L, T *I, int32_t n_atm) {
+void enqueue_lambda_step(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, int32_t ld, const double *phi,
+                         const double *chi_L, const double *chi_c, const double *B, double eps, double *S_L, T *I,
+                         int32_t n_atm) {
   T *chi = g->d_nchi.as<T>(), *S = g->d_nS.as<T>(), *Ib = g->d_nIb.as<T>();
   auto *dS = g->d_dS.as<unsigned long long>();
   vrt::launch_zero_u64(s, n_atm, dS);
-  vrt::launch_nlte_assemble<T>(s, g->n, nl, phi, chi_L, chi_c, B, S_L, chi, S);
-  enqueue_sweep<T>(g, s, ex == VRT_EXEC_GRAPH ? VRT_EXEC_BATCHED : ex, nl, chi, S, Ib, nullptr, I);
-  vrt::launch_line_update<T>(s, g->n, nl, g->R, I, g->d_w.as<double>(), g->d_wlam.as<double>(), phi, B, eps, S_L,
-                             n_atm, g->d_atm_ptr.as<int64_t>(), g->d_active.as<int32_t>(), dS);
+  vrt::launch_nlte_assemble<T>(s, g->n, nl, ld, phi, chi_L, chi_c, B, S_L, chi, S);
+  enqueue_sweep<T>(g, s, ex == VRT_EXEC_GRAPH ? VRT_EXEC_BATCHED : ex, ld, chi, S, Ib, nullptr, I);
+  vrt::launch_line_update<T>(s, g->n, nl, ld, g->R, I, g->d_w.as<double>(), g->d_wlam.as<double>(), phi, B, eps,
+                             S_L, n_atm, g->d_atm_ptr.as<int64_t>(), g->d_active.as<int32_t>(), dS);
 }
 
 // Lambda iteration of n_atm independent atmospheres stored as one grid:
@@ -671,8 +675,10 @@ vrt_status two_level_solve(vrt_grid g, vrt_exec ex, int32_t nl, const double *wl
                            int32_t *n_iter) {
   vrt_ctx ctx = g->ctx;
   hipStream_t s = ctx->stream;
-  const size_t nn = (size_t)g->n * (size_t)nl;
-  T *I = intensity_buffer<T>(g, nl, nullptr);
+  constexpr int32_t per16 = 16 / (int32_t)sizeof(T);
+  const int32_t ld = (nl + per16 - 1) / per16 * per16;
+  const size_t nn = (size_t)g->n * (size_t)ld;
+  T *I = intensity_buffer<T>(g, ld, nullptr);
   VRT_HIP(hipStreamSynchronize(s));  // earlier work may still read the buffers replaced below
   g->d_nchi.alloc(nn * sizeof(T));
   g->d_nS.alloc(nn * sizeof(T));
@@ -706,7 +712,7 @@ vrt_status two_level_solve(vrt_grid g, vrt_exec ex, int32_t nl, const double *wl
     VRT_HIP(hipStreamSynchronize(s));
     if (bad) fail(VRT_E_GRID, "a site reads an upwind neighbour in another atmosphere");
   }
-  vrt::launch_broadcast<T>(s, g->n, nl, B, g->d_nIb.as<T>());
+  vrt::launch_broadcast<T>(s, g->n, ld, B, g->d_nIb.as<T>());
   const int pexec = ex == VRT_EXEC_PERSISTENT && g->kind == 0 ? 1 : 0;
   const bool use_graph = ex == VRT_EXEC_GRAPH || (ex == VRT_EXEC_PERSISTENT && g->kind != 0);
   if (use_graph) {
@@ -726,7 +732,7 @@ vrt_status two_level_solve(vrt_grid g, vrt_exec ex, int32_t nl, const double *wl
       VRT_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
       hipGraph_t graph = nullptr;
       try {
-        enqueue_lambda_step<T>(g, cs, VRT_EXEC_GRAPH, nl, phi, chi_L, chi_c, B, eps, S_L, I, n_atm);
+        enqueue_lambda_step<T>(g, cs, VRT_EXEC_GRAPH, nl, ld, phi, chi_L, chi_c, B, eps, S_L, I, n_atm);
       } catch (...) {
         (void)hipStreamEndCapture(cs, &graph);
         if (graph) (void)hipGraphDestroy(graph);
@@ -750,7 +756,7 @@ vrt_status two_level_solve(vrt_grid g, vrt_exec ex, int32_t nl, const double *wl
     if (use_graph)
       VRT_HIP(hipGraphLaunch(g->nlte_graph, s));
     else
-      enqueue_lambda_step<T>(g, s, ex, nl, phi, chi_L, chi_c, B, eps, S_L, I, n_atm);
+      enqueue_lambda_step<T>(g, s, ex, nl, ld, phi, chi_L, chi_c, B, eps, S_L, I, n_atm);
     VRT_HIP(hipMemcpyAsync(g->h_dS, g->d_dS.p, (size_t)n_atm * 8, hipMemcpyDeviceToHost, s));
     VRT_HIP(hipStreamSynchronize(s));
     if (pexec) {
@@ -783,6 +789,9 @@ vrt_status two_level_solve(vrt_grid g, vrt_exec ex, int32_t nl, const double *wl
       VRT_HIP(hipMemcpyAsync(g->d_active.p, active, (size_t)n_atm * 4, hipMemcpyHostToDevice, s));
   }
   g->last_I = I;
+  g->last_prec = sizeof(T) == 4 ? VRT_F32 : VRT_F64;
+  g->last_nl = nl;
+  g->last_ld = ld;
   return n_active == 0 ? VRT_OK : VRT_W_NOT_CONVERGED;
 }
 
@@ -828,6 +837,9 @@ void formal_solution(vrt_grid g, vrt_exec ex, int32_t nl, const void *chi_, cons
     VRT_HIP(hipGraphLaunch(it->second, ctx->stream));
   }
   g->last_I = I;
+  g->last_prec = sizeof(T) == 4 ? VRT_F32 : VRT_F64;
+  g->last_nl = nl;
+  g->last_ld = nl;
 }
 
 bool valid_prec(vrt_prec p) { return p == VRT_F64 || p == VRT_F32; }
@@ -1476,13 +1488,20 @@ vrt_status vrt_emergent_gather(vrt_grid g, vrt_prec prec, int32_t n_lambda, cons
     if (g->R == 0) fail(VRT_E_STATE, "rays not set");
     const void *I = I_rays ? I_rays : g->last_I;
     if (!I) fail(VRT_E_STATE, "no formal solution has run");
+    int32_t ld = n_lambda;
+    if (!I_rays) {
+      if (prec != g->last_prec || n_lambda != g->last_nl)
+        fail(VRT_E_ARG, "the last solution had %d wavelengths in %s precision", g->last_nl,
+             g->last_prec == VRT_F32 ? "single" : "double");
+      ld = g->last_ld;
+    }
     const int64_t total = g->em_off.back();
     if (total > 0 && !out) fail(VRT_E_ARG, "null output");
     if (prec == VRT_F32)
-      vrt::launch_emergent<float>(g->ctx->stream, total, n_lambda, g->n, g->d_em_ray.as<int32_t>(),
+      vrt::launch_emergent<float>(g->ctx->stream, total, n_lambda, ld, g->n, g->d_em_ray.as<int32_t>(),
                                   g->d_em_site.as<int32_t>(), static_cast<const float *>(I), static_cast<float *>(out));
     else
-      vrt::launch_emergent<double>(g->ctx->stream, total, n_lambda, g->n, g->d_em_ray.as<int32_t>(),
+      vrt::launch_emergent<double>(g->ctx->stream, total, n_lambda, ld, g->n, g->d_em_ray.as<int32_t>(),
                                    g->d_em_site.as<int32_t>(), static_cast<const double *>(I),
                                    static_cast<double *>(out));
     return VRT_OK;

@@ -193,7 +193,9 @@ struct vrt_grid_s {
 
   // scratch for per-ray intensities when the caller passes none
   vrt::DevBuf d_Iscr;
-  const void *last_I = nullptr;
+  const void *last_I = nullptr;  // intensities of the last solution (library scratch)
+  int last_prec = -1;            // their precision, wavelength count and row stride
+  int32_t last_nl = 0, last_ld = 0;
 
   // persistent sweep state: per-(ray, site) epoch stamps, the epoch, a device
   // error flag (a bounded wait gave up) and wave-item tables by width
@@ -265,7 +267,7 @@ void launch_sweep(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *
 template <typename T>
 void launch_jreduce(hipStream_t s, const T *I, int32_t R, int64_t nn, const double *w, T *J);
 template <typename T>
-void launch_emergent(hipStream_t s, int64_t total, int32_t nl, int64_t n, const int32_t *em_ray,
+void launch_emergent(hipStream_t s, int64_t total, int32_t nl, int32_t ld, int64_t n, const int32_t *em_ray,
                      const int32_t *em_site, const T *I, T *out);
 
 // ---- k_source.hip
@@ -285,15 +287,15 @@ void launch_persistent_sweep(hipStream_t s, const PersistItems &items, int32_t m
 
 // ---- k_nlte.hip
 template <typename T>
-void launch_nlte_assemble(hipStream_t s, int64_t n, int32_t nl, const double *phi, const double *chi_L,
+void launch_nlte_assemble(hipStream_t s, int64_t n, int32_t nl, int32_t ld, const double *phi, const double *chi_L,
                           const double *chi_c, const double *B, const double *S_L, T *chi, T *S);
-template <typename T> void launch_broadcast(hipStream_t s, int64_t n, int32_t nl, const double *v, T *out);
+template <typename T> void launch_broadcast(hipStream_t s, int64_t n, int32_t ld, const double *v, T *out);
 void launch_zero_u64(hipStream_t s, int32_t count, unsigned long long *p);
 // sets *bad to 1 if a selected upwind neighbour of a site lies in another atmosphere
 void launch_check_partition(hipStream_t s, int64_t n, int32_t R, const int32_t *k1, const int32_t *k2, int32_t n_atm,
                             const int64_t *atm_ptr, int32_t *bad);
 template <typename T>
-void launch_line_update(hipStream_t s, int64_t n, int32_t nl, int32_t R, const T *I, const double *w,
+void launch_line_update(hipStream_t s, int64_t n, int32_t nl, int32_t ld, int32_t R, const T *I, const double *w,
                         const double *wlam, const double *phi, const double *B, double eps, double *S_L,
                         int32_t n_atm, const int64_t *atm_ptr, const int32_t *active, unsigned long long *dS_bits);
 

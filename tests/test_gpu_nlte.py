@@ -143,3 +143,28 @@ def test_bad_arguments(v, ctx, case):
         v.two_level_solve(G, line.wlam, to_dev(line.phi, d), to_dev(line.chi_line, d), chi_c, B, 1e-2, S, max_iter=3)
     assert e.value.status == v.VRT_E_NUMERIC
     G.close()
+
+
+def test_emergent_gather_after_solve(v, ctx, case):
+    """The library keeps the intensities of the last iteration in rows padded to
+    16-byte multiples; the emergent gather reads them with that stride and
+    rejects a wavelength count or precision other than the solve's."""
+    flush("nlte emergent gather")
+    G, chi_c, B = _gpu_inputs(v, ctx, case)
+    line = case["line"]
+    d = torch.float64
+    S = B.clone()
+    v.two_level_solve(G, line.wlam, to_dev(line.phi, d), to_dev(line.chi_line, d), chi_c, B, 1e-2, S, max_iter=2,
+                      tol=0.0, sweep_dtype=torch.float32)
+    off, sites = G.emergent_index()
+    nl = len(line.wlam)
+    em = torch.empty((int(off[-1]), nl), dtype=torch.float32, device="cuda:0")
+    v.emergent_gather(G, em)
+    torch.cuda.synchronize()
+    assert torch.isfinite(em).all()
+    for bad_nl, dt in ((nl - 1, torch.float32), (nl, torch.float64)):
+        out = torch.empty((int(off[-1]), bad_nl), dtype=dt, device="cuda:0")
+        with pytest.raises(v.VrtError) as e:
+            v.emergent_gather(G, out)
+        assert e.value.status == v.VRT_E_ARG
+    G.close()

@@ -7,9 +7,10 @@
 // fused pass that forms the profile-weighted mean intensity
 //   Jbar = sum_lambda wlam phi sum_r w_r I_r
 // in double precision straight from the per-ray intensities (J per wavelength
-// never goes to memory), updates S_L <- (1 - eps) Jbar + eps B in double
-// precision and max-reduces |dS_L| / |S_L| for the convergence test, per
-// atmosphere when several independent atmospheres are solved as one grid.
+// never goes to memory; Jbar per site does, 8 bytes), then a per-site pass
+// updates S_L <- (1 - eps) Jbar + eps B in double precision and max-reduces
+// |dS_L| / |S_L| for the convergence test, per atmosphere when several
+// independent atmospheres are solved as one grid.
 
 #include "vrt_internal.h"
 
@@ -64,60 +65,91 @@ __device__ __forceinline__ int32_t atm_of(int64_t i, int32_t n_atm, const int64_
   return lo;
 }
 
-// One wavefront per site, lanes over wavelengths; each wave walks a contiguous
-// chunk of sites. Sites of atmosphere a are [atm_ptr[a], atm_ptr[a+1]); a wave
-// keeps the running maximum change of the atmosphere it is in and flushes it
-// with one atomic when it leaves that atmosphere. Inactive (converged)
-// atmospheres keep their S_line.
-// I rows have ld >= nl entries (only the first nl are line wavelengths).
+// Profile-weighted mean intensity Jbar = sum_lambda wlam phi sum_r w_r I_r, in
+// double precision. Half a wavefront (32 lanes) per site, each lane a 16-byte
+// vector of wavelengths; the ray sum runs in fixed order and the wavelength
+// sum is a fixed shuffle tree, so the result is deterministic. I rows have
+// ld >= nl entries (ld a multiple of the vector width; only the first nl are
+// line wavelengths).
 template <typename T>
-__global__ __launch_bounds__(256) void line_update_kernel(int64_t n, int32_t nl, int32_t ld, int32_t R,
-                                                          const T *__restrict__ I,
-                                                          const double *__restrict__ w,
-                                                          const double *__restrict__ wlam,
-                                                          const double *__restrict__ phi,
+__global__ __launch_bounds__(256) void jbar_kernel(int64_t n, int32_t nl, int32_t ld, int32_t R,
+                                                   const T *__restrict__ I, const double *__restrict__ w,
+                                                   const double *__restrict__ wlam, const double *__restrict__ phi,
+                                                   double *__restrict__ Jbar) {
+  constexpr int V = 16 / (int)sizeof(T);
+  typedef T VT __attribute__((ext_vector_type(V)));
+  const int lane = threadIdx.x & 63;
+  const int l32 = lane & 31;
+  const int64_t site = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 2 + (lane >> 5);
+  double part = 0.0;
+  if (site < n) {
+    const int64_t nn = n * ld;
+    for (int l = l32 * V; l < nl; l += 32 * V) {
+      double acc[V];
+#pragma unroll
+      for (int e = 0; e < V; ++e) acc[e] = 0.0;
+      for (int32_t r = 0; r < R; ++r) {
+        const VT x = *reinterpret_cast<const VT *>(I + (int64_t)r * nn + site * ld + l);
+        const double wr = w[r];
+#pragma unroll
+        for (int e = 0; e < V; ++e) acc[e] += wr * (double)x[e];
+      }
+#pragma unroll
+      for (int e = 0; e < V; ++e)
+        if (l + e < nl) part += wlam[l + e] * phi[site * nl + l + e] * acc[e];
+    }
+  }
+  // xor offsets below 32 stay inside each half-wavefront
+#pragma unroll
+  for (int o = 16; o >= 1; o >>= 1) part += __shfl_xor(part, o, 64);
+  if (site < n && l32 == 0) Jbar[site] = part;
+}
+
+// NaN-keeping maximum of non-negative changes (a NaN must reach the host)
+__device__ __forceinline__ double keep_nan_max(double m, double x) { return (x > m || x != x) ? x : m; }
+
+// One thread per site: S_line <- (1 - eps) Jbar + eps B for sites of active
+// atmospheres, and the largest |dS|/|S| per atmosphere (a block covers a
+// contiguous range of sites, hence of atmospheres; one atomic per block and
+// atmosphere it touches). Inactive (converged) atmospheres keep their S_line.
+__global__ __launch_bounds__(256) void line_update_kernel(int64_t n, const double *__restrict__ Jbar,
                                                           const double *__restrict__ B, double eps,
                                                           double *__restrict__ S_L, int32_t n_atm,
                                                           const int64_t *__restrict__ atm_ptr,
                                                           const int32_t *__restrict__ active,
                                                           unsigned long long *dS_bits) {
-  const int lane = threadIdx.x & 63;
-  const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-  const int64_t chunk = (n + waves - 1) / waves;
-  const int64_t i0 = wave * chunk, i1 = (i0 + chunk < n) ? i0 + chunk : n;
-  if (i0 >= i1) return;
-  const int64_t nn = n * ld;
-  int32_t atm = atm_of(i0, n_atm, atm_ptr);
-  double dmax = 0.0;
-  bool any = false;
-  for (int64_t i = i0; i < i1; ++i) {
-    while (i >= atm_ptr[atm + 1]) {
-      if (any && lane == 0) atomicMax(&dS_bits[atm], (unsigned long long)__double_as_longlong(dmax));
-      dmax = 0.0;
-      any = false;
-      ++atm;
+  __shared__ double red[4];
+  const int64_t b0 = (int64_t)blockIdx.x * blockDim.x;
+  if (b0 >= n) return;  // uniform over the block
+  const int64_t b1 = (b0 + blockDim.x < n) ? b0 + blockDim.x : n;
+  const int32_t a0 = atm_of(b0, n_atm, atm_ptr), a1 = atm_of(b1 - 1, n_atm, atm_ptr);
+  const int64_t i = b0 + threadIdx.x;
+  int32_t a = -1;
+  double d = -1.0;  // -1: no change recorded by this thread
+  if (i < n) {
+    a = atm_of(i, n_atm, atm_ptr);
+    if (active[a]) {
+      const double s_old = S_L[i];
+      const double s_new = (1.0 - eps) * Jbar[i] + eps * B[i];
+      d = fabs(s_new - s_old) / fabs(s_old);
+      S_L[i] = s_new;
     }
-    if (!active[atm]) continue;
-    double acc = 0.0;
-    for (int l = lane; l < nl; l += 64) {
-      const int64_t q = i * ld + l;
-      double j = 0.0;
-      for (int32_t r = 0; r < R; ++r) j += w[r] * (double)I[(int64_t)r * nn + q];
-      acc += wlam[l] * phi[i * nl + l] * j;
-    }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    const double s_old = S_L[i];
-    const double s_new = (1.0 - eps) * acc + eps * B[i];
-    const double d = fabs(s_new - s_old) / fabs(s_old);
-    // NaN compares false: keep it so the host sees a non-finite change
-    dmax = (d > dmax || d != d) ? d : dmax;
-    any = true;
-    if (lane == 0) S_L[i] = s_new;
   }
-  // non-negative doubles order like their bit patterns; NaN sorts above +inf
-  if (any && lane == 0) atomicMax(&dS_bits[atm], (unsigned long long)__double_as_longlong(dmax));
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int32_t k = a0; k <= a1; ++k) {
+    double m = (a == k) ? d : -1.0;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) m = keep_nan_max(m, __shfl_xor(m, o, 64));
+    if (lane == 0) red[wv] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double mb = red[0];
+      for (int q = 1; q < (int)(blockDim.x >> 6); ++q) mb = keep_nan_max(mb, red[q]);
+      // non-negative doubles order like their bit patterns; NaN sorts above +inf
+      if (!(mb < 0.0)) atomicMax(&dS_bits[k], (unsigned long long)__double_as_longlong(mb));
+    }
+    __syncthreads();
+  }
 }
 
 __global__ void check_partition_kernel(int64_t n, int32_t R, const int32_t *__restrict__ k1,
@@ -170,12 +202,15 @@ void launch_check_partition(hipStream_t s, int64_t n, int32_t R, const int32_t *
 template <typename T>
 void launch_line_update(hipStream_t s, int64_t n, int32_t nl, int32_t ld, int32_t R, const T *I, const double *w,
                         const double *wlam, const double *phi, const double *B, double eps, double *S_L,
-                        int32_t n_atm, const int64_t *atm_ptr, const int32_t *active, unsigned long long *dS_bits) {
+                        int32_t n_atm, const int64_t *atm_ptr, const int32_t *active, unsigned long long *dS_bits,
+                        double *Jbar) {
   if (n == 0) return;
-  int64_t blocks = (n + 3) / 4;
-  if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(line_update_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, n, nl, ld, R, I, w, wlam, phi,
-                     B, eps, S_L, n_atm, atm_ptr, active, dS_bits);
+  if (ld % (16 / (int)sizeof(T)) != 0 || (reinterpret_cast<uintptr_t>(I) & 15u) != 0)
+    throw Error(VRT_E_STATE, "line update needs 16-byte intensity rows");
+  hipLaunchKernelGGL(jbar_kernel<T>, dim3(nb(n, 8)), dim3(256), 0, s, n, nl, ld, R, I, w, wlam, phi, Jbar);
+  VRT_HIP(hipGetLastError());
+  hipLaunchKernelGGL(line_update_kernel, dim3(nb(n, 256)), dim3(256), 0, s, n, Jbar, B, eps, S_L, n_atm, atm_ptr,
+                     active, dS_bits);
   VRT_HIP(hipGetLastError());
 }
 
@@ -186,12 +221,12 @@ template void launch_nlte_assemble<double>(hipStream_t, int64_t, int32_t, int32_
 template void launch_broadcast<float>(hipStream_t, int64_t, int32_t, const double *, float *);
 template void launch_broadcast<double>(hipStream_t, int64_t, int32_t, const double *, double *);
 template void launch_line_update<float>(hipStream_t, int64_t, int32_t, int32_t, int32_t, const float *,
-                                        const double *,
-                                        const double *, const double *, const double *, double, double *, int32_t,
-                                        const int64_t *, const int32_t *, unsigned long long *);
+                                        const double *, const double *, const double *, const double *, double,
+                                        double *, int32_t, const int64_t *, const int32_t *, unsigned long long *,
+                                        double *);
 template void launch_line_update<double>(hipStream_t, int64_t, int32_t, int32_t, int32_t, const double *,
-                                         const double *,
-                                         const double *, const double *, const double *, double, double *, int32_t,
-                                         const int64_t *, const int32_t *, unsigned long long *);
+                                         const double *, const double *, const double *, const double *, double,
+                                         double *, int32_t, const int64_t *, const int32_t *, unsigned long long *,
+                                         double *);
 
 }  // namespace vrt

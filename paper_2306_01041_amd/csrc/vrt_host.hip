@@ -660,7 +660,8 @@ void enqueue_lambda_step(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, int
   vrt::launch_nlte_assemble<T>(s, g->n, nl, ld, phi, chi_L, chi_c, B, S_L, chi, S);
   enqueue_sweep<T>(g, s, ex == VRT_EXEC_GRAPH ? VRT_EXEC_BATCHED : ex, ld, chi, S, Ib, nullptr, I);
   vrt::launch_line_update<T>(s, g->n, nl, ld, g->R, I, g->d_w.as<double>(), g->d_wlam.as<double>(), phi, B, eps,
-                             S_L, n_atm, g->d_atm_ptr.as<int64_t>(), g->d_active.as<int32_t>(), dS);
+                             S_L, n_atm, g->d_atm_ptr.as<int64_t>(), g->d_active.as<int32_t>(), dS,
+                             g->d_jbar.as<double>());
 }
 
 // Lambda iteration of n_atm independent atmospheres stored as one grid:
@@ -683,6 +684,7 @@ vrt_status two_level_solve(vrt_grid g, vrt_exec ex, int32_t nl, const double *wl
   g->d_nchi.alloc(nn * sizeof(T));
   g->d_nS.alloc(nn * sizeof(T));
   g->d_nIb.alloc(nn * sizeof(T));
+  g->d_jbar.alloc((size_t)g->n * 8);
   g->d_dS.alloc((size_t)n_atm * 8);
   g->d_atm_ptr.alloc((size_t)(n_atm + 1) * 8);
   g->d_active.alloc((size_t)n_atm * 4 + 4);  // the last word is the partition-check flag
@@ -723,7 +725,8 @@ vrt_status two_level_solve(vrt_grid g, vrt_exec ex, int32_t nl, const double *wl
     // the graph also bakes in the scratch pointers, which the allocations above may have moved
     const bool same = g->nlte_graph && g->nlte_key == key && g->nlte_scratch[0] == g->d_nchi.p &&
                       g->nlte_scratch[1] == g->d_nS.p && g->nlte_scratch[2] == g->d_nIb.p &&
-                      g->nlte_scratch[3] == (const void *)I && g->nlte_scratch[4] == g->d_wlam.p;
+                      g->nlte_scratch[3] == (const void *)I && g->nlte_scratch[4] == g->d_wlam.p &&
+                      g->nlte_scratch[5] == g->d_jbar.p;
     if (!same) {
       if (g->nlte_graph) (void)hipGraphExecDestroy(g->nlte_graph);
       g->nlte_graph = nullptr;
@@ -748,6 +751,7 @@ vrt_status two_level_solve(vrt_grid g, vrt_exec ex, int32_t nl, const double *wl
       g->nlte_scratch[2] = g->d_nIb.p;
       g->nlte_scratch[3] = I;
       g->nlte_scratch[4] = g->d_wlam.p;
+      g->nlte_scratch[5] = g->d_jbar.p;
     }
   }
   for (int32_t a = 0; a < n_atm; ++a) n_iter[a] = 0;

@@ -206,7 +206,7 @@ struct vrt_grid_s {
 
   // two-level iteration scratch: chi, S, I_bottom in the sweep precision, the
   // profile weights, the max-change word and its pinned host copy
-  vrt::DevBuf d_nchi, d_nS, d_nIb, d_wlam, d_dS, d_atm_ptr, d_active;
+  vrt::DevBuf d_nchi, d_nS, d_nIb, d_wlam, d_dS, d_atm_ptr, d_active, d_jbar;
   unsigned long long *h_dS = nullptr;  // pinned, [n_atm]
   int32_t *h_active = nullptr;         // pinned, [n_atm]
   int32_t h_dS_cap = 0;
@@ -214,7 +214,7 @@ struct vrt_grid_s {
   std::tuple<int, int32_t, const void *, const void *, const void *, const void *, const void *, double, int, int32_t,
              const void *, const void *, const void *>
       nlte_key{};
-  const void *nlte_scratch[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  const void *nlte_scratch[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 
   // reverse sweep: per-ray dependents lists (absolute offsets [R][n+1], the
   // dependent site, and the weight and length of the line it reads), scratch
@@ -297,7 +297,8 @@ void launch_check_partition(hipStream_t s, int64_t n, int32_t R, const int32_t *
 template <typename T>
 void launch_line_update(hipStream_t s, int64_t n, int32_t nl, int32_t ld, int32_t R, const T *I, const double *w,
                         const double *wlam, const double *phi, const double *B, double eps, double *S_L,
-                        int32_t n_atm, const int64_t *atm_ptr, const int32_t *active, unsigned long long *dS_bits);
+                        int32_t n_atm, const int64_t *atm_ptr, const int32_t *active, unsigned long long *dS_bits,
+                        double *Jbar);
 
 // ---- k_adjoint.hip
 template <typename T>

@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--workload", choices=["c1", "c2", "c3"], default="c1",
                     help="c1: the formal solution (default line); c2: the two-level Lambda iteration on 1,048,576 "
                          "sites; c3: 48 atmospheres of 32,768-524,288 sites solved as one batch")
+    ap.add_argument("--accel", action="store_true",
+                    help="c2/c3: the Jacobi-accelerated iteration (local operator) instead of the plain one")
     ap.add_argument("--max-iter", type=int, default=None,
                     help="iteration cap of the c2/c3 Lambda iterations (default 1000 for c2, 100 for c3)")
     ap.add_argument("--mode", choices=["auto", "graph", "batched", "persistent"], default="auto",
@@ -465,7 +467,7 @@ def run_lambda(args):
     log(f"Lambda iteration, at most {max_iter} iterations")
     t1 = time.perf_counter()
     st, its, hist = v.two_level_solve_batched(G, off, wlam, phi, chi_L, chi_c, B, eps, S_L,
-                                              max_iter=max_iter, tol=1e-3, sweep_dtype=f32)
+                                              max_iter=max_iter, tol=1e-3, sweep_dtype=f32, accel=args.accel)
     torch.cuda.synchronize()
     total_s = time.perf_counter() - t1
     n_iter = int(np.max(its))
@@ -480,7 +482,7 @@ def run_lambda(args):
         "higher_is_better": True,
         "dtype": "f32",
         "data": "synthetic (seeded Bifrost-like stratified atmospheres, rejection-sampled Voronoi sites)",
-        "config": {"workload": ("two-level Lambda iteration, " +
+        "config": {"workload": (("accelerated (Jacobi) " if args.accel else "") + "two-level Lambda iteration, " +
                                 (f"{U.n} sites" if len(grids) == 1 else
                                  f"{len(grids)} atmospheres, {U.n} sites in total") +
                                 f", {nl} line wavelengths, {R} rays, eps {eps}, FP32 sweeps, FP64 update"),

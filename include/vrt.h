@@ -314,13 +314,22 @@ vrt_status vrt_lte_continuum_vjp(vrt_grid grid, vrt_prec prec, int32_t n_lambda,
  *   S_line    device [n] double: start value in, final value out.
  *   dS_hist   host [max_iter] or NULL: the change after each iteration.
  *   n_iter    host: iterations done.
+ *   accel     0: the plain Lambda iteration above. 1 (Voronoi grids): the
+ *             Jacobi-accelerated iteration, which divides each correction by
+ *             1 - (1 - eps) Lbar_i with Lbar_i = dJbar_i/dS_line,i =
+ *             sum_lambda wlam phi (chi_line phi / chi) Lambda*_ii and
+ *             Lambda*_ii = sum_r w_r sum_j w_j Psi_0(x_j) the weight of S_i in
+ *             I_i along each ray (Eq. 2, 5); computed once per call in double
+ *             precision. Same fixed point, far fewer iterations at small eps
+ *             (the cure Sect. 2.2 names for eps < 1e-3).
  * Blocks (one small device-to-host read per iteration). Returns VRT_OK when
  * converged, VRT_W_NOT_CONVERGED at the cap, VRT_E_NUMERIC on a non-finite
  * change. Voronoi and regular grids. */
 vrt_status vrt_two_level_solve(vrt_grid grid, vrt_prec sweep_prec, vrt_exec exec, int32_t n_lambda,
                                const double *wlam, const double *phi, const double *chi_line,
                                const double *chi_cont, const double *B, double eps, int32_t max_iter,
-                               double tol, double *S_line, double *dS_hist, int32_t *n_iter);
+                               double tol, int32_t accel, double *S_line, double *dS_hist,
+                               int32_t *n_iter);
 
 /* Many independent atmospheres solved as one batch (Sect. 3: the method is
  * applied per snapshot; a batch of uneven snapshots shares every launch).
@@ -342,8 +351,8 @@ vrt_status vrt_two_level_solve_batched(vrt_grid grid, vrt_prec sweep_prec, vrt_e
                                        int32_t n_lambda, const double *wlam, const double *phi,
                                        const double *chi_line, const double *chi_cont,
                                        const double *B, double eps, int32_t max_iter, double tol,
-                                       double *S_line, int32_t n_atm, const int64_t *atm_ptr,
-                                       double *dS_hist, int32_t *n_iter);
+                                       int32_t accel, double *S_line, int32_t n_atm,
+                                       const int64_t *atm_ptr, double *dS_hist, int32_t *n_iter);
 
 /* Wait for the context stream, then report and clear the grid's device error
  * flag: VRT_OK, or VRT_E_TIMEOUT if a bounded wait of a persistent sweep gave

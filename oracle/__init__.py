@@ -73,6 +73,9 @@ def lib():
         L.orc_fs_voronoi_vjp.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _d, _d, _d, _i32, _i32,
                                          _d, _d, _d, _d, _d, _d, _d, _d, _d, _d, _d, _d]
         L.orc_fs_voronoi_vjp.restype = ctypes.c_int
+        L.orc_lambda_diag.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _d, _i32, _i32, _d, _d, _d,
+                                      _d, _d]
+        L.orc_lambda_diag.restype = None
         L.orc_lte_vjp.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, ctypes.c_double, _d, _d, _d, _d, _d, _d, _d]
         _lib = L
     return _lib
@@ -191,6 +194,20 @@ def fs_voronoi(grid, dirs, ray_w, sel: Selection, chi, S, I_bottom, I_top=None, 
     if st != 0:
         raise MemoryError("orc_fs_voronoi failed")
     return (J, I) if keep_I else J
+
+
+def lambda_diag(grid, dirs, ray_w, sel: Selection, chi):
+    """Diagonal of the Lambda operator, dJ_i/dS_i [n, nl] (orc_lambda_diag)."""
+    ray_w = _c(ray_w, np.float64)
+    chi = _c(chi, np.float64)
+    n = grid.n
+    if chi.ndim == 1:
+        chi = chi[:, None]
+    nl = chi.shape[1]
+    out = np.empty((n, nl), np.float64)
+    lib().orc_lambda_diag(n, len(ray_w), nl, _p(ray_w, _d), _p(sel.k1, _i32), _p(sel.k2, _i32), _p(sel.w1, _d),
+                          _p(sel.ds1, _d), _p(sel.ds2, _d), _p(chi, _d), _p(out, _d))
+    return out
 
 
 def fs_regular(nx, ny, z, dx, dy, dirs, ray_w, chi, S, I_bottom, I_top=None, keep_I: bool = False):

@@ -6,7 +6,9 @@ Follows Sect. 2.1: the line source function of a two-level atom under complete
 redistribution is S_L = (1 - eps) Jbar + eps B (Eq. 3 with the profile-weighted
 mean intensity Jbar), J = Lambda[S] is one formal solution over all rays (Eq.
 4), and the plain Lambda iteration alternates the two until the largest
-relative change of S_L drops below a tolerance (about 1e-3, Sect. 3.3).
+relative change of S_L drops below a tolerance (about 1e-3, Sect. 3.3). The
+accelerated variant divides each correction by 1 - (1 - eps) Lbar*, with Lbar*
+the diagonal of the line operator (the local, Jacobi operator).
 
 With a grey continuum of opacity chi_c and thermal source B beside the line of
 opacity chi_L phi_lambda, the total opacity and source at each wavelength are
@@ -19,7 +21,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import fs_voronoi
+from . import fs_voronoi, lambda_diag
 
 
 def assemble(chi_c, chi_L, phi, B, S_L):
@@ -46,16 +48,43 @@ def lambda_step(grid, dirs, ray_w, sel, chi_c, chi_L, phi, wlam, B, eps, S_L, I_
     return S_new, dS
 
 
+def line_diag(grid, dirs, ray_w, sel, chi_c, chi_L, phi, wlam):
+    """Diagonal of the line operator, dJbar_i/dS_L,i = sum_lambda wlam phi (chi_L phi / chi) Lambda*_ii:
+    S_L,i enters S_lambda,i with the weight chi_L phi / chi (Eq. 3 with the
+    continuum), and Lambda*_ii carries it to J_lambda,i."""
+    chi = chi_c[:, None] + chi_L[:, None] * phi
+    Ld = lambda_diag(grid, dirs, ray_w, sel, chi)
+    return np.sum(wlam[None, :] * phi * (chi_L[:, None] * phi / chi) * Ld, axis=1)
+
+
+def ali_step(grid, dirs, ray_w, sel, chi_c, chi_L, phi, wlam, B, eps, S_L, Lbar, I_top=None):
+    """One Jacobi-accelerated step: S_L + [(1 - eps) Jbar + eps B - S_L] / [1 - (1 - eps) Lbar]."""
+    chi, S = assemble(chi_c, chi_L, phi, B, S_L)
+    nl = phi.shape[1]
+    Ib = np.repeat(B[:, None], nl, axis=1)
+    It = None if I_top is None else np.repeat(np.asarray(I_top)[:, None], nl, axis=1)
+    J = fs_voronoi(grid, dirs, ray_w, sel, chi, S, Ib, I_top=It)
+    S_fs = (1.0 - eps) * jbar(phi, wlam, J) + eps * B
+    S_new = S_L + (S_fs - S_L) / (1.0 - (1.0 - eps) * Lbar)
+    dS = float(np.max(np.abs(S_new - S_L) / np.abs(S_L)))
+    return S_new, dS
+
+
 def lambda_iterate(grid, dirs, ray_w, sel, chi_c, chi_L, phi, wlam, B, eps, max_iter=1000, tol=1e-3,
-                   S_start=None, I_top=None):
-    """Plain Lambda iteration from S_L = B (or ``S_start``) until max dS/S < tol.
+                   S_start=None, I_top=None, accel=False):
+    """Lambda iteration from S_L = B (or ``S_start``) until max dS/S < tol:
+    plain, or with the Jacobi (local-operator) acceleration when ``accel``.
 
     Returns (S_L, history of dS, number of iterations done, converged flag).
     """
     S_L = np.array(B if S_start is None else S_start, dtype=np.float64)
+    Lbar = line_diag(grid, dirs, ray_w, sel, chi_c, chi_L, phi, wlam) if accel else None
     hist = []
     for it in range(max_iter):
-        S_L, dS = lambda_step(grid, dirs, ray_w, sel, chi_c, chi_L, phi, wlam, B, eps, S_L, I_top)
+        if accel:
+            S_L, dS = ali_step(grid, dirs, ray_w, sel, chi_c, chi_L, phi, wlam, B, eps, S_L, Lbar, I_top)
+        else:
+            S_L, dS = lambda_step(grid, dirs, ray_w, sel, chi_c, chi_L, phi, wlam, B, eps, S_L, I_top)
         hist.append(dS)
         if not np.isfinite(dS):
             raise FloatingPointError("non-finite source-function change")
@@ -64,15 +93,13 @@ def lambda_iterate(grid, dirs, ray_w, sel, chi_c, chi_L, phi, wlam, B, eps, max_
     return S_L, np.array(hist), max_iter, False
 
 
-def dense_fixed_point(grid, dirs, ray_w, sel, chi_c, chi_L, phi, wlam, B, eps, I_top=None, groups=None):
-    """Fixed point of the Lambda iteration by a dense linear solve.
-
-    For fixed opacities Jbar is affine in S_L: Jbar = M S_L + c. c is Jbar at
-    S_L = 0, column j of M is Jbar(e_j) - c (one formal solution per column).
-    ``groups`` (optional list of index arrays) ties sites that share one
-    unknown, e.g. the sites of one plane of a horizontally uniform column.
-    Solves (1 - (1 - eps) M) S = (1 - eps) c + eps B.
-    """
+def jbar_matrix(grid, dirs, ray_w, sel, chi_c, chi_L, phi, wlam, B, I_top=None, groups=None):
+    """The affine map of the line source function to Jbar for fixed opacities,
+    Jbar = M S_L + c: c is Jbar at S_L = 0 and column j of M is Jbar(e_j) - c
+    (one formal solution per column). ``groups`` (optional list of index
+    arrays) ties sites that share one unknown, e.g. the sites of one plane of a
+    horizontally uniform column. Returns (M, c at the group representatives,
+    the representatives)."""
     n = grid.n
     nl = phi.shape[1]
     Ib = np.repeat(B[:, None], nl, axis=1)
@@ -92,8 +119,19 @@ def dense_fixed_point(grid, dirs, ray_w, sel, chi_c, chi_L, phi, wlam, B, eps, I
         e = np.zeros(n)
         e[gidx] = 1.0
         M[:, j] = (jb(e) - c)[rep]
+    return M, c[rep], rep
+
+
+def dense_fixed_point(grid, dirs, ray_w, sel, chi_c, chi_L, phi, wlam, B, eps, I_top=None, groups=None):
+    """Fixed point of the Lambda iteration by a dense linear solve of
+    (1 - (1 - eps) M) S = (1 - eps) c + eps B (see jbar_matrix)."""
+    n = grid.n
+    if groups is None:
+        groups = [np.array([i]) for i in range(n)]
+    M, c, rep = jbar_matrix(grid, dirs, ray_w, sel, chi_c, chi_L, phi, wlam, B, I_top=I_top, groups=groups)
+    m = len(groups)
     A = np.eye(m) - (1.0 - eps) * M
-    rhs = (1.0 - eps) * c[rep] + eps * B[rep]
+    rhs = (1.0 - eps) * c + eps * B[rep]
     sol = np.linalg.solve(A, rhs)
     S = np.empty(n)
     for j, gidx in enumerate(groups):

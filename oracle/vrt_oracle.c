@@ -552,3 +552,40 @@ void orc_lte_vjp(int64_t n, int32_t nl, const double *lam, double kappa0, const 
         g_rho[i] = gr;
     }
 }
+
+/* ---------------------------------------------------------------------------
+ * Local (diagonal) operator of the formal solution, for the accelerated
+ * Lambda iteration (the Jacobi operator the paper names as the cure for small
+ * eps, Sect. 2.2): along ray r, site i's intensity depends on its own source
+ * function only through the Psi_0 S_i term of each of its upwind lines
+ * (Eq. 2 with linear S, Eq. 5), and the upwind intensities never depend on
+ * S_i. Hence
+ *   Lambda*_ii = dJ_i/dS_i = sum_r w_r sum_j w_j Psi_0(x_j),
+ * with x_j = (chi_kj + chi_i) ds_j / 2, w_j the Eq. 5 weights (1 for a single
+ * line) and 0 at a ray's upwind-boundary sites. out [n][nl].
+ * ------------------------------------------------------------------------- */
+void orc_lambda_diag(int64_t n, int32_t n_rays, int32_t nl, const double *ray_w, const int32_t *k1,
+                     const int32_t *k2, const double *w1, const double *ds1, const double *ds2,
+                     const double *chi, double *out) {
+    for (int64_t q = 0; q < n * (int64_t)nl; ++q) out[q] = 0.0;
+    for (int32_t r = 0; r < n_rays; ++r) {
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t ri = (int64_t)r * n + i;
+            if (k1[ri] < 0) continue;
+            for (int32_t l = 0; l < nl; ++l) {
+                double E, pu, p0, sum = 0.0;
+                const double ci = chi[i * nl + l];
+                if (k2[ri] < 0) {
+                    orc_psi(0.5 * (chi[(int64_t)k1[ri] * nl + l] + ci) * ds1[ri], &E, &pu, &p0);
+                    sum = p0;
+                } else {
+                    orc_psi(0.5 * (chi[(int64_t)k1[ri] * nl + l] + ci) * ds1[ri], &E, &pu, &p0);
+                    sum = w1[ri] * p0;
+                    orc_psi(0.5 * (chi[(int64_t)k2[ri] * nl + l] + ci) * ds2[ri], &E, &pu, &p0);
+                    sum += (1.0 - w1[ri]) * p0;
+                }
+                out[i * nl + l] += ray_w[r] * sum;
+            }
+        }
+    }
+}

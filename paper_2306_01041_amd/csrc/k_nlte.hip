@@ -12,6 +12,7 @@
 // |dS_L| / |S_L| for the convergence test, per atmosphere when several
 // independent atmospheres are solved as one grid.
 
+#include "segment.h"
 #include "vrt_internal.h"
 
 namespace {
@@ -105,15 +106,71 @@ __global__ __launch_bounds__(256) void jbar_kernel(int64_t n, int32_t nl, int32_
   if (site < n && l32 == 0) Jbar[site] = part;
 }
 
+// Diagonal of the line operator for the accelerated (Jacobi) iteration:
+//   Lambda*_ii(lambda) = sum_r w_r sum_j w_j Psi_0(x_j),  x_j = (chi_kj + chi_i) ds_j / 2,
+// the weight of S_i in I_i along each ray (Eq. 2 with linear S, Eq. 5; upwind
+// intensities do not depend on S_i, boundary sites have none), and
+//   Lbar_i = sum_lambda wlam phi (chi_L phi / chi) Lambda*_ii(lambda),
+// the weight of S_L,i in Jbar_i (S_L enters S_lambda with chi_L phi / chi).
+// Opacities chi = chi_c + chi_L phi are formed here in double precision. One
+// wavefront per site, lanes over wavelengths, rays summed in fixed order.
+__global__ __launch_bounds__(256) void line_diag_kernel(int64_t n, int32_t nl, int32_t R,
+                                                        const double *__restrict__ ray_w,
+                                                        const int32_t *__restrict__ k1,
+                                                        const int32_t *__restrict__ k2,
+                                                        const double *__restrict__ w1,
+                                                        const double *__restrict__ ds1,
+                                                        const double *__restrict__ ds2,
+                                                        const double *__restrict__ chi_c,
+                                                        const double *__restrict__ chi_L,
+                                                        const double *__restrict__ phi,
+                                                        const double *__restrict__ wlam, double *__restrict__ Lbar) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < n; i += waves) {
+    double part = 0.0;
+    for (int l = lane; l < nl; l += 64) {
+      const double pl = phi[i * nl + l];
+      const double ci = chi_c[i] + chi_L[i] * pl;
+      double diag = 0.0;
+      for (int32_t r = 0; r < R; ++r) {
+        const int64_t ri = (int64_t)r * n + i;
+        const int32_t a = k1[ri], b = k2[ri];
+        if (a < 0) continue;
+        double E, pu, p0;
+        const double ca = chi_c[a] + chi_L[a] * phi[(int64_t)a * nl + l];
+        vrt::Seg<double>::weights(0.5 * (ca + ci) * ds1[ri], E, pu, p0);
+        double sum;
+        if (b < 0) {
+          sum = p0;
+        } else {
+          const double cb = chi_c[b] + chi_L[b] * phi[(int64_t)b * nl + l];
+          double p0b;
+          vrt::Seg<double>::weights(0.5 * (cb + ci) * ds2[ri], E, pu, p0b);
+          sum = w1[ri] * p0 + (1.0 - w1[ri]) * p0b;
+        }
+        diag += ray_w[r] * sum;
+      }
+      part += wlam[l] * pl * (chi_L[i] * pl / ci) * diag;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o, 64);
+    if (lane == 0) Lbar[i] = part;
+  }
+}
+
 // NaN-keeping maximum of non-negative changes (a NaN must reach the host)
 __device__ __forceinline__ double keep_nan_max(double m, double x) { return (x > m || x != x) ? x : m; }
 
 // One thread per site: S_line <- (1 - eps) Jbar + eps B for sites of active
-// atmospheres, and the largest |dS|/|S| per atmosphere (a block covers a
-// contiguous range of sites, hence of atmospheres; one atomic per block and
-// atmosphere it touches). Inactive (converged) atmospheres keep their S_line.
+// atmospheres (with Lbar, the accelerated form S_line + [(1 - eps) Jbar + eps B
+// - S_line] / [1 - (1 - eps) Lbar]), and the largest |dS|/|S| per atmosphere (a
+// block covers a contiguous range of sites, hence of atmospheres; one atomic
+// per block and atmosphere it touches). Inactive (converged) atmospheres keep
+// their S_line.
 __global__ __launch_bounds__(256) void line_update_kernel(int64_t n, const double *__restrict__ Jbar,
                                                           const double *__restrict__ B, double eps,
+                                                          const double *__restrict__ Lbar,
                                                           double *__restrict__ S_L, int32_t n_atm,
                                                           const int64_t *__restrict__ atm_ptr,
                                                           const int32_t *__restrict__ active,
@@ -130,7 +187,8 @@ __global__ __launch_bounds__(256) void line_update_kernel(int64_t n, const doubl
     a = atm_of(i, n_atm, atm_ptr);
     if (active[a]) {
       const double s_old = S_L[i];
-      const double s_new = (1.0 - eps) * Jbar[i] + eps * B[i];
+      const double s_fs = (1.0 - eps) * Jbar[i] + eps * B[i];
+      const double s_new = Lbar ? s_old + (s_fs - s_old) / (1.0 - (1.0 - eps) * Lbar[i]) : s_fs;
       d = fabs(s_new - s_old) / fabs(s_old);
       S_L[i] = s_new;
     }
@@ -203,14 +261,25 @@ template <typename T>
 void launch_line_update(hipStream_t s, int64_t n, int32_t nl, int32_t ld, int32_t R, const T *I, const double *w,
                         const double *wlam, const double *phi, const double *B, double eps, double *S_L,
                         int32_t n_atm, const int64_t *atm_ptr, const int32_t *active, unsigned long long *dS_bits,
-                        double *Jbar) {
+                        double *Jbar, const double *Lbar) {
   if (n == 0) return;
   if (ld % (16 / (int)sizeof(T)) != 0 || (reinterpret_cast<uintptr_t>(I) & 15u) != 0)
     throw Error(VRT_E_STATE, "line update needs 16-byte intensity rows");
   hipLaunchKernelGGL(jbar_kernel<T>, dim3(nb(n, 8)), dim3(256), 0, s, n, nl, ld, R, I, w, wlam, phi, Jbar);
   VRT_HIP(hipGetLastError());
-  hipLaunchKernelGGL(line_update_kernel, dim3(nb(n, 256)), dim3(256), 0, s, n, Jbar, B, eps, S_L, n_atm, atm_ptr,
-                     active, dS_bits);
+  hipLaunchKernelGGL(line_update_kernel, dim3(nb(n, 256)), dim3(256), 0, s, n, Jbar, B, eps, Lbar, S_L, n_atm,
+                     atm_ptr, active, dS_bits);
+  VRT_HIP(hipGetLastError());
+}
+
+void launch_line_diag(hipStream_t s, int64_t n, int32_t nl, int32_t R, const double *ray_w, const int32_t *k1,
+                      const int32_t *k2, const double *w1, const double *ds1, const double *ds2, const double *chi_c,
+                      const double *chi_L, const double *phi, const double *wlam, double *Lbar) {
+  if (n == 0) return;
+  int64_t blocks = (n + 3) / 4;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(line_diag_kernel, dim3((unsigned)blocks), dim3(256), 0, s, n, nl, R, ray_w, k1, k2, w1, ds1, ds2,
+                     chi_c, chi_L, phi, wlam, Lbar);
   VRT_HIP(hipGetLastError());
 }
 
@@ -223,10 +292,10 @@ template void launch_broadcast<double>(hipStream_t, int64_t, int32_t, const doub
 template void launch_line_update<float>(hipStream_t, int64_t, int32_t, int32_t, int32_t, const float *,
                                         const double *, const double *, const double *, const double *, double,
                                         double *, int32_t, const int64_t *, const int32_t *, unsigned long long *,
-                                        double *);
+                                        double *, const double *);
 template void launch_line_update<double>(hipStream_t, int64_t, int32_t, int32_t, int32_t, const double *,
                                          const double *, const double *, const double *, const double *, double,
                                          double *, int32_t, const int64_t *, const int32_t *, unsigned long long *,
-                                         double *);
+                                         double *, const double *);
 
 }  // namespace vrt

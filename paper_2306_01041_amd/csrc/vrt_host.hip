@@ -653,7 +653,7 @@ void formal_solution_vjp(vrt_grid g, int32_t nl, const T *chi, const T *S, const
 template <typename T>
 void enqueue_lambda_step(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, int32_t ld, const double *phi,
                          const double *chi_L, const double *chi_c, const double *B, double eps, double *S_L, T *I,
-                         int32_t n_atm) {
+                         int32_t n_atm, const double *Lbar) {
   T *chi = g->d_nchi.as<T>(), *S = g->d_nS.as<T>(), *Ib = g->d_nIb.as<T>();
   auto *dS = g->d_dS.as<unsigned long long>();
   vrt::launch_zero_u64(s, n_atm, dS);
@@ -661,7 +661,7 @@ void enqueue_lambda_step(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, int
   enqueue_sweep<T>(g, s, ex == VRT_EXEC_GRAPH ? VRT_EXEC_BATCHED : ex, ld, chi, S, Ib, nullptr, I);
   vrt::launch_line_update<T>(s, g->n, nl, ld, g->R, I, g->d_w.as<double>(), g->d_wlam.as<double>(), phi, B, eps,
                              S_L, n_atm, g->d_atm_ptr.as<int64_t>(), g->d_active.as<int32_t>(), dS,
-                             g->d_jbar.as<double>());
+                             g->d_jbar.as<double>(), Lbar);
 }
 
 // Lambda iteration of n_atm independent atmospheres stored as one grid:
@@ -672,8 +672,8 @@ void enqueue_lambda_step(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, int
 template <typename T>
 vrt_status two_level_solve(vrt_grid g, vrt_exec ex, int32_t nl, const double *wlam, const double *phi,
                            const double *chi_L, const double *chi_c, const double *B, double eps, int32_t max_iter,
-                           double tol, double *S_L, int32_t n_atm, const int64_t *atm_ptr, double *hist,
-                           int32_t *n_iter) {
+                           double tol, int32_t accel, double *S_L, int32_t n_atm, const int64_t *atm_ptr,
+                           double *hist, int32_t *n_iter) {
   vrt_ctx ctx = g->ctx;
   hipStream_t s = ctx->stream;
   constexpr int32_t per16 = 16 / (int32_t)sizeof(T);
@@ -715,18 +715,27 @@ vrt_status two_level_solve(vrt_grid g, vrt_exec ex, int32_t nl, const double *wl
     if (bad) fail(VRT_E_GRID, "a site reads an upwind neighbour in another atmosphere");
   }
   vrt::launch_broadcast<T>(s, g->n, ld, B, g->d_nIb.as<T>());
+  const double *Lbar = nullptr;
+  if (accel) {
+    if (g->kind != 0) fail(VRT_E_ARG, "the accelerated iteration needs a Voronoi grid");
+    g->d_lbar.alloc((size_t)g->n * 8);
+    vrt::launch_line_diag(s, g->n, nl, g->R, g->d_w.as<double>(), g->d_k1.as<int32_t>(), g->d_k2.as<int32_t>(),
+                          g->d_w1.as<double>(), g->d_ds1.as<double>(), g->d_ds2.as<double>(), chi_c, chi_L, phi,
+                          g->d_wlam.as<double>(), g->d_lbar.as<double>());
+    Lbar = g->d_lbar.as<double>();
+  }
   const int pexec = ex == VRT_EXEC_PERSISTENT && g->kind == 0 ? 1 : 0;
   const bool use_graph = ex == VRT_EXEC_GRAPH || (ex == VRT_EXEC_PERSISTENT && g->kind != 0);
   if (use_graph) {
     const auto key = std::make_tuple((int)sizeof(T), nl, (const void *)phi, (const void *)chi_L,
                                      (const void *)chi_c, (const void *)B, (const void *)S_L, eps, pexec, n_atm,
                                      (const void *)g->d_atm_ptr.p, (const void *)g->d_active.p,
-                                     (const void *)g->d_dS.p);
+                                     (const void *)g->d_dS.p, accel ? 1 : 0);
     // the graph also bakes in the scratch pointers, which the allocations above may have moved
     const bool same = g->nlte_graph && g->nlte_key == key && g->nlte_scratch[0] == g->d_nchi.p &&
                       g->nlte_scratch[1] == g->d_nS.p && g->nlte_scratch[2] == g->d_nIb.p &&
                       g->nlte_scratch[3] == (const void *)I && g->nlte_scratch[4] == g->d_wlam.p &&
-                      g->nlte_scratch[5] == g->d_jbar.p;
+                      g->nlte_scratch[5] == g->d_jbar.p && g->nlte_scratch[6] == (const void *)Lbar;
     if (!same) {
       if (g->nlte_graph) (void)hipGraphExecDestroy(g->nlte_graph);
       g->nlte_graph = nullptr;
@@ -735,7 +744,7 @@ vrt_status two_level_solve(vrt_grid g, vrt_exec ex, int32_t nl, const double *wl
       VRT_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
       hipGraph_t graph = nullptr;
       try {
-        enqueue_lambda_step<T>(g, cs, VRT_EXEC_GRAPH, nl, ld, phi, chi_L, chi_c, B, eps, S_L, I, n_atm);
+        enqueue_lambda_step<T>(g, cs, VRT_EXEC_GRAPH, nl, ld, phi, chi_L, chi_c, B, eps, S_L, I, n_atm, Lbar);
       } catch (...) {
         (void)hipStreamEndCapture(cs, &graph);
         if (graph) (void)hipGraphDestroy(graph);
@@ -752,6 +761,7 @@ vrt_status two_level_solve(vrt_grid g, vrt_exec ex, int32_t nl, const double *wl
       g->nlte_scratch[3] = I;
       g->nlte_scratch[4] = g->d_wlam.p;
       g->nlte_scratch[5] = g->d_jbar.p;
+      g->nlte_scratch[6] = Lbar;
     }
   }
   for (int32_t a = 0; a < n_atm; ++a) n_iter[a] = 0;
@@ -760,7 +770,7 @@ vrt_status two_level_solve(vrt_grid g, vrt_exec ex, int32_t nl, const double *wl
     if (use_graph)
       VRT_HIP(hipGraphLaunch(g->nlte_graph, s));
     else
-      enqueue_lambda_step<T>(g, s, ex, nl, ld, phi, chi_L, chi_c, B, eps, S_L, I, n_atm);
+      enqueue_lambda_step<T>(g, s, ex, nl, ld, phi, chi_L, chi_c, B, eps, S_L, I, n_atm, Lbar);
     VRT_HIP(hipMemcpyAsync(g->h_dS, g->d_dS.p, (size_t)n_atm * 8, hipMemcpyDeviceToHost, s));
     VRT_HIP(hipStreamSynchronize(s));
     if (pexec) {
@@ -1328,8 +1338,8 @@ vrt_status vrt_formal_solution(vrt_grid g, vrt_prec prec, vrt_exec exec, int32_t
 
 static vrt_status two_level_entry(vrt_grid g, vrt_prec prec, vrt_exec exec, int32_t n_lambda, const double *wlam,
                                   const double *phi, const double *chi_line, const double *chi_cont, const double *B,
-                                  double eps, int32_t max_iter, double tol, double *S_line, int32_t n_atm,
-                                  const int64_t *atm_ptr, double *dS_hist, int32_t *n_iter) {
+                                  double eps, int32_t max_iter, double tol, int32_t accel, double *S_line,
+                                  int32_t n_atm, const int64_t *atm_ptr, double *dS_hist, int32_t *n_iter) {
   if (!valid_prec(prec) || n_lambda <= 0 || !wlam || max_iter < 0 || !(tol >= 0.0) || !(eps >= 0.0 && eps <= 1.0))
     fail(VRT_E_ARG, "bad two-level arguments");
   if (exec != VRT_EXEC_PLAIN && exec != VRT_EXEC_BATCHED && exec != VRT_EXEC_GRAPH && exec != VRT_EXEC_PERSISTENT)
@@ -1343,25 +1353,26 @@ static vrt_status two_level_entry(vrt_grid g, vrt_prec prec, vrt_exec exec, int3
   for (int32_t a = 0; a < n_atm; ++a) n_iter[a] = 0;
   if (g->n == 0 || max_iter == 0) return max_iter == 0 ? VRT_W_NOT_CONVERGED : VRT_OK;
   if (!phi || !chi_line || !chi_cont || !B || !S_line) fail(VRT_E_ARG, "null device array");
+  if (accel != 0 && accel != 1) fail(VRT_E_ARG, "accel must be 0 or 1");
   if (prec == VRT_F32)
-    return two_level_solve<float>(g, exec, n_lambda, wlam, phi, chi_line, chi_cont, B, eps, max_iter, tol, S_line,
-                                  n_atm, atm_ptr, dS_hist, n_iter);
-  return two_level_solve<double>(g, exec, n_lambda, wlam, phi, chi_line, chi_cont, B, eps, max_iter, tol, S_line,
-                                 n_atm, atm_ptr, dS_hist, n_iter);
+    return two_level_solve<float>(g, exec, n_lambda, wlam, phi, chi_line, chi_cont, B, eps, max_iter, tol, accel,
+                                  S_line, n_atm, atm_ptr, dS_hist, n_iter);
+  return two_level_solve<double>(g, exec, n_lambda, wlam, phi, chi_line, chi_cont, B, eps, max_iter, tol, accel,
+                                 S_line, n_atm, atm_ptr, dS_hist, n_iter);
 }
 
 vrt_status vrt_two_level_solve(vrt_grid g, vrt_prec prec, vrt_exec exec, int32_t n_lambda, const double *wlam,
                                const double *phi, const double *chi_line, const double *chi_cont, const double *B,
-                               double eps, int32_t max_iter, double tol, double *S_line, double *dS_hist,
-                               int32_t *n_iter) {
+                               double eps, int32_t max_iter, double tol, int32_t accel, double *S_line,
+                               double *dS_hist, int32_t *n_iter) {
   if (!g) return VRT_E_ARG;
   return guarded(g->ctx, [&]() -> vrt_status {
     const int64_t ptr[2] = {0, g->n};
     int32_t it = 0;
     vrt_status st = VRT_OK;
     try {
-      st = two_level_entry(g, prec, exec, n_lambda, wlam, phi, chi_line, chi_cont, B, eps, max_iter, tol, S_line, 1,
-                           ptr, dS_hist, &it);
+      st = two_level_entry(g, prec, exec, n_lambda, wlam, phi, chi_line, chi_cont, B, eps, max_iter, tol, accel,
+                           S_line, 1, ptr, dS_hist, &it);
     } catch (...) {
       if (n_iter) *n_iter = it;
       throw;
@@ -1374,12 +1385,12 @@ vrt_status vrt_two_level_solve(vrt_grid g, vrt_prec prec, vrt_exec exec, int32_t
 vrt_status vrt_two_level_solve_batched(vrt_grid g, vrt_prec prec, vrt_exec exec, int32_t n_lambda,
                                        const double *wlam, const double *phi, const double *chi_line,
                                        const double *chi_cont, const double *B, double eps, int32_t max_iter,
-                                       double tol, double *S_line, int32_t n_atm, const int64_t *atm_ptr,
-                                       double *dS_hist, int32_t *n_iter) {
+                                       double tol, int32_t accel, double *S_line, int32_t n_atm,
+                                       const int64_t *atm_ptr, double *dS_hist, int32_t *n_iter) {
   if (!g) return VRT_E_ARG;
   return guarded(g->ctx, [&]() -> vrt_status {
-    return two_level_entry(g, prec, exec, n_lambda, wlam, phi, chi_line, chi_cont, B, eps, max_iter, tol, S_line,
-                           n_atm, atm_ptr, dS_hist, n_iter);
+    return two_level_entry(g, prec, exec, n_lambda, wlam, phi, chi_line, chi_cont, B, eps, max_iter, tol, accel,
+                           S_line, n_atm, atm_ptr, dS_hist, n_iter);
   });
 }
 

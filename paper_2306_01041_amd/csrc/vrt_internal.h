@@ -206,15 +206,15 @@ struct vrt_grid_s {
 
   // two-level iteration scratch: chi, S, I_bottom in the sweep precision, the
   // profile weights, the max-change word and its pinned host copy
-  vrt::DevBuf d_nchi, d_nS, d_nIb, d_wlam, d_dS, d_atm_ptr, d_active, d_jbar;
+  vrt::DevBuf d_nchi, d_nS, d_nIb, d_wlam, d_dS, d_atm_ptr, d_active, d_jbar, d_lbar;
   unsigned long long *h_dS = nullptr;  // pinned, [n_atm]
   int32_t *h_active = nullptr;         // pinned, [n_atm]
   int32_t h_dS_cap = 0;
   hipGraphExec_t nlte_graph = nullptr;
   std::tuple<int, int32_t, const void *, const void *, const void *, const void *, const void *, double, int, int32_t,
-             const void *, const void *, const void *>
+             const void *, const void *, const void *, int>
       nlte_key{};
-  const void *nlte_scratch[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  const void *nlte_scratch[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 
   // reverse sweep: per-ray dependents lists (absolute offsets [R][n+1], the
   // dependent site, and the weight and length of the line it reads), scratch
@@ -298,7 +298,11 @@ template <typename T>
 void launch_line_update(hipStream_t s, int64_t n, int32_t nl, int32_t ld, int32_t R, const T *I, const double *w,
                         const double *wlam, const double *phi, const double *B, double eps, double *S_L,
                         int32_t n_atm, const int64_t *atm_ptr, const int32_t *active, unsigned long long *dS_bits,
-                        double *Jbar);
+                        double *Jbar, const double *Lbar);
+// diagonal of the line operator per site (accelerated iteration)
+void launch_line_diag(hipStream_t s, int64_t n, int32_t nl, int32_t R, const double *ray_w, const int32_t *k1,
+                      const int32_t *k2, const double *w1, const double *ds1, const double *ds2, const double *chi_c,
+                      const double *chi_L, const double *phi, const double *wlam, double *Lbar);
 
 // ---- k_adjoint.hip
 template <typename T>

@@ -96,11 +96,11 @@ vrt_formal_solution = _sig("vrt_formal_solution", _st, [_vp, ctypes.c_int32, cty
                                                         _vp, _vp, _vp, _vp])
 vrt_two_level_solve = _sig("vrt_two_level_solve", _st, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _d, _vp,
                                                         _vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,
-                                                        ctypes.c_double, _vp, _d, _i32])
+                                                        ctypes.c_double, ctypes.c_int32, _vp, _d, _i32])
 vrt_two_level_solve_batched = _sig("vrt_two_level_solve_batched", _st,
                                    [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _d, _vp, _vp, _vp, _vp,
-                                    ctypes.c_double, ctypes.c_int32, ctypes.c_double, _vp, ctypes.c_int32, _i64, _d,
-                                    _i32])
+                                    ctypes.c_double, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _vp,
+                                    ctypes.c_int32, _i64, _d, _i32])
 vrt_formal_solution_vjp = _sig("vrt_formal_solution_vjp", _st, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp,
                                                                 _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                                                 ctypes.c_int32])
@@ -371,7 +371,7 @@ def autotune(grid: Grid, chi, S, J, I_bottom=None, I_top=None, I_rays=None, reps
 
 
 def two_level_solve(grid: Grid, wlam, phi, chi_line, chi_cont, B, eps, S_line, max_iter=1000, tol=1e-3,
-                    sweep_dtype=None, exec_mode=VRT_EXEC_GRAPH):
+                    sweep_dtype=None, exec_mode=VRT_EXEC_GRAPH, accel=False):
     """Lambda iteration of the two-level line; S_line (device float64 [n]) is updated in place.
 
     Returns (status, n_iter, dS history as numpy). status is VRT_OK or VRT_W_NOT_CONVERGED.
@@ -391,12 +391,13 @@ def two_level_solve(grid: Grid, wlam, phi, chi_line, chi_cont, B, eps, S_line, m
     prec = VRT_F32 if sweep_dtype == torch.float32 else VRT_F64
     st = grid.ctx.check(vrt_two_level_solve(grid.handle, prec, int(exec_mode), nl, _p(wlam, _d), _dev(phi),
                                             _dev(chi_line), _dev(chi_cont), _dev(B), float(eps), int(max_iter),
-                                            float(tol), _dev(S_line), _p(hist, _d), ctypes.byref(it)))
+                                            float(tol), 1 if accel else 0, _dev(S_line), _p(hist, _d),
+                                            ctypes.byref(it)))
     return st, it.value, hist[: it.value].copy()
 
 
 def two_level_solve_batched(grid: Grid, atm_ptr, wlam, phi, chi_line, chi_cont, B, eps, S_line, max_iter=1000,
-                            tol=1e-3, sweep_dtype=None, exec_mode=VRT_EXEC_GRAPH):
+                            tol=1e-3, sweep_dtype=None, exec_mode=VRT_EXEC_GRAPH, accel=False):
     """Lambda iteration of independent atmospheres stored as one grid (atmosphere a owns
     sites atm_ptr[a]:atm_ptr[a+1]); each converges and freezes on its own.
 
@@ -421,8 +422,8 @@ def two_level_solve_batched(grid: Grid, atm_ptr, wlam, phi, chi_line, chi_cont, 
     prec = VRT_F32 if sweep_dtype == torch.float32 else VRT_F64
     st = grid.ctx.check(vrt_two_level_solve_batched(grid.handle, prec, int(exec_mode), nl, _p(wlam, _d), _dev(phi),
                                                     _dev(chi_line), _dev(chi_cont), _dev(B), float(eps),
-                                                    int(max_iter), float(tol), _dev(S_line), n_atm, _p(ptr, _i64),
-                                                    _p(hist, _d), _p(its, _i32)))
+                                                    int(max_iter), float(tol), 1 if accel else 0, _dev(S_line),
+                                                    n_atm, _p(ptr, _i64), _p(hist, _d), _p(its, _i32)))
     return st, its, hist[: int(its.max(initial=0))].copy()
 
 

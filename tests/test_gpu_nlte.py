@@ -168,3 +168,52 @@ def test_emergent_gather_after_solve(v, ctx, case):
             v.emergent_gather(G, out)
         assert e.value.status == v.VRT_E_ARG
     G.close()
+
+
+@pytest.mark.parametrize("prec,eps", [("f64", 1e-4), ("f32", 1e-2)])
+def test_accelerated_iterates_match_oracle(v, ctx, case, prec, eps):
+    """Jacobi-accelerated iteration (diagonal of the line operator, computed on
+    each side from its own selection and segment weights): iterates after 1, 2
+    and 10 steps against the oracle, and the iteration count at eps = 1e-4.
+
+    The accelerated correction is divided by 1 - (1 - eps) Lbar, which magnifies
+    any rounding difference in Jbar by kappa = 1 / (1 - (1 - eps) Lbar) (up to
+    ~1/eps in the line core; 2.3e3 here at eps = 1e-4). The bounds are therefore
+    kappa_max times the precision of Jbar per step: 1e-14 for FP64 sweeps,
+    1e-6 for FP32 sweeps (checked at eps = 1e-2, kappa_max ~ 1e2)."""
+    flush(f"nlte accelerated prec={prec} eps={eps}")
+    G, chi_c, B = _gpu_inputs(v, ctx, case)
+    line = case["line"]
+    d = torch.float64
+    phi, chi_L = to_dev(line.phi, d), to_dev(line.chi_line, d)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    Lbar = onl.line_diag(case["g"], case["dirs"], case["w"], case["sel"], case["chi_c"], line.chi_line, line.phi,
+                         line.wlam)
+    kappa = float(np.max(1.0 / (1.0 - (1.0 - eps) * Lbar)))
+    unit = 1e-14 if prec == "f64" else 1e-6
+    S = B.clone()
+    S_o = case["B"].copy()
+    done = 0
+    for k in (1, 2, 10):
+        st, nit, hist = v.two_level_solve(G, line.wlam, phi, chi_L, chi_c, B, eps, S, max_iter=k - done, tol=0.0,
+                                          sweep_dtype=dt, accel=True)
+        S_o, hist_o, _, _ = onl.lambda_iterate(case["g"], case["dirs"], case["w"], case["sel"], case["chi_c"],
+                                                line.chi_line, line.phi, line.wlam, case["B"], eps,
+                                                max_iter=k - done, tol=0.0, S_start=S_o, accel=True)
+        torch.cuda.synchronize()
+        err = relerr(S.cpu().numpy(), S_o)
+        flush(f"  after {k} iterations: max rel err {err:.2e} (bound {unit * kappa * k:.1e}, kappa_max {kappa:.0f})")
+        assert err <= unit * kappa * k
+        # the changes are relative quantities of any size (the first accelerated step is large)
+        assert np.all(np.abs(hist - hist_o) <= unit * kappa * k * np.maximum(1.0, np.abs(hist_o)))
+        done = k
+    if prec == "f64":
+        S = B.clone()
+        st, nit, hist = v.two_level_solve(G, line.wlam, phi, chi_L, chi_c, B, eps, S, max_iter=500, tol=1e-3,
+                                          sweep_dtype=torch.float64, accel=True)
+        _, hist_o, nit_o, ok = onl.lambda_iterate(case["g"], case["dirs"], case["w"], case["sel"], case["chi_c"],
+                                                   line.chi_line, line.phi, line.wlam, case["B"], eps, max_iter=500,
+                                                   tol=1e-3, accel=True)
+        flush(f"  converged in {nit} iterations (oracle {nit_o})")
+        assert ok and st == v.VRT_OK and nit == nit_o
+    G.close()

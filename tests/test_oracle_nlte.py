@@ -113,3 +113,59 @@ def test_sqrt_eps_law_eps_1e4(orc):
     assert np.all(np.diff(errs) < 0)
     assert np.all(errs[:-1] / errs[1:] > 2.0)
     assert errs[-1] < 0.05
+
+
+def test_lambda_diag_is_the_diagonal_of_lambda(orc, small):
+    """dJ_i/dS_i by brute force: the formal solution of a unit source at one site
+    (no boundary radiation) has J_i = Lambda_ii at that site."""
+    atm, g, dirs, w = small
+    sel = orc.select(g, dirs)
+    rng = np.random.default_rng(11)
+    nl = 3
+    chi = 10 ** rng.uniform(-7.0, -4.0, (g.n, nl))
+    Ld = orc.lambda_diag(g, dirs, w, sel, chi)
+    zero = np.zeros((g.n, nl))
+    for i in rng.choice(g.n, 40, replace=False):
+        S = zero.copy()
+        S[i] = 1.0
+        J = orc.fs_voronoi(g, dirs, w, sel, chi, S, zero)
+        assert np.allclose(J[i], Ld[i], rtol=1e-13, atol=0), (i, J[i], Ld[i])
+    # boundary sites of every ray contribute nothing, interior ones are in (0, 1)
+    assert np.all(Ld >= 0) and np.all(Ld < 1)
+
+
+def test_line_diag_is_the_diagonal_of_the_jbar_map(orc):
+    atm = synth.make_atmosphere(60, seed=8)
+    g = synth.voronoi_neighbours(atm.xyz, atm.box.lo, atm.box.hi)
+    dirs, w = synth.gauss_legendre_quadrature()
+    sel = orc.select(g, dirs)
+    rng = np.random.default_rng(12)
+    phi, wl = _line(g, 7, 13)
+    chi_c = 10 ** rng.uniform(-7, -6, g.n)
+    chi_L = 10 ** rng.uniform(-6, -5, g.n)
+    B = rng.uniform(1.0, 3.0, g.n)
+    M, _, _ = nlte.jbar_matrix(g, dirs, w, sel, chi_c, chi_L, phi, wl, B)
+    Lbar = nlte.line_diag(g, dirs, w, sel, chi_c, chi_L, phi, wl)
+    assert np.max(np.abs(np.diag(M) - Lbar)) <= 1e-13 * np.max(np.abs(Lbar))
+
+
+@pytest.mark.parametrize("eps", [1e-2, 1e-4])
+def test_accelerated_iteration_reaches_dense_fixed_point(orc, small, eps):
+    """The Jacobi-accelerated iteration has the same fixed point and gets there
+    in fewer iterations than the plain one."""
+    atm, g, dirs, w = small
+    sel = orc.select(g, dirs)
+    rng = np.random.default_rng(1)
+    phi, wl = _line(g, 5, 2)
+    chi_c = 10 ** rng.uniform(-7, -6, g.n)
+    chi_L = 10 ** rng.uniform(-5, -4, g.n)
+    B = rng.uniform(1.0, 3.0, g.n)
+    S_dense = nlte.dense_fixed_point(g, dirs, w, sel, chi_c, chi_L, phi, wl, B, eps)
+    S_a, hist_a, nit_a, ok_a = nlte.lambda_iterate(g, dirs, w, sel, chi_c, chi_L, phi, wl, B, eps, max_iter=3000,
+                                                   tol=1e-12, accel=True)
+    assert ok_a
+    assert np.max(np.abs(S_a - S_dense) / S_dense) < 1e-9
+    _, _, nit_p, _ = nlte.lambda_iterate(g, dirs, w, sel, chi_c, chi_L, phi, wl, B, eps, max_iter=3000, tol=1e-6)
+    _, _, nit_a6, _ = nlte.lambda_iterate(g, dirs, w, sel, chi_c, chi_L, phi, wl, B, eps, max_iter=3000, tol=1e-6,
+                                          accel=True)
+    assert nit_a6 < nit_p

@@ -16,6 +16,8 @@ Printed as one JSON line with, besides the headline value:
   adjoint      forward and reverse-sweep times of the differentiable emergent
                intensity (32 wavelengths 500-700 nm on the same grid) and
                their ratio;
+  regular_grid the same formal solution on the regular 128 x 128 x 256 grid
+               (short characteristics), FP32 graph-launched and plain FP64;
   cpu_baseline the FP64 CPU oracle timed on this host on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--sites N] [--no-cpu]
@@ -79,6 +81,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU baseline")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing")
+    ap.add_argument("--no-regular", action="store_true", help="skip the regular-grid timing")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the grid's default launch layout (for profiler runs that average over dispatches)")
     ap.add_argument("--workload", choices=["c1", "c2", "c3"], default="c1",
@@ -297,6 +300,45 @@ def main():
             f"emergent intensities: {fw2:.3f} / {bw2:.3f} ms")
         del Tq, rq, target, T_tgt
 
+    # the regular 128 x 128 x 256 grid of the same recipe (short characteristics):
+    # FP32 graph-launched and plain FP64, 64 wavelengths, 24 rays
+    regular = None
+    if not args.no_regular:
+        del chi, S, J
+        nx = ny = 128
+        nz = 256
+        box = atm.box
+        dxr = (box.hi[0] - box.lo[0]) / nx
+        dyr = (box.hi[1] - box.lo[1]) / ny
+        zr = box.lo[2] + (box.hi[2] - box.lo[2]) * np.arange(nz) / (nz - 1)
+        X, Y, Z = np.meshgrid(box.lo[0] + dxr * np.arange(nx), box.lo[1] + dyr * np.arange(ny), zr, indexing="xy")
+        xyz = np.stack([a.transpose(2, 0, 1).ravel() for a in (X, Y, Z)], 1)  # site (k * ny + j) * nx + i
+        atr = synth.make_atmosphere(len(xyz), seed=seed, xyz=xyz)
+        Gr = v.Grid.regular(ctx, nx, ny, zr, dxr, dyr)
+        Gr.set_rays(dirs, w)
+        Tr, rr = torch.as_tensor(atr.T, device=dev), torch.as_tensor(atr.rho, device=dev)
+        ur = len(xyz) * R * nl
+        regular = {"workload": f"regular grid {nx}x{ny}x{nz}, {nl} wavelengths 400-900 nm, {R} rays, short "
+                               f"characteristics with bilinear upwind interpolation"}
+        for name, dt, mode, reps in (("fp32_graph", torch.float32, v.VRT_EXEC_GRAPH, 5),
+                                     ("fp64_plain", torch.float64, v.VRT_EXEC_PLAIN, 2)):
+            chr_ = torch.empty((len(xyz), nl), dtype=dt, device=dev)
+            Sr = torch.empty_like(chr_)
+            Jr = torch.empty_like(chr_)
+            v.lte_continuum(Gr, lam, atr.kappa0, Tr, rr, chr_, Sr)
+            v.formal_solution(Gr, chr_, Sr, Jr, exec_mode=mode)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                v.formal_solution(Gr, chr_, Sr, Jr, exec_mode=mode)
+            torch.cuda.synchronize()
+            ms_r = (time.perf_counter() - t0) * 1e3 / reps
+            regular[name] = {"ms": round(ms_r, 3), "updates_per_s": ur / (ms_r * 1e-3)}
+            log(f"regular grid {name}: {ms_r:.2f} ms -> {ur / (ms_r * 1e-3):.3e} updates/s")
+            del chr_, Sr, Jr
+        regular["speedup_fp32_graph"] = round(regular["fp64_plain"]["ms"] / regular["fp32_graph"]["ms"], 2)
+        Gr.close()
+
     # CPU oracle on a bounded sample: the same formal solution (all sites, rays and
     # wavelengths), repeated until about 10 s of host time have been spent
     cpu = None
@@ -347,6 +389,7 @@ def main():
         "whole_step_effective_GBs": round(updates * (20.0 + 20.0 / nl) / (ms_step * 1e-3) / 1e9, 1),
         "fp64_plain": fp64,
         "adjoint": adjoint,
+        "regular_grid": regular,
         "cpu_baseline": cpu,
         "setup_s": round(setup_s, 3),
         "tuning": tuning,

@@ -11,35 +11,61 @@
 // One launch handles one plane step of a contiguous block of rays. The
 // bilinear weights are the same for every point of a plane, so lanes differ
 // only in wavelength and point; each wavefront covers 64/C points of one ray
-// with C lanes striding over wavelengths.
+// with C lanes striding over wavelengths, V wavelengths (16 bytes) per lane
+// when the rows allow it.
 
 #include "segment.h"
 #include "vrt_internal.h"
 
 namespace {
 
-__device__ __forceinline__ void periodic_cell(double q, double d, int32_t np, int32_t &i0, int32_t &i1, double &t) {
-  const double f = q / d;
-  const double fl = floor(f);
-  t = f - fl;
-  int64_t a = (int64_t)fl % np;
-  if (a < 0) a += np;
-  i0 = (int32_t)a;
-  i1 = (int32_t)((a + 1) % np);
+// Lane-vector of V elements (16-byte loads and stores when V > 1).
+template <typename T, int V> struct RLane {
+  typedef T type __attribute__((ext_vector_type(V)));
+  static __device__ __forceinline__ type load(const T *p) { return *reinterpret_cast<const type *>(p); }
+  static __device__ __forceinline__ void store(T *p, const type &v) { *reinterpret_cast<type *>(p) = v; }
+};
+template <typename T> struct RLane<T, 1> {
+  typedef T type;
+  static __device__ __forceinline__ type load(const T *p) { return *p; }
+  static __device__ __forceinline__ void store(T *p, const type &v) { *p = v; }
+};
+template <typename T, int V> __device__ __forceinline__ T el(const typename RLane<T, V>::type &v, int k) {
+  if constexpr (V == 1) return v;
+  else return v[k];
+}
+template <typename T, int V> __device__ __forceinline__ void set_el(typename RLane<T, V>::type &v, int k, T x) {
+  if constexpr (V == 1) v = x;
+  else v[k] = x;
 }
 
-template <typename T, int C>
+// The upwind point of every grid point of a plane is the point itself shifted
+// by -ds (mx, my); on a uniform grid the cell offset and the bilinear weights
+// are therefore the same for the whole plane: q / d = i + shift + t with an
+// integer shift and 0 <= t < 1.
+__device__ __forceinline__ void plane_shift(double q_over_d, int32_t np, int32_t &shift, double &t) {
+  const double fl = floor(q_over_d);
+  t = q_over_d - fl;
+  int64_t a = (int64_t)fl % np;
+  if (a < 0) a += np;
+  shift = (int32_t)a;  // in [0, np)
+}
+
+// C lanes per point, V consecutive wavelengths per lane (nl a multiple of V).
+template <typename T, int C, int V>
 __global__ __launch_bounds__(256) void regular_kernel(int32_t step, int32_t ray_begin, int32_t ray_count, int32_t nx,
                                                       int32_t ny, int32_t nz, double dx, double dy,
                                                       const double *__restrict__ z, const double *__restrict__ dirs,
                                                       int32_t nl, const T *__restrict__ chi, const T *__restrict__ S,
                                                       const T *__restrict__ Ibot, const T *__restrict__ Itop, T *I) {
+  using L = RLane<T, V>;
+  using VT = typename L::type;
   constexpr int SPW = 64 / C;
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const int64_t plane = (int64_t)nx * ny;
   const int64_t item = wave * SPW + lane / C;
-  const int l0 = lane % C;
+  const int l0 = (lane % C) * V;
   if (item >= plane * ray_count) return;
   const int32_t r = ray_begin + (int32_t)(item / plane);
   const int64_t p = item - (int64_t)(r - ray_begin) * plane;
@@ -51,37 +77,54 @@ __global__ __launch_bounds__(256) void regular_kernel(int32_t step, int32_t ray_
   T *Iray = I + (int64_t)r * n * nl;
   const int64_t me = ((int64_t)k * plane + p) * nl;
   if (step == 0) {
-    for (int l = l0; l < nl; l += C) {
-      T v = T(0);
-      if (up) v = Ibot[me + l];
-      else if (Itop) v = Itop[me + l];
-      Iray[me + l] = v;
+    for (int l = l0; l < nl; l += C * V) {
+      VT v;
+      if (up) v = L::load(Ibot + me + l);
+      else if (Itop) v = L::load(Itop + me + l);
+      else v = VT(T(0));
+      L::store(Iray + me + l, v);
     }
     return;
   }
   const int32_t ku = up ? k - 1 : k + 1;
   const double ds = fabs(z[k] - z[ku]) / fabs(mz);
-  int32_t ix0, ix1, iy0, iy1;
+  int32_t sx, sy;
   double tx, ty;
-  periodic_cell((double)i * dx - ds * mx, dx, nx, ix0, ix1, tx);
-  periodic_cell((double)j * dy - ds * my, dy, ny, iy0, iy1, ty);
+  plane_shift(-ds * mx / dx, nx, sx, tx);
+  plane_shift(-ds * my / dy, ny, sy, ty);
+  int32_t ix0 = i + sx, iy0 = j + sy;
+  if (ix0 >= nx) ix0 -= nx;
+  if (iy0 >= ny) iy0 -= ny;
+  const int32_t ix1 = ix0 + 1 == nx ? 0 : ix0 + 1, iy1 = iy0 + 1 == ny ? 0 : iy0 + 1;
   const T a00 = (T)((1.0 - tx) * (1.0 - ty)), a10 = (T)(tx * (1.0 - ty));
   const T a01 = (T)((1.0 - tx) * ty), a11 = (T)(tx * ty);
   const int64_t pu0 = (int64_t)ku * plane;
   const int64_t c00 = (pu0 + (int64_t)iy0 * nx + ix0) * nl, c10 = (pu0 + (int64_t)iy0 * nx + ix1) * nl;
   const int64_t c01 = (pu0 + (int64_t)iy1 * nx + ix0) * nl, c11 = (pu0 + (int64_t)iy1 * nx + ix1) * nl;
   const T h = (T)(0.5 * ds);
-  for (int l = l0; l < nl; l += C) {
-    const T Iu = a00 * Iray[c00 + l] + a10 * Iray[c10 + l] + a01 * Iray[c01 + l] + a11 * Iray[c11 + l];
-    const T Su = a00 * S[c00 + l] + a10 * S[c10 + l] + a01 * S[c01 + l] + a11 * S[c11 + l];
-    const T cu = a00 * chi[c00 + l] + a10 * chi[c10 + l] + a01 * chi[c01 + l] + a11 * chi[c11 + l];
-    T E, pw, p0;
-    vrt::Seg<T>::weights((cu + chi[me + l]) * h, E, pw, p0);
-    Iray[me + l] = E * Iu + pw * Su + p0 * S[me + l];
+  for (int l = l0; l < nl; l += C * V) {
+    const VT i00 = L::load(Iray + c00 + l), i10 = L::load(Iray + c10 + l);
+    const VT i01 = L::load(Iray + c01 + l), i11 = L::load(Iray + c11 + l);
+    const VT s00 = L::load(S + c00 + l), s10 = L::load(S + c10 + l);
+    const VT s01 = L::load(S + c01 + l), s11 = L::load(S + c11 + l);
+    const VT x00 = L::load(chi + c00 + l), x10 = L::load(chi + c10 + l);
+    const VT x01 = L::load(chi + c01 + l), x11 = L::load(chi + c11 + l);
+    const VT cm = L::load(chi + me + l), sm = L::load(S + me + l);
+    VT out;
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      const T Iu = a00 * el<T, V>(i00, e) + a10 * el<T, V>(i10, e) + a01 * el<T, V>(i01, e) + a11 * el<T, V>(i11, e);
+      const T Su = a00 * el<T, V>(s00, e) + a10 * el<T, V>(s10, e) + a01 * el<T, V>(s01, e) + a11 * el<T, V>(s11, e);
+      const T cu = a00 * el<T, V>(x00, e) + a10 * el<T, V>(x10, e) + a01 * el<T, V>(x01, e) + a11 * el<T, V>(x11, e);
+      T E, pw, p0;
+      vrt::Seg<T>::weights((cu + el<T, V>(cm, e)) * h, E, pw, p0);
+      set_el<T, V>(out, e, E * Iu + pw * Su + p0 * el<T, V>(sm, e));
+    }
+    L::store(Iray + me + l, out);
   }
 }
 
-template <typename T, int C>
+template <typename T, int C, int V>
 void launch_rc(hipStream_t s, int32_t step, int32_t rb, int32_t rc, int32_t nx, int32_t ny, int32_t nz, double dx,
                double dy, const double *z, const double *dirs, int32_t nl, const T *chi, const T *S, const T *Ibot,
                const T *Itop, T *I) {
@@ -89,9 +132,26 @@ void launch_rc(hipStream_t s, int32_t step, int32_t rb, int32_t rc, int32_t nx, 
   const int64_t items = (int64_t)nx * ny * rc;
   const int64_t waves = (items + SPW - 1) / SPW;
   const int64_t blocks = (waves + 3) / 4;
-  hipLaunchKernelGGL((regular_kernel<T, C>), dim3((unsigned)blocks), dim3(256), 0, s, step, rb, rc, nx, ny, nz, dx,
+  hipLaunchKernelGGL((regular_kernel<T, C, V>), dim3((unsigned)blocks), dim3(256), 0, s, step, rb, rc, nx, ny, nz, dx,
                      dy, z, dirs, nl, chi, S, Ibot, Itop, I);
 }
+
+template <typename T, int V>
+void launch_rv(hipStream_t s, int32_t step, int32_t rb, int32_t rc, int32_t nx, int32_t ny, int32_t nz, double dx,
+               double dy, const double *z, const double *dirs, int32_t nl, const T *chi, const T *S, const T *Ibot,
+               const T *Itop, T *I) {
+  switch (vrt::lanes_per_record(nl / V)) {
+    case 64: launch_rc<T, 64, V>(s, step, rb, rc, nx, ny, nz, dx, dy, z, dirs, nl, chi, S, Ibot, Itop, I); break;
+    case 32: launch_rc<T, 32, V>(s, step, rb, rc, nx, ny, nz, dx, dy, z, dirs, nl, chi, S, Ibot, Itop, I); break;
+    case 16: launch_rc<T, 16, V>(s, step, rb, rc, nx, ny, nz, dx, dy, z, dirs, nl, chi, S, Ibot, Itop, I); break;
+    case 8: launch_rc<T, 8, V>(s, step, rb, rc, nx, ny, nz, dx, dy, z, dirs, nl, chi, S, Ibot, Itop, I); break;
+    case 4: launch_rc<T, 4, V>(s, step, rb, rc, nx, ny, nz, dx, dy, z, dirs, nl, chi, S, Ibot, Itop, I); break;
+    case 2: launch_rc<T, 2, V>(s, step, rb, rc, nx, ny, nz, dx, dy, z, dirs, nl, chi, S, Ibot, Itop, I); break;
+    default: launch_rc<T, 1, V>(s, step, rb, rc, nx, ny, nz, dx, dy, z, dirs, nl, chi, S, Ibot, Itop, I); break;
+  }
+}
+
+inline bool al16r(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 }  // namespace
 
@@ -102,13 +162,12 @@ void launch_regular(hipStream_t s, int32_t step, int32_t ray_begin, int32_t ray_
                     int32_t nz, double dx, double dy, const double *z, const double *dirs, int32_t nl, const T *chi,
                     const T *S, const T *Ibot, const T *Itop, T *I) {
   if (ray_count <= 0 || nx * ny == 0) return;
-  if (nl >= 33) launch_rc<T, 64>(s, step, ray_begin, ray_count, nx, ny, nz, dx, dy, z, dirs, nl, chi, S, Ibot, Itop, I);
-  else if (nl >= 17) launch_rc<T, 32>(s, step, ray_begin, ray_count, nx, ny, nz, dx, dy, z, dirs, nl, chi, S, Ibot, Itop, I);
-  else if (nl >= 9) launch_rc<T, 16>(s, step, ray_begin, ray_count, nx, ny, nz, dx, dy, z, dirs, nl, chi, S, Ibot, Itop, I);
-  else if (nl >= 5) launch_rc<T, 8>(s, step, ray_begin, ray_count, nx, ny, nz, dx, dy, z, dirs, nl, chi, S, Ibot, Itop, I);
-  else if (nl >= 3) launch_rc<T, 4>(s, step, ray_begin, ray_count, nx, ny, nz, dx, dy, z, dirs, nl, chi, S, Ibot, Itop, I);
-  else if (nl == 2) launch_rc<T, 2>(s, step, ray_begin, ray_count, nx, ny, nz, dx, dy, z, dirs, nl, chi, S, Ibot, Itop, I);
-  else launch_rc<T, 1>(s, step, ray_begin, ray_count, nx, ny, nz, dx, dy, z, dirs, nl, chi, S, Ibot, Itop, I);
+  constexpr int VW = 16 / sizeof(T);
+  const bool aligned = al16r(chi) && al16r(S) && al16r(Ibot) && al16r(Itop) && al16r(I);
+  if (aligned && nl % VW == 0)
+    launch_rv<T, VW>(s, step, ray_begin, ray_count, nx, ny, nz, dx, dy, z, dirs, nl, chi, S, Ibot, Itop, I);
+  else
+    launch_rv<T, 1>(s, step, ray_begin, ray_count, nx, ny, nz, dx, dy, z, dirs, nl, chi, S, Ibot, Itop, I);
   VRT_HIP(hipGetLastError());
 }
 

@@ -192,6 +192,11 @@ vrt_status vrt_grid_set_rays(vrt_grid grid, int32_t n_rays, const double *dir, c
  *                           records per wavefront when the row length and the
  *                           arrays' alignment allow it) [16]. */
 #define VRT_TUNE_LANE_BYTES 8
+/*   VRT_TUNE_RAY_GROUPS     1..64: sweep the rays of a batched or graph sweep
+ *                           in this many consecutive passes over contiguous
+ *                           ray ranges (fewer rows in flight per level step,
+ *                           more launches) [1]. */
+#define VRT_TUNE_RAY_GROUPS 9
 /*   VRT_TUNE_SPIN_CAP       bound on the polls of one wait in the persistent
  *                           sweep [2^22]; a wait that exceeds it gives up.
  *   VRT_TUNE_PERSIST_BLOCKS cap on the persistent sweep's workgroups

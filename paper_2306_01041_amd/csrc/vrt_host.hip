@@ -490,6 +490,18 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
         VRT_HIP(hipEventRecord(ctx->join_ev[(size_t)c - 1], ctx->aux[(size_t)c - 1]));
         VRT_HIP(hipStreamWaitEvent(s, ctx->join_ev[(size_t)c - 1], 0));
       }
+    } else if (g->ray_groups > 1 && R > 1) {
+      // contiguous ray ranges swept one after another: each level step then
+      // touches fewer rows, so an upwind row is more likely still cached
+      const int32_t K = std::min<int32_t>(g->ray_groups, R);
+      for (int32_t c = 0; c < K; ++c) {
+        const int32_t r0 = (int32_t)((int64_t)c * R / K), r1 = (int32_t)((int64_t)(c + 1) * R / K);
+        for (int32_t st = 0; st < g->n_steps; ++st) {
+          const int64_t b = g->seg_off[(size_t)st * R + r0];
+          const int64_t e = g->seg_off[(size_t)st * R + r1 - 1] + g->seg_cnt[(size_t)st * R + r1 - 1];
+          sweep(b, e - b);
+        }
+      }
     } else {
       for (int32_t st = 0; st < g->n_steps; ++st)
         sweep(g->step_ptr[(size_t)st], g->step_ptr[(size_t)st + 1] - g->step_ptr[(size_t)st]);
@@ -1150,6 +1162,9 @@ vrt_status vrt_grid_tune(vrt_grid g, int32_t knob, int64_t value) {
     } else if (knob == VRT_TUNE_CHAINS) {
       if (value < 1 || value > 8) fail(VRT_E_ARG, "chain count must be in 1..8");
       g->chains = (int)value;
+    } else if (knob == VRT_TUNE_RAY_GROUPS) {
+      if (value < 1 || value > 64) fail(VRT_E_ARG, "ray groups must be in 1..64");
+      g->ray_groups = (int)value;
     } else if (knob == VRT_TUNE_LANE_BYTES) {
       if (value != 16 && value != 32) fail(VRT_E_ARG, "lane bytes must be 16 or 32");
       g->lane_bytes = (int)value;

@@ -183,6 +183,7 @@ struct vrt_grid_s {
   int ray_affinity = 0;  // 1: each ray's records always run on the same die
   int chains = 1;        // independent launch chains (streams) a sweep is split into
   int lane_bytes = 16;   // bytes of a row each lane moves per access (16 or 32)
+  int ray_groups = 1;    // the rays are swept in this many consecutive passes
 
   // ray-affinity tables: ray_die[r], and per step [kDies][xk][2] = {first
   // record, running count} over the segments of each die's rays

@@ -272,14 +272,16 @@ def test_tuning_knobs_do_not_change_results(v, ctx, quad, grids):
     chi, S = to_dev(chi_o, f), to_dev(S_o, f)
     ref = None
     for order in (0, 1):
-        for xcd, aff, ch, lb in ((0, 0, 1, 16), (3, 0, 1, 16), (8, 0, 1, 16), (8, 1, 1, 16), (8, 0, 2, 16),
-                                 (0, 0, 3, 16), (8, 0, 5, 16), (8, 0, 1, 32), (8, 1, 1, 32)):
+        for xcd, aff, ch, lb, rg in ((0, 0, 1, 16, 1), (3, 0, 1, 16, 1), (8, 0, 1, 16, 1), (8, 1, 1, 16, 1),
+                                     (8, 0, 2, 16, 1), (0, 0, 3, 16, 1), (8, 0, 5, 16, 1), (8, 0, 1, 32, 1),
+                                     (8, 1, 1, 32, 1), (8, 0, 1, 16, 3), (8, 0, 1, 16, 5)):
             G = v.Grid.from_synth(ctx, g)
             G.tune(v.VRT_TUNE_RECORD_ORDER, order)
             G.tune(v.VRT_TUNE_XCD_CHUNKS, xcd)
             G.tune(v.VRT_TUNE_RAY_AFFINITY, aff)
             G.tune(v.VRT_TUNE_CHAINS, ch)
             G.tune(v.VRT_TUNE_LANE_BYTES, lb)
+            G.tune(v.VRT_TUNE_RAY_GROUPS, rg)
             G.set_rays(dirs, w)
             J = torch.empty_like(chi)
             v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_GRAPH)
@@ -287,7 +289,7 @@ def test_tuning_knobs_do_not_change_results(v, ctx, quad, grids):
             out = J.cpu().numpy()
             if ref is None:
                 ref = out
-            assert np.array_equal(out, ref), (order, xcd, aff, ch, lb)
+            assert np.array_equal(out, ref), (order, xcd, aff, ch, lb, rg)
             G.close()
     G = _gpu_grid(v, ctx, g, dirs, w)
     J = torch.empty_like(chi)

@@ -77,6 +77,11 @@ def lib():
                                       _d, _d]
         L.orc_lambda_diag.restype = None
         L.orc_lte_vjp.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, ctypes.c_double, _d, _d, _d, _d, _d, _d, _d]
+        L.orc_idw2.argtypes = [ctypes.c_int64, _d, ctypes.c_int64, _d, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, _i32, _d, _d]
+        L.orc_idw2.restype = None
+        L.orc_lc_vertical.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _d, _d, _d, _d, _d]
+        L.orc_lc_vertical.restype = None
         _lib = L
     return _lib
 
@@ -260,6 +265,56 @@ def emergent_sites(grid, dirs):
     for d in np.asarray(dirs):
         bit = 2 if d[2] > 0 else 1
         out.append(np.nonzero(np.asarray(grid.wall) & bit)[0].astype(np.int32))
+    return out
+
+
+# ----------------------------------------------------------------------------
+# final synthesis: back-interpolation to a regular grid and vertical rays
+# ----------------------------------------------------------------------------
+
+def regular_points(nx, ny, dx, dy, z):
+    """Points (i dx, j dy, z_k) of a regular grid as [nx ny nz, 3], row (k ny + j) nx + i."""
+    z = _c(z, np.float64)
+    x = np.arange(nx, dtype=np.float64) * float(dx)
+    y = np.arange(ny, dtype=np.float64) * float(dy)
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    return np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+
+
+def idw2(xyz, pts, lo, hi, periodic_xy=True, power: float = 1.0):
+    """Two nearest sites of every point and the inverse-distance weight of the
+    nearer one (orc_idw2, brute force). Returns idx int32 [m, 2], w1 [m] and
+    the squared distances d2 [m, 2]."""
+    xyz = _c(xyz, np.float64)
+    pts = _c(pts, np.float64).reshape(-1, 3)
+    L = np.asarray(hi, np.float64) - np.asarray(lo, np.float64)
+    m = pts.shape[0]
+    idx = np.empty((m, 2), np.int32)
+    w1 = np.empty(m, np.float64)
+    d2 = np.empty((m, 2), np.float64)
+    lib().orc_idw2(xyz.shape[0], _p(xyz, _d), m, _p(pts, _d), 1 if periodic_xy else 0, float(L[0]), float(L[1]),
+                   float(power), _p(idx, _i32), _p(w1, _d), _p(d2, _d))
+    return idx, w1, d2
+
+
+def idw_apply(idx, w1, f):
+    """Interpolated values w1 f[i1] + (1 - w1) f[i2] (f [n] or [n, k])."""
+    f = np.asarray(f, np.float64)
+    w = w1 if f.ndim == 1 else w1[:, None]
+    return w * f[idx[:, 0]] + (1.0 - w) * f[idx[:, 1]]
+
+
+def lc_vertical(ncol, z, chi, S, I_bottom):
+    """Intensity at the top of each vertical column at mu = 1 (orc_lc_vertical):
+    chi, S [nz * ncol, nl], I_bottom [ncol, nl]; returns [ncol, nl]."""
+    z = _c(z, np.float64)
+    nz = len(z)
+    chi = _c(chi, np.float64).reshape(nz * ncol, -1)
+    S = _c(S, np.float64).reshape(nz * ncol, -1)
+    nl = chi.shape[1]
+    Ib = _c(np.broadcast_to(I_bottom, (ncol, nl)), np.float64)
+    out = np.empty((ncol, nl), np.float64)
+    lib().orc_lc_vertical(ncol, nz, nl, _p(z, _d), _p(chi, _d), _p(S, _d), _p(Ib, _d), _p(out, _d))
     return out
 
 

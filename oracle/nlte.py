@@ -21,7 +21,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import fs_voronoi, lambda_diag
+from . import fs_voronoi, idw2, idw_apply, lambda_diag, lc_vertical, regular_points
 
 
 def assemble(chi_c, chi_L, phi, B, S_L):
@@ -137,3 +137,22 @@ def dense_fixed_point(grid, dirs, ray_w, sel, chi_c, chi_L, phi, wlam, B, eps, I
     for j, gidx in enumerate(groups):
         S[gidx] = sol[j]
     return S
+
+
+def synthesize(grid, S_line, nx, ny, dx, dy, z, phi, chi_L, chi_c, B, power=1.0, I_bottom=None):
+    """Emergent line intensity at mu = 1 on a regular grid from a solution on a
+    Voronoi grid (Sect. 2.5, closing paragraph): S_line on the sites is carried
+    to the regular points by inverse-distance weights of the two nearest sites,
+    the line and continuum are assembled there (phi [m, nl], chi_L, chi_c, B
+    [m], m = nx ny nz in row order (k ny + j) nx + i), and each column is
+    integrated upwards from I_bottom (default B of the bottom plane). Returns
+    the top-plane intensities [nx ny, nl]."""
+    z = np.asarray(z, np.float64)
+    pts = regular_points(nx, ny, dx, dy, z)
+    idx, w1, _ = idw2(grid.xyz, pts, grid.lo, grid.hi, grid.periodic_xy, power)
+    S_reg = idw_apply(idx, w1, S_line)
+    chi, S = assemble(chi_c, chi_L, phi, B, S_reg)
+    ncol = nx * ny
+    if I_bottom is None:
+        I_bottom = np.repeat(B[:ncol, None], phi.shape[1], axis=1)
+    return lc_vertical(ncol, z, chi, S, I_bottom)

@@ -589,3 +589,97 @@ void orc_lambda_diag(int64_t n, int32_t n_rays, int32_t nl, const double *ray_w,
         }
     }
 }
+
+/* ---------------------------------------------------------------------------
+ * Final synthesis (Sect. 2.5, closing paragraph; Sect. 3.2): the converged
+ * solution on the irregular grid is carried back to a regular grid by
+ * inverse-distance interpolation from the two nearest sites, and the emergent
+ * intensity at mu = 1 is then a long-characteristics solution along each
+ * vertical column of that grid.
+ *
+ * orc_idw2: for every query point q, the two distinct sites nearest to it,
+ * found by brute force over all sites. Distance (reading S1): components
+ * dx = xq - xs and dy = yq - ys are brought into [-L/2, L/2] by adding or
+ * subtracting the period L when the grid is periodic in x and y, dz = zq - zs,
+ * and d2 = dx*dx + dy*dy + dz*dz in that order (no fused multiply-add). Keys
+ * (d2, site index) are compared lexicographically, so ties go to the smaller
+ * index. Weights (reading S2): u_k = d_k^-p, w1 = u_1 / (u_1 + u_2), written
+ * as w1 = a_2 / (a_1 + a_2) with a_k = d_k^p = (d2_k)^(p/2), which is 1 when
+ * d_1 = 0; w1 = 1 when both distances are 0. A grid with one site gives
+ * i2 = i1 and w1 = 1. Outputs idx [m][2], w1 [m], d2 [m][2] (d2 may be NULL).
+ * ------------------------------------------------------------------------- */
+static double orc_wrap(double d, int periodic, double L) {
+    if (!periodic) return d;
+    const double h = 0.5 * L;
+    while (d > h) d -= L;
+    while (d < -h) d += L;
+    return d;
+}
+
+void orc_idw2(int64_t n, const double *xyz, int64_t m, const double *pts, int periodic, double Lx, double Ly,
+              double power, int32_t *idx, double *w1, double *d2out) {
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < m; ++q) {
+        int64_t b1 = -1, b2 = -1;
+        double e1 = 0.0, e2 = 0.0;
+        for (int64_t s = 0; s < n; ++s) {
+            const double dx = orc_wrap(pts[3 * q + 0] - xyz[3 * s + 0], periodic, Lx);
+            const double dy = orc_wrap(pts[3 * q + 1] - xyz[3 * s + 1], periodic, Ly);
+            const double dz = pts[3 * q + 2] - xyz[3 * s + 2];
+            const double d2 = dx * dx + dy * dy + dz * dz;
+            /* sites arrive in increasing index, so a strict < keeps the smaller index on ties */
+            if (b1 < 0 || d2 < e1) {
+                b2 = b1;
+                e2 = e1;
+                b1 = s;
+                e1 = d2;
+            } else if (b2 < 0 || d2 < e2) {
+                b2 = s;
+                e2 = d2;
+            }
+        }
+        double w = 1.0;
+        if (b2 < 0) {
+            b2 = b1;
+            e2 = e1;
+        } else {
+            const double a1 = pow(e1, 0.5 * power), a2 = pow(e2, 0.5 * power);
+            if (a1 + a2 > 0.0) w = a2 / (a1 + a2);
+        }
+        idx[2 * q + 0] = (int32_t)b1;
+        idx[2 * q + 1] = (int32_t)b2;
+        w1[q] = w;
+        if (d2out) {
+            d2out[2 * q + 0] = e1;
+            d2out[2 * q + 1] = e2;
+        }
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * Long characteristics at mu = 1 (Sect. 2.5, closing paragraph): along each
+ * vertical column c of a regular grid, from the bottom plane upwards,
+ *   I_0 = I_bottom[c],  I_k = e^-x I_(k-1) + Psi_u(x) S_(k-1) + Psi_0(x) S_k,
+ *   x = (chi_(k-1) + chi_k) / 2 * (z_k - z_(k-1)),
+ * the linear-source step of Eq. 2 with the trapezoid optical depth (R5). The
+ * result is I at the top plane. chi, S [nz * ncol][nl] (point (k, c) at row
+ * k * ncol + c), I_bottom and I_top [ncol][nl].
+ * ------------------------------------------------------------------------- */
+void orc_lc_vertical(int64_t ncol, int32_t nz, int32_t nl, const double *z, const double *chi, const double *S,
+                     const double *I_bottom, double *I_top) {
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < ncol; ++c) {
+        for (int32_t l = 0; l < nl; ++l) {
+            double I = I_bottom[c * nl + l];
+            for (int32_t k = 1; k < nz; ++k) {
+                const int64_t lo = ((int64_t)(k - 1) * ncol + c) * nl + l;
+                const int64_t hi = ((int64_t)k * ncol + c) * nl + l;
+                const double x = 0.5 * (chi[lo] + chi[hi]) * (z[k] - z[k - 1]);
+                double E, pu, p0;
+                orc_psi(x, &E, &pu, &p0);
+                I = E * I + pu * S[lo] + p0 * S[hi];
+            }
+            I_top[c * nl + l] = I;
+        }
+    }
+}

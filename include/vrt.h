@@ -380,6 +380,69 @@ vrt_status vrt_grid_emergent_index(vrt_grid grid, int64_t *offsets, int32_t *sit
 vrt_status vrt_emergent_gather(vrt_grid grid, vrt_prec prec, int32_t n_lambda, const void *I_rays,
                                void *out);
 
+/* Final synthesis on the original regular grid (Sect. 2.5, closing paragraph;
+ * Sect. 3.2): quantities converged on the Voronoi grid are carried back to
+ * the regular points by inverse-distance interpolation from the two nearest
+ * sites, and the emergent intensity at mu = 1 follows from long
+ * characteristics up each vertical column.
+ *
+ * vrt_idw_map: for every point p = (i dx, j dy, z[k]) of `regular` (row
+ * (k ny + j) nx + i), the two distinct sites of `voronoi` nearest to p and
+ * the weight of the nearer one.
+ *   Distance: dx = x_p - x_s and dy = y_p - y_s taken to their minimum image
+ *   (|d| <= L/2) on a periodic grid, dz = z_p - z_s, d2 = dx^2 + dy^2 + dz^2
+ *   (formed without fused multiply-add); ties go to the smaller site index.
+ *   Weights u_k = d_k^-power, w1 = u_1 / (u_1 + u_2) (1 when p is a site;
+ *   a one-site grid gives idx = (0, 0), w1 = 1).
+ *   idx  device [m][2] int32 output (nearest, second nearest),
+ *   w1   device [m] double output,
+ *   d2   device [m][2] double output of the squared distances, or NULL;
+ *   m = nx ny nz. The search walks the neighbour lists, so they must hold
+ *   every face neighbour (as vrt_grid_create_voronoi expects).
+ * Both grids must share a context. A periodic Voronoi grid needs the same
+ * periods (nx dx = Lx, ny dy = Ly within 1e-9) and a box starting within one
+ * period of x = y = 0; a non-periodic one must contain every point in x and
+ * y; the planes must lie inside [lo[2], hi[2]] (VRT_E_ARG otherwise).
+ * Returns VRT_E_GRID if a walk does not settle (incomplete neighbour lists).
+ * Blocks. */
+vrt_status vrt_idw_map(vrt_grid voronoi, vrt_grid regular, double power, int32_t *idx, double *w1,
+                       double *d2);
+
+/* dst[p][c] = w1[p] src[idx[p][0]][c] + (1 - w1[p]) src[idx[p][1]][c] for every
+ * regular point p and column c < n_cols: src device [n_sites][n_cols] double
+ * on the Voronoi sites, dst device [m][n_cols] double; idx and w1 as written
+ * by vrt_idw_map. An index outside the Voronoi grid gives NaN. Enqueued. */
+vrt_status vrt_idw_apply(vrt_grid voronoi, vrt_grid regular, int32_t n_cols, const int32_t *idx, const double *w1,
+                         const double *src, double *dst);
+
+/* Emergent line intensity at mu = 1 on the regular grid from a two-level
+ * solution on the Voronoi grid (the paper's final synthesis):
+ *   S_line at each regular point = the vrt_idw_apply interpolation of S_line
+ *   (device [n_sites] double) with idx, w1 from vrt_idw_map;
+ *   chi_lambda = chi_cont + chi_line phi_lambda,
+ *   S_lambda   = (chi_line phi_lambda S_line + chi_cont B) / chi_lambda
+ *   at each point, with phi device [m][n_lambda] in `prec` and chi_line,
+ *   chi_cont, B device [m] double; then along each column (i, j), from the
+ *   bottom plane upwards, I_k = e^-x I_(k-1) + Psi_u(x) S_(k-1) + Psi_0(x) S_k,
+ *   x = (chi_(k-1) + chi_k)/2 (z_k - z_(k-1)) (Eq. 2 with S linear).
+ *   I_bottom  device [ny nx][n_lambda] in `prec`, or NULL = B of the bottom
+ *             point (thermalised, as in the Lambda iteration);
+ *   I_top     device [ny nx][n_lambda] output in `prec` (row j nx + i).
+ * The column integration runs in `prec`; the interpolation in double. Uses a
+ * library buffer of 4 m values owned by the regular grid. Enqueued. */
+vrt_status vrt_synthesis_vertical(vrt_grid voronoi, vrt_grid regular, vrt_prec prec, int32_t n_lambda,
+                                  const int32_t *idx, const double *w1, const double *S_line, const void *phi,
+                                  const double *chi_line, const double *chi_cont, const double *B,
+                                  const void *I_bottom, void *I_top);
+
+/* Long characteristics at mu = 1 for given chi and S (device [m][n_lambda],
+ * `prec`) on a regular grid, as in vrt_synthesis_vertical (the LTE continuum
+ * synthesis of Sect. 3.2). I_bottom device [ny nx][n_lambda] or NULL = S of
+ * the bottom point; I_top device [ny nx][n_lambda] output. One launch.
+ * Enqueued. */
+vrt_status vrt_lc_vertical(vrt_grid regular, vrt_prec prec, int32_t n_lambda, const void *chi, const void *S,
+                           const void *I_bottom, void *I_top);
+
 #ifdef __cplusplus
 }
 #endif

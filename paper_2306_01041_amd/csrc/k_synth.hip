@@ -1,0 +1,314 @@
+// Final synthesis on the original regular grid (Sect. 2.5, closing
+// paragraph; Sect. 3.2): quantities converged on the Voronoi grid are carried
+// back to the regular points by inverse-distance weights of the two nearest
+// sites, and the emergent intensity at mu = 1 is a long-characteristics
+// solution up each vertical column.
+//
+// Nearest sites. The site nearest to a point p is found by a greedy walk over
+// the Voronoi neighbour lists: from a start site, move to the neighbour with
+// the smallest key (d^2, site index) while that key is smaller than the
+// current one. A Voronoi cell is the intersection of the half-spaces cut by
+// its face neighbours, so a site that no neighbour beats holds p in its cell
+// (the walk stops exactly at the nearest site; periodic images are handled by
+// the minimum-image distance, and the box walls clip every cell the same
+// way). The second-nearest site shares a face with the nearest one: shrinking
+// the empty ball about p that passes through the second site, towards that
+// site, until it touches the first gives an empty ball through both, whose
+// centre lies inside the (convex) box. So the scan of the nearest site's list
+// that confirms the walk's end also yields the second site. Points are
+// processed coarse to fine (strides 64, 16, 4, 1 in each direction); each
+// point starts from the nearest site of its coarse parent, so walks are a few
+// steps long. Distances use the same operations in the same order as their
+// definition and no fused multiply-add, so the chosen sites are reproducible
+// on any IEEE-754 machine.
+//
+// Columns. One thread per (column, wavelength); consecutive threads take
+// consecutive wavelengths and then columns, so each horizontal plane of a
+// [point][lambda] array is read as one contiguous stream. Every thread walks
+// its column from the bottom plane to the top with the linear-source step.
+
+#include "segment.h"
+#include "vrt_internal.h"
+
+namespace {
+
+// d reduced into [-L/2, L/2] by whole periods; the host guarantees |d| < 2L + L/2
+__device__ __forceinline__ double wrap_period(double d, int periodic, double L) {
+  if (!periodic) return d;
+  const double h = 0.5 * L;
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+    if (d > h) d -= L;
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+    if (d < -h) d += L;
+  return d;
+}
+
+__device__ __forceinline__ double site_dist2(double px, double py, double pz, const double *__restrict__ xyz,
+                                             int32_t s, int periodic, double Lx, double Ly) {
+#pragma clang fp contract(off)
+  const double dx = wrap_period(px - xyz[3 * (int64_t)s + 0], periodic, Lx);
+  const double dy = wrap_period(py - xyz[3 * (int64_t)s + 1], periodic, Ly);
+  const double dz = pz - xyz[3 * (int64_t)s + 2];
+  return dx * dx + dy * dy + dz * dz;
+}
+
+__device__ __forceinline__ bool key_less(double da, int32_t ia, double db, int32_t ib) {
+  return da < db || (da == db && ia < ib);
+}
+
+__global__ __launch_bounds__(256) void idw_level_kernel(int32_t nx, int32_t ny, int32_t nz, double dx, double dy,
+                                                        const double *__restrict__ z, int32_t stride,
+                                                        int32_t parent, int64_t n, const double *__restrict__ xyz,
+                                                        const int64_t *__restrict__ ptr,
+                                                        const int32_t *__restrict__ nbr, int periodic, double Lx,
+                                                        double Ly, double power, int32_t *__restrict__ idx,
+                                                        double *__restrict__ w1, double *__restrict__ d2,
+                                                        int32_t *__restrict__ bad) {
+  const int64_t cx = (nx + stride - 1) / stride, cy = (ny + stride - 1) / stride, cz = (nz + stride - 1) / stride;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cx * cy * cz) return;
+  const int32_t i = (int32_t)(t % cx) * stride;
+  const int32_t j = (int32_t)((t / cx) % cy) * stride;
+  const int32_t k = (int32_t)(t / (cx * cy)) * stride;
+  // points on the parent lattice were done by an earlier launch
+  if (parent > 0 && i % parent == 0 && j % parent == 0 && k % parent == 0) return;
+  const int64_t p = ((int64_t)k * ny + j) * nx + i;
+  int32_t cur = 0;
+  if (parent > 0) {
+    const int64_t q = ((int64_t)(k / parent * parent) * ny + j / parent * parent) * nx + i / parent * parent;
+    const int32_t s = idx[2 * q];
+    if (s >= 0 && s < n) cur = s;
+  }
+  const double px = (double)i * dx, py = (double)j * dy, pz = z[k];
+  double dc = site_dist2(px, py, pz, xyz, cur, periodic, Lx, Ly);
+  int32_t i1 = -1, i2 = -1;
+  double e1 = 0.0, e2 = 0.0;
+  // the key falls at every move, so there are at most n - 1 moves
+  for (int64_t it = 0; it < n; ++it) {
+    int32_t b = -1;
+    double db = 0.0;
+    for (int64_t e = ptr[cur]; e < ptr[cur + 1]; ++e) {
+      const int32_t s = nbr[e];
+      if (s == cur) continue;  // a periodic image of the site itself
+      const double d = site_dist2(px, py, pz, xyz, s, periodic, Lx, Ly);
+      if (b < 0 || key_less(d, s, db, b)) {
+        b = s;
+        db = d;
+      }
+    }
+    if (b >= 0 && key_less(db, b, dc, cur)) {
+      cur = b;
+      dc = db;
+      continue;
+    }
+    i1 = cur;
+    e1 = dc;
+    i2 = b;
+    e2 = db;
+    break;
+  }
+  double w = 1.0;
+  if (i1 < 0) {
+    *bad = 1;  // the walk did not settle: the neighbour lists are not a Voronoi diagram
+    i1 = i2 = -1;
+    w = __builtin_nan("");
+  } else if (i2 < 0) {
+    i2 = i1;
+    e2 = e1;
+  } else {
+    const double a1 = pow(e1, 0.5 * power), a2 = pow(e2, 0.5 * power);
+    if (a1 + a2 > 0.0) w = a2 / (a1 + a2);
+  }
+  idx[2 * p + 0] = i1;
+  idx[2 * p + 1] = i2;
+  w1[p] = w;
+  if (d2) {
+    d2[2 * p + 0] = e1;
+    d2[2 * p + 1] = e2;
+  }
+}
+
+__global__ __launch_bounds__(256) void idw_apply_kernel(int64_t m, int32_t nc, int64_t n_src,
+                                                        const int32_t *__restrict__ idx, const double *__restrict__ w1,
+                                                        const double *__restrict__ src, double *__restrict__ dst) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m * nc) return;
+  const int64_t p = t / nc;
+  const int32_t c = (int32_t)(t - p * nc);
+  const int32_t a = idx[2 * p], b = idx[2 * p + 1];
+  if (a < 0 || a >= n_src || b < 0 || b >= n_src) {
+    dst[t] = __builtin_nan("");
+    return;
+  }
+  const double w = w1[p];
+  dst[t] = w * src[(int64_t)a * nc + c] + (1.0 - w) * src[(int64_t)b * nc + c];
+}
+
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+
+// Per regular point: (chi_line, chi_cont, chi_cont * B, S_line interpolated
+// from the two nearest sites), in the precision of the column integration.
+template <typename T>
+__global__ __launch_bounds__(256) void line_pack_kernel(int64_t m, int64_t n_src, const int32_t *__restrict__ idx,
+                                                        const double *__restrict__ w1,
+                                                        const double *__restrict__ S_site,
+                                                        const double *__restrict__ chi_L,
+                                                        const double *__restrict__ chi_c,
+                                                        const double *__restrict__ B,
+                                                        typename Vec4<T>::type *__restrict__ pack) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= m) return;
+  const int32_t a = idx[2 * p], b = idx[2 * p + 1];
+  double SL = __builtin_nan("");
+  if (a >= 0 && a < n_src && b >= 0 && b < n_src) {
+    const double w = w1[p];
+    SL = w * S_site[a] + (1.0 - w) * S_site[b];
+  }
+  typename Vec4<T>::type v;
+  v.x = (T)chi_L[p];
+  v.y = (T)chi_c[p];
+  v.z = (T)(chi_c[p] * B[p]);
+  v.w = (T)SL;
+  pack[p] = v;
+}
+
+// Opacity and source of one (point, wavelength).
+template <typename T> struct LineSource {
+  const T *phi;
+  const typename Vec4<T>::type *pack;
+  __device__ __forceinline__ void at(int64_t p, int64_t pl, T &chi, T &S) const {
+    const typename Vec4<T>::type v = pack[p];
+    const T lo = v.x * phi[pl];
+    chi = v.y + lo;
+    S = (lo * v.w + v.z) / chi;
+  }
+};
+
+template <typename T> struct PlainSource {
+  const T *chi, *S;
+  __device__ __forceinline__ void at(int64_t, int64_t pl, T &c, T &s) const {
+    c = chi[pl];
+    s = S[pl];
+  }
+};
+
+// I_bottom defaults: the line synthesis enters with B of the bottom point, the
+// plain solve with the bottom point's source function (thermalised).
+template <typename T> __device__ __forceinline__ T default_bottom(const LineSource<T> &, const double *B, int64_t c, T) {
+  return (T)B[c];
+}
+template <typename T> __device__ __forceinline__ T default_bottom(const PlainSource<T> &, const double *, int64_t, T S0) {
+  return S0;
+}
+
+template <typename T, class Src>
+__global__ __launch_bounds__(256) void vertical_kernel(int64_t ncol, int32_t nz, int32_t nl,
+                                                       const double *__restrict__ z, Src src,
+                                                       const double *__restrict__ B, const T *__restrict__ Ib,
+                                                       T *__restrict__ out) {
+  const int64_t plane = ncol * nl;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= plane) return;
+  const int64_t c = t / nl;
+  T chi0, S0;
+  src.at(c, t, chi0, S0);
+  T I = Ib ? Ib[t] : default_bottom(src, B, c, S0);
+  constexpr int U = sizeof(T) == 4 ? 4 : 2;  // planes whose inputs are loaded before they are integrated
+  int32_t k = 1;
+  for (; k + U <= nz; k += U) {
+    T chi1[U], S1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) src.at((int64_t)(k + u) * ncol + c, (int64_t)(k + u) * plane + t, chi1[u], S1[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const T x = (T)0.5 * (chi0 + chi1[u]) * (T)(z[k + u] - z[k + u - 1]);
+      T E, pu, p0;
+      vrt::Seg<T>::weights(x, E, pu, p0);
+      I = E * I + pu * S0 + p0 * S1[u];
+      chi0 = chi1[u];
+      S0 = S1[u];
+    }
+  }
+  for (; k < nz; ++k) {
+    T chi1, S1;
+    src.at((int64_t)k * ncol + c, (int64_t)k * plane + t, chi1, S1);
+    const T x = (T)0.5 * (chi0 + chi1) * (T)(z[k] - z[k - 1]);
+    T E, pu, p0;
+    vrt::Seg<T>::weights(x, E, pu, p0);
+    I = E * I + pu * S0 + p0 * S1;
+    chi0 = chi1;
+    S0 = S1;
+  }
+  out[t] = I;
+}
+
+inline unsigned blocks_for(int64_t count, int threads = 256) { return (unsigned)((count + threads - 1) / threads); }
+
+}  // namespace
+
+namespace vrt {
+
+void launch_idw_level(hipStream_t s, int32_t nx, int32_t ny, int32_t nz, double dx, double dy, const double *z,
+                      int32_t stride, int32_t parent, int64_t n, const double *xyz, const int64_t *ptr,
+                      const int32_t *nbr, bool periodic, double Lx, double Ly, double power, int32_t *idx,
+                      double *w1, double *d2, int32_t *bad) {
+  const int64_t cnt = (int64_t)((nx + stride - 1) / stride) * ((ny + stride - 1) / stride) *
+                      ((nz + stride - 1) / stride);
+  if (cnt == 0) return;
+  idw_level_kernel<<<blocks_for(cnt), 256, 0, s>>>(nx, ny, nz, dx, dy, z, stride, parent, n, xyz, ptr, nbr,
+                                                   periodic ? 1 : 0, Lx, Ly, power, idx, w1, d2, bad);
+  VRT_HIP(hipGetLastError());
+}
+
+void launch_idw_apply(hipStream_t s, int64_t m, int32_t nc, int64_t n_src, const int32_t *idx, const double *w1,
+                      const double *src, double *dst) {
+  if (m * nc == 0) return;
+  idw_apply_kernel<<<blocks_for(m * nc), 256, 0, s>>>(m, nc, n_src, idx, w1, src, dst);
+  VRT_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_line_pack(hipStream_t s, int64_t m, int64_t n_src, const int32_t *idx, const double *w1,
+                      const double *S_site, const double *chi_L, const double *chi_c, const double *B, void *pack) {
+  if (m == 0) return;
+  line_pack_kernel<T><<<blocks_for(m), 256, 0, s>>>(m, n_src, idx, w1, S_site, chi_L, chi_c, B,
+                                                    static_cast<typename Vec4<T>::type *>(pack));
+  VRT_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_vertical_line(hipStream_t s, int64_t ncol, int32_t nz, int32_t nl, const double *z, const T *phi,
+                          const void *pack, const double *B, const T *Ib, T *out) {
+  if (ncol * nl == 0) return;
+  LineSource<T> src{phi, static_cast<const typename Vec4<T>::type *>(pack)};
+  vertical_kernel<T, LineSource<T>><<<blocks_for(ncol * nl), 256, 0, s>>>(ncol, nz, nl, z, src, B, Ib, out);
+  VRT_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_vertical_plain(hipStream_t s, int64_t ncol, int32_t nz, int32_t nl, const double *z, const T *chi,
+                           const T *S, const T *Ib, T *out) {
+  if (ncol * nl == 0) return;
+  PlainSource<T> src{chi, S};
+  vertical_kernel<T, PlainSource<T>><<<blocks_for(ncol * nl), 256, 0, s>>>(ncol, nz, nl, z, src, nullptr, Ib, out);
+  VRT_HIP(hipGetLastError());
+}
+
+template void launch_line_pack<float>(hipStream_t, int64_t, int64_t, const int32_t *, const double *, const double *,
+                                      const double *, const double *, const double *, void *);
+template void launch_line_pack<double>(hipStream_t, int64_t, int64_t, const int32_t *, const double *, const double *,
+                                       const double *, const double *, const double *, void *);
+template void launch_vertical_line<float>(hipStream_t, int64_t, int32_t, int32_t, const double *, const float *,
+                                          const void *, const double *, const float *, float *);
+template void launch_vertical_line<double>(hipStream_t, int64_t, int32_t, int32_t, const double *, const double *,
+                                           const void *, const double *, const double *, double *);
+template void launch_vertical_plain<float>(hipStream_t, int64_t, int32_t, int32_t, const double *, const float *,
+                                           const float *, const float *, float *);
+template void launch_vertical_plain<double>(hipStream_t, int64_t, int32_t, int32_t, const double *, const double *,
+                                            const double *, const double *, double *);
+
+}  // namespace vrt

@@ -1538,4 +1538,105 @@ vrt_status vrt_emergent_gather(vrt_grid g, vrt_prec prec, int32_t n_lambda, cons
   });
 }
 
+vrt_status vrt_idw_map(vrt_grid vor, vrt_grid reg, double power, int32_t *idx, double *w1, double *d2) {
+  if (!vor || !reg) return VRT_E_ARG;
+  return guarded(reg->ctx, [&] {
+    if (vor->ctx != reg->ctx) fail(VRT_E_ARG, "the two grids belong to different contexts");
+    if (vor->kind != 0 || reg->kind != 1) fail(VRT_E_ARG, "expected a Voronoi grid and a regular grid");
+    if (vor->n < 1) fail(VRT_E_ARG, "the Voronoi grid has no sites");
+    if (!(power > 0.0) || !std::isfinite(power)) fail(VRT_E_ARG, "power must be positive and finite");
+    if (!idx || !w1) fail(VRT_E_ARG, "null output");
+    const double Lx = vor->hi[0] - vor->lo[0], Ly = vor->hi[1] - vor->lo[1];
+    const double X = (double)(reg->nx - 1) * reg->dx, Y = (double)(reg->ny - 1) * reg->dy;
+    if (vor->periodic) {
+      // one period in both grids, and boxes close enough that a difference of
+      // coordinates needs at most three period shifts
+      if (std::fabs((double)reg->nx * reg->dx - Lx) > 1e-9 * Lx || std::fabs((double)reg->ny * reg->dy - Ly) > 1e-9 * Ly)
+        fail(VRT_E_ARG, "the regular grid's periods (%g, %g) differ from the Voronoi box (%g, %g)",
+             (double)reg->nx * reg->dx, (double)reg->ny * reg->dy, Lx, Ly);
+      if (std::fabs(vor->lo[0]) > Lx || std::fabs(vor->lo[1]) > Ly)
+        fail(VRT_E_ARG, "the Voronoi box must start within one period of x = y = 0");
+    } else if (vor->lo[0] > 0.0 || vor->lo[1] > 0.0 || X > vor->hi[0] || Y > vor->hi[1]) {
+      fail(VRT_E_ARG, "regular points outside the Voronoi box in x or y");
+    }
+    if (reg->h_z.front() < vor->lo[2] || reg->h_z.back() > vor->hi[2])
+      fail(VRT_E_ARG, "regular planes outside the Voronoi box in z");
+    hipStream_t s = reg->ctx->stream;
+    reg->d_walk_bad.alloc(sizeof(unsigned long long));
+    vrt::launch_zero_u64(s, 1, reg->d_walk_bad.as<unsigned long long>());
+    int32_t *bad = reg->d_walk_bad.as<int32_t>();
+    const int32_t strides[4] = {64, 16, 4, 1};
+    for (int l = 0; l < 4; ++l)
+      vrt::launch_idw_level(s, reg->nx, reg->ny, reg->nz, reg->dx, reg->dy, reg->d_z.as<double>(), strides[l],
+                            l ? strides[l - 1] : 0, vor->n, vor->d_xyz.as<double>(), vor->d_ptr.as<int64_t>(),
+                            vor->d_idx.as<int32_t>(), vor->periodic, Lx, Ly, power, idx, w1, d2, bad);
+    int32_t h_bad = 0;
+    VRT_HIP(hipMemcpyAsync(&h_bad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    VRT_HIP(hipStreamSynchronize(s));
+    if (h_bad) fail(VRT_E_GRID, "the nearest-site walk did not settle: the neighbour lists are incomplete");
+    return VRT_OK;
+  });
+}
+
+vrt_status vrt_idw_apply(vrt_grid vor, vrt_grid reg, int32_t n_cols, const int32_t *idx, const double *w1,
+                         const double *src, double *dst) {
+  if (!vor || !reg) return VRT_E_ARG;
+  return guarded(reg->ctx, [&] {
+    if (vor->ctx != reg->ctx) fail(VRT_E_ARG, "the two grids belong to different contexts");
+    if (vor->kind != 0 || reg->kind != 1) fail(VRT_E_ARG, "expected a Voronoi grid and a regular grid");
+    if (n_cols <= 0 || !idx || !w1 || !src || !dst) fail(VRT_E_ARG, "bad interpolation arguments");
+    vrt::launch_idw_apply(reg->ctx->stream, reg->n, n_cols, vor->n, idx, w1, src, dst);
+    return VRT_OK;
+  });
+}
+
+vrt_status vrt_synthesis_vertical(vrt_grid vor, vrt_grid reg, vrt_prec prec, int32_t n_lambda, const int32_t *idx,
+                                  const double *w1, const double *S_line, const void *phi, const double *chi_line,
+                                  const double *chi_cont, const double *B, const void *I_bottom, void *I_top) {
+  if (!vor || !reg) return VRT_E_ARG;
+  return guarded(reg->ctx, [&] {
+    if (vor->ctx != reg->ctx) fail(VRT_E_ARG, "the two grids belong to different contexts");
+    if (vor->kind != 0 || reg->kind != 1) fail(VRT_E_ARG, "expected a Voronoi grid and a regular grid");
+    if (!valid_prec(prec) || n_lambda <= 0) fail(VRT_E_ARG, "bad precision or n_lambda");
+    if (!idx || !w1 || !S_line || !phi || !chi_line || !chi_cont || !B || !I_top)
+      fail(VRT_E_ARG, "null argument");
+    hipStream_t s = reg->ctx->stream;
+    const int64_t m = reg->n, ncol = (int64_t)reg->nx * reg->ny;
+    const double *z = reg->d_z.as<double>();
+    reg->d_pack.alloc((size_t)m * 4 * (prec == VRT_F32 ? sizeof(float) : sizeof(double)));
+    if (prec == VRT_F32) {
+      vrt::launch_line_pack<float>(s, m, vor->n, idx, w1, S_line, chi_line, chi_cont, B, reg->d_pack.p);
+      vrt::launch_vertical_line<float>(s, ncol, reg->nz, n_lambda, z, static_cast<const float *>(phi), reg->d_pack.p,
+                                       B, static_cast<const float *>(I_bottom), static_cast<float *>(I_top));
+    } else {
+      vrt::launch_line_pack<double>(s, m, vor->n, idx, w1, S_line, chi_line, chi_cont, B, reg->d_pack.p);
+      vrt::launch_vertical_line<double>(s, ncol, reg->nz, n_lambda, z, static_cast<const double *>(phi),
+                                        reg->d_pack.p, B, static_cast<const double *>(I_bottom),
+                                        static_cast<double *>(I_top));
+    }
+    return VRT_OK;
+  });
+}
+
+vrt_status vrt_lc_vertical(vrt_grid reg, vrt_prec prec, int32_t n_lambda, const void *chi, const void *S,
+                           const void *I_bottom, void *I_top) {
+  if (!reg) return VRT_E_ARG;
+  return guarded(reg->ctx, [&] {
+    if (reg->kind != 1) fail(VRT_E_ARG, "expected a regular grid");
+    if (!valid_prec(prec) || n_lambda <= 0 || !chi || !S || !I_top) fail(VRT_E_ARG, "bad arguments");
+    hipStream_t s = reg->ctx->stream;
+    const int64_t ncol = (int64_t)reg->nx * reg->ny;
+    const double *z = reg->d_z.as<double>();
+    if (prec == VRT_F32)
+      vrt::launch_vertical_plain<float>(s, ncol, reg->nz, n_lambda, z, static_cast<const float *>(chi),
+                                        static_cast<const float *>(S), static_cast<const float *>(I_bottom),
+                                        static_cast<float *>(I_top));
+    else
+      vrt::launch_vertical_plain<double>(s, ncol, reg->nz, n_lambda, z, static_cast<const double *>(chi),
+                                         static_cast<const double *>(S), static_cast<const double *>(I_bottom),
+                                         static_cast<double *>(I_top));
+    return VRT_OK;
+  });
+}
+
 }  // extern "C"

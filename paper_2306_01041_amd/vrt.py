@@ -111,6 +111,11 @@ vrt_lte_continuum_vjp = _sig("vrt_lte_continuum_vjp", _st, [_vp, ctypes.c_int32,
 vrt_grid_device_status = _sig("vrt_grid_device_status", _st, [_vp])
 vrt_grid_emergent_index = _sig("vrt_grid_emergent_index", _st, [_vp, _i64, _i32])
 vrt_emergent_gather = _sig("vrt_emergent_gather", _st, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp])
+vrt_idw_map = _sig("vrt_idw_map", _st, [_vp, _vp, ctypes.c_double, _vp, _vp, _vp])
+vrt_idw_apply = _sig("vrt_idw_apply", _st, [_vp, _vp, ctypes.c_int32, _vp, _vp, _vp, _vp])
+vrt_synthesis_vertical = _sig("vrt_synthesis_vertical", _st, [_vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp,
+                                                              _vp, _vp, _vp, _vp, _vp, _vp])
+vrt_lc_vertical = _sig("vrt_lc_vertical", _st, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp])
 
 EXPORTED = [n for n in dir() if n.startswith("vrt_")]
 
@@ -242,7 +247,9 @@ class Grid:
         h = _vp()
         ctx.check(vrt_grid_create_regular(ctx.handle, int(nx), int(ny), len(z), float(dx), float(dy), _p(z, _d),
                                           ctypes.byref(h)))
-        return cls(ctx, h, "regular")
+        g = cls(ctx, h, "regular")
+        g.z = z.copy()
+        return g
 
     def set_rays(self, dirs, w, r_exp: float = 7.0):
         dirs = np.ascontiguousarray(dirs, np.float64)
@@ -554,3 +561,93 @@ def lte_emergent(T, rho, grid: Grid, lam, kappa0, dtype=None, keep_intensities=T
         _LTE_EMERGENT = _make_lte_emergent()
     return _LTE_EMERGENT.apply(T, rho, grid, lam, kappa0, torch.float32 if dtype is None else dtype,
                                keep_intensities, ray_group, emergent_dtype)
+
+
+# ----------------------------------------------------------------------------
+# final synthesis on the regular grid
+# ----------------------------------------------------------------------------
+
+def _pair(voronoi: Grid, regular: Grid):
+    if voronoi.kind != "voronoi" or regular.kind != "regular":
+        raise ValueError("expected a Voronoi grid and a regular grid")
+    return voronoi.info()["n_sites"], regular.info()["n_sites"]
+
+
+def idw_map(voronoi: Grid, regular: Grid, power: float = 1.0, with_d2: bool = False):
+    """Two nearest Voronoi sites of every regular point and the inverse-distance
+    weight of the nearer one: (idx int32 [m, 2], w1 float64 [m][, d2 [m, 2]]) on
+    the GPU. Blocks."""
+    import torch
+
+    _, m = _pair(voronoi, regular)
+    dev = torch.device("cuda", regular.ctx.device)
+    idx = torch.empty((m, 2), dtype=torch.int32, device=dev)
+    w1 = torch.empty(m, dtype=torch.float64, device=dev)
+    d2 = torch.empty((m, 2), dtype=torch.float64, device=dev) if with_d2 else None
+    regular.ctx.check(vrt_idw_map(voronoi.handle, regular.handle, float(power), _dev(idx), _dev(w1), _dev(d2)))
+    return (idx, w1, d2) if with_d2 else (idx, w1)
+
+
+def idw_apply(voronoi: Grid, regular: Grid, idx, w1, src, dst=None):
+    """Interpolate src (float64 [n_sites] or [n_sites, k]) to the regular points."""
+    import torch
+
+    n, m = _pair(voronoi, regular)
+    k = 1 if src.dim() == 1 else src.shape[1]
+    _need(idx, (m, 2), torch.int32, "idx")
+    _need(w1, (m,), torch.float64, "w1")
+    _need(src, (n,) if src.dim() == 1 else (n, k), torch.float64, "src")
+    shape = (m,) if src.dim() == 1 else (m, k)
+    if dst is None:
+        dst = torch.empty(shape, dtype=torch.float64, device=src.device)
+    _need(dst, shape, torch.float64, "dst")
+    regular.ctx.check(vrt_idw_apply(voronoi.handle, regular.handle, int(k), _dev(idx), _dev(w1), _dev(src),
+                                    _dev(dst)))
+    return dst
+
+
+def synthesis_vertical(voronoi: Grid, regular: Grid, idx, w1, S_line, phi, chi_line, chi_cont, B, I_bottom=None,
+                       out=None):
+    """Emergent line intensity at mu = 1, [ny nx, n_lambda] in phi's dtype, from
+    S_line on the Voronoi sites and the line data on the regular points."""
+    import torch
+
+    n, m = _pair(voronoi, regular)
+    if phi.dim() != 2:
+        raise ValueError("phi must be [n_points, n_lambda]")
+    nl = phi.shape[1]
+    ncol = m // len(regular.z)
+    _need(idx, (m, 2), torch.int32, "idx")
+    _need(w1, (m,), torch.float64, "w1")
+    _need(S_line, (n,), torch.float64, "S_line")
+    _need(phi, (m, nl), phi.dtype, "phi")
+    for t, name in ((chi_line, "chi_line"), (chi_cont, "chi_cont"), (B, "B")):
+        _need(t, (m,), torch.float64, name)
+    _need(I_bottom, (ncol, nl), phi.dtype, "I_bottom")
+    if out is None:
+        out = torch.empty((ncol, nl), dtype=phi.dtype, device=phi.device)
+    _need(out, (ncol, nl), phi.dtype, "out")
+    regular.ctx.check(vrt_synthesis_vertical(voronoi.handle, regular.handle, _prec_of(phi), int(nl), _dev(idx),
+                                             _dev(w1), _dev(S_line), _dev(phi), _dev(chi_line), _dev(chi_cont),
+                                             _dev(B), _dev(I_bottom), _dev(out)))
+    return out
+
+
+def lc_vertical(regular: Grid, chi, S, I_bottom=None, out=None):
+    """Intensity at the top of every column at mu = 1 for chi, S [n_points, n_lambda]."""
+    m = regular.info()["n_sites"]
+    if chi.dim() != 2:
+        raise ValueError("chi must be [n_points, n_lambda]")
+    nl = chi.shape[1]
+    ncol = m // len(regular.z)
+    _need(chi, (m, nl), chi.dtype, "chi")
+    _need(S, (m, nl), chi.dtype, "S")
+    _need(I_bottom, (ncol, nl), chi.dtype, "I_bottom")
+    if out is None:
+        import torch
+
+        out = torch.empty((ncol, nl), dtype=chi.dtype, device=chi.device)
+    _need(out, (ncol, nl), chi.dtype, "out")
+    regular.ctx.check(vrt_lc_vertical(regular.handle, _prec_of(chi), int(nl), _dev(chi), _dev(S), _dev(I_bottom),
+                                      _dev(out)))
+    return out

@@ -24,6 +24,7 @@ the HIP library.
 
 from __future__ import annotations
 
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass
 
 import numpy as np
@@ -36,6 +37,7 @@ C_LIGHT = 299792458.0
 K_BOLTZMANN = 1.380649e-23
 M_H = 1.6735575e-27  # kg, hydrogen atom
 XI_MICRO = 2.0e3     # m/s
+_ROWS = 65536        # sites per block of the profile table
 
 
 def doppler_width_nm(T, lam0_nm=LAMBDA0_NM, xi=XI_MICRO):
@@ -53,7 +55,10 @@ class LineSetup:
     damping: float
 
 
-def line_setup(T, rho, n_lambda: int = 101, damping: float = 0.01, half_width: float = 5.0) -> LineSetup:
+def line_setup(T, rho, n_lambda: int = 101, damping: float = 0.01, half_width: float = 5.0,
+               workers: int = 1) -> LineSetup:
+    """Line data of every site; `workers` threads fill row blocks of phi (the
+    result does not depend on it)."""
     T = np.asarray(T, dtype=np.float64)
     rho = np.asarray(rho, dtype=np.float64)
     dl_ref = float(doppler_width_nm(6500.0))
@@ -63,9 +68,21 @@ def line_setup(T, rho, n_lambda: int = 101, damping: float = 0.01, half_width: f
         wl[0] *= 0.5
         wl[-1] *= 0.5
     dl = doppler_width_nm(T)
-    # H(a, v)/(sqrt(pi) dl) equals the normalised Voigt profile with Gaussian sigma = dl/sqrt(2), Lorentz gamma = a dl
-    phi = voigt_profile((lam[None, :] - LAMBDA0_NM), dl[:, None] / np.sqrt(2.0), damping * dl[:, None])
-    phi /= np.sum(wl[None, :] * phi, axis=1)[:, None]
+    phi = np.empty((len(T), n_lambda), np.float64)
+
+    def rows(a):
+        b = min(a + _ROWS, len(T))
+        # H(a, v)/(sqrt(pi) dl) is the normalised Voigt profile with Gaussian sigma = dl/sqrt(2), Lorentz gamma = a dl
+        p = voigt_profile((lam[None, :] - LAMBDA0_NM), dl[a:b, None] / np.sqrt(2.0), damping * dl[a:b, None])
+        phi[a:b] = p / np.sum(wl[None, :] * p, axis=1)[:, None]
+
+    starts = range(0, len(T), _ROWS)
+    if workers > 1:
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            list(ex.map(rows, starts))
+    else:
+        for a in starts:
+            rows(a)
     # line-centre tau = 1 at 1.5 Mm on the unperturbed stratification
     T_top = float(T0_of_z(1.5 * MM))
     dlt = float(doppler_width_nm(T_top))

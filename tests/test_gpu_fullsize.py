@@ -11,7 +11,10 @@ times (FP32 sweeps, graph-launched, default launch layout):
   the FP64 forward on 64 random sites each for T and rho, and against the
   oracle's gradient;
 * one two-level Lambda iteration on the 1,048,576-site grid with the
-  101-point line, against the oracle's iteration.
+  101-point line, against the oracle's iteration;
+* the final synthesis from the 262,144-site grid to the regular 128 x 128 x
+  256 grid with the 101-point line: the nearest sites of 4,096 sampled points
+  bit for bit and the mu = 1 emergent intensity of 64 sampled columns.
 
 Each case prints what it is about to run and the errors it finds.
 """
@@ -266,3 +269,54 @@ def test_c2_one_iteration_full_size(v, ctx):
     assert nit == 1 and st == v.VRT_W_NOT_CONVERGED
     assert e <= 1e-5
     assert abs(hist[0] - hist_o[0]) <= 3e-5
+
+
+def test_c1_synthesis_full_size(v, ctx, c1):
+    atm, g, _, _, _ = c1
+    nx = ny = 128
+    nz = 256
+    box = atm.box
+    dx = (box.hi[0] - box.lo[0]) / nx
+    dy = (box.hi[1] - box.lo[1]) / ny
+    z = box.lo[2] + (box.hi[2] - box.lo[2]) * np.arange(nz) / (nz - 1)
+    t0 = time.time()
+    pts = oracle.regular_points(nx, ny, dx, dy, z)
+    reg = synth.make_atmosphere(len(pts), seed=SEED, xyz=pts)
+    line = line_setup(reg.T, reg.rho, n_lambda=101, workers=16)
+    lam0 = np.array([LAMBDA0_NM * 1e-9])
+    chi_c, B = oracle.lte(lam0, reg.kappa0, reg.T, reg.rho)
+    chi_c, B = chi_c[:, 0], B[:, 0]
+    _, Bs = oracle.lte(lam0, atm.kappa0, atm.T, atm.rho)
+    rng = np.random.default_rng(SEED + 7)
+    S_line = Bs[:, 0] * (0.5 + rng.random(g.n))
+    flush(f"c1 synthesis: 262,144 sites -> 128x128x256 points, 101 wavelengths; inputs in {time.time() - t0:.1f} s")
+    G = v.Grid.from_synth(ctx, g)
+    R = v.Grid.regular(ctx, nx, ny, z, dx, dy)
+    idx, w1, d2 = v.idw_map(G, R, with_d2=True)
+    idx, w1, d2 = idx.cpu().numpy(), w1.cpu().numpy(), d2.cpu().numpy()
+    assert idx.min() >= 0 and idx.max() < g.n and np.all(d2[:, 0] <= d2[:, 1])
+    assert np.all((w1 >= 0.5) & (w1 <= 1.0))
+    pick = rng.choice(len(pts), 4096, replace=False)
+    io, wo, d2o = oracle.idw2(g.xyz, pts[pick], g.lo, g.hi, True)
+    assert np.array_equal(idx[pick], io) and np.array_equal(d2[pick], d2o)
+    assert relerr(w1[pick], wo) <= 1e-12
+    flush("  nearest sites of 4,096 sampled points match the oracle bit for bit")
+    f64 = torch.float64
+    args = [to_dev(S_line, f64), None, to_dev(line.chi_line, f64), to_dev(chi_c, f64), to_dev(B, f64)]
+    idx_d, w1_d = to_dev(idx, torch.int32), to_dev(w1, f64)
+    # the oracle's own interpolation on every point of 64 sampled columns
+    ncol = nx * ny
+    cols = np.sort(rng.choice(ncol, 64, replace=False))
+    rows = (np.arange(nz)[:, None] * ncol + cols[None, :]).ravel()  # (plane, column) order
+    io, wo, _ = oracle.idw2(g.xyz, pts[rows], g.lo, g.hi, True)
+    chi_o, S_o = onl.assemble(chi_c[rows], line.chi_line[rows], line.phi[rows], B[rows], oracle.idw_apply(io, wo, S_line))
+    ref = oracle.lc_vertical(len(cols), z, chi_o, S_o, np.repeat(B[cols, None], 101, axis=1))
+    for dt, tol in ((torch.float32, 1e-5), (f64, 1e-12)):
+        args[1] = to_dev(line.phi, dt)
+        out = v.synthesis_vertical(G, R, idx_d, w1_d, *args).cpu().numpy()
+        e = relerr(out[cols], ref)
+        flush(f"  {dt} synthesis: max rel err over 64 columns {e:.3e}")
+        assert e <= tol
+        args[1] = None
+    G.close()
+    R.close()

@@ -18,6 +18,10 @@ Printed as one JSON line with, besides the headline value:
                their ratio;
   regular_grid the same formal solution on the regular 128 x 128 x 256 grid
                (short characteristics), FP32 graph-launched and plain FP64;
+  synthesis    the final synthesis from the Voronoi grid to that regular grid
+               with the 101-point line: the nearest-site map (once per grid
+               pair) and the mu = 1 long-characteristics line synthesis in FP32
+               and FP64, with its algorithmic HBM rate;
   cpu_baseline the FP64 CPU oracle timed on this host on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--sites N] [--no-cpu]
@@ -81,12 +85,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 GPU baseline")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing")
-    ap.add_argument("--no-regular", action="store_true", help="skip the regular-grid timing")
+    ap.add_argument("--no-regular", action="store_true", help="skip the regular-grid and synthesis timings")
+    ap.add_argument("--no-synthesis", action="store_true", help="skip the final-synthesis timing")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the grid's default launch layout (for profiler runs that average over dispatches)")
-    ap.add_argument("--workload", choices=["c1", "c2", "c3"], default="c1",
+    ap.add_argument("--workload", choices=["c1", "c2", "c3", "synth"], default="c1",
                     help="c1: the formal solution (default line); c2: the two-level Lambda iteration on 1,048,576 "
-                         "sites; c3: 48 atmospheres of 32,768-524,288 sites solved as one batch")
+                         "sites; c3: 48 atmospheres of 32,768-524,288 sites solved as one batch; synth: only the "
+                         "final synthesis from the 262,144-site grid to the regular 128 x 128 x 256 grid")
     ap.add_argument("--accel", action="store_true",
                     help="c2/c3: the Jacobi-accelerated iteration (local operator) instead of the plain one")
     ap.add_argument("--max-iter", type=int, default=None,
@@ -109,6 +115,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "synth":
+        run_synthesis_only(args)
+        return
     if args.workload != "c1":
         run_lambda(args)
         return
@@ -303,16 +312,12 @@ def main():
     # the regular 128 x 128 x 256 grid of the same recipe (short characteristics):
     # FP32 graph-launched and plain FP64, 64 wavelengths, 24 rays
     regular = None
+    synthesis = None
     if not args.no_regular:
         del chi, S, J
         nx = ny = 128
         nz = 256
-        box = atm.box
-        dxr = (box.hi[0] - box.lo[0]) / nx
-        dyr = (box.hi[1] - box.lo[1]) / ny
-        zr = box.lo[2] + (box.hi[2] - box.lo[2]) * np.arange(nz) / (nz - 1)
-        X, Y, Z = np.meshgrid(box.lo[0] + dxr * np.arange(nx), box.lo[1] + dyr * np.arange(ny), zr, indexing="xy")
-        xyz = np.stack([a.transpose(2, 0, 1).ravel() for a in (X, Y, Z)], 1)  # site (k * ny + j) * nx + i
+        dxr, dyr, zr, xyz = regular_recipe(atm.box, nx, ny, nz)
         atr = synth.make_atmosphere(len(xyz), seed=seed, xyz=xyz)
         Gr = v.Grid.regular(ctx, nx, ny, zr, dxr, dyr)
         Gr.set_rays(dirs, w)
@@ -337,6 +342,8 @@ def main():
             log(f"regular grid {name}: {ms_r:.2f} ms -> {ur / (ms_r * 1e-3):.3e} updates/s")
             del chr_, Sr, Jr
         regular["speedup_fp32_graph"] = round(regular["fp64_plain"]["ms"] / regular["fp32_graph"]["ms"], 2)
+        if not args.no_synthesis:
+            synthesis = run_synthesis(v, G, Gr, g, atm, atr, nx, ny, zr, stream)
         Gr.close()
 
     # CPU oracle on a bounded sample: the same formal solution (all sites, rays and
@@ -390,6 +397,7 @@ def main():
         "fp64_plain": fp64,
         "adjoint": adjoint,
         "regular_grid": regular,
+        "synthesis": synthesis,
         "cpu_baseline": cpu,
         "setup_s": round(setup_s, 3),
         "tuning": tuning,
@@ -398,6 +406,111 @@ def main():
     G.close()
     ctx.close()
     del stream
+
+
+def synthesis_bytes(m, ncol, nl, fp):
+    """Algorithmic HBM bytes of one line synthesis on m regular points: the
+    packing pass reads the two site indices and the weight (16 B), chi_line,
+    chi_cont and B (24 B) and two S_line values (16 B) and writes 4 values per
+    point; the column pass reads the profile (m nl values) and the packed
+    point data once and writes the top-plane intensities."""
+    pack = m * (16 + 24 + 16 + 4 * fp)
+    columns = m * nl * fp + m * 4 * fp + ncol * nl * fp
+    return pack + columns
+
+
+def run_synthesis(v, G, Gr, g, atm, atr, nx, ny, zr, stream):
+    """Final synthesis (the paper's last step): S_line on the Voronoi sites is
+    carried to the regular points by two-nearest-site inverse-distance weights
+    and the emergent line intensity at mu = 1 follows from long characteristics
+    up every column. S_line is B times a seeded factor (the timing does not
+    depend on the values)."""
+    import torch
+
+    import oracle
+    from synth.nlte import LAMBDA0_NM, line_setup
+
+    dev = "cuda:0"
+    nl = 101
+    m = len(atr.T)
+    ncol = nx * ny
+    t0 = time.time()
+    line = line_setup(atr.T, atr.rho, n_lambda=nl, workers=16)
+    lam0 = np.array([LAMBDA0_NM * 1e-9])
+    # the grey continuum at line centre is an input here, as in the tests
+    chi_c, B = oracle.lte(lam0, atr.kappa0, atr.T, atr.rho)
+    _, Bs = oracle.lte(lam0, atm.kappa0, atm.T, atm.rho)
+    S_line = Bs[:, 0] * (0.5 + np.random.default_rng(1048).random(g.n))
+    log(f"synthesis inputs built in {time.time() - t0:.1f} s")
+    f64 = torch.float64
+    d = {k: torch.as_tensor(np.ascontiguousarray(a), dtype=f64, device=dev)
+         for k, a in (("S", S_line), ("chiL", line.chi_line), ("chic", chi_c[:, 0]), ("B", B[:, 0]))}
+    v.idw_map(G, Gr)  # first call pays one-time costs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    idx, w1 = v.idw_map(G, Gr)
+    map_ms = (time.perf_counter() - t0) * 1e3
+    res = {"workload": f"final synthesis: S_line on {g.n} Voronoi sites -> regular {nx}x{ny}x{len(zr)} points "
+                       f"(two nearest sites, inverse distance), {nl}-point line, mu = 1 long characteristics",
+           "points": m, "columns": ncol, "wavelengths": nl, "idw_map_ms": round(map_ms, 3)}
+    for name, dt in (("fp32", torch.float32), ("fp64", f64)):
+        phi = torch.as_tensor(line.phi, dtype=dt, device=dev)
+        out = torch.empty((ncol, nl), dtype=dt, device=dev)
+        for _ in range(2):
+            v.synthesis_vertical(G, Gr, idx, w1, d["S"], phi, d["chiL"], d["chic"], d["B"], out=out)
+        reps = 10
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            v.synthesis_vertical(G, Gr, idx, w1, d["S"], phi, d["chiL"], d["chic"], d["B"], out=out)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        nbytes = synthesis_bytes(m, ncol, nl, 4 if dt == torch.float32 else 8)
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        res[name] = {"ms": round(ms, 4), "point_lambda_per_s": m * nl / (ms * 1e-3),
+                     "algorithmic_bytes": nbytes, "achieved_GBs": round(gbs, 1),
+                     "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        log(f"synthesis {name}: {ms:.3f} ms -> {gbs:.0f} GB/s algorithmic ({gbs / HBM_PEAK_GBS:.2f} of HBM)")
+        del phi, out
+    log(f"nearest-site map of {m} points: {map_ms:.2f} ms")
+    return res
+
+
+def regular_recipe(box, nx=128, ny=128, nz=256):
+    """Spacings, planes and points of the regular grid over the recipe's box
+    (point (k ny + j) nx + i at (lo_x + i dx, lo_y + j dy, z_k))."""
+    dxr = (box.hi[0] - box.lo[0]) / nx
+    dyr = (box.hi[1] - box.lo[1]) / ny
+    zr = box.lo[2] + (box.hi[2] - box.lo[2]) * np.arange(nz) / (nz - 1)
+    X, Y, Z = np.meshgrid(box.lo[0] + dxr * np.arange(nx), box.lo[1] + dyr * np.arange(ny), zr, indexing="xy")
+    xyz = np.stack([a.transpose(2, 0, 1).ravel() for a in (X, Y, Z)], 1)
+    return dxr, dyr, zr, xyz
+
+
+def run_synthesis_only(args):
+    import torch
+
+    import paper_2306_01041_amd
+    import synth
+
+    v = paper_2306_01041_amd.load()
+    seed = 1041
+    t0 = time.time()
+    atm = synth.make_atmosphere(args.sites, seed=seed)
+    g = synth.voronoi_neighbours(atm.xyz, atm.box.lo, atm.box.hi)
+    nx = ny = 128
+    dxr, dyr, zr, xyz = regular_recipe(atm.box, nx, ny, 256)
+    atr = synth.make_atmosphere(len(xyz), seed=seed, xyz=xyz)
+    log(f"grids built in {time.time() - t0:.1f} s")
+    ctx = v.Context(0)
+    G = v.Grid.from_synth(ctx, g)
+    Gr = v.Grid.regular(ctx, nx, ny, zr, dxr, dyr)
+    res = run_synthesis(v, G, Gr, g, atm, atr, nx, ny, zr, torch.cuda.current_stream())
+    print(json.dumps({"workload": "synth", "synthesis": res}))
+    Gr.close()
+    G.close()
+    ctx.close()
 
 
 def _make_grid(args):

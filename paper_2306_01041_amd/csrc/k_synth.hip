@@ -150,8 +150,12 @@ template <typename T> struct Vec4;
 template <> struct Vec4<float> { using type = float4; };
 template <> struct Vec4<double> { using type = double4; };
 
-// Per regular point: (chi_line, chi_cont, chi_cont * B, S_line interpolated
-// from the two nearest sites), in the precision of the column integration.
+// Per regular point: (chi_line, chi_cont, chi_cont (B - S_line), S_line), with
+// S_line interpolated from the two nearest sites, formed in double precision
+// and stored in the precision of the column pass. With chi = chi_cont +
+// chi_line phi, the source (chi_line phi S_line + chi_cont B) / chi equals
+// S_line + chi_cont (B - S_line) / chi, which costs one fused multiply-add and
+// one quotient per wavelength.
 template <typename T>
 __global__ __launch_bounds__(256) void line_pack_kernel(int64_t m, int64_t n_src, const int32_t *__restrict__ idx,
                                                         const double *__restrict__ w1,
@@ -171,10 +175,47 @@ __global__ __launch_bounds__(256) void line_pack_kernel(int64_t m, int64_t n_src
   typename Vec4<T>::type v;
   v.x = (T)chi_L[p];
   v.y = (T)chi_c[p];
-  v.z = (T)(chi_c[p] * B[p]);
+  v.z = (T)(chi_c[p] * (B[p] - SL));
   v.w = (T)SL;
   pack[p] = v;
 }
+
+// Quotient a / b: IEEE division in double precision; in single precision the
+// hardware reciprocal (about 1 ulp) times a, which is what the column pass can
+// afford per (point, wavelength, plane).
+__device__ __forceinline__ double quot(double a, double b) { return a / b; }
+__device__ __forceinline__ float quot(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
+// One linear-source step up a column, I <- e^-x I + Psi_u S_u + Psi_0 S_0.
+// Double precision uses the shared segment weights in that form. Single
+// precision uses the equivalent I <- S_u + e^-x (I - S_u) + Psi_0 (S_0 - S_u)
+// (Psi_u = 1 - e^-x - Psi_0), which needs only e^-x and Psi_0 and keeps the
+// rounding proportional to the differences; it evaluates both forms of Psi_0
+// and selects, because the lanes of one wavefront hold different wavelengths,
+// so optically thin and thick segments sit side by side and a branch would run
+// both sides anyway: the series sum_{n=1..5} (-1)^(n+1) x^n/(n+1)! below
+// x = 1/10 (the first omitted term is below 1e-8 of Psi_0 there) and
+// 1 - (1 - e^-x)/x above, with e^-x from the hardware base-2 exponential.
+template <typename T> struct ColumnStep {
+  static __device__ __forceinline__ T advance(T I, T x, T Su, T S0) {
+    T E, pu, p0;
+    vrt::Seg<T>::weights(x, E, pu, p0);
+    return E * I + pu * Su + p0 * S0;
+  }
+};
+template <> struct ColumnStep<float> {
+  static __device__ __forceinline__ float advance(float I, float x, float Su, float S0) {
+    const float E = __builtin_amdgcn_exp2f(-x * 1.44269504088896341f);
+    float s = 1.0f / 720.0f;
+    s = s * x - 1.0f / 120.0f;
+    s = s * x + 1.0f / 24.0f;
+    s = s * x - 1.0f / 6.0f;
+    s = s * x + 0.5f;
+    const float closed = 1.0f - (1.0f - E) * __builtin_amdgcn_rcpf(x);
+    const float p0 = x < 0.1f ? s * x : closed;
+    return Su + E * (I - Su) + p0 * (S0 - Su);
+  }
+};
 
 // Opacity and source of one (point, wavelength).
 template <typename T> struct LineSource {
@@ -182,9 +223,8 @@ template <typename T> struct LineSource {
   const typename Vec4<T>::type *pack;
   __device__ __forceinline__ void at(int64_t p, int64_t pl, T &chi, T &S) const {
     const typename Vec4<T>::type v = pack[p];
-    const T lo = v.x * phi[pl];
-    chi = v.y + lo;
-    S = (lo * v.w + v.z) / chi;
+    chi = v.y + v.x * phi[pl];
+    S = v.w + quot(v.z, chi);
   }
 };
 
@@ -217,7 +257,7 @@ __global__ __launch_bounds__(256) void vertical_kernel(int64_t ncol, int32_t nz,
   T chi0, S0;
   src.at(c, t, chi0, S0);
   T I = Ib ? Ib[t] : default_bottom(src, B, c, S0);
-  constexpr int U = sizeof(T) == 4 ? 4 : 2;  // planes whose inputs are loaded before they are integrated
+  constexpr int U = sizeof(T) == 4 ? 8 : 2;  // planes whose inputs are loaded before they are integrated
   int32_t k = 1;
   for (; k + U <= nz; k += U) {
     T chi1[U], S1[U];
@@ -225,10 +265,8 @@ __global__ __launch_bounds__(256) void vertical_kernel(int64_t ncol, int32_t nz,
     for (int u = 0; u < U; ++u) src.at((int64_t)(k + u) * ncol + c, (int64_t)(k + u) * plane + t, chi1[u], S1[u]);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const T x = (T)0.5 * (chi0 + chi1[u]) * (T)(z[k + u] - z[k + u - 1]);
-      T E, pu, p0;
-      vrt::Seg<T>::weights(x, E, pu, p0);
-      I = E * I + pu * S0 + p0 * S1[u];
+      const T x = (chi0 + chi1[u]) * (T)(0.5 * (z[k + u] - z[k + u - 1]));
+      I = ColumnStep<T>::advance(I, x, S0, S1[u]);
       chi0 = chi1[u];
       S0 = S1[u];
     }
@@ -236,10 +274,8 @@ __global__ __launch_bounds__(256) void vertical_kernel(int64_t ncol, int32_t nz,
   for (; k < nz; ++k) {
     T chi1, S1;
     src.at((int64_t)k * ncol + c, (int64_t)k * plane + t, chi1, S1);
-    const T x = (T)0.5 * (chi0 + chi1) * (T)(z[k] - z[k - 1]);
-    T E, pu, p0;
-    vrt::Seg<T>::weights(x, E, pu, p0);
-    I = E * I + pu * S0 + p0 * S1;
+    const T x = (chi0 + chi1) * (T)(0.5 * (z[k] - z[k - 1]));
+    I = ColumnStep<T>::advance(I, x, S0, S1);
     chi0 = chi1;
     S0 = S1;
   }

@@ -400,8 +400,8 @@ vrt_status vrt_emergent_gather(vrt_grid grid, vrt_prec prec, int32_t n_lambda, c
  *   m = nx ny nz. The search walks the neighbour lists, so they must hold
  *   every face neighbour (as vrt_grid_create_voronoi expects).
  * Both grids must share a context. A periodic Voronoi grid needs the same
- * periods (nx dx = Lx, ny dy = Ly within 1e-9) and a box starting within one
- * period of x = y = 0; a non-periodic one must contain every point in x and
+ * periods (nx dx = Lx, ny dy = Ly within 1e-9) and a box starting within half
+ * a period of x = y = 0; a non-periodic one must contain every point in x and
  * y; the planes must lie inside [lo[2], hi[2]] (VRT_E_ARG otherwise).
  * Returns VRT_E_GRID if a walk does not settle (incomplete neighbour lists).
  * Blocks. */

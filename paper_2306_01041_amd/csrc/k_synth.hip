@@ -16,9 +16,10 @@
 // site, until it touches the first gives an empty ball through both, whose
 // centre lies inside the (convex) box. So the scan of the nearest site's list
 // that confirms the walk's end also yields the second site. Points are
-// processed coarse to fine (strides 64, 16, 4, 1 in each direction); each
-// point starts from the nearest site of its coarse parent, so walks are a few
-// steps long. Distances use the same operations in the same order as their
+// processed coarse to fine: the points of a coarse lattice (at most 64 of
+// them) by brute force over all sites, then lattices of half the stride down
+// to every point, each new point walking from the nearest site of its parent
+// on the previous lattice, so walks are a few steps long. Distances use the same operations in the same order as their
 // definition and no fused multiply-add, so the chosen sites are reproducible
 // on any IEEE-754 machine.
 //
@@ -32,30 +33,75 @@
 
 namespace {
 
-// d reduced into [-L/2, L/2] by whole periods; the host guarantees |d| < 2L + L/2
+// d reduced into [-L/2, L/2] by one period: the host guarantees that points
+// lie in [0, L) and the box starts within half a period of 0, so |d| < 3L/2
+// and one shift suffices (the same result as repeated shifts)
 __device__ __forceinline__ double wrap_period(double d, int periodic, double L) {
-  if (!periodic) return d;
   const double h = 0.5 * L;
-#pragma unroll
-  for (int r = 0; r < 3; ++r)
-    if (d > h) d -= L;
-#pragma unroll
-  for (int r = 0; r < 3; ++r)
-    if (d < -h) d += L;
-  return d;
+  const double up = d < -h ? d + L : d;
+  return periodic ? (d > h ? d - L : up) : d;
+}
+
+__device__ __forceinline__ double point_dist2(double px, double py, double pz, double sx, double sy, double sz,
+                                              int periodic, double Lx, double Ly) {
+#pragma clang fp contract(off)
+  const double dx = wrap_period(px - sx, periodic, Lx);
+  const double dy = wrap_period(py - sy, periodic, Ly);
+  const double dz = pz - sz;
+  return dx * dx + dy * dy + dz * dz;
 }
 
 __device__ __forceinline__ double site_dist2(double px, double py, double pz, const double *__restrict__ xyz,
                                              int32_t s, int periodic, double Lx, double Ly) {
-#pragma clang fp contract(off)
-  const double dx = wrap_period(px - xyz[3 * (int64_t)s + 0], periodic, Lx);
-  const double dy = wrap_period(py - xyz[3 * (int64_t)s + 1], periodic, Ly);
-  const double dz = pz - xyz[3 * (int64_t)s + 2];
-  return dx * dx + dy * dy + dz * dz;
+  return point_dist2(px, py, pz, xyz[3 * (int64_t)s + 0], xyz[3 * (int64_t)s + 1], xyz[3 * (int64_t)s + 2],
+                     periodic, Lx, Ly);
 }
 
 __device__ __forceinline__ bool key_less(double da, int32_t ia, double db, int32_t ib) {
   return da < db || (da == db && ia < ib);
+}
+
+// entries of a neighbour list, or sites of a brute-force scan, loaded together
+constexpr int kScan = 8;
+
+// insert (site s, key d) into the two smallest keys so far (s < 0: nothing)
+__device__ __forceinline__ void top2_insert(int32_t s, double d, int32_t &b1, double &e1, int32_t &b2, double &e2) {
+  if (s < 0) return;
+  if (b1 < 0 || key_less(d, s, e1, b1)) {
+    b2 = b1;
+    e2 = e1;
+    b1 = s;
+    e1 = d;
+  } else if (b2 < 0 || key_less(d, s, e2, b2)) {
+    b2 = s;
+    e2 = d;
+  }
+}
+
+// Weight of the nearer site, u_k = d_k^-power normalised: w1 = a_2/(a_1 + a_2)
+// with a_k = (d2_k)^(power/2), 1 when the point is a site; a lone site is its
+// own second neighbour.
+__device__ __forceinline__ void store_pair(int64_t p, int32_t i1, double e1, int32_t i2, double e2, double power,
+                                           int32_t *__restrict__ idx, double *__restrict__ w1,
+                                           double *__restrict__ d2) {
+  double w = 1.0;
+  if (i1 < 0) {
+    i2 = -1;
+    w = __builtin_nan("");
+  } else if (i2 < 0) {
+    i2 = i1;
+    e2 = e1;
+  } else {
+    const double a1 = pow(e1, 0.5 * power), a2 = pow(e2, 0.5 * power);
+    if (a1 + a2 > 0.0) w = a2 / (a1 + a2);
+  }
+  idx[2 * p + 0] = i1;
+  idx[2 * p + 1] = i2;
+  w1[p] = w;
+  if (d2) {
+    d2[2 * p + 0] = e1;
+    d2[2 * p + 1] = e2;
+  }
 }
 
 __global__ __launch_bounds__(256) void idw_level_kernel(int32_t nx, int32_t ny, int32_t nz, double dx, double dy,
@@ -89,13 +135,28 @@ __global__ __launch_bounds__(256) void idw_level_kernel(int32_t nx, int32_t ny, 
   for (int64_t it = 0; it < n; ++it) {
     int32_t b = -1;
     double db = 0.0;
-    for (int64_t e = ptr[cur]; e < ptr[cur + 1]; ++e) {
-      const int32_t s = nbr[e];
-      if (s == cur) continue;  // a periodic image of the site itself
-      const double d = site_dist2(px, py, pz, xyz, s, periodic, Lx, Ly);
-      if (b < 0 || key_less(d, s, db, b)) {
-        b = s;
-        db = d;
+    // the list is read kScan entries at a time, all indices and then all
+    // coordinates of a batch in flight together
+    const int64_t e_end = ptr[cur + 1];
+    for (int64_t e0 = ptr[cur]; e0 < e_end; e0 += kScan) {
+      int32_t sn[kScan];
+      double sx[kScan], sy[kScan], sz[kScan];
+#pragma unroll
+      for (int u = 0; u < kScan; ++u) sn[u] = e0 + u < e_end ? nbr[e0 + u] : cur;
+#pragma unroll
+      for (int u = 0; u < kScan; ++u) {
+        sx[u] = xyz[3 * (int64_t)sn[u] + 0];
+        sy[u] = xyz[3 * (int64_t)sn[u] + 1];
+        sz[u] = xyz[3 * (int64_t)sn[u] + 2];
+      }
+#pragma unroll
+      for (int u = 0; u < kScan; ++u) {
+        if (sn[u] == cur) continue;  // past the list's end, or a periodic image of the site itself
+        const double d = point_dist2(px, py, pz, sx[u], sy[u], sz[u], periodic, Lx, Ly);
+        if (b < 0 || key_less(d, sn[u], db, b)) {
+          b = sn[u];
+          db = d;
+        }
       }
     }
     if (b >= 0 && key_less(db, b, dc, cur)) {
@@ -109,25 +170,117 @@ __global__ __launch_bounds__(256) void idw_level_kernel(int32_t nx, int32_t ny, 
     e2 = db;
     break;
   }
-  double w = 1.0;
-  if (i1 < 0) {
-    *bad = 1;  // the walk did not settle: the neighbour lists are not a Voronoi diagram
-    i1 = i2 = -1;
-    w = __builtin_nan("");
-  } else if (i2 < 0) {
-    i2 = i1;
-    e2 = e1;
-  } else {
-    const double a1 = pow(e1, 0.5 * power), a2 = pow(e2, 0.5 * power);
-    if (a1 + a2 > 0.0) w = a2 / (a1 + a2);
+  if (i1 < 0) *bad = 1;  // the walk did not settle: the neighbour lists are not a Voronoi diagram
+  store_pair(p, i1, e1, i2, e2, power, idx, w1, d2);
+}
+
+// Two nearest sites of the points on one lattice by brute force, in two
+// passes. First every workgroup takes kBrutePts points and one chunk of
+// kBruteChunk sites: each thread reads a strided share of the chunk's sites
+// once and keeps, for every one of the points, the two smallest keys; a tree
+// merge in LDS per point leaves the chunk's two. Then one thread per point
+// merges its chunks.
+constexpr int64_t kBruteChunk = 8192;
+constexpr int kBrutePts = 8;
+
+__global__ __launch_bounds__(256) void idw_brute_partial_kernel(int32_t nx, int32_t ny, double dx, double dy,
+                                                                const double *__restrict__ z, int32_t stride,
+                                                                int64_t n_pts, int64_t n, int64_t n_chunks,
+                                                                const double *__restrict__ xyz, int periodic,
+                                                                double Lx, double Ly, int32_t *__restrict__ pb,
+                                                                double *__restrict__ pe) {
+  __shared__ double se1[256], se2[256];
+  __shared__ int32_t sb1[256], sb2[256];
+  const int64_t cx = (nx + stride - 1) / stride, cy = (ny + stride - 1) / stride;
+  const int64_t blk = blockIdx.x;
+  const int64_t g = blk / n_chunks, c = blk - g * n_chunks;
+  double px[kBrutePts], py[kBrutePts], pz[kBrutePts];
+  int32_t b1[kBrutePts], b2[kBrutePts];
+  double e1[kBrutePts], e2[kBrutePts];
+#pragma unroll
+  for (int u = 0; u < kBrutePts; ++u) {
+    // points past the lattice repeat its last point (their results are not stored)
+    const int64_t q = g * kBrutePts + u < n_pts ? g * kBrutePts + u : n_pts - 1;
+    px[u] = (double)((int32_t)(q % cx) * stride) * dx;
+    py[u] = (double)((int32_t)((q / cx) % cy) * stride) * dy;
+    pz[u] = z[(q / (cx * cy)) * stride];
+    b1[u] = b2[u] = -1;
+    e1[u] = e2[u] = 0.0;
   }
-  idx[2 * p + 0] = i1;
-  idx[2 * p + 1] = i2;
-  w1[p] = w;
-  if (d2) {
-    d2[2 * p + 0] = e1;
-    d2[2 * p + 1] = e2;
+  const int64_t end = (c + 1) * kBruteChunk < n ? (c + 1) * kBruteChunk : n;
+  // kScan sites per thread in flight at a time
+  for (int64_t s0 = c * kBruteChunk + threadIdx.x; s0 < end; s0 += kScan * blockDim.x) {
+    double sx[kScan], sy[kScan], sz[kScan];
+#pragma unroll
+    for (int v = 0; v < kScan; ++v) {
+      const int64_t s = s0 + v * blockDim.x < end ? s0 + v * blockDim.x : s0;
+      sx[v] = xyz[3 * s + 0];
+      sy[v] = xyz[3 * s + 1];
+      sz[v] = xyz[3 * s + 2];
+    }
+#pragma unroll
+    for (int v = 0; v < kScan; ++v) {
+      const int64_t s = s0 + v * blockDim.x;
+      if (s >= end) break;
+#pragma unroll
+      for (int u = 0; u < kBrutePts; ++u) {
+        const double d = point_dist2(px[u], py[u], pz[u], sx[v], sy[v], sz[v], periodic, Lx, Ly);
+        if (b2[u] < 0 || d <= e2[u]) top2_insert((int32_t)s, d, b1[u], e1[u], b2[u], e2[u]);
+      }
+    }
   }
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < kBrutePts; ++u) {
+    sb1[tid] = b1[u];
+    se1[tid] = e1[u];
+    sb2[tid] = b2[u];
+    se2[tid] = e2[u];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if (tid < h) {
+        int32_t a1 = sb1[tid], a2 = sb2[tid];
+        double f1 = se1[tid], f2 = se2[tid];
+        top2_insert(sb1[tid + h], se1[tid + h], a1, f1, a2, f2);
+        top2_insert(sb2[tid + h], se2[tid + h], a1, f1, a2, f2);
+        sb1[tid] = a1;
+        se1[tid] = f1;
+        sb2[tid] = a2;
+        se2[tid] = f2;
+      }
+      __syncthreads();
+    }
+    const int64_t q = g * kBrutePts + u;
+    if (tid == 0 && q < n_pts) {
+      const int64_t r = 2 * (q * n_chunks + c);
+      pb[r] = sb1[0];
+      pb[r + 1] = sb2[0];
+      pe[r] = se1[0];
+      pe[r + 1] = se2[0];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void idw_brute_merge_kernel(int32_t nx, int32_t ny, int32_t nz, int32_t stride,
+                                                              int64_t n_chunks, const int32_t *__restrict__ pb,
+                                                              const double *__restrict__ pe, double power,
+                                                              int32_t *__restrict__ idx, double *__restrict__ w1,
+                                                              double *__restrict__ d2) {
+  const int64_t cx = (nx + stride - 1) / stride, cy = (ny + stride - 1) / stride, cz = (nz + stride - 1) / stride;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= cx * cy * cz) return;
+  int32_t b1 = -1, b2 = -1;
+  double e1 = 0.0, e2 = 0.0;
+  for (int64_t c = 0; c < n_chunks; ++c) {
+    const int64_t r = 2 * (q * n_chunks + c);
+    top2_insert(pb[r], pe[r], b1, e1, b2, e2);
+    top2_insert(pb[r + 1], pe[r + 1], b1, e1, b2, e2);
+  }
+  const int32_t i = (int32_t)(q % cx) * stride;
+  const int32_t j = (int32_t)((q / cx) % cy) * stride;
+  const int32_t k = (int32_t)(q / (cx * cy)) * stride;
+  store_pair(((int64_t)k * ny + j) * nx + i, b1, e1, b2, e2, power, idx, w1, d2);
 }
 
 __global__ __launch_bounds__(256) void idw_apply_kernel(int64_t m, int32_t nc, int64_t n_src,
@@ -297,6 +450,27 @@ void launch_idw_level(hipStream_t s, int32_t nx, int32_t ny, int32_t nz, double 
   if (cnt == 0) return;
   idw_level_kernel<<<blocks_for(cnt), 256, 0, s>>>(nx, ny, nz, dx, dy, z, stride, parent, n, xyz, ptr, nbr,
                                                    periodic ? 1 : 0, Lx, Ly, power, idx, w1, d2, bad);
+  VRT_HIP(hipGetLastError());
+}
+
+int64_t idw_brute_scratch_pairs(int32_t nx, int32_t ny, int32_t nz, int32_t stride, int64_t n) {
+  const int64_t cnt = (int64_t)((nx + stride - 1) / stride) * ((ny + stride - 1) / stride) *
+                      ((nz + stride - 1) / stride);
+  return cnt * ((n + kBruteChunk - 1) / kBruteChunk);
+}
+
+void launch_idw_brute(hipStream_t s, int32_t nx, int32_t ny, int32_t nz, double dx, double dy, const double *z,
+                      int32_t stride, int64_t n, const double *xyz, bool periodic, double Lx, double Ly, double power,
+                      int32_t *idx, double *w1, double *d2, int32_t *pb, double *pe) {
+  const int64_t cnt = (int64_t)((nx + stride - 1) / stride) * ((ny + stride - 1) / stride) *
+                      ((nz + stride - 1) / stride);
+  const int64_t n_chunks = (n + kBruteChunk - 1) / kBruteChunk;
+  if (cnt == 0 || n_chunks == 0) return;
+  const int64_t groups = (cnt + kBrutePts - 1) / kBrutePts;
+  idw_brute_partial_kernel<<<(unsigned)(groups * n_chunks), 256, 0, s>>>(nx, ny, dx, dy, z, stride, cnt, n, n_chunks,
+                                                                          xyz, periodic ? 1 : 0, Lx, Ly, pb, pe);
+  VRT_HIP(hipGetLastError());
+  idw_brute_merge_kernel<<<blocks_for(cnt), 256, 0, s>>>(nx, ny, nz, stride, n_chunks, pb, pe, power, idx, w1, d2);
   VRT_HIP(hipGetLastError());
 }
 

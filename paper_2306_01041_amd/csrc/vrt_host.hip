@@ -1550,12 +1550,12 @@ vrt_status vrt_idw_map(vrt_grid vor, vrt_grid reg, double power, int32_t *idx, d
     const double X = (double)(reg->nx - 1) * reg->dx, Y = (double)(reg->ny - 1) * reg->dy;
     if (vor->periodic) {
       // one period in both grids, and boxes close enough that a difference of
-      // coordinates needs at most three period shifts
+      // coordinates needs at most one period shift
       if (std::fabs((double)reg->nx * reg->dx - Lx) > 1e-9 * Lx || std::fabs((double)reg->ny * reg->dy - Ly) > 1e-9 * Ly)
         fail(VRT_E_ARG, "the regular grid's periods (%g, %g) differ from the Voronoi box (%g, %g)",
              (double)reg->nx * reg->dx, (double)reg->ny * reg->dy, Lx, Ly);
-      if (std::fabs(vor->lo[0]) > Lx || std::fabs(vor->lo[1]) > Ly)
-        fail(VRT_E_ARG, "the Voronoi box must start within one period of x = y = 0");
+      if (std::fabs(vor->lo[0]) > 0.5 * Lx || std::fabs(vor->lo[1]) > 0.5 * Ly)
+        fail(VRT_E_ARG, "the Voronoi box must start within half a period of x = y = 0");
     } else if (vor->lo[0] > 0.0 || vor->lo[1] > 0.0 || X > vor->hi[0] || Y > vor->hi[1]) {
       fail(VRT_E_ARG, "regular points outside the Voronoi box in x or y");
     }
@@ -1565,11 +1565,23 @@ vrt_status vrt_idw_map(vrt_grid vor, vrt_grid reg, double power, int32_t *idx, d
     reg->d_walk_bad.alloc(sizeof(unsigned long long));
     vrt::launch_zero_u64(s, 1, reg->d_walk_bad.as<unsigned long long>());
     int32_t *bad = reg->d_walk_bad.as<int32_t>();
-    const int32_t strides[4] = {64, 16, 4, 1};
-    for (int l = 0; l < 4; ++l)
-      vrt::launch_idw_level(s, reg->nx, reg->ny, reg->nz, reg->dx, reg->dy, reg->d_z.as<double>(), strides[l],
-                            l ? strides[l - 1] : 0, vor->n, vor->d_xyz.as<double>(), vor->d_ptr.as<int64_t>(),
-                            vor->d_idx.as<int32_t>(), vor->periodic, Lx, Ly, power, idx, w1, d2, bad);
+    // brute force on the finest lattice whose work (points x sites) stays
+    // under 2^24 distances, then halve the stride
+    auto lattice_points = [&](int64_t st) {
+      return ((reg->nx + st - 1) / st) * ((reg->ny + st - 1) / st) * ((reg->nz + st - 1) / st);
+    };
+    int32_t s0 = 1;
+    while (lattice_points(s0) > 1 && lattice_points(s0) * vor->n > (int64_t(1) << 24)) s0 *= 2;
+    const int64_t pairs = vrt::idw_brute_scratch_pairs(reg->nx, reg->ny, reg->nz, s0, vor->n);
+    reg->d_brute.alloc((size_t)pairs * 2 * (sizeof(int32_t) + sizeof(double)));
+    double *pe = reg->d_brute.as<double>();
+    int32_t *pb = reinterpret_cast<int32_t *>(pe + 2 * pairs);
+    vrt::launch_idw_brute(s, reg->nx, reg->ny, reg->nz, reg->dx, reg->dy, reg->d_z.as<double>(), s0, vor->n,
+                          vor->d_xyz.as<double>(), vor->periodic, Lx, Ly, power, idx, w1, d2, pb, pe);
+    for (int32_t st = s0 / 2; st >= 1; st /= 2)
+      vrt::launch_idw_level(s, reg->nx, reg->ny, reg->nz, reg->dx, reg->dy, reg->d_z.as<double>(), st, 2 * st,
+                            vor->n, vor->d_xyz.as<double>(), vor->d_ptr.as<int64_t>(), vor->d_idx.as<int32_t>(),
+                            vor->periodic, Lx, Ly, power, idx, w1, d2, bad);
     int32_t h_bad = 0;
     VRT_HIP(hipMemcpyAsync(&h_bad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     VRT_HIP(hipStreamSynchronize(s));

@@ -96,26 +96,6 @@ struct PersistItems {
 
 
 
-// ---- k_synth.hip
-// one level of the coarse-to-fine nearest-site search (stride 64, 16, 4, 1;
-// parent = the previous stride, 0 for the first)
-void launch_idw_level(hipStream_t s, int32_t nx, int32_t ny, int32_t nz, double dx, double dy, const double *z,
-                      int32_t stride, int32_t parent, int64_t n, const double *xyz, const int64_t *ptr,
-                      const int32_t *nbr, bool periodic, double Lx, double Ly, double power, int32_t *idx,
-                      double *w1, double *d2, int32_t *bad);
-void launch_idw_apply(hipStream_t s, int64_t m, int32_t nc, int64_t n_src, const int32_t *idx, const double *w1,
-                      const double *src, double *dst);
-// pack holds m float4 (T = float) or double4 (T = double)
-template <typename T>
-void launch_line_pack(hipStream_t s, int64_t m, int64_t n_src, const int32_t *idx, const double *w1,
-                      const double *S_site, const double *chi_L, const double *chi_c, const double *B, void *pack);
-template <typename T>
-void launch_vertical_line(hipStream_t s, int64_t ncol, int32_t nz, int32_t nl, const double *z, const T *phi,
-                          const void *pack, const double *B, const T *Ib, T *out);
-template <typename T>
-void launch_vertical_plain(hipStream_t s, int64_t ncol, int32_t nz, int32_t nl, const double *z, const T *chi,
-                           const T *S, const T *Ib, T *out);
-
 }  // namespace vrt
 
 struct vrt_ctx_s {
@@ -245,7 +225,7 @@ struct vrt_grid_s {
 
   // final synthesis on a regular grid: per-point packed line data and the
   // nearest-site walk's error flag
-  vrt::DevBuf d_pack, d_walk_bad;
+  vrt::DevBuf d_pack, d_walk_bad, d_brute;
 
   // captured launch sequences, keyed by (prec, n_lambda, pointers)
   using GraphKey = std::tuple<int, int32_t, const void *, const void *, const void *, const void *, void *, void *>;
@@ -355,8 +335,15 @@ void launch_regular(hipStream_t s, int32_t step, int32_t ray_begin, int32_t ray_
                     int32_t nl, const T *chi, const T *S, const T *Ibot, const T *Itop, T *I);
 
 // ---- k_synth.hip
-// one level of the coarse-to-fine nearest-site search (stride 64, 16, 4, 1;
-// parent = the previous stride, 0 for the first)
+// the two nearest sites of the points on the lattice of one stride, by brute
+// force over all sites (the coarsest level of the search); pb, pe hold
+// idw_brute_scratch_pairs() pairs of (site, key)
+int64_t idw_brute_scratch_pairs(int32_t nx, int32_t ny, int32_t nz, int32_t stride, int64_t n);
+void launch_idw_brute(hipStream_t s, int32_t nx, int32_t ny, int32_t nz, double dx, double dy, const double *z,
+                      int32_t stride, int64_t n, const double *xyz, bool periodic, double Lx, double Ly, double power,
+                      int32_t *idx, double *w1, double *d2, int32_t *pb, double *pe);
+// one finer level of the search: the points of lattice `stride` not on lattice
+// `parent`, each walking from its parent point's nearest site
 void launch_idw_level(hipStream_t s, int32_t nx, int32_t ny, int32_t nz, double dx, double dy, const double *z,
                       int32_t stride, int32_t parent, int64_t n, const double *xyz, const int64_t *ptr,
                       const int32_t *nbr, bool periodic, double Lx, double Ly, double power, int32_t *idx,

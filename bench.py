@@ -56,17 +56,22 @@ def sweep_bytes_per_update(nl: int, fp: int) -> float:
     return 3.0 * fp + (16.0 + 4.0 * fp) / nl
 
 
-def counter_traffic(nl, n, mode):
+LAYOUT_KEYS = ("record_order", "xcd_chunks", "ray_affinity", "chains", "lane_bytes", "interleave")
+
+
+def counter_traffic(nl, n, mode, layout):
     """HBM bytes per sweep launch measured by rocprofv3 counters (FETCH_SIZE x
     its copy-kernel calibration + WRITE_SIZE), read from the committed profile
-    summary, or None when that summary was taken on another workload or on
-    kernel sources that have changed since."""
+    summary, or None when that summary was taken on another workload, another
+    launch layout or kernel sources that have changed since."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "sweep_kernel_c1_counters.json")
     if mode == "persistent" or nl != 64 or n != 262144 or not os.path.exists(path):
         return None
     rec = json.load(open(path))
+    if {k: rec.get("layout", {}).get(k) for k in LAYOUT_KEYS} != {k: layout.get(k) for k in LAYOUT_KEYS}:
+        return None
     h = hashlib.sha256()
     for f in ("paper_2306_01041_amd/csrc/k_sweep.hip", "paper_2306_01041_amd/csrc/segment.h"):
         h.update(open(os.path.join(ROOT, f), "rb").read())
@@ -89,6 +94,9 @@ def main():
     ap.add_argument("--no-synthesis", action="store_true", help="skip the final-synthesis timing")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the grid's default launch layout (for profiler runs that average over dispatches)")
+    ap.add_argument("--interleave", action="store_true",
+                    help="with --no-autotune: sweep the interleaved record copy (the layout the autotuner picks "
+                         "on this workload)")
     ap.add_argument("--workload", choices=["c1", "c2", "c3", "synth"], default="c1",
                     help="c1: the formal solution (default line); c2: the two-level Lambda iteration on 1,048,576 "
                          "sites; c3: 48 atmospheres of 32,768-524,288 sites solved as one batch; synth: only the "
@@ -183,6 +191,11 @@ def main():
     v.lte_continuum(G, lam, atm.kappa0, T, rho, chi, S)
     tuning = None if args.no_autotune else v.autotune(G, chi, S, J, reps=5)
     log(f"autotune: {tuning}")
+    if tuning is None and args.interleave:
+        G.tune(v.VRT_TUNE_INTERLEAVE, 1)
+    layout = dict(tuning["chosen"]) if tuning else {"record_order": 1, "xcd_chunks": 8, "ray_affinity": 0,
+                                                    "chains": 1, "lane_bytes": 16,
+                                                    "interleave": 1 if args.interleave else 0}
 
     for _ in range(args.warmup):
         step()
@@ -226,7 +239,7 @@ def main():
     bytes_per_launch = bpu * updates / launches
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
     jr_bytes = (4.0 + 4.0 / R) * jr_units / jr_launches  # read every ray's I once, write J once
-    traffic = counter_traffic(nl, g.n, args.mode)
+    traffic = counter_traffic(nl, g.n, args.mode, layout)
     log(f"sweep: {launches} launches/step, {sweep_ms:.3f} ms, mean {avg_launch_ms * 1e3:.2f} us/launch, "
         f"{achieved:.0f} GB/s algorithmic (counters: {traffic}); J quadrature {jr_one:.3f} ms "
         f"({jr_bytes / (jr_one * 1e-3) / 1e9:.0f} GB/s)")
@@ -401,6 +414,7 @@ def main():
         "cpu_baseline": cpu,
         "setup_s": round(setup_s, 3),
         "tuning": tuning,
+        "layout": {k: layout.get(k) for k in LAYOUT_KEYS},
     }
     print(json.dumps(out))
     G.close()

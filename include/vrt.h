@@ -197,6 +197,13 @@ vrt_status vrt_grid_set_rays(vrt_grid grid, int32_t n_rays, const double *dir, c
  *                           ray ranges (fewer rows in flight per level step,
  *                           more launches) [1]. */
 #define VRT_TUNE_RAY_GROUPS 9
+/*   VRT_TUNE_INTERLEAVE     1 = batched and graph sweeps (without chains, ray
+ *                           groups or ray affinity) read a second copy of the
+ *                           records in which each level step is ordered by the
+ *                           sites' horizontal Morton code across all rays, so
+ *                           a die's chunk of a step is a region of the box
+ *                           for every ray [0]. */
+#define VRT_TUNE_INTERLEAVE 10
 /*   VRT_TUNE_SPIN_CAP       bound on the polls of one wait in the persistent
  *                           sweep [2^22]; a wait that exceeds it gives up.
  *   VRT_TUNE_PERSIST_BLOCKS cap on the persistent sweep's workgroups

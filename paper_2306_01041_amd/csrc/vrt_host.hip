@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <numeric>
+#include <thread>
 
 #include "vrt_internal.h"
 
@@ -212,6 +213,74 @@ void build_affinity(vrt_grid g) {
 }
 
 
+// Morton code of each site's horizontal position in the box (16 bits per axis)
+std::vector<uint64_t> morton_codes(vrt_grid g) {
+  const int64_t n = g->n;
+  std::vector<uint64_t> code((size_t)n);
+  const std::vector<double> &xyz = g->h_xyz;
+  const double Lx = g->hi[0] - g->lo[0], Ly = g->hi[1] - g->lo[1];
+  auto q = [](double v) {
+    double f = std::floor(v * 65536.0);
+    return (uint32_t)std::min(65535.0, std::max(0.0, f));
+  };
+  for (int64_t i = 0; i < n; ++i) {
+    const uint32_t ux = q((xyz[3 * i] - g->lo[0]) / Lx), uy = q((xyz[3 * i + 1] - g->lo[1]) / Ly);
+    uint64_t m = 0;
+    for (int b = 0; b < 16; ++b) m |= (uint64_t)((ux >> b) & 1u) << (2 * b) | (uint64_t)((uy >> b) & 1u) << (2 * b + 1);
+    code[(size_t)i] = m;
+  }
+  return code;
+}
+
+// The records of every level step reordered by (Morton code of the site, ray,
+// site): the records of one step are independent, so any order within a step
+// gives the same intensities.
+void build_interleaved(vrt_grid g) {
+  hipStream_t s = g->ctx->stream;
+  const int64_t nr = g->n_rec;
+  std::vector<int4> ri((size_t)nr);
+  std::vector<vrt::RecF32> r32((size_t)nr);
+  std::vector<vrt::RecF64> r64((size_t)nr);
+  VRT_HIP(hipMemcpyAsync(ri.data(), g->d_ri.p, (size_t)nr * sizeof(int4), hipMemcpyDeviceToHost, s));
+  VRT_HIP(hipMemcpyAsync(r32.data(), g->d_rf32.p, (size_t)nr * sizeof(vrt::RecF32), hipMemcpyDeviceToHost, s));
+  VRT_HIP(hipMemcpyAsync(r64.data(), g->d_rf64.p, (size_t)nr * sizeof(vrt::RecF64), hipMemcpyDeviceToHost, s));
+  VRT_HIP(hipStreamSynchronize(s));
+  const std::vector<uint64_t> code = morton_codes(g);
+  std::vector<int64_t> perm((size_t)nr);
+  std::iota(perm.begin(), perm.end(), int64_t(0));
+  std::vector<int4> ri2((size_t)nr);
+  std::vector<vrt::RecF32> r32b((size_t)nr);
+  std::vector<vrt::RecF64> r64b((size_t)nr);
+  // steps are independent: host threads take every nth step
+  const int nth = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  auto work = [&](int t) {
+    for (int32_t st = t; st < g->n_steps; st += nth) {
+      const int64_t b0 = g->step_ptr[(size_t)st], e0 = g->step_ptr[(size_t)st + 1];
+      std::sort(perm.begin() + b0, perm.begin() + e0, [&](int64_t u, int64_t v) {
+        const int4 &a = ri[(size_t)u], &c = ri[(size_t)v];
+        const uint64_t ka = code[(size_t)a.x], kc = code[(size_t)c.x];
+        if (ka != kc) return ka < kc;
+        if (a.w != c.w) return a.w < c.w;
+        return a.x < c.x;
+      });
+      for (int64_t k = b0; k < e0; ++k) {
+        ri2[(size_t)k] = ri[(size_t)perm[(size_t)k]];
+        r32b[(size_t)k] = r32[(size_t)perm[(size_t)k]];
+        r64b[(size_t)k] = r64[(size_t)perm[(size_t)k]];
+      }
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 1; t < nth; ++t) pool.emplace_back(work, t);
+  work(0);
+  for (auto &th : pool) th.join();
+  upload(g->d_ri_x, ri2.data(), ri2.size(), s);
+  upload(g->d_rf32_x, r32b.data(), r32b.size(), s);
+  upload(g->d_rf64_x, r64b.data(), r64b.size(), s);
+  VRT_HIP(hipStreamSynchronize(s));  // the host vectors must outlive the copies
+  g->interleaved_built = true;
+}
+
 void set_rays_voronoi(vrt_grid g) {
   hipStream_t s = g->ctx->stream;
   const int64_t n = g->n;
@@ -291,19 +360,8 @@ void set_rays_voronoi(vrt_grid g) {
   DevBuf d_rec_order, d_visit;
   const int32_t *rec_order = g->d_order.as<int32_t>();
   if (g->record_order == 1 && n > 1) {
-    std::vector<uint64_t> key((size_t)n);
-    const std::vector<double> &xyz = g->h_xyz;
-    const double Lx = g->hi[0] - g->lo[0], Ly = g->hi[1] - g->lo[1];
-    for (int64_t i = 0; i < n; ++i) {
-      auto q = [](double v) {
-        double f = std::floor(v * 65536.0);
-        return (uint32_t)std::min(65535.0, std::max(0.0, f));
-      };
-      const uint32_t ux = q((xyz[3 * i] - g->lo[0]) / Lx), uy = q((xyz[3 * i + 1] - g->lo[1]) / Ly);
-      uint64_t m = 0;
-      for (int b = 0; b < 16; ++b) m |= (uint64_t)((ux >> b) & 1u) << (2 * b) | (uint64_t)((uy >> b) & 1u) << (2 * b + 1);
-      key[(size_t)i] = (m << 31) | (uint64_t)i;
-    }
+    std::vector<uint64_t> key = morton_codes(g);
+    for (int64_t i = 0; i < n; ++i) key[(size_t)i] = (key[(size_t)i] << 31) | (uint64_t)i;
     std::sort(key.begin(), key.end());
     std::vector<int32_t> visit((size_t)n);
     for (int64_t i = 0; i < n; ++i) visit[(size_t)i] = (int32_t)(key[(size_t)i] & 0x7fffffffu);
@@ -359,6 +417,8 @@ void set_rays_voronoi(vrt_grid g) {
                    g->d_ds2.as<double>(), g->d_dirs.as<double>(), g->d_ri.as<int4>(), g->d_rf32.as<vrt::RecF32>(),
                    g->d_rf64.as<vrt::RecF64>());
   VRT_HIP(hipStreamSynchronize(s));
+  g->interleaved_built = false;
+  if (g->interleave) build_interleaved(g);
 }
 
 template <typename T> T *intensity_buffer(vrt_grid g, int32_t nl, void *I_rays) {
@@ -503,8 +563,19 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
         }
       }
     } else {
-      for (int32_t st = 0; st < g->n_steps; ++st)
-        sweep(g->step_ptr[(size_t)st], g->step_ptr[(size_t)st + 1] - g->step_ptr[(size_t)st]);
+      const int4 *rix = ri;
+      const auto *rfx = rf;
+      if (g->interleave && g->interleaved_built) {
+        rix = g->d_ri_x.as<int4>();
+        rfx = sizeof(T) == 4 ? reinterpret_cast<decltype(rf)>(g->d_rf32_x.p) : reinterpret_cast<decltype(rf)>(g->d_rf64_x.p);
+      }
+      for (int32_t st = 0; st < g->n_steps; ++st) {
+        const int64_t b = g->step_ptr[(size_t)st], c = g->step_ptr[(size_t)st + 1] - b;
+        if (c <= 0) continue;
+        timed_launch(ctx, s, tm, 0, c * nl, [&] {
+          vrt::launch_sweep<T>(s, rix, rfx, b, c, nl, n, chi, S, Ib, It, I, xc, 0, nullptr, 0, g->lane_bytes);
+        });
+      }
     }
   } else {
     const double *z = g->d_z.as<double>(), *dirs = g->d_dirs.as<double>();
@@ -1165,6 +1236,10 @@ vrt_status vrt_grid_tune(vrt_grid g, int32_t knob, int64_t value) {
     } else if (knob == VRT_TUNE_RAY_GROUPS) {
       if (value < 1 || value > 64) fail(VRT_E_ARG, "ray groups must be in 1..64");
       g->ray_groups = (int)value;
+    } else if (knob == VRT_TUNE_INTERLEAVE) {
+      if (value != 0 && value != 1) fail(VRT_E_ARG, "interleave must be 0 or 1");
+      g->interleave = (int)value;
+      if (g->interleave && g->kind == 0 && g->R > 0) build_interleaved(g);
     } else if (knob == VRT_TUNE_LANE_BYTES) {
       if (value != 16 && value != 32) fail(VRT_E_ARG, "lane bytes must be 16 or 32");
       g->lane_bytes = (int)value;
@@ -1197,12 +1272,15 @@ vrt_status vrt_grid_autotune(vrt_grid g, vrt_prec prec, int32_t n_lambda, const 
     std::string rep = "{\"candidates\": [";
     double best = 1e300;
     int best_order = g->record_order, best_xcd = g->xcd_chunks, best_aff = g->ray_affinity, best_ch = g->chains,
-        best_lb = g->lane_bytes;
-    // (die chunks, ray affinity, chains, lane bytes) per record order; split
-    // chains are not candidates: kernels on separate queues were measured not
-    // to overlap
-    static const int cands[][4] = {{0, 0, 1, 16}, {8, 0, 1, 16}, {0, 1, 1, 16}, {8, 0, 1, 32}, {0, 1, 1, 32}};
+        best_lb = g->lane_bytes, best_il = g->interleave;
+    // (die chunks, ray affinity, chains, lane bytes, interleave) per record
+    // order; split chains are not candidates: kernels on separate queues were
+    // measured not to overlap. The interleaved copy sorts every step by
+    // position whatever the record order, so it is timed under one order only.
+    static const int cands[][5] = {{0, 0, 1, 16, 0}, {8, 0, 1, 16, 0}, {0, 1, 1, 16, 0}, {8, 0, 1, 32, 0},
+                                   {0, 1, 1, 32, 0}, {8, 0, 1, 16, 1},  {0, 0, 1, 16, 1}};
     bool first = true;
+    g->interleave = 0;
     for (int order = 0; order <= 1; ++order) {
       if (order != g->record_order || first) {
         g->record_order = order;
@@ -1210,11 +1288,14 @@ vrt_status vrt_grid_autotune(vrt_grid g, vrt_prec prec, int32_t n_lambda, const 
         set_rays_voronoi(g);
       }
       for (const auto &cd : cands) {
-        const int xcd = cd[0], aff = cd[1], ch = cd[2], lb = cd[3];
+        const int xcd = cd[0], aff = cd[1], ch = cd[2], lb = cd[3], il = cd[4];
+        if (il && (order != 1 || g->n_rec > (int64_t(1) << 26))) continue;  // the copy is built on the host
+        if (il && !g->interleaved_built) build_interleaved(g);
         g->xcd_chunks = xcd;
         g->ray_affinity = aff;
         g->chains = ch;
         g->lane_bytes = lb;
+        g->interleave = il;
         g->drop_graphs();
         auto run = [&] {
           if (prec == VRT_F32)
@@ -1230,11 +1311,11 @@ vrt_status vrt_grid_autotune(vrt_grid g, vrt_prec prec, int32_t n_lambda, const 
         float ms = 0.0f;
         VRT_HIP(hipEventElapsedTime(&ms, e0, e1));
         const double mean = ms / reps;
-        char buf[128];
+        char buf[192];
         snprintf(buf, sizeof buf,
                  "%s{\"record_order\": %d, \"xcd_chunks\": %d, \"ray_affinity\": %d, \"chains\": %d, "
-                 "\"lane_bytes\": %d, \"ms\": %.5f}",
-                 first ? "" : ", ", order, xcd, aff, ch, lb, mean);
+                 "\"lane_bytes\": %d, \"interleave\": %d, \"ms\": %.5f}",
+                 first ? "" : ", ", order, xcd, aff, ch, lb, il, mean);
         rep += buf;
         first = false;
         if (mean < best) {
@@ -1244,11 +1325,13 @@ vrt_status vrt_grid_autotune(vrt_grid g, vrt_prec prec, int32_t n_lambda, const 
           best_aff = aff;
           best_ch = ch;
           best_lb = lb;
+          best_il = il;
         }
       }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    g->interleave = 0;
     if (best_order != g->record_order) {
       g->record_order = best_order;
       set_rays_voronoi(g);
@@ -1257,12 +1340,14 @@ vrt_status vrt_grid_autotune(vrt_grid g, vrt_prec prec, int32_t n_lambda, const 
     g->ray_affinity = best_aff;
     g->chains = best_ch;
     g->lane_bytes = best_lb;
+    g->interleave = best_il;
+    if (best_il && !g->interleaved_built) build_interleaved(g);
     g->drop_graphs();
     char buf[260];
     snprintf(buf, sizeof buf,
              "], \"chosen\": {\"record_order\": %d, \"xcd_chunks\": %d, \"ray_affinity\": %d, \"chains\": %d, "
-             "\"lane_bytes\": %d, \"ms\": %.5f}}",
-             best_order, best_xcd, best_aff, best_ch, best_lb, best);
+             "\"lane_bytes\": %d, \"interleave\": %d, \"ms\": %.5f}}",
+             best_order, best_xcd, best_aff, best_ch, best_lb, best_il, best);
     rep += buf;
     if (report && report_len > 0) snprintf(report, (size_t)report_len, "%s", rep.c_str());
     return VRT_OK;

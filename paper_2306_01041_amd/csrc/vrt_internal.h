@@ -184,6 +184,9 @@ struct vrt_grid_s {
   int chains = 1;        // independent launch chains (streams) a sweep is split into
   int lane_bytes = 16;   // bytes of a row each lane moves per access (16 or 32)
   int ray_groups = 1;    // the rays are swept in this many consecutive passes
+  int interleave = 0;    // 1: step-wide sweeps read a copy of the records ordered by position across rays
+  vrt::DevBuf d_ri_x, d_rf32_x, d_rf64_x;
+  bool interleaved_built = false;
 
   // ray-affinity tables: ray_die[r], and per step [kDies][xk][2] = {first
   // record, running count} over the segments of each die's rays

@@ -42,6 +42,7 @@ VRT_TUNE_RAY_AFFINITY = 5
 VRT_TUNE_CHAINS = 6
 VRT_TUNE_LANE_BYTES = 8
 VRT_TUNE_RAY_GROUPS = 9
+VRT_TUNE_INTERLEAVE = 10
 
 VRT_F64 = 0
 VRT_F32 = 1

@@ -272,9 +272,11 @@ def test_tuning_knobs_do_not_change_results(v, ctx, quad, grids):
     chi, S = to_dev(chi_o, f), to_dev(S_o, f)
     ref = None
     for order in (0, 1):
-        for xcd, aff, ch, lb, rg in ((0, 0, 1, 16, 1), (3, 0, 1, 16, 1), (8, 0, 1, 16, 1), (8, 1, 1, 16, 1),
-                                     (8, 0, 2, 16, 1), (0, 0, 3, 16, 1), (8, 0, 5, 16, 1), (8, 0, 1, 32, 1),
-                                     (8, 1, 1, 32, 1), (8, 0, 1, 16, 3), (8, 0, 1, 16, 5)):
+        for xcd, aff, ch, lb, rg, il in ((0, 0, 1, 16, 1, 0), (3, 0, 1, 16, 1, 0), (8, 0, 1, 16, 1, 0),
+                                         (8, 1, 1, 16, 1, 0), (8, 0, 2, 16, 1, 0), (0, 0, 3, 16, 1, 0),
+                                         (8, 0, 5, 16, 1, 0), (8, 0, 1, 32, 1, 0), (8, 1, 1, 32, 1, 0),
+                                         (8, 0, 1, 16, 3, 0), (8, 0, 1, 16, 5, 0), (8, 0, 1, 16, 1, 1),
+                                         (0, 0, 1, 32, 1, 1), (8, 0, 2, 16, 1, 1)):
             G = v.Grid.from_synth(ctx, g)
             G.tune(v.VRT_TUNE_RECORD_ORDER, order)
             G.tune(v.VRT_TUNE_XCD_CHUNKS, xcd)
@@ -282,19 +284,29 @@ def test_tuning_knobs_do_not_change_results(v, ctx, quad, grids):
             G.tune(v.VRT_TUNE_CHAINS, ch)
             G.tune(v.VRT_TUNE_LANE_BYTES, lb)
             G.tune(v.VRT_TUNE_RAY_GROUPS, rg)
+            G.tune(v.VRT_TUNE_INTERLEAVE, il)  # before the rays: built with the schedule
             G.set_rays(dirs, w)
             J = torch.empty_like(chi)
-            v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_GRAPH)
-            torch.cuda.synchronize()
-            out = J.cpu().numpy()
-            if ref is None:
-                ref = out
-            assert np.array_equal(out, ref), (order, xcd, aff, ch, lb, rg)
+            for mode in (v.VRT_EXEC_GRAPH, v.VRT_EXEC_BATCHED, v.VRT_EXEC_PLAIN):
+                v.formal_solution(G, chi, S, J, exec_mode=mode)
+                torch.cuda.synchronize()
+                out = J.cpu().numpy()
+                if ref is None:
+                    ref = out
+                assert np.array_equal(out, ref), (order, xcd, aff, ch, lb, rg, il, mode)
             G.close()
+    # switched on after the rays are set: the copy is built at once
+    G = _gpu_grid(v, ctx, g, dirs, w)
+    G.tune(v.VRT_TUNE_INTERLEAVE, 1)
+    J = torch.empty_like(chi)
+    v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_GRAPH)
+    torch.cuda.synchronize()
+    assert np.array_equal(J.cpu().numpy(), ref)
+    G.close()
     G = _gpu_grid(v, ctx, g, dirs, w)
     J = torch.empty_like(chi)
     rep = v.autotune(G, chi, S, J, reps=2)
-    assert len(rep["candidates"]) == 10
+    assert len(rep["candidates"]) == 12
     assert rep["chosen"]["ms"] == min(c["ms"] for c in rep["candidates"])
     v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_GRAPH)
     torch.cuda.synchronize()

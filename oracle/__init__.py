@@ -77,6 +77,11 @@ def lib():
                                       _d, _d]
         L.orc_lambda_diag.restype = None
         L.orc_lte_vjp.argtypes = [ctypes.c_int64, ctypes.c_int32, _d, ctypes.c_double, _d, _d, _d, _d, _d, _d, _d]
+        L.orc_bezier_weights.argtypes = [ctypes.c_double, _d, _d, _d, _d]
+        L.orc_bezier_weights.restype = None
+        L.orc_fs_voronoi_bezier.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _d, _d, _d, _i32, _i32,
+                                            _d, _d, _d, _i32, _i32, _d, _d, _d, _d, _d, _d, _d, _d, _d]
+        L.orc_fs_voronoi_bezier.restype = ctypes.c_int
         L.orc_idw2.argtypes = [ctypes.c_int64, _d, ctypes.c_int64, _d, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                ctypes.c_double, _i32, _d, _d]
         L.orc_idw2.restype = None
@@ -234,6 +239,46 @@ def fs_regular(nx, ny, z, dx, dy, dirs, ray_w, chi, S, I_bottom, I_top=None, kee
                               _p(chi, _d), _p(S, _d), _p(I_bottom, _d), _p(It, _d), _p(I, _d), _p(J, _d))
     if st != 0:
         raise MemoryError("orc_fs_regular failed")
+    return (J, I) if keep_I else J
+
+
+def bezier_weights(x: float):
+    """(e^-x, alpha, beta, gamma) of the quadratic Bezier segment: I = e^-x I_u +
+    alpha S_u + beta S_0 + gamma C."""
+    E, a, b, c = (ctypes.c_double() for _ in range(4))
+    lib().orc_bezier_weights(float(x), ctypes.byref(E), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+    return E.value, a.value, b.value, c.value
+
+
+def select_downwind(grid, dirs, r_exp: float = 7.0) -> Selection:
+    """Downwind lines of every ray and site: the upwind selection of the opposite directions."""
+    return select(grid, -np.asarray(dirs, np.float64), r_exp)
+
+
+def fs_voronoi_bezier(grid, dirs, ray_w, sel: Selection, down: Selection, chi, S, I_bottom, I_top=None,
+                      keep_I: bool = False):
+    """J [n, nl] (and I) on the Voronoi grid with the quadratic Bezier segment."""
+    dirs = _c(dirs, np.float64)
+    ray_w = _c(ray_w, np.float64)
+    chi = _c(chi, np.float64)
+    S = _c(S, np.float64)
+    n = grid.n
+    if chi.ndim == 1:
+        chi = chi[:, None]
+        S = S.reshape(n, -1)
+    nl = chi.shape[1]
+    I_bottom = _c(np.broadcast_to(I_bottom, (n, nl)) if np.ndim(I_bottom) else np.full((n, nl), I_bottom), np.float64)
+    It = None if I_top is None else _c(np.broadcast_to(I_top, (n, nl)), np.float64)
+    R = dirs.shape[0]
+    J = np.empty((n, nl), np.float64)
+    I = np.empty((R, n, nl), np.float64) if keep_I else None
+    st = lib().orc_fs_voronoi_bezier(n, R, nl, _p(_c(grid.xyz, np.float64), _d), _p(dirs, _d), _p(ray_w, _d),
+                                     _p(sel.k1, _i32), _p(sel.k2, _i32), _p(sel.w1, _d), _p(sel.ds1, _d),
+                                     _p(sel.ds2, _d), _p(down.k1, _i32), _p(down.k2, _i32), _p(down.w1, _d),
+                                     _p(down.ds1, _d), _p(down.ds2, _d), _p(chi, _d), _p(S, _d), _p(I_bottom, _d),
+                                     _p(It, _d), _p(I, _d), _p(J, _d))
+    if st != 0:
+        raise MemoryError("orc_fs_voronoi_bezier failed")
     return (J, I) if keep_I else J
 
 

@@ -683,3 +683,171 @@ void orc_lc_vertical(int64_t ncol, int32_t nz, int32_t nl, const double *z, cons
         }
     }
 }
+
+/* ---------------------------------------------------------------------------
+ * Quadratic Bezier segment (the higher-order scheme the paper points to in
+ * Sect. 2.5: de la Cruz Rodriguez & Piskunov 2013). Along a segment of
+ * optical depth x from an upwind point u to the point 0, S is the quadratic
+ * Bezier curve with end values S_u, S_0 and control value C; with s = t/x,
+ *   S(t) = S_u (1 - s)^2 + 2 C s (1 - s) + S_0 s^2,
+ *   I_0 = e^-x I_u + alpha S_u + beta S_0 + gamma C,
+ *   alpha = int_0^x (1-s)^2 e^-(x-t) dt = [2 - e^-x (x^2 + 2x + 2)] / x^2,
+ *   beta  = int_0^x s^2 e^-(x-t) dt     = 1 - 2 (e^-x + x - 1) / x^2,
+ *   gamma = int_0^x 2s(1-s) e^-(x-t) dt = 2 (x - 2 + e^-x (x + 2)) / x^2.
+ * Below x = 1 the three are summed from their power series,
+ *   alpha = sum_{m>=3} (-1)^(m+1) (m-1)(m-2) x^(m-2) / m!,
+ *   beta  = sum_{m>=3} 2 (-1)^(m+1) x^(m-2) / m!,
+ *   gamma = sum_{m>=3} 2 (-1)^(m+1) (m-2) x^(m-2) / m!,
+ * which removes the cancellation of the closed forms at small x.
+ * ------------------------------------------------------------------------- */
+void orc_bezier_weights(double x, double *E, double *alpha, double *beta, double *gamma) {
+    const double e = exp(-x);
+    *E = e;
+    if (x < 1.0) {
+        double a = 0.0, b = 0.0, c = 0.0;
+        double p = x / 6.0; /* x^(m-2)/m! for m = 3 */
+        for (int m = 3; m <= 45; ++m) {
+            const double sg = (m % 2 == 1) ? 1.0 : -1.0; /* (-1)^(m+1) */
+            a += sg * (double)((m - 1) * (m - 2)) * p;
+            b += sg * 2.0 * p;
+            c += sg * 2.0 * (double)(m - 2) * p;
+            p *= x / (double)(m + 1);
+        }
+        *alpha = a;
+        *beta = b;
+        *gamma = c;
+    } else {
+        const double x2 = x * x;
+        *alpha = (2.0 - e * (x2 + 2.0 * x + 2.0)) / x2;
+        *beta = 1.0 - 2.0 * (e + x - 1.0) / x2;
+        *gamma = 2.0 * (x - 2.0 + e * (x + 2.0)) / x2;
+    }
+}
+
+/* Control value of one upwind line (reading Q1). The derivative of S at the
+ * point 0 along the ray comes from the upwind slope d_u = (S_0 - S_u)/x and
+ * the downwind slope d_d (weighted over the downwind lines, of optical depth
+ * x_d) by the Fritsch-Butland harmonic mean:
+ *   S' = d_u d_d / (a d_d + (1 - a) d_u),  a = (1 + x_d / (x + x_d)) / 3,
+ * when d_u d_d > 0, else S' = 0; without downwind lines S' = d_u (the
+ * segment is then linear). C = S_0 - x S' / 2, kept between S_u and S_0.
+ * has_d: whether downwind data exist (x_d > 0). */
+static double orc_bezier_control(double Su, double S0, double x, int has_d, double dd, double xd) {
+    if (!(x > 0.0)) return S0;
+    const double du = (S0 - Su) / x;
+    double d;
+    if (!has_d) {
+        d = du;
+    } else if (du * dd > 0.0) {
+        const double a = (1.0 + xd / (x + xd)) / 3.0;
+        d = du * dd / (a * dd + (1.0 - a) * du);
+    } else {
+        d = 0.0;
+    }
+    double C = S0 - 0.5 * x * d;
+    const double lo = Su < S0 ? Su : S0, hi = Su < S0 ? S0 : Su;
+    if (C < lo) C = lo;
+    if (C > hi) C = hi;
+    return C;
+}
+
+/* ---------------------------------------------------------------------------
+ * Voronoi formal solution with the quadratic Bezier segment (reading Q1).
+ * As orc_fs_voronoi, plus the downwind lines of every (ray, site): the upwind
+ * selection of the opposite direction (q1, q2 sites, qw1 weight of q1, qd1,
+ * qd2 lengths; q1 < 0 at sites on the far wall). For site i, wavelength l:
+ *   x'_j = (chi_qj + chi_i)/2 qd_j,  d_d = sum_j qw_j (S_qj - S_i)/x'_j,
+ *   x_d = sum_j qw_j x'_j  (qw_2 = 1 - qw1; one line: weight 1);
+ * every upwind line j then gives I_j = e^-x I_kj + alpha S_kj + beta S_i +
+ * gamma C_j with C_j from orc_bezier_control, and I_i = sum_j w_j I_j (Eq. 5).
+ * A zero downwind optical depth leaves the downwind slope unused.
+ * ------------------------------------------------------------------------- */
+static void orc_sweep_one_ray_bezier(int64_t n, int32_t nl, double nz, const int32_t *K1, const int32_t *K2,
+                                     const double *W1, const double *D1, const double *D2, const int32_t *Q1,
+                                     const int32_t *Q2, const double *QW1, const double *QD1, const double *QD2,
+                                     const double *chi, const double *S, const double *Ibot, const double *Itop,
+                                     const int64_t *hz, double *I) {
+    for (int64_t p = 0; p < n; ++p) {
+        const int64_t i = hz[p];
+        double *Ii = I + i * nl;
+        if (K1[i] < 0) {
+            for (int32_t l = 0; l < nl; ++l)
+                Ii[l] = nz > 0.0 ? Ibot[i * nl + l] : (Itop ? Itop[i * nl + l] : 0.0);
+            continue;
+        }
+        for (int32_t l = 0; l < nl; ++l) {
+            const double chi_i = chi[i * nl + l], S_i = S[i * nl + l];
+            /* downwind slope and optical depth */
+            int has_d = Q1[i] >= 0;
+            double dd = 0.0, xd = 0.0;
+            if (has_d) {
+                const int nq = Q2[i] >= 0 ? 2 : 1;
+                for (int j = 0; j < nq; ++j) {
+                    const int64_t q = j == 0 ? Q1[i] : Q2[i];
+                    const double wq = nq == 1 ? 1.0 : (j == 0 ? QW1[i] : 1.0 - QW1[i]);
+                    const double xq = 0.5 * (chi[q * nl + l] + chi_i) * (j == 0 ? QD1[i] : QD2[i]);
+                    if (!(xq > 0.0)) {
+                        has_d = 0;
+                        break;
+                    }
+                    dd += wq * (S[q * nl + l] - S_i) / xq;
+                    xd += wq * xq;
+                }
+            }
+            const int nk = K2[i] >= 0 ? 2 : 1;
+            double sum = 0.0;
+            for (int j = 0; j < nk; ++j) {
+                const int64_t k = j == 0 ? K1[i] : K2[i];
+                const double w = nk == 1 ? 1.0 : (j == 0 ? W1[i] : 1.0 - W1[i]);
+                const double x = 0.5 * (chi[k * nl + l] + chi_i) * (j == 0 ? D1[i] : D2[i]);
+                const double Su = S[k * nl + l];
+                const double C = orc_bezier_control(Su, S_i, x, has_d, dd, xd);
+                double E, a, b, c;
+                orc_bezier_weights(x, &E, &a, &b, &c);
+                sum += w * (E * I[k * nl + l] + a * Su + b * S_i + c * C);
+            }
+            Ii[l] = sum;
+        }
+    }
+}
+
+int orc_fs_voronoi_bezier(int64_t n, int32_t n_rays, int32_t nl, const double *xyz, const double *dirs,
+                          const double *ray_w, const int32_t *k1, const int32_t *k2, const double *w1,
+                          const double *ds1, const double *ds2, const int32_t *q1, const int32_t *q2,
+                          const double *qw1, const double *qd1, const double *qd2, const double *chi, const double *S,
+                          const double *I_bottom, const double *I_top, double *I_out, double *J) {
+    const int64_t nn = n * (int64_t)nl;
+    int nth = orc_num_threads();
+    if (nth > n_rays) nth = n_rays;
+    if (nth < 1) nth = 1;
+    double *buf = NULL;
+    if (!I_out) {
+        buf = (double *)malloc(sizeof(double) * (size_t)nth * (size_t)(nn > 0 ? nn : 1));
+        if (!buf) return -5;
+    }
+    int64_t *hz = (int64_t *)malloc(sizeof(int64_t) * 2 * (size_t)(n > 0 ? n : 1));
+    if (!hz) { free(buf); return -5; }
+    orc_height_order(n, xyz, 1.0, hz);
+    orc_height_order(n, xyz, -1.0, hz + n);
+    for (int64_t t = 0; t < nn; ++t) J[t] = 0.0;
+    for (int32_t r0 = 0; r0 < n_rays; r0 += nth) {
+        const int32_t cnt = (n_rays - r0) < nth ? (n_rays - r0) : nth;
+#pragma omp parallel for schedule(static, 1) num_threads(nth)
+        for (int32_t t = 0; t < cnt; ++t) {
+            const int32_t r = r0 + t;
+            const int64_t o = (int64_t)r * n;
+            double *I = I_out ? I_out + (int64_t)r * nn : buf + (int64_t)t * nn;
+            orc_sweep_one_ray_bezier(n, nl, dirs[3 * r + 2], k1 + o, k2 + o, w1 + o, ds1 + o, ds2 + o, q1 + o, q2 + o,
+                                     qw1 + o, qd1 + o, qd2 + o, chi, S, I_bottom, I_top,
+                                     dirs[3 * r + 2] > 0.0 ? hz : hz + n, I);
+        }
+        for (int32_t t = 0; t < cnt; ++t) {
+            const int32_t r = r0 + t;
+            const double *I = I_out ? I_out + (int64_t)r * nn : buf + (int64_t)t * nn;
+            for (int64_t q = 0; q < nn; ++q) J[q] += ray_w[r] * I[q];
+        }
+    }
+    free(buf);
+    free(hz);
+    return 0;
+}

@@ -204,6 +204,21 @@ vrt_status vrt_grid_set_rays(vrt_grid grid, int32_t n_rays, const double *dir, c
  *                           a die's chunk of a step is a region of the box
  *                           for every ray [0]. */
 #define VRT_TUNE_INTERLEAVE 10
+/*   VRT_TUNE_SEGMENT        source model along a Delaunay line (Voronoi grids):
+ *                           0 = linear (Sect. 2.5) [0]; 1 = quadratic Bezier
+ *                           (the higher-order solver Sect. 2.5 points to, de
+ *                           la Cruz Rodriguez & Piskunov 2013): I = e^-x I_k +
+ *                           alpha S_k + beta S_i + gamma C, with the control
+ *                           value C = S_i - x S'_i / 2 from the Fritsch-Butland
+ *                           mean of the upwind slope and the slope along the
+ *                           site's downwind lines (the Eq. 5-6 selection for the
+ *                           opposite direction), kept between S_k and S_i.
+ *                           Formal solutions and plain (accel = 0) two-level
+ *                           iterations with PLAIN, BATCHED or GRAPH execution;
+ *                           the persistent sweep, the reverse sweep, the
+ *                           accelerated iteration and the autotuner return
+ *                           VRT_E_ARG with it. */
+#define VRT_TUNE_SEGMENT 11
 /*   VRT_TUNE_SPIN_CAP       bound on the polls of one wait in the persistent
  *                           sweep [2^22]; a wait that exceeds it gives up.
  *   VRT_TUNE_PERSIST_BLOCKS cap on the persistent sweep's workgroups

@@ -21,7 +21,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import fs_voronoi, idw2, idw_apply, lambda_diag, lc_vertical, regular_points
+from . import fs_voronoi, fs_voronoi_bezier, idw2, idw_apply, lambda_diag, lc_vertical, regular_points
 
 
 def assemble(chi_c, chi_L, phi, B, S_L):
@@ -36,13 +36,18 @@ def jbar(phi, wlam, J):
     return np.sum(wlam[None, :] * phi * J, axis=1)
 
 
-def lambda_step(grid, dirs, ray_w, sel, chi_c, chi_L, phi, wlam, B, eps, S_L, I_top=None):
-    """One Lambda iteration: returns (S_L new, max relative change)."""
+def lambda_step(grid, dirs, ray_w, sel, chi_c, chi_L, phi, wlam, B, eps, S_L, I_top=None, down=None):
+    """One Lambda iteration: returns (S_L new, max relative change). With the
+    downwind lines ``down`` the formal solution uses the quadratic Bezier
+    segment instead of the linear one."""
     chi, S = assemble(chi_c, chi_L, phi, B, S_L)
     nl = phi.shape[1]
     Ib = np.repeat(B[:, None], nl, axis=1)
     It = None if I_top is None else np.repeat(np.asarray(I_top)[:, None], nl, axis=1)
-    J = fs_voronoi(grid, dirs, ray_w, sel, chi, S, Ib, I_top=It)
+    if down is None:
+        J = fs_voronoi(grid, dirs, ray_w, sel, chi, S, Ib, I_top=It)
+    else:
+        J = fs_voronoi_bezier(grid, dirs, ray_w, sel, down, chi, S, Ib, I_top=It)
     S_new = (1.0 - eps) * jbar(phi, wlam, J) + eps * B
     dS = float(np.max(np.abs(S_new - S_L) / np.abs(S_L)))
     return S_new, dS
@@ -71,12 +76,16 @@ def ali_step(grid, dirs, ray_w, sel, chi_c, chi_L, phi, wlam, B, eps, S_L, Lbar,
 
 
 def lambda_iterate(grid, dirs, ray_w, sel, chi_c, chi_L, phi, wlam, B, eps, max_iter=1000, tol=1e-3,
-                   S_start=None, I_top=None, accel=False):
+                   S_start=None, I_top=None, accel=False, down=None):
     """Lambda iteration from S_L = B (or ``S_start``) until max dS/S < tol:
-    plain, or with the Jacobi (local-operator) acceleration when ``accel``.
+    plain, or with the Jacobi (local-operator) acceleration when ``accel``;
+    the plain one with the quadratic Bezier segment when ``down`` (the
+    downwind lines) is given.
 
     Returns (S_L, history of dS, number of iterations done, converged flag).
     """
+    if accel and down is not None:
+        raise ValueError("the accelerated iteration uses the linear segment")
     S_L = np.array(B if S_start is None else S_start, dtype=np.float64)
     Lbar = line_diag(grid, dirs, ray_w, sel, chi_c, chi_L, phi, wlam) if accel else None
     hist = []
@@ -84,7 +93,7 @@ def lambda_iterate(grid, dirs, ray_w, sel, chi_c, chi_L, phi, wlam, B, eps, max_
         if accel:
             S_L, dS = ali_step(grid, dirs, ray_w, sel, chi_c, chi_L, phi, wlam, B, eps, S_L, Lbar, I_top)
         else:
-            S_L, dS = lambda_step(grid, dirs, ray_w, sel, chi_c, chi_L, phi, wlam, B, eps, S_L, I_top)
+            S_L, dS = lambda_step(grid, dirs, ray_w, sel, chi_c, chi_L, phi, wlam, B, eps, S_L, I_top, down)
         hist.append(dS)
         if not np.isfinite(dS):
             raise FloatingPointError("non-finite source-function change")

@@ -1,0 +1,193 @@
+// Formal-solution sweep with the quadratic Bezier segment, the higher-order
+// solver the paper points to for its Delaunay lines (Sect. 2.5; de la Cruz
+// Rodriguez & Piskunov 2013).
+//
+// Along an upwind line of optical depth x from site k to site i the source is
+// the quadratic Bezier curve with end values S_k, S_i and control value C:
+//   I_j = e^-x I_k + alpha(x) S_k + beta(x) S_i + gamma(x) C,
+//   alpha = [2 - e^-x (x^2 + 2x + 2)]/x^2, beta = 1 - 2(e^-x + x - 1)/x^2,
+//   gamma = 2(x - 2 + e^-x (x + 2))/x^2,
+// summed from their power series below x = 1. C = S_i - x S'_i / 2 with the
+// derivative S'_i along the ray from the Fritsch-Butland harmonic mean of the
+// upwind slope (S_i - S_k)/x and the downwind slope d_d, zero where the two
+// differ in sign, the upwind slope alone where the site has no downwind line;
+// C is kept between S_k and S_i. The downwind slope averages the site's
+// downwind lines (the upwind selection of the opposite direction, Eq. 5-6):
+//   d_d = sum_j q_j (S_qj - S_i)/x'_j, x_d = sum_j q_j x'_j,
+//   x'_j = (chi_qj + chi_i) ds'_j / 2.
+// The site's intensity is w1 I_1 + (1 - w1) I_2 (Eq. 5).
+//
+// One launch updates a contiguous range of the sweep records (one level of
+// one ray, or one level step of all rays), 16 lanes per record striding over
+// wavelengths.
+
+#include "segment.h"
+#include "vrt_internal.h"
+
+namespace {
+
+template <typename T> struct Bez;
+
+template <> struct Bez<double> {
+  static __device__ __forceinline__ void weights(double x, double &E, double &a, double &b, double &c) {
+    E = exp(-x);
+    if (x < 1.0) {
+      // Horner over m = 22 .. 3 of (-1)^(m+1) {(m-1)(m-2), 2, 2(m-2)} x^(m-3)/m!, times x
+      double sa = 0.0, sb = 0.0, sc = 0.0;
+#pragma unroll
+      for (int m = 22; m >= 3; --m) {
+        const double f = ((m & 1) ? 1.0 : -1.0) * vrt::inv_factorial(m);
+        sa = sa * x + (double)((m - 1) * (m - 2)) * f;
+        sb = sb * x + 2.0 * f;
+        sc = sc * x + 2.0 * (double)(m - 2) * f;
+      }
+      a = sa * x;
+      b = sb * x;
+      c = sc * x;
+    } else {
+      const double x2 = x * x;
+      a = (2.0 - E * (x2 + 2.0 * x + 2.0)) / x2;
+      b = 1.0 - 2.0 * (E + x - 1.0) / x2;
+      c = 2.0 * (x - 2.0 + E * (x + 2.0)) / x2;
+    }
+  }
+};
+
+template <> struct Bez<float> {
+  static __device__ __forceinline__ void weights(float x, float &E, float &a, float &b, float &c) {
+    E = expf(-x);
+    if (x < 1.0f) {
+      // m = 13 .. 3: the first omitted term is below 2e-8 of each weight at x = 1
+      float sa = 0.0f, sb = 0.0f, sc = 0.0f;
+#pragma unroll
+      for (int m = 13; m >= 3; --m) {
+        const float f = (float)(((m & 1) ? 1.0 : -1.0) * vrt::inv_factorial(m));
+        sa = sa * x + (float)((m - 1) * (m - 2)) * f;
+        sb = sb * x + 2.0f * f;
+        sc = sc * x + 2.0f * (float)(m - 2) * f;
+      }
+      a = sa * x;
+      b = sb * x;
+      c = sc * x;
+    } else {
+      const float x2 = x * x;
+      a = (2.0f - E * (x2 + 2.0f * x + 2.0f)) / x2;
+      b = 1.0f - 2.0f * (E + x - 1.0f) / x2;
+      c = 2.0f * (x - 2.0f + E * (x + 2.0f)) / x2;
+    }
+  }
+};
+
+// control value of one upwind line (see the file comment)
+template <typename T>
+__device__ __forceinline__ T control(T Su, T S0, T x, bool has_d, T dd, T xd) {
+  if (!(x > T(0))) return S0;
+  const T du = (S0 - Su) / x;
+  T d;
+  if (!has_d) {
+    d = du;
+  } else if (du * dd > T(0)) {
+    const T a = (T(1) + xd / (x + xd)) / T(3);
+    d = du * dd / (a * dd + (T(1) - a) * du);
+  } else {
+    d = T(0);
+  }
+  T C = S0 - T(0.5) * x * d;
+  const T lo = Su < S0 ? Su : S0, hi = Su < S0 ? S0 : Su;
+  C = C < lo ? lo : C;
+  C = C > hi ? hi : C;
+  return C;
+}
+
+constexpr int kLanes = 16;  // lanes per record
+
+template <typename T>
+__global__ __launch_bounds__(256) void bezier_sweep_kernel(
+    const int4 *__restrict__ ri, const typename vrt::RecOf<T>::type *__restrict__ rf, int64_t rec_begin,
+    int64_t rec_count, int32_t nl, int64_t n, const int32_t *__restrict__ q1, const int32_t *__restrict__ q2,
+    const double *__restrict__ qw1, const double *__restrict__ qd1, const double *__restrict__ qd2,
+    const T *__restrict__ chi, const T *__restrict__ S, const T *__restrict__ Ibot, const T *__restrict__ Itop,
+    T *I) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r = t / kLanes;
+  if (r >= rec_count) return;
+  const int l0 = (int)(t % kLanes);
+  const int64_t rec = rec_begin + r;
+  const int4 q = ri[rec];
+  const int32_t site = q.x, k1 = q.y, k2 = q.z, ray = q.w >> 1;
+  const bool up = (q.w & 1) != 0;
+  T *Iray = I + (int64_t)ray * n * nl;
+  const int64_t bi = (int64_t)site * nl;
+  if (k1 < 0) {
+    for (int l = l0; l < nl; l += kLanes) Iray[bi + l] = up ? Ibot[bi + l] : (Itop ? Itop[bi + l] : T(0));
+    return;
+  }
+  const auto f = rf[rec];
+  const bool two = k2 >= 0;
+  const T w1 = two ? (T)f.w1 : T(1);
+  const T h1 = T(0.5) * f.ds1, h2 = T(0.5) * f.ds2;
+  const int64_t rs = (int64_t)ray * n + site;
+  const int32_t d1 = q1[rs], d2 = q2[rs];
+  const bool two_d = d2 >= 0;
+  const T qa = two_d ? (T)qw1[rs] : T(1);
+  const T g1 = T(0.5) * (T)qd1[rs], g2 = T(0.5) * (T)qd2[rs];
+  for (int l = l0; l < nl; l += kLanes) {
+    const T ci = chi[bi + l], si = S[bi + l];
+    bool has_d = d1 >= 0;
+    T dd = T(0), xd = T(0);
+    if (has_d) {
+      const T x1 = (chi[(int64_t)d1 * nl + l] + ci) * g1;
+      T x2 = T(1);
+      if (two_d) x2 = (chi[(int64_t)d2 * nl + l] + ci) * g2;
+      if (!(x1 > T(0)) || !(x2 > T(0))) {
+        has_d = false;
+      } else {
+        dd = qa * (S[(int64_t)d1 * nl + l] - si) / x1;
+        xd = qa * x1;
+        if (two_d) {
+          dd += (T(1) - qa) * (S[(int64_t)d2 * nl + l] - si) / x2;
+          xd += (T(1) - qa) * x2;
+        }
+      }
+    }
+    T out = T(0);
+    for (int j = 0; j < (two ? 2 : 1); ++j) {
+      const int64_t bk = (int64_t)(j == 0 ? k1 : k2) * nl;
+      const T x = (chi[bk + l] + ci) * (j == 0 ? h1 : h2);
+      const T Su = S[bk + l];
+      const T C = control(Su, si, x, has_d, dd, xd);
+      T E, a, b, c;
+      Bez<T>::weights(x, E, a, b, c);
+      const T Ij = E * Iray[bk + l] + a * Su + b * si + c * C;
+      out += (j == 0 ? w1 : T(1) - w1) * Ij;
+    }
+    Iray[bi + l] = out;
+  }
+}
+
+}  // namespace
+
+namespace vrt {
+
+template <typename T>
+void launch_bezier_sweep(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *rf, int64_t rec_begin,
+                         int64_t rec_count, int32_t nl, int64_t n, const int32_t *q1, const int32_t *q2,
+                         const double *qw1, const double *qd1, const double *qd2, const T *chi, const T *S,
+                         const T *Ibot, const T *Itop, T *I) {
+  if (rec_count <= 0) return;
+  const int64_t threads = rec_count * kLanes;
+  bezier_sweep_kernel<T><<<(unsigned)((threads + 255) / 256), 256, 0, s>>>(
+      ri, rf, rec_begin, rec_count, nl, n, q1, q2, qw1, qd1, qd2, chi, S, Ibot, Itop, I);
+  VRT_HIP(hipGetLastError());
+}
+
+template void launch_bezier_sweep<float>(hipStream_t, const int4 *, const RecF32 *, int64_t, int64_t, int32_t,
+                                         int64_t, const int32_t *, const int32_t *, const double *, const double *,
+                                         const double *, const float *, const float *, const float *, const float *,
+                                         float *);
+template void launch_bezier_sweep<double>(hipStream_t, const int4 *, const RecF64 *, int64_t, int64_t, int32_t,
+                                          int64_t, const int32_t *, const int32_t *, const double *, const double *,
+                                          const double *, const double *, const double *, const double *,
+                                          const double *, double *);
+
+}  // namespace vrt

@@ -281,6 +281,41 @@ void build_interleaved(vrt_grid g) {
   g->interleaved_built = true;
 }
 
+// Downwind lines of every (ray, site) for the quadratic segment: the upwind
+// selection (Eq. 5-6, the same rules) for the opposite direction.
+void build_downwind(vrt_grid g) {
+  hipStream_t s = g->ctx->stream;
+  const int64_t n = g->n;
+  const int32_t R = g->R;
+  const int64_t RN = (int64_t)R * n;
+  std::vector<double> neg(g->h_dirs.size());
+  for (size_t k = 0; k < neg.size(); ++k) neg[k] = -g->h_dirs[k];
+  DevBuf d_neg, d_misc;
+  upload(d_neg, neg.data(), neg.size(), s);
+  g->d_q1.alloc(RN * 4);
+  g->d_q2.alloc(RN * 4);
+  g->d_qw1.alloc(RN * 8);
+  g->d_qd1.alloc(RN * 8);
+  g->d_qd2.alloc(RN * 8);
+  d_misc.alloc(sizeof(unsigned long long) * (size_t)R + 16);
+  auto *d_nfb = d_misc.as<unsigned long long>();
+  auto *d_bad = reinterpret_cast<int32_t *>(d_nfb + R);
+  VRT_HIP(hipMemsetAsync(d_nfb, 0, sizeof(unsigned long long) * (size_t)R, s));
+  const int32_t big = 0x7fffffff;
+  VRT_HIP(hipMemcpyAsync(d_bad, &big, 4, hipMemcpyHostToDevice, s));
+  const double Lx = g->periodic ? g->hi[0] - g->lo[0] : 0.0;
+  const double Ly = g->periodic ? g->hi[1] - g->lo[1] : 0.0;
+  vrt::launch_select(s, n, R, g->d_xyz.as<double>(), g->d_ptr.as<int64_t>(), g->d_idx.as<int32_t>(),
+                     g->d_shift.as<int8_t>(), g->d_wall.as<uint8_t>(), Lx, Ly, d_neg.as<double>(), g->r_exp,
+                     g->d_q1.as<int32_t>(), g->d_q2.as<int32_t>(), g->d_qw1.as<double>(), g->d_qd1.as<double>(),
+                     g->d_qd2.as<double>(), d_nfb, d_bad);
+  int32_t bad = 0;
+  VRT_HIP(hipMemcpyAsync(&bad, d_bad, 4, hipMemcpyDeviceToHost, s));
+  VRT_HIP(hipStreamSynchronize(s));  // the host direction table must outlive the copy
+  if (bad != big) fail(VRT_E_GRID, "site %d has no neighbour downwind in height", bad);
+  g->down_built = true;
+}
+
 void set_rays_voronoi(vrt_grid g) {
   hipStream_t s = g->ctx->stream;
   const int64_t n = g->n;
@@ -419,6 +454,8 @@ void set_rays_voronoi(vrt_grid g) {
   VRT_HIP(hipStreamSynchronize(s));
   g->interleaved_built = false;
   if (g->interleave) build_interleaved(g);
+  g->down_built = false;
+  if (g->segment) build_downwind(g);
 }
 
 template <typename T> T *intensity_buffer(vrt_grid g, int32_t nl, void *I_rays) {
@@ -490,7 +527,26 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
   const int64_t n = g->n;
   vrt_ctx ctx = g->ctx;
   const bool tm = ctx->profiling && ex != VRT_EXEC_GRAPH && s == ctx->stream;
-  if (g->kind == 0 && ex == VRT_EXEC_PERSISTENT) {
+  if (g->kind == 0 && g->segment == 1) {
+    const int4 *ri = g->d_ri.as<int4>();
+    const auto *rf = records<T>(g);
+    auto sweep = [&](int64_t b, int64_t c) {
+      if (c <= 0) return;
+      timed_launch(ctx, s, tm, 0, c * nl, [&] {
+        vrt::launch_bezier_sweep<T>(s, ri, rf, b, c, nl, n, g->d_q1.as<int32_t>(), g->d_q2.as<int32_t>(),
+                                    g->d_qw1.as<double>(), g->d_qd1.as<double>(), g->d_qd2.as<double>(), chi, S, Ib,
+                                    It, I);
+      });
+    };
+    if (ex == VRT_EXEC_PLAIN) {
+      for (int32_t r = 0; r < R; ++r)
+        for (int32_t st = 0; st < g->n_levels[(size_t)r]; ++st)
+          sweep(g->seg_off[(size_t)st * R + r], g->seg_cnt[(size_t)st * R + r]);
+    } else {
+      for (int32_t st = 0; st < g->n_steps; ++st)
+        sweep(g->step_ptr[(size_t)st], g->step_ptr[(size_t)st + 1] - g->step_ptr[(size_t)st]);
+    }
+  } else if (g->kind == 0 && ex == VRT_EXEC_PERSISTENT) {
     const bool aligned = vrt::al16(chi) && vrt::al16(S) && vrt::al16(Ib) && vrt::al16(It) && vrt::al16(I);
     const vrt::PersistItems &items = persistent_items(g, vrt::persistent_records_per_wave(nl, sizeof(T), aligned));
     int32_t *ep = g->d_epoch.as<int32_t>();
@@ -1242,6 +1298,11 @@ vrt_status vrt_grid_tune(vrt_grid g, int32_t knob, int64_t value) {
       if (value != 0 && value != 1) fail(VRT_E_ARG, "interleave must be 0 or 1");
       g->interleave = (int)value;
       if (g->interleave && g->kind == 0 && g->R > 0) build_interleaved(g);
+    } else if (knob == VRT_TUNE_SEGMENT) {
+      if (value != 0 && value != 1) fail(VRT_E_ARG, "segment must be 0 (linear) or 1 (quadratic Bezier)");
+      if (value == 1 && g->kind != 0) fail(VRT_E_ARG, "the quadratic segment needs a Voronoi grid");
+      g->segment = (int)value;
+      if (g->segment && g->R > 0 && !g->down_built) build_downwind(g);
     } else if (knob == VRT_TUNE_LANE_BYTES) {
       if (value != 16 && value != 32) fail(VRT_E_ARG, "lane bytes must be 16 or 32");
       g->lane_bytes = (int)value;
@@ -1266,6 +1327,7 @@ vrt_status vrt_grid_autotune(vrt_grid g, vrt_prec prec, int32_t n_lambda, const 
   return guarded(g->ctx, [&] {
     if (!valid_prec(prec) || n_lambda <= 0 || reps <= 0) fail(VRT_E_ARG, "bad autotune arguments");
     if (g->R == 0) fail(VRT_E_STATE, "rays not set");
+    if (g->segment) fail(VRT_E_ARG, "the autotuner times the linear sweep's layouts");
     if (g->n == 0 || g->kind != 0) return VRT_OK;
     hipStream_t s = g->ctx->stream;
     hipEvent_t e0, e1;
@@ -1429,6 +1491,8 @@ vrt_status vrt_formal_solution(vrt_grid g, vrt_prec prec, vrt_exec exec, int32_t
     if (n_lambda <= 0) fail(VRT_E_ARG, "n_lambda must be positive");
     if (g->R == 0) fail(VRT_E_STATE, "rays not set");
     if (g->n > 0 && (!chi || !S || !J)) fail(VRT_E_ARG, "chi, S and J are required");
+    if (g->segment && exec == VRT_EXEC_PERSISTENT)
+      fail(VRT_E_ARG, "the quadratic segment runs plain, batched or graph sweeps");
     if (g->n == 0) return VRT_OK;
     if (prec == VRT_F32)
       formal_solution<float>(g, exec, n_lambda, chi, S, I_bottom, I_top, J, I_rays);
@@ -1456,6 +1520,8 @@ static vrt_status two_level_entry(vrt_grid g, vrt_prec prec, vrt_exec exec, int3
   if (g->n == 0 || max_iter == 0) return max_iter == 0 ? VRT_W_NOT_CONVERGED : VRT_OK;
   if (!phi || !chi_line || !chi_cont || !B || !S_line) fail(VRT_E_ARG, "null device array");
   if (accel != 0 && accel != 1) fail(VRT_E_ARG, "accel must be 0 or 1");
+  if (g->segment && (accel || exec == VRT_EXEC_PERSISTENT))
+    fail(VRT_E_ARG, "the quadratic segment runs the plain iteration with plain, batched or graph sweeps");
   if (prec == VRT_F32)
     return two_level_solve<float>(g, exec, n_lambda, wlam, phi, chi_line, chi_cont, B, eps, max_iter, tol, accel,
                                   S_line, n_atm, atm_ptr, dS_hist, n_iter);
@@ -1504,6 +1570,7 @@ vrt_status vrt_formal_solution_vjp(vrt_grid g, vrt_prec prec, int32_t n_lambda, 
   return guarded(g->ctx, [&] {
     if (!valid_prec(prec) || n_lambda <= 0 || ray_group < 0) fail(VRT_E_ARG, "bad precision, n_lambda or ray group");
     if (g->kind != 0) fail(VRT_E_ARG, "the reverse sweep exists for Voronoi grids only");
+    if (g->segment) fail(VRT_E_ARG, "the reverse sweep differentiates the linear segment only");
     if (g->R == 0) fail(VRT_E_STATE, "rays not set");
     if (g->n == 0) return VRT_OK;
     if (!chi || !S) fail(VRT_E_ARG, "chi and S are required");

@@ -185,6 +185,9 @@ struct vrt_grid_s {
   int lane_bytes = 16;   // bytes of a row each lane moves per access (16 or 32)
   int ray_groups = 1;    // the rays are swept in this many consecutive passes
   int interleave = 0;    // 1: step-wide sweeps read a copy of the records ordered by position across rays
+  int segment = 0;       // 0: linear source along a line, 1: quadratic Bezier (needs the downwind lines)
+  vrt::DevBuf d_q1, d_q2, d_qw1, d_qd1, d_qd2;  // downwind lines [R][n]: the selection of the opposite rays
+  bool down_built = false;
   vrt::DevBuf d_ri_x, d_rf32_x, d_rf64_x;
   bool interleaved_built = false;
 
@@ -336,6 +339,15 @@ template <typename T>
 void launch_regular(hipStream_t s, int32_t step, int32_t ray_begin, int32_t ray_count, int32_t nx,
                     int32_t ny, int32_t nz, double dx, double dy, const double *z, const double *dirs,
                     int32_t nl, const T *chi, const T *S, const T *Ibot, const T *Itop, T *I);
+
+// ---- k_bezier.hip
+// the quadratic Bezier sweep of a contiguous record range; q1, q2, qw1, qd1,
+// qd2 [R][n] are the downwind lines (the upwind selection of the opposite rays)
+template <typename T>
+void launch_bezier_sweep(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *rf, int64_t rec_begin,
+                         int64_t rec_count, int32_t nl, int64_t n, const int32_t *q1, const int32_t *q2,
+                         const double *qw1, const double *qd1, const double *qd2, const T *chi, const T *S,
+                         const T *Ibot, const T *Itop, T *I);
 
 // ---- k_synth.hip
 // the two nearest sites of the points on the lattice of one stride, by brute

@@ -43,6 +43,7 @@ VRT_TUNE_CHAINS = 6
 VRT_TUNE_LANE_BYTES = 8
 VRT_TUNE_RAY_GROUPS = 9
 VRT_TUNE_INTERLEAVE = 10
+VRT_TUNE_SEGMENT = 11
 
 VRT_F64 = 0
 VRT_F32 = 1

@@ -1,0 +1,168 @@
+"""GPU parity of the quadratic Bezier segment (the higher-order solver Sect. 2.5
+points to) against the oracle's Bezier sweep: intensities and J in FP64 to
+1e-12, FP32 J to 1e-5 (single intensities 1e-4), for one, three and 64
+wavelengths with optical
+depths per segment from thin to thick; the same results from plain, batched
+and graph execution; the two-level iteration with the Bezier formal solution;
+and the combinations the library refuses."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import flush, recipe_grid, relerr, to_dev
+from oracle import nlte as onl
+from synth.nlte import LAMBDA0_NM, line_setup
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def v():
+    import paper_2306_01041_amd
+
+    return paper_2306_01041_amd.load()
+
+
+@pytest.fixture(scope="module")
+def ctx(v):
+    c = v.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def case():
+    atm, g = recipe_grid(2000, seed=505)
+    dirs, w = synth.gauss_legendre_quadrature()
+    return atm, g, dirs, w, oracle.select(g, dirs), oracle.select_downwind(g, dirs)
+
+
+def _fields(atm, nl, seed):
+    lam = np.linspace(450e-9, 700e-9, nl)
+    chi, S = oracle.lte(lam, atm.kappa0, atm.T, atm.rho)
+    # spread the segment optical depths over several decades
+    chi = chi * np.random.default_rng(seed).uniform(0.01, 100.0, (1, nl))
+    return chi, S
+
+
+def _bezier_grid(v, ctx, g, dirs, w, before=True):
+    G = v.Grid.from_synth(ctx, g)
+    if before:
+        G.tune(v.VRT_TUNE_SEGMENT, 1)
+        G.set_rays(dirs, w)
+    else:
+        G.set_rays(dirs, w)
+        G.tune(v.VRT_TUNE_SEGMENT, 1)
+    return G
+
+
+@pytest.mark.parametrize("nl", [1, 3, 64])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_bezier_matches_oracle(v, ctx, case, nl, prec):
+    flush(f"bezier nl={nl} {prec}")
+    atm, g, dirs, w, sel, down = case
+    chi, S = _fields(atm, nl, nl)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    if prec == "f32":
+        # the oracle takes the same (rounded) inputs: optical depths of several
+        # hundred would otherwise magnify the input rounding in e^-tau
+        chi, S = (a.astype(np.float32).astype(np.float64) for a in (chi, S))
+    Jo, Io = oracle.fs_voronoi_bezier(g, dirs, w, sel, down, chi, S, S, keep_I=True)
+    G = _bezier_grid(v, ctx, g, dirs, w, before=(nl != 3))
+    c_d, S_d = to_dev(chi, dt), to_dev(S, dt)
+    out = {}
+    for mode in ("GRAPH", "BATCHED", "PLAIN"):
+        J = torch.empty_like(c_d)
+        I = torch.empty((len(dirs), g.n, nl), dtype=dt, device="cuda:0")
+        v.formal_solution(G, c_d, S_d, J, I_rays=I, exec_mode=getattr(v, "VRT_EXEC_" + mode))
+        torch.cuda.synchronize()
+        out[mode] = (J.cpu().numpy(), I.cpu().numpy())
+    # FP32: 1e-5 on J and 1e-4 on single intensities (small downward intensities
+    # near the top carry their rounding relative to a small value), as for the
+    # linear segment
+    tol = 1e-12 if prec == "f64" else 1e-5
+    eJ, eI = relerr(out["GRAPH"][0], Jo), relerr(out["GRAPH"][1], Io)
+    flush(f"  J {eJ:.2e}, I {eI:.2e}")
+    assert eJ <= tol and eI <= (tol if prec == "f64" else 1e-4)
+    for mode in ("BATCHED", "PLAIN"):
+        assert np.array_equal(out[mode][0], out["GRAPH"][0]) and np.array_equal(out[mode][1], out["GRAPH"][1])
+    # back to the linear segment
+    G.tune(v.VRT_TUNE_SEGMENT, 0)
+    J = torch.empty_like(c_d)
+    v.formal_solution(G, c_d, S_d, J)
+    torch.cuda.synchronize()
+    assert relerr(J.cpu().numpy(), oracle.fs_voronoi(g, dirs, w, sel, chi, S, S)) <= tol
+    G.close()
+
+
+def test_bezier_isothermal_and_top_boundary(v, ctx, case):
+    flush("bezier isothermal")
+    atm, g, dirs, w, sel, down = case
+    nl = 2
+    chi, _ = _fields(atm, nl, 7)
+    B = np.broadcast_to(np.array([3.0, 11.0]), (g.n, nl)).copy()
+    G = _bezier_grid(v, ctx, g, dirs, w)
+    d = torch.float64
+    J = torch.empty((g.n, nl), dtype=d, device="cuda:0")
+    v.formal_solution(G, to_dev(chi, d), to_dev(B, d), J, I_top=to_dev(B, d))
+    assert relerr(J.cpu().numpy(), B) <= 1e-14
+    G.close()
+
+
+def test_bezier_refusals(v, ctx, case):
+    flush("bezier refusals")
+    atm, g, dirs, w, sel, down = case
+    chi, S = _fields(atm, 4, 3)
+    G = _bezier_grid(v, ctx, g, dirs, w)
+    d = torch.float64
+    c_d, S_d = to_dev(chi, d), to_dev(S, d)
+    J = torch.empty_like(c_d)
+    for call in (lambda: v.formal_solution(G, c_d, S_d, J, exec_mode=v.VRT_EXEC_PERSISTENT),
+                 lambda: v.formal_solution_vjp(G, c_d, S_d, dL_dJ=torch.ones_like(c_d)),
+                 lambda: v.autotune(G, c_d, S_d, J, reps=1)):
+        with pytest.raises(v.VrtError) as e:
+            call()
+        assert e.value.status == v.VRT_E_ARG
+    R = v.Grid.regular(ctx, 4, 4, np.linspace(0, 1, 5), 0.25, 0.25)
+    with pytest.raises(v.VrtError) as e:
+        R.tune(v.VRT_TUNE_SEGMENT, 1)
+    assert e.value.status == v.VRT_E_ARG
+    R.close()
+    # the grid still runs
+    v.formal_solution(G, c_d, S_d, J)
+    torch.cuda.synchronize()
+    G.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_bezier_two_level_iteration_matches_oracle(v, ctx, prec):
+    flush(f"bezier two-level {prec}")
+    atm, g = recipe_grid(1500, seed=506)
+    dirs, w = synth.gauss_legendre_quadrature()
+    line = line_setup(atm.T, atm.rho, n_lambda=21)
+    lam0 = np.array([LAMBDA0_NM * 1e-9])
+    chi_c, B = oracle.lte(lam0, atm.kappa0, atm.T, atm.rho)
+    chi_c, B = chi_c[:, 0], B[:, 0]
+    eps, its = 1e-2, 6
+    sel, down = oracle.select(g, dirs), oracle.select_downwind(g, dirs)
+    S_o, h_o, _, _ = onl.lambda_iterate(g, dirs, w, sel, chi_c, line.chi_line, line.phi, line.wlam, B, eps,
+                                        max_iter=its, tol=0.0, down=down)
+    G = _bezier_grid(v, ctx, g, dirs, w)
+    d = torch.float64
+    S = to_dev(B, d)
+    st, nit, hist = v.two_level_solve(G, line.wlam, to_dev(line.phi, d), to_dev(line.chi_line, d), to_dev(chi_c, d),
+                                      to_dev(B, d), eps, S, max_iter=its, tol=0.0,
+                                      sweep_dtype=d if prec == "f64" else torch.float32)
+    torch.cuda.synchronize()
+    e = relerr(S.cpu().numpy(), S_o)
+    flush(f"  S_line after {its} iterations: {e:.2e}")
+    assert nit == its and e <= (1e-12 if prec == "f64" else 1e-5)
+    with pytest.raises(v.VrtError) as err:
+        v.two_level_solve(G, line.wlam, to_dev(line.phi, d), to_dev(line.chi_line, d), to_dev(chi_c, d),
+                          to_dev(B, d), eps, to_dev(B, d), max_iter=2, accel=True)
+    assert err.value.status == v.VRT_E_ARG
+    G.close()

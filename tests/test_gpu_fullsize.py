@@ -14,7 +14,9 @@ times (FP32 sweeps, graph-launched, default launch layout):
   101-point line, against the oracle's iteration;
 * the final synthesis from the 262,144-site grid to the regular 128 x 128 x
   256 grid with the 101-point line: the nearest sites of 4,096 sampled points
-  bit for bit and the mu = 1 emergent intensity of 64 sampled columns.
+  bit for bit and the mu = 1 emergent intensity of 64 sampled columns;
+* the quadratic Bezier segment on the 262,144-site grid, 64 wavelengths, FP32
+  graph-launched: J against the oracle's Bezier sweep (1e-5).
 
 Each case prints what it is about to run and the errors it finds.
 """
@@ -320,3 +322,25 @@ def test_c1_synthesis_full_size(v, ctx, c1):
         args[1] = None
     G.close()
     R.close()
+
+
+def test_c1_bezier_full_size(v, ctx, c1):
+    atm, g, dirs, w, sel = c1
+    nl = 64
+    lam = np.linspace(400e-9, 900e-9, nl)
+    chi_o, S_o = oracle.lte(lam, atm.kappa0, atm.T, atm.rho)
+    flush("c1 Bezier segment, 262,144 sites, 64 wavelengths, FP32 graph")
+    G = v.Grid.from_synth(ctx, g)
+    G.tune(v.VRT_TUNE_SEGMENT, 1)
+    G.set_rays(dirs, w)
+    f = torch.float32
+    J = torch.empty((g.n, nl), dtype=f, device="cuda:0")
+    v.formal_solution(G, to_dev(chi_o, f), to_dev(S_o, f), J, exec_mode=v.VRT_EXEC_GRAPH)
+    torch.cuda.synchronize()
+    G.close()
+    t0 = time.time()
+    Jo = oracle.fs_voronoi_bezier(g, dirs, w, sel, oracle.select_downwind(g, dirs), chi_o, S_o, S_o)
+    flush(f"  oracle done in {time.time() - t0:.1f} s")
+    e = relerr(J.cpu().numpy(), Jo)
+    flush(f"  FP32 Bezier J vs oracle: {e:.3e}")
+    assert e <= 1e-5

@@ -13,6 +13,8 @@ Printed as one JSON line with, besides the headline value:
                launch time (HIP events on the library's stream), vs 8 TB/s;
   fp64_plain   the plain FP64 GPU path (one launch per ray and level) and the
                FP32-batched speed-up over it;
+  bezier_segment  the formal solution with the quadratic Bezier segment and
+               its time relative to the linear one;
   adjoint      forward and reverse-sweep times of the differentiable emergent
                intensity (32 wavelengths 500-700 nm on the same grid) and
                their ratio;
@@ -92,6 +94,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward timing")
     ap.add_argument("--no-regular", action="store_true", help="skip the regular-grid and synthesis timings")
     ap.add_argument("--no-synthesis", action="store_true", help="skip the final-synthesis timing")
+    ap.add_argument("--no-bezier", action="store_true", help="skip the quadratic-segment timing")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the grid's default launch layout (for profiler runs that average over dispatches)")
     ap.add_argument("--interleave", action="store_true",
@@ -268,6 +271,25 @@ def main():
         log(f"FP64 plain step {ms64:.2f} ms; FP32 graph speed-up {ms64 / ms_step:.1f}x; FP32 J err {jerr:.2e}")
         del chi64, S64, J64
 
+    # the quadratic Bezier segment on the same grid and fields (FP32, graph-launched)
+    bezier = None
+    if not args.no_bezier:
+        G.tune(v.VRT_TUNE_SEGMENT, 1)
+        v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_GRAPH)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(5):
+            v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_GRAPH)
+        e1.record(stream)
+        e1.synchronize()
+        ms_b = e0.elapsed_time(e1) / 5
+        G.tune(v.VRT_TUNE_SEGMENT, 0)
+        bezier = {"workload": "the same formal solution with the quadratic Bezier segment (FP32, graph)",
+                  "ms": round(ms_b, 3), "updates_per_s": updates / (ms_b * 1e-3),
+                  "over_linear": round(ms_b / fs_ms, 2)}
+        log(f"Bezier segment: {ms_b:.3f} ms per formal solution ({ms_b / fs_ms:.2f}x the linear one)")
+
     # adjoint of the LTE formal solution (same grid, 32 wavelengths 500-700 nm):
     # forward = continuum + formal solution keeping per-ray intensities + emergent
     # gather; backward = emergent scatter + reverse sweep + LTE chain rule
@@ -408,6 +430,7 @@ def main():
                      "sweep_ms_per_step": round(sweep_ms, 4), "j_quadrature_ms": round(jr_one, 4)},
         "whole_step_effective_GBs": round(updates * (20.0 + 20.0 / nl) / (ms_step * 1e-3) / 1e9, 1),
         "fp64_plain": fp64,
+        "bezier_segment": bezier,
         "adjoint": adjoint,
         "regular_grid": regular,
         "synthesis": synthesis,

@@ -19,12 +19,18 @@
 //
 // One launch updates a contiguous range of the sweep records (one level of
 // one ray, or one level step of all rays), 16 lanes per record striding over
-// wavelengths.
+// wavelengths with 16-byte vectors when the rows allow, workgroups dealt to
+// the dies in contiguous chunks of records.
 
 #include "segment.h"
 #include "vrt_internal.h"
 
 namespace {
+
+// a / b: IEEE division in double precision; in single precision the hardware
+// reciprocal (about 1 ulp) times a
+__device__ __forceinline__ double qdiv(double a, double b) { return a / b; }
+__device__ __forceinline__ float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
 template <typename T> struct Bez;
 
@@ -70,10 +76,10 @@ template <> struct Bez<float> {
       b = sb * x;
       c = sc * x;
     } else {
-      const float x2 = x * x;
-      a = (2.0f - E * (x2 + 2.0f * x + 2.0f)) / x2;
-      b = 1.0f - 2.0f * (E + x - 1.0f) / x2;
-      c = 2.0f * (x - 2.0f + E * (x + 2.0f)) / x2;
+      const float x2 = x * x, r = __builtin_amdgcn_rcpf(x2);
+      a = (2.0f - E * (x2 + 2.0f * x + 2.0f)) * r;
+      b = 1.0f - 2.0f * (E + x - 1.0f) * r;
+      c = 2.0f * (x - 2.0f + E * (x + 2.0f)) * r;
     }
   }
 };
@@ -82,13 +88,13 @@ template <> struct Bez<float> {
 template <typename T>
 __device__ __forceinline__ T control(T Su, T S0, T x, bool has_d, T dd, T xd) {
   if (!(x > T(0))) return S0;
-  const T du = (S0 - Su) / x;
+  const T du = qdiv(S0 - Su, x);
   T d;
   if (!has_d) {
     d = du;
   } else if (du * dd > T(0)) {
-    const T a = (T(1) + xd / (x + xd)) / T(3);
-    d = du * dd / (a * dd + (T(1) - a) * du);
+    const T a = (T(1) + qdiv(xd, x + xd)) * T(1.0 / 3.0);
+    d = qdiv(du * dd, a * dd + (T(1) - a) * du);
   } else {
     d = T(0);
   }
@@ -101,17 +107,48 @@ __device__ __forceinline__ T control(T Su, T S0, T x, bool has_d, T dd, T xd) {
 
 constexpr int kLanes = 16;  // lanes per record
 
-template <typename T>
+template <typename T, int V> struct BLane {
+  typedef T type __attribute__((ext_vector_type(V)));
+  static __device__ __forceinline__ type load(const T *p) { return *reinterpret_cast<const type *>(p); }
+  static __device__ __forceinline__ void store(T *p, const type &v) { *reinterpret_cast<type *>(p) = v; }
+};
+template <typename T> struct BLane<T, 1> {
+  typedef T type;
+  static __device__ __forceinline__ type load(const T *p) { return *p; }
+  static __device__ __forceinline__ void store(T *p, const type &v) { *p = v; }
+};
+template <typename T, int V> __device__ __forceinline__ T el(const typename BLane<T, V>::type &v, int k) {
+  if constexpr (V == 1) return v;
+  else return v[k];
+}
+template <typename T, int V> __device__ __forceinline__ void set_el(typename BLane<T, V>::type &v, int k, T x) {
+  if constexpr (V == 1) v = x;
+  else v[k] = x;
+}
+
+// Workgroup b works on the (b mod k)-th of k contiguous chunks of the launch's
+// records, so neighbouring records share an accelerator die (dealt round-robin).
+__device__ __forceinline__ int64_t die_chunked_block(int32_t k) {
+  const int64_t b = blockIdx.x, nb = gridDim.x;
+  if (k <= 1 || nb < k) return b;
+  const int64_t x = b % k, j = b / k, per = nb / k, rem = nb % k;
+  return x * per + (x < rem ? x : rem) + j;
+}
+
+// kLanes lanes per record, V consecutive wavelengths per lane (nl a multiple of V)
+template <typename T, int V>
 __global__ __launch_bounds__(256) void bezier_sweep_kernel(
     const int4 *__restrict__ ri, const typename vrt::RecOf<T>::type *__restrict__ rf, int64_t rec_begin,
     int64_t rec_count, int32_t nl, int64_t n, const int32_t *__restrict__ q1, const int32_t *__restrict__ q2,
     const double *__restrict__ qw1, const double *__restrict__ qd1, const double *__restrict__ qd2,
     const T *__restrict__ chi, const T *__restrict__ S, const T *__restrict__ Ibot, const T *__restrict__ Itop,
-    T *I) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    T *I, int32_t xcd_chunks) {
+  using L = BLane<T, V>;
+  using VT = typename L::type;
+  const int64_t t = die_chunked_block(xcd_chunks) * blockDim.x + threadIdx.x;
   const int64_t r = t / kLanes;
   if (r >= rec_count) return;
-  const int l0 = (int)(t % kLanes);
+  const int l0 = (int)(t % kLanes) * V;
   const int64_t rec = rec_begin + r;
   const int4 q = ri[rec];
   const int32_t site = q.x, k1 = q.y, k2 = q.z, ray = q.w >> 1;
@@ -119,7 +156,13 @@ __global__ __launch_bounds__(256) void bezier_sweep_kernel(
   T *Iray = I + (int64_t)ray * n * nl;
   const int64_t bi = (int64_t)site * nl;
   if (k1 < 0) {
-    for (int l = l0; l < nl; l += kLanes) Iray[bi + l] = up ? Ibot[bi + l] : (Itop ? Itop[bi + l] : T(0));
+    for (int l = l0; l < nl; l += kLanes * V) {
+      VT v;
+      if (up) v = L::load(Ibot + bi + l);
+      else if (Itop) v = L::load(Itop + bi + l);
+      else v = VT(T(0));
+      L::store(Iray + bi + l, v);
+    }
     return;
   }
   const auto f = rf[rec];
@@ -131,37 +174,66 @@ __global__ __launch_bounds__(256) void bezier_sweep_kernel(
   const bool two_d = d2 >= 0;
   const T qa = two_d ? (T)qw1[rs] : T(1);
   const T g1 = T(0.5) * (T)qd1[rs], g2 = T(0.5) * (T)qd2[rs];
-  for (int l = l0; l < nl; l += kLanes) {
-    const T ci = chi[bi + l], si = S[bi + l];
-    bool has_d = d1 >= 0;
-    T dd = T(0), xd = T(0);
-    if (has_d) {
-      const T x1 = (chi[(int64_t)d1 * nl + l] + ci) * g1;
-      T x2 = T(1);
-      if (two_d) x2 = (chi[(int64_t)d2 * nl + l] + ci) * g2;
-      if (!(x1 > T(0)) || !(x2 > T(0))) {
-        has_d = false;
-      } else {
-        dd = qa * (S[(int64_t)d1 * nl + l] - si) / x1;
-        xd = qa * x1;
-        if (two_d) {
-          dd += (T(1) - qa) * (S[(int64_t)d2 * nl + l] - si) / x2;
-          xd += (T(1) - qa) * x2;
-        }
+  const int64_t bk1 = (int64_t)k1 * nl, bk2 = (int64_t)(two ? k2 : k1) * nl;
+  const int64_t bd1 = (int64_t)(d1 >= 0 ? d1 : site) * nl, bd2 = (int64_t)(two_d ? d2 : site) * nl;
+  for (int l = l0; l < nl; l += kLanes * V) {
+    const VT ci = L::load(chi + bi + l), si = L::load(S + bi + l);
+    const VT ck1 = L::load(chi + bk1 + l), sk1 = L::load(S + bk1 + l), ik1 = L::load(Iray + bk1 + l);
+    VT ck2 = ck1, sk2 = sk1, ik2 = ik1;
+    if (two) {
+      ck2 = L::load(chi + bk2 + l);
+      sk2 = L::load(S + bk2 + l);
+      ik2 = L::load(Iray + bk2 + l);
+    }
+    VT cq1 = ci, sq1 = si, cq2 = ci, sq2 = si;
+    if (d1 >= 0) {
+      cq1 = L::load(chi + bd1 + l);
+      sq1 = L::load(S + bd1 + l);
+      if (two_d) {
+        cq2 = L::load(chi + bd2 + l);
+        sq2 = L::load(S + bd2 + l);
       }
     }
-    T out = T(0);
-    for (int j = 0; j < (two ? 2 : 1); ++j) {
-      const int64_t bk = (int64_t)(j == 0 ? k1 : k2) * nl;
-      const T x = (chi[bk + l] + ci) * (j == 0 ? h1 : h2);
-      const T Su = S[bk + l];
-      const T C = control(Su, si, x, has_d, dd, xd);
-      T E, a, b, c;
-      Bez<T>::weights(x, E, a, b, c);
-      const T Ij = E * Iray[bk + l] + a * Su + b * si + c * C;
-      out += (j == 0 ? w1 : T(1) - w1) * Ij;
+    VT out;
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      const T c0 = el<T, V>(ci, e), s0 = el<T, V>(si, e);
+      bool has_d = d1 >= 0;
+      T dd = T(0), xd = T(0);
+      if (has_d) {
+        const T x1 = (el<T, V>(cq1, e) + c0) * g1;
+        const T x2 = two_d ? (el<T, V>(cq2, e) + c0) * g2 : T(1);
+        if (!(x1 > T(0)) || !(x2 > T(0))) {
+          has_d = false;
+        } else {
+          dd = qa * qdiv(el<T, V>(sq1, e) - s0, x1);
+          xd = qa * x1;
+          if (two_d) {
+            dd += (T(1) - qa) * qdiv(el<T, V>(sq2, e) - s0, x2);
+            xd += (T(1) - qa) * x2;
+          }
+        }
+      }
+      T Iv;
+      {
+        const T x = (el<T, V>(ck1, e) + c0) * h1;
+        const T Su = el<T, V>(sk1, e);
+        const T C = control(Su, s0, x, has_d, dd, xd);
+        T E, a, b, c;
+        Bez<T>::weights(x, E, a, b, c);
+        Iv = w1 * (E * el<T, V>(ik1, e) + a * Su + b * s0 + c * C);
+      }
+      if (two) {
+        const T x = (el<T, V>(ck2, e) + c0) * h2;
+        const T Su = el<T, V>(sk2, e);
+        const T C = control(Su, s0, x, has_d, dd, xd);
+        T E, a, b, c;
+        Bez<T>::weights(x, E, a, b, c);
+        Iv += (T(1) - w1) * (E * el<T, V>(ik2, e) + a * Su + b * s0 + c * C);
+      }
+      set_el<T, V>(out, e, Iv);
     }
-    Iray[bi + l] = out;
+    L::store(Iray + bi + l, out);
   }
 }
 
@@ -173,21 +245,27 @@ template <typename T>
 void launch_bezier_sweep(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *rf, int64_t rec_begin,
                          int64_t rec_count, int32_t nl, int64_t n, const int32_t *q1, const int32_t *q2,
                          const double *qw1, const double *qd1, const double *qd2, const T *chi, const T *S,
-                         const T *Ibot, const T *Itop, T *I) {
+                         const T *Ibot, const T *Itop, T *I, int32_t xcd_chunks) {
   if (rec_count <= 0) return;
-  const int64_t threads = rec_count * kLanes;
-  bezier_sweep_kernel<T><<<(unsigned)((threads + 255) / 256), 256, 0, s>>>(
-      ri, rf, rec_begin, rec_count, nl, n, q1, q2, qw1, qd1, qd2, chi, S, Ibot, Itop, I);
+  const unsigned blocks = (unsigned)((rec_count * kLanes + 255) / 256);
+  constexpr int V = 16 / (int)sizeof(T);
+  auto al = [](const void *p) { return p == nullptr || (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  if (nl % V == 0 && al(chi) && al(S) && al(Ibot) && al(Itop) && al(I))
+    bezier_sweep_kernel<T, V><<<blocks, 256, 0, s>>>(ri, rf, rec_begin, rec_count, nl, n, q1, q2, qw1, qd1, qd2, chi,
+                                                     S, Ibot, Itop, I, xcd_chunks);
+  else
+    bezier_sweep_kernel<T, 1><<<blocks, 256, 0, s>>>(ri, rf, rec_begin, rec_count, nl, n, q1, q2, qw1, qd1, qd2, chi,
+                                                     S, Ibot, Itop, I, xcd_chunks);
   VRT_HIP(hipGetLastError());
 }
 
 template void launch_bezier_sweep<float>(hipStream_t, const int4 *, const RecF32 *, int64_t, int64_t, int32_t,
                                          int64_t, const int32_t *, const int32_t *, const double *, const double *,
                                          const double *, const float *, const float *, const float *, const float *,
-                                         float *);
+                                         float *, int32_t);
 template void launch_bezier_sweep<double>(hipStream_t, const int4 *, const RecF64 *, int64_t, int64_t, int32_t,
                                           int64_t, const int32_t *, const int32_t *, const double *, const double *,
                                           const double *, const double *, const double *, const double *,
-                                          const double *, double *);
+                                          const double *, double *, int32_t);
 
 }  // namespace vrt

@@ -530,21 +530,29 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
   if (g->kind == 0 && g->segment == 1) {
     const int4 *ri = g->d_ri.as<int4>();
     const auto *rf = records<T>(g);
-    auto sweep = [&](int64_t b, int64_t c) {
+    auto sweep = [&](const int4 *rix, decltype(rf) rfx, int64_t b, int64_t c) {
       if (c <= 0) return;
       timed_launch(ctx, s, tm, 0, c * nl, [&] {
-        vrt::launch_bezier_sweep<T>(s, ri, rf, b, c, nl, n, g->d_q1.as<int32_t>(), g->d_q2.as<int32_t>(),
+        vrt::launch_bezier_sweep<T>(s, rix, rfx, b, c, nl, n, g->d_q1.as<int32_t>(), g->d_q2.as<int32_t>(),
                                     g->d_qw1.as<double>(), g->d_qd1.as<double>(), g->d_qd2.as<double>(), chi, S, Ib,
-                                    It, I);
+                                    It, I, g->xcd_chunks);
       });
     };
     if (ex == VRT_EXEC_PLAIN) {
       for (int32_t r = 0; r < R; ++r)
         for (int32_t st = 0; st < g->n_levels[(size_t)r]; ++st)
-          sweep(g->seg_off[(size_t)st * R + r], g->seg_cnt[(size_t)st * R + r]);
+          sweep(ri, rf, g->seg_off[(size_t)st * R + r], g->seg_cnt[(size_t)st * R + r]);
     } else {
+      // step-wide launches read the interleaved copy when there is one
+      const int4 *rix = ri;
+      auto rfx = rf;
+      if (g->interleave && g->interleaved_built) {
+        rix = g->d_ri_x.as<int4>();
+        rfx = sizeof(T) == 4 ? reinterpret_cast<decltype(rf)>(g->d_rf32_x.p)
+                             : reinterpret_cast<decltype(rf)>(g->d_rf64_x.p);
+      }
       for (int32_t st = 0; st < g->n_steps; ++st)
-        sweep(g->step_ptr[(size_t)st], g->step_ptr[(size_t)st + 1] - g->step_ptr[(size_t)st]);
+        sweep(rix, rfx, g->step_ptr[(size_t)st], g->step_ptr[(size_t)st + 1] - g->step_ptr[(size_t)st]);
     }
   } else if (g->kind == 0 && ex == VRT_EXEC_PERSISTENT) {
     const bool aligned = vrt::al16(chi) && vrt::al16(S) && vrt::al16(Ib) && vrt::al16(It) && vrt::al16(I);

@@ -347,7 +347,7 @@ template <typename T>
 void launch_bezier_sweep(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *rf, int64_t rec_begin,
                          int64_t rec_count, int32_t nl, int64_t n, const int32_t *q1, const int32_t *q2,
                          const double *qw1, const double *qd1, const double *qd2, const T *chi, const T *S,
-                         const T *Ibot, const T *Itop, T *I);
+                         const T *Ibot, const T *Itop, T *I, int32_t xcd_chunks);
 
 // ---- k_synth.hip
 // the two nearest sites of the points on the lattice of one stride, by brute

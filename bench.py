@@ -100,10 +100,12 @@ def main():
     ap.add_argument("--interleave", action="store_true",
                     help="with --no-autotune: sweep the interleaved record copy (the layout the autotuner picks "
                          "on this workload)")
-    ap.add_argument("--workload", choices=["c1", "c2", "c3", "synth"], default="c1",
+    ap.add_argument("--workload", choices=["c1", "c2", "c3", "synth", "design"], default="c1",
                     help="c1: the formal solution (default line); c2: the two-level Lambda iteration on 1,048,576 "
                          "sites; c3: 48 atmospheres of 32,768-524,288 sites solved as one batch; synth: only the "
-                         "final synthesis from the 262,144-site grid to the regular 128 x 128 x 256 grid")
+                         "final synthesis from the 262,144-site grid to the regular 128 x 128 x 256 grid; "
+                         "design: the grid-design accuracy workload (searchlight beams, LTE continuum "
+                         "intensities against site count and sampling density)")
     ap.add_argument("--accel", action="store_true",
                     help="c2/c3: the Jacobi-accelerated iteration (local operator) instead of the plain one")
     ap.add_argument("--max-iter", type=int, default=None,
@@ -128,6 +130,9 @@ def main():
         sys.exit(2)
     if args.workload == "synth":
         run_synthesis_only(args)
+        return
+    if args.workload == "design":
+        run_design(args)
         return
     if args.workload != "c1":
         run_lambda(args)
@@ -548,6 +553,135 @@ def run_synthesis_only(args):
     Gr.close()
     G.close()
     ctx.close()
+
+
+def _design_grid(args):
+    """Sites of one sampling density, their Voronoi grid and state (process pool)."""
+    import synth
+    from synth import design
+
+    name, n, seed = args
+    xyz = synth.sample_sites(n, seed) if name == "dlntau" else design.sample_sites_density(n, seed, name)
+    atm = synth.make_atmosphere(n, seed=1041, xyz=xyz)
+    g = synth.voronoi_neighbours(atm.xyz, atm.box.lo, atm.box.hi)
+    return name, n, atm, g
+
+
+def run_design(args):
+    """Grid-design workload (accuracy, not throughput):
+    * searchlight beams (Sect. 3.1): 51^3 uniformly random sites and the 51^3
+      lattice in a periodic 1 m box, chi = S = 0, a beam of radius 0.2 m on the
+      bottom face, one ray at 20, 45 and 60 degrees from the vertical: peak and
+      edge width of the beam at the top, and the shift of its centre against
+      tan(theta);
+    * LTE continuum at 500 nm and mu = 1 (Sect. 3.2): the opacity at the sites of
+      grids sampled from several densities and site counts is carried to the
+      regular 128 x 128 x 256 grid by two-nearest-site inverse distances and the
+      columns are integrated; the result is compared with the same columns on
+      the exact regular-grid opacity."""
+    from multiprocessing import get_context
+
+    import torch
+
+    import paper_2306_01041_amd
+    import synth
+    from synth import design
+
+    v = paper_2306_01041_amd.load()
+    dev = "cuda:0"
+    f64 = torch.float64
+    ctx = v.Context(0)
+    out = {"workload": "design", "searchlight": [], "lte_sweep": []}
+
+    # searchlight
+    xyz, lo, hi, _, _, beam = design.searchlight()
+    t0 = time.time()
+    g = synth.voronoi_neighbours(xyz, lo, hi, periodic_xy=True)
+    log(f"searchlight grid {g.n} sites in {time.time() - t0:.1f} s")
+    n_side = 51
+    zr = np.linspace(0.0, 1.0, n_side)
+    dxr = 1.0 / n_side
+    Xr, Yr = np.meshgrid(np.arange(n_side) * dxr, np.arange(n_side) * dxr, indexing="xy")
+    for theta in (20.0, 45.0, 60.0):
+        th = np.deg2rad(theta)
+        d = np.array([[np.sin(th), 0.0, np.cos(th)]])
+        row = {"theta_deg": theta}
+        for kind in ("voronoi", "regular"):
+            if kind == "voronoi":
+                G = v.Grid.from_synth(ctx, g)
+                m = g.n
+                Ib = beam(g.xyz[:, 0], g.xyz[:, 1])
+            else:
+                G = v.Grid.regular(ctx, n_side, n_side, zr, dxr, dxr)
+                m = n_side ** 3
+                Ib = np.zeros(m)
+                Ib[: n_side * n_side] = beam(Xr.ravel(), Yr.ravel())
+            G.set_rays(d, np.array([1.0]))
+            zero = torch.zeros((m, 1), dtype=f64, device=dev)
+            J = torch.empty_like(zero)
+            I = torch.empty((1, m, 1), dtype=f64, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            v.formal_solution(G, zero, zero, J, I_bottom=torch.as_tensor(Ib[:, None], device=dev), I_rays=I)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            _, sites = G.emergent_index()
+            It = I[0, :, 0].cpu().numpy()[sites]
+            if kind == "voronoi":
+                xt = g.xyz[sites, 0]
+            else:
+                xt = (sites % n_side) * dxr
+            cx = (np.angle(np.sum(It * np.exp(2j * np.pi * xt))) / (2 * np.pi)) % 1.0
+            want = (0.5 + np.tan(th)) % 1.0
+            shift_err = (cx - want + 0.5) % 1.0 - 0.5
+            # edge width: the area where 0.1 < I < 0.9, over the beam circumference
+            frac_edge = float(np.mean((It > 0.1) & (It < 0.9)))
+            row[kind] = {"peak": float(It.max()), "edge_width_m": frac_edge / (2 * np.pi * 0.2),
+                         "centre_error_m": float(shift_err), "ms": round(ms, 3)}
+            G.close()
+        out["searchlight"].append(row)
+        log(f"searchlight {theta:.0f} deg: {row}")
+
+    # LTE continuum against site count and sampling density
+    box = synth.BoxSpec()
+    nx = ny = 128
+    dxr, dyr, zr, xyz_r = regular_recipe(box, nx, ny, 256)
+    atr = synth.make_atmosphere(len(xyz_r), seed=1041, xyz=xyz_r)
+    R = v.Grid.regular(ctx, nx, ny, zr, dxr, dyr)
+    lam = np.array([500e-9])
+    Tr, rr = torch.as_tensor(atr.T, device=dev), torch.as_tensor(atr.rho, device=dev)
+    chi_r = torch.empty((len(xyz_r), 1), dtype=f64, device=dev)
+    S_r = torch.empty_like(chi_r)
+    v.lte_continuum(R, lam, atr.kappa0, Tr, rr, chi_r, S_r)
+    I_ref = v.lc_vertical(R, chi_r, S_r).cpu().numpy()[:, 0]
+    jobs = [(name, n, 1041) for n in (65536, 262144) for name in ("dlntau", "log_nh_t", "log_nhii", "alpha_c")]
+    with get_context("spawn").Pool(min(8, len(jobs))) as pool:
+        for name, n, atm, gd in pool.imap(_design_grid, jobs):
+            G = v.Grid.from_synth(ctx, gd)
+            chi_s = torch.empty((n, 1), dtype=f64, device=dev)
+            S_s = torch.empty_like(chi_s)
+            v.lte_continuum(G, lam, atm.kappa0, torch.as_tensor(atm.T, device=dev),
+                            torch.as_tensor(atm.rho, device=dev), chi_s, S_s)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            idx, w1 = v.idw_map(G, R)
+            chi_i = v.idw_apply(G, R, idx, w1, chi_s[:, 0].contiguous())
+            I_int = v.lc_vertical(R, chi_i[:, None].contiguous(), S_r)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            I_int = I_int.cpu().numpy()[:, 0]
+            rel = np.abs(I_int - I_ref) / I_ref
+            row = {"density": name, "sites": n, "mean_rel_err": float(rel.mean()),
+                   "p99_rel_err": float(np.quantile(rel, 0.99)), "max_rel_err": float(rel.max()),
+                   "contrast_ref": float(I_ref.std() / I_ref.mean()), "contrast": float(I_int.std() / I_int.mean()),
+                   "correlation": float(np.corrcoef(I_ref, I_int)[0, 1]), "map_and_solve_ms": round(ms, 3)}
+            out["lte_sweep"].append(row)
+            log(f"LTE sweep {name} {n}: mean err {row['mean_rel_err']:.3e}, p99 {row['p99_rel_err']:.3e}, "
+                f"corr {row['correlation']:.4f}")
+            G.close()
+    R.close()
+    ctx.close()
+    print(json.dumps(out))
 
 
 def _make_grid(args):

@@ -225,3 +225,35 @@ def test_batch_sizes_are_seeded_and_in_range():
     assert len(s) == 48 and min(s) >= 32768 and max(s) <= 524288
     # log-uniform: about half below the geometric mean of the bounds
     assert 14 <= sum(x < np.sqrt(32768 * 524288) for x in s) <= 34
+
+
+@pytest.mark.parametrize("name", ["alpha_c", "log_nhii", "log_nh_t"])
+def test_design_densities_are_sampled_in_proportion(name):
+    """Rejection sampling (Sect. 2.4) reproduces the target density: the
+    height histogram of the accepted sites matches the x-y integral of f."""
+    from synth import design
+
+    box = synth.BoxSpec()
+    n = 200000
+    xyz = design.sample_sites_density(n, 11, name)
+    assert xyz.shape == (n, 3)
+    assert np.all(xyz >= np.asarray(box.lo)) and np.all(xyz <= np.asarray(box.hi))
+    edges = np.linspace(box.lo[2], box.hi[2], 13)
+    got = np.histogram(xyz[:, 2], edges)[0] / n
+    rng = np.random.default_rng(12)
+    probe = np.asarray(box.lo) + rng.random((1 << 21, 3)) * box.L
+    f = design.target_density(name, probe)
+    want = np.histogram(probe[:, 2], edges, weights=f)[0]
+    want /= want.sum()
+    big = want > 0.01
+    assert np.all(np.abs(got[big] - want[big]) <= 0.05 * want[big] + 0.002)
+
+
+def test_design_densities_order_the_heights():
+    """The line-oriented density puts more sites high in the box than the
+    continuum extinction (which piles them at the bottom)."""
+    from synth import design
+
+    zc = np.median(design.sample_sites_density(20000, 3, "alpha_c")[:, 2])
+    zl = np.median(design.sample_sites_density(20000, 3, "log_nh_t")[:, 2])
+    assert zc < 0.0 < zl

@@ -98,8 +98,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the grid's default launch layout (for profiler runs that average over dispatches)")
     ap.add_argument("--interleave", action="store_true",
-                    help="with --no-autotune: sweep the interleaved record copy (the layout the autotuner picks "
-                         "on this workload)")
+                    help="sweep the interleaved record copy: with --no-autotune on c1 (the layout the autotuner "
+                         "picks there), and on c2/c3")
     ap.add_argument("--workload", choices=["c1", "c2", "c3", "synth", "design"], default="c1",
                     help="c1: the formal solution (default line); c2: the two-level Lambda iteration on 1,048,576 "
                          "sites; c3: 48 atmospheres of 32,768-524,288 sites solved as one batch; synth: only the "
@@ -751,6 +751,10 @@ def run_lambda(args):
     setup_s = time.time() - t0
     info = G.info()
     log(f"rays set in {setup_s:.2f} s: {info}")
+    if args.interleave:
+        t0 = time.time()
+        G.tune(v.VRT_TUNE_INTERLEAVE, 1)
+        log(f"interleaved record copy built in {time.time() - t0:.2f} s")
     d = torch.float64
     lam0 = np.array([LAMBDA0_NM * 1e-9])
     # one continuum constant for the batch (a recipe constant)
@@ -825,6 +829,7 @@ def run_lambda(args):
         "solve_s": round(total_s, 3),
         "setup_s": round(setup_s, 3),
         "whole_step_effective_GBs": round(updates * (20.0 + 20.0 / nl) / (fs_ms * 1e-3) / 1e9, 1),
+        "interleaved_records": bool(args.interleave),
     }
     print(json.dumps(out))
     G.close()

@@ -16,12 +16,12 @@
 // site, until it touches the first gives an empty ball through both, whose
 // centre lies inside the (convex) box. So the scan of the nearest site's list
 // that confirms the walk's end also yields the second site. Points are
-// processed coarse to fine: the points of a coarse lattice (at most 64 of
-// them) by brute force over all sites, then lattices of half the stride down
-// to every point, each new point walking from the nearest site of its parent
-// on the previous lattice, so walks are a few steps long. Distances use the same operations in the same order as their
-// definition and no fused multiply-add, so the chosen sites are reproducible
-// on any IEEE-754 machine.
+// processed coarse to fine: the points of a coarse lattice (points x sites at
+// most 2^24) by brute force over all sites, then lattices of half the stride
+// down to every point, each new point walking from the nearest site of its
+// parent on the previous lattice, so walks are a few steps long. Distances use
+// the same operations in the same order as their definition and no fused
+// multiply-add, so the chosen sites are reproducible on any IEEE-754 machine.
 //
 // Columns. One thread per (column, wavelength); consecutive threads take
 // consecutive wavelengths and then columns, so each horizontal plane of a

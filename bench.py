@@ -68,14 +68,19 @@ def counter_traffic(nl, n, mode, layout):
     launch layout or kernel sources that have changed since."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "sweep_kernel_c1_counters.json")
-    if mode == "persistent" or nl != 64 or n != 262144 or not os.path.exists(path):
+    persistent = mode == "persistent"
+    name = "persistent_sweep_c1_counters.json" if persistent else "sweep_kernel_c1_counters.json"
+    path = os.path.join(ROOT, "profiles", name)
+    if nl != 64 or n != 262144 or not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if {k: rec.get("layout", {}).get(k) for k in LAYOUT_KEYS} != {k: layout.get(k) for k in LAYOUT_KEYS}:
+    # the persistent sweep reads the per-ray record order whatever the layout knobs say
+    if not persistent and ({k: rec.get("layout", {}).get(k) for k in LAYOUT_KEYS}
+                           != {k: layout.get(k) for k in LAYOUT_KEYS}):
         return None
     h = hashlib.sha256()
-    for f in ("paper_2306_01041_amd/csrc/k_sweep.hip", "paper_2306_01041_amd/csrc/segment.h"):
+    src = "k_persist.hip" if persistent else "k_sweep.hip"
+    for f in (f"paper_2306_01041_amd/csrc/{src}", "paper_2306_01041_amd/csrc/segment.h"):
         h.update(open(os.path.join(ROOT, f), "rb").read())
     if h.hexdigest()[:16] != rec.get("source_sha256_16"):
         return None
@@ -179,14 +184,17 @@ def main():
     mode_times = {}
     if args.mode == "auto":
         for name in ("graph", "persistent"):
-            for _ in range(2):
-                v.formal_solution(G, chi, S, J, exec_mode=modes[name])
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(5):
-                v.formal_solution(G, chi, S, J, exec_mode=modes[name])
-            G.device_status()
-            mode_times[name] = (time.perf_counter() - t0) * 1e3 / 5
+            try:
+                for _ in range(2):
+                    v.formal_solution(G, chi, S, J, exec_mode=modes[name])
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(5):
+                    v.formal_solution(G, chi, S, J, exec_mode=modes[name])
+                G.device_status()
+                mode_times[name] = (time.perf_counter() - t0) * 1e3 / 5
+            except v.VrtError as e:  # a mode that reports an error is not a candidate
+                log(f"launch mode {name} failed: {e}")
         args.mode = min(mode_times, key=mode_times.get)
         log(f"launch modes (ms per formal solution): {mode_times} -> {args.mode}")
     mode = modes[args.mode]

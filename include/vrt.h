@@ -61,10 +61,11 @@ typedef enum { VRT_F64 = 0, VRT_F32 = 1 } vrt_prec;
  * PLAIN:      one kernel per (ray, level) of the upwind schedule, rays in turn.
  * BATCHED:    one kernel per level step with all rays in flight together.
  * GRAPH:      BATCHED, captured once into a HIP graph and replayed.
- * PERSISTENT: one cooperative kernel for all rays and levels; each site waits
- *             for the completion stamps of its upwind sites (Voronoi grids;
- *             regular grids fall back to GRAPH). Check vrt_grid_device_status
- *             after synchronising to learn whether a bounded wait gave up. */
+ * PERSISTENT: one kernel for all rays and levels; each site waits for the
+ *             completion stamps of its upwind sites (Voronoi grids; regular
+ *             grids fall back to GRAPH). One ray's intensities must stay below
+ *             4 GiB (else VRT_E_ARG). Check vrt_grid_device_status after
+ *             synchronising to learn whether a bounded wait gave up. */
 typedef enum {
   VRT_EXEC_PLAIN = 0,
   VRT_EXEC_BATCHED = 1,

@@ -1,23 +1,49 @@
 // Persistent, dataflow-ordered Voronoi sweep: the whole formal solution of
-// every ray in one cooperative launch instead of one launch per level.
+// every ray in one launch instead of one launch per level step.
 //
-// Work is the step-major sweep record list (level 0 of every ray, then level
-// 1, ...), cut into wave items of at most 64/C records that never straddle a
-// level step (records of one step are independent of each other, so no item
-// waits on itself). Every wavefront of the grid is
-// resident (cooperative launch) and walks the items w, w + W, w + 2W, ... in
-// increasing order (W = number of wavefronts). Before updating a site it waits
-// until both of its upwind sites carry the current epoch stamp in a
-// per-(ray, site) flag; after writing the site's intensity row it publishes
-// the row (release at agent scope) and stamps the site's flag. Upwind sites
-// always sit in earlier items, and the wave that owns the earliest unfinished
-// item has finished all its own earlier items, so that item can always
-// proceed: the sweep cannot deadlock. Each wait is bounded anyway; a wave that
-// exceeds the bound raises a device error flag, every other waiting wave sees
-// it and stops waiting, and the launch always drains.
+// Work is the step-major sweep record list (level step 0 of every ray, then
+// step 1, ...), cut into wave items of at most 64/C records that never
+// straddle a level step (records of one step are independent of each other,
+// so no item waits on itself).
+//
+// Ranks. Every wavefront first registers in a counter; the first one to
+// register waits until the whole grid has registered, or until the count has
+// stopped growing for a while, then freezes the counter and publishes the
+// count W. A wavefront that registered before the freeze has a rank q < W
+// and walks items q, q + W, q + 2W, ... in increasing order; one that
+// registers after the freeze (a workgroup that was not resident) does
+// nothing. Only running wavefronts therefore hold work. The occupancy the
+// runtime reports cannot promise that by itself: it counts vector registers,
+// and a kernel with more than about 80 scalar registers fits one wavefront
+// per SIMD fewer than reported (measured: with 86 to 98 scalar registers a
+// grid sized that way was never wholly resident, with 71 it was). The
+// kernels are compiled with at most 80 scalar registers, so the whole grid
+// is normally resident and the freeze comes as soon as the last wavefront
+// has registered.
+//
+// Dataflow. Before updating a site a lane waits until both of its upwind
+// sites carry the current epoch stamp in a per-(ray, site) flag; after
+// writing the site's intensity row the wave stamps the site. Upwind sites
+// always sit in earlier items, and the wavefront that owns the earliest
+// unfinished item has finished all its own earlier items, so that item can
+// always proceed: the sweep cannot deadlock. Each wait is bounded anyway; a
+// wave that exceeds the bound raises a device error flag, every other waiting
+// wave then stops waiting, and the launch drains.
+//
+// Coherence without cache maintenance. The eight dies have separate L2
+// caches, and the agent-scope fences that order plain accesses write back
+// and invalidate a whole L2 at every handshake (a sweep built on them took
+// 49 ms). Instead every access to the data that passes between wavefronts
+// carries the device-scope cache policy (sc1): the intensity rows are stored
+// and loaded through buffer descriptors with sc1, and the stamps, polls and
+// registration words are relaxed agent-scope atomics. A wave waits for its
+// row stores to complete (vmcnt 0) before it stamps, and reads an upwind row
+// only after it has seen the row's stamp. chi, S and the boundary rows are
+// only read, so they stay cached.
 //
 // Flags hold an epoch number that a one-thread kernel increments before each
-// sweep, so they never need clearing between sweeps.
+// sweep (and the registration words are cleared there), so the flags never
+// need clearing between sweeps.
 
 #include "segment.h"
 #include "vrt_internal.h"
@@ -27,29 +53,65 @@ namespace {
 template <typename T, int V> struct PLane {
   typedef T type __attribute__((ext_vector_type(V)));
   static __device__ __forceinline__ type load(const T *p) { return *reinterpret_cast<const type *>(p); }
-  static __device__ __forceinline__ void store(T *p, const type &v) { *reinterpret_cast<type *>(p) = v; }
   static __device__ __forceinline__ T get(const type &v, int k) { return v[k]; }
   static __device__ __forceinline__ void set(type &v, int k, T x) { v[k] = x; }
 };
 template <typename T> struct PLane<T, 1> {
   typedef T type;
   static __device__ __forceinline__ type load(const T *p) { return *p; }
-  static __device__ __forceinline__ void store(T *p, const type &v) { *p = v; }
   static __device__ __forceinline__ T get(const type &v, int) { return v; }
   static __device__ __forceinline__ void set(type &v, int, T x) { v = x; }
 };
 
-__global__ void epoch_kernel(int32_t *epoch) { *epoch += 1; }
+// Scope of the polls and stamps: relaxed agent-scope atomics (sc1)
+constexpr int kXScope = __HIP_MEMORY_SCOPE_AGENT;
+// cache-policy bits of the intensity-row buffer accesses: sc1 (device scope)
+constexpr int kRowPolicy = 16;
+// buffer descriptor word 3 of an untyped 32-bit buffer on gfx9 targets
+constexpr int kRawBufferWord3 = 0x00020000;
+
+// Device-scope loads and stores of 4, 8 or 16 bytes at byte offset `off` of
+// the buffer `r` (one ray's block of intensity rows)
+template <typename X> __device__ __forceinline__ X row_load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  if constexpr (sizeof(X) == 16) {
+    return __builtin_bit_cast(X, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, kRowPolicy));
+  } else if constexpr (sizeof(X) == 8) {
+    return __builtin_bit_cast(X, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, kRowPolicy));
+  } else {
+    return __builtin_bit_cast(X, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kRowPolicy));
+  }
+}
+template <typename X> __device__ __forceinline__ void row_store(__amdgpu_buffer_rsrc_t r, uint32_t off, const X &v) {
+  if constexpr (sizeof(X) == 16) {
+    typedef uint32_t U __attribute__((ext_vector_type(4)));
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U, v), r, off, 0, kRowPolicy);
+  } else if constexpr (sizeof(X) == 8) {
+    typedef uint32_t U __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U, v), r, off, 0, kRowPolicy);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, kRowPolicy);
+  }
+}
+
+constexpr int32_t kFrozen = 1 << 30;
+
+// words: [0] epoch, [1] device error, [2] registration word (count, plus
+// kFrozen once frozen), [3] frozen count + 1 (0 until frozen)
+__global__ void begin_kernel(int32_t *words) {
+  words[0] += 1;
+  words[2] = 0;
+  words[3] = 0;
+}
 
 // Wait until *f == epoch. Returns false if the bound was exceeded or another
 // wave already gave up (then the caller proceeds without the data).
 __device__ __forceinline__ bool wait_stamp(const int32_t *f, int32_t epoch, int32_t *err, int64_t cap) {
   int64_t it = 0;
-  while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+  while (__hip_atomic_load(f, __ATOMIC_RELAXED, kXScope) != epoch) {
     ++it;
-    if ((it & 63) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+    if ((it & 63) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, kXScope) != 0) return false;
     if (it > cap) {
-      __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, kXScope);
       return false;
     }
     __builtin_amdgcn_s_sleep(1);
@@ -57,36 +119,87 @@ __device__ __forceinline__ bool wait_stamp(const int32_t *f, int32_t epoch, int3
   return true;
 }
 
+// polls without a new registration after which the count is frozen
+constexpr int32_t kStallPolls = 512;
+
+// Registration (wave-uniform): returns this wavefront's rank and sets W, or
+// returns -1 for a wavefront that registered after the freeze. The first
+// wavefront polls until `total` have registered, the count has not changed
+// for kStallPolls polls, or `cap` polls have passed.
+__device__ __forceinline__ int64_t register_wave(int32_t *words, int32_t total, int64_t cap, int lane,
+                                                 int64_t &W) {
+  int32_t *reg = words + 2, *frozen = words + 3, *err = words + 1;
+  int32_t old = 0;
+  if (lane == 0) old = __hip_atomic_fetch_add(reg, 1, __ATOMIC_RELAXED, kXScope);
+  old = __builtin_amdgcn_readfirstlane(old);
+  if (old & kFrozen) return -1;
+  if (old == 0) {
+    int64_t it = 0;
+    int32_t last = -1, still = 0;
+    for (;;) {
+      const int32_t c = __hip_atomic_load(reg, __ATOMIC_RELAXED, kXScope);
+      if (c >= total || ++it > cap) break;
+      if (c == last) {
+        if (++still > kStallPolls) break;
+      } else {
+        last = c;
+        still = 0;
+      }
+      __builtin_amdgcn_s_sleep(8);
+    }
+    int32_t got = 0;
+    if (lane == 0) {
+      got = __hip_atomic_fetch_or(reg, kFrozen, __ATOMIC_RELAXED, kXScope) & (kFrozen - 1);
+      __hip_atomic_store(frozen, got + 1, __ATOMIC_RELAXED, kXScope);
+    }
+    W = __builtin_amdgcn_readfirstlane(got);
+    return 0;
+  }
+  int64_t it = 0;
+  int32_t f;
+  while ((f = __hip_atomic_load(frozen, __ATOMIC_RELAXED, kXScope)) == 0) {
+    if (++it > cap) {
+      __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, kXScope);
+      return -1;
+    }
+    __builtin_amdgcn_s_sleep(8);
+  }
+  W = __builtin_amdgcn_readfirstlane(f - 1);
+  return old;
+}
+
 // item_rec[i] = first record of wave item i, item_cnt[i] = its record count (<= 64/C)
 template <typename T, int C, int V>
-__global__ __launch_bounds__(256) void persistent_sweep_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void persistent_sweep_kernel(
     const int4 *__restrict__ ri, const typename vrt::RecOf<T>::type *__restrict__ rf,
     const int64_t *__restrict__ item_rec, const int32_t *__restrict__ item_cnt, int64_t n_items, int32_t nl,
-    int64_t n, const T *__restrict__ chi, const T *__restrict__ S, const T *__restrict__ Ibot,
-    const T *__restrict__ Itop, T *I, int32_t *flags, const int32_t *__restrict__ epoch_p, int32_t *err,
-    int64_t spin_cap) {
+    int64_t n, int64_t flag_ld, const T *__restrict__ chi, const T *__restrict__ S, const T *__restrict__ Ibot,
+    const T *__restrict__ Itop, T *I, int32_t *flags, int32_t *words, int64_t spin_cap) {
   using L = PLane<T, V>;
   using VT = typename L::type;
-  const int32_t epoch = *epoch_p;
+  const int32_t epoch = words[0];
+  int32_t *err = words + 1;
   const int lane = threadIdx.x & 63;
-  const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int64_t W = (int64_t)gridDim.x * (blockDim.x >> 6);
+  int64_t W = 0;
+  const int64_t rank = register_wave(words, (int32_t)(gridDim.x * (blockDim.x >> 6)), spin_cap, lane, W);
+  if (rank < 0) return;
   const int l0 = (lane % C) * V;
-  for (int64_t item = gw; item < n_items; item += W) {
-    const int sub = lane / C;
+  const int sub = lane / C;
+  for (int64_t item = rank; item < n_items; item += W) {
     const bool live = sub < item_cnt[item];
     const int64_t rec = item_rec[item] + sub;
     int4 q = make_int4(0, -1, -1, 0);
     if (live) q = ri[rec];
     const int32_t site = q.x, k1 = q.y, k2 = q.z, ray = q.w >> 1;
     const bool up = (q.w & 1) != 0;
-    int32_t *fr = flags + (int64_t)ray * n;
+    int32_t *fr = flags + (int64_t)ray * flag_ld;
     if (live && k1 >= 0) {
       if (wait_stamp(fr + k1, epoch, err, spin_cap) && k2 >= 0) wait_stamp(fr + k2, epoch, err, spin_cap);
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (live) {
-      T *Iray = I + (int64_t)ray * n * nl;
+      // one ray's block of n * nl values (below 4 GiB: checked by the host)
+      const __amdgpu_buffer_rsrc_t Iray = __builtin_amdgcn_make_buffer_rsrc(
+          I + (int64_t)ray * n * nl, 0, (int)(uint32_t)(n * nl * (int64_t)sizeof(T)), kRawBufferWord3);
       const int64_t bi = (int64_t)site * nl;
       if (k1 < 0) {
         for (int l = l0; l < nl; l += C * V) {
@@ -94,7 +207,7 @@ __global__ __launch_bounds__(256) void persistent_sweep_kernel(
           if (up) v = L::load(Ibot + bi + l);
           else if (Itop) v = L::load(Itop + bi + l);
           else v = VT(T(0));
-          L::store(Iray + bi + l, v);
+          row_store<VT>(Iray, (uint32_t)((bi + l) * sizeof(T)), v);
         }
       } else {
         const auto f = rf[rec];
@@ -105,12 +218,13 @@ __global__ __launch_bounds__(256) void persistent_sweep_kernel(
         const int64_t b2 = (int64_t)(two ? k2 : k1) * nl;
         for (int l = l0; l < nl; l += C * V) {
           const VT ci = L::load(chi + bi + l), si = L::load(S + bi + l);
-          const VT c1 = L::load(chi + b1 + l), s1 = L::load(S + b1 + l), u1 = L::load(Iray + b1 + l);
+          const VT c1 = L::load(chi + b1 + l), s1 = L::load(S + b1 + l);
+          const VT u1 = row_load<VT>(Iray, (uint32_t)((b1 + l) * sizeof(T)));
           VT c2, s2, u2;
           if (two) {
             c2 = L::load(chi + b2 + l);
             s2 = L::load(S + b2 + l);
-            u2 = L::load(Iray + b2 + l);
+            u2 = row_load<VT>(Iray, (uint32_t)((b2 + l) * sizeof(T)));
           }
           VT out;
 #pragma unroll
@@ -126,21 +240,22 @@ __global__ __launch_bounds__(256) void persistent_sweep_kernel(
             }
             L::set(out, k, Iv);
           }
-          L::store(Iray + bi + l, out);
+          row_store<VT>(Iray, (uint32_t)((bi + l) * sizeof(T)), out);
         }
       }
     }
-    // publish the rows written by every lane of the wave, then stamp the sites
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    if (live && (lane % C) == 0) __hip_atomic_store(fr + site, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // every row store of the wave has completed before any of its stamps
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    if (live && (lane % C) == 0) __hip_atomic_store(fr + site, epoch, __ATOMIC_RELAXED, kXScope);
   }
 }
 
 template <typename T, int C, int V>
 void launch_pc(hipStream_t s, const vrt::PersistItems &it, int32_t max_blocks, const int4 *ri,
-               const typename vrt::RecOf<T>::type *rf, int32_t nl, int64_t n, const T *chi, const T *S,
-               const T *Ibot, const T *Itop, T *I, int32_t *flags, const int32_t *epoch, int32_t *err,
-               int64_t cap) {
+               const typename vrt::RecOf<T>::type *rf, int32_t nl, int64_t n, int64_t flag_ld, const T *chi,
+               const T *S, const T *Ibot, const T *Itop, T *I, int32_t *flags, int32_t *words, int64_t cap) {
   if (it.spw != 64 / C) throw vrt::Error(VRT_E_STATE, "persistent item table built for another record width");
   auto kern = persistent_sweep_kernel<T, C, V>;
   int dev = 0, cus = 0, per_cu = 0;
@@ -148,34 +263,32 @@ void launch_pc(hipStream_t s, const vrt::PersistItems &it, int32_t max_blocks, c
   VRT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   VRT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0));
   if (per_cu < 1) throw vrt::Error(VRT_E_HIP, "persistent sweep kernel cannot be resident");
-  const int64_t items = it.n_items;
+  // as many workgroups as the runtime says can be resident (registration
+  // gives work only to those that run), at most one wave item per wavefront
   int64_t blocks = (int64_t)cus * per_cu;
   if (max_blocks > 0 && blocks > max_blocks) blocks = max_blocks;
-  if (blocks > (items + 3) / 4) blocks = (items + 3) / 4;
+  if (blocks > (it.n_items + 3) / 4) blocks = (it.n_items + 3) / 4;
   if (blocks < 1) blocks = 1;
   const int64_t *item_rec = it.rec.as<int64_t>();
   const int32_t *item_cnt = it.cnt.as<int32_t>();
-  int64_t n_items = items;
-  void *args[] = {(void *)&ri,  (void *)&rf,   (void *)&item_rec, (void *)&item_cnt, (void *)&n_items,
-                  (void *)&nl,  (void *)&n,    (void *)&chi,      (void *)&S,        (void *)&Ibot,
-                  (void *)&Itop, (void *)&I,   (void *)&flags,    (void *)&epoch,    (void *)&err,
-                  (void *)&cap};
-  VRT_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3((unsigned)blocks), dim3(256), args, 0,
-                                     s));
+  const int64_t n_items = it.n_items;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, s, ri, rf, item_rec, item_cnt, n_items, nl, n,
+                     flag_ld, chi, S, Ibot, Itop, I, flags, words, cap);
+  VRT_HIP(hipGetLastError());
 }
 
 template <typename T, int V>
 void launch_pv(hipStream_t s, const vrt::PersistItems &it, int32_t mb, const int4 *ri,
-               const typename vrt::RecOf<T>::type *rf, int32_t nl, int64_t n, const T *chi, const T *S, const T *Ibot,
-               const T *Itop, T *I, int32_t *flags, const int32_t *epoch, int32_t *err, int64_t cap) {
+               const typename vrt::RecOf<T>::type *rf, int32_t nl, int64_t n, int64_t fl, const T *chi, const T *S,
+               const T *Ibot, const T *Itop, T *I, int32_t *flags, int32_t *words, int64_t cap) {
   switch (vrt::lanes_per_record(nl / V)) {
-    case 64: launch_pc<T, 64, V>(s, it, mb, ri, rf, nl, n, chi, S, Ibot, Itop, I, flags, epoch, err, cap); break;
-    case 32: launch_pc<T, 32, V>(s, it, mb, ri, rf, nl, n, chi, S, Ibot, Itop, I, flags, epoch, err, cap); break;
-    case 16: launch_pc<T, 16, V>(s, it, mb, ri, rf, nl, n, chi, S, Ibot, Itop, I, flags, epoch, err, cap); break;
-    case 8: launch_pc<T, 8, V>(s, it, mb, ri, rf, nl, n, chi, S, Ibot, Itop, I, flags, epoch, err, cap); break;
-    case 4: launch_pc<T, 4, V>(s, it, mb, ri, rf, nl, n, chi, S, Ibot, Itop, I, flags, epoch, err, cap); break;
-    case 2: launch_pc<T, 2, V>(s, it, mb, ri, rf, nl, n, chi, S, Ibot, Itop, I, flags, epoch, err, cap); break;
-    default: launch_pc<T, 1, V>(s, it, mb, ri, rf, nl, n, chi, S, Ibot, Itop, I, flags, epoch, err, cap); break;
+    case 64: launch_pc<T, 64, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap); break;
+    case 32: launch_pc<T, 32, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap); break;
+    case 16: launch_pc<T, 16, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap); break;
+    case 8: launch_pc<T, 8, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap); break;
+    case 4: launch_pc<T, 4, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap); break;
+    case 2: launch_pc<T, 2, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap); break;
+    default: launch_pc<T, 1, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap); break;
   }
 }
 
@@ -185,8 +298,8 @@ namespace vrt {
 
 bool al16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
-void launch_epoch(hipStream_t s, int32_t *epoch) {
-  hipLaunchKernelGGL(epoch_kernel, dim3(1), dim3(1), 0, s, epoch);
+void launch_persist_begin(hipStream_t s, int32_t *words) {
+  hipLaunchKernelGGL(begin_kernel, dim3(1), dim3(1), 0, s, words);
   VRT_HIP(hipGetLastError());
 }
 
@@ -198,24 +311,26 @@ int32_t persistent_records_per_wave(int32_t nl, int elem_bytes, bool aligned) {
 
 template <typename T>
 void launch_persistent_sweep(hipStream_t s, const PersistItems &items, int32_t max_blocks, const int4 *ri,
-                             const typename RecOf<T>::type *rf, int32_t nl, int64_t n, const T *chi, const T *S,
-                             const T *Ibot, const T *Itop, T *I, int32_t *flags, const int32_t *epoch, int32_t *err,
+                             const typename RecOf<T>::type *rf, int32_t nl, int64_t n, int64_t flag_ld, const T *chi,
+                             const T *S, const T *Ibot, const T *Itop, T *I, int32_t *flags, int32_t *words,
                              int64_t spin_cap) {
   if (items.n_items <= 0) return;
+  if (n * (int64_t)nl * (int64_t)sizeof(T) >= (int64_t(1) << 32))
+    throw Error(VRT_E_ARG, "persistent sweep: one ray's intensities exceed 4 GiB; use the level-step modes");
   constexpr int VW = 16 / sizeof(T);
   const bool aligned = al16(chi) && al16(S) && al16(Ibot) && al16(Itop) && al16(I);
   if (aligned && nl % VW == 0)
-    launch_pv<T, VW>(s, items, max_blocks, ri, rf, nl, n, chi, S, Ibot, Itop, I, flags, epoch, err, spin_cap);
+    launch_pv<T, VW>(s, items, max_blocks, ri, rf, nl, n, flag_ld, chi, S, Ibot, Itop, I, flags, words, spin_cap);
   else
-    launch_pv<T, 1>(s, items, max_blocks, ri, rf, nl, n, chi, S, Ibot, Itop, I, flags, epoch, err, spin_cap);
+    launch_pv<T, 1>(s, items, max_blocks, ri, rf, nl, n, flag_ld, chi, S, Ibot, Itop, I, flags, words, spin_cap);
 }
 
 template void launch_persistent_sweep<float>(hipStream_t, const PersistItems &, int32_t, const int4 *, const RecF32 *,
-                                             int32_t, int64_t, const float *, const float *, const float *,
-                                             const float *, float *, int32_t *, const int32_t *, int32_t *, int64_t);
+                                             int32_t, int64_t, int64_t, const float *, const float *, const float *,
+                                             const float *, float *, int32_t *, int32_t *, int64_t);
 template void launch_persistent_sweep<double>(hipStream_t, const PersistItems &, int32_t, const int4 *,
-                                              const RecF64 *, int32_t, int64_t, const double *, const double *,
-                                              const double *, const double *, double *, int32_t *, const int32_t *,
+                                              const RecF64 *, int32_t, int64_t, int64_t, const double *,
+                                              const double *, const double *, const double *, double *, int32_t *,
                                               int32_t *, int64_t);
 
 }  // namespace vrt

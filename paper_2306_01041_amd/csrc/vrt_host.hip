@@ -484,17 +484,21 @@ template <typename F> void timed_launch(vrt_ctx ctx, hipStream_t s, bool timed, 
   ctx->pending.push_back(t);
 }
 
-// Wave items of the persistent sweep for `spw` records per wave: every level
-// step is cut separately, so no item holds two levels of one ray.
-// per-(ray, site) epoch stamps and the epoch / device-error words
+// per-(ray, site) epoch stamps, each ray's block padded to whole 128-byte
+// cache lines, and the epoch / device-error / registration words
+int64_t flag_ld(vrt_grid g) { return (g->n + 31) / 32 * 32; }
+
 void ensure_flags(vrt_grid g) {
   if (g->d_flags.p) return;
-  g->d_flags.alloc((size_t)g->R * (size_t)g->n * 4);
-  VRT_HIP(hipMemsetAsync(g->d_flags.p, 0, (size_t)g->R * (size_t)g->n * 4, g->ctx->stream));
-  g->d_epoch.alloc(16);
-  VRT_HIP(hipMemsetAsync(g->d_epoch.p, 0, 16, g->ctx->stream));
+  const size_t bytes = (size_t)g->R * (size_t)flag_ld(g) * 4;
+  g->d_flags.alloc(bytes);
+  VRT_HIP(hipMemsetAsync(g->d_flags.p, 0, bytes, g->ctx->stream));
+  g->d_epoch.alloc(64);
+  VRT_HIP(hipMemsetAsync(g->d_epoch.p, 0, 64, g->ctx->stream));
 }
 
+// Wave items of the persistent sweep for `spw` records per wave: every level
+// step is cut separately, so no item holds two levels of one ray.
 const vrt::PersistItems &persistent_items(vrt_grid g, int32_t spw) {
   auto it = g->persist_items.find(spw);
   if (it != g->persist_items.end()) return *it->second;
@@ -557,11 +561,11 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
   } else if (g->kind == 0 && ex == VRT_EXEC_PERSISTENT) {
     const bool aligned = vrt::al16(chi) && vrt::al16(S) && vrt::al16(Ib) && vrt::al16(It) && vrt::al16(I);
     const vrt::PersistItems &items = persistent_items(g, vrt::persistent_records_per_wave(nl, sizeof(T), aligned));
-    int32_t *ep = g->d_epoch.as<int32_t>();
-    vrt::launch_epoch(s, ep);
+    int32_t *words = g->d_epoch.as<int32_t>();
+    vrt::launch_persist_begin(s, words);
     timed_launch(ctx, s, tm, 0, g->n_rec * nl, [&] {
-      vrt::launch_persistent_sweep<T>(s, items, g->persist_max_blocks, g->d_ri.as<int4>(), records<T>(g), nl, n, chi,
-                                      S, Ib, It, I, g->d_flags.as<int32_t>(), ep, ep + 1, g->spin_cap);
+      vrt::launch_persistent_sweep<T>(s, items, g->persist_max_blocks, g->d_ri.as<int4>(), records<T>(g), nl, n,
+                                      flag_ld(g), chi, S, Ib, It, I, g->d_flags.as<int32_t>(), words, g->spin_cap);
     });
   } else if (g->kind == 0) {
     const int4 *ri = g->d_ri.as<int4>();

@@ -287,13 +287,16 @@ void launch_lte(hipStream_t s, int64_t n, int32_t nl, const double *lam, double 
                 const double *rho, T *chi, T *S);
 
 // ---- k_persist.hip
-void launch_epoch(hipStream_t s, int32_t *epoch);
+// words: [0] epoch, [1] device error (non-zero: a bounded wait gave up),
+// [2] registration word, [3] frozen wavefront count + 1. Flags of ray r start
+// at flags + r * flag_ld.
+void launch_persist_begin(hipStream_t s, int32_t *words);
 int32_t persistent_records_per_wave(int32_t nl, int elem_bytes, bool aligned);
 bool al16(const void *p);
 template <typename T>
 void launch_persistent_sweep(hipStream_t s, const PersistItems &items, int32_t max_blocks, const int4 *ri,
-                             const typename RecOf<T>::type *rf, int32_t nl, int64_t n, const T *chi, const T *S,
-                             const T *Ibot, const T *Itop, T *I, int32_t *flags, const int32_t *epoch, int32_t *err,
+                             const typename RecOf<T>::type *rf, int32_t nl, int64_t n, int64_t flag_ld, const T *chi,
+                             const T *S, const T *Ibot, const T *Itop, T *I, int32_t *flags, int32_t *words,
                              int64_t spin_cap);
 
 // ---- k_nlte.hip

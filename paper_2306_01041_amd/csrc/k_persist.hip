@@ -2,9 +2,10 @@
 // every ray in one launch instead of one launch per level step.
 //
 // Work is the step-major sweep record list (level step 0 of every ray, then
-// step 1, ...), cut into wave items of at most 64/C records that never
-// straddle a level step (records of one step are independent of each other,
-// so no item waits on itself).
+// step 1, ...), cut into wave items of at most 64/C records of one (level
+// step, ray) segment (records of one step are independent of each other, so
+// no item waits on itself). The item table carries the ray, so the buffer
+// descriptor of the ray's intensity rows is uniform across the wavefront.
 //
 // Ranks. Every wavefront first registers in a counter; the first one to
 // register waits until the whole grid has registered, or until the count has
@@ -168,7 +169,8 @@ __device__ __forceinline__ int64_t register_wave(int32_t *words, int32_t total, 
   return old;
 }
 
-// item_rec[i] = first record of wave item i, item_cnt[i] = its record count (<= 64/C)
+// item_rec[i] = first record of wave item i, item_cnt[i] = its record count
+// (<= 64/C) + 256 x its ray
 template <typename T, int C, int V>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void persistent_sweep_kernel(
     const int4 *__restrict__ ri, const typename vrt::RecOf<T>::type *__restrict__ rf,
@@ -186,7 +188,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void pers
   const int l0 = (lane % C) * V;
   const int sub = lane / C;
   for (int64_t item = rank; item < n_items; item += W) {
-    const bool live = sub < item_cnt[item];
+    const int32_t cr = item_cnt[item];
+    const bool live = sub < (cr & 255);
     const int64_t rec = item_rec[item] + sub;
     int4 q = make_int4(0, -1, -1, 0);
     if (live) q = ri[rec];
@@ -197,9 +200,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void pers
       if (wait_stamp(fr + k1, epoch, err, spin_cap) && k2 >= 0) wait_stamp(fr + k2, epoch, err, spin_cap);
     }
     if (live) {
-      // one ray's block of n * nl values (below 4 GiB: checked by the host)
+      // the item's ray's block of n * nl values (below 4 GiB: checked by the host)
       const __amdgpu_buffer_rsrc_t Iray = __builtin_amdgcn_make_buffer_rsrc(
-          I + (int64_t)ray * n * nl, 0, (int)(uint32_t)(n * nl * (int64_t)sizeof(T)), kRawBufferWord3);
+          I + (int64_t)(cr >> 8) * n * nl, 0, (int)(uint32_t)(n * nl * (int64_t)sizeof(T)), kRawBufferWord3);
       const int64_t bi = (int64_t)site * nl;
       if (k1 < 0) {
         for (int l = l0; l < nl; l += C * V) {

@@ -497,18 +497,23 @@ void ensure_flags(vrt_grid g) {
   VRT_HIP(hipMemsetAsync(g->d_epoch.p, 0, 64, g->ctx->stream));
 }
 
-// Wave items of the persistent sweep for `spw` records per wave: every level
-// step is cut separately, so no item holds two levels of one ray.
+// Wave items of the persistent sweep for `spw` records per wave: every
+// (level step, ray) segment is cut separately, so no item holds two levels
+// of one ray or two rays; cnt holds the record count + 256 x the ray.
 const vrt::PersistItems &persistent_items(vrt_grid g, int32_t spw) {
   auto it = g->persist_items.find(spw);
   if (it != g->persist_items.end()) return *it->second;
+  const int32_t R = g->R;
+  if (R >= (1 << 23)) fail(VRT_E_ARG, "persistent sweep: too many rays");
   std::vector<int64_t> rec;
   std::vector<int32_t> cnt;
   for (int32_t st = 0; st < g->n_steps; ++st) {
-    const int64_t b = g->step_ptr[(size_t)st], e = g->step_ptr[(size_t)st + 1];
-    for (int64_t r = b; r < e; r += spw) {
-      rec.push_back(r);
-      cnt.push_back((int32_t)std::min<int64_t>(spw, e - r));
+    for (int32_t ray = 0; ray < R; ++ray) {
+      const int64_t b = g->seg_off[(size_t)st * R + ray], e = b + g->seg_cnt[(size_t)st * R + ray];
+      for (int64_t r = b; r < e; r += spw) {
+        rec.push_back(r);
+        cnt.push_back((int32_t)std::min<int64_t>(spw, e - r) + 256 * ray);
+      }
     }
   }
   std::unique_ptr<vrt::PersistItems> p(new vrt::PersistItems);

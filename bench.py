@@ -788,25 +788,38 @@ def run_lambda(args):
     chi[:, nl:] = chi_c[:, None]
     S[:, nl:] = B[:, None]
     J = torch.empty_like(chi)
-    for _ in range(2):
-        v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_GRAPH)
-    torch.cuda.synchronize()
-    k = 5
-    t1 = time.perf_counter()
-    for _ in range(k):
-        v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_GRAPH)
-    torch.cuda.synchronize()
-    fs_ms = (time.perf_counter() - t1) * 1e3 / k
+    # launch modes: the graph of level steps and the persistent sweep (auto: the
+    # faster of those that run; the persistent sweep refuses rays above 4 GiB)
+    modes = {"graph": v.VRT_EXEC_GRAPH, "batched": v.VRT_EXEC_BATCHED, "persistent": v.VRT_EXEC_PERSISTENT}
+    fs_by_mode = {}
+    for name in (("graph", "persistent") if args.mode == "auto" else (args.mode,)):
+        try:
+            for _ in range(2):
+                v.formal_solution(G, chi, S, J, exec_mode=modes[name])
+            torch.cuda.synchronize()
+            k = 5
+            t1 = time.perf_counter()
+            for _ in range(k):
+                v.formal_solution(G, chi, S, J, exec_mode=modes[name])
+            torch.cuda.synchronize()
+            G.device_status()
+            fs_by_mode[name] = (time.perf_counter() - t1) * 1e3 / k
+        except v.VrtError as e:
+            log(f"launch mode {name} not used: {e}")
+    mode_name = min(fs_by_mode, key=fs_by_mode.get)
+    fs_ms = fs_by_mode[mode_name]
     del chi, S, J
     updates = U.n * R * nl
-    log(f"formal solution {fs_ms:.3f} ms -> {updates / (fs_ms * 1e-3):.3e} updates/s")
+    log(f"formal solution (ms by launch mode): {fs_by_mode} -> {mode_name}: {fs_ms:.3f} ms, "
+        f"{updates / (fs_ms * 1e-3):.3e} updates/s")
 
     # the iteration to convergence (or the cap)
     max_iter = args.max_iter if args.max_iter is not None else (1000 if args.workload == "c2" else 100)
     log(f"Lambda iteration, at most {max_iter} iterations")
     t1 = time.perf_counter()
     st, its, hist = v.two_level_solve_batched(G, off, wlam, phi, chi_L, chi_c, B, eps, S_L,
-                                              max_iter=max_iter, tol=1e-3, sweep_dtype=f32, accel=args.accel)
+                                              max_iter=max_iter, tol=1e-3, sweep_dtype=f32,
+                                              exec_mode=modes[mode_name], accel=args.accel)
     torch.cuda.synchronize()
     total_s = time.perf_counter() - t1
     n_iter = int(np.max(its))
@@ -828,6 +841,8 @@ def run_lambda(args):
                    "sites": U.n, "atmospheres": len(grids), "wavelengths": nl, "rays": R,
                    "levels_max": info["max_levels"]},
         "formal_solution_ms": round(fs_ms, 3),
+        "launch_mode": mode_name,
+        "formal_solution_ms_by_mode": {k: round(t, 3) for k, t in fs_by_mode.items()},
         "ms_per_iteration": round(it_ms, 3),
         "formal_solution_share": round(fs_ms / it_ms, 3),
         "iterations": {"min": int(np.min(its)), "max": n_iter, "median": float(np.median(its)), "cap": max_iter},

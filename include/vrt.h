@@ -222,8 +222,11 @@ vrt_status vrt_grid_set_rays(vrt_grid grid, int32_t n_rays, const double *dir, c
 #define VRT_TUNE_SEGMENT 11
 /*   VRT_TUNE_SPIN_CAP       bound on the polls of one wait in the persistent
  *                           sweep [2^22]; a wait that exceeds it gives up.
- *   VRT_TUNE_PERSIST_BLOCKS cap on the persistent sweep's workgroups
- *                           [0 = as many as can be resident]. */
+ *   VRT_TUNE_PERSIST_BLOCKS workgroups of the persistent sweep, 1 .. 2^20
+ *                           [0 = as many as the runtime reports can be
+ *                           resident]; any count gives the same results
+ *                           (workgroups that are not resident when the
+ *                           others start take no work). */
 #define VRT_TUNE_SPIN_CAP 3
 #define VRT_TUNE_PERSIST_BLOCKS 4
 vrt_status vrt_grid_tune(vrt_grid grid, int32_t knob, int64_t value);

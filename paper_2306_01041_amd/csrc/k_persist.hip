@@ -266,11 +266,12 @@ void launch_pc(hipStream_t s, const vrt::PersistItems &it, int32_t max_blocks, c
   VRT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   VRT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0));
   if (per_cu < 1) throw vrt::Error(VRT_E_HIP, "persistent sweep kernel cannot be resident");
-  // as many workgroups as the runtime says can be resident (registration
-  // gives work only to those that run), at most one wave item per wavefront
+  // as many workgroups as the runtime says can be resident, at most one wave
+  // item per wavefront, unless the caller set the count (registration gives
+  // work only to those that run, so any count is correct)
   int64_t blocks = (int64_t)cus * per_cu;
-  if (max_blocks > 0 && blocks > max_blocks) blocks = max_blocks;
   if (blocks > (it.n_items + 3) / 4) blocks = (it.n_items + 3) / 4;
+  if (max_blocks > 0) blocks = max_blocks;
   if (blocks < 1) blocks = 1;
   const int64_t *item_rec = it.rec.as<int64_t>();
   const int32_t *item_cnt = it.cnt.as<int32_t>();

@@ -208,7 +208,7 @@ struct vrt_grid_s {
   // error flag (a bounded wait gave up) and wave-item tables by width
   vrt::DevBuf d_flags, d_epoch;
   std::map<int32_t, std::unique_ptr<vrt::PersistItems>> persist_items;
-  int32_t persist_max_blocks = 0;  // 0 = as many as can be resident
+  int32_t persist_max_blocks = 0;  // persistent-sweep workgroups; 0 = as many as can be resident
   int64_t spin_cap = int64_t(1) << 22;
 
   // two-level iteration scratch: chi, S, I_bottom in the sweep precision, the

@@ -339,6 +339,32 @@ def test_persistent_fp32_matches_graph_bitwise(v, ctx, quad, grids, nl):
     G.close()
 
 
+@pytest.mark.parametrize("nl", [64, 101])
+@pytest.mark.parametrize("blocks", [8, 8192])
+def test_persistent_any_grid_size_gives_the_same_result(v, ctx, quad, grids, nl, blocks):
+    """Work goes only to wavefronts that registered before the count was
+    frozen, so a grid of 8 workgroups, and one of 8192 (several times what can
+    be resident: the late workgroups take no work), give the graph sweep's
+    intensities bit for bit."""
+    flush(f"persistent grid of {blocks} workgroups nl={nl}")
+    atm, g = grids[16384]
+    dirs, w = quad
+    G = _gpu_grid(v, ctx, g, dirs, w)
+    chi_o, S_o = _fields(atm, nl, 13)
+    f = torch.float32
+    chi, S = to_dev(chi_o, f), to_dev(S_o, f)
+    Jg = torch.empty_like(chi)
+    v.formal_solution(G, chi, S, Jg, exec_mode=v.VRT_EXEC_GRAPH)
+    torch.cuda.synchronize()
+    G.tune(v.VRT_TUNE_PERSIST_BLOCKS, blocks)
+    for rep in range(2):
+        J = torch.full_like(chi, -1.0)
+        v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_PERSISTENT)
+        G.device_status()
+        assert np.array_equal(J.cpu().numpy(), Jg.cpu().numpy()), rep
+    G.close()
+
+
 def test_persistent_bounded_wait_reports_timeout(v, ctx, quad, grids):
     """A spin bound of zero polls makes the first unmet wait give up: the kernel
     still drains, the device status reports a timeout once, and the next

@@ -1,9 +1,11 @@
-"""Parity at the full workload sizes, in the launch configuration the benchmark
-times (FP32 sweeps, graph-launched, default launch layout):
+"""Parity at the full workload sizes, in the launch configurations the benchmark
+times (FP32 sweeps, graph-launched and persistent, default launch layout):
 
 * 262,144-site Voronoi grid, 64 wavelengths 400-900 nm, 24 rays: J and the
-  emergent intensities against the FP64 oracle (FP32 1e-5 on J), and the plain
-  FP64 GPU path against it (1e-12);
+  emergent intensities against the FP64 oracle (FP32 1e-5 on J) from the
+  graph-launched level steps and from the persistent sweep (the benchmark's
+  launch mode on this workload; identical to the graph bit for bit), and the
+  plain FP64 GPU path against it (1e-12);
 * the regular 128 x 128 x 256 grid: every 16th of the 64 wavelengths against
   the oracle at full grid size, and all 64 in FP32 against the FP64 GPU path;
 * the adjoint of the emergent intensity (32 wavelengths 500-700 nm, FP32
@@ -80,14 +82,20 @@ def test_c1_voronoi_full_size(v, ctx, c1):
     G = v.Grid.from_synth(ctx, g)
     G.set_rays(dirs, w)
     T, rho = to_dev(atm.T, torch.float64), to_dev(atm.rho, torch.float64)
-    for dt, tol_J, tol_I in ((torch.float32, 1e-5, 1e-4), (torch.float64, 1e-12, 1e-12)):
-        flush(f"  GPU {dt}")
+    prev = None
+    for dt, mode, tol_J, tol_I in ((torch.float32, v.VRT_EXEC_GRAPH, 1e-5, 1e-4),
+                                   (torch.float32, v.VRT_EXEC_PERSISTENT, 1e-5, 1e-4),
+                                   (torch.float64, v.VRT_EXEC_PLAIN, 1e-12, 1e-12)):
+        flush(f"  GPU {dt}, launch mode {mode}")
         chi = torch.empty((g.n, nl), dtype=dt, device="cuda:0")
         S = torch.empty_like(chi)
         J = torch.empty_like(chi)
         v.lte_continuum(G, lam, atm.kappa0, T, rho, chi, S)
-        mode = v.VRT_EXEC_GRAPH if dt == torch.float32 else v.VRT_EXEC_PLAIN
         v.formal_solution(G, chi, S, J, exec_mode=mode)
+        G.device_status()
+        if mode == v.VRT_EXEC_PERSISTENT:
+            assert np.array_equal(J.cpu().numpy(), prev)
+        prev = J.cpu().numpy()
         off, sites = G.emergent_index()
         em = torch.empty((int(off[-1]), nl), dtype=dt, device="cuda:0")
         v.emergent_gather(G, em)

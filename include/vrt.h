@@ -220,6 +220,13 @@ vrt_status vrt_grid_set_rays(vrt_grid grid, int32_t n_rays, const double *dir, c
  *                           accelerated iteration and the autotuner return
  *                           VRT_E_ARG with it. */
 #define VRT_TUNE_SEGMENT 11
+/*   VRT_TUNE_REVERSE_PERSISTENT 1 = the reverse sweep of vrt_formal_solution_vjp
+ *                           runs each ray group as one persistent launch (the
+ *                           dataflow of the persistent sweep run backwards:
+ *                           a site waits for the stamps of the sites that read
+ *                           it in the forward sweep); identical results [0].
+ *                           Check vrt_grid_device_status afterwards. */
+#define VRT_TUNE_REVERSE_PERSISTENT 13
 /*   VRT_TUNE_SPIN_CAP       bound on the polls of one wait in the persistent
  *                           sweep [2^22]; a wait that exceeds it gives up.
  *   VRT_TUNE_PERSIST_BLOCKS workgroups of the persistent sweep, 1 .. 2^20

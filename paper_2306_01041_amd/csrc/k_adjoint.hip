@@ -17,6 +17,7 @@
 // double precision afterwards; at boundary sites Ibar is the sensitivity to the
 // boundary intensity.
 
+#include "persist.h"
 #include "segment.h"
 #include "vrt_internal.h"
 
@@ -48,36 +49,53 @@ __device__ __forceinline__ T dI_dx(T E, T dp0, T Iu, T Su, T Sd) {
   return (T)(-(double)E * dI + (double)dp0 * dS);
 }
 
-// C lanes per record, V wavelengths per lane. Scratch arrays (I, Ibar, Sbar,
-// Cbar) hold the rays [ray0, ray0 + group) of the current ray group.
-template <typename T, int C, int V>
-__global__ __launch_bounds__(256) void reverse_kernel(
-    const int4 *__restrict__ ri, const typename vrt::RecOf<T>::type *__restrict__ rf, int64_t rec_begin,
-    int64_t rec_count, int32_t nl, int64_t n, int32_t ray0, const int64_t *__restrict__ dep_ptr,
-    const int32_t *__restrict__ dep_site, const typename vrt::RecOf<T>::type *__restrict__ dep_rec,
-    const T *__restrict__ chi, const T *__restrict__ S, const T *__restrict__ I, const T *__restrict__ gI,
-    const T *__restrict__ gJ, const double *__restrict__ ray_w, T *Ibar, T *__restrict__ Sbar,
-    T *__restrict__ Cbar) {
+// Adjoint rows of one ray, addressed by element index within the ray's block:
+// plain accesses for the level-step kernel (the kernel boundary orders them)
+template <typename T, int V> struct PlainRows {
+  T *base;
+  __device__ __forceinline__ typename ALane<T, V>::type load(int64_t e) const { return ALane<T, V>::load(base + e); }
+  __device__ __forceinline__ void store(int64_t e, const typename ALane<T, V>::type &v) const {
+    ALane<T, V>::store(base + e, v);
+  }
+};
+
+// and device-scope buffer accesses for the persistent kernel (other
+// wavefronts read the rows during the launch)
+template <typename T, int V> struct CoherentRows {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ typename ALane<T, V>::type load(int64_t e) const {
+    return vrt_persist::row_load<typename ALane<T, V>::type>(r, (uint32_t)(e * (int64_t)sizeof(T)));
+  }
+  __device__ __forceinline__ void store(int64_t e, const typename ALane<T, V>::type &v) const {
+    vrt_persist::row_store<typename ALane<T, V>::type>(r, (uint32_t)(e * (int64_t)sizeof(T)), v);
+  }
+};
+
+// The reverse update of one record (site k of one ray) for the wavelengths
+// l0, l0 + C V, ...: gather from the dependents, then the own segments.
+// Rows: the adjoint rows of the record's ray (dependents read, own written).
+template <typename T, int C, int V, typename Rows>
+__device__ __forceinline__ void reverse_record(const int4 q, const typename vrt::RecOf<T>::type *__restrict__ rf,
+                                               int64_t rec, int l0, int32_t nl, int64_t n, int32_t ray0,
+                                               const int64_t *__restrict__ dep_ptr,
+                                               const int32_t *__restrict__ dep_site,
+                                               const typename vrt::RecOf<T>::type *__restrict__ dep_rec,
+                                               const T *__restrict__ chi, const T *__restrict__ S,
+                                               const T *__restrict__ I, const T *__restrict__ gI,
+                                               const T *__restrict__ gJ, const double *__restrict__ ray_w,
+                                               const Rows &rows, T *__restrict__ Sbar, T *__restrict__ Cbar) {
   using L = ALane<T, V>;
   using VT = typename L::type;
-  constexpr int SPW = 64 / C;
-  const int lane = threadIdx.x & 63;
-  const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int64_t rec = wave * SPW + lane / C;
-  const int l0 = (lane % C) * V;
-  if (rec >= rec_count) return;
-  const int4 q = ri[rec_begin + rec];
   const int32_t k = q.x, k1 = q.y, k2 = q.z, ray = q.w >> 1;
   const int64_t nn = n * nl;
   const int64_t loc = (int64_t)(ray - ray0) * nn;  // this ray in the group scratch
   const T *Ir = I + loc;
-  const T *Ib_r = Ibar + loc;
   const int64_t bk = (int64_t)k * nl;
   const int64_t d0 = dep_ptr[(int64_t)ray * (n + 1) + k], d1 = dep_ptr[(int64_t)ray * (n + 1) + k + 1];
   const T wr = (T)ray_w[ray];
   const bool own = k1 >= 0;
   typename vrt::RecOf<T>::type f{};
-  if (own) f = rf[rec_begin + rec];
+  if (own) f = rf[rec];
   const bool two = k2 >= 0;
   const T w1 = two ? (T)f.w1 : T(1), w2 = T(1) - (T)f.w1;
   for (int l = l0; l < nl; l += C * V) {
@@ -96,7 +114,7 @@ __global__ __launch_bounds__(256) void reverse_kernel(
       const auto dr = dep_rec[t];  // w1 = weight of the line d reads from k, ds1 = its length
       const T wd = dr.w1, hd = T(0.5) * dr.ds1;
       const int64_t bd = (int64_t)d * nl;
-      const VT cd = L::load(chi + bd + l), sd = L::load(S + bd + l), ad_ = L::load(Ib_r + bd + l);
+      const VT cd = L::load(chi + bd + l), sd = L::load(S + bd + l), ad_ = rows.load(bd + l);
 #pragma unroll
       for (int e = 0; e < V; ++e) {
         T E, pu, p0, dp0;
@@ -127,9 +145,86 @@ __global__ __launch_bounds__(256) void reverse_kernel(
         }
       }
     }
-    L::store(Ibar + loc + bk + l, ib);
+    rows.store(bk + l, ib);
     L::store(Sbar + loc + bk + l, sb);
     L::store(Cbar + loc + bk + l, cb);
+  }
+}
+
+// Level-step reverse kernel: one launch per level step (in decreasing order),
+// C lanes per record, V wavelengths per lane. Scratch arrays (I, Ibar, Sbar,
+// Cbar) hold the rays [ray0, ray0 + group) of the current ray group.
+template <typename T, int C, int V>
+__global__ __launch_bounds__(256) void reverse_kernel(
+    const int4 *__restrict__ ri, const typename vrt::RecOf<T>::type *__restrict__ rf, int64_t rec_begin,
+    int64_t rec_count, int32_t nl, int64_t n, int32_t ray0, const int64_t *__restrict__ dep_ptr,
+    const int32_t *__restrict__ dep_site, const typename vrt::RecOf<T>::type *__restrict__ dep_rec,
+    const T *__restrict__ chi, const T *__restrict__ S, const T *__restrict__ I, const T *__restrict__ gI,
+    const T *__restrict__ gJ, const double *__restrict__ ray_w, T *Ibar, T *__restrict__ Sbar,
+    T *__restrict__ Cbar) {
+  constexpr int SPW = 64 / C;
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int64_t rec = wave * SPW + lane / C;
+  const int l0 = (lane % C) * V;
+  if (rec >= rec_count) return;
+  const int4 q = ri[rec_begin + rec];
+  const PlainRows<T, V> rows{Ibar + (int64_t)((q.w >> 1) - ray0) * n * nl};
+  reverse_record<T, C, V>(q, rf, rec_begin + rec, l0, nl, n, ray0, dep_ptr, dep_site, dep_rec, chi, S, I, gI, gJ,
+                          ray_w, rows, Sbar, Cbar);
+}
+
+// Persistent reverse kernel: every level step of a ray group in one launch, the
+// dataflow of the persistent forward sweep run backwards. Items are the
+// group's (level step, ray) segments in decreasing step order, cut into at
+// most 64/C records; item_cnt holds the record count + 256 x (ray - ray0).
+// Before updating site k a lane waits until every dependent of k (the sites
+// that read k in the forward sweep, all in later forward steps, so in earlier
+// items) carries the epoch stamp; after writing k's adjoint row the wave
+// stamps k. The adjoint rows pass between wavefronts with the device-scope
+// policy; Sbar and Cbar are read only after the launch.
+template <typename T, int C, int V>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void persistent_reverse_kernel(
+    const int4 *__restrict__ ri, const typename vrt::RecOf<T>::type *__restrict__ rf,
+    const int64_t *__restrict__ item_rec, const int32_t *__restrict__ item_cnt, int64_t n_items, int32_t nl,
+    int64_t n, int32_t ray0, const int64_t *__restrict__ dep_ptr, const int32_t *__restrict__ dep_site,
+    const typename vrt::RecOf<T>::type *__restrict__ dep_rec, const T *__restrict__ chi, const T *__restrict__ S,
+    const T *__restrict__ I, const T *__restrict__ gI, const T *__restrict__ gJ, const double *__restrict__ ray_w,
+    T *Ibar, T *__restrict__ Sbar, T *__restrict__ Cbar, int64_t flag_ld, int32_t *flags, int32_t *words,
+    int64_t spin_cap) {
+  const int32_t epoch = words[0];
+  int32_t *err = words + 1;
+  const int lane = threadIdx.x & 63;
+  int64_t W = 0;
+  const int64_t rank =
+      vrt_persist::register_wave(words, (int32_t)(gridDim.x * (blockDim.x >> 6)), spin_cap, lane, W);
+  if (rank < 0) return;
+  const int l0 = (lane % C) * V;
+  const int sub = lane / C;
+  const int64_t nn = n * nl;
+  for (int64_t item = rank; item < n_items; item += W) {
+    const int32_t cr = item_cnt[item];
+    const bool live = sub < (cr & 255);
+    const int64_t rec = item_rec[item] + sub;
+    int4 q = make_int4(0, -1, -1, 0);
+    if (live) q = ri[rec];
+    const int32_t k = q.x, ray = q.w >> 1;
+    int32_t *fr = flags + (int64_t)ray * flag_ld;
+    if (live) {
+      const int64_t d0 = dep_ptr[(int64_t)ray * (n + 1) + k], d1 = dep_ptr[(int64_t)ray * (n + 1) + k + 1];
+      bool ok = true;
+      for (int64_t t = d0; t < d1 && ok; ++t) ok = vrt_persist::wait_stamp(fr + dep_site[t], epoch, err, spin_cap);
+      // the item's ray's block of the group's adjoint rows (below 4 GiB: checked by the host)
+      const CoherentRows<T, V> rows{__builtin_amdgcn_make_buffer_rsrc(
+          Ibar + (int64_t)(cr >> 8) * nn, 0, (int)(uint32_t)(nn * (int64_t)sizeof(T)), vrt_persist::kRawBufferWord3)};
+      reverse_record<T, C, V>(q, rf, rec, l0, nl, n, ray0, dep_ptr, dep_site, dep_rec, chi, S, I, gI, gJ, ray_w,
+                              rows, Sbar, Cbar);
+    }
+    // every adjoint-row store of the wave has completed before any of its stamps
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    if (live && (lane % C) == 0) __hip_atomic_store(fr + k, epoch, __ATOMIC_RELAXED, vrt_persist::kXScope);
   }
 }
 
@@ -255,6 +350,51 @@ void launch_rv(hipStream_t s, const int4 *ri, const typename vrt::RecOf<T>::type
 
 inline unsigned nbk(int64_t work, int bs) { return (unsigned)((work + bs - 1) / bs); }
 
+template <typename T, int C, int V>
+void launch_prc(hipStream_t s, const vrt::PersistItems &it, int32_t max_blocks, const int4 *ri,
+                const typename vrt::RecOf<T>::type *rf, int32_t nl, int64_t n, int32_t ray0, const int64_t *dp,
+                const int32_t *ds_, const typename vrt::RecOf<T>::type *dr, const T *chi, const T *S, const T *I,
+                const T *gI, const T *gJ, const double *w, T *Ib, T *Sb, T *Cb, int64_t flag_ld, int32_t *flags,
+                int32_t *words, int64_t cap) {
+  if (it.spw != 64 / C) throw vrt::Error(VRT_E_STATE, "persistent item table built for another record width");
+  auto kern = persistent_reverse_kernel<T, C, V>;
+  int dev = 0, cus = 0, per_cu = 0;
+  VRT_HIP(hipGetDevice(&dev));
+  VRT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  VRT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0));
+  if (per_cu < 1) throw vrt::Error(VRT_E_HIP, "persistent reverse kernel cannot be resident");
+  // as for the forward persistent sweep: any count is correct
+  int64_t blocks = (int64_t)cus * per_cu;
+  if (blocks > (it.n_items + 3) / 4) blocks = (it.n_items + 3) / 4;
+  if (max_blocks > 0) blocks = max_blocks;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, s, ri, rf, it.rec.as<int64_t>(),
+                     it.cnt.as<int32_t>(), it.n_items, nl, n, ray0, dp, ds_, dr, chi, S, I, gI, gJ, w, Ib, Sb, Cb,
+                     flag_ld, flags, words, cap);
+  VRT_HIP(hipGetLastError());
+}
+
+template <typename T, int V>
+void launch_prv(hipStream_t s, const vrt::PersistItems &it, int32_t mb, const int4 *ri,
+                const typename vrt::RecOf<T>::type *rf, int32_t nl, int64_t n, int32_t ray0, const int64_t *dp,
+                const int32_t *ds_, const typename vrt::RecOf<T>::type *dr, const T *chi, const T *S, const T *I,
+                const T *gI, const T *gJ, const double *w, T *Ib, T *Sb, T *Cb, int64_t fl, int32_t *flags,
+                int32_t *words, int64_t cap) {
+#define VRT_PRC(CC)                                                                                                  \
+  launch_prc<T, CC, V>(s, it, mb, ri, rf, nl, n, ray0, dp, ds_, dr, chi, S, I, gI, gJ, w, Ib, Sb, Cb, fl, flags,    \
+                       words, cap)
+  switch (vrt::lanes_per_record(nl / V)) {
+    case 64: VRT_PRC(64); break;
+    case 32: VRT_PRC(32); break;
+    case 16: VRT_PRC(16); break;
+    case 8: VRT_PRC(8); break;
+    case 4: VRT_PRC(4); break;
+    case 2: VRT_PRC(2); break;
+    default: VRT_PRC(1); break;
+  }
+#undef VRT_PRC
+}
+
 }  // namespace
 
 namespace vrt {
@@ -274,6 +414,32 @@ void launch_reverse(hipStream_t s, const int4 *ri, const typename RecOf<T>::type
     launch_rv<T, 1>(s, ri, rf, rec_begin, rec_count, nl, n, ray0, dep_ptr, dep_site, dep_rec, chi, S, I, gI, gJ,
                     ray_w, Ibar, Sbar, Cbar);
   VRT_HIP(hipGetLastError());
+}
+
+int32_t reverse_records_per_wave(int32_t nl, int elem_bytes, bool aligned) {
+  const int VW = 16 / elem_bytes;
+  const int V = (aligned && nl % VW == 0) ? VW : 1;
+  return 64 / lanes_per_record(nl / V);
+}
+
+template <typename T>
+void launch_persistent_reverse(hipStream_t s, const PersistItems &items, int32_t max_blocks, const int4 *ri,
+                               const typename RecOf<T>::type *rf, int32_t nl, int64_t n, int32_t ray0,
+                               const int64_t *dep_ptr, const int32_t *dep_site, const typename RecOf<T>::type *dep_rec,
+                               const T *chi, const T *S, const T *I, const T *gI, const T *gJ, const double *ray_w,
+                               T *Ibar, T *Sbar, T *Cbar, int64_t flag_ld, int32_t *flags, int32_t *words,
+                               int64_t spin_cap) {
+  if (items.n_items <= 0) return;
+  if (n * (int64_t)nl * (int64_t)sizeof(T) >= (int64_t(1) << 32))
+    throw Error(VRT_E_ARG, "persistent reverse sweep: one ray's adjoint rows exceed 4 GiB");
+  constexpr int VW = 16 / sizeof(T);
+  const bool aligned = al16(chi) && al16(S) && al16(I) && al16(Ibar) && al16(Sbar) && al16(Cbar);
+  if (aligned && nl % VW == 0)
+    launch_prv<T, VW>(s, items, max_blocks, ri, rf, nl, n, ray0, dep_ptr, dep_site, dep_rec, chi, S, I, gI, gJ, ray_w,
+                      Ibar, Sbar, Cbar, flag_ld, flags, words, spin_cap);
+  else
+    launch_prv<T, 1>(s, items, max_blocks, ri, rf, nl, n, ray0, dep_ptr, dep_site, dep_rec, chi, S, I, gI, gJ, ray_w,
+                     Ibar, Sbar, Cbar, flag_ld, flags, words, spin_cap);
 }
 
 template <typename T>
@@ -324,6 +490,10 @@ void launch_lte_vjp(hipStream_t s, int64_t n, int32_t nl, const double *lam, dou
                                   int64_t, int32_t, const int64_t *, const int32_t *, const RecOf<T>::type *,         \
                                   const T *, const T *, const T *, const T *, const T *, const double *, T *, T *,    \
                                   T *);                                                                               \
+  template void launch_persistent_reverse<T>(                                                                         \
+      hipStream_t, const PersistItems &, int32_t, const int4 *, const RecOf<T>::type *, int32_t, int64_t, int32_t,    \
+      const int64_t *, const int32_t *, const RecOf<T>::type *, const T *, const T *, const T *, const T *, const T *, \
+      const double *, T *, T *, T *, int64_t, int32_t *, int32_t *, int64_t);                                          \
   template void launch_reverse_reduce<T>(hipStream_t, int64_t, int32_t, int32_t, int32_t, const double *,             \
                                          const uint8_t *, const T *, const T *, const T *, double *, double *,        \
                                          double *, double *);                                                         \

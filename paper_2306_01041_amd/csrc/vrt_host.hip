@@ -738,6 +738,37 @@ void build_dependents(vrt_grid g) {
   g->deps_built = true;
 }
 
+// Wave items of the persistent reverse sweep of rays [r0, r0 + gc) for `spw`
+// records per wave: the (level step, ray) segments in decreasing step order,
+// each cut separately; cnt holds the record count + 256 x (ray - r0).
+const vrt::PersistItems &reverse_items(vrt_grid g, int32_t spw, int32_t r0, int32_t gc) {
+  const int64_t key = ((int64_t)spw << 40) | ((int64_t)r0 << 20) | (int64_t)gc;
+  auto it = g->reverse_items.find(key);
+  if (it != g->reverse_items.end()) return *it->second;
+  const int32_t R = g->R;
+  std::vector<int64_t> rec;
+  std::vector<int32_t> cnt;
+  for (int32_t st = g->n_steps - 1; st >= 0; --st) {
+    for (int32_t ray = r0; ray < r0 + gc; ++ray) {
+      const int64_t b = g->seg_off[(size_t)st * R + ray], e = b + g->seg_cnt[(size_t)st * R + ray];
+      for (int64_t r = b; r < e; r += spw) {
+        rec.push_back(r);
+        cnt.push_back((int32_t)std::min<int64_t>(spw, e - r) + 256 * (ray - r0));
+      }
+    }
+  }
+  std::unique_ptr<vrt::PersistItems> p(new vrt::PersistItems);
+  p->spw = spw;
+  p->n_items = (int64_t)rec.size();
+  upload(p->rec, rec.data(), rec.size(), g->ctx->stream);
+  upload(p->cnt, cnt.data(), cnt.size(), g->ctx->stream);
+  ensure_flags(g);
+  VRT_HIP(hipStreamSynchronize(g->ctx->stream));  // host tables are local
+  auto &ref = *p;
+  g->reverse_items.emplace(key, std::move(p));
+  return ref;
+}
+
 template <typename T> const typename vrt::RecOf<T>::type *dep_records(vrt_grid g);
 template <> const vrt::RecF32 *dep_records<float>(vrt_grid g) { return g->d_dep_rf32.as<vrt::RecF32>(); }
 template <> const vrt::RecF64 *dep_records<double>(vrt_grid g) { return g->d_dep_rf64.as<vrt::RecF64>(); }
@@ -787,11 +818,24 @@ void formal_solution_vjp(vrt_grid g, int32_t nl, const T *chi, const T *S, const
       }
       Ifw = Iw;
     }
-    for (int32_t st = g->n_steps - 1; st >= 0; --st) {
-      int64_t b, c;
-      seg(st, b, c);
-      vrt::launch_reverse<T>(s, ri, rf, b, c, nl, n, r0, g->d_dep_ptr.as<int64_t>(), g->d_dep_site.as<int32_t>(),
-                             dep_records<T>(g), chi, S, Ifw, gI, gJ, g->d_w.as<double>(), Ibar, Sbar, Cbar);
+    if (g->reverse_persistent) {
+      const bool aligned = vrt::al16(chi) && vrt::al16(S) && vrt::al16(Ifw) && vrt::al16(Ibar) &&
+                           vrt::al16(Sbar) && vrt::al16(Cbar);
+      const vrt::PersistItems &items =
+          reverse_items(g, vrt::reverse_records_per_wave(nl, sizeof(T), aligned), r0, gc);
+      int32_t *words = g->d_epoch.as<int32_t>();
+      vrt::launch_persist_begin(s, words);
+      vrt::launch_persistent_reverse<T>(s, items, g->persist_max_blocks, ri, rf, nl, n, r0,
+                                        g->d_dep_ptr.as<int64_t>(), g->d_dep_site.as<int32_t>(), dep_records<T>(g),
+                                        chi, S, Ifw, gI, gJ, g->d_w.as<double>(), Ibar, Sbar, Cbar, flag_ld(g),
+                                        g->d_flags.as<int32_t>(), words, g->spin_cap);
+    } else {
+      for (int32_t st = g->n_steps - 1; st >= 0; --st) {
+        int64_t b, c;
+        seg(st, b, c);
+        vrt::launch_reverse<T>(s, ri, rf, b, c, nl, n, r0, g->d_dep_ptr.as<int64_t>(), g->d_dep_site.as<int32_t>(),
+                               dep_records<T>(g), chi, S, Ifw, gI, gJ, g->d_w.as<double>(), Ibar, Sbar, Cbar);
+      }
     }
     vrt::launch_reverse_reduce<T>(s, n, nl, r0, gc, g->d_dirs.as<double>(), g->d_wall.as<uint8_t>(), Ibar, Sbar,
                                   Cbar, acc, acc + nn, acc + 2 * nn, acc + 3 * nn);
@@ -1272,6 +1316,7 @@ vrt_status vrt_grid_set_rays(vrt_grid g, int32_t n_rays, const double *dir, cons
     if (!(std::fabs(sum - 1.0) < 1e-12)) fail(VRT_E_ARG, "ray weights sum to %.17g, not 1", sum);
     g->drop_graphs();
     g->persist_items.clear();
+    g->reverse_items.clear();
     g->d_flags.release();
     g->d_epoch.release();
     g->deps_built = false;
@@ -1320,6 +1365,9 @@ vrt_status vrt_grid_tune(vrt_grid g, int32_t knob, int64_t value) {
       if (value == 1 && g->kind != 0) fail(VRT_E_ARG, "the quadratic segment needs a Voronoi grid");
       g->segment = (int)value;
       if (g->segment && g->R > 0 && !g->down_built) build_downwind(g);
+    } else if (knob == VRT_TUNE_REVERSE_PERSISTENT) {
+      if (value != 0 && value != 1) fail(VRT_E_ARG, "reverse persistent must be 0 or 1");
+      g->reverse_persistent = (int)value;
     } else if (knob == VRT_TUNE_LANE_BYTES) {
       if (value != 16 && value != 32) fail(VRT_E_ARG, "lane bytes must be 16 or 32");
       g->lane_bytes = (int)value;

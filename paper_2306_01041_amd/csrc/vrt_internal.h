@@ -186,6 +186,8 @@ struct vrt_grid_s {
   int ray_groups = 1;    // the rays are swept in this many consecutive passes
   int interleave = 0;    // 1: step-wide sweeps read a copy of the records ordered by position across rays
   int segment = 0;       // 0: linear source along a line, 1: quadratic Bezier (needs the downwind lines)
+  int reverse_persistent = 0;  // 1: the reverse sweep of a ray group runs as one persistent launch
+  std::map<int64_t, std::unique_ptr<vrt::PersistItems>> reverse_items;  // keyed by (spw, first ray, group)
   vrt::DevBuf d_q1, d_q2, d_qw1, d_qd1, d_qd2;  // downwind lines [R][n]: the selection of the opposite rays
   bool down_built = false;
   vrt::DevBuf d_ri_x, d_rf32_x, d_rf64_x;
@@ -324,6 +326,17 @@ void launch_reverse(hipStream_t s, const int4 *ri, const typename RecOf<T>::type
                     int64_t rec_count, int32_t nl, int64_t n, int32_t ray0, const int64_t *dep_ptr,
                     const int32_t *dep_site, const typename RecOf<T>::type *dep_rec, const T *chi, const T *S,
                     const T *I, const T *gI, const T *gJ, const double *ray_w, T *Ibar, T *Sbar, T *Cbar);
+// Every level step of a ray group's reverse sweep in one launch; items from
+// the group's (step, ray) segments in decreasing step order, item_cnt =
+// count + 256 x (ray - ray0); stamps and words as for the persistent sweep.
+int32_t reverse_records_per_wave(int32_t nl, int elem_bytes, bool aligned);
+template <typename T>
+void launch_persistent_reverse(hipStream_t s, const PersistItems &items, int32_t max_blocks, const int4 *ri,
+                               const typename RecOf<T>::type *rf, int32_t nl, int64_t n, int32_t ray0,
+                               const int64_t *dep_ptr, const int32_t *dep_site, const typename RecOf<T>::type *dep_rec,
+                               const T *chi, const T *S, const T *I, const T *gI, const T *gJ, const double *ray_w,
+                               T *Ibar, T *Sbar, T *Cbar, int64_t flag_ld, int32_t *flags, int32_t *words,
+                               int64_t spin_cap);
 template <typename T>
 void launch_reverse_reduce(hipStream_t s, int64_t n, int32_t nl, int32_t ray0, int32_t group, const double *dirs,
                            const uint8_t *wall, const T *Ibar, const T *Sbar, const T *Cbar, double *acc_chi,

@@ -105,6 +105,53 @@ def test_ray_groups_and_recompute_agree(v, ctx, case):
     G.close()
 
 
+@pytest.mark.parametrize("nl", [8, 64])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_persistent_reverse_matches_level_steps(v, ctx, case, nl, prec):
+    """The persistent reverse sweep performs the level-step reverse sweep's
+    arithmetic per record, so its adjoints are bit-identical, for all rays at
+    once and for ray groups, with kept and recomputed forward intensities;
+    a spin bound of zero polls reports a timeout and the next call is correct."""
+    flush(f"persistent reverse nl={nl} {prec}")
+    atm, g, dirs, w, sel = case
+    lam = np.linspace(500e-9, 700e-9, nl)
+    chi, S = oracle.lte(lam, atm.kappa0, atm.T, atm.rho)
+    chi = chi * np.random.default_rng(nl + 7).uniform(0.5, 2.0, (1, nl))
+    rng = np.random.default_rng(3)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    gI = to_dev(rng.standard_normal((len(dirs), g.n, nl)), dt)
+    gJ = to_dev(rng.standard_normal((g.n, nl)), dt)
+    G = v.Grid.from_synth(ctx, g)
+    G.set_rays(dirs, w)
+    c_d, S_d = to_dev(chi, dt), to_dev(S, dt)
+    J = torch.empty_like(c_d)
+    I = torch.empty((len(dirs), g.n, nl), dtype=dt, device="cuda:0")
+    v.formal_solution(G, c_d, S_d, J, I_rays=I)
+    for group, keep in ((0, True), (5, False), (24, False)):
+        ref = [t.cpu().numpy() for t in v.formal_solution_vjp(G, c_d, S_d, dL_dI=gI, dL_dJ=gJ,
+                                                               I_rays=I if keep else None, ray_group=group)]
+        G.tune(v.VRT_TUNE_REVERSE_PERSISTENT, 1)
+        got = v.formal_solution_vjp(G, c_d, S_d, dL_dI=gI, dL_dJ=gJ, I_rays=I if keep else None, ray_group=group)
+        G.device_status()
+        G.tune(v.VRT_TUNE_REVERSE_PERSISTENT, 0)
+        for a, b in zip(got, ref):
+            assert np.array_equal(a.cpu().numpy(), b), (group, keep)
+    G.tune(v.VRT_TUNE_REVERSE_PERSISTENT, 1)
+    G.tune(v.VRT_TUNE_SPIN_CAP, 0)
+    v.formal_solution_vjp(G, c_d, S_d, dL_dI=gI, I_rays=I)
+    with pytest.raises(v.VrtError) as e:
+        G.device_status()
+    assert e.value.status == v.VRT_E_TIMEOUT
+    G.tune(v.VRT_TUNE_SPIN_CAP, 1 << 22)
+    got = v.formal_solution_vjp(G, c_d, S_d, dL_dI=gI, dL_dJ=gJ, I_rays=I)
+    G.device_status()
+    G.tune(v.VRT_TUNE_REVERSE_PERSISTENT, 0)
+    ref = v.formal_solution_vjp(G, c_d, S_d, dL_dI=gI, dL_dJ=gJ, I_rays=I)
+    for a, b in zip(got, ref):
+        assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+    G.close()
+
+
 def test_lte_chain_rule_matches_oracle(v, ctx, case):
     flush("lte vjp")
     atm, g, dirs, w, sel = case

@@ -90,7 +90,8 @@ __global__ __launch_bounds__(256) void jbar_kernel(int64_t n, int32_t nl, int32_
 #pragma unroll
       for (int e = 0; e < V; ++e) acc[e] = 0.0;
       for (int32_t r = 0; r < R; ++r) {
-        const VT x = *reinterpret_cast<const VT *>(I + (int64_t)r * nn + site * ld + l);
+        // each intensity is read once: non-temporal (streaming) loads
+        const VT x = __builtin_nontemporal_load(reinterpret_cast<const VT *>(I + (int64_t)r * nn + site * ld + l));
         const double wr = w[r];
 #pragma unroll
         for (int e = 0; e < V; ++e) acc[e] += wr * (double)x[e];

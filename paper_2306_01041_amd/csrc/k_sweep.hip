@@ -174,7 +174,8 @@ __global__ __launch_bounds__(256) void jreduce_kernel(const T *__restrict__ I, i
 #pragma unroll
     for (int k = 0; k < V; ++k) acc[k] = 0.0;
     for (int32_t r = 0; r < R; ++r) {
-      const VT x = L::load(I + (int64_t)r * nn + t * V);
+      // each intensity is read once: non-temporal (streaming) loads
+      const VT x = __builtin_nontemporal_load(reinterpret_cast<const VT *>(I + (int64_t)r * nn + t * V));
       const double wr = w[r];
 #pragma unroll
       for (int k = 0; k < V; ++k) acc[k] += wr * (double)L::get(x, k);

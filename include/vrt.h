@@ -215,10 +215,9 @@ vrt_status vrt_grid_set_rays(vrt_grid grid, int32_t n_rays, const double *dir, c
  *                           site's downwind lines (the Eq. 5-6 selection for the
  *                           opposite direction), kept between S_k and S_i.
  *                           Formal solutions and plain (accel = 0) two-level
- *                           iterations with PLAIN, BATCHED or GRAPH execution;
- *                           the persistent sweep, the reverse sweep, the
- *                           accelerated iteration and the autotuner return
- *                           VRT_E_ARG with it. */
+ *                           iterations in every execution mode; the reverse
+ *                           sweep, the accelerated iteration and the autotuner
+ *                           return VRT_E_ARG with it. */
 #define VRT_TUNE_SEGMENT 11
 /*   VRT_TUNE_REVERSE_PERSISTENT 1 = the reverse sweep of vrt_formal_solution_vjp
  *                           runs each ray group as one persistent launch (the

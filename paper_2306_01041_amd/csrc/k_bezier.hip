@@ -22,6 +22,7 @@
 // wavelengths with 16-byte vectors when the rows allow, workgroups dealt to
 // the dies in contiguous chunks of records.
 
+#include "persist.h"
 #include "segment.h"
 #include "vrt_internal.h"
 
@@ -135,25 +136,40 @@ __device__ __forceinline__ int64_t die_chunked_block(int32_t k) {
   return x * per + (x < rem ? x : rem) + j;
 }
 
-// kLanes lanes per record, V consecutive wavelengths per lane (nl a multiple of V)
-template <typename T, int V>
-__global__ __launch_bounds__(256) void bezier_sweep_kernel(
-    const int4 *__restrict__ ri, const typename vrt::RecOf<T>::type *__restrict__ rf, int64_t rec_begin,
-    int64_t rec_count, int32_t nl, int64_t n, const int32_t *__restrict__ q1, const int32_t *__restrict__ q2,
-    const double *__restrict__ qw1, const double *__restrict__ qd1, const double *__restrict__ qd2,
-    const T *__restrict__ chi, const T *__restrict__ S, const T *__restrict__ Ibot, const T *__restrict__ Itop,
-    T *I, int32_t xcd_chunks) {
+// Intensity rows of one ray, addressed by element index within the ray's
+// block: plain accesses for the level-step kernel (the kernel boundary orders
+// them), device-scope buffer accesses for the persistent kernel
+template <typename T, int V> struct PlainRows {
+  T *base;
+  __device__ __forceinline__ typename BLane<T, V>::type load(int64_t e) const { return BLane<T, V>::load(base + e); }
+  __device__ __forceinline__ void store(int64_t e, const typename BLane<T, V>::type &v) const {
+    BLane<T, V>::store(base + e, v);
+  }
+};
+template <typename T, int V> struct CoherentRows {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ typename BLane<T, V>::type load(int64_t e) const {
+    return vrt_persist::row_load<typename BLane<T, V>::type>(r, (uint32_t)(e * (int64_t)sizeof(T)));
+  }
+  __device__ __forceinline__ void store(int64_t e, const typename BLane<T, V>::type &v) const {
+    vrt_persist::row_store<typename BLane<T, V>::type>(r, (uint32_t)(e * (int64_t)sizeof(T)), v);
+  }
+};
+
+// The quadratic-segment update of one record (site of one ray) for the
+// wavelengths l0, l0 + kLanes V, ...; rows: the record's ray's intensities.
+template <typename T, int V, typename Rows>
+__device__ __forceinline__ void bezier_record(const int4 q, const typename vrt::RecOf<T>::type *__restrict__ rf,
+                                              int64_t rec, int l0, int32_t nl, int64_t n,
+                                              const int32_t *__restrict__ q1, const int32_t *__restrict__ q2,
+                                              const double *__restrict__ qw1, const double *__restrict__ qd1,
+                                              const double *__restrict__ qd2, const T *__restrict__ chi,
+                                              const T *__restrict__ S, const T *__restrict__ Ibot,
+                                              const T *__restrict__ Itop, const Rows &rows) {
   using L = BLane<T, V>;
   using VT = typename L::type;
-  const int64_t t = die_chunked_block(xcd_chunks) * blockDim.x + threadIdx.x;
-  const int64_t r = t / kLanes;
-  if (r >= rec_count) return;
-  const int l0 = (int)(t % kLanes) * V;
-  const int64_t rec = rec_begin + r;
-  const int4 q = ri[rec];
   const int32_t site = q.x, k1 = q.y, k2 = q.z, ray = q.w >> 1;
   const bool up = (q.w & 1) != 0;
-  T *Iray = I + (int64_t)ray * n * nl;
   const int64_t bi = (int64_t)site * nl;
   if (k1 < 0) {
     for (int l = l0; l < nl; l += kLanes * V) {
@@ -161,7 +177,7 @@ __global__ __launch_bounds__(256) void bezier_sweep_kernel(
       if (up) v = L::load(Ibot + bi + l);
       else if (Itop) v = L::load(Itop + bi + l);
       else v = VT(T(0));
-      L::store(Iray + bi + l, v);
+      rows.store(bi + l, v);
     }
     return;
   }
@@ -178,12 +194,12 @@ __global__ __launch_bounds__(256) void bezier_sweep_kernel(
   const int64_t bd1 = (int64_t)(d1 >= 0 ? d1 : site) * nl, bd2 = (int64_t)(two_d ? d2 : site) * nl;
   for (int l = l0; l < nl; l += kLanes * V) {
     const VT ci = L::load(chi + bi + l), si = L::load(S + bi + l);
-    const VT ck1 = L::load(chi + bk1 + l), sk1 = L::load(S + bk1 + l), ik1 = L::load(Iray + bk1 + l);
+    const VT ck1 = L::load(chi + bk1 + l), sk1 = L::load(S + bk1 + l), ik1 = rows.load(bk1 + l);
     VT ck2 = ck1, sk2 = sk1, ik2 = ik1;
     if (two) {
       ck2 = L::load(chi + bk2 + l);
       sk2 = L::load(S + bk2 + l);
-      ik2 = L::load(Iray + bk2 + l);
+      ik2 = rows.load(bk2 + l);
     }
     VT cq1 = ci, sq1 = si, cq2 = ci, sq2 = si;
     if (d1 >= 0) {
@@ -233,7 +249,76 @@ __global__ __launch_bounds__(256) void bezier_sweep_kernel(
       }
       set_el<T, V>(out, e, Iv);
     }
-    L::store(Iray + bi + l, out);
+    rows.store(bi + l, out);
+  }
+}
+
+
+// kLanes lanes per record, V consecutive wavelengths per lane (nl a multiple of V)
+template <typename T, int V>
+__global__ __launch_bounds__(256) void bezier_sweep_kernel(
+    const int4 *__restrict__ ri, const typename vrt::RecOf<T>::type *__restrict__ rf, int64_t rec_begin,
+    int64_t rec_count, int32_t nl, int64_t n, const int32_t *__restrict__ q1, const int32_t *__restrict__ q2,
+    const double *__restrict__ qw1, const double *__restrict__ qd1, const double *__restrict__ qd2,
+    const T *__restrict__ chi, const T *__restrict__ S, const T *__restrict__ Ibot, const T *__restrict__ Itop,
+    T *I, int32_t xcd_chunks) {
+  const int64_t t = die_chunked_block(xcd_chunks) * blockDim.x + threadIdx.x;
+  const int64_t r = t / kLanes;
+  if (r >= rec_count) return;
+  const int l0 = (int)(t % kLanes) * V;
+  const int64_t rec = rec_begin + r;
+  const int4 q = ri[rec];
+  const PlainRows<T, V> rows{I + (int64_t)(q.w >> 1) * n * nl};
+  bezier_record<T, V>(q, rf, rec, l0, nl, n, q1, q2, qw1, qd1, qd2, chi, S, Ibot, Itop, rows);
+}
+
+// Persistent quadratic-segment sweep: every ray and level in one launch, with
+// the dataflow, registration and device-scope row accesses of the persistent
+// linear sweep. Items: (level step, ray) segments in step order, at most
+// 64 / kLanes records each; item_cnt = record count + 256 x ray. Only the
+// upwind rows pass between wavefronts (the downwind lines read S and chi).
+template <typename T, int V>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void persistent_bezier_kernel(
+    const int4 *__restrict__ ri, const typename vrt::RecOf<T>::type *__restrict__ rf,
+    const int64_t *__restrict__ item_rec, const int32_t *__restrict__ item_cnt, int64_t n_items, int32_t nl,
+    int64_t n, const int32_t *__restrict__ q1, const int32_t *__restrict__ q2, const double *__restrict__ qw1,
+    const double *__restrict__ qd1, const double *__restrict__ qd2, const T *__restrict__ chi,
+    const T *__restrict__ S, const T *__restrict__ Ibot, const T *__restrict__ Itop, T *I, int64_t flag_ld,
+    int32_t *flags, int32_t *words, int64_t spin_cap) {
+  const int32_t epoch = words[0];
+  int32_t *err = words + 1;
+  const int lane = threadIdx.x & 63;
+  int64_t W = 0;
+  const int64_t rank =
+      vrt_persist::register_wave(words, (int32_t)(gridDim.x * (blockDim.x >> 6)), spin_cap, lane, W);
+  if (rank < 0) return;
+  const int l0 = (lane % kLanes) * V;
+  const int sub = lane / kLanes;
+  for (int64_t item = rank; item < n_items; item += W) {
+    const int32_t cr = item_cnt[item];
+    const bool live = sub < (cr & 255);
+    const int64_t rec = item_rec[item] + sub;
+    int4 q = make_int4(0, -1, -1, 0);
+    if (live) q = ri[rec];
+    const int32_t site = q.x, k1 = q.y, k2 = q.z, ray = q.w >> 1;
+    int32_t *fr = flags + (int64_t)ray * flag_ld;
+    if (live && k1 >= 0) {
+      if (vrt_persist::wait_stamp(fr + k1, epoch, err, spin_cap) && k2 >= 0)
+        vrt_persist::wait_stamp(fr + k2, epoch, err, spin_cap);
+    }
+    if (live) {
+      // the item's ray's block of n * nl values (below 4 GiB: checked by the host)
+      const CoherentRows<T, V> rows{__builtin_amdgcn_make_buffer_rsrc(
+          I + (int64_t)(cr >> 8) * n * nl, 0, (int)(uint32_t)(n * nl * (int64_t)sizeof(T)),
+          vrt_persist::kRawBufferWord3)};
+      bezier_record<T, V>(q, rf, rec, l0, nl, n, q1, q2, qw1, qd1, qd2, chi, S, Ibot, Itop, rows);
+    }
+    // every row store of the wave has completed before any of its stamps
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    if (live && (lane % kLanes) == 0)
+      __hip_atomic_store(fr + site, epoch, __ATOMIC_RELAXED, vrt_persist::kXScope);
   }
 }
 
@@ -258,6 +343,52 @@ void launch_bezier_sweep(hipStream_t s, const int4 *ri, const typename RecOf<T>:
                                                      S, Ibot, Itop, I, xcd_chunks);
   VRT_HIP(hipGetLastError());
 }
+
+int32_t bezier_records_per_wave() { return 64 / kLanes; }
+
+template <typename T>
+void launch_persistent_bezier(hipStream_t s, const PersistItems &items, int32_t max_blocks, const int4 *ri,
+                              const typename RecOf<T>::type *rf, int32_t nl, int64_t n, const int32_t *q1,
+                              const int32_t *q2, const double *qw1, const double *qd1, const double *qd2,
+                              const T *chi, const T *S, const T *Ibot, const T *Itop, T *I, int64_t flag_ld,
+                              int32_t *flags, int32_t *words, int64_t spin_cap) {
+  if (items.n_items <= 0) return;
+  if (items.spw != 64 / kLanes) throw Error(VRT_E_STATE, "persistent item table built for another record width");
+  if (n * (int64_t)nl * (int64_t)sizeof(T) >= (int64_t(1) << 32))
+    throw Error(VRT_E_ARG, "persistent sweep: one ray's intensities exceed 4 GiB; use the level-step modes");
+  constexpr int VW = 16 / (int)sizeof(T);
+  auto al = [](const void *p) { return p == nullptr || (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  const bool vec = nl % VW == 0 && al(chi) && al(S) && al(Ibot) && al(Itop) && al(I);
+  auto launch = [&](auto kern) {
+    int dev = 0, cus = 0, per_cu = 0;
+    VRT_HIP(hipGetDevice(&dev));
+    VRT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    VRT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0));
+    if (per_cu < 1) throw Error(VRT_E_HIP, "persistent Bezier kernel cannot be resident");
+    // any count is correct (registration gives work only to running wavefronts)
+    int64_t blocks = (int64_t)cus * per_cu;
+    if (blocks > (items.n_items + 3) / 4) blocks = (items.n_items + 3) / 4;
+    if (max_blocks > 0) blocks = max_blocks;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, s, ri, rf, items.rec.as<int64_t>(),
+                       items.cnt.as<int32_t>(), items.n_items, nl, n, q1, q2, qw1, qd1, qd2, chi, S, Ibot, Itop, I,
+                       flag_ld, flags, words, spin_cap);
+    VRT_HIP(hipGetLastError());
+  };
+  if (vec) launch(persistent_bezier_kernel<T, VW>);
+  else launch(persistent_bezier_kernel<T, 1>);
+}
+
+template void launch_persistent_bezier<float>(hipStream_t, const PersistItems &, int32_t, const int4 *,
+                                              const RecF32 *, int32_t, int64_t, const int32_t *, const int32_t *,
+                                              const double *, const double *, const double *, const float *,
+                                              const float *, const float *, const float *, float *, int64_t,
+                                              int32_t *, int32_t *, int64_t);
+template void launch_persistent_bezier<double>(hipStream_t, const PersistItems &, int32_t, const int4 *,
+                                               const RecF64 *, int32_t, int64_t, const int32_t *, const int32_t *,
+                                               const double *, const double *, const double *, const double *,
+                                               const double *, const double *, const double *, double *, int64_t,
+                                               int32_t *, int32_t *, int64_t);
 
 template void launch_bezier_sweep<float>(hipStream_t, const int4 *, const RecF32 *, int64_t, int64_t, int32_t,
                                          int64_t, const int32_t *, const int32_t *, const double *, const double *,

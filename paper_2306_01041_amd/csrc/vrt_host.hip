@@ -547,7 +547,17 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
                                     It, I, g->xcd_chunks);
       });
     };
-    if (ex == VRT_EXEC_PLAIN) {
+    if (ex == VRT_EXEC_PERSISTENT) {
+      const vrt::PersistItems &items = persistent_items(g, vrt::bezier_records_per_wave());
+      int32_t *words = g->d_epoch.as<int32_t>();
+      vrt::launch_persist_begin(s, words);
+      timed_launch(ctx, s, tm, 0, g->n_rec * nl, [&] {
+        vrt::launch_persistent_bezier<T>(s, items, g->persist_max_blocks, ri, rf, nl, n, g->d_q1.as<int32_t>(),
+                                         g->d_q2.as<int32_t>(), g->d_qw1.as<double>(), g->d_qd1.as<double>(),
+                                         g->d_qd2.as<double>(), chi, S, Ib, It, I, flag_ld(g),
+                                         g->d_flags.as<int32_t>(), words, g->spin_cap);
+      });
+    } else if (ex == VRT_EXEC_PLAIN) {
       for (int32_t r = 0; r < R; ++r)
         for (int32_t st = 0; st < g->n_levels[(size_t)r]; ++st)
           sweep(ri, rf, g->seg_off[(size_t)st * R + r], g->seg_cnt[(size_t)st * R + r]);
@@ -1556,8 +1566,6 @@ vrt_status vrt_formal_solution(vrt_grid g, vrt_prec prec, vrt_exec exec, int32_t
     if (n_lambda <= 0) fail(VRT_E_ARG, "n_lambda must be positive");
     if (g->R == 0) fail(VRT_E_STATE, "rays not set");
     if (g->n > 0 && (!chi || !S || !J)) fail(VRT_E_ARG, "chi, S and J are required");
-    if (g->segment && exec == VRT_EXEC_PERSISTENT)
-      fail(VRT_E_ARG, "the quadratic segment runs plain, batched or graph sweeps");
     if (g->n == 0) return VRT_OK;
     if (prec == VRT_F32)
       formal_solution<float>(g, exec, n_lambda, chi, S, I_bottom, I_top, J, I_rays);
@@ -1585,8 +1593,7 @@ static vrt_status two_level_entry(vrt_grid g, vrt_prec prec, vrt_exec exec, int3
   if (g->n == 0 || max_iter == 0) return max_iter == 0 ? VRT_W_NOT_CONVERGED : VRT_OK;
   if (!phi || !chi_line || !chi_cont || !B || !S_line) fail(VRT_E_ARG, "null device array");
   if (accel != 0 && accel != 1) fail(VRT_E_ARG, "accel must be 0 or 1");
-  if (g->segment && (accel || exec == VRT_EXEC_PERSISTENT))
-    fail(VRT_E_ARG, "the quadratic segment runs the plain iteration with plain, batched or graph sweeps");
+  if (g->segment && accel) fail(VRT_E_ARG, "the quadratic segment runs the plain (unaccelerated) iteration");
   if (prec == VRT_F32)
     return two_level_solve<float>(g, exec, n_lambda, wlam, phi, chi_line, chi_cont, B, eps, max_iter, tol, accel,
                                   S_line, n_atm, atm_ptr, dS_hist, n_iter);

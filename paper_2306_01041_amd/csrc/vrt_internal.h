@@ -359,6 +359,16 @@ void launch_regular(hipStream_t s, int32_t step, int32_t ray_begin, int32_t ray_
 // ---- k_bezier.hip
 // the quadratic Bezier sweep of a contiguous record range; q1, q2, qw1, qd1,
 // qd2 [R][n] are the downwind lines (the upwind selection of the opposite rays)
+// Every ray and level of the quadratic-segment sweep in one launch (items of
+// bezier_records_per_wave() records; stamps and words as for the persistent
+// linear sweep).
+int32_t bezier_records_per_wave();
+template <typename T>
+void launch_persistent_bezier(hipStream_t s, const PersistItems &items, int32_t max_blocks, const int4 *ri,
+                              const typename RecOf<T>::type *rf, int32_t nl, int64_t n, const int32_t *q1,
+                              const int32_t *q2, const double *qw1, const double *qd1, const double *qd2,
+                              const T *chi, const T *S, const T *Ibot, const T *Itop, T *I, int64_t flag_ld,
+                              int32_t *flags, int32_t *words, int64_t spin_cap);
 template <typename T>
 void launch_bezier_sweep(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *rf, int64_t rec_begin,
                          int64_t rec_count, int32_t nl, int64_t n, const int32_t *q1, const int32_t *q2,

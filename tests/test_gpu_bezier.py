@@ -2,8 +2,9 @@
 points to) against the oracle's Bezier sweep: intensities and J in FP64 to
 1e-12, FP32 J to 1e-5 (single intensities 1e-4), for one, three and 64
 wavelengths with optical
-depths per segment from thin to thick; the same results from plain, batched
-and graph execution; the two-level iteration with the Bezier formal solution;
+depths per segment from thin to thick; the same results from plain, batched,
+graph and persistent execution; the two-level iteration with the Bezier formal
+solution (graph and persistent);
 and the combinations the library refuses."""
 
 import numpy as np
@@ -75,11 +76,11 @@ def test_bezier_matches_oracle(v, ctx, case, nl, prec):
     G = _bezier_grid(v, ctx, g, dirs, w, before=(nl != 3))
     c_d, S_d = to_dev(chi, dt), to_dev(S, dt)
     out = {}
-    for mode in ("GRAPH", "BATCHED", "PLAIN"):
+    for mode in ("GRAPH", "BATCHED", "PLAIN", "PERSISTENT"):
         J = torch.empty_like(c_d)
         I = torch.empty((len(dirs), g.n, nl), dtype=dt, device="cuda:0")
         v.formal_solution(G, c_d, S_d, J, I_rays=I, exec_mode=getattr(v, "VRT_EXEC_" + mode))
-        torch.cuda.synchronize()
+        G.device_status()
         out[mode] = (J.cpu().numpy(), I.cpu().numpy())
     # FP32: 1e-5 on J and 1e-4 on single intensities (small downward intensities
     # near the top carry their rounding relative to a small value), as for the
@@ -88,7 +89,7 @@ def test_bezier_matches_oracle(v, ctx, case, nl, prec):
     eJ, eI = relerr(out["GRAPH"][0], Jo), relerr(out["GRAPH"][1], Io)
     flush(f"  J {eJ:.2e}, I {eI:.2e}")
     assert eJ <= tol and eI <= (tol if prec == "f64" else 1e-4)
-    for mode in ("BATCHED", "PLAIN"):
+    for mode in ("BATCHED", "PLAIN", "PERSISTENT"):
         assert np.array_equal(out[mode][0], out["GRAPH"][0]) and np.array_equal(out[mode][1], out["GRAPH"][1])
     # back to the linear segment
     G.tune(v.VRT_TUNE_SEGMENT, 0)
@@ -121,8 +122,7 @@ def test_bezier_refusals(v, ctx, case):
     d = torch.float64
     c_d, S_d = to_dev(chi, d), to_dev(S, d)
     J = torch.empty_like(c_d)
-    for call in (lambda: v.formal_solution(G, c_d, S_d, J, exec_mode=v.VRT_EXEC_PERSISTENT),
-                 lambda: v.formal_solution_vjp(G, c_d, S_d, dL_dJ=torch.ones_like(c_d)),
+    for call in (lambda: v.formal_solution_vjp(G, c_d, S_d, dL_dJ=torch.ones_like(c_d)),
                  lambda: v.autotune(G, c_d, S_d, J, reps=1)):
         with pytest.raises(v.VrtError) as e:
             call()
@@ -153,14 +153,15 @@ def test_bezier_two_level_iteration_matches_oracle(v, ctx, prec):
                                         max_iter=its, tol=0.0, down=down)
     G = _bezier_grid(v, ctx, g, dirs, w)
     d = torch.float64
-    S = to_dev(B, d)
-    st, nit, hist = v.two_level_solve(G, line.wlam, to_dev(line.phi, d), to_dev(line.chi_line, d), to_dev(chi_c, d),
-                                      to_dev(B, d), eps, S, max_iter=its, tol=0.0,
-                                      sweep_dtype=d if prec == "f64" else torch.float32)
-    torch.cuda.synchronize()
-    e = relerr(S.cpu().numpy(), S_o)
-    flush(f"  S_line after {its} iterations: {e:.2e}")
-    assert nit == its and e <= (1e-12 if prec == "f64" else 1e-5)
+    for mode in (v.VRT_EXEC_GRAPH, v.VRT_EXEC_PERSISTENT):
+        S = to_dev(B, d)
+        st, nit, hist = v.two_level_solve(G, line.wlam, to_dev(line.phi, d), to_dev(line.chi_line, d),
+                                          to_dev(chi_c, d), to_dev(B, d), eps, S, max_iter=its, tol=0.0,
+                                          sweep_dtype=d if prec == "f64" else torch.float32, exec_mode=mode)
+        torch.cuda.synchronize()
+        e = relerr(S.cpu().numpy(), S_o)
+        flush(f"  S_line after {its} iterations (launch mode {mode}): {e:.2e}")
+        assert nit == its and e <= (1e-12 if prec == "f64" else 1e-5)
     with pytest.raises(v.VrtError) as err:
         v.two_level_solve(G, line.wlam, to_dev(line.phi, d), to_dev(line.chi_line, d), to_dev(chi_c, d),
                           to_dev(B, d), eps, to_dev(B, d), max_iter=2, accel=True)

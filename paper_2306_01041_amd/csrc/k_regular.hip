@@ -10,9 +10,12 @@
 //
 // One launch handles one plane step of a contiguous block of rays. The
 // bilinear weights are the same for every point of a plane, so lanes differ
-// only in wavelength and point; each wavefront covers 64/C points of one ray
-// with C lanes striding over wavelengths, V wavelengths (16 bytes) per lane
-// when the rows allow it.
+// only in wavelength and point; each wavefront covers 64/C consecutive points
+// of one grid row (x direction) of one ray, with C lanes striding over
+// wavelengths, V wavelengths (16 bytes) per lane when the rows allow it.
+// Because the ray, the row and the plane geometry are the same for the whole
+// wavefront, they are computed once per wavefront in scalar registers; only the
+// point's x index and the wavelength differ between lanes.
 
 #include "segment.h"
 #include "vrt_internal.h"
@@ -42,13 +45,17 @@ template <typename T, int V> __device__ __forceinline__ void set_el(typename RLa
 // The upwind point of every grid point of a plane is the point itself shifted
 // by -ds (mx, my); on a uniform grid the cell offset and the bilinear weights
 // are therefore the same for the whole plane: q / d = i + shift + t with an
-// integer shift and 0 <= t < 1.
+// integer shift and 0 <= t < 1. The shift is reduced modulo np in double
+// precision (exact for integers below 2^53); the two corrections catch the
+// quotient's rounding.
 __device__ __forceinline__ void plane_shift(double q_over_d, int32_t np, int32_t &shift, double &t) {
   const double fl = floor(q_over_d);
   t = q_over_d - fl;
-  int64_t a = (int64_t)fl % np;
-  if (a < 0) a += np;
-  shift = (int32_t)a;  // in [0, np)
+  const double dn = (double)np;
+  double m = fl - dn * floor(fl / dn);
+  if (m < 0.0) m += dn;
+  if (m >= dn) m -= dn;
+  shift = (int32_t)m;  // in [0, np)
 }
 
 // C lanes per point, V consecutive wavelengths per lane (nl a multiple of V).
@@ -62,14 +69,19 @@ __global__ __launch_bounds__(256) void regular_kernel(int32_t step, int32_t ray_
   using VT = typename L::type;
   constexpr int SPW = 64 / C;
   const int lane = threadIdx.x & 63;
-  const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int64_t plane = (int64_t)nx * ny;
-  const int64_t item = wave * SPW + lane / C;
+  // wavefront -> (ray, row j, first x of the wavefront), all wave-uniform
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  const uint32_t wpr = ((uint32_t)nx + SPW - 1) / SPW;
+  const uint32_t row = wave / wpr;
+  if (row >= (uint32_t)ray_count * (uint32_t)ny) return;
+  const uint32_t rr = row / (uint32_t)ny;
+  const int32_t j = (int32_t)(row - rr * (uint32_t)ny);
+  const int32_t i = (int32_t)((wave - row * wpr) * SPW) + lane / C;
+  if (i >= nx) return;
   const int l0 = (lane % C) * V;
-  if (item >= plane * ray_count) return;
-  const int32_t r = ray_begin + (int32_t)(item / plane);
-  const int64_t p = item - (int64_t)(r - ray_begin) * plane;
-  const int32_t i = (int32_t)(p % nx), j = (int32_t)(p / nx);
+  const int32_t r = ray_begin + (int32_t)rr;
+  const int64_t plane = (int64_t)nx * ny;
+  const int64_t p = (int64_t)j * nx + i;
   const double mx = dirs[3 * r + 0], my = dirs[3 * r + 1], mz = dirs[3 * r + 2];
   const bool up = mz > 0.0;
   const int32_t k = up ? step : nz - 1 - step;
@@ -129,9 +141,9 @@ void launch_rc(hipStream_t s, int32_t step, int32_t rb, int32_t rc, int32_t nx, 
                double dy, const double *z, const double *dirs, int32_t nl, const T *chi, const T *S, const T *Ibot,
                const T *Itop, T *I) {
   constexpr int SPW = 64 / C;
-  const int64_t items = (int64_t)nx * ny * rc;
-  const int64_t waves = (items + SPW - 1) / SPW;
+  const int64_t waves = (int64_t)rc * ny * ((nx + SPW - 1) / SPW);
   const int64_t blocks = (waves + 3) / 4;
+  if (waves >= (int64_t)1 << 31) throw vrt::Error(VRT_E_ARG, "regular grid too large for one plane launch");
   hipLaunchKernelGGL((regular_kernel<T, C, V>), dim3((unsigned)blocks), dim3(256), 0, s, step, rb, rc, nx, ny, nz, dx,
                      dy, z, dirs, nl, chi, S, Ibot, Itop, I);
 }

@@ -40,10 +40,14 @@ def _case(nx, ny, nz, nl, seed):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("mode", ["PLAIN", "GRAPH"])
-@pytest.mark.parametrize("nl", [1, 5, 70])
-def test_regular_matches_oracle(v, ctx, prec, mode, nl):
-    flush(f"regular prec={prec} mode={mode} nl={nl}")
-    nx, ny, nz = 16, 12, 21
+@pytest.mark.parametrize("nl", [1, 5, 8, 70])
+@pytest.mark.parametrize("shape", [(16, 12, 21), (13, 7, 9)])
+def test_regular_matches_oracle(v, ctx, prec, mode, nl, shape):
+    # (13, 7): rows that are not a multiple of the points a wavefront covers
+    # (1 to 64 depending on the row length), so the last wavefront of each row
+    # is partly idle
+    flush(f"regular prec={prec} mode={mode} nl={nl} shape={shape}")
+    nx, ny, nz = shape
     z, chi, S, Ib = _case(nx, ny, nz, nl, nl)
     dirs, w = synth.gauss_legendre_quadrature()
     Jo, Io = oracle.fs_regular(nx, ny, z, 0.11, 0.13, dirs, w, chi, S, Ib, keep_I=True)

@@ -146,6 +146,45 @@ def test_c0_lte_continuum_fp64(v, ctx, quad, grids):
     G.close()
 
 
+@pytest.mark.parametrize("nl", [1, 3, 4, 8, 17, 37, 64, 101, 104])
+def test_lte_and_emergent_gather_every_lane_width(v, ctx, quad, grids, nl):
+    """The LTE source kernel gives each site a group of 1 to 64 lanes with 1 or
+    16 bytes of wavelengths per lane, depending on the wavelength count: the opacity and
+    the Planck source against the FP64 oracle in both precisions, and the
+    gathered rows equal to the intensities they copy, read from the caller's
+    rows and from the library's own (padded) rows."""
+    flush(f"lte + emergent gather nl={nl}")
+    atm, g = grids[1000]
+    dirs, w = quad
+    G = _gpu_grid(v, ctx, g, dirs, w)
+    lam = wavelengths(nl)
+    chi_o, S_o = oracle.lte(lam, atm.kappa0, atm.T, atm.rho)
+    T, rho = to_dev(atm.T, torch.float64), to_dev(atm.rho, torch.float64)
+    for d, tol in ((torch.float64, 1e-14), (torch.float32, 1e-7)):
+        chi = torch.empty((g.n, nl), dtype=d, device="cuda:0")
+        S = torch.empty_like(chi)
+        v.lte_continuum(G, lam, atm.kappa0, T, rho, chi, S)
+        torch.cuda.synchronize()
+        assert relerr(chi.cpu().numpy(), chi_o) <= tol
+        assert relerr(S.cpu().numpy(), S_o) <= tol
+    f = torch.float32
+    J = torch.empty_like(chi)
+    I = torch.empty((len(dirs), g.n, nl), dtype=f, device="cuda:0")
+    off, sites = G.emergent_index()
+    v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_GRAPH)
+    em_lib = torch.empty((int(off[-1]), nl), dtype=f, device="cuda:0")
+    v.emergent_gather(G, em_lib)
+    v.formal_solution(G, chi, S, J, I_rays=I, exec_mode=v.VRT_EXEC_GRAPH)
+    em = torch.empty_like(em_lib)
+    v.emergent_gather(G, em, I_rays=I)
+    torch.cuda.synchronize()
+    Ih, emh = I.cpu().numpy(), em.cpu().numpy()
+    for r in range(len(dirs)):
+        assert np.array_equal(emh[off[r]:off[r + 1]], Ih[r, sites[off[r]:off[r + 1]]])
+    assert torch.equal(em, em_lib)
+    G.close()
+
+
 @pytest.mark.parametrize("nl", [1, 64])
 def test_fp32_batched_matches_fp64_oracle(v, ctx, quad, grids, nl):
     flush(f"fp32 vs oracle nl={nl}")

@@ -188,14 +188,44 @@ __global__ __launch_bounds__(256) void jreduce_kernel(const T *__restrict__ I, i
 }
 
 // I rows have ld >= nl entries; out rows have nl.
-template <typename T>
-__global__ void emergent_kernel(int64_t total, int32_t nl, int32_t ld, int64_t n, const int32_t *__restrict__ em_ray,
-                                const int32_t *__restrict__ em_site, const T *__restrict__ I, T *__restrict__ out) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= total * nl) return;
-  const int64_t e = t / nl;
-  const int32_t l = (int32_t)(t - e * nl);
-  out[t] = I[((int64_t)em_ray[e] * n + em_site[e]) * ld + l];
+// C lanes per emergent row (a power of two), 64/C rows per wavefront, V
+// consecutive wavelengths (16 bytes) per lane when the rows allow it.
+template <typename T, int C, int V>
+__global__ __launch_bounds__(256) void emergent_kernel(int64_t total, int32_t nl, int32_t ld, int64_t n,
+                                                       const int32_t *__restrict__ em_ray,
+                                                       const int32_t *__restrict__ em_site, const T *__restrict__ I,
+                                                       T *__restrict__ out) {
+  using L = Lane<T, V>;
+  constexpr int SPW = 64 / C;
+  const int lane = threadIdx.x & 63;
+  const int64_t e = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * SPW + lane / C;
+  if (e >= total) return;
+  const T *src = I + ((int64_t)em_ray[e] * n + em_site[e]) * ld;
+  T *dst = out + e * nl;
+  for (int32_t l = (lane % C) * V; l < nl; l += C * V) L::store(dst + l, L::load(src + l));
+}
+
+template <typename T, int C, int V>
+void launch_ec(hipStream_t s, int64_t total, int32_t nl, int32_t ld, int64_t n, const int32_t *em_ray,
+               const int32_t *em_site, const T *I, T *out) {
+  constexpr int SPW = 64 / C;
+  const int64_t blocks = (total + 4 * SPW - 1) / (4 * SPW);
+  hipLaunchKernelGGL((emergent_kernel<T, C, V>), dim3((unsigned)blocks), dim3(256), 0, s, total, nl, ld, n, em_ray,
+                     em_site, I, out);
+}
+
+template <typename T, int V>
+void launch_ev(hipStream_t s, int64_t total, int32_t nl, int32_t ld, int64_t n, const int32_t *em_ray,
+               const int32_t *em_site, const T *I, T *out) {
+  switch (vrt::lanes_per_record(nl / V)) {
+    case 64: launch_ec<T, 64, V>(s, total, nl, ld, n, em_ray, em_site, I, out); break;
+    case 32: launch_ec<T, 32, V>(s, total, nl, ld, n, em_ray, em_site, I, out); break;
+    case 16: launch_ec<T, 16, V>(s, total, nl, ld, n, em_ray, em_site, I, out); break;
+    case 8: launch_ec<T, 8, V>(s, total, nl, ld, n, em_ray, em_site, I, out); break;
+    case 4: launch_ec<T, 4, V>(s, total, nl, ld, n, em_ray, em_site, I, out); break;
+    case 2: launch_ec<T, 2, V>(s, total, nl, ld, n, em_ray, em_site, I, out); break;
+    default: launch_ec<T, 1, V>(s, total, nl, ld, n, em_ray, em_site, I, out); break;
+  }
 }
 
 // With a ray-affinity table, c is the largest record count of one die and the
@@ -274,10 +304,11 @@ void launch_jreduce(hipStream_t s, const T *I, int32_t R, int64_t nn, const doub
 template <typename T>
 void launch_emergent(hipStream_t s, int64_t total, int32_t nl, int32_t ld, int64_t n, const int32_t *em_ray,
                      const int32_t *em_site, const T *I, T *out) {
-  const int64_t work = total * nl;
-  if (work == 0) return;
-  hipLaunchKernelGGL(emergent_kernel<T>, dim3((unsigned)((work + 255) / 256)), dim3(256), 0, s, total, nl, ld, n,
-                     em_ray, em_site, I, out);
+  if (total == 0 || nl == 0) return;
+  if (nl % kVec<T> == 0 && ld % kVec<T> == 0 && aligned16(I) && aligned16(out))
+    launch_ev<T, kVec<T>>(s, total, nl, ld, n, em_ray, em_site, I, out);
+  else
+    launch_ev<T, 1>(s, total, nl, ld, n, em_ray, em_site, I, out);
   VRT_HIP(hipGetLastError());
 }
 

@@ -182,6 +182,16 @@ def test_lte_and_emergent_gather_every_lane_width(v, ctx, quad, grids, nl):
     for r in range(len(dirs)):
         assert np.array_equal(emh[off[r]:off[r + 1]], Ih[r, sites[off[r]:off[r + 1]]])
     assert torch.equal(em, em_lib)
+    # outputs that start 4 bytes past a 16-byte boundary take the one-element-per-lane
+    # forms of both kernels and must give the same bits
+    chi_m = torch.empty(g.n * nl + 1, dtype=f, device="cuda:0")[1:].view(g.n, nl)
+    S_m = torch.empty(g.n * nl + 1, dtype=f, device="cuda:0")[1:].view(g.n, nl)
+    v.lte_continuum(G, lam, atm.kappa0, T, rho, chi_m, S_m)
+    em_m = torch.empty(int(off[-1]) * nl + 1, dtype=f, device="cuda:0")[1:].view(int(off[-1]), nl)
+    v.emergent_gather(G, em_m, I_rays=I)
+    torch.cuda.synchronize()
+    assert torch.equal(chi_m, chi) and torch.equal(S_m, S)
+    assert torch.equal(em_m, em)
     G.close()
 
 

@@ -67,17 +67,87 @@ template <typename T> struct PLane<T, 1> {
 
 using namespace vrt_persist;
 
-// words: [0] epoch, [1] device error, [2] registration word (count, plus
-// kFrozen once frozen), [3] frozen count + 1 (0 until frozen)
-__global__ void begin_kernel(int32_t *words) {
-  words[0] += 1;
+// words: [0] epoch of the stamped sweeps, [1] device error (bit 0 a wait gave
+// up, bit 1 a negative or NaN intensity in a sign-encoded sweep), [2]
+// registration word (count, plus kFrozen once frozen), [3] frozen count + 1 (0
+// until frozen), [5] epoch of the sign-encoded sweeps
+__global__ void begin_kernel(int32_t *words, int32_t which) {
+  words[which] += 1;
   words[2] = 0;
   words[3] = 0;
 }
 
+// Sign-encoded rows: the intensities of the linear-segment sweep are never
+// negative (S >= 0, non-negative segment weights and boundary values), so a
+// sweep of odd epoch stores -I and one of even epoch +I, and a consumer knows
+// an upwind row is this sweep's once every element it loaded carries the
+// epoch's sign. The previous sweep's rows carry the other sign, so no stamps,
+// no per-sweep reset and no store-to-stamp ordering are needed. Rows are read
+// back as |I|.
+template <typename T> __device__ __forceinline__ T abs_el(T x) {
+  if constexpr (sizeof(T) == 4) return __builtin_fabsf(x);
+  else return __builtin_fabs(x);
+}
+
+// fills a sign-encoded block with zeros of the current epoch's sign, so that
+// the next epoch reads none of it as written
+template <typename T> __global__ void sign_fill_kernel(T *__restrict__ p, int64_t count, const int32_t *words) {
+  const T z = (words[5] & 1) ? -T(0) : T(0);
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x)
+    p[t] = z;
+}
+
 // item_rec[i] = first record of wave item i, item_cnt[i] = its record count
 // (<= 64/C) + 256 x its ray
-template <typename T, int C, int V>
+// Row access of the persistent sweep. Stamped: plain device-scope load and
+// store. Sign-encoded: the load is repeated (bounded, like a stamp wait) until
+// every element carries the epoch's sign and is returned as |I|; the store
+// writes the epoch's sign and flags a negative or NaN value, which the encoding
+// cannot carry.
+template <typename T, typename VT, typename L, int V, bool SIGN>
+__device__ __forceinline__ VT get_row(__amdgpu_buffer_rsrc_t r, uint32_t off, bool neg, int32_t *err, int64_t cap) {
+  VT u = row_load<VT>(r, off);
+  if constexpr (SIGN) {
+    auto ready = [&](const VT &x) {
+      bool ok = true;
+#pragma unroll
+      for (int k = 0; k < V; ++k) ok = ok && ((__builtin_signbit(L::get(x, k)) != 0) == neg);
+      return ok;
+    };
+    int64_t it = 0;
+    while (!ready(u)) {
+      ++it;
+      if ((it & 63) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, kXScope) != 0) break;
+      if (it > cap) {
+        __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, kXScope);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      u = row_load<VT>(r, off);
+    }
+#pragma unroll
+    for (int k = 0; k < V; ++k) L::set(u, k, abs_el<T>(L::get(u, k)));
+  }
+  return u;
+}
+
+template <typename T, typename VT, typename L, int V, bool SIGN>
+__device__ __forceinline__ void put_row(__amdgpu_buffer_rsrc_t r, uint32_t off, VT v, bool neg, int32_t *err) {
+  if constexpr (SIGN) {
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      const T x = L::get(v, k);
+      bad = bad || !(x >= T(0));
+      const T a = abs_el<T>(x);
+      L::set(v, k, neg ? -a : a);
+    }
+    if (bad) __hip_atomic_fetch_or(err, 2, __ATOMIC_RELAXED, kXScope);
+  }
+  row_store<VT>(r, off, v);
+}
+
+template <typename T, int C, int V, bool SIGN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void persistent_sweep_kernel(
     const int4 *__restrict__ ri, const typename vrt::RecOf<T>::type *__restrict__ rf,
     const int64_t *__restrict__ item_rec, const int32_t *__restrict__ item_cnt, int64_t n_items, int32_t nl,
@@ -85,8 +155,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void pers
     const T *__restrict__ Itop, T *I, int32_t *flags, int32_t *words, int64_t spin_cap) {
   using L = PLane<T, V>;
   using VT = typename L::type;
-  const int32_t epoch = words[0];
+  const int32_t epoch = SIGN ? words[5] : words[0];
   int32_t *err = words + 1;
+  // a sign-encoded sweep after an unacknowledged error would trust rows of an
+  // unknown sign: it does nothing until the host has read and cleared the error
+  if (SIGN && __hip_atomic_load(err, __ATOMIC_RELAXED, kXScope) != 0) return;
+  const bool neg = (epoch & 1) != 0;
   const int lane = threadIdx.x & 63;
   int64_t W = 0;
   const int64_t rank = register_wave(words, (int32_t)(gridDim.x * (blockDim.x >> 6)), spin_cap, lane, W);
@@ -102,7 +176,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void pers
     const int32_t site = q.x, k1 = q.y, k2 = q.z, ray = q.w >> 1;
     const bool up = (q.w & 1) != 0;
     int32_t *fr = flags + (int64_t)ray * flag_ld;
-    if (live && k1 >= 0) {
+    if (!SIGN && live && k1 >= 0) {
       if (wait_stamp(fr + k1, epoch, err, spin_cap) && k2 >= 0) wait_stamp(fr + k2, epoch, err, spin_cap);
     }
     if (live) {
@@ -116,7 +190,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void pers
           if (up) v = L::load(Ibot + bi + l);
           else if (Itop) v = L::load(Itop + bi + l);
           else v = VT(T(0));
-          row_store<VT>(Iray, (uint32_t)((bi + l) * sizeof(T)), v);
+          put_row<T, VT, L, V, SIGN>(Iray, (uint32_t)((bi + l) * sizeof(T)), v, neg, err);
         }
       } else {
         const auto f = rf[rec];
@@ -128,12 +202,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void pers
         for (int l = l0; l < nl; l += C * V) {
           const VT ci = L::load(chi + bi + l), si = L::load(S + bi + l);
           const VT c1 = L::load(chi + b1 + l), s1 = L::load(S + b1 + l);
-          const VT u1 = row_load<VT>(Iray, (uint32_t)((b1 + l) * sizeof(T)));
+          const VT u1 = get_row<T, VT, L, V, SIGN>(Iray, (uint32_t)((b1 + l) * sizeof(T)), neg, err, spin_cap);
           VT c2, s2, u2;
           if (two) {
             c2 = L::load(chi + b2 + l);
             s2 = L::load(S + b2 + l);
-            u2 = row_load<VT>(Iray, (uint32_t)((b2 + l) * sizeof(T)));
+            u2 = get_row<T, VT, L, V, SIGN>(Iray, (uint32_t)((b2 + l) * sizeof(T)), neg, err, spin_cap);
           }
           VT out;
 #pragma unroll
@@ -149,24 +223,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void pers
             }
             L::set(out, k, Iv);
           }
-          row_store<VT>(Iray, (uint32_t)((bi + l) * sizeof(T)), out);
+          put_row<T, VT, L, V, SIGN>(Iray, (uint32_t)((bi + l) * sizeof(T)), out, neg, err);
         }
       }
     }
-    // every row store of the wave has completed before any of its stamps
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    __builtin_amdgcn_s_waitcnt(0);
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    if (live && (lane % C) == 0) __hip_atomic_store(fr + site, epoch, __ATOMIC_RELAXED, kXScope);
+    if constexpr (!SIGN) {
+      // every row store of the wave has completed before any of its stamps
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      __builtin_amdgcn_s_waitcnt(0);
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      if (live && (lane % C) == 0) __hip_atomic_store(fr + site, epoch, __ATOMIC_RELAXED, kXScope);
+    }
   }
 }
 
 template <typename T, int C, int V>
 void launch_pc(hipStream_t s, const vrt::PersistItems &it, int32_t max_blocks, const int4 *ri,
                const typename vrt::RecOf<T>::type *rf, int32_t nl, int64_t n, int64_t flag_ld, const T *chi,
-               const T *S, const T *Ibot, const T *Itop, T *I, int32_t *flags, int32_t *words, int64_t cap) {
+               const T *S, const T *Ibot, const T *Itop, T *I, int32_t *flags, int32_t *words, int64_t cap,
+               bool sign) {
   if (it.spw != 64 / C) throw vrt::Error(VRT_E_STATE, "persistent item table built for another record width");
-  auto kern = persistent_sweep_kernel<T, C, V>;
+  auto kern = sign ? persistent_sweep_kernel<T, C, V, true> : persistent_sweep_kernel<T, C, V, false>;
   int dev = 0, cus = 0, per_cu = 0;
   VRT_HIP(hipGetDevice(&dev));
   VRT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -190,15 +267,15 @@ void launch_pc(hipStream_t s, const vrt::PersistItems &it, int32_t max_blocks, c
 template <typename T, int V>
 void launch_pv(hipStream_t s, const vrt::PersistItems &it, int32_t mb, const int4 *ri,
                const typename vrt::RecOf<T>::type *rf, int32_t nl, int64_t n, int64_t fl, const T *chi, const T *S,
-               const T *Ibot, const T *Itop, T *I, int32_t *flags, int32_t *words, int64_t cap) {
+               const T *Ibot, const T *Itop, T *I, int32_t *flags, int32_t *words, int64_t cap, bool sg) {
   switch (vrt::lanes_per_record(nl / V)) {
-    case 64: launch_pc<T, 64, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap); break;
-    case 32: launch_pc<T, 32, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap); break;
-    case 16: launch_pc<T, 16, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap); break;
-    case 8: launch_pc<T, 8, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap); break;
-    case 4: launch_pc<T, 4, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap); break;
-    case 2: launch_pc<T, 2, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap); break;
-    default: launch_pc<T, 1, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap); break;
+    case 64: launch_pc<T, 64, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg); break;
+    case 32: launch_pc<T, 32, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg); break;
+    case 16: launch_pc<T, 16, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg); break;
+    case 8: launch_pc<T, 8, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg); break;
+    case 4: launch_pc<T, 4, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg); break;
+    case 2: launch_pc<T, 2, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg); break;
+    default: launch_pc<T, 1, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg); break;
   }
 }
 
@@ -208,10 +285,20 @@ namespace vrt {
 
 bool al16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
-void launch_persist_begin(hipStream_t s, int32_t *words) {
-  hipLaunchKernelGGL(begin_kernel, dim3(1), dim3(1), 0, s, words);
+void launch_persist_begin(hipStream_t s, int32_t *words, bool sign) {
+  hipLaunchKernelGGL(begin_kernel, dim3(1), dim3(1), 0, s, words, sign ? 5 : 0);
   VRT_HIP(hipGetLastError());
 }
+
+template <typename T> void launch_sign_fill(hipStream_t s, T *p, int64_t count, const int32_t *words) {
+  if (count <= 0) return;
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(sign_fill_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, p, count, words);
+  VRT_HIP(hipGetLastError());
+}
+template void launch_sign_fill<float>(hipStream_t, float *, int64_t, const int32_t *);
+template void launch_sign_fill<double>(hipStream_t, double *, int64_t, const int32_t *);
 
 int32_t persistent_records_per_wave(int32_t nl, int elem_bytes, bool aligned) {
   const int VW = 16 / elem_bytes;
@@ -223,24 +310,26 @@ template <typename T>
 void launch_persistent_sweep(hipStream_t s, const PersistItems &items, int32_t max_blocks, const int4 *ri,
                              const typename RecOf<T>::type *rf, int32_t nl, int64_t n, int64_t flag_ld, const T *chi,
                              const T *S, const T *Ibot, const T *Itop, T *I, int32_t *flags, int32_t *words,
-                             int64_t spin_cap) {
+                             int64_t spin_cap, bool sign) {
   if (items.n_items <= 0) return;
   if (n * (int64_t)nl * (int64_t)sizeof(T) >= (int64_t(1) << 32))
     throw Error(VRT_E_ARG, "persistent sweep: one ray's intensities exceed 4 GiB; use the level-step modes");
   constexpr int VW = 16 / sizeof(T);
   const bool aligned = al16(chi) && al16(S) && al16(Ibot) && al16(Itop) && al16(I);
   if (aligned && nl % VW == 0)
-    launch_pv<T, VW>(s, items, max_blocks, ri, rf, nl, n, flag_ld, chi, S, Ibot, Itop, I, flags, words, spin_cap);
+    launch_pv<T, VW>(s, items, max_blocks, ri, rf, nl, n, flag_ld, chi, S, Ibot, Itop, I, flags, words, spin_cap,
+                     sign);
   else
-    launch_pv<T, 1>(s, items, max_blocks, ri, rf, nl, n, flag_ld, chi, S, Ibot, Itop, I, flags, words, spin_cap);
+    launch_pv<T, 1>(s, items, max_blocks, ri, rf, nl, n, flag_ld, chi, S, Ibot, Itop, I, flags, words, spin_cap,
+                    sign);
 }
 
 template void launch_persistent_sweep<float>(hipStream_t, const PersistItems &, int32_t, const int4 *, const RecF32 *,
                                              int32_t, int64_t, int64_t, const float *, const float *, const float *,
-                                             const float *, float *, int32_t *, int32_t *, int64_t);
+                                             const float *, float *, int32_t *, int32_t *, int64_t, bool);
 template void launch_persistent_sweep<double>(hipStream_t, const PersistItems &, int32_t, const int4 *,
                                               const RecF64 *, int32_t, int64_t, int64_t, const double *,
                                               const double *, const double *, const double *, double *, int32_t *,
-                                              int32_t *, int64_t);
+                                              int32_t *, int64_t, bool);
 
 }  // namespace vrt

@@ -163,7 +163,8 @@ __global__ __launch_bounds__(256) void sweep_kernel_wide(
 }
 
 // J = sum_r w_r I_r with double accumulation (ray order fixed); V elements per thread.
-template <typename T, int V>
+// ABS reads sign-encoded rows (the persistent sweep's epoch sign) as |I|.
+template <typename T, int V, bool ABS>
 __global__ __launch_bounds__(256) void jreduce_kernel(const T *__restrict__ I, int32_t R, int64_t nn,
                                                       const double *__restrict__ w, T *__restrict__ J) {
   using L = Lane<T, V>;
@@ -178,7 +179,7 @@ __global__ __launch_bounds__(256) void jreduce_kernel(const T *__restrict__ I, i
       const VT x = __builtin_nontemporal_load(reinterpret_cast<const VT *>(I + (int64_t)r * nn + t * V));
       const double wr = w[r];
 #pragma unroll
-      for (int k = 0; k < V; ++k) acc[k] += wr * (double)L::get(x, k);
+      for (int k = 0; k < V; ++k) acc[k] += wr * (ABS ? __builtin_fabs((double)L::get(x, k)) : (double)L::get(x, k));
     }
     VT out;
 #pragma unroll
@@ -190,7 +191,7 @@ __global__ __launch_bounds__(256) void jreduce_kernel(const T *__restrict__ I, i
 // I rows have ld >= nl entries; out rows have nl.
 // C lanes per emergent row (a power of two), 64/C rows per wavefront, V
 // consecutive wavelengths (16 bytes) per lane when the rows allow it.
-template <typename T, int C, int V>
+template <typename T, int C, int V, bool ABS>
 __global__ __launch_bounds__(256) void emergent_kernel(int64_t total, int32_t nl, int32_t ld, int64_t n,
                                                        const int32_t *__restrict__ em_ray,
                                                        const int32_t *__restrict__ em_site, const T *__restrict__ I,
@@ -202,29 +203,36 @@ __global__ __launch_bounds__(256) void emergent_kernel(int64_t total, int32_t nl
   if (e >= total) return;
   const T *src = I + ((int64_t)em_ray[e] * n + em_site[e]) * ld;
   T *dst = out + e * nl;
-  for (int32_t l = (lane % C) * V; l < nl; l += C * V) L::store(dst + l, L::load(src + l));
+  for (int32_t l = (lane % C) * V; l < nl; l += C * V) {
+    auto x = L::load(src + l);
+    if constexpr (ABS) {
+#pragma unroll
+      for (int k = 0; k < V; ++k) L::set(x, k, (T)__builtin_fabs((double)L::get(x, k)));
+    }
+    L::store(dst + l, x);
+  }
 }
 
 template <typename T, int C, int V>
 void launch_ec(hipStream_t s, int64_t total, int32_t nl, int32_t ld, int64_t n, const int32_t *em_ray,
-               const int32_t *em_site, const T *I, T *out) {
+               const int32_t *em_site, const T *I, T *out, bool ab) {
   constexpr int SPW = 64 / C;
   const int64_t blocks = (total + 4 * SPW - 1) / (4 * SPW);
-  hipLaunchKernelGGL((emergent_kernel<T, C, V>), dim3((unsigned)blocks), dim3(256), 0, s, total, nl, ld, n, em_ray,
-                     em_site, I, out);
+  auto kern = ab ? emergent_kernel<T, C, V, true> : emergent_kernel<T, C, V, false>;
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, s, total, nl, ld, n, em_ray, em_site, I, out);
 }
 
 template <typename T, int V>
 void launch_ev(hipStream_t s, int64_t total, int32_t nl, int32_t ld, int64_t n, const int32_t *em_ray,
-               const int32_t *em_site, const T *I, T *out) {
+               const int32_t *em_site, const T *I, T *out, bool ab) {
   switch (vrt::lanes_per_record(nl / V)) {
-    case 64: launch_ec<T, 64, V>(s, total, nl, ld, n, em_ray, em_site, I, out); break;
-    case 32: launch_ec<T, 32, V>(s, total, nl, ld, n, em_ray, em_site, I, out); break;
-    case 16: launch_ec<T, 16, V>(s, total, nl, ld, n, em_ray, em_site, I, out); break;
-    case 8: launch_ec<T, 8, V>(s, total, nl, ld, n, em_ray, em_site, I, out); break;
-    case 4: launch_ec<T, 4, V>(s, total, nl, ld, n, em_ray, em_site, I, out); break;
-    case 2: launch_ec<T, 2, V>(s, total, nl, ld, n, em_ray, em_site, I, out); break;
-    default: launch_ec<T, 1, V>(s, total, nl, ld, n, em_ray, em_site, I, out); break;
+    case 64: launch_ec<T, 64, V>(s, total, nl, ld, n, em_ray, em_site, I, out, ab); break;
+    case 32: launch_ec<T, 32, V>(s, total, nl, ld, n, em_ray, em_site, I, out, ab); break;
+    case 16: launch_ec<T, 16, V>(s, total, nl, ld, n, em_ray, em_site, I, out, ab); break;
+    case 8: launch_ec<T, 8, V>(s, total, nl, ld, n, em_ray, em_site, I, out, ab); break;
+    case 4: launch_ec<T, 4, V>(s, total, nl, ld, n, em_ray, em_site, I, out, ab); break;
+    case 2: launch_ec<T, 2, V>(s, total, nl, ld, n, em_ray, em_site, I, out, ab); break;
+    default: launch_ec<T, 1, V>(s, total, nl, ld, n, em_ray, em_site, I, out, ab); break;
   }
 }
 
@@ -288,27 +296,26 @@ void launch_sweep(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *
 }
 
 template <typename T>
-void launch_jreduce(hipStream_t s, const T *I, int32_t R, int64_t nn, const double *w, T *J) {
+void launch_jreduce(hipStream_t s, const T *I, int32_t R, int64_t nn, const double *w, T *J, bool abs_rows) {
   if (nn == 0) return;
   const bool vec = nn % kVec<T> == 0 && aligned16(I) && aligned16(J);
   const int64_t items = vec ? nn / kVec<T> : nn;
   int64_t blocks = (items + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  if (vec)
-    hipLaunchKernelGGL((jreduce_kernel<T, kVec<T>>), dim3((unsigned)blocks), dim3(256), 0, s, I, R, nn, w, J);
-  else
-    hipLaunchKernelGGL((jreduce_kernel<T, 1>), dim3((unsigned)blocks), dim3(256), 0, s, I, R, nn, w, J);
+  auto kern = vec ? (abs_rows ? jreduce_kernel<T, kVec<T>, true> : jreduce_kernel<T, kVec<T>, false>)
+                  : (abs_rows ? jreduce_kernel<T, 1, true> : jreduce_kernel<T, 1, false>);
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, s, I, R, nn, w, J);
   VRT_HIP(hipGetLastError());
 }
 
 template <typename T>
 void launch_emergent(hipStream_t s, int64_t total, int32_t nl, int32_t ld, int64_t n, const int32_t *em_ray,
-                     const int32_t *em_site, const T *I, T *out) {
+                     const int32_t *em_site, const T *I, T *out, bool abs_rows) {
   if (total == 0 || nl == 0) return;
   if (nl % kVec<T> == 0 && ld % kVec<T> == 0 && aligned16(I) && aligned16(out))
-    launch_ev<T, kVec<T>>(s, total, nl, ld, n, em_ray, em_site, I, out);
+    launch_ev<T, kVec<T>>(s, total, nl, ld, n, em_ray, em_site, I, out, abs_rows);
   else
-    launch_ev<T, 1>(s, total, nl, ld, n, em_ray, em_site, I, out);
+    launch_ev<T, 1>(s, total, nl, ld, n, em_ray, em_site, I, out, abs_rows);
   VRT_HIP(hipGetLastError());
 }
 
@@ -318,11 +325,12 @@ template void launch_sweep<float>(hipStream_t, const int4 *, const RecF32 *, int
 template void launch_sweep<double>(hipStream_t, const int4 *, const RecF64 *, int64_t, int64_t, int32_t, int64_t,
                                    const double *, const double *, const double *, const double *, double *, int32_t,
                                    int32_t, const int64_t *, int32_t, int32_t);
-template void launch_jreduce<float>(hipStream_t, const float *, int32_t, int64_t, const double *, float *);
-template void launch_jreduce<double>(hipStream_t, const double *, int32_t, int64_t, const double *, double *);
+template void launch_jreduce<float>(hipStream_t, const float *, int32_t, int64_t, const double *, float *, bool);
+template void launch_jreduce<double>(hipStream_t, const double *, int32_t, int64_t, const double *, double *,
+                                     bool);
 template void launch_emergent<float>(hipStream_t, int64_t, int32_t, int32_t, int64_t, const int32_t *,
-                                     const int32_t *, const float *, float *);
+                                     const int32_t *, const float *, float *, bool);
 template void launch_emergent<double>(hipStream_t, int64_t, int32_t, int32_t, int64_t, const int32_t *,
-                                      const int32_t *, const double *, double *);
+                                      const int32_t *, const double *, double *, bool);
 
 }  // namespace vrt

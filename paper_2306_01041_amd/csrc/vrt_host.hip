@@ -468,6 +468,28 @@ template <typename T> T *intensity_buffer(vrt_grid g, int32_t nl, void *I_rays) 
   return g->d_Iscr.as<T>();
 }
 
+// Rows of the sign-encoded persistent sweep: a block of their own (no other
+// mode writes it), refilled with zeros of the current epoch's sign whenever its
+// layout changes or an error was acknowledged, so that no element left from
+// another layout or an abandoned sweep reads as written by the next epoch.
+void ensure_flags(vrt_grid g);
+template <typename T> T *sign_buffer(vrt_grid g, int32_t nl) {
+  ensure_flags(g);
+  const int64_t count = (int64_t)g->R * g->n * nl;
+  const int64_t key[4] = {(int64_t)sizeof(T), nl, g->R, g->n};
+  bool fill = false;
+  if ((size_t)count * sizeof(T) > g->d_Isgn.bytes) {
+    g->d_Isgn.alloc((size_t)count * sizeof(T));
+    fill = true;
+  }
+  for (int k = 0; k < 4; ++k) fill = fill || g->sgn_key[k] != key[k];
+  if (fill) {
+    vrt::launch_sign_fill<T>(g->ctx->stream, g->d_Isgn.as<T>(), count, g->d_epoch.as<int32_t>());
+    for (int k = 0; k < 4; ++k) g->sgn_key[k] = key[k];
+  }
+  return g->d_Isgn.as<T>();
+}
+
 // Runs one launch, bracketed by timing events when the context profiles
 // (never inside a graph capture: `timed` is false there).
 template <typename F> void timed_launch(vrt_ctx ctx, hipStream_t s, bool timed, int kernel, int64_t units, F &&launch) {
@@ -531,7 +553,7 @@ const vrt::PersistItems &persistent_items(vrt_grid g, int32_t spw) {
 // The sweeps of every ray (no angle quadrature).
 template <typename T>
 void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *chi, const T *S, const T *Ib,
-                   const T *It, T *I) {
+                   const T *It, T *I, bool sign = false) {
   const int32_t R = g->R;
   const int64_t n = g->n;
   vrt_ctx ctx = g->ctx;
@@ -577,10 +599,11 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
     const bool aligned = vrt::al16(chi) && vrt::al16(S) && vrt::al16(Ib) && vrt::al16(It) && vrt::al16(I);
     const vrt::PersistItems &items = persistent_items(g, vrt::persistent_records_per_wave(nl, sizeof(T), aligned));
     int32_t *words = g->d_epoch.as<int32_t>();
-    vrt::launch_persist_begin(s, words);
+    vrt::launch_persist_begin(s, words, sign);
     timed_launch(ctx, s, tm, 0, g->n_rec * nl, [&] {
       vrt::launch_persistent_sweep<T>(s, items, g->persist_max_blocks, g->d_ri.as<int4>(), records<T>(g), nl, n,
-                                      flag_ld(g), chi, S, Ib, It, I, g->d_flags.as<int32_t>(), words, g->spin_cap);
+                                      flag_ld(g), chi, S, Ib, It, I, g->d_flags.as<int32_t>(), words, g->spin_cap,
+                                      sign);
     });
   } else if (g->kind == 0) {
     const int4 *ri = g->d_ri.as<int4>();
@@ -679,14 +702,14 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
 
 template <typename T>
 void enqueue_fs(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *chi, const T *S, const T *Ib,
-                const T *It, T *J, T *I) {
-  enqueue_sweep<T>(g, s, ex, nl, chi, S, Ib, It, I);
+                const T *It, T *J, T *I, bool sign = false) {
+  enqueue_sweep<T>(g, s, ex, nl, chi, S, Ib, It, I, sign);
   vrt_ctx ctx = g->ctx;
   const bool tm = ctx->profiling && ex != VRT_EXEC_GRAPH && s == ctx->stream;
   const int32_t R = g->R;
   const int64_t n = g->n;
   timed_launch(ctx, s, tm, 1, (int64_t)R * n * nl,
-               [&] { vrt::launch_jreduce<T>(s, I, R, n * nl, g->d_w.as<double>(), J); });
+               [&] { vrt::launch_jreduce<T>(s, I, R, n * nl, g->d_w.as<double>(), J, sign); });
 }
 
 // Per-ray dependents lists: for every site k, the sites d whose forward update
@@ -1015,6 +1038,7 @@ vrt_status two_level_solve(vrt_grid g, vrt_exec ex, int32_t nl, const double *wl
       VRT_HIP(hipMemcpyAsync(g->d_active.p, active, (size_t)n_atm * 4, hipMemcpyHostToDevice, s));
   }
   g->last_I = I;
+  g->last_abs = false;
   g->last_prec = sizeof(T) == 4 ? VRT_F32 : VRT_F64;
   g->last_nl = nl;
   g->last_ld = ld;
@@ -1028,11 +1052,14 @@ void formal_solution(vrt_grid g, vrt_exec ex, int32_t nl, const void *chi_, cons
   const T *Ib = Ib_ ? static_cast<const T *>(Ib_) : S;
   const T *It = static_cast<const T *>(It_);
   T *J = static_cast<T *>(J_);
-  T *I = intensity_buffer<T>(g, nl, Ir_);
   vrt_ctx ctx = g->ctx;
   if (ex == VRT_EXEC_PERSISTENT && g->kind != 0) ex = VRT_EXEC_GRAPH;
+  // the linear-segment persistent sweep into the library's own rows uses the
+  // sign-encoded protocol; rows handed in by the caller keep the stamps
+  const bool sign = ex == VRT_EXEC_PERSISTENT && g->segment == 0 && !Ir_;
+  T *I = sign ? sign_buffer<T>(g, nl) : intensity_buffer<T>(g, nl, Ir_);
   if (ex != VRT_EXEC_GRAPH) {
-    enqueue_fs<T>(g, ctx->stream, ex, nl, chi, S, Ib, It, J, I);
+    enqueue_fs<T>(g, ctx->stream, ex, nl, chi, S, Ib, It, J, I, sign);
   } else {
     const vrt_grid_s::GraphKey key{sizeof(T), nl, chi, S, Ib, It, J, I};
     auto it = g->graphs.find(key);
@@ -1063,6 +1090,7 @@ void formal_solution(vrt_grid g, vrt_exec ex, int32_t nl, const void *chi_, cons
     VRT_HIP(hipGraphLaunch(it->second, ctx->stream));
   }
   g->last_I = I;
+  g->last_abs = sign;
   g->last_prec = sizeof(T) == 4 ? VRT_F32 : VRT_F64;
   g->last_nl = nl;
   g->last_ld = nl;
@@ -1337,6 +1365,10 @@ vrt_status vrt_grid_set_rays(vrt_grid g, int32_t n_rays, const double *dir, cons
     upload(g->d_dirs, dir, 3 * (size_t)n_rays, g->ctx->stream);
     upload(g->d_w, w, (size_t)n_rays, g->ctx->stream);
     g->d_Iscr.release();
+    g->d_Isgn.release();
+    for (int k = 0; k < 4; ++k) g->sgn_key[k] = 0;
+    g->last_I = nullptr;  // the rows it pointed to are gone
+    g->last_abs = false;
     if (g->kind == 0) {
       set_rays_voronoi(g);
     } else {
@@ -1721,6 +1753,10 @@ vrt_status vrt_grid_device_status(vrt_grid g) {
     VRT_HIP(hipMemcpy(&err, g->d_epoch.as<int32_t>() + 1, 4, hipMemcpyDeviceToHost));
     if (err == 0) return VRT_OK;
     VRT_HIP(hipMemset(g->d_epoch.as<int32_t>() + 1, 0, 4));
+    for (int k = 0; k < 4; ++k) g->sgn_key[k] = 0;  // the sign-encoded rows are refilled before their next use
+    if (err & 2)
+      fail(VRT_E_NUMERIC, "negative or NaN intensity in the sign-encoded persistent sweep (it needs I >= 0; pass "
+                          "I_rays or use another execution mode for such inputs)");
     fail(VRT_E_TIMEOUT, "a bounded wait of the persistent sweep gave up (spin cap %lld)", (long long)g->spin_cap);
     return VRT_OK;
   });
@@ -1745,6 +1781,7 @@ vrt_status vrt_emergent_gather(vrt_grid g, vrt_prec prec, int32_t n_lambda, cons
     const void *I = I_rays ? I_rays : g->last_I;
     if (!I) fail(VRT_E_STATE, "no formal solution has run");
     int32_t ld = n_lambda;
+    const bool ab = !I_rays && g->last_abs;
     if (!I_rays) {
       if (prec != g->last_prec || n_lambda != g->last_nl)
         fail(VRT_E_ARG, "the last solution had %d wavelengths in %s precision", g->last_nl,
@@ -1755,11 +1792,12 @@ vrt_status vrt_emergent_gather(vrt_grid g, vrt_prec prec, int32_t n_lambda, cons
     if (total > 0 && !out) fail(VRT_E_ARG, "null output");
     if (prec == VRT_F32)
       vrt::launch_emergent<float>(g->ctx->stream, total, n_lambda, ld, g->n, g->d_em_ray.as<int32_t>(),
-                                  g->d_em_site.as<int32_t>(), static_cast<const float *>(I), static_cast<float *>(out));
+                                  g->d_em_site.as<int32_t>(), static_cast<const float *>(I), static_cast<float *>(out),
+                                  ab);
     else
       vrt::launch_emergent<double>(g->ctx->stream, total, n_lambda, ld, g->n, g->d_em_ray.as<int32_t>(),
                                    g->d_em_site.as<int32_t>(), static_cast<const double *>(I),
-                                   static_cast<double *>(out));
+                                   static_cast<double *>(out), ab);
     return VRT_OK;
   });
 }

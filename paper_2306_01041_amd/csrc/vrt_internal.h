@@ -203,6 +203,11 @@ struct vrt_grid_s {
   // scratch for per-ray intensities when the caller passes none
   vrt::DevBuf d_Iscr;
   const void *last_I = nullptr;  // intensities of the last solution (library scratch)
+  bool last_abs = false;         // last_I holds sign-encoded rows (read as |I|)
+  // rows of the sign-encoded persistent sweep, owned by that mode alone, and the
+  // layout {element bytes, wavelengths, rays, sites} they were last filled for
+  vrt::DevBuf d_Isgn;
+  int64_t sgn_key[4] = {0, 0, 0, 0};
   int last_prec = -1;            // their precision, wavelength count and row stride
   int32_t last_nl = 0, last_ld = 0;
 
@@ -278,10 +283,11 @@ void launch_sweep(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *
                   const T *Itop, T *I, int32_t xcd_chunks, int32_t ray0, const int64_t *xtab = nullptr,
                   int32_t xk = 0, int32_t lane_bytes = 16);
 template <typename T>
-void launch_jreduce(hipStream_t s, const T *I, int32_t R, int64_t nn, const double *w, T *J);
+void launch_jreduce(hipStream_t s, const T *I, int32_t R, int64_t nn, const double *w, T *J,
+                    bool abs_rows = false);
 template <typename T>
 void launch_emergent(hipStream_t s, int64_t total, int32_t nl, int32_t ld, int64_t n, const int32_t *em_ray,
-                     const int32_t *em_site, const T *I, T *out);
+                     const int32_t *em_site, const T *I, T *out, bool abs_rows = false);
 
 // ---- k_source.hip
 template <typename T>
@@ -292,14 +298,18 @@ void launch_lte(hipStream_t s, int64_t n, int32_t nl, const double *lam, double 
 // words: [0] epoch, [1] device error (non-zero: a bounded wait gave up),
 // [2] registration word, [3] frozen wavefront count + 1. Flags of ray r start
 // at flags + r * flag_ld.
-void launch_persist_begin(hipStream_t s, int32_t *words);
+// starts a persistent sweep: bumps the stamped (sign = false) or the sign-encoded
+// (sign = true) epoch and resets the registration words
+void launch_persist_begin(hipStream_t s, int32_t *words, bool sign = false);
+// fills count elements with zeros of the current sign-encoded epoch's sign
+template <typename T> void launch_sign_fill(hipStream_t s, T *p, int64_t count, const int32_t *words);
 int32_t persistent_records_per_wave(int32_t nl, int elem_bytes, bool aligned);
 bool al16(const void *p);
 template <typename T>
 void launch_persistent_sweep(hipStream_t s, const PersistItems &items, int32_t max_blocks, const int4 *ri,
                              const typename RecOf<T>::type *rf, int32_t nl, int64_t n, int64_t flag_ld, const T *chi,
                              const T *S, const T *Ibot, const T *Itop, T *I, int32_t *flags, int32_t *words,
-                             int64_t spin_cap);
+                             int64_t spin_cap, bool sign = false);
 
 // ---- k_nlte.hip
 template <typename T>

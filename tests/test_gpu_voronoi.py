@@ -414,6 +414,67 @@ def test_persistent_any_grid_size_gives_the_same_result(v, ctx, quad, grids, nl,
     G.close()
 
 
+def test_persistent_sign_encoded_rows_across_modes_and_layouts(v, ctx, quad, grids):
+    """Without caller rows the persistent sweep keeps its own sign-encoded rows
+    (odd epochs store -I). Solutions of changing precision and wavelength count,
+    interleaved with graph-launched and stamped (caller-row) persistent solutions,
+    must each give the graph sweep's J and emergent rows bit for bit."""
+    flush("persistent sign-encoded rows")
+    atm, g = grids[16384]
+    dirs, w = quad
+    G = _gpu_grid(v, ctx, g, dirs, w)
+    off, _ = G.emergent_index()
+    for d, nl in ((torch.float32, 64), (torch.float32, 5), (torch.float64, 3), (torch.float32, 64)):
+        chi_o, S_o = _fields(atm, nl, 17 + nl)
+        chi, S = to_dev(chi_o, d), to_dev(S_o, d)
+        Jg = torch.empty_like(chi)
+        v.formal_solution(G, chi, S, Jg, exec_mode=v.VRT_EXEC_GRAPH)
+        em_g = torch.empty((int(off[-1]), nl), dtype=d, device="cuda:0")
+        v.emergent_gather(G, em_g)
+        I = torch.empty((len(dirs), g.n, nl), dtype=d, device="cuda:0")
+        for rep in range(4):
+            J = torch.full_like(chi, -1.0)
+            if rep == 2:  # caller rows: the stamped protocol, plain positive rows
+                v.formal_solution(G, chi, S, J, I_rays=I, exec_mode=v.VRT_EXEC_PERSISTENT)
+            else:
+                v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_PERSISTENT)
+            em = torch.empty_like(em_g)
+            v.emergent_gather(G, em, I_rays=I if rep == 2 else None)
+            G.device_status()
+            assert torch.equal(J, Jg), (d, nl, rep)
+            assert torch.equal(em, em_g), (d, nl, rep)
+            if rep == 2:
+                assert bool((I >= 0).all())
+    G.close()
+
+
+def test_persistent_sign_encoding_rejects_negative_intensities(v, ctx, quad, grids):
+    """A negative source function gives negative intensities, which the sign
+    encoding cannot carry: the sweep still drains, the device status reports a
+    numeric error once, and the next solution of valid inputs is correct."""
+    flush("persistent sign-encoded rows, negative source")
+    atm, g = grids[16384]
+    dirs, w = quad
+    G = _gpu_grid(v, ctx, g, dirs, w)
+    chi_o, S_o = _fields(atm, 8, 19)
+    f = torch.float32
+    chi, S = to_dev(chi_o, f), to_dev(S_o, f)
+    Jg = torch.empty_like(chi)
+    v.formal_solution(G, chi, S, Jg, exec_mode=v.VRT_EXEC_GRAPH)
+    Sneg = -S  # every boundary intensity (I_bottom defaults to S) is negative
+    J = torch.empty_like(chi)
+    v.formal_solution(G, chi, Sneg, J, exec_mode=v.VRT_EXEC_PERSISTENT)
+    with pytest.raises(v.VrtError) as e:
+        G.device_status()
+    assert e.value.status == v.VRT_E_NUMERIC
+    G.device_status()  # cleared
+    for _ in range(2):
+        v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_PERSISTENT)
+        G.device_status()
+        assert torch.equal(J, Jg)
+    G.close()
+
+
 def test_persistent_bounded_wait_reports_timeout(v, ctx, quad, grids):
     """A spin bound of zero polls makes the first unmet wait give up: the kernel
     still drains, the device status reports a timeout once, and the next

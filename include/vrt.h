@@ -61,11 +61,18 @@ typedef enum { VRT_F64 = 0, VRT_F32 = 1 } vrt_prec;
  * PLAIN:      one kernel per (ray, level) of the upwind schedule, rays in turn.
  * BATCHED:    one kernel per level step with all rays in flight together.
  * GRAPH:      BATCHED, captured once into a HIP graph and replayed.
- * PERSISTENT: one kernel for all rays and levels; each site waits for the
- *             completion stamps of its upwind sites (Voronoi grids; regular
- *             grids fall back to GRAPH). One ray's intensities must stay below
- *             4 GiB (else VRT_E_ARG). Check vrt_grid_device_status after
- *             synchronising to learn whether a bounded wait gave up. */
+ * PERSISTENT: one kernel for all rays and levels (Voronoi grids; regular
+ *             grids fall back to GRAPH). Into caller rows (I_rays) each site
+ *             waits for the completion stamps of its upwind sites. Into the
+ *             library's own rows (I_rays NULL, linear segment) readiness rides
+ *             in the sign bit: odd epochs store -I, and a site waits until the
+ *             upwind elements it loads carry its epoch's sign; the J quadrature
+ *             and vrt_emergent_gather read those rows as |I|. That encoding
+ *             needs I >= 0 (S, I_bottom, I_top >= 0); a negative or NaN
+ *             intensity is reported as VRT_E_NUMERIC. One ray's intensities must
+ *             stay below 4 GiB (else VRT_E_ARG). Check vrt_grid_device_status
+ *             after synchronising to learn whether a bounded wait gave up
+ *             (VRT_E_TIMEOUT) or a value could not be encoded (VRT_E_NUMERIC). */
 typedef enum {
   VRT_EXEC_PLAIN = 0,
   VRT_EXEC_BATCHED = 1,

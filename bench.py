@@ -463,7 +463,7 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic),
                      "algorithmic_bytes_per_launch": round(bytes_per_launch),
-                     "kernel": ("persistent_sweep_kernel<float,16,4>" if args.mode == "persistent"
+                     "kernel": ("persistent_sweep_kernel<float,16,4,true>" if args.mode == "persistent"
                                 else "sweep_kernel<float,16,4>"), "bytes_per_update": round(bpu, 4),
                      "mean_launch_us": round(avg_launch_ms * 1e3, 2), "launches_per_step": launches,
                      "sweep_ms_per_step": round(sweep_ms, 4), "j_quadrature_ms": round(jr_one, 4)},

@@ -191,6 +191,79 @@ def test_regular_integer_shift_transport(orc):
     assert np.max(np.abs(top - want)) < 1e-12
 
 
+@pytest.mark.parametrize("up", [True, False])
+def test_regular_fractional_shift_fourier_mode(orc, up):
+    """Bilinear interpolation at a fractional upwind offset (Sect. 2.6, linear
+    interpolation in the upwind plane), pinned by its closed form. With constant
+    chi, S = 0 and a boundary plane cos(k x) that is constant in y, the upwind
+    point of every point lies a = p + t cells upwind in x, and linear
+    interpolation of the Fourier mode e^{ikx} there gives the mode times
+    e^{-ikp dx} ((1 - t) + t e^{-ik dx}); each plane also attenuates by
+    e^{-chi ds}. After s planes the intensity is Re[(e^{-chi ds} G)^s e^{ikx}].
+    Nearest-cell rounding or swapped weights change |G| and fail."""
+    nx, ny, nz = 24, 3, 8
+    dx, dy = 1.0, 0.8
+    z = np.arange(nz, dtype=float)  # dz = 1
+    a_x, a_y = 2.37, 0.61  # upwind offset per plane, in cells of x and of y
+    mz = 1.0 / np.sqrt(1.0 + (a_x * dx) ** 2 + (a_y * dy) ** 2)
+    d = np.array([[a_x * dx * mz, a_y * dy * mz, mz if up else -mz]])
+    w = np.array([1.0])
+    m = 3
+    k = 2 * np.pi * m / (nx * dx)
+    x = np.arange(nx) * dx
+    plane = np.broadcast_to(np.cos(k * x)[None, :], (ny, nx))
+    n = nx * ny * nz
+    chi_v = 0.05
+    chi = np.full((n, 1), chi_v)
+    bnd = np.zeros((nz, ny, nx))
+    bnd[0 if up else nz - 1] = plane
+    kw = dict(keep_I=True)
+    if up:
+        J, I = orc.fs_regular(nx, ny, z, dx, dy, d, w, chi, np.zeros_like(chi), bnd.reshape(-1, 1), **kw)
+    else:
+        J, I = orc.fs_regular(nx, ny, z, dx, dy, d, w, chi, np.zeros_like(chi), np.zeros((n, 1)),
+                              I_top=bnd.reshape(-1, 1), **kw)
+    got = I[0, :, 0].reshape(nz, ny, nx)
+    ds = 1.0 / mz
+    p, t = 2, 0.37
+    G = np.exp(-chi_v * ds) * np.exp(-1j * k * p * dx) * ((1 - t) + t * np.exp(-1j * k * dx))
+    for s in range(nz):
+        kk = s if up else nz - 1 - s
+        want = np.real(G ** s * np.exp(1j * k * x))
+        assert np.max(np.abs(got[kk] - want[None, :])) < 1e-13, s
+    # the interpolation damps the mode: |G| < e^{-chi ds} (nearest-cell rounding would not)
+    assert abs(G) < np.exp(-chi_v * ds) * 0.95
+
+
+def test_regular_fractional_shift_matches_map_coordinates(orc):
+    """Multi-plane optically thin transport (chi = S = 0: each plane is the
+    upwind plane interpolated) of a random periodic pattern, at fractional
+    offsets in both x and y with dx != dy, against scipy's periodic linear
+    interpolation (map_coordinates, order 1, grid-wrap) applied plane by plane."""
+    from scipy.ndimage import map_coordinates
+
+    nx, ny, nz = 13, 11, 6
+    dx, dy = 0.7, 1.3
+    z = np.cumsum(np.r_[0.0, np.random.default_rng(31).uniform(0.5, 1.5, nz - 1)])  # uneven planes
+    d = np.array([[0.55, -0.31, 0.0]])
+    d[0, 2] = np.sqrt(1 - d[0, 0] ** 2 - d[0, 1] ** 2)
+    w = np.array([1.0])
+    pattern = np.random.default_rng(32).uniform(0.0, 1.0, (ny, nx))
+    n = nx * ny * nz
+    chi = np.zeros((n, 1))
+    Ib = np.zeros((nz, ny, nx))
+    Ib[0] = pattern
+    J, I = orc.fs_regular(nx, ny, z, dx, dy, d, w, chi, np.zeros_like(chi), Ib.reshape(-1, 1), keep_I=True)
+    got = I[0, :, 0].reshape(nz, ny, nx)
+    jj, ii = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    want = pattern
+    for s in range(1, nz):
+        ds = (z[s] - z[s - 1]) / d[0, 2]
+        coords = [jj - ds * d[0, 1] / dy, ii - ds * d[0, 0] / dx]
+        want = map_coordinates(want, coords, order=1, mode="grid-wrap")
+        assert np.max(np.abs(got[s] - want)) < 1e-13, s
+
+
 def test_regular_isothermal(orc):
     nx, ny = 4, 4
     z = np.linspace(0, 3, 12)

@@ -213,13 +213,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void pers
 #pragma unroll
           for (int k = 0; k < V; ++k) {
             const T cik = L::get(ci, k), sik = L::get(si, k);
-            T E, pu, p0;
-            vrt::Seg<T>::weights((L::get(c1, k) + cik) * h1, E, pu, p0);
-            T Iv = E * L::get(u1, k) + pu * L::get(s1, k) + p0 * sik;
+            T Iv = vrt::seg_line<T>((L::get(c1, k) + cik) * h1, L::get(u1, k), L::get(s1, k), sik);
             if (two) {
-              vrt::Seg<T>::weights((L::get(c2, k) + cik) * h2, E, pu, p0);
-              const T Ib = E * L::get(u2, k) + pu * L::get(s2, k) + p0 * sik;
-              Iv = w1 * Iv + w2 * Ib;
+              const T Ib = vrt::seg_line<T>((L::get(c2, k) + cik) * h2, L::get(u2, k), L::get(s2, k), sik);
+              Iv = vrt::seg_mix<T>(w1, w2, Iv, Ib);
             }
             L::set(out, k, Iv);
           }

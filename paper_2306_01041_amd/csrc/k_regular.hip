@@ -128,9 +128,7 @@ __global__ __launch_bounds__(256) void regular_kernel(int32_t step, int32_t ray_
       const T Iu = a00 * el<T, V>(i00, e) + a10 * el<T, V>(i10, e) + a01 * el<T, V>(i01, e) + a11 * el<T, V>(i11, e);
       const T Su = a00 * el<T, V>(s00, e) + a10 * el<T, V>(s10, e) + a01 * el<T, V>(s01, e) + a11 * el<T, V>(s11, e);
       const T cu = a00 * el<T, V>(x00, e) + a10 * el<T, V>(x10, e) + a01 * el<T, V>(x01, e) + a11 * el<T, V>(x11, e);
-      T E, pw, p0;
-      vrt::Seg<T>::weights((cu + el<T, V>(cm, e)) * h, E, pw, p0);
-      set_el<T, V>(out, e, E * Iu + pw * Su + p0 * el<T, V>(sm, e));
+      set_el<T, V>(out, e, vrt::seg_line<T>((cu + el<T, V>(cm, e)) * h, Iu, Su, el<T, V>(sm, e)));
     }
     L::store(Iray + me + l, out);
   }

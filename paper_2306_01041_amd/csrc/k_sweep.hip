@@ -125,13 +125,10 @@ __device__ __forceinline__ void sweep_body(const int4 *__restrict__ ri,
 #pragma unroll
     for (int k = 0; k < V; ++k) {
       const T cik = L::get(ci, k), sik = L::get(si, k);
-      T E, pu, p0;
-      vrt::Seg<T>::weights((L::get(c1, k) + cik) * h1, E, pu, p0);
-      T Iv = E * L::get(u1, k) + pu * L::get(s1, k) + p0 * sik;
+      T Iv = vrt::seg_line<T>((L::get(c1, k) + cik) * h1, L::get(u1, k), L::get(s1, k), sik);
       if (two) {
-        vrt::Seg<T>::weights((L::get(c2, k) + cik) * h2, E, pu, p0);
-        const T Ib = E * L::get(u2, k) + pu * L::get(s2, k) + p0 * sik;
-        Iv = w1 * Iv + w2 * Ib;
+        const T Ib = vrt::seg_line<T>((L::get(c2, k) + cik) * h2, L::get(u2, k), L::get(s2, k), sik);
+        Iv = vrt::seg_mix<T>(w1, w2, Iv, Ib);
       }
       L::set(out, k, Iv);
     }
@@ -163,13 +160,24 @@ __global__ __launch_bounds__(256) void sweep_kernel_wide(
 }
 
 // J = sum_r w_r I_r with double accumulation (ray order fixed); V elements per thread.
-// ABS reads sign-encoded rows (the persistent sweep's epoch sign) as |I|.
+// ABS reads sign-encoded rows (the persistent sweep's epoch sign) as |I|; if
+// the sweep's device error word is set, those rows are not this epoch's (the
+// sweep stopped early or did not run), and J is written as NaN instead.
 template <typename T, int V, bool ABS>
 __global__ __launch_bounds__(256) void jreduce_kernel(const T *__restrict__ I, int32_t R, int64_t nn,
-                                                      const double *__restrict__ w, T *__restrict__ J) {
+                                                      const double *__restrict__ w, T *__restrict__ J,
+                                                      const int32_t *__restrict__ err) {
   using L = Lane<T, V>;
   using VT = typename L::type;
   const int64_t nv = nn / V;
+  if (ABS && err && *err != 0) {
+    VT nan;
+#pragma unroll
+    for (int k = 0; k < V; ++k) L::set(nan, k, (T)__builtin_nan(""));
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nv; t += (int64_t)gridDim.x * blockDim.x)
+      L::store(J + t * V, nan);
+    return;
+  }
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nv; t += (int64_t)gridDim.x * blockDim.x) {
     double acc[V];
 #pragma unroll
@@ -190,24 +198,27 @@ __global__ __launch_bounds__(256) void jreduce_kernel(const T *__restrict__ I, i
 
 // I rows have ld >= nl entries; out rows have nl.
 // C lanes per emergent row (a power of two), 64/C rows per wavefront, V
-// consecutive wavelengths (16 bytes) per lane when the rows allow it.
+// consecutive wavelengths (16 bytes) per lane when the rows allow it. ABS:
+// sign-encoded rows, NaN when the sweep's device error word is set (as in J).
 template <typename T, int C, int V, bool ABS>
 __global__ __launch_bounds__(256) void emergent_kernel(int64_t total, int32_t nl, int32_t ld, int64_t n,
                                                        const int32_t *__restrict__ em_ray,
                                                        const int32_t *__restrict__ em_site, const T *__restrict__ I,
-                                                       T *__restrict__ out) {
+                                                       T *__restrict__ out, const int32_t *__restrict__ err) {
   using L = Lane<T, V>;
   constexpr int SPW = 64 / C;
   const int lane = threadIdx.x & 63;
   const int64_t e = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * SPW + lane / C;
   if (e >= total) return;
+  const bool stale = ABS && err && *err != 0;
   const T *src = I + ((int64_t)em_ray[e] * n + em_site[e]) * ld;
   T *dst = out + e * nl;
   for (int32_t l = (lane % C) * V; l < nl; l += C * V) {
     auto x = L::load(src + l);
     if constexpr (ABS) {
 #pragma unroll
-      for (int k = 0; k < V; ++k) L::set(x, k, (T)__builtin_fabs((double)L::get(x, k)));
+      for (int k = 0; k < V; ++k)
+        L::set(x, k, stale ? (T)__builtin_nan("") : (T)__builtin_fabs((double)L::get(x, k)));
     }
     L::store(dst + l, x);
   }
@@ -215,24 +226,24 @@ __global__ __launch_bounds__(256) void emergent_kernel(int64_t total, int32_t nl
 
 template <typename T, int C, int V>
 void launch_ec(hipStream_t s, int64_t total, int32_t nl, int32_t ld, int64_t n, const int32_t *em_ray,
-               const int32_t *em_site, const T *I, T *out, bool ab) {
+               const int32_t *em_site, const T *I, T *out, bool ab, const int32_t *err) {
   constexpr int SPW = 64 / C;
   const int64_t blocks = (total + 4 * SPW - 1) / (4 * SPW);
   auto kern = ab ? emergent_kernel<T, C, V, true> : emergent_kernel<T, C, V, false>;
-  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, s, total, nl, ld, n, em_ray, em_site, I, out);
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, s, total, nl, ld, n, em_ray, em_site, I, out, err);
 }
 
 template <typename T, int V>
 void launch_ev(hipStream_t s, int64_t total, int32_t nl, int32_t ld, int64_t n, const int32_t *em_ray,
-               const int32_t *em_site, const T *I, T *out, bool ab) {
+               const int32_t *em_site, const T *I, T *out, bool ab, const int32_t *err) {
   switch (vrt::lanes_per_record(nl / V)) {
-    case 64: launch_ec<T, 64, V>(s, total, nl, ld, n, em_ray, em_site, I, out, ab); break;
-    case 32: launch_ec<T, 32, V>(s, total, nl, ld, n, em_ray, em_site, I, out, ab); break;
-    case 16: launch_ec<T, 16, V>(s, total, nl, ld, n, em_ray, em_site, I, out, ab); break;
-    case 8: launch_ec<T, 8, V>(s, total, nl, ld, n, em_ray, em_site, I, out, ab); break;
-    case 4: launch_ec<T, 4, V>(s, total, nl, ld, n, em_ray, em_site, I, out, ab); break;
-    case 2: launch_ec<T, 2, V>(s, total, nl, ld, n, em_ray, em_site, I, out, ab); break;
-    default: launch_ec<T, 1, V>(s, total, nl, ld, n, em_ray, em_site, I, out, ab); break;
+    case 64: launch_ec<T, 64, V>(s, total, nl, ld, n, em_ray, em_site, I, out, ab, err); break;
+    case 32: launch_ec<T, 32, V>(s, total, nl, ld, n, em_ray, em_site, I, out, ab, err); break;
+    case 16: launch_ec<T, 16, V>(s, total, nl, ld, n, em_ray, em_site, I, out, ab, err); break;
+    case 8: launch_ec<T, 8, V>(s, total, nl, ld, n, em_ray, em_site, I, out, ab, err); break;
+    case 4: launch_ec<T, 4, V>(s, total, nl, ld, n, em_ray, em_site, I, out, ab, err); break;
+    case 2: launch_ec<T, 2, V>(s, total, nl, ld, n, em_ray, em_site, I, out, ab, err); break;
+    default: launch_ec<T, 1, V>(s, total, nl, ld, n, em_ray, em_site, I, out, ab, err); break;
   }
 }
 
@@ -296,7 +307,8 @@ void launch_sweep(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *
 }
 
 template <typename T>
-void launch_jreduce(hipStream_t s, const T *I, int32_t R, int64_t nn, const double *w, T *J, bool abs_rows) {
+void launch_jreduce(hipStream_t s, const T *I, int32_t R, int64_t nn, const double *w, T *J, bool abs_rows,
+                    const int32_t *err) {
   if (nn == 0) return;
   const bool vec = nn % kVec<T> == 0 && aligned16(I) && aligned16(J);
   const int64_t items = vec ? nn / kVec<T> : nn;
@@ -304,18 +316,18 @@ void launch_jreduce(hipStream_t s, const T *I, int32_t R, int64_t nn, const doub
   if (blocks > 65536) blocks = 65536;
   auto kern = vec ? (abs_rows ? jreduce_kernel<T, kVec<T>, true> : jreduce_kernel<T, kVec<T>, false>)
                   : (abs_rows ? jreduce_kernel<T, 1, true> : jreduce_kernel<T, 1, false>);
-  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, s, I, R, nn, w, J);
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, s, I, R, nn, w, J, err);
   VRT_HIP(hipGetLastError());
 }
 
 template <typename T>
 void launch_emergent(hipStream_t s, int64_t total, int32_t nl, int32_t ld, int64_t n, const int32_t *em_ray,
-                     const int32_t *em_site, const T *I, T *out, bool abs_rows) {
+                     const int32_t *em_site, const T *I, T *out, bool abs_rows, const int32_t *err) {
   if (total == 0 || nl == 0) return;
   if (nl % kVec<T> == 0 && ld % kVec<T> == 0 && aligned16(I) && aligned16(out))
-    launch_ev<T, kVec<T>>(s, total, nl, ld, n, em_ray, em_site, I, out, abs_rows);
+    launch_ev<T, kVec<T>>(s, total, nl, ld, n, em_ray, em_site, I, out, abs_rows, err);
   else
-    launch_ev<T, 1>(s, total, nl, ld, n, em_ray, em_site, I, out, abs_rows);
+    launch_ev<T, 1>(s, total, nl, ld, n, em_ray, em_site, I, out, abs_rows, err);
   VRT_HIP(hipGetLastError());
 }
 
@@ -325,12 +337,13 @@ template void launch_sweep<float>(hipStream_t, const int4 *, const RecF32 *, int
 template void launch_sweep<double>(hipStream_t, const int4 *, const RecF64 *, int64_t, int64_t, int32_t, int64_t,
                                    const double *, const double *, const double *, const double *, double *, int32_t,
                                    int32_t, const int64_t *, int32_t, int32_t);
-template void launch_jreduce<float>(hipStream_t, const float *, int32_t, int64_t, const double *, float *, bool);
+template void launch_jreduce<float>(hipStream_t, const float *, int32_t, int64_t, const double *, float *, bool,
+                                    const int32_t *);
 template void launch_jreduce<double>(hipStream_t, const double *, int32_t, int64_t, const double *, double *,
-                                     bool);
+                                     bool, const int32_t *);
 template void launch_emergent<float>(hipStream_t, int64_t, int32_t, int32_t, int64_t, const int32_t *,
-                                     const int32_t *, const float *, float *, bool);
+                                     const int32_t *, const float *, float *, bool, const int32_t *);
 template void launch_emergent<double>(hipStream_t, int64_t, int32_t, int32_t, int64_t, const int32_t *,
-                                      const int32_t *, const double *, double *, bool);
+                                      const int32_t *, const double *, double *, bool, const int32_t *);
 
 }  // namespace vrt

@@ -5,9 +5,10 @@
 // Below x = 1/2 both come from their power series
 //   Psi_0 = sum_{n>=1} (-1)^(n+1) x^n/(n+1)!,  Psi_u = sum_{n>=1} (-1)^(n+1) n x^n/(n+1)!,
 // which removes the 0/0 at x = 0 and the cancellation of the closed form at
-// small x. The reverse sweep also needs the derivatives: dPsi_0/dx = Psi_u / x
-// (whose series is the Psi_u series divided by x) and dPsi_u/dx = e^-x -
-// dPsi_0/dx. Shared by the Voronoi, regular-grid and reverse sweeps.
+// small x (single precision forms Psi_u as x times the series of r - Psi_0/x,
+// r = (1 - e^-x)/x, which is the same series). The reverse sweep also needs
+// the derivatives: dPsi_0/dx = Psi_u / x (whose series is the Psi_u series
+// divided by x) and dPsi_u/dx = e^-x - dPsi_0/dx. Shared by the Voronoi, regular-grid and reverse sweeps.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -17,47 +18,51 @@ namespace vrt {
 template <typename T> struct Seg;
 
 template <> struct Seg<float> {
-  // ten terms: truncation below 1e-12 relative for x < 1/2
   static __device__ __forceinline__ void weights(float x, float &E, float &pu, float &p0) {
     float d0;
     weights(x, E, pu, p0, d0);
   }
-  // also d0 = dPsi_0/dx = Psi_u / x (then dPsi_u/dx = e^-x - d0)
+  // Branchless: both forms are evaluated and the lane selects one, because the
+  // lanes of a wavefront hold different wavelengths and sites and would
+  // otherwise run both sides of a branch one after the other. With
+  // r = (1 - e^-x)/x, Psi_0 = 1 - r and Psi_u = r - e^-x:
+  //  * x >= 1/2: e^-x from the hardware base-2 exponential of -x log2(e)
+  //    (relative error below 1e-6 for x < 10, where e^-x still matters) and
+  //    r = (1 - e^-x) times the hardware reciprocal of x;
+  //  * x < 1/2: Psi_0 = x P(x) and Psi_u = x (R(x) - P(x)) from the power
+  //    series P = sum_{n>=1} (-1)^(n+1) x^(n-1)/(n+1)! (seven terms) and
+  //    R = r = sum_{n>=0} (-1)^n x^n/(n+1)! (eight terms), truncated below
+  //    1e-8 relative, so that Psi_0 and Psi_u keep their relative accuracy as
+  //    x -> 0 (the closed form loses it to the cancellation in 1 - e^-x).
+  // Worst relative error of Psi_0 and Psi_u over all x: 5e-7 and 8.4e-7 (at
+  // x just above 1/2, from the rounding of e^-x).
+  // Also d0 = dPsi_0/dx = Psi_u/x (then dPsi_u/dx = e^-x - d0).
   static __device__ __forceinline__ void weights(float x, float &E, float &pu, float &p0, float &d0) {
-    if (x < 0.5f) {
-      // Psi_0 = sum_{n>=1} (-1)^(n+1) x^n/(n+1)!, Psi_u = sum (-1)^(n+1) n x^n/(n+1)!
-      const float a = 1.0f / 39916800.0f;  // 1/11!
-      float s0 = -a;
-      s0 = s0 * x + 1.0f / 3628800.0f;
-      s0 = s0 * x - 1.0f / 362880.0f;
-      s0 = s0 * x + 1.0f / 40320.0f;
-      s0 = s0 * x - 1.0f / 5040.0f;
-      s0 = s0 * x + 1.0f / 720.0f;
-      s0 = s0 * x - 1.0f / 120.0f;
-      s0 = s0 * x + 1.0f / 24.0f;
-      s0 = s0 * x - 1.0f / 6.0f;
-      s0 = s0 * x + 0.5f;
-      float su = -10.0f / 39916800.0f;
-      su = su * x + 9.0f / 3628800.0f;
-      su = su * x - 8.0f / 362880.0f;
-      su = su * x + 7.0f / 40320.0f;
-      su = su * x - 6.0f / 5040.0f;
-      su = su * x + 5.0f / 720.0f;
-      su = su * x - 4.0f / 120.0f;
-      su = su * x + 3.0f / 24.0f;
-      su = su * x - 2.0f / 6.0f;
-      su = su * x + 0.5f;
-      p0 = s0 * x;
-      pu = su * x;
-      d0 = su;
-      E = expf(-x);
-    } else {
-      E = expf(-x);
-      const float r = (1.0f - E) / x;
-      p0 = 1.0f - r;
-      pu = r - E;
-      d0 = pu / x;
-    }
+#pragma clang fp contract(off)
+    E = __builtin_amdgcn_exp2f(x * -1.44269504088896341f);
+    const float inv = __builtin_amdgcn_rcpf(x);
+    const float rc = (1.0f - E) * inv;
+    const float p0c = 1.0f - rc, puc = rc - E;
+    float P = 1.0f / 40320.0f;  // P = 1/2 - x/6 + x^2/24 - ... + x^6/8!
+    P = __builtin_fmaf(P, x, -1.0f / 5040.0f);
+    P = __builtin_fmaf(P, x, 1.0f / 720.0f);
+    P = __builtin_fmaf(P, x, -1.0f / 120.0f);
+    P = __builtin_fmaf(P, x, 1.0f / 24.0f);
+    P = __builtin_fmaf(P, x, -1.0f / 6.0f);
+    P = __builtin_fmaf(P, x, 0.5f);
+    float R = -1.0f / 40320.0f;  // R = 1 - x/2 + x^2/6 - ... - x^7/8!
+    R = __builtin_fmaf(R, x, 1.0f / 5040.0f);
+    R = __builtin_fmaf(R, x, -1.0f / 720.0f);
+    R = __builtin_fmaf(R, x, 1.0f / 120.0f);
+    R = __builtin_fmaf(R, x, -1.0f / 24.0f);
+    R = __builtin_fmaf(R, x, 1.0f / 6.0f);
+    R = __builtin_fmaf(R, x, -0.5f);
+    R = __builtin_fmaf(R, x, 1.0f);
+    const float Q = R - P;  // Psi_u / x
+    const bool s = x < 0.5f;
+    p0 = s ? x * P : p0c;
+    pu = s ? x * Q : puc;
+    d0 = s ? Q : puc * inv;
   }
 };
 
@@ -96,5 +101,27 @@ template <> struct Seg<double> {
     }
   }
 };
+
+// single-rounding multiply-add of either precision
+__device__ __forceinline__ float seg_fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double seg_fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// One line of the segment update (Eq. 2 with S linear along the line):
+// I = e^-x I_u + Psi_u S_u + Psi_0 S_0, rounded as
+// fma(e^-x, I_u, fma(Psi_u, S_u, Psi_0 S_0)). Every sweep forms its lines and
+// their Eq. 5 weighting with these two functions, with contraction off, so
+// that launch modes and lane layouts that share a record give the same bits.
+template <typename T> __device__ __forceinline__ T seg_line(T x, T Iu, T Su, T S0) {
+#pragma clang fp contract(off)
+  T E, pu, p0;
+  Seg<T>::weights(x, E, pu, p0);
+  return seg_fma(E, Iu, seg_fma(pu, Su, p0 * S0));
+}
+
+// Eq. 5 with two lines: w1 a + w2 b (w2 = 1 - w1), rounded as fma(w1, a, w2 b)
+template <typename T> __device__ __forceinline__ T seg_mix(T w1, T w2, T a, T b) {
+#pragma clang fp contract(off)
+  return seg_fma(w1, a, w2 * b);
+}
 
 }  // namespace vrt

@@ -49,6 +49,20 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (first processor entry of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+
+    return platform.processor() or "unknown"
+
+
 def sweep_bytes_per_update(nl: int, fp: int) -> float:
     """Algorithmic HBM bytes of the sweep kernel per site*ray*wavelength update:
     read S_i and chi_i, write I_i (3 * fp bytes), plus the per-(ray, site) sweep
@@ -435,7 +449,7 @@ def main():
             dt += time.perf_counter() - t0
             reps += 1
         cpu = {"value": reps * updates / dt, "unit": "site*ray*lambda updates/s",
-               "cores": oracle.num_threads(), "kind": "oracle",
+               "cores": oracle.num_threads(), "cpu_model": cpu_model(), "kind": "oracle",
                "sample": f"{reps} FP64 formal solution(s) of the full workload ({g.n} sites x {R} rays x {nl} "
                          f"wavelengths), {dt:.1f} s"}
         log(f"CPU oracle {cpu['value']:.3e} updates/s on {cpu['cores']} threads ({dt:.1f} s)")
@@ -503,7 +517,6 @@ def run_synthesis(v, G, Gr, g, atm, atr, nx, ny, zr, stream):
     depend on the values)."""
     import torch
 
-    import oracle
     from synth.nlte import LAMBDA0_NM, line_setup
 
     dev = "cuda:0"
@@ -513,14 +526,23 @@ def run_synthesis(v, G, Gr, g, atm, atr, nx, ny, zr, stream):
     t0 = time.time()
     line = line_setup(atr.T, atr.rho, n_lambda=nl, workers=16)
     lam0 = np.array([LAMBDA0_NM * 1e-9])
-    # the grey continuum at line centre is an input here, as in the tests
-    chi_c, B = oracle.lte(lam0, atr.kappa0, atr.T, atr.rho)
-    _, Bs = oracle.lte(lam0, atm.kappa0, atm.T, atm.rho)
-    S_line = Bs[:, 0] * (0.5 + np.random.default_rng(1048).random(g.n))
-    log(f"synthesis inputs built in {time.time() - t0:.1f} s")
     f64 = torch.float64
-    d = {k: torch.as_tensor(np.ascontiguousarray(a), dtype=f64, device=dev)
-         for k, a in (("S", S_line), ("chiL", line.chi_line), ("chic", chi_c[:, 0]), ("B", B[:, 0]))}
+
+    def continuum(grid, a):
+        """grey continuum opacity and B at line centre, assembled by the library on the device"""
+        n = len(a.T)
+        chi = torch.empty((n, 1), dtype=f64, device=dev)
+        B = torch.empty_like(chi)
+        v.lte_continuum(grid, lam0, a.kappa0, torch.as_tensor(a.T, device=dev), torch.as_tensor(a.rho, device=dev),
+                        chi, B)
+        return chi[:, 0].contiguous(), B[:, 0].contiguous()
+
+    chi_c, B = continuum(Gr, atr)
+    _, Bs = continuum(G, atm)
+    S_line = Bs * torch.as_tensor(0.5 + np.random.default_rng(1048).random(g.n), device=dev)
+    log(f"synthesis inputs built in {time.time() - t0:.1f} s")
+    d = {"S": S_line, "chiL": torch.as_tensor(np.ascontiguousarray(line.chi_line), dtype=f64, device=dev),
+         "chic": chi_c, "B": B}
     v.idw_map(G, Gr)  # first call pays one-time costs
     torch.cuda.synchronize()
     t0 = time.perf_counter()

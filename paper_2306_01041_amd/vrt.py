@@ -10,8 +10,11 @@ Importing this module fails loudly when the library has not been built.
 
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 
 import numpy as np
 
@@ -163,8 +166,29 @@ def validate_voronoi(n, xyz, nbr_ptr, nbr_idx, nbr_shift, wall, lo, hi, periodic
     return st, buf.value.decode()
 
 
+# Live contexts, closed (with their grids) by an exit hook while the HIP runtime
+# and torch's streams still exist. Garbage collection during interpreter
+# shutdown runs in no defined order relative to the runtime's own teardown, so
+# __del__ makes no library call once the interpreter is finalizing.
+_live_contexts = weakref.WeakSet()
+
+
+def _close_all_contexts():
+    for c in list(_live_contexts):
+        try:
+            c.close()
+        except Exception:
+            pass
+
+
+atexit.register(_close_all_contexts)
+
+
 class Context:
-    """A library context on one GPU, enqueuing on a HIP stream (default: torch's current stream)."""
+    """A library context on one GPU, enqueuing on a HIP stream (default: torch's current stream).
+
+    Close it with close() (or let the exit hook do it); a context that is
+    garbage-collected while the interpreter runs is closed then."""
 
     def __init__(self, device: int = 0, stream=None):
         import torch
@@ -178,6 +202,7 @@ class Context:
             raise VrtError(st, "vrt_ctx_create failed")
         self.handle = h
         self.device = device
+        _live_contexts.add(self)
 
     def check(self, st):
         if st < 0:
@@ -209,8 +234,11 @@ class Context:
         if self.handle:
             vrt_ctx_destroy(self.handle)
             self.handle = None
+        _live_contexts.discard(self)
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -305,6 +333,8 @@ class Grid:
         self.handle = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -212,6 +212,14 @@ vrt_status vrt_grid_set_rays(vrt_grid grid, int32_t n_rays, const double *dir, c
  *                           a die's chunk of a step is a region of the box
  *                           for every ray [0]. */
 #define VRT_TUNE_INTERLEAVE 10
+/*   VRT_TUNE_PIPELINE       0 = one group of records per wavefront in the
+ *                           level-step sweeps; 2, 4 or 8 = each wavefront
+ *                           sweeps that many consecutive groups, with the
+ *                           next groups' records and rows loaded while one is
+ *                           computed (16-byte lanes and rows of at most one
+ *                           lane-vector per lane; other layouts keep the
+ *                           classic kernel). Results are the same bits. */
+#define VRT_TUNE_PIPELINE 14
 /*   VRT_TUNE_SEGMENT        source model along a Delaunay line (Voronoi grids):
  *                           0 = linear (Sect. 2.5) [0]; 1 = quadratic Bezier
  *                           (the higher-order solver Sect. 2.5 points to, de

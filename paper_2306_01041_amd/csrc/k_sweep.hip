@@ -159,6 +159,94 @@ __global__ __launch_bounds__(256) void sweep_kernel_wide(
   sweep_body<T, C, V>(ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I, xcd_chunks, ray0, xtab, xk);
 }
 
+// Pipelined form of the same update for interior records (level steps >= 1:
+// step 0 holds exactly the boundary sites), for rows of at most C*V
+// wavelengths (one lane-vector per lane). A launch of classic wavefronts is
+// bound by latency, not by bandwidth or arithmetic: each wavefront runs one
+// dependent chain (its records, then the rows they name, then the update) and
+// ends, and with eight wavefronts per SIMD too few loads are in flight. Here a
+// wavefront sweeps Q consecutive groups of 64/C records, fully unrolled: the
+// records of group j + 2 and the rows of group j + 1 are issued before group j
+// is computed, so the in-order completion of vector loads lets each wait cover
+// only what it needs. The code has no branches between the loads and their
+// uses (both lines are always formed, then selected; records past the range and
+// lanes past the row clamp their loads to valid addresses and store the same
+// bits as the lane that owns the element), because a join of divergent paths
+// makes the compiler wait for every load in flight. The arithmetic per record is the classic kernel's: same bits.
+template <typename T, int C, int V, int Q>
+__global__ __launch_bounds__(256) void sweep_pipe_kernel(
+    const int4 *__restrict__ ri, const typename vrt::RecOf<T>::type *__restrict__ rf, int64_t rec_begin,
+    int64_t rec_count, int32_t nl, int64_t n, const T *__restrict__ chi, const T *__restrict__ S, T *I,
+    int32_t xcd_chunks) {
+  using L = Lane<T, V>;
+  using VT = typename L::type;
+  using RF = typename vrt::RecOf<T>::type;
+  constexpr int SPW = 64 / C;
+  const int lane = threadIdx.x & 63;
+  const int lv = (lane % C) * V;
+  const int l = lv < nl ? lv : nl - V;  // a lane past the row re-reads the last vector
+  const int64_t wave = chunked_block(xcd_chunks) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int64_t first = wave * (int64_t)(SPW * Q) + lane / C;
+  int4 q[Q];
+  RF f[Q];
+  VT ci[Q], si[Q], c1[Q], s1[Q], u1[Q], c2[Q], s2[Q], u2[Q];
+  auto load_rec = [&](int j) {
+    const int64_t r = first + (int64_t)j * SPW;
+    const int64_t rc = rec_begin + (r < rec_count ? r : rec_count - 1);
+    q[j] = ri[rc];
+    f[j] = rf[rc];
+  };
+  auto load_rows = [&](int j) {
+    // a missing second line reads the first again; indices are clamped so that
+    // no load leaves the arrays even for a record this kernel does not expect
+    const int32_t k1 = q[j].y > 0 ? q[j].y : 0;
+    const int32_t k2 = q[j].z >= 0 ? q[j].z : k1;
+    T *Iray = I + (int64_t)(q[j].w >> 1) * n * nl;
+    const int64_t bi = (int64_t)q[j].x * nl + l, b1 = (int64_t)k1 * nl + l, b2 = (int64_t)k2 * nl + l;
+    ci[j] = L::load(chi + bi);
+    si[j] = L::load(S + bi);
+    c1[j] = L::load(chi + b1);
+    s1[j] = L::load(S + b1);
+    u1[j] = L::load(Iray + b1);
+    c2[j] = L::load(chi + b2);
+    s2[j] = L::load(S + b2);
+    u2[j] = L::load(Iray + b2);
+  };
+  auto finish = [&](int j) {
+    const T w1 = f[j].w1, w2 = T(1) - f[j].w1;
+    const T h1 = T(0.5) * f[j].ds1, h2 = T(0.5) * f[j].ds2;
+    const bool two = q[j].z >= 0;
+    VT out;
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      const T cik = L::get(ci[j], k), sik = L::get(si[j], k);
+      const T Ia = vrt::seg_line<T>((L::get(c1[j], k) + cik) * h1, L::get(u1[j], k), L::get(s1[j], k), sik);
+      const T Ib = vrt::seg_line<T>((L::get(c2[j], k) + cik) * h2, L::get(u2[j], k), L::get(s2[j], k), sik);
+      const T Im = vrt::seg_mix<T>(w1, w2, Ia, Ib);
+      L::set(out, k, two ? Im : Ia);
+    }
+    // unconditional: a lane past the range holds the last record and a lane
+    // past the row the row's last vector, so it writes the very bits the
+    // owning lane writes (a guarded store would let the compiler sink this
+    // group's loads into the guard, after the previous group's compute)
+    L::store(I + (int64_t)(q[j].w >> 1) * n * nl + (int64_t)q[j].x * nl + l, out);
+  };
+  // scheduling barriers keep each stage's loads ahead of the previous group's
+  // arithmetic (left alone, the scheduler moves loads next to their uses to
+  // save registers, which serialises the groups again)
+  load_rec(0);
+  if (Q > 1) load_rec(1);
+  load_rows(0);
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    if (j + 2 < Q) load_rec(j + 2);
+    if (j + 1 < Q) load_rows(j + 1);
+    __builtin_amdgcn_sched_barrier(0);
+    finish(j);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
 // J = sum_r w_r I_r with double accumulation (ray order fixed); V elements per thread.
 // ABS reads sign-encoded rows (the persistent sweep's epoch sign) as |I|; if
 // the sweep's device error word is set, those rows are not this epoch's (the
@@ -249,11 +337,31 @@ void launch_ev(hipStream_t s, int64_t total, int32_t nl, int32_t ld, int64_t n, 
 
 // With a ray-affinity table, c is the largest record count of one die and the
 // grid holds that many records for every die.
+template <typename T, int C, int V, int Q>
+void launch_pipe(hipStream_t s, const int4 *ri, const typename vrt::RecOf<T>::type *rf, int64_t b, int64_t c,
+                 int32_t nl, int64_t n, const T *chi, const T *S, T *I, int32_t xc) {
+  constexpr int SPW = 64 / C;
+  const int64_t waves = (c + SPW * Q - 1) / (SPW * Q);
+  const int64_t blocks = (waves + 3) / 4;
+  hipLaunchKernelGGL((sweep_pipe_kernel<T, C, V, Q>), dim3((unsigned)blocks), dim3(256), 0, s, ri, rf, b, c, nl, n,
+                     chi, S, I, xc);
+}
+
 template <typename T, int C, int V>
 void launch_c(hipStream_t s, const int4 *ri, const typename vrt::RecOf<T>::type *rf, int64_t b, int64_t c, int32_t nl,
               int64_t n, const T *chi, const T *S, const T *Ibot, const T *Itop, T *I, int32_t xc, int32_t ray0,
-              const int64_t *xtab, int32_t xk) {
+              const int64_t *xtab, int32_t xk, int32_t pipe) {
   constexpr int SPW = 64 / C;
+  if constexpr (V * sizeof(T) == 16) {
+    // the pipelined kernel (pipe > 0 is passed only for interior level steps):
+    // per-ray rows from I (ray0 = 0), no affinity table, one lane-vector per lane
+    if (pipe > 0 && !xtab && ray0 == 0 && nl <= C * V) {
+      if (pipe >= 8) launch_pipe<T, C, V, 8>(s, ri, rf, b, c, nl, n, chi, S, I, xc);
+      else if (pipe >= 4) launch_pipe<T, C, V, 4>(s, ri, rf, b, c, nl, n, chi, S, I, xc);
+      else launch_pipe<T, C, V, 2>(s, ri, rf, b, c, nl, n, chi, S, I, xc);
+      return;
+    }
+  }
   const int64_t waves = (c + SPW - 1) / SPW;
   const int64_t blocks = xtab ? (int64_t)vrt::kDies * ((waves + 3) / 4) : (waves + 3) / 4;
   if constexpr (sizeof(T) != 4 || V * sizeof(T) > 16)
@@ -268,15 +376,15 @@ void launch_c(hipStream_t s, const int4 *ri, const typename vrt::RecOf<T>::type 
 template <typename T, int V>
 void launch_v(hipStream_t s, const int4 *ri, const typename vrt::RecOf<T>::type *rf, int64_t b, int64_t c, int32_t nl,
               int64_t n, const T *chi, const T *S, const T *Ibot, const T *Itop, T *I, int32_t xc, int32_t ray0,
-              const int64_t *xtab, int32_t xk) {
+              const int64_t *xtab, int32_t xk, int32_t pp) {
   const int32_t m = nl / V;
-  if (m >= 33) launch_c<T, 64, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk);
-  else if (m >= 17) launch_c<T, 32, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk);
-  else if (m >= 9) launch_c<T, 16, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk);
-  else if (m >= 5) launch_c<T, 8, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk);
-  else if (m >= 3) launch_c<T, 4, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk);
-  else if (m == 2) launch_c<T, 2, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk);
-  else launch_c<T, 1, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk);
+  if (m >= 33) launch_c<T, 64, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk, pp);
+  else if (m >= 17) launch_c<T, 32, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk, pp);
+  else if (m >= 9) launch_c<T, 16, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk, pp);
+  else if (m >= 5) launch_c<T, 8, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk, pp);
+  else if (m >= 3) launch_c<T, 4, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk, pp);
+  else if (m == 2) launch_c<T, 2, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk, pp);
+  else launch_c<T, 1, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk, pp);
 }
 
 // 16-byte lane vectors when the row length allows (and rows then stay 16-byte aligned)
@@ -292,17 +400,19 @@ namespace vrt {
 template <typename T>
 void launch_sweep(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *rf, int64_t rec_begin,
                   int64_t rec_count, int32_t nl, int64_t n, const T *chi, const T *S, const T *Ibot, const T *Itop,
-                  T *I, int32_t xcd_chunks, int32_t ray0, const int64_t *xtab, int32_t xk, int32_t lane_bytes) {
+                  T *I, int32_t xcd_chunks, int32_t ray0, const int64_t *xtab, int32_t xk, int32_t lane_bytes,
+                  int32_t pipe) {
   if (rec_count <= 0) return;
   const bool aligned = aligned16(chi) && aligned16(S) && aligned16(Ibot) && aligned16(Itop) && aligned16(I);
   const bool aligned32 = aligned32p(chi) && aligned32p(S) && aligned32p(Ibot) && aligned32p(Itop) && aligned32p(I);
   if (lane_bytes == 32 && aligned32 && nl % (2 * kVec<T>) == 0)
     launch_v<T, 2 * kVec<T>>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I, xcd_chunks, ray0, xtab,
-                             xk);
+                             xk, 0);
   else if (aligned && nl % kVec<T> == 0)
-    launch_v<T, kVec<T>>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I, xcd_chunks, ray0, xtab, xk);
+    launch_v<T, kVec<T>>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I, xcd_chunks, ray0, xtab, xk,
+                         pipe);
   else
-    launch_v<T, 1>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I, xcd_chunks, ray0, xtab, xk);
+    launch_v<T, 1>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I, xcd_chunks, ray0, xtab, xk, 0);
   VRT_HIP(hipGetLastError());
 }
 
@@ -333,10 +443,10 @@ void launch_emergent(hipStream_t s, int64_t total, int32_t nl, int32_t ld, int64
 
 template void launch_sweep<float>(hipStream_t, const int4 *, const RecF32 *, int64_t, int64_t, int32_t, int64_t,
                                   const float *, const float *, const float *, const float *, float *, int32_t,
-                                  int32_t, const int64_t *, int32_t, int32_t);
+                                  int32_t, const int64_t *, int32_t, int32_t, int32_t);
 template void launch_sweep<double>(hipStream_t, const int4 *, const RecF64 *, int64_t, int64_t, int32_t, int64_t,
                                    const double *, const double *, const double *, const double *, double *, int32_t,
-                                   int32_t, const int64_t *, int32_t, int32_t);
+                                   int32_t, const int64_t *, int32_t, int32_t, int32_t);
 template void launch_jreduce<float>(hipStream_t, const float *, int32_t, int64_t, const double *, float *, bool,
                                     const int32_t *);
 template void launch_jreduce<double>(hipStream_t, const double *, int32_t, int64_t, const double *, double *,

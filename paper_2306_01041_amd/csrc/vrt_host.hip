@@ -519,6 +519,29 @@ void ensure_flags(vrt_grid g) {
   VRT_HIP(hipMemsetAsync(g->d_epoch.p, 0, 64, g->ctx->stream));
 }
 
+// Reads and acknowledges the persistent sweeps' device error word (callers
+// synchronise the stream first). A set word clears the word and the layout
+// key of the sign-encoded rows, so those rows are refilled with zeros of the
+// current epoch's sign before their next use: a sweep that stopped early or did
+// not run left rows of an older sign, which a later epoch of the same sign
+// would otherwise read as written. Value 2 (a negative or NaN intensity that
+// the sign encoding cannot carry) is reported as VRT_E_NUMERIC, value 1 (a
+// bounded wait gave up) as VRT_E_TIMEOUT; `iter` > 0 names the iteration.
+void take_device_error(vrt_grid g, int32_t iter) {
+  if (!g->d_epoch.p) return;
+  int32_t err = 0;
+  VRT_HIP(hipMemcpy(&err, g->d_epoch.as<int32_t>() + 1, 4, hipMemcpyDeviceToHost));
+  if (err == 0) return;
+  VRT_HIP(hipMemset(g->d_epoch.as<int32_t>() + 1, 0, 4));
+  for (int k = 0; k < 4; ++k) g->sgn_key[k] = 0;
+  char at[48] = "";
+  if (iter > 0) snprintf(at, sizeof at, " at iteration %d", iter);
+  if (err & 2)
+    fail(VRT_E_NUMERIC, "negative or NaN intensity in the sign-encoded persistent sweep%s (it needs I >= 0; pass "
+                        "I_rays or use another execution mode for such inputs)", at);
+  fail(VRT_E_TIMEOUT, "a bounded wait of the persistent sweep gave up%s (spin cap %lld)", at, (long long)g->spin_cap);
+}
+
 // Wave items of the persistent sweep for `spw` records per wave: every
 // (level step, ray) segment is cut separately, so no item holds two levels
 // of one ray or two rays; cnt holds the record count + 256 x the ray.
@@ -609,16 +632,19 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
     const int4 *ri = g->d_ri.as<int4>();
     const auto *rf = records<T>(g);
     const int32_t xc = g->xcd_chunks;
-    auto sweep = [&](int64_t b, int64_t c) {
+    // level step st of the step-major records; the pipelined kernel takes the
+    // interior steps (st >= 1) of the step-wide modes
+    auto sweep = [&](int32_t st, int64_t b, int64_t c) {
       if (c <= 0) return;
+      const int32_t pp = (ex == VRT_EXEC_PLAIN || st == 0) ? 0 : g->pipe;
       timed_launch(ctx, s, tm, 0, c * nl, [&] {
-        vrt::launch_sweep<T>(s, ri, rf, b, c, nl, n, chi, S, Ib, It, I, xc, 0, nullptr, 0, g->lane_bytes);
+        vrt::launch_sweep<T>(s, ri, rf, b, c, nl, n, chi, S, Ib, It, I, xc, 0, nullptr, 0, g->lane_bytes, pp);
       });
     };
     if (ex == VRT_EXEC_PLAIN) {
       for (int32_t r = 0; r < R; ++r)
         for (int32_t st = 0; st < g->n_levels[(size_t)r]; ++st)
-          sweep(g->seg_off[(size_t)st * R + r], g->seg_cnt[(size_t)st * R + r]);
+          sweep(st, g->seg_off[(size_t)st * R + r], g->seg_cnt[(size_t)st * R + r]);
     } else if (g->ray_affinity) {
       const int64_t *xt = g->d_xtab.as<int64_t>();
       const size_t per = (size_t)vrt::kDies * g->xk * 2;
@@ -648,7 +674,7 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
           timed_launch(ctx, sc, tm, 0, (e - b) * nl,
                        [&] {
                          vrt::launch_sweep<T>(sc, ri, rf, b, e - b, nl, n, chi, S, Ib, It, I, xc, 0, nullptr, 0,
-                                              g->lane_bytes);
+                                              g->lane_bytes, st > 0 ? g->pipe : 0);
                        });
         }
       }
@@ -665,7 +691,7 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
         for (int32_t st = 0; st < g->n_steps; ++st) {
           const int64_t b = g->seg_off[(size_t)st * R + r0];
           const int64_t e = g->seg_off[(size_t)st * R + r1 - 1] + g->seg_cnt[(size_t)st * R + r1 - 1];
-          sweep(b, e - b);
+          sweep(st, b, e - b);
         }
       }
     } else {
@@ -679,7 +705,8 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
         const int64_t b = g->step_ptr[(size_t)st], c = g->step_ptr[(size_t)st + 1] - b;
         if (c <= 0) continue;
         timed_launch(ctx, s, tm, 0, c * nl, [&] {
-          vrt::launch_sweep<T>(s, rix, rfx, b, c, nl, n, chi, S, Ib, It, I, xc, 0, nullptr, 0, g->lane_bytes);
+          vrt::launch_sweep<T>(s, rix, rfx, b, c, nl, n, chi, S, Ib, It, I, xc, 0, nullptr, 0, g->lane_bytes,
+                               st > 0 ? g->pipe : 0);
         });
       }
     }
@@ -709,7 +736,10 @@ void enqueue_fs(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *chi
   const int32_t R = g->R;
   const int64_t n = g->n;
   timed_launch(ctx, s, tm, 1, (int64_t)R * n * nl,
-               [&] { vrt::launch_jreduce<T>(s, I, R, n * nl, g->d_w.as<double>(), J, sign); });
+               [&] {
+                 vrt::launch_jreduce<T>(s, I, R, n * nl, g->d_w.as<double>(), J, sign,
+                                        sign ? g->d_epoch.as<int32_t>() + 1 : nullptr);
+               });
 }
 
 // Per-ray dependents lists: for every site k, the sites d whose forward update
@@ -1008,14 +1038,7 @@ vrt_status two_level_solve(vrt_grid g, vrt_exec ex, int32_t nl, const double *wl
       enqueue_lambda_step<T>(g, s, ex, nl, ld, phi, chi_L, chi_c, B, eps, S_L, I, n_atm, Lbar);
     VRT_HIP(hipMemcpyAsync(g->h_dS, g->d_dS.p, (size_t)n_atm * 8, hipMemcpyDeviceToHost, s));
     VRT_HIP(hipStreamSynchronize(s));
-    if (pexec) {
-      int32_t err = 0;
-      VRT_HIP(hipMemcpy(&err, g->d_epoch.as<int32_t>() + 1, 4, hipMemcpyDeviceToHost));
-      if (err) {
-        VRT_HIP(hipMemset(g->d_epoch.as<int32_t>() + 1, 0, 4));
-        fail(VRT_E_TIMEOUT, "a bounded wait of the persistent sweep gave up at iteration %d", it + 1);
-      }
-    }
+    if (pexec) take_device_error(g, it + 1);
     bool changed = false;
     for (int32_t a = 0; a < n_atm; ++a) {
       double d = -1.0;
@@ -1410,6 +1433,9 @@ vrt_status vrt_grid_tune(vrt_grid g, int32_t knob, int64_t value) {
     } else if (knob == VRT_TUNE_REVERSE_PERSISTENT) {
       if (value != 0 && value != 1) fail(VRT_E_ARG, "reverse persistent must be 0 or 1");
       g->reverse_persistent = (int)value;
+    } else if (knob == VRT_TUNE_PIPELINE) {
+      if (value != 0 && value != 2 && value != 4 && value != 8) fail(VRT_E_ARG, "pipeline depth must be 0, 2, 4 or 8");
+      g->pipe = (int)value;
     } else if (knob == VRT_TUNE_LANE_BYTES) {
       if (value != 16 && value != 32) fail(VRT_E_ARG, "lane bytes must be 16 or 32");
       g->lane_bytes = (int)value;
@@ -1748,16 +1774,7 @@ vrt_status vrt_grid_device_status(vrt_grid g) {
   if (!g) return VRT_E_ARG;
   return guarded(g->ctx, [&] {
     VRT_HIP(hipStreamSynchronize(g->ctx->stream));
-    if (!g->d_epoch.p) return VRT_OK;
-    int32_t err = 0;
-    VRT_HIP(hipMemcpy(&err, g->d_epoch.as<int32_t>() + 1, 4, hipMemcpyDeviceToHost));
-    if (err == 0) return VRT_OK;
-    VRT_HIP(hipMemset(g->d_epoch.as<int32_t>() + 1, 0, 4));
-    for (int k = 0; k < 4; ++k) g->sgn_key[k] = 0;  // the sign-encoded rows are refilled before their next use
-    if (err & 2)
-      fail(VRT_E_NUMERIC, "negative or NaN intensity in the sign-encoded persistent sweep (it needs I >= 0; pass "
-                          "I_rays or use another execution mode for such inputs)");
-    fail(VRT_E_TIMEOUT, "a bounded wait of the persistent sweep gave up (spin cap %lld)", (long long)g->spin_cap);
+    take_device_error(g, 0);
     return VRT_OK;
   });
 }
@@ -1790,14 +1807,15 @@ vrt_status vrt_emergent_gather(vrt_grid g, vrt_prec prec, int32_t n_lambda, cons
     }
     const int64_t total = g->em_off.back();
     if (total > 0 && !out) fail(VRT_E_ARG, "null output");
+    const int32_t *err = ab ? g->d_epoch.as<int32_t>() + 1 : nullptr;
     if (prec == VRT_F32)
       vrt::launch_emergent<float>(g->ctx->stream, total, n_lambda, ld, g->n, g->d_em_ray.as<int32_t>(),
                                   g->d_em_site.as<int32_t>(), static_cast<const float *>(I), static_cast<float *>(out),
-                                  ab);
+                                  ab, err);
     else
       vrt::launch_emergent<double>(g->ctx->stream, total, n_lambda, ld, g->n, g->d_em_ray.as<int32_t>(),
                                    g->d_em_site.as<int32_t>(), static_cast<const double *>(I),
-                                   static_cast<double *>(out), ab);
+                                   static_cast<double *>(out), ab, err);
     return VRT_OK;
   });
 }

@@ -185,6 +185,7 @@ struct vrt_grid_s {
   int lane_bytes = 16;   // bytes of a row each lane moves per access (16 or 32)
   int ray_groups = 1;    // the rays are swept in this many consecutive passes
   int interleave = 0;    // 1: step-wide sweeps read a copy of the records ordered by position across rays
+  int pipe = 0;          // > 0: level-step sweeps use the pipelined kernel with this many record groups per wave
   int segment = 0;       // 0: linear source along a line, 1: quadratic Bezier (needs the downwind lines)
   int reverse_persistent = 0;  // 1: the reverse sweep of a ray group runs as one persistent launch
   std::map<int64_t, std::unique_ptr<vrt::PersistItems>> reverse_items;  // keyed by (spw, first ray, group)
@@ -276,18 +277,27 @@ void launch_pack(hipStream_t s, int64_t n, int32_t R, int32_t Lmax, const int32_
 // ---- k_sweep.hip
 // I holds the rays from ray0 on (ray r writes I + (r - ray0) * n * nl). With
 // xtab (one step's ray-affinity table [kDies][xk][2]), rec_count is the
-// largest record count of one die and rec_begin is unused.
+// largest record count of one die and rec_begin is unused. pipe > 0: each
+// wavefront sweeps pipe (2, 4 or 8) groups of records with the next groups'
+// loads in flight (16-byte lanes, rows of at most one lane-vector per lane,
+// ray0 = 0, no affinity table; otherwise the classic kernel runs). The
+// pipelined kernel updates interior records only: pass pipe > 0 for level
+// steps >= 1 (step 0 holds exactly the boundary sites).
 template <typename T>
 void launch_sweep(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *rf, int64_t rec_begin,
                   int64_t rec_count, int32_t nl, int64_t n, const T *chi, const T *S, const T *Ibot,
                   const T *Itop, T *I, int32_t xcd_chunks, int32_t ray0, const int64_t *xtab = nullptr,
-                  int32_t xk = 0, int32_t lane_bytes = 16);
+                  int32_t xk = 0, int32_t lane_bytes = 16, int32_t pipe = 0);
+// abs_rows: I holds sign-encoded rows (read as |I|); then err is the persistent
+// sweep's device error word, and a set word makes the outputs NaN (the rows
+// are not the current epoch's)
 template <typename T>
 void launch_jreduce(hipStream_t s, const T *I, int32_t R, int64_t nn, const double *w, T *J,
-                    bool abs_rows = false);
+                    bool abs_rows = false, const int32_t *err = nullptr);
 template <typename T>
 void launch_emergent(hipStream_t s, int64_t total, int32_t nl, int32_t ld, int64_t n, const int32_t *em_ray,
-                     const int32_t *em_site, const T *I, T *out, bool abs_rows = false);
+                     const int32_t *em_site, const T *I, T *out, bool abs_rows = false,
+                     const int32_t *err = nullptr);
 
 // ---- k_source.hip
 template <typename T>

@@ -14,6 +14,8 @@ times (FP32 sweeps, graph-launched and persistent, default launch layout):
   oracle's gradient;
 * one two-level Lambda iteration on the 1,048,576-site grid with the
   101-point line, against the oracle's iteration;
+* on the 262,144- and 1,048,576-site grids, every ray's upwind sites, levels,
+  sweep order and level pointers bit for bit against the oracle;
 * the final synthesis from the 262,144-site grid to the regular 128 x 128 x
   256 grid with the 101-point line: the nearest sites of 4,096 sampled points
   bit for bit and the mu = 1 emergent intensity of 64 sampled columns;
@@ -67,6 +69,30 @@ def c1():
     return atm, g, dirs, w, sel
 
 
+def _check_schedules(G, g, dirs, sel):
+    """Integer work bit for bit against the oracle for every ray: the two
+    upwind sites of every site, its level, the sweep order and the level
+    pointers, with the fallback count and the deepest level; the line weight
+    and lengths as in the small-grid test (1e-13, 1e-15)."""
+    t0 = time.time()
+    lev, order, ptrs, nlev = oracle.levels(g, dirs, sel)
+    flush(f"  oracle levels for {len(dirs)} rays in {time.time() - t0:.1f} s")
+    info = G.info()
+    assert info["n_fallback"] == int(sel.n_fallback.sum())
+    assert info["max_levels"] == int(nlev.max())
+    for r in range(len(dirs)):
+        s = G.schedule(r)
+        assert np.array_equal(s["k1"], sel.k1[r]), r
+        assert np.array_equal(s["k2"], sel.k2[r]), r
+        assert np.array_equal(s["level"], lev[r]), r
+        assert np.array_equal(s["order"], order[r]), r
+        assert np.array_equal(s["level_ptr"], ptrs[r]), r
+        assert relerr(s["w1"], sel.w1[r]) <= 1e-13, r
+        assert relerr(s["ds1"], sel.ds1[r]) <= 1e-15, r
+        assert relerr(s["ds2"], sel.ds2[r]) <= 1e-15, r
+    flush(f"  schedules of {len(dirs)} rays bit-exact ({int(nlev.max())} levels at most)")
+
+
 def test_c1_voronoi_full_size(v, ctx, c1):
     atm, g, dirs, w, sel = c1
     nl = 64
@@ -81,6 +107,7 @@ def test_c1_voronoi_full_size(v, ctx, c1):
     del Io
     G = v.Grid.from_synth(ctx, g)
     G.set_rays(dirs, w)
+    _check_schedules(G, g, dirs, sel)
     T, rho = to_dev(atm.T, torch.float64), to_dev(atm.rho, torch.float64)
     prev = None
     for dt, mode, tol_J, tol_I in ((torch.float32, v.VRT_EXEC_GRAPH, 1e-5, 1e-4),
@@ -266,11 +293,12 @@ def test_c2_one_iteration_full_size(v, ctx):
     st, nit, hist = v.two_level_solve(G, line.wlam, to_dev(line.phi, d), to_dev(line.chi_line, d), chi_c, B, eps, S,
                                       max_iter=1, tol=0.0, sweep_dtype=torch.float32)
     torch.cuda.synchronize()
+    sel = oracle.select(g, dirs)
+    _check_schedules(G, g, dirs, sel)
     G.close()
     flush("  oracle FP64 iteration (1,048,576 sites x 24 rays x 101 wavelengths)")
     t0 = time.time()
     chi_co, B_o = oracle.lte(lam0, atm.kappa0, atm.T, atm.rho)
-    sel = oracle.select(g, dirs)
     S_o, hist_o, _, _ = onl.lambda_iterate(g, dirs, w, sel, chi_co[:, 0], line.chi_line, line.phi, line.wlam,
                                            B_o[:, 0], eps, max_iter=1, tol=0.0)
     flush(f"  oracle done in {time.time() - t0:.1f} s")

@@ -475,6 +475,59 @@ def test_persistent_sign_encoding_rejects_negative_intensities(v, ctx, quad, gri
     G.close()
 
 
+def test_persistent_error_state_is_never_stale(v, ctx, quad, grids):
+    """An error left by a sign-encoded sweep must never let later results come
+    from rows of an older epoch. After a sweep with negative intensities
+    (unacknowledged), a second sign-encoded solution does not run: its J and
+    emergent intensities come back as NaN rather than as the previous rows. A
+    persistent two-level solve then reports the pending error with its own
+    code (numeric, not a timeout) and acknowledges it, and the next valid
+    sign-encoded solution equals the graph-launched one bit for bit."""
+    from synth.nlte import LAMBDA0_NM, line_setup
+
+    flush("persistent error state: sign-encoded, then two-level")
+    atm, g = grids[16384]
+    dirs, w = quad
+    G = _gpu_grid(v, ctx, g, dirs, w)
+    chi_o, S_o = _fields(atm, 8, 23)
+    f = torch.float32
+    chi, S = to_dev(chi_o, f), to_dev(S_o, f)
+    Jg = torch.empty_like(chi)
+    v.formal_solution(G, chi, S, Jg, exec_mode=v.VRT_EXEC_GRAPH)
+    em_g = torch.empty((G.emergent_index()[0][-1], 8), dtype=f, device="cuda:0")
+    v.emergent_gather(G, em_g)
+    J = torch.empty_like(chi)
+    v.formal_solution(G, chi, -S, J, exec_mode=v.VRT_EXEC_PERSISTENT)  # sets the numeric error
+    assert bool(torch.isnan(J).all())
+    v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_PERSISTENT)  # error still pending: does not run
+    torch.cuda.synchronize()
+    assert bool(torch.isnan(J).all())
+    em = torch.empty_like(em_g)
+    v.emergent_gather(G, em)
+    torch.cuda.synchronize()
+    assert bool(torch.isnan(em).all())
+    # a persistent two-level solve reports the pending error as numeric
+    line = line_setup(atm.T, atm.rho, n_lambda=9)
+    d = torch.float64
+    chi_c = torch.empty((g.n, 1), dtype=d, device="cuda:0")
+    B = torch.empty_like(chi_c)
+    v.lte_continuum(G, np.array([LAMBDA0_NM * 1e-9]), atm.kappa0, to_dev(atm.T, d), to_dev(atm.rho, d), chi_c, B)
+    chi_c, B = chi_c[:, 0].contiguous(), B[:, 0].contiguous()
+    S_L = B.clone()
+    with pytest.raises(v.VrtError) as e:
+        v.two_level_solve(G, line.wlam, to_dev(line.phi, d), to_dev(line.chi_line, d), chi_c, B, 1e-2, S_L,
+                          max_iter=3, tol=1e-3, sweep_dtype=f, exec_mode=v.VRT_EXEC_PERSISTENT)
+    assert e.value.status == v.VRT_E_NUMERIC
+    G.device_status()  # acknowledged by the solve
+    for _ in range(3):
+        v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_PERSISTENT)
+        G.device_status()
+        assert torch.equal(J, Jg)
+        v.emergent_gather(G, em)
+        assert torch.equal(em, em_g)
+    G.close()
+
+
 def test_persistent_bounded_wait_reports_timeout(v, ctx, quad, grids):
     """A spin bound of zero polls makes the first unmet wait give up: the kernel
     still drains, the device status reports a timeout once, and the next

@@ -128,9 +128,14 @@ def main():
     ap.add_argument("--accel", action="store_true",
                     help="c2/c3: the Jacobi-accelerated iteration (local operator) instead of the plain one")
     ap.add_argument("--max-iter", type=int, default=None,
-                    help="iteration cap of the c2/c3 Lambda iterations (default 1000 for c2, 100 for c3)")
+                    help="iteration cap of the timed plain c2/c3 Lambda iterations (default 20 for c2, 10 for c3; "
+                         "the accelerated iteration runs to convergence)")
     ap.add_argument("--mode", choices=["auto", "graph", "batched", "persistent"], default="auto",
                     help="launch mode of the timed steps (auto: the faster of graph and persistent)")
+    ap.add_argument("--workers", type=int, default=16,
+                    help="processes that build the c3 batch's atmospheres (1: in this process, e.g. under a profiler)")
+    ap.add_argument("--no-lambda", action="store_true",
+                    help="default run: skip the c2 and c3 two-level iteration blocks")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (to scale HBM counters) and exit")
     args = ap.parse_args()
@@ -365,8 +370,10 @@ def main():
             return fw_ms, bw_ms
 
         u4 = g.n * R * nl4
-        # the reverse sweep as level-step launches and as one persistent launch;
-        # the faster is reported as the adjoint time
+        # the default pipeline (FP32 sweeps, the misfit's emergent intensities
+        # from an FP64 forward sweep: gradients within 1e-4 of central
+        # differences); the reverse sweep as level-step launches and as one
+        # persistent launch, the faster reported as the adjoint time
         fw_l, bw_l = timed(None)
         G.tune(v.VRT_TUNE_REVERSE_PERSISTENT, 1)
         try:
@@ -378,23 +385,23 @@ def main():
         reverse_mode = "persistent" if bw_p < bw_l else "level steps"
         G.tune(v.VRT_TUNE_REVERSE_PERSISTENT, 1 if bw_p < bw_l else 0)
         fw_ms, bw_ms = (fw_p, bw_p) if bw_p < bw_l else (fw_l, bw_l)
-        fw2, bw2 = timed(torch.float64)
+        fw2, bw2 = timed(torch.float32)  # all-FP32
         G.tune(v.VRT_TUNE_REVERSE_PERSISTENT, 0)
         adjoint = {"workload": f"adjoint of the LTE formal solution, {g.n} sites, {nl4} wavelengths 500-700 nm, "
-                               f"{R} rays, FP32 sweeps, FP64 ray accumulation, loss sum (I_em - I_target)^2",
+                               f"{R} rays, FP32 sweeps, FP64 ray accumulation, loss sum (I_em - I_target)^2 with "
+                               f"I_em from an FP64 forward sweep (gradient within 1e-4 of central differences)",
                    "forward_ms": round(fw_ms, 3), "adjoint_ms": round(bw_ms, 3),
                    "adjoint_over_forward": round(bw_ms / fw_ms, 3), "reverse_sweep": reverse_mode,
                    "adjoint_ms_by_reverse_sweep": {"level steps": round(bw_l, 3),
                                                    "persistent": None if bw_p == float("inf") else round(bw_p, 3)},
                    "forward_updates_per_s": u4 / (fw_ms * 1e-3), "adjoint_updates_per_s": u4 / (bw_ms * 1e-3),
-                   "fp64_emergent": {"note": "misfit from an FP64 forward sweep, FP32 reverse sweep with its own "
-                                             "FP32 forward recompute (gradient within 1e-4 of central differences)",
-                                     "forward_ms": round(fw2, 3), "adjoint_ms": round(bw2, 3),
-                                     "adjoint_over_forward": round(bw2 / fw2, 3)},
+                   "all_fp32": {"note": "misfit from the FP32 forward sweep (faster forward; gradient within "
+                                        "2e-3 of central differences when the residuals are small)",
+                                "forward_ms": round(fw2, 3), "adjoint_ms": round(bw2, 3),
+                                "adjoint_over_forward": round(bw2 / fw2, 3)},
                    "grad_finite": bool(torch.isfinite(Tq.grad).all() and torch.isfinite(rq.grad).all())}
         log(f"adjoint: forward {fw_ms:.3f} ms, backward {bw_ms:.3f} ms ({reverse_mode}; level steps {bw_l:.3f}, "
-            f"persistent {bw_p:.3f}), ratio {bw_ms / fw_ms:.2f}; with FP64 emergent intensities: {fw2:.3f} / "
-            f"{bw2:.3f} ms")
+            f"persistent {bw_p:.3f}), ratio {bw_ms / fw_ms:.2f}; all-FP32: {fw2:.3f} / {bw2:.3f} ms")
         del Tq, rq, target, T_tgt
 
     # the regular 128 x 128 x 256 grid of the same recipe (short characteristics):
@@ -492,10 +499,16 @@ def main():
         "tuning": tuning,
         "layout": {k: layout.get(k) for k in LAYOUT_KEYS},
     }
-    print(json.dumps(out))
     G.close()
     ctx.close()
-    del stream
+    del stream, T, rho, em
+    torch.cuda.empty_cache()
+    # the two-level iteration workloads, whose sweeps read more than the 256 MB
+    # of the last-level cache holds: 1,048,576 sites, and 48 atmospheres in one batch
+    if not args.no_lambda:
+        out["c2"] = lambda_block("c2", max_iter=20, accel_iter=1000, workers=args.workers)
+        out["c3"] = lambda_block("c3", max_iter=5, accel_iter=200, workers=args.workers)
+    print(json.dumps(out))
 
 
 def synthesis_bytes(m, ncol, nl, fp):
@@ -740,48 +753,68 @@ def run_design(args):
     print(json.dumps(out))
 
 
-def _make_grid(args):
-    """One seeded atmosphere, its Voronoi grid and its line profile (module
-    level, for the process pool)."""
-    import synth
-    from synth.nlte import line_setup
+def lambda_counter_traffic(workload, mode):
+    """HBM bytes per formal solution's sweep launches (rocprofv3 FETCH_SIZE x
+    its copy-kernel calibration + WRITE_SIZE, summed over the launches of one
+    formal solution) from the committed summary of this workload, or None when
+    it was taken on another launch mode or on kernel sources that have changed
+    since."""
+    import hashlib
 
-    n, seed = args
-    atm = synth.make_atmosphere(n, seed=seed)
-    g = synth.voronoi_neighbours(atm.xyz, atm.box.lo, atm.box.hi)
-    line = line_setup(atm.T, atm.rho, n_lambda=101)
-    return atm, g, line
+    path = os.path.join(ROOT, "profiles", f"sweep_{workload}_counters.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("launch_mode") != mode:
+        return None
+    h = hashlib.sha256()
+    for f in rec.get("sources", []):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest()[:16] != rec.get("source_sha256_16"):
+        return None
+    return rec["sweep_bytes_per_formal_solution"]["total"]
 
 
-def run_lambda(args):
+def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", interleave=False, workers=16):
     """Two-level Lambda iteration on 1,048,576 sites (c2) or on a batch of 48
-    atmospheres of 32,768-524,288 sites (c3): 101 line wavelengths, 24 rays,
-    eps = 1e-4, FP32 sweeps, FP64 line update, graph-captured iterations, to
-    max |dS|/S < 1e-3. Reports the time per iteration, the iteration counts,
-    the formal solution's share of an iteration and its update rate."""
-    import multiprocessing as mp
-
+    atmospheres of 32,768-524,288 sites (c3): 101 line wavelengths (rows padded
+    to 104), 24 rays, eps = 1e-4, FP32 sweeps, FP64 line update, graph-captured
+    iterations. Times the formal solution alone in the iteration's layout (the
+    launch mode that is faster of graph and persistent), a bounded number of
+    plain iterations, and the accelerated (Jacobi) iteration to convergence;
+    returns the block's dictionary, with the roofline of the formal solution on
+    two byte bases: the whole-solution model (20 B + 20 B / Nlambda per update:
+    read S and chi, write I, read-modify-write J) over the whole formal
+    solution, and the sweep kernel's own bytes (read S_i and chi_i, write I_i,
+    the record shared by the wavelengths) over the sweep launches alone."""
     import torch
 
     import paper_2306_01041_amd
     import synth
-    from synth.nlte import LAMBDA0_NM
+    from synth.nlte import LAMBDA0_NM, line_case
 
     v = paper_2306_01041_amd.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
     seed = 1041
     t0 = time.time()
-    if args.workload == "c2":
+    if workload == "c2":
         jobs = [(1048576, seed)]
     else:
         # atmosphere j of the batch uses seed + 1 + j
         jobs = [(n, seed + 1 + j) for j, n in enumerate(synth.batch_sizes(48, 32768, 524288, seed))]
-    with mp.get_context("spawn").Pool(min(16, len(jobs))) as pool:
-        made = []
-        for k, r in enumerate(pool.imap(_make_grid, jobs)):
-            made.append(r)
-            log(f"atmosphere {k + 1}/{len(jobs)}: {r[1].n} sites")
+    made = []
+    if len(jobs) == 1 or workers <= 1:
+        for k, job in enumerate(jobs):
+            made.append(line_case(job))
+            log(f"atmosphere {k + 1}/{len(jobs)}: {made[-1][1].n} sites")
+    else:
+        import multiprocessing as mp
+
+        with mp.get_context("spawn").Pool(min(workers, len(jobs))) as pool:
+            for k, r in enumerate(pool.imap(line_case, jobs)):
+                made.append(r)
+                log(f"atmosphere {k + 1}/{len(jobs)}: {r[1].n} sites")
     atms = [m[0] for m in made]
     grids = [m[1] for m in made]
     lines = [m[2] for m in made]
@@ -798,19 +831,19 @@ def run_lambda(args):
     del lines
     dirs, w = synth.gauss_legendre_quadrature()
     R = len(dirs)
-    log(f"{len(grids)} atmosphere(s), {U.n} sites, inputs built in {time.time() - t0:.1f} s")
+    build_s = time.time() - t0
+    log(f"{workload}: {len(grids)} atmosphere(s), {U.n} sites, inputs built in {build_s:.1f} s")
 
     ctx = v.Context(0)
+    stream = torch.cuda.current_stream()
     G = v.Grid.from_synth(ctx, U)
     t0 = time.time()
     G.set_rays(dirs, w)
     setup_s = time.time() - t0
     info = G.info()
     log(f"rays set in {setup_s:.2f} s: {info}")
-    if args.interleave:
-        t0 = time.time()
+    if interleave:
         G.tune(v.VRT_TUNE_INTERLEAVE, 1)
-        log(f"interleaved record copy built in {time.time() - t0:.2f} s")
     d = torch.float64
     lam0 = np.array([LAMBDA0_NM * 1e-9])
     # one continuum constant for the batch (a recipe constant)
@@ -826,13 +859,12 @@ def run_lambda(args):
     # (16-byte multiples) with the continuum in the padding; only the 101 line
     # wavelengths count as updates
     f32 = torch.float32
-    S_L = B.clone()
     ld = (nl + 3) // 4 * 4
     chi = torch.empty((U.n, ld), dtype=f32, device=dev)
     S = torch.empty_like(chi)
     chi[:, :nl] = chi_c[:, None] + chi_L[:, None] * phi
-    S[:, :nl] = (chi_L[:, None] * phi * S_L[:, None] + chi_c[:, None] * B[:, None]) / (chi_c[:, None] +
-                                                                                   chi_L[:, None] * phi)
+    S[:, :nl] = (chi_L[:, None] * phi * B[:, None] + chi_c[:, None] * B[:, None]) / (chi_c[:, None] +
+                                                                                 chi_L[:, None] * phi)
     chi[:, nl:] = chi_c[:, None]
     S[:, nl:] = B[:, None]
     J = torch.empty_like(chi)
@@ -840,71 +872,114 @@ def run_lambda(args):
     # faster of those that run; the persistent sweep refuses rays above 4 GiB)
     modes = {"graph": v.VRT_EXEC_GRAPH, "batched": v.VRT_EXEC_BATCHED, "persistent": v.VRT_EXEC_PERSISTENT}
     fs_by_mode = {}
-    for name in (("graph", "persistent") if args.mode == "auto" else (args.mode,)):
+    for name in (("graph", "persistent") if mode_pref == "auto" else (mode_pref,)):
         try:
             for _ in range(2):
                 v.formal_solution(G, chi, S, J, exec_mode=modes[name])
             torch.cuda.synchronize()
             k = 5
-            t1 = time.perf_counter()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
             for _ in range(k):
                 v.formal_solution(G, chi, S, J, exec_mode=modes[name])
-            torch.cuda.synchronize()
+            e1.record(stream)
+            e1.synchronize()
             G.device_status()
-            fs_by_mode[name] = (time.perf_counter() - t1) * 1e3 / k
+            fs_by_mode[name] = e0.elapsed_time(e1) / k
         except v.VrtError as e:
             log(f"launch mode {name} not used: {e}")
     mode_name = min(fs_by_mode, key=fs_by_mode.get)
     fs_ms = fs_by_mode[mode_name]
-    del chi, S, J
-    updates = U.n * R * nl
-    log(f"formal solution (ms by launch mode): {fs_by_mode} -> {mode_name}: {fs_ms:.3f} ms, "
-        f"{updates / (fs_ms * 1e-3):.3e} updates/s")
-
-    # the iteration to convergence (or the cap)
-    max_iter = args.max_iter if args.max_iter is not None else (1000 if args.workload == "c2" else 100)
-    log(f"Lambda iteration, at most {max_iter} iterations")
-    t1 = time.perf_counter()
-    st, its, hist = v.two_level_solve_batched(G, off, wlam, phi, chi_L, chi_c, B, eps, S_L,
-                                              max_iter=max_iter, tol=1e-3, sweep_dtype=f32,
-                                              exec_mode=modes[mode_name], accel=args.accel)
+    # the angle quadrature of J on its own (one eager launch, HIP events on the library stream)
+    ctx.profile_reset()
+    ctx.set_profiling(True)
+    v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_BATCHED)
+    jr_ms, jr_launches, _ = ctx.profile(1)
+    sw_ms_b, sw_launches, _ = ctx.profile(0)
+    ctx.set_profiling(False)
     torch.cuda.synchronize()
-    total_s = time.perf_counter() - t1
-    n_iter = int(np.max(its))
-    it_ms = total_s * 1e3 / max(n_iter, 1)
-    log(f"Lambda iteration: status {st}, iterations {np.min(its)}..{n_iter}, {it_ms:.3f} ms per iteration, "
-        f"{total_s:.2f} s in total")
+    jr_one = jr_ms / max(jr_launches, 1)
+    sweep_ms = fs_ms - jr_one
+    launches = 1 if mode_name == "persistent" else sw_launches
+    updates = U.n * R * nl
+    upd_s = updates / (fs_ms * 1e-3)
+    whole_bpu = 20.0 + 20.0 / nl
+    sweep_bpu = sweep_bytes_per_update(nl, 4) * ld / nl  # the sweep moves ld-entry rows
+    sweep_gbs = sweep_bpu * updates / (sweep_ms * 1e-3) / 1e9
+    traffic = lambda_counter_traffic(workload, mode_name)
+    del chi, S, J
+    log(f"{workload}: formal solution (ms by launch mode): {fs_by_mode} -> {mode_name}: {fs_ms:.3f} ms, "
+        f"{upd_s:.3e} updates/s; sweep {sweep_ms:.3f} ms ({sweep_gbs:.0f} GB/s own bytes), J {jr_one:.3f} ms")
+
+    # plain iterations (timing) and the accelerated iteration to convergence
+    res_it = {}
+    for name, acc, cap in (("plain", False, max_iter), ("accelerated", True, accel_iter)):
+        S_L = B.clone()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st, its, hist = v.two_level_solve_batched(G, off, wlam, phi, chi_L, chi_c, B, eps, S_L, max_iter=cap,
+                                                  tol=1e-3, sweep_dtype=f32, exec_mode=modes[mode_name],
+                                                  accel=acc)
+        torch.cuda.synchronize()
+        total_s = time.perf_counter() - t1
+        n_iter = int(np.max(its))
+        it_ms = total_s * 1e3 / max(n_iter, 1)
+        # each atmosphere's change at its own last iteration (the history holds -1 after it stopped)
+        last = np.array([hist[its[a] - 1, a] for a in range(len(its))]) if n_iter else np.zeros(0)
+        res_it[name] = {"ms_per_iteration": round(it_ms, 3), "iterations": {"min": int(np.min(its)), "max": n_iter,
+                                                                              "median": float(np.median(its)),
+                                                                              "cap": cap},
+                        "converged": bool(st == v.VRT_OK),
+                        "atmospheres_converged": int(np.sum(last < 1e-3)),
+                        "final_change": {"min": float(np.min(last)), "max": float(np.max(last))},
+                        "solve_s": round(total_s, 3)}
+        log(f"{workload} {name} iteration: status {st}, iterations {np.min(its)}..{n_iter}, {it_ms:.3f} ms per "
+            f"iteration, {total_s:.2f} s")
     out = {
-        "metric": "site*ray*lambda updates/s of the formal solution inside the two-level Lambda iteration",
-        "value": updates / (fs_ms * 1e-3),
-        "unit": "site*ray*lambda updates/s",
-        "n_gpus": 1,
-        "higher_is_better": True,
-        "dtype": "f32",
-        "data": "synthetic (seeded Bifrost-like stratified atmospheres, rejection-sampled Voronoi sites)",
-        "config": {"workload": (("accelerated (Jacobi) " if args.accel else "") + "two-level Lambda iteration, " +
-                                (f"{U.n} sites" if len(grids) == 1 else
-                                 f"{len(grids)} atmospheres, {U.n} sites in total") +
-                                f", {nl} line wavelengths, {R} rays, eps {eps}, FP32 sweeps, FP64 update"),
-                   "sites": U.n, "atmospheres": len(grids), "wavelengths": nl, "rays": R,
-                   "levels_max": info["max_levels"]},
-        "formal_solution_ms": round(fs_ms, 3),
-        "launch_mode": mode_name,
+        "workload": (f"two-level Lambda iteration, " +
+                     (f"{U.n} sites" if len(grids) == 1 else f"{len(grids)} atmospheres, {U.n} sites in total") +
+                     f", {nl} line wavelengths, {R} rays, eps {eps}, FP32 sweeps, FP64 update"),
+        "sites": U.n, "atmospheres": len(grids), "wavelengths": nl, "rays": R, "levels_max": info["max_levels"],
+        "formal_solution_ms": round(fs_ms, 3), "updates_per_s": upd_s, "launch_mode": mode_name,
         "formal_solution_ms_by_mode": {k: round(t, 3) for k, t in fs_by_mode.items()},
-        "ms_per_iteration": round(it_ms, 3),
-        "formal_solution_share": round(fs_ms / it_ms, 3),
-        "iterations": {"min": int(np.min(its)), "max": n_iter, "median": float(np.median(its)), "cap": max_iter},
-        "converged": bool(st == v.VRT_OK),
-        "atmospheres_converged": int(np.sum(its < max_iter) + np.sum((its == max_iter) & (hist[-1] < 1e-3))),
-        "final_change": {"min": float(np.min(hist[-1])), "max": float(np.max(hist[-1]))},
-        "solve_s": round(total_s, 3),
-        "setup_s": round(setup_s, 3),
-        "whole_step_effective_GBs": round(updates * (20.0 + 20.0 / nl) / (fs_ms * 1e-3) / 1e9, 1),
-        "interleaved_records": bool(args.interleave),
+        "roofline": {
+            "bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "whole_solution": {"bytes_per_update": round(whole_bpu, 3),
+                               "achieved": round(upd_s * whole_bpu / 1e9, 1),
+                               "frac": round(upd_s * whole_bpu / 1e9 / HBM_PEAK_GBS, 4)},
+            "sweep_kernel": {"kernel": ("persistent_sweep_kernel<float,32,4,true>" if mode_name == "persistent"
+                                        else "sweep_kernel<float,32,4>"),
+                             "bytes_per_update": round(sweep_bpu, 3), "sweep_ms": round(sweep_ms, 3),
+                             "launches": launches, "achieved": round(sweep_gbs, 1),
+                             "frac": round(sweep_gbs / HBM_PEAK_GBS, 4),
+                             "traffic": None if traffic is None else round(traffic),
+                             "traffic_over_algorithmic": None if traffic is None else
+                             round(traffic / (sweep_bpu * updates), 3)},
+            "j_quadrature_ms": round(jr_one, 3)},
+        "formal_solution_share": round(fs_ms / res_it["plain"]["ms_per_iteration"], 3),
+        "iteration": res_it,
+        "inputs_build_s": round(build_s, 1), "setup_s": round(setup_s, 3),
+        "interleaved_records": bool(interleave),
     }
-    print(json.dumps(out))
     G.close()
     ctx.close()
+    del phi, chi_L, chi_c, B
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_lambda(args):
+    """The c2 / c3 workloads alone: one JSON line with the block's figures."""
+    out = lambda_block(args.workload, max_iter=args.max_iter or (20 if args.workload == "c2" else 10),
+                       accel_iter=1000 if args.workload == "c2" else 200, mode_pref="auto" if args.mode == "auto"
+                       else args.mode, interleave=args.interleave, workers=args.workers)
+    line = {"metric": "site*ray*lambda updates/s of the formal solution inside the two-level Lambda iteration",
+            "value": out["updates_per_s"], "unit": "site*ray*lambda updates/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "f32",
+            "data": "synthetic (seeded Bifrost-like stratified atmospheres, rejection-sampled Voronoi sites)",
+            "config": {"workload": out["workload"], "sites": out["sites"], "atmospheres": out["atmospheres"]}}
+    line.update(out)
+    print(json.dumps(line))
 
 
 if __name__ == "__main__":

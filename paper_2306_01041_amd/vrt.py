@@ -581,20 +581,25 @@ def lte_emergent(T, rho, grid: Grid, lam, kappa0, dtype=None, keep_intensities=T
                  emergent_dtype=None):
     """Differentiable emergent intensities [n_emergent, nl] (see LTEEmergent).
 
-    dtype is the precision of the sweeps (float32 by default). With
-    emergent_dtype=torch.float64 and float32 sweeps, the returned intensities
-    come from a double-precision forward sweep, so that a misfit whose residuals
-    are small against the intensities is formed accurately; the reverse sweep
-    still runs in single precision (it recomputes its own single-precision
-    forward intensities).
+    dtype is the precision of the sweeps (float32 by default). emergent_dtype
+    is the precision of the forward sweep whose intensities are returned; by
+    default float64 when the sweeps are float32: a misfit's residuals are often
+    a fraction of a percent of the intensities, and a single-precision forward
+    sweep's ~1e-6 rounding would then reach the gradient at ~1e-4. The reverse
+    sweep still runs in single precision on its own single-precision forward
+    intensities. Pass emergent_dtype=torch.float32 for an all-single-precision
+    pipeline (faster forward, gradients good to ~1e-3 of central differences
+    in that regime).
     """
     import torch
 
     global _LTE_EMERGENT
     if _LTE_EMERGENT is None:
         _LTE_EMERGENT = _make_lte_emergent()
-    return _LTE_EMERGENT.apply(T, rho, grid, lam, kappa0, torch.float32 if dtype is None else dtype,
-                               keep_intensities, ray_group, emergent_dtype)
+    dtype = torch.float32 if dtype is None else dtype
+    if emergent_dtype is None:
+        emergent_dtype = torch.float64 if dtype == torch.float32 else dtype
+    return _LTE_EMERGENT.apply(T, rho, grid, lam, kappa0, dtype, keep_intensities, ray_group, emergent_dtype)
 
 
 # ----------------------------------------------------------------------------

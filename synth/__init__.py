@@ -19,6 +19,7 @@ from .atmosphere import (
     horizontal_field,
     kappa0_and_density,
     sample_sites,
+    locality_order,
     make_atmosphere,
 )
 from .voronoi import VoronoiGrid, voronoi_neighbours, lattice_grid, check_symmetric, concat_grids
@@ -33,6 +34,7 @@ __all__ = [
     "horizontal_field",
     "kappa0_and_density",
     "sample_sites",
+    "locality_order",
     "make_atmosphere",
     "VoronoiGrid",
     "voronoi_neighbours",

@@ -117,33 +117,67 @@ def kappa0_and_density(box: BoxSpec = BoxSpec(), n_z: int = 300001):
     return kappa0, z, f
 
 
-def sample_sites(n: int, seed: int, box: BoxSpec = BoxSpec(), uniform: bool = False, batch: int = 1 << 20):
+def _spread_bits(v, bits=16):
+    """Interleave the low `bits` bits of v with zeros (bit b moves to bit 2b)."""
+    v = v.astype(np.uint64)
+    out = np.zeros_like(v)
+    for b in range(bits):
+        out |= ((v >> np.uint64(b)) & np.uint64(1)) << np.uint64(2 * b)
+    return out
+
+
+def locality_order(xyz, box: BoxSpec = BoxSpec()):
+    """Permutation that numbers sites the way a block-structured container
+    visits them: horizontal slabs one mean site spacing thick, bottom to top,
+    and inside a slab the Morton (Z-order) curve of (x, y) on a 2^16 x 2^16
+    lattice of the box. Sites that are close in space get close numbers, so
+    [site][wavelength] rows that one level of a sweep touches lie close
+    together in memory. Stable: ties keep the sampling order."""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    n = len(xyz)
+    if n == 0:
+        return np.zeros(0, np.int64)
+    lo = np.asarray(box.lo, dtype=np.float64)
+    L = box.L
+    h = float(np.prod(L) / n) ** (1.0 / 3.0)
+    slab = np.floor((xyz[:, 2] - lo[2]) / h).astype(np.int64)
+    q = np.clip(np.floor((xyz[:, :2] - lo[:2]) / L[:2] * 65536.0), 0, 65535).astype(np.int64)
+    morton = _spread_bits(q[:, 0]) | (_spread_bits(q[:, 1]) << np.uint64(1))
+    return np.lexsort((morton, slab))
+
+
+def sample_sites(n: int, seed: int, box: BoxSpec = BoxSpec(), uniform: bool = False, batch: int = 1 << 20,
+                 ordered: bool = True):
     """Rejection-sample n sites (Sect. 2.4, four steps).
 
     1. propose a position uniformly in the box and evaluate the target density
        there; 2. draw a uniform rejection level in [0, f_max); 3. accept if the
        proposal density is at least the rejection level; 4. repeat until n
        sites are accepted. With ``uniform=True`` every proposal is accepted
-       (the searchlight test samples sites uniformly).
+       (the searchlight test samples sites uniformly). With ``ordered`` (the
+       default) the accepted sites are numbered in ``locality_order``;
+       otherwise in the order they were accepted.
     Returns float64 [n, 3].
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     lo = np.asarray(box.lo, dtype=np.float64)
     L = box.L
     if uniform:
-        return lo + rng.random((n, 3)) * L
-    _, zt, ft = kappa0_and_density(box)
-    fmax = ft.max()
-    out = []
-    got = 0
-    while got < n:
-        prop = lo + rng.random((batch, 3)) * L
-        fp = np.interp(prop[:, 2], zt, ft)
-        u = rng.random(batch) * fmax
-        acc = prop[fp >= u]
-        out.append(acc)
-        got += len(acc)
-    return np.concatenate(out)[:n]
+        xyz = lo + rng.random((n, 3)) * L
+    else:
+        _, zt, ft = kappa0_and_density(box)
+        fmax = ft.max()
+        out = []
+        got = 0
+        while got < n:
+            prop = lo + rng.random((batch, 3)) * L
+            fp = np.interp(prop[:, 2], zt, ft)
+            u = rng.random(batch) * fmax
+            acc = prop[fp >= u]
+            out.append(acc)
+            got += len(acc)
+        xyz = np.concatenate(out)[:n]
+    return np.ascontiguousarray(xyz[locality_order(xyz, box)]) if ordered else xyz
 
 
 @dataclass

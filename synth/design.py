@@ -22,7 +22,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .atmosphere import BoxSpec, T0_of_z, horizontal_field, rho_of_z, sample_field
+from .atmosphere import BoxSpec, T0_of_z, horizontal_field, locality_order, rho_of_z, sample_field
 
 M_H = 1.6735575e-27     # kg
 M_E = 9.1093837015e-31  # kg
@@ -61,7 +61,8 @@ def sample_sites_density(n: int, seed: int, name: str, box: BoxSpec = BoxSpec(),
     """Rejection-sample n sites from ``target_density(name)`` (Sect. 2.4): propose
     uniformly, draw the rejection level uniformly in [0, f_max), accept when
     f(proposal) >= level. f_max is 1.05 times the largest f over 2^20 seeded
-    probe points and the z-axis extremes."""
+    probe points and the z-axis extremes. Sites are numbered in
+    ``locality_order``, as ``sample_sites`` numbers them."""
     rng = np.random.Generator(np.random.PCG64(seed))
     lo = np.asarray(box.lo, np.float64)
     L = box.L
@@ -76,7 +77,8 @@ def sample_sites_density(n: int, seed: int, name: str, box: BoxSpec = BoxSpec(),
         acc = prop[target_density(name, prop, box, field_seed) >= rng.random(batch) * fmax]
         out.append(acc)
         got += len(acc)
-    return np.concatenate(out)[:n]
+    xyz = np.concatenate(out)[:n]
+    return np.ascontiguousarray(xyz[locality_order(xyz, box)])
 
 
 def searchlight(n_side: int = 51, seed: int = 1041, radius: float = 0.2, theta_deg: float = 20.0):

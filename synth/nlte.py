@@ -90,3 +90,17 @@ def line_setup(T, rho, n_lambda: int = 101, damping: float = 0.01, half_width: f
     K_L = 1.0 / (phi0 * float(rho_of_z(1.5 * MM)) * H_RHO)
     return LineSetup(lam_nm=lam, wlam=wl, phi=np.ascontiguousarray(phi), chi_line=K_L * rho, K_L=K_L,
                      damping=damping)
+
+
+def line_case(job):
+    """One seeded atmosphere of the two-level workloads with its Voronoi grid and
+    line data: job = (n_sites, seed) -> (Atmosphere, VoronoiGrid, LineSetup with
+    101 wavelengths). A module-level function, so a process pool can build the
+    atmospheres of a batch in parallel."""
+    from .atmosphere import make_atmosphere
+    from .voronoi import voronoi_neighbours
+
+    n, seed = job
+    atm = make_atmosphere(n, seed=seed)
+    g = voronoi_neighbours(atm.xyz, atm.box.lo, atm.box.hi)
+    return atm, g, line_setup(atm.T, atm.rho, n_lambda=101)

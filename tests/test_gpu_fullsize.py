@@ -16,6 +16,9 @@ times (FP32 sweeps, graph-launched and persistent, default launch layout):
   101-point line, against the oracle's iteration;
 * on the 262,144- and 1,048,576-site grids, every ray's upwind sites, levels,
   sweep order and level pointers bit for bit against the oracle;
+* one Lambda iteration of the 48-atmosphere batch (about 10 million sites,
+  FP32 sweeps, graph-launched), four atmospheres against standalone oracle
+  iterations;
 * the final synthesis from the 262,144-site grid to the regular 128 x 128 x
   256 grid with the 101-point line: the nearest sites of 4,096 sampled points
   bit for bit and the mu = 1 emergent intensity of 64 sampled columns;
@@ -185,11 +188,13 @@ def test_c1_regular_full_size(v, ctx):
 
 
 def test_c4_adjoint_full_size(v, ctx, c1):
-    """Three pipelines: FP64 sweeps; FP32 sweeps; FP32 sweeps with the emergent
-    intensities of the misfit from an FP64 forward sweep. The FP32 reverse sweep
-    itself is accurate to ~1e-7, but with FP32 emergent intensities the misfit
-    residuals (a few tenths of a percent of the intensity) carry the forward
-    sweep's ~1e-6 rounding, which reaches the gradient as a few 1e-5 normwise."""
+    """Three pipelines: FP64 sweeps; FP32 sweeps with the emergent intensities
+    of the misfit from an FP64 forward sweep (the default of lte_emergent with
+    FP32 sweeps, and the pipeline the benchmark times); all-FP32 (emergent
+    intensities from the FP32 forward sweep). The FP32 reverse sweep itself is
+    accurate to ~1e-7, but with FP32 emergent intensities the misfit residuals
+    (a few tenths of a percent of the intensity) carry the forward sweep's ~1e-6
+    rounding, which reaches the gradient as a few 1e-5 normwise."""
     atm, g, dirs, w, sel = c1
     nl = 32
     lam = np.linspace(500e-9, 700e-9, nl)
@@ -211,7 +216,7 @@ def test_c4_adjoint_full_size(v, ctx, c1):
     with torch.no_grad():
         tgt64 = v.lte_emergent(to_dev(T_tgt, f64), rho, G, lam, atm.kappa0, dtype=f64).double()[up_t]
     grads = {}
-    for name, dt, edt in (("f64", f64, None), ("f32", f32, None), ("f32+em64", f32, f64)):
+    for name, dt, edt in (("f64", f64, None), ("f32", f32, f32), ("f32+em64", f32, None)):
         flush(f"c4 adjoint, GPU {name}")
         Tq = T.clone().requires_grad_(True)
         rq = rho.clone().requires_grad_(True)
@@ -263,11 +268,13 @@ def test_c4_adjoint_full_size(v, ctx, c1):
     G.close()
     assert abs(L64 - Lo) <= 1e-10 * abs(Lo)
     assert max(vs_oracle["f64"]) <= 1e-10
-    # the 1e-4 target against central differences, with FP64 and with FP32 sweeps
+    # the 1e-4 target against central differences, with FP64 sweeps and with
+    # the default FP32-sweep pipeline (the one the benchmark times)
     assert max(worst["f64"].values()) <= 1e-4
     assert max(worst["f32+em64"].values()) <= 1e-4
     assert max(vs_oracle["f32+em64"]) <= 1e-5
-    # FP32 emergent intensities in the misfit: bounded by the forward rounding
+    # all-FP32 (emergent intensities of the misfit in FP32): bounded by the
+    # forward rounding
     assert max(norms["f32"]) <= 1e-4
     assert max(worst["f32"].values()) <= 2e-3
 
@@ -307,6 +314,70 @@ def test_c2_one_iteration_full_size(v, ctx):
     assert nit == 1 and st == v.VRT_W_NOT_CONVERGED
     assert e <= 1e-5
     assert abs(hist[0] - hist_o[0]) <= 3e-5
+
+
+def test_c3_batch_one_iteration_full_size(v, ctx):
+    """The 48-atmosphere batch (32,768-524,288 sites each, log-uniform, seeds
+    1042..1089; about 10 million sites in one grid), one plain Lambda iteration
+    with FP32 sweeps in the graph-launched mode the benchmark times, against
+    standalone oracle iterations of four of its atmospheres (the smallest, the
+    largest and two seeded picks): S_line to 1e-5, atmosphere by atmosphere."""
+    import multiprocessing as mp
+
+    from synth.nlte import line_case
+
+    flush("c3: building the 48 atmospheres of the batch")
+    t0 = time.time()
+    sizes = synth.batch_sizes(48, 32768, 524288, SEED)
+    jobs = [(n, SEED + 1 + j) for j, n in enumerate(sizes)]
+    with mp.get_context("spawn").Pool(16) as pool:
+        made = list(pool.imap(line_case, jobs))
+    atms = [m[0] for m in made]
+    grids = [m[1] for m in made]
+    lines = [m[2] for m in made]
+    del made
+    U, off = synth.concat_grids(grids)
+    flush(f"  {U.n} sites in {time.time() - t0:.1f} s")
+    dirs, w = synth.gauss_legendre_quadrature()
+    lam0 = np.array([LAMBDA0_NM * 1e-9])
+    eps = 1e-4
+    d = torch.float64
+    G = v.Grid.from_synth(ctx, U)
+    G.set_rays(dirs, w)
+    T = np.concatenate([a.T for a in atms])
+    rho = np.concatenate([a.rho for a in atms])
+    chi_c = torch.empty((U.n, 1), dtype=d, device="cuda:0")
+    B = torch.empty_like(chi_c)
+    v.lte_continuum(G, lam0, atms[0].kappa0, to_dev(T, d), to_dev(rho, d), chi_c, B)
+    chi_c, B = chi_c[:, 0].contiguous(), B[:, 0].contiguous()
+    phi = torch.empty((U.n, 101), dtype=d, device="cuda:0")
+    for a, ln in enumerate(lines):
+        phi[off[a]:off[a + 1]].copy_(torch.as_tensor(ln.phi))
+    chi_L = to_dev(np.concatenate([ln.chi_line for ln in lines]), d)
+    S = B.clone()
+    flush("  GPU: one iteration of the whole batch (FP32 sweeps, graph)")
+    st, its, hist = v.two_level_solve_batched(G, off, lines[0].wlam, phi, chi_L, chi_c, B, eps, S, max_iter=1,
+                                              tol=0.0, sweep_dtype=torch.float32, exec_mode=v.VRT_EXEC_GRAPH)
+    torch.cuda.synchronize()
+    S = S.cpu().numpy()
+    G.close()
+    del phi, chi_L, chi_c, B
+    assert st == v.VRT_W_NOT_CONVERGED and np.all(its == 1)
+    rng = np.random.Generator(np.random.PCG64(SEED))
+    rest = [a for a in range(48) if a not in (int(np.argmin(sizes)), int(np.argmax(sizes)))]
+    pick = [int(np.argmin(sizes)), int(np.argmax(sizes))] + [int(a) for a in rng.choice(rest, 2, replace=False)]
+    for a in pick:
+        g, atm, ln = grids[a], atms[a], lines[a]
+        t0 = time.time()
+        chi_co, B_o = oracle.lte(lam0, atm.kappa0, atm.T, atm.rho)
+        sel = oracle.select(g, dirs)
+        S_o, h_o, _, _ = onl.lambda_iterate(g, dirs, w, sel, chi_co[:, 0], ln.chi_line, ln.phi, ln.wlam, B_o[:, 0],
+                                            eps, max_iter=1, tol=0.0)
+        e = relerr(S[off[a]:off[a + 1]], S_o)
+        flush(f"  atmosphere {a} ({g.n} sites): max rel err of S_line {e:.3e}, change GPU {hist[0, a]:.6e} "
+              f"oracle {h_o[0]:.6e} (oracle {time.time() - t0:.1f} s)")
+        assert e <= 1e-5
+        assert abs(hist[0, a] - h_o[0]) <= 3e-5
 
 
 def test_c1_synthesis_full_size(v, ctx, c1):

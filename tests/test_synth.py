@@ -257,3 +257,33 @@ def test_design_densities_order_the_heights():
     zc = np.median(design.sample_sites_density(20000, 3, "alpha_c")[:, 2])
     zl = np.median(design.sample_sites_density(20000, 3, "log_nh_t")[:, 2])
     assert zc < 0.0 < zl
+
+
+def test_locality_order_numbers_sites_by_slab_then_morton():
+    """Generated sites come numbered slab by slab (one mean spacing thick,
+    bottom to top) and along the Morton curve of (x, y) inside a slab; the set
+    of sites is the accepted sample itself, only renumbered."""
+    box = synth.BoxSpec()
+    raw = synth.sample_sites(5000, seed=44, ordered=False)
+    xyz = synth.sample_sites(5000, seed=44)
+    perm = synth.locality_order(raw, box)
+    assert np.array_equal(np.sort(perm), np.arange(len(raw)))
+    assert np.array_equal(xyz, raw[perm])
+    lo, L = np.asarray(box.lo), box.L
+    h = float(np.prod(L) / len(xyz)) ** (1 / 3)
+    slab = np.floor((xyz[:, 2] - lo[2]) / h).astype(np.int64)
+    assert np.all(np.diff(slab) >= 0)
+    q = np.clip(np.floor((xyz[:, :2] - lo[:2]) / L[:2] * 65536.0), 0, 65535).astype(np.int64)
+
+    def morton(ix, iy):
+        m = 0
+        for b in range(16):
+            m |= ((ix >> b) & 1) << (2 * b) | ((iy >> b) & 1) << (2 * b + 1)
+        return m
+
+    keys = [(int(s_), morton(int(a), int(b))) for s_, (a, b) in zip(slab, q)]
+    assert keys == sorted(keys)
+    # neighbours in the numbering are neighbours in space: the mean distance
+    # between consecutive sites is a few spacings, not a box size
+    step = np.linalg.norm(np.diff(xyz, axis=0), axis=1)
+    assert np.median(step) < 3 * h

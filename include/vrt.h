@@ -306,6 +306,25 @@ vrt_status vrt_formal_solution(vrt_grid grid, vrt_prec prec, vrt_exec exec, int3
                                const void *chi, const void *S, const void *I_bottom,
                                const void *I_top, void *J, void *I_rays);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * formal solution as vrt_formal_solution in the VRT_EXEC_BATCHED mode (the
+ * same kernels, so the same J bit for bit), with the per-ray intensities in a
+ * static device buffer of the library (64 MiB per GPU, held until the process
+ * ends) instead of memory allocated on first use. Calls no hipMalloc, hipFree
+ * or other allocating routine. Arguments as for vrt_formal_solution without
+ * exec and I_rays; the grid must have its rays set (the schedules are built
+ * there). Every call on one GPU shares that buffer, so calls that overlap on a
+ * GPU (other streams, other threads) race. The intensities are not kept for
+ * vrt_emergent_gather afterwards (pass I_rays there). Errors:
+ *   VRT_E_ARG   sizes beyond the buffer (n_rays x n x n_lambda x element size
+ *               above 64 MiB), bad precision or n_lambda, null chi, S or J,
+ *               or a Voronoi grid tuned to split launch chains (those create
+ *               streams);
+ *   VRT_E_STATE rays not set. */
+vrt_status vrt_formal_solution_noalloc(vrt_grid grid, vrt_prec prec, int32_t n_lambda, const void *chi,
+                                       const void *S, const void *I_bottom, const void *I_top, void *J);
+
 /* Reverse-mode derivative (vector-Jacobian product) of vrt_formal_solution on
  * a Voronoi grid, for gradients of a misfit of the intensities (Sect. 2.1 Eq.
  * 2, Sect. 2.5 Eq. 5 differentiated by hand). Given

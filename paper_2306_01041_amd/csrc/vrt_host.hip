@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <thread>
 
@@ -17,7 +18,39 @@
 using vrt::DevBuf;
 using vrt::Error;
 
+// Scratch of vrt_formal_solution_noalloc, the entry point that allocates
+// nothing: the per-ray intensities live in this file-scope device array. Every
+// GPU the library runs on holds its own copy until the process ends. In host
+// code the name is not a device address: the address comes from
+// hipGetSymbolAddress, once per device with that device current, when a
+// context is created on it (scratch_dev below), and only that address is
+// passed to kernels.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// records the device address of `scratch` on the current device (called with
+// `device` current); returns false if the runtime cannot give it
+bool init_scratch_dev(int device) {
+  if (device < 0 || device >= kMaxDevices) return false;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[device]) return true;
+  void *p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return false;
+  g_scratch_dev[device] = p;
+  return true;
+}
+
+void *scratch_dev(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_dev[device];
+}
 
 constexpr const char *kVersion = "vrt 0.1.0 (gfx950)";
 
@@ -1212,7 +1245,7 @@ vrt_status vrt_ctx_create(int32_t device, void *stream, vrt_ctx *out) {
   if (!c) return VRT_E_NOMEM;
   c->device = device;
   c->stream = static_cast<hipStream_t>(stream);
-  if (hipSetDevice(device) != hipSuccess) {
+  if (hipSetDevice(device) != hipSuccess || !init_scratch_dev(device)) {
     delete c;
     return VRT_E_HIP;
   }
@@ -1629,6 +1662,56 @@ vrt_status vrt_formal_solution(vrt_grid g, vrt_prec prec, vrt_exec exec, int32_t
       formal_solution<float>(g, exec, n_lambda, chi, S, I_bottom, I_top, J, I_rays);
     else
       formal_solution<double>(g, exec, n_lambda, chi, S, I_bottom, I_top, J, I_rays);
+    return VRT_OK;
+  });
+}
+
+vrt_status vrt_formal_solution_noalloc(vrt_grid g, vrt_prec prec, int32_t n_lambda, const void *chi, const void *S,
+                                       const void *I_bottom, const void *I_top, void *J) {
+  if (!g) return VRT_E_ARG;
+  return guarded(g->ctx, [&] {
+    if (!valid_prec(prec)) fail(VRT_E_ARG, "bad precision");
+    if (n_lambda <= 0) fail(VRT_E_ARG, "n_lambda must be positive");
+    if (g->R == 0) fail(VRT_E_STATE, "rays not set");
+    if (g->n > 0 && (!chi || !S || !J)) fail(VRT_E_ARG, "chi, S and J are required");
+    if (g->n == 0) return VRT_OK;
+    const size_t elem = prec == VRT_F32 ? 4 : 8;
+    const size_t need = (size_t)g->R * (size_t)g->n * (size_t)n_lambda * elem;
+    if (need > kNoAllocScratchBytes)
+      fail(VRT_E_ARG, "the intensities of %d rays x %lld sites x %d wavelengths take %zu bytes; the "
+                      "no-allocation entry point holds %zu (use vrt_formal_solution)",
+           g->R, (long long)g->n, n_lambda, need, kNoAllocScratchBytes);
+    if (g->kind == 0 && g->chains > 1 && !g->ray_affinity)
+      fail(VRT_E_ARG, "split launch chains create streams: set VRT_TUNE_CHAINS to 1 for this entry point");
+    void *base = scratch_dev(g->ctx->device);
+    if (!base) fail(VRT_E_STATE, "no scratch address for device %d", g->ctx->device);
+    // the level-step sweeps and the J quadrature of vrt_formal_solution in the
+    // batched mode, eagerly and without timing events, with the intensities in
+    // the static scratch
+    vrt_ctx ctx = g->ctx;
+    const bool prof = ctx->profiling;
+    ctx->profiling = false;
+    try {
+      if (prec == VRT_F32) {
+        const float *c = static_cast<const float *>(chi), *s = static_cast<const float *>(S);
+        enqueue_fs<float>(g, ctx->stream, VRT_EXEC_BATCHED, n_lambda, c, s,
+                          I_bottom ? static_cast<const float *>(I_bottom) : s, static_cast<const float *>(I_top),
+                          static_cast<float *>(J), static_cast<float *>(base));
+      } else {
+        const double *c = static_cast<const double *>(chi), *s = static_cast<const double *>(S);
+        enqueue_fs<double>(g, ctx->stream, VRT_EXEC_BATCHED, n_lambda, c, s,
+                           I_bottom ? static_cast<const double *>(I_bottom) : s, static_cast<const double *>(I_top),
+                           static_cast<double *>(J), static_cast<double *>(base));
+      }
+    } catch (...) {
+      ctx->profiling = prof;
+      throw;
+    }
+    ctx->profiling = prof;
+    // the rows stay in scratch that every call on this device shares: no
+    // later gather may read them as this grid's last solution
+    g->last_I = nullptr;
+    g->last_abs = false;
     return VRT_OK;
   });
 }

@@ -102,6 +102,8 @@ vrt_lte_continuum = _sig("vrt_lte_continuum", _st, [_vp, ctypes.c_int32, ctypes.
                                                     _vp, _vp, _vp])
 vrt_formal_solution = _sig("vrt_formal_solution", _st, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
                                                         _vp, _vp, _vp, _vp])
+vrt_formal_solution_noalloc = _sig("vrt_formal_solution_noalloc", _st, [_vp, ctypes.c_int32, ctypes.c_int32, _vp,
+                                                                        _vp, _vp, _vp, _vp])
 vrt_two_level_solve = _sig("vrt_two_level_solve", _st, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _d, _vp,
                                                         _vp, _vp, _vp, ctypes.c_double, ctypes.c_int32,
                                                         ctypes.c_double, ctypes.c_int32, _vp, _d, _i32])
@@ -382,6 +384,21 @@ def formal_solution(grid: Grid, chi, S, J, I_bottom=None, I_top=None, I_rays=Non
     _need(I_rays, (R, n, nl), chi.dtype, "I_rays")
     grid.ctx.check(vrt_formal_solution(grid.handle, _prec_of(chi), int(exec_mode), int(nl), _dev(chi), _dev(S),
                                        _dev(I_bottom), _dev(I_top), _dev(J), _dev(I_rays)))
+
+
+def formal_solution_noalloc(grid: Grid, chi, S, J, I_bottom=None, I_top=None):
+    """vrt_formal_solution_noalloc: the batched formal solution with the per-ray
+    intensities in the library's static per-GPU buffer (no allocation; calls on
+    one GPU must not overlap)."""
+    inf = grid.info()
+    n = inf["n_sites"]
+    if chi.dim() != 2:
+        raise ValueError("chi must be [n_sites, n_lambda]")
+    nl = chi.shape[1]
+    for t, name in ((chi, "chi"), (S, "S"), (J, "J"), (I_bottom, "I_bottom"), (I_top, "I_top")):
+        _need(t, (n, nl), chi.dtype, name)
+    grid.ctx.check(vrt_formal_solution_noalloc(grid.handle, _prec_of(chi), int(nl), _dev(chi), _dev(S),
+                                               _dev(I_bottom), _dev(I_top), _dev(J)))
 
 
 def emergent_gather(grid: Grid, out, I_rays=None):

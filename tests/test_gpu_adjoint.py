@@ -77,7 +77,7 @@ def test_reverse_sweep_matches_oracle(v, ctx, case, nl, prec):
             big = np.abs(want) > 1e-6 * np.max(np.abs(want))
             ee = float(np.max(np.abs(got[big] - want[big]) / np.abs(want[big]), initial=0.0))
             msg += f", element-wise {ee:.2e} over {int(big.sum())} of {big.size} entries"
-            assert ee <= 1e-9, name
+            assert ee <= 1e-10, name
         flush(msg)
         assert e <= tol, name
     G.close()

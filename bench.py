@@ -134,6 +134,8 @@ def main():
                     help="launch mode of the timed steps (auto: the faster of graph and persistent)")
     ap.add_argument("--workers", type=int, default=16,
                     help="processes that build the c3 batch's atmospheres (1: in this process, e.g. under a profiler)")
+    ap.add_argument("--no-accel", action="store_true",
+                    help="c2/c3 alone: skip the accelerated iteration to convergence (short profiler runs)")
     ap.add_argument("--no-lambda", action="store_true",
                     help="default run: skip the c2 and c3 two-level iteration blocks")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -914,6 +916,8 @@ def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", int
     # plain iterations (timing) and the accelerated iteration to convergence
     res_it = {}
     for name, acc, cap in (("plain", False, max_iter), ("accelerated", True, accel_iter)):
+        if not cap:
+            continue
         S_L = B.clone()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -956,7 +960,8 @@ def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", int
                              "traffic_over_algorithmic": None if traffic is None else
                              round(traffic / (sweep_bpu * updates), 3)},
             "j_quadrature_ms": round(jr_one, 3)},
-        "formal_solution_share": round(fs_ms / res_it["plain"]["ms_per_iteration"], 3),
+        "formal_solution_share": (round(fs_ms / res_it["plain"]["ms_per_iteration"], 3) if "plain" in res_it
+                                  else None),
         "iteration": res_it,
         "inputs_build_s": round(build_s, 1), "setup_s": round(setup_s, 3),
         "interleaved_records": bool(interleave),
@@ -971,8 +976,9 @@ def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", int
 def run_lambda(args):
     """The c2 / c3 workloads alone: one JSON line with the block's figures."""
     out = lambda_block(args.workload, max_iter=args.max_iter or (20 if args.workload == "c2" else 10),
-                       accel_iter=1000 if args.workload == "c2" else 200, mode_pref="auto" if args.mode == "auto"
-                       else args.mode, interleave=args.interleave, workers=args.workers)
+                       accel_iter=0 if args.no_accel else (1000 if args.workload == "c2" else 200),
+                       mode_pref="auto" if args.mode == "auto" else args.mode, interleave=args.interleave,
+                       workers=args.workers)
     line = {"metric": "site*ray*lambda updates/s of the formal solution inside the two-level Lambda iteration",
             "value": out["updates_per_s"], "unit": "site*ray*lambda updates/s", "n_gpus": 1,
             "higher_is_better": True, "dtype": "f32",

@@ -72,7 +72,7 @@ def sweep_bytes_per_update(nl: int, fp: int) -> float:
     return 3.0 * fp + (16.0 + 4.0 * fp) / nl
 
 
-LAYOUT_KEYS = ("record_order", "xcd_chunks", "ray_affinity", "chains", "lane_bytes", "interleave")
+LAYOUT_KEYS = ("record_order", "xcd_chunks", "ray_affinity", "chains", "lane_bytes", "interleave", "pipeline")
 
 
 def counter_traffic(nl, n, mode, layout):
@@ -202,8 +202,24 @@ def main():
     em = torch.empty((int(off[-1]), nl), dtype=f32, device=dev)
 
     modes = {"graph": v.VRT_EXEC_GRAPH, "batched": v.VRT_EXEC_BATCHED, "persistent": v.VRT_EXEC_PERSISTENT}
+    # the library's autotuner times the launch layouts and the persistent sweep
+    # on this workload and keeps the fastest on the grid (its launch mode too)
+    v.lte_continuum(G, lam, atm.kappa0, T, rho, chi, S)
+    tuning = None if args.no_autotune else v.autotune(G, chi, S, J, reps=5)
+    log(f"autotune: {tuning}")
+    if tuning is None and args.interleave:
+        G.tune(v.VRT_TUNE_INTERLEAVE, 1)
+    layout = dict(tuning["chosen"]) if tuning else {"record_order": 1, "xcd_chunks": 8, "ray_affinity": 0,
+                                                    "chains": 1, "lane_bytes": 16,
+                                                    "interleave": 1 if args.interleave else 0, "pipeline": 0}
     mode_times = {}
-    if args.mode == "auto":
+    if args.mode == "auto" and tuning:
+        args.mode = tuning["chosen"]["exec"]
+        for c in tuning["candidates"]:
+            if c["ms"] is not None and c["ms"] < mode_times.get(c["exec"], float("inf")):
+                mode_times[c["exec"]] = c["ms"]
+        log(f"launch modes (best ms per formal solution in the autotuner): {mode_times} -> {args.mode}")
+    elif args.mode == "auto":
         for name in ("graph", "persistent"):
             try:
                 for _ in range(2):
@@ -224,15 +240,6 @@ def main():
         v.lte_continuum(G, lam, atm.kappa0, T, rho, chi, S)
         v.formal_solution(G, chi, S, J, exec_mode=mode)
         v.emergent_gather(G, em)
-
-    v.lte_continuum(G, lam, atm.kappa0, T, rho, chi, S)
-    tuning = None if args.no_autotune else v.autotune(G, chi, S, J, reps=5)
-    log(f"autotune: {tuning}")
-    if tuning is None and args.interleave:
-        G.tune(v.VRT_TUNE_INTERLEAVE, 1)
-    layout = dict(tuning["chosen"]) if tuning else {"record_order": 1, "xcd_chunks": 8, "ray_affinity": 0,
-                                                    "chains": 1, "lane_bytes": 16,
-                                                    "interleave": 1 if args.interleave else 0}
 
     for _ in range(args.warmup):
         step()
@@ -844,8 +851,6 @@ def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", int
     setup_s = time.time() - t0
     info = G.info()
     log(f"rays set in {setup_s:.2f} s: {info}")
-    if interleave:
-        G.tune(v.VRT_TUNE_INTERLEAVE, 1)
     d = torch.float64
     lam0 = np.array([LAMBDA0_NM * 1e-9])
     # one continuum constant for the batch (a recipe constant)
@@ -870,11 +875,23 @@ def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", int
     chi[:, nl:] = chi_c[:, None]
     S[:, nl:] = B[:, None]
     J = torch.empty_like(chi)
-    # launch modes: the graph of level steps and the persistent sweep (auto: the
-    # faster of those that run; the persistent sweep refuses rays above 4 GiB)
+    # launch modes: the autotuner (auto) times the graph of level steps under
+    # its layouts and the persistent sweep, and keeps the fastest on the grid
     modes = {"graph": v.VRT_EXEC_GRAPH, "batched": v.VRT_EXEC_BATCHED, "persistent": v.VRT_EXEC_PERSISTENT}
+    tuning = None
+    if mode_pref == "auto":
+        t1 = time.time()
+        tuning = v.autotune(G, chi, S, J, reps=3)
+        log(f"{workload}: autotune in {time.time() - t1:.1f} s, chosen {tuning['chosen']}")
+        mode_pref = tuning["chosen"]["exec"]
+    elif interleave:
+        G.tune(v.VRT_TUNE_INTERLEAVE, 1)
     fs_by_mode = {}
-    for name in (("graph", "persistent") if mode_pref == "auto" else (mode_pref,)):
+    if tuning:
+        for c in tuning["candidates"]:
+            if c["ms"] is not None and c["ms"] < fs_by_mode.get(c["exec"], float("inf")):
+                fs_by_mode[c["exec"]] = c["ms"]
+    for name in (mode_pref,):
         try:
             for _ in range(2):
                 v.formal_solution(G, chi, S, J, exec_mode=modes[name])
@@ -887,11 +904,11 @@ def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", int
             e1.record(stream)
             e1.synchronize()
             G.device_status()
-            fs_by_mode[name] = e0.elapsed_time(e1) / k
+            fs_ms = e0.elapsed_time(e1) / k
         except v.VrtError as e:
             log(f"launch mode {name} not used: {e}")
-    mode_name = min(fs_by_mode, key=fs_by_mode.get)
-    fs_ms = fs_by_mode[mode_name]
+            raise
+    mode_name = mode_pref
     # the angle quadrature of J on its own (one eager launch, HIP events on the library stream)
     ctx.profile_reset()
     ctx.set_profiling(True)
@@ -946,6 +963,7 @@ def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", int
         "sites": U.n, "atmospheres": len(grids), "wavelengths": nl, "rays": R, "levels_max": info["max_levels"],
         "formal_solution_ms": round(fs_ms, 3), "updates_per_s": upd_s, "launch_mode": mode_name,
         "formal_solution_ms_by_mode": {k: round(t, 3) for k, t in fs_by_mode.items()},
+        "tuning": tuning["chosen"] if tuning else None,
         "roofline": {
             "bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "whole_solution": {"bytes_per_update": round(whole_bpu, 3),
@@ -964,7 +982,7 @@ def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", int
                                   else None),
         "iteration": res_it,
         "inputs_build_s": round(build_s, 1), "setup_s": round(setup_s, 3),
-        "interleaved_records": bool(interleave),
+        "interleaved_records": int(tuning["chosen"]["interleave"]) if tuning else int(bool(interleave)),
     }
     G.close()
     ctx.close()

@@ -72,12 +72,15 @@ typedef enum { VRT_F64 = 0, VRT_F32 = 1 } vrt_prec;
  *             intensity is reported as VRT_E_NUMERIC. One ray's intensities must
  *             stay below 4 GiB (else VRT_E_ARG). Check vrt_grid_device_status
  *             after synchronising to learn whether a bounded wait gave up
- *             (VRT_E_TIMEOUT) or a value could not be encoded (VRT_E_NUMERIC). */
+ *             (VRT_E_TIMEOUT) or a value could not be encoded (VRT_E_NUMERIC).
+ * AUTO:       the mode vrt_grid_autotune chose for the grid (GRAPH until the
+ *             autotuner has run on it). */
 typedef enum {
   VRT_EXEC_PLAIN = 0,
   VRT_EXEC_BATCHED = 1,
   VRT_EXEC_GRAPH = 2,
-  VRT_EXEC_PERSISTENT = 3
+  VRT_EXEC_PERSISTENT = 3,
+  VRT_EXEC_AUTO = 4
 } vrt_exec;
 
 typedef struct vrt_ctx_s *vrt_ctx;
@@ -210,7 +213,10 @@ vrt_status vrt_grid_set_rays(vrt_grid grid, int32_t n_rays, const double *dir, c
  *                           records in which each level step is ordered by the
  *                           sites' horizontal Morton code across all rays, so
  *                           a die's chunk of a step is a region of the box
- *                           for every ray [0]. */
+ *                           for every ray; 2 = the same copy ordered by site
+ *                           index across rays (for sites numbered along space,
+ *                           e.g. a batch of atmospheres, whose Morton codes
+ *                           would interleave the atmospheres) [0]. */
 #define VRT_TUNE_INTERLEAVE 10
 /*   VRT_TUNE_PIPELINE       0 = one group of records per wavefront in the
  *                           level-step sweeps; 2, 4 or 8 = each wavefront
@@ -252,12 +258,17 @@ vrt_status vrt_grid_set_rays(vrt_grid grid, int32_t n_rays, const double *dir, c
 #define VRT_TUNE_PERSIST_BLOCKS 4
 vrt_status vrt_grid_tune(vrt_grid grid, int32_t knob, int64_t value);
 
-/* Autotuner: times launch layouts (record order x a fixed list of {die
- * chunks, ray affinity, chains} settings) on a formal solution with the given arguments (as for
- * vrt_formal_solution with VRT_EXEC_GRAPH), `reps` replays each after one
- * warm-up, keeps the fastest setting on the grid and writes a one-line JSON
- * report (host, may be NULL) of every candidate's mean time in ms. Re-packs
- * the sweep records when the record order changes. Blocks. */
+/* Autotuner: times candidate launch settings on a formal solution with the
+ * given arguments (as for vrt_formal_solution): for each record order, the
+ * graph-launched level steps under a fixed list of {die chunks, ray
+ * affinity, lane bytes, interleaved record copy (Morton or site order),
+ * pipeline depth} settings, and (Voronoi grids, linear segment) the
+ * persistent sweep; `reps` replays each after one warm-up. Keeps the fastest
+ * setting on the grid, including its launch mode for VRT_EXEC_AUTO, and
+ * writes a one-line JSON report (host, may be NULL) of every candidate's mean
+ * time in ms and the choice. A candidate that fails (e.g. the persistent
+ * sweep of a ray above 4 GiB) is reported with "ms": null and skipped.
+ * Re-packs the sweep records when the record order changes. Blocks. */
 vrt_status vrt_grid_autotune(vrt_grid grid, vrt_prec prec, int32_t n_lambda, const void *chi,
                              const void *S, const void *I_bottom, const void *I_top, void *J,
                              void *I_rays, int32_t reps, char *report, int64_t report_len);

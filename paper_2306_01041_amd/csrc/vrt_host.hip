@@ -265,9 +265,11 @@ std::vector<uint64_t> morton_codes(vrt_grid g) {
   return code;
 }
 
-// The records of every level step reordered by (Morton code of the site, ray,
-// site): the records of one step are independent, so any order within a step
-// gives the same intensities.
+// The records of every level step reordered across rays: by (Morton code of
+// the site, ray, site) for interleave mode 1, by (site, ray) for mode 2 (with
+// sites numbered along space, as a batch of atmospheres is, this keeps each
+// atmosphere's records together). The records of one step are independent,
+// so any order within a step gives the same intensities.
 void build_interleaved(vrt_grid g) {
   hipStream_t s = g->ctx->stream;
   const int64_t nr = g->n_rec;
@@ -278,7 +280,8 @@ void build_interleaved(vrt_grid g) {
   VRT_HIP(hipMemcpyAsync(r32.data(), g->d_rf32.p, (size_t)nr * sizeof(vrt::RecF32), hipMemcpyDeviceToHost, s));
   VRT_HIP(hipMemcpyAsync(r64.data(), g->d_rf64.p, (size_t)nr * sizeof(vrt::RecF64), hipMemcpyDeviceToHost, s));
   VRT_HIP(hipStreamSynchronize(s));
-  const std::vector<uint64_t> code = morton_codes(g);
+  const bool by_site = g->interleave == 2;
+  const std::vector<uint64_t> code = by_site ? std::vector<uint64_t>() : morton_codes(g);
   std::vector<int64_t> perm((size_t)nr);
   std::iota(perm.begin(), perm.end(), int64_t(0));
   std::vector<int4> ri2((size_t)nr);
@@ -291,7 +294,8 @@ void build_interleaved(vrt_grid g) {
       const int64_t b0 = g->step_ptr[(size_t)st], e0 = g->step_ptr[(size_t)st + 1];
       std::sort(perm.begin() + b0, perm.begin() + e0, [&](int64_t u, int64_t v) {
         const int4 &a = ri[(size_t)u], &c = ri[(size_t)v];
-        const uint64_t ka = code[(size_t)a.x], kc = code[(size_t)c.x];
+        const uint64_t ka = by_site ? (uint64_t)a.x : code[(size_t)a.x];
+        const uint64_t kc = by_site ? (uint64_t)c.x : code[(size_t)c.x];
         if (ka != kc) return ka < kc;
         if (a.w != c.w) return a.w < c.w;
         return a.x < c.x;
@@ -311,7 +315,7 @@ void build_interleaved(vrt_grid g) {
   upload(g->d_rf32_x, r32b.data(), r32b.size(), s);
   upload(g->d_rf64_x, r64b.data(), r64b.size(), s);
   VRT_HIP(hipStreamSynchronize(s));  // the host vectors must outlive the copies
-  g->interleaved_built = true;
+  g->interleaved_built = g->interleave;
 }
 
 // Downwind lines of every (ray, site) for the quadratic segment: the upwind
@@ -485,7 +489,7 @@ void set_rays_voronoi(vrt_grid g) {
                    g->d_ds2.as<double>(), g->d_dirs.as<double>(), g->d_ri.as<int4>(), g->d_rf32.as<vrt::RecF32>(),
                    g->d_rf64.as<vrt::RecF64>());
   VRT_HIP(hipStreamSynchronize(s));
-  g->interleaved_built = false;
+  g->interleaved_built = 0;
   if (g->interleave) build_interleaved(g);
   g->down_built = false;
   if (g->segment) build_downwind(g);
@@ -643,7 +647,7 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
       // step-wide launches read the interleaved copy when there is one
       const int4 *rix = ri;
       auto rfx = rf;
-      if (g->interleave && g->interleaved_built) {
+      if (g->interleave && g->interleaved_built == g->interleave) {
         rix = g->d_ri_x.as<int4>();
         rfx = sizeof(T) == 4 ? reinterpret_cast<decltype(rf)>(g->d_rf32_x.p)
                              : reinterpret_cast<decltype(rf)>(g->d_rf64_x.p);
@@ -730,7 +734,7 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
     } else {
       const int4 *rix = ri;
       const auto *rfx = rf;
-      if (g->interleave && g->interleaved_built) {
+      if (g->interleave && g->interleaved_built == g->interleave) {
         rix = g->d_ri_x.as<int4>();
         rfx = sizeof(T) == 4 ? reinterpret_cast<decltype(rf)>(g->d_rf32_x.p) : reinterpret_cast<decltype(rf)>(g->d_rf64_x.p);
       }
@@ -1455,9 +1459,9 @@ vrt_status vrt_grid_tune(vrt_grid g, int32_t knob, int64_t value) {
       if (value < 1 || value > 64) fail(VRT_E_ARG, "ray groups must be in 1..64");
       g->ray_groups = (int)value;
     } else if (knob == VRT_TUNE_INTERLEAVE) {
-      if (value != 0 && value != 1) fail(VRT_E_ARG, "interleave must be 0 or 1");
+      if (value < 0 || value > 2) fail(VRT_E_ARG, "interleave must be 0, 1 or 2");
       g->interleave = (int)value;
-      if (g->interleave && g->kind == 0 && g->R > 0) build_interleaved(g);
+      if (g->interleave && g->kind == 0 && g->R > 0 && g->interleaved_built != g->interleave) build_interleaved(g);
     } else if (knob == VRT_TUNE_SEGMENT) {
       if (value != 0 && value != 1) fail(VRT_E_ARG, "segment must be 0 (linear) or 1 (quadratic Bezier)");
       if (value == 1 && g->kind != 0) fail(VRT_E_ARG, "the quadratic segment needs a Voronoi grid");
@@ -1499,85 +1503,105 @@ vrt_status vrt_grid_autotune(vrt_grid g, vrt_prec prec, int32_t n_lambda, const 
     hipEvent_t e0, e1;
     VRT_HIP(hipEventCreate(&e0));
     VRT_HIP(hipEventCreate(&e1));
+    struct Cand {
+      int xcd, aff, lb, il, pipe, exec;
+    };
+    struct Setting {
+      int order, xcd, aff, lb, il, pipe, exec;
+    };
+    // graph-launched level steps under die chunks x ray affinity x lane bytes
+    // x interleaved copy x pipeline depth, and the persistent sweep (whose
+    // launch ignores those knobs). Split chains are not candidates: kernels on
+    // separate queues were measured not to overlap. The interleaved copies
+    // sort every step across rays whatever the record order, so they are timed
+    // under one order only; they are built on the host, up to 2^28 records.
+    const int G = VRT_EXEC_GRAPH, P = VRT_EXEC_PERSISTENT;
+    static const Cand cands[] = {{0, 0, 16, 0, 0, G}, {8, 0, 16, 0, 0, G}, {0, 1, 16, 0, 0, G}, {8, 0, 32, 0, 0, G},
+                                 {0, 1, 32, 0, 0, G}, {8, 0, 16, 0, 2, G}, {8, 0, 16, 0, 4, G}, {8, 0, 16, 1, 0, G},
+                                 {0, 0, 16, 1, 0, G}, {8, 0, 16, 1, 2, G}, {8, 0, 16, 2, 0, G}, {8, 0, 16, 2, 2, G},
+                                 {8, 0, 16, 0, 0, P}};
     std::string rep = "{\"candidates\": [";
     double best = 1e300;
-    int best_order = g->record_order, best_xcd = g->xcd_chunks, best_aff = g->ray_affinity, best_ch = g->chains,
-        best_lb = g->lane_bytes, best_il = g->interleave;
-    // (die chunks, ray affinity, chains, lane bytes, interleave) per record
-    // order; split chains are not candidates: kernels on separate queues were
-    // measured not to overlap. The interleaved copy sorts every step by
-    // position whatever the record order, so it is timed under one order only.
-    static const int cands[][5] = {{0, 0, 1, 16, 0}, {8, 0, 1, 16, 0}, {0, 1, 1, 16, 0}, {8, 0, 1, 32, 0},
-                                   {0, 1, 1, 32, 0}, {8, 0, 1, 16, 1},  {0, 0, 1, 16, 1}};
+    Setting bs{g->record_order, g->xcd_chunks, g->ray_affinity, g->lane_bytes, g->interleave, g->pipe,
+               g->tuned_exec};
+    g->chains = 1;
     bool first = true;
-    g->interleave = 0;
+    auto fmt = [](int exec) { return exec == VRT_EXEC_PERSISTENT ? "persistent" : "graph"; };
     for (int order = 0; order <= 1; ++order) {
       if (order != g->record_order || first) {
         g->record_order = order;
+        g->interleave = 0;
         g->drop_graphs();
         set_rays_voronoi(g);
       }
       for (const auto &cd : cands) {
-        const int xcd = cd[0], aff = cd[1], ch = cd[2], lb = cd[3], il = cd[4];
-        if (il && (order != 1 || g->n_rec > (int64_t(1) << 26))) continue;  // the copy is built on the host
-        if (il && !g->interleaved_built) build_interleaved(g);
-        g->xcd_chunks = xcd;
-        g->ray_affinity = aff;
-        g->chains = ch;
-        g->lane_bytes = lb;
-        g->interleave = il;
+        if (cd.il && (order != 1 || g->n_rec > (int64_t(1) << 28))) continue;
+        if (cd.exec == P && g->segment) continue;
+        g->xcd_chunks = cd.xcd;
+        g->ray_affinity = cd.aff;
+        g->lane_bytes = cd.lb;
+        g->interleave = cd.il;
+        g->pipe = cd.pipe;
+        if (cd.il && g->interleaved_built != cd.il) build_interleaved(g);
         g->drop_graphs();
         auto run = [&] {
           if (prec == VRT_F32)
-            formal_solution<float>(g, VRT_EXEC_GRAPH, n_lambda, chi, S, I_bottom, I_top, J, I_rays);
+            formal_solution<float>(g, (vrt_exec)cd.exec, n_lambda, chi, S, I_bottom, I_top, J, I_rays);
           else
-            formal_solution<double>(g, VRT_EXEC_GRAPH, n_lambda, chi, S, I_bottom, I_top, J, I_rays);
+            formal_solution<double>(g, (vrt_exec)cd.exec, n_lambda, chi, S, I_bottom, I_top, J, I_rays);
         };
-        run();  // capture + warm-up
-        VRT_HIP(hipEventRecord(e0, s));
-        for (int r = 0; r < reps; ++r) run();
-        VRT_HIP(hipEventRecord(e1, s));
-        VRT_HIP(hipEventSynchronize(e1));
-        float ms = 0.0f;
-        VRT_HIP(hipEventElapsedTime(&ms, e0, e1));
-        const double mean = ms / reps;
-        char buf[192];
+        double mean = -1.0;
+        try {
+          run();  // capture + warm-up
+          VRT_HIP(hipEventRecord(e0, s));
+          for (int r = 0; r < reps; ++r) run();
+          VRT_HIP(hipEventRecord(e1, s));
+          VRT_HIP(hipEventSynchronize(e1));
+          if (cd.exec == P) take_device_error(g, 0);
+          float ms = 0.0f;
+          VRT_HIP(hipEventElapsedTime(&ms, e0, e1));
+          mean = ms / reps;
+        } catch (const Error &e) {
+          if (e.code == VRT_E_HIP || e.code == VRT_E_NOMEM) throw;
+          VRT_HIP(hipStreamSynchronize(s));
+          take_device_error(g, 0);  // rethrows a pending device error as its own status
+        }
+        char buf[256], msb[32];
+        if (mean >= 0.0) snprintf(msb, sizeof msb, "%.5f", mean);
+        else snprintf(msb, sizeof msb, "null");
         snprintf(buf, sizeof buf,
-                 "%s{\"record_order\": %d, \"xcd_chunks\": %d, \"ray_affinity\": %d, \"chains\": %d, "
-                 "\"lane_bytes\": %d, \"interleave\": %d, \"ms\": %.5f}",
-                 first ? "" : ", ", order, xcd, aff, ch, lb, il, mean);
+                 "%s{\"exec\": \"%s\", \"record_order\": %d, \"xcd_chunks\": %d, \"ray_affinity\": %d, "
+                 "\"lane_bytes\": %d, \"interleave\": %d, \"pipeline\": %d, \"ms\": %s}",
+                 first ? "" : ", ", fmt(cd.exec), order, cd.xcd, cd.aff, cd.lb, cd.il, cd.pipe, msb);
         rep += buf;
         first = false;
-        if (mean < best) {
+        if (mean >= 0.0 && mean < best) {
           best = mean;
-          best_order = order;
-          best_xcd = xcd;
-          best_aff = aff;
-          best_ch = ch;
-          best_lb = lb;
-          best_il = il;
+          bs = Setting{order, cd.xcd, cd.aff, cd.lb, cd.il, cd.pipe, cd.exec};
         }
       }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    g->chains = 1;  // every candidate was timed with one launch chain
     g->interleave = 0;
-    if (best_order != g->record_order) {
-      g->record_order = best_order;
+    if (bs.order != g->record_order) {
+      g->record_order = bs.order;
       set_rays_voronoi(g);
     }
-    g->xcd_chunks = best_xcd;
-    g->ray_affinity = best_aff;
-    g->chains = best_ch;
-    g->lane_bytes = best_lb;
-    g->interleave = best_il;
-    if (best_il && !g->interleaved_built) build_interleaved(g);
+    g->xcd_chunks = bs.xcd;
+    g->ray_affinity = bs.aff;
+    g->lane_bytes = bs.lb;
+    g->interleave = bs.il;
+    g->pipe = bs.pipe;
+    g->tuned_exec = bs.exec;
+    if (bs.il && g->interleaved_built != bs.il) build_interleaved(g);
     g->drop_graphs();
-    char buf[260];
+    char buf[320];
     snprintf(buf, sizeof buf,
-             "], \"chosen\": {\"record_order\": %d, \"xcd_chunks\": %d, \"ray_affinity\": %d, \"chains\": %d, "
-             "\"lane_bytes\": %d, \"interleave\": %d, \"ms\": %.5f}}",
-             best_order, best_xcd, best_aff, best_ch, best_lb, best_il, best);
+             "], \"chosen\": {\"exec\": \"%s\", \"record_order\": %d, \"xcd_chunks\": %d, \"ray_affinity\": %d, "
+             "\"lane_bytes\": %d, \"interleave\": %d, \"pipeline\": %d, \"ms\": %.5f}}",
+             fmt(bs.exec), bs.order, bs.xcd, bs.aff, bs.lb, bs.il, bs.pipe, best);
     rep += buf;
     if (report && report_len > 0) snprintf(report, (size_t)report_len, "%s", rep.c_str());
     return VRT_OK;
@@ -1651,6 +1675,7 @@ vrt_status vrt_formal_solution(vrt_grid g, vrt_prec prec, vrt_exec exec, int32_t
                                const void *S, const void *I_bottom, const void *I_top, void *J, void *I_rays) {
   if (!g) return VRT_E_ARG;
   return guarded(g->ctx, [&] {
+    if (exec == VRT_EXEC_AUTO) exec = (vrt_exec)g->tuned_exec;
     if (!valid_prec(prec) || (exec != VRT_EXEC_PLAIN && exec != VRT_EXEC_BATCHED && exec != VRT_EXEC_GRAPH &&
                               exec != VRT_EXEC_PERSISTENT))
       fail(VRT_E_ARG, "bad precision or execution mode");
@@ -1722,6 +1747,7 @@ static vrt_status two_level_entry(vrt_grid g, vrt_prec prec, vrt_exec exec, int3
                                   int32_t n_atm, const int64_t *atm_ptr, double *dS_hist, int32_t *n_iter) {
   if (!valid_prec(prec) || n_lambda <= 0 || !wlam || max_iter < 0 || !(tol >= 0.0) || !(eps >= 0.0 && eps <= 1.0))
     fail(VRT_E_ARG, "bad two-level arguments");
+  if (exec == VRT_EXEC_AUTO) exec = (vrt_exec)g->tuned_exec;
   if (exec != VRT_EXEC_PLAIN && exec != VRT_EXEC_BATCHED && exec != VRT_EXEC_GRAPH && exec != VRT_EXEC_PERSISTENT)
     fail(VRT_E_ARG, "bad execution mode");
   if (n_atm <= 0 || !atm_ptr || !n_iter) fail(VRT_E_ARG, "bad atmosphere partition");

@@ -184,7 +184,8 @@ struct vrt_grid_s {
   int chains = 1;        // independent launch chains (streams) a sweep is split into
   int lane_bytes = 16;   // bytes of a row each lane moves per access (16 or 32)
   int ray_groups = 1;    // the rays are swept in this many consecutive passes
-  int interleave = 0;    // 1: step-wide sweeps read a copy of the records ordered by position across rays
+  int interleave = 0;    // step-wide sweeps read a copy of the records ordered across rays by the site's
+                         // horizontal Morton code (1) or by site index (2); 0 = per-ray order
   int pipe = 0;          // > 0: level-step sweeps use the pipelined kernel with this many record groups per wave
   int segment = 0;       // 0: linear source along a line, 1: quadratic Bezier (needs the downwind lines)
   int reverse_persistent = 0;  // 1: the reverse sweep of a ray group runs as one persistent launch
@@ -192,7 +193,8 @@ struct vrt_grid_s {
   vrt::DevBuf d_q1, d_q2, d_qw1, d_qd1, d_qd2;  // downwind lines [R][n]: the selection of the opposite rays
   bool down_built = false;
   vrt::DevBuf d_ri_x, d_rf32_x, d_rf64_x;
-  bool interleaved_built = false;
+  int interleaved_built = 0;  // interleave mode of the copy in d_ri_x, d_rf*_x (0 = none)
+  int tuned_exec = VRT_EXEC_GRAPH;  // launch mode chosen by the autotuner (VRT_EXEC_AUTO resolves to it)
 
   // ray-affinity tables: ray_die[r], and per step [kDies][xk][2] = {first
   // record, running count} over the segments of each die's rays

@@ -56,6 +56,7 @@ VRT_EXEC_PLAIN = 0
 VRT_EXEC_BATCHED = 1
 VRT_EXEC_GRAPH = 2
 VRT_EXEC_PERSISTENT = 3
+VRT_EXEC_AUTO = 4  # the launch mode the autotuner chose for the grid
 
 _vp = ctypes.c_void_p
 _d = ctypes.POINTER(ctypes.c_double)
@@ -423,9 +424,9 @@ def autotune(grid: Grid, chi, S, J, I_bottom=None, I_top=None, I_rays=None, reps
     for t, name in ((chi, "chi"), (S, "S"), (J, "J"), (I_bottom, "I_bottom"), (I_top, "I_top")):
         _need(t, (n, nl), chi.dtype, name)
     _need(I_rays, (R, n, nl), chi.dtype, "I_rays")
-    buf = ctypes.create_string_buffer(4096)
+    buf = ctypes.create_string_buffer(16384)
     grid.ctx.check(vrt_grid_autotune(grid.handle, _prec_of(chi), int(nl), _dev(chi), _dev(S), _dev(I_bottom),
-                                     _dev(I_top), _dev(J), _dev(I_rays), int(reps), buf, 4096))
+                                     _dev(I_top), _dev(J), _dev(I_rays), int(reps), buf, 16384))
     return json.loads(buf.value.decode() or "{}")
 
 

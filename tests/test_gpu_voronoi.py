@@ -310,9 +310,10 @@ def test_errors_do_not_launch(v, ctx, quad, grids):
 
 
 def test_tuning_knobs_do_not_change_results(v, ctx, quad, grids):
-    """Record order and die-chunk mapping only reorder independent work: the
-    results are bit-identical for every setting, and the autotuner reports
-    every candidate and keeps one of them."""
+    """Record order, die-chunk mapping, interleaved record copies and the
+    pipelined kernel only reorder independent work: the results are
+    bit-identical for every setting, and the autotuner reports every candidate
+    (level-step layouts and the persistent sweep) and keeps the fastest."""
     flush("tuning knobs")
     atm, g = grids[16384]
     dirs, w = quad
@@ -321,11 +322,13 @@ def test_tuning_knobs_do_not_change_results(v, ctx, quad, grids):
     chi, S = to_dev(chi_o, f), to_dev(S_o, f)
     ref = None
     for order in (0, 1):
-        for xcd, aff, ch, lb, rg, il in ((0, 0, 1, 16, 1, 0), (3, 0, 1, 16, 1, 0), (8, 0, 1, 16, 1, 0),
-                                         (8, 1, 1, 16, 1, 0), (8, 0, 2, 16, 1, 0), (0, 0, 3, 16, 1, 0),
-                                         (8, 0, 5, 16, 1, 0), (8, 0, 1, 32, 1, 0), (8, 1, 1, 32, 1, 0),
-                                         (8, 0, 1, 16, 3, 0), (8, 0, 1, 16, 5, 0), (8, 0, 1, 16, 1, 1),
-                                         (0, 0, 1, 32, 1, 1), (8, 0, 2, 16, 1, 1)):
+        for xcd, aff, ch, lb, rg, il, pp in ((0, 0, 1, 16, 1, 0, 0), (3, 0, 1, 16, 1, 0, 0), (8, 0, 1, 16, 1, 0, 0),
+                                             (8, 1, 1, 16, 1, 0, 0), (8, 0, 2, 16, 1, 0, 0), (0, 0, 3, 16, 1, 0, 0),
+                                             (8, 0, 5, 16, 1, 0, 0), (8, 0, 1, 32, 1, 0, 0), (8, 1, 1, 32, 1, 0, 0),
+                                             (8, 0, 1, 16, 3, 0, 0), (8, 0, 1, 16, 5, 0, 0), (8, 0, 1, 16, 1, 1, 0),
+                                             (0, 0, 1, 32, 1, 1, 0), (8, 0, 2, 16, 1, 1, 0), (8, 0, 1, 16, 1, 2, 0),
+                                             (0, 0, 1, 16, 1, 2, 2), (8, 0, 1, 16, 1, 0, 2), (8, 0, 1, 16, 1, 1, 4),
+                                             (8, 0, 3, 16, 1, 0, 8), (8, 0, 1, 16, 3, 0, 2)):
             G = v.Grid.from_synth(ctx, g)
             G.tune(v.VRT_TUNE_RECORD_ORDER, order)
             G.tune(v.VRT_TUNE_XCD_CHUNKS, xcd)
@@ -334,6 +337,7 @@ def test_tuning_knobs_do_not_change_results(v, ctx, quad, grids):
             G.tune(v.VRT_TUNE_LANE_BYTES, lb)
             G.tune(v.VRT_TUNE_RAY_GROUPS, rg)
             G.tune(v.VRT_TUNE_INTERLEAVE, il)  # before the rays: built with the schedule
+            G.tune(v.VRT_TUNE_PIPELINE, pp)
             G.set_rays(dirs, w)
             J = torch.empty_like(chi)
             for mode in (v.VRT_EXEC_GRAPH, v.VRT_EXEC_BATCHED, v.VRT_EXEC_PLAIN):
@@ -342,7 +346,7 @@ def test_tuning_knobs_do_not_change_results(v, ctx, quad, grids):
                 out = J.cpu().numpy()
                 if ref is None:
                     ref = out
-                assert np.array_equal(out, ref), (order, xcd, aff, ch, lb, rg, il, mode)
+                assert np.array_equal(out, ref), (order, xcd, aff, ch, lb, rg, il, pp, mode)
             G.close()
     # switched on after the rays are set: the copy is built at once
     G = _gpu_grid(v, ctx, g, dirs, w)
@@ -355,11 +359,15 @@ def test_tuning_knobs_do_not_change_results(v, ctx, quad, grids):
     G = _gpu_grid(v, ctx, g, dirs, w)
     J = torch.empty_like(chi)
     rep = v.autotune(G, chi, S, J, reps=2)
-    assert len(rep["candidates"]) == 12
-    assert rep["chosen"]["ms"] == min(c["ms"] for c in rep["candidates"])
-    v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_GRAPH)
-    torch.cuda.synchronize()
-    assert np.array_equal(J.cpu().numpy(), ref)
+    # per record order: 7 level-step layouts without the interleaved copies and
+    # the persistent sweep, plus 5 with them under the Morton order
+    assert len(rep["candidates"]) == 21
+    assert {c["exec"] for c in rep["candidates"]} == {"graph", "persistent"}
+    assert rep["chosen"]["ms"] == min(c["ms"] for c in rep["candidates"] if c["ms"] is not None)
+    for mode in (v.VRT_EXEC_AUTO, v.VRT_EXEC_GRAPH, v.VRT_EXEC_PERSISTENT):
+        v.formal_solution(G, chi, S, J, exec_mode=mode)
+        G.device_status()
+        assert np.array_equal(J.cpu().numpy(), ref), mode
     with pytest.raises(v.VrtError):
         G.tune(99, 1)
     G.close()

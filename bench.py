@@ -116,9 +116,12 @@ def main():
     ap.add_argument("--no-bezier", action="store_true", help="skip the quadratic-segment timing")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the grid's default launch layout (for profiler runs that average over dispatches)")
-    ap.add_argument("--interleave", action="store_true",
-                    help="sweep the interleaved record copy: with --no-autotune on c1 (the layout the autotuner "
-                         "picks there), and on c2/c3")
+    ap.add_argument("--interleave", type=int, choices=[0, 1, 2], default=0,
+                    help="with a fixed layout (c1: --no-autotune; c2/c3: --mode other than auto): sweep the "
+                         "interleaved record copy, in Morton order (1) or in site-index order (2)")
+    ap.add_argument("--pipeline", type=int, choices=[0, 2, 4, 8], default=0,
+                    help="with a fixed layout: interior level steps launch the pipelined sweep kernel with this "
+                         "many groups of records in flight per wavefront (0: the plain level-step kernel)")
     ap.add_argument("--workload", choices=["c1", "c2", "c3", "synth", "design"], default="c1",
                     help="c1: the formal solution (default line); c2: the two-level Lambda iteration on 1,048,576 "
                          "sites; c3: 48 atmospheres of 32,768-524,288 sites solved as one batch; synth: only the "
@@ -207,11 +210,12 @@ def main():
     v.lte_continuum(G, lam, atm.kappa0, T, rho, chi, S)
     tuning = None if args.no_autotune else v.autotune(G, chi, S, J, reps=5)
     log(f"autotune: {tuning}")
-    if tuning is None and args.interleave:
-        G.tune(v.VRT_TUNE_INTERLEAVE, 1)
+    if tuning is None:
+        G.tune(v.VRT_TUNE_INTERLEAVE, args.interleave)
+        G.tune(v.VRT_TUNE_PIPELINE, args.pipeline)
     layout = dict(tuning["chosen"]) if tuning else {"record_order": 1, "xcd_chunks": 8, "ray_affinity": 0,
                                                     "chains": 1, "lane_bytes": 16,
-                                                    "interleave": 1 if args.interleave else 0, "pipeline": 0}
+                                                    "interleave": args.interleave, "pipeline": args.pipeline}
     mode_times = {}
     if args.mode == "auto" and tuning:
         args.mode = tuning["chosen"]["exec"]
@@ -355,9 +359,9 @@ def main():
         Tq = T.clone().requires_grad_(True)
         rq = rho.clone().requires_grad_(True)
 
-        def timed(emergent_dtype):
+        def timed(emergent_dtype, **kw):
             def fwd():
-                em4 = v.lte_emergent(Tq, rq, G, lam4, atm.kappa0, emergent_dtype=emergent_dtype)
+                em4 = v.lte_emergent(Tq, rq, G, lam4, atm.kappa0, emergent_dtype=emergent_dtype, **kw)
                 return ((em4.double() - target.double()) ** 2).sum()
 
             for _ in range(2):
@@ -396,6 +400,13 @@ def main():
         fw_ms, bw_ms = (fw_p, bw_p) if bw_p < bw_l else (fw_l, bw_l)
         fw2, bw2 = timed(torch.float32)  # all-FP32
         G.tune(v.VRT_TUNE_REVERSE_PERSISTENT, 0)
+        # memory-bounded backward: forward intensities dropped after the forward
+        # pass and recomputed from per-level-chunk checkpoints (16 steps)
+        ck = 16
+        fw3, bw3 = timed(None, keep_intensities=False, checkpoint_levels=ck)
+        mem = {key: v.formal_solution_vjp_scratch(G, torch.float32, nl4, keep_intensities=keep,
+                                                  checkpoint_levels=kk)
+               for key, keep, kk in (("kept", True, 0), ("recomputed", False, 0), ("checkpointed", False, ck))}
         adjoint = {"workload": f"adjoint of the LTE formal solution, {g.n} sites, {nl4} wavelengths 500-700 nm, "
                                f"{R} rays, FP32 sweeps, FP64 ray accumulation, loss sum (I_em - I_target)^2 with "
                                f"I_em from an FP64 forward sweep (gradient within 1e-4 of central differences)",
@@ -408,9 +419,15 @@ def main():
                                         "2e-3 of central differences when the residuals are small)",
                                 "forward_ms": round(fw2, 3), "adjoint_ms": round(bw2, 3),
                                 "adjoint_over_forward": round(bw2 / fw2, 3)},
+                   "checkpointed": {"note": f"forward intensities not kept; the reverse sweep recomputes them from "
+                                            f"per-level-chunk checkpoints every {ck} level steps",
+                                    "checkpoint_levels": ck, "forward_ms": round(fw3, 3),
+                                    "adjoint_ms": round(bw3, 3), "adjoint_over_forward": round(bw3 / fw3, 3),
+                                    "scratch_bytes": mem},
                    "grad_finite": bool(torch.isfinite(Tq.grad).all() and torch.isfinite(rq.grad).all())}
         log(f"adjoint: forward {fw_ms:.3f} ms, backward {bw_ms:.3f} ms ({reverse_mode}; level steps {bw_l:.3f}, "
-            f"persistent {bw_p:.3f}), ratio {bw_ms / fw_ms:.2f}; all-FP32: {fw2:.3f} / {bw2:.3f} ms")
+            f"persistent {bw_p:.3f}), ratio {bw_ms / fw_ms:.2f}; all-FP32: {fw2:.3f} / {bw2:.3f} ms; "
+            f"checkpointed every {ck} steps: {fw3:.3f} / {bw3:.3f} ms, scratch {mem}")
         del Tq, rq, target, T_tgt
 
     # the regular 128 x 128 x 256 grid of the same recipe (short characteristics):
@@ -493,8 +510,7 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic),
                      "algorithmic_bytes_per_launch": round(bytes_per_launch),
-                     "kernel": ("persistent_sweep_kernel<float,16,4,true>" if args.mode == "persistent"
-                                else "sweep_kernel<float,16,4>"), "bytes_per_update": round(bpu, 4),
+                     "kernel": sweep_kernel_names(args.mode, layout, 16), "bytes_per_update": round(bpu, 4),
                      "mean_launch_us": round(avg_launch_ms * 1e3, 2), "launches_per_step": launches,
                      "sweep_ms_per_step": round(sweep_ms, 4), "j_quadrature_ms": round(jr_one, 4)},
         "whole_step_effective_GBs": round(updates * (20.0 + 20.0 / nl) / (ms_step * 1e-3) / 1e9, 1),
@@ -762,12 +778,25 @@ def run_design(args):
     print(json.dumps(out))
 
 
-def lambda_counter_traffic(workload, mode):
+LAMBDA_LAYOUT_KEYS = ("record_order", "xcd_chunks", "ray_affinity", "lane_bytes", "interleave", "pipeline")
+
+
+def sweep_kernel_names(mode, layout, c):
+    """The sweep kernels one formal solution launches in this launch mode and layout."""
+    if mode == "persistent":
+        return f"persistent_sweep_kernel<float,{c},4,true>"
+    pp = layout.get("pipeline", 0)
+    if pp:
+        return f"sweep_pipe_kernel<float,{c},4,{pp}> (interior level steps) + sweep_kernel<float,{c},4>"
+    return f"sweep_kernel<float,{c},4>"
+
+
+def lambda_counter_traffic(workload, mode, layout):
     """HBM bytes per formal solution's sweep launches (rocprofv3 FETCH_SIZE x
     its copy-kernel calibration + WRITE_SIZE, summed over the launches of one
     formal solution) from the committed summary of this workload, or None when
-    it was taken on another launch mode or on kernel sources that have changed
-    since."""
+    it was taken on another launch mode, another launch layout or on kernel
+    sources that have changed since."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", f"sweep_{workload}_counters.json")
@@ -775,6 +804,9 @@ def lambda_counter_traffic(workload, mode):
         return None
     rec = json.load(open(path))
     if rec.get("launch_mode") != mode:
+        return None
+    if mode != "persistent" and ({k: rec.get("layout", {}).get(k) for k in LAMBDA_LAYOUT_KEYS}
+                                 != {k: layout.get(k) for k in LAMBDA_LAYOUT_KEYS}):
         return None
     h = hashlib.sha256()
     for f in rec.get("sources", []):
@@ -784,7 +816,7 @@ def lambda_counter_traffic(workload, mode):
     return rec["sweep_bytes_per_formal_solution"]["total"]
 
 
-def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", interleave=False, workers=16):
+def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", interleave=0, pipeline=0, workers=16):
     """Two-level Lambda iteration on 1,048,576 sites (c2) or on a batch of 48
     atmospheres of 32,768-524,288 sites (c3): 101 line wavelengths (rows padded
     to 104), 24 rays, eps = 1e-4, FP32 sweeps, FP64 line update, graph-captured
@@ -884,8 +916,12 @@ def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", int
         tuning = v.autotune(G, chi, S, J, reps=3)
         log(f"{workload}: autotune in {time.time() - t1:.1f} s, chosen {tuning['chosen']}")
         mode_pref = tuning["chosen"]["exec"]
-    elif interleave:
-        G.tune(v.VRT_TUNE_INTERLEAVE, 1)
+        layout = dict(tuning["chosen"])
+    else:
+        G.tune(v.VRT_TUNE_INTERLEAVE, interleave)
+        G.tune(v.VRT_TUNE_PIPELINE, pipeline)
+        layout = {"record_order": 1, "xcd_chunks": 8, "ray_affinity": 0, "lane_bytes": 16,
+                  "interleave": interleave, "pipeline": pipeline}
     fs_by_mode = {}
     if tuning:
         for c in tuning["candidates"]:
@@ -925,7 +961,7 @@ def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", int
     whole_bpu = 20.0 + 20.0 / nl
     sweep_bpu = sweep_bytes_per_update(nl, 4) * ld / nl  # the sweep moves ld-entry rows
     sweep_gbs = sweep_bpu * updates / (sweep_ms * 1e-3) / 1e9
-    traffic = lambda_counter_traffic(workload, mode_name)
+    traffic = lambda_counter_traffic(workload, mode_name, layout)
     del chi, S, J
     log(f"{workload}: formal solution (ms by launch mode): {fs_by_mode} -> {mode_name}: {fs_ms:.3f} ms, "
         f"{upd_s:.3e} updates/s; sweep {sweep_ms:.3f} ms ({sweep_gbs:.0f} GB/s own bytes), J {jr_one:.3f} ms")
@@ -964,13 +1000,13 @@ def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", int
         "formal_solution_ms": round(fs_ms, 3), "updates_per_s": upd_s, "launch_mode": mode_name,
         "formal_solution_ms_by_mode": {k: round(t, 3) for k, t in fs_by_mode.items()},
         "tuning": tuning["chosen"] if tuning else None,
+        "layout": {k: layout.get(k) for k in LAMBDA_LAYOUT_KEYS},
         "roofline": {
             "bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "whole_solution": {"bytes_per_update": round(whole_bpu, 3),
                                "achieved": round(upd_s * whole_bpu / 1e9, 1),
                                "frac": round(upd_s * whole_bpu / 1e9 / HBM_PEAK_GBS, 4)},
-            "sweep_kernel": {"kernel": ("persistent_sweep_kernel<float,32,4,true>" if mode_name == "persistent"
-                                        else "sweep_kernel<float,32,4>"),
+            "sweep_kernel": {"kernel": sweep_kernel_names(mode_name, layout, 32),
                              "bytes_per_update": round(sweep_bpu, 3), "sweep_ms": round(sweep_ms, 3),
                              "launches": launches, "achieved": round(sweep_gbs, 1),
                              "frac": round(sweep_gbs / HBM_PEAK_GBS, 4),
@@ -982,7 +1018,6 @@ def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", int
                                   else None),
         "iteration": res_it,
         "inputs_build_s": round(build_s, 1), "setup_s": round(setup_s, 3),
-        "interleaved_records": int(tuning["chosen"]["interleave"]) if tuning else int(bool(interleave)),
     }
     G.close()
     ctx.close()
@@ -996,7 +1031,7 @@ def run_lambda(args):
     out = lambda_block(args.workload, max_iter=args.max_iter or (20 if args.workload == "c2" else 10),
                        accel_iter=0 if args.no_accel else (1000 if args.workload == "c2" else 200),
                        mode_pref="auto" if args.mode == "auto" else args.mode, interleave=args.interleave,
-                       workers=args.workers)
+                       pipeline=args.pipeline, workers=args.workers)
     line = {"metric": "site*ray*lambda updates/s of the formal solution inside the two-level Lambda iteration",
             "value": out["updates_per_s"], "unit": "site*ray*lambda updates/s", "n_gpus": 1,
             "higher_is_better": True, "dtype": "f32",

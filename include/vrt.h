@@ -354,12 +354,39 @@ vrt_status vrt_formal_solution_noalloc(vrt_grid grid, vrt_prec prec, int32_t n_l
  *              their forward intensities when I_rays is NULL, so the scratch
  *              memory scales with g instead of n_rays (checkpointing by ray
  *              group, for memory-bound cases).
- * Enqueued, not blocking. */
+ *   checkpoint_levels  0 = keep the recomputed forward intensities of every
+ *              level step (I_rays NULL: a ray group's full rows); k > 0 =
+ *              per-level-chunk checkpoints: the level steps are cut into
+ *              chunks of k; a first forward pass keeps only the rows that a
+ *              later chunk reads (the frontier), and the reverse sweep
+ *              recomputes each chunk's rows from them just before its own
+ *              reverse steps, in one buffer the size of the largest chunk.
+ *              Forward work about doubles; the rows held drop from
+ *              group x n to (largest chunk + frontier), both much smaller for
+ *              k well below the level count. The results are bit-identical
+ *              to k = 0 with the same ray_group. Ignored when I_rays is given
+ *              (nothing is recomputed); the reverse sweep then always runs
+ *              as level-step launches. The plan (one int4 per sweep record)
+ *              is built on the host on first use for each (k, ray_group).
+ * Enqueued, not blocking (building a plan blocks). Errors: VRT_E_ARG for a
+ * negative ray_group or checkpoint_levels. */
 vrt_status vrt_formal_solution_vjp(vrt_grid grid, vrt_prec prec, int32_t n_lambda, const void *chi,
                                    const void *S, const void *I_bottom, const void *I_top,
                                    const void *I_rays, const void *dL_dI, const void *dL_dJ,
                                    void *dL_dchi, void *dL_dS, void *dL_dIbottom, void *dL_dItop,
-                                   int32_t ray_group);
+                                   int32_t ray_group, int32_t checkpoint_levels);
+
+/* Device bytes that vrt_formal_solution_vjp holds as scratch for these
+ * settings (keep_intensities != 0: the caller passes I_rays; else the forward
+ * intensities are recomputed, with checkpoint_levels as there): the adjoint
+ * rows of a ray group, the double accumulators, and the recomputed rows
+ * (a ray group's full rows, or the largest level chunk plus the frontier and
+ * the checkpoint plan). Builds the checkpoint plan when needed (host, blocks).
+ * Lets a caller pick ray_group and checkpoint_levels for a memory budget.
+ * Errors: VRT_E_ARG (bad arguments, regular grid), VRT_E_STATE (rays not set). */
+vrt_status vrt_formal_solution_vjp_scratch(vrt_grid grid, vrt_prec prec, int32_t n_lambda,
+                                           int32_t keep_intensities, int32_t ray_group,
+                                           int32_t checkpoint_levels, int64_t *bytes);
 
 /* Adjoint of vrt_emergent_gather: writes dL_dI (device [n_rays][n][n_lambda])
  * with dL_dIem (device, layout of vrt_emergent_gather's output) at the

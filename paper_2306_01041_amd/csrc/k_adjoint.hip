@@ -74,7 +74,9 @@ template <typename T, int V> struct CoherentRows {
 // The reverse update of one record (site k of one ray) for the wavelengths
 // l0, l0 + C V, ...: gather from the dependents, then the own segments.
 // Rows: the adjoint rows of the record's ray (dependents read, own written).
-template <typename T, int C, int V, typename Rows>
+// With CK the forward rows come from checkpoint buffers (see ck_rows) instead
+// of I at the site's index.
+template <typename T, int C, int V, typename Rows, bool CK = false>
 __device__ __forceinline__ void reverse_record(const int4 q, const typename vrt::RecOf<T>::type *__restrict__ rf,
                                                int64_t rec, int l0, int32_t nl, int64_t n, int32_t ray0,
                                                const int64_t *__restrict__ dep_ptr,
@@ -83,14 +85,28 @@ __device__ __forceinline__ void reverse_record(const int4 q, const typename vrt:
                                                const T *__restrict__ chi, const T *__restrict__ S,
                                                const T *__restrict__ I, const T *__restrict__ gI,
                                                const T *__restrict__ gJ, const double *__restrict__ ray_w,
-                                               const Rows &rows, T *__restrict__ Sbar, T *__restrict__ Cbar) {
+                                               const Rows &rows, T *__restrict__ Sbar, T *__restrict__ Cbar,
+                                               const int4 *__restrict__ ck = nullptr, const T *Ich = nullptr,
+                                               const T *Ifr = nullptr) {
   using L = ALane<T, V>;
   using VT = typename L::type;
   const int32_t k = q.x, k1 = q.y, k2 = q.z, ray = q.w >> 1;
   const int64_t nn = n * nl;
   const int64_t loc = (int64_t)(ray - ray0) * nn;  // this ray in the group scratch
-  const T *Ir = I + loc;
   const int64_t bk = (int64_t)k * nl;
+  // the forward rows of the site and of its two upwind sites
+  const T *Iown, *Iup1, *Iup2;
+  if constexpr (CK) {
+    const int4 t = ck[rec];
+    Iown = Ich + (int64_t)t.x * nl;
+    Iup1 = t.z >= 0 ? Ich + (int64_t)t.z * nl : Ifr + (int64_t)(-t.z - 1) * nl;
+    Iup2 = t.w >= 0 ? Ich + (int64_t)t.w * nl : Ifr + (int64_t)(-t.w - 1) * nl;
+  } else {
+    const T *Ir = I + loc;
+    Iown = Ir + bk;
+    Iup1 = Ir + (int64_t)(k1 >= 0 ? k1 : 0) * nl;
+    Iup2 = Ir + (int64_t)(k2 >= 0 ? k2 : 0) * nl;
+  }
   const int64_t d0 = dep_ptr[(int64_t)ray * (n + 1) + k], d1 = dep_ptr[(int64_t)ray * (n + 1) + k + 1];
   const T wr = (T)ray_w[ray];
   const bool own = k1 >= 0;
@@ -99,7 +115,7 @@ __device__ __forceinline__ void reverse_record(const int4 q, const typename vrt:
   const bool two = k2 >= 0;
   const T w1 = two ? (T)f.w1 : T(1), w2 = T(1) - (T)f.w1;
   for (int l = l0; l < nl; l += C * V) {
-    const VT ck = L::load(chi + bk + l), sk = L::load(S + bk + l), ik = L::load(Ir + bk + l);
+    const VT ck_ = L::load(chi + bk + l), sk = L::load(S + bk + l), ik = L::load(Iown + l);
     VT ib, sb, cb;
     for (int e = 0; e < V; ++e) {
       T seed = gI ? gI[(int64_t)ray * nn + bk + l + e] : T(0);
@@ -118,7 +134,7 @@ __device__ __forceinline__ void reverse_record(const int4 q, const typename vrt:
 #pragma unroll
       for (int e = 0; e < V; ++e) {
         T E, pu, p0, dp0;
-        vrt::Seg<T>::weights((L::get(ck, e) + L::get(cd, e)) * hd, E, pu, p0, dp0);
+        vrt::Seg<T>::weights((L::get(ck_, e) + L::get(cd, e)) * hd, E, pu, p0, dp0);
         const T a = L::get(ad_, e) * wd;
         L::set(ib, e, L::get(ib, e) + a * E);
         L::set(sb, e, L::get(sb, e) + a * pu);
@@ -133,11 +149,11 @@ __device__ __forceinline__ void reverse_record(const int4 q, const typename vrt:
         const T w = j == 0 ? w1 : w2;
         const T h = T(0.5) * (j == 0 ? (T)f.ds1 : (T)f.ds2);
         const int64_t bu = (int64_t)u * nl;
-        const VT cu = L::load(chi + bu + l), su = L::load(S + bu + l), iu = L::load(Ir + bu + l);
+        const VT cu = L::load(chi + bu + l), su = L::load(S + bu + l), iu = L::load((j == 0 ? Iup1 : Iup2) + l);
 #pragma unroll
         for (int e = 0; e < V; ++e) {
           T E, pu, p0, dp0;
-          vrt::Seg<T>::weights((L::get(cu, e) + L::get(ck, e)) * h, E, pu, p0, dp0);
+          vrt::Seg<T>::weights((L::get(cu, e) + L::get(ck_, e)) * h, E, pu, p0, dp0);
           const T a = L::get(ib, e) * w;
           L::set(sb, e, L::get(sb, e) + a * p0);
           const T xb = a * dI_dx(E, dp0, L::get(iu, e), L::get(su, e), L::get(sk, e));
@@ -153,15 +169,16 @@ __device__ __forceinline__ void reverse_record(const int4 q, const typename vrt:
 
 // Level-step reverse kernel: one launch per level step (in decreasing order),
 // C lanes per record, V wavelengths per lane. Scratch arrays (I, Ibar, Sbar,
-// Cbar) hold the rays [ray0, ray0 + group) of the current ray group.
-template <typename T, int C, int V>
+// Cbar) hold the rays [ray0, ray0 + group) of the current ray group; with CK
+// the forward rows come from the checkpoint buffers Ich and Ifr through ck.
+template <typename T, int C, int V, bool CK>
 __global__ __launch_bounds__(256) void reverse_kernel(
     const int4 *__restrict__ ri, const typename vrt::RecOf<T>::type *__restrict__ rf, int64_t rec_begin,
     int64_t rec_count, int32_t nl, int64_t n, int32_t ray0, const int64_t *__restrict__ dep_ptr,
     const int32_t *__restrict__ dep_site, const typename vrt::RecOf<T>::type *__restrict__ dep_rec,
     const T *__restrict__ chi, const T *__restrict__ S, const T *__restrict__ I, const T *__restrict__ gI,
     const T *__restrict__ gJ, const double *__restrict__ ray_w, T *Ibar, T *__restrict__ Sbar,
-    T *__restrict__ Cbar) {
+    T *__restrict__ Cbar, const int4 *__restrict__ ck, const T *Ich, const T *Ifr) {
   constexpr int SPW = 64 / C;
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -170,8 +187,8 @@ __global__ __launch_bounds__(256) void reverse_kernel(
   if (rec >= rec_count) return;
   const int4 q = ri[rec_begin + rec];
   const PlainRows<T, V> rows{Ibar + (int64_t)((q.w >> 1) - ray0) * n * nl};
-  reverse_record<T, C, V>(q, rf, rec_begin + rec, l0, nl, n, ray0, dep_ptr, dep_site, dep_rec, chi, S, I, gI, gJ,
-                          ray_w, rows, Sbar, Cbar);
+  reverse_record<T, C, V, PlainRows<T, V>, CK>(q, rf, rec_begin + rec, l0, nl, n, ray0, dep_ptr, dep_site, dep_rec,
+                                               chi, S, I, gI, gJ, ray_w, rows, Sbar, Cbar, ck, Ich, Ifr);
 }
 
 // Persistent reverse kernel: every level step of a ray group in one launch, the
@@ -326,26 +343,31 @@ __global__ __launch_bounds__(256) void lte_vjp_kernel(int64_t n, int32_t nl, con
 template <typename T, int C, int V>
 void launch_rc(hipStream_t s, const int4 *ri, const typename vrt::RecOf<T>::type *rf, int64_t b, int64_t c, int32_t nl,
                int64_t n, int32_t ray0, const int64_t *dp, const int32_t *ds_, const typename vrt::RecOf<T>::type *dr,
-               const T *chi, const T *S, const T *I, const T *gI, const T *gJ, const double *w, T *Ib, T *Sb, T *Cb) {
+               const T *chi, const T *S, const T *I, const T *gI, const T *gJ, const double *w, T *Ib, T *Sb, T *Cb,
+               const int4 *ck, const T *Ich, const T *Ifr) {
   constexpr int SPW = 64 / C;
   const int64_t waves = (c + SPW - 1) / SPW;
-  hipLaunchKernelGGL((reverse_kernel<T, C, V>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, ri, rf, b, c, nl,
-                     n, ray0, dp, ds_, dr, chi, S, I, gI, gJ, w, Ib, Sb, Cb);
+  auto kern = ck ? reverse_kernel<T, C, V, true> : reverse_kernel<T, C, V, false>;
+  hipLaunchKernelGGL(kern, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, ri, rf, b, c, nl, n, ray0, dp, ds_, dr,
+                     chi, S, I, gI, gJ, w, Ib, Sb, Cb, ck, Ich, Ifr);
 }
 
 template <typename T, int V>
 void launch_rv(hipStream_t s, const int4 *ri, const typename vrt::RecOf<T>::type *rf, int64_t b, int64_t c, int32_t nl,
                int64_t n, int32_t ray0, const int64_t *dp, const int32_t *ds_, const typename vrt::RecOf<T>::type *dr,
-               const T *chi, const T *S, const T *I, const T *gI, const T *gJ, const double *w, T *Ib, T *Sb, T *Cb) {
+               const T *chi, const T *S, const T *I, const T *gI, const T *gJ, const double *w, T *Ib, T *Sb, T *Cb,
+               const int4 *ck, const T *Ich, const T *Ifr) {
+#define VRT_RC(CC) launch_rc<T, CC, V>(s, ri, rf, b, c, nl, n, ray0, dp, ds_, dr, chi, S, I, gI, gJ, w, Ib, Sb, Cb, ck, Ich, Ifr)
   switch (vrt::lanes_per_record(nl / V)) {
-    case 64: launch_rc<T, 64, V>(s, ri, rf, b, c, nl, n, ray0, dp, ds_, dr, chi, S, I, gI, gJ, w, Ib, Sb, Cb); break;
-    case 32: launch_rc<T, 32, V>(s, ri, rf, b, c, nl, n, ray0, dp, ds_, dr, chi, S, I, gI, gJ, w, Ib, Sb, Cb); break;
-    case 16: launch_rc<T, 16, V>(s, ri, rf, b, c, nl, n, ray0, dp, ds_, dr, chi, S, I, gI, gJ, w, Ib, Sb, Cb); break;
-    case 8: launch_rc<T, 8, V>(s, ri, rf, b, c, nl, n, ray0, dp, ds_, dr, chi, S, I, gI, gJ, w, Ib, Sb, Cb); break;
-    case 4: launch_rc<T, 4, V>(s, ri, rf, b, c, nl, n, ray0, dp, ds_, dr, chi, S, I, gI, gJ, w, Ib, Sb, Cb); break;
-    case 2: launch_rc<T, 2, V>(s, ri, rf, b, c, nl, n, ray0, dp, ds_, dr, chi, S, I, gI, gJ, w, Ib, Sb, Cb); break;
-    default: launch_rc<T, 1, V>(s, ri, rf, b, c, nl, n, ray0, dp, ds_, dr, chi, S, I, gI, gJ, w, Ib, Sb, Cb); break;
+    case 64: VRT_RC(64); break;
+    case 32: VRT_RC(32); break;
+    case 16: VRT_RC(16); break;
+    case 8: VRT_RC(8); break;
+    case 4: VRT_RC(4); break;
+    case 2: VRT_RC(2); break;
+    default: VRT_RC(1); break;
   }
+#undef VRT_RC
 }
 
 inline unsigned nbk(int64_t work, int bs) { return (unsigned)((work + bs - 1) / bs); }
@@ -403,16 +425,18 @@ template <typename T>
 void launch_reverse(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *rf, int64_t rec_begin,
                     int64_t rec_count, int32_t nl, int64_t n, int32_t ray0, const int64_t *dep_ptr,
                     const int32_t *dep_site, const typename RecOf<T>::type *dep_rec, const T *chi, const T *S,
-                    const T *I, const T *gI, const T *gJ, const double *ray_w, T *Ibar, T *Sbar, T *Cbar) {
+                    const T *I, const T *gI, const T *gJ, const double *ray_w, T *Ibar, T *Sbar, T *Cbar,
+                    const int4 *ck, const T *Ich, const T *Ifr) {
   if (rec_count <= 0) return;
   constexpr int VW = 16 / sizeof(T);
-  const bool aligned = al16(chi) && al16(S) && al16(I) && al16(Ibar) && al16(Sbar) && al16(Cbar);
+  const bool aligned = al16(chi) && al16(S) && al16(I) && al16(Ibar) && al16(Sbar) && al16(Cbar) && al16(Ich) &&
+                       al16(Ifr);
   if (aligned && nl % VW == 0)
     launch_rv<T, VW>(s, ri, rf, rec_begin, rec_count, nl, n, ray0, dep_ptr, dep_site, dep_rec, chi, S, I, gI, gJ,
-                     ray_w, Ibar, Sbar, Cbar);
+                     ray_w, Ibar, Sbar, Cbar, ck, Ich, Ifr);
   else
     launch_rv<T, 1>(s, ri, rf, rec_begin, rec_count, nl, n, ray0, dep_ptr, dep_site, dep_rec, chi, S, I, gI, gJ,
-                    ray_w, Ibar, Sbar, Cbar);
+                    ray_w, Ibar, Sbar, Cbar, ck, Ich, Ifr);
   VRT_HIP(hipGetLastError());
 }
 
@@ -489,7 +513,7 @@ void launch_lte_vjp(hipStream_t s, int64_t n, int32_t nl, const double *lam, dou
   template void launch_reverse<T>(hipStream_t, const int4 *, const RecOf<T>::type *, int64_t, int64_t, int32_t,      \
                                   int64_t, int32_t, const int64_t *, const int32_t *, const RecOf<T>::type *,         \
                                   const T *, const T *, const T *, const T *, const T *, const double *, T *, T *,    \
-                                  T *);                                                                               \
+                                  T *, const int4 *, const T *, const T *);                                           \
   template void launch_persistent_reverse<T>(                                                                         \
       hipStream_t, const PersistItems &, int32_t, const int4 *, const RecOf<T>::type *, int32_t, int64_t, int32_t,    \
       const int64_t *, const int32_t *, const RecOf<T>::type *, const T *, const T *, const T *, const T *, const T *, \

@@ -387,6 +387,99 @@ void launch_v(hipStream_t s, const int4 *ri, const typename vrt::RecOf<T>::type 
   else launch_c<T, 1, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk, pp);
 }
 
+// Forward sweep with checkpointed intensities, for the reverse sweep: the rows
+// of one ray group do not live at their site's index but in two compact
+// buffers, a chunk buffer Ich holding the rows of the level chunk being swept
+// and a frontier buffer Ifr holding, for every later chunk, the rows it reads
+// from earlier chunks. ck[rec] = {chunk slot of the record, frontier slot or
+// -1, location of the upwind row of line 1, of line 2}; a location >= 0 is a
+// chunk slot, -(f + 1) frontier slot f. The update is the arithmetic of
+// sweep_body, so the rows are bit-identical to an unchecked sweep's.
+template <typename T, int C, int V>
+__global__ __launch_bounds__(256) void ck_sweep_kernel(const int4 *__restrict__ ri,
+                                                       const typename vrt::RecOf<T>::type *__restrict__ rf,
+                                                       const int4 *__restrict__ ck, int64_t rec_begin,
+                                                       int64_t rec_count, int32_t nl, const T *__restrict__ chi,
+                                                       const T *__restrict__ S, const T *__restrict__ Ibot,
+                                                       const T *__restrict__ Itop, T *Ich, T *Ifr) {
+  using L = Lane<T, V>;
+  using VT = typename L::type;
+  constexpr int SPW = 64 / C;
+  const int lane = threadIdx.x & 63;
+  const int l0 = (lane % C) * V;
+  const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int64_t r = wave * SPW + lane / C;
+  if (r >= rec_count) return;
+  const int64_t rec = rec_begin + r;
+  const int4 q = ri[rec];
+  const int4 t = ck[rec];
+  const int32_t site = q.x, k1 = q.y, k2 = q.z;
+  const bool up = (q.w & 1) != 0;
+  T *own = Ich + (int64_t)t.x * nl;
+  T *fr = t.y >= 0 ? Ifr + (int64_t)t.y * nl : nullptr;
+  const int64_t bi = (int64_t)site * nl;
+  if (k1 < 0) {
+    for (int l = l0; l < nl; l += C * V) {
+      VT v;
+      if (up) v = L::load(Ibot + bi + l);
+      else if (Itop) v = L::load(Itop + bi + l);
+      else v = VT(T(0));
+      L::store(own + l, v);
+      if (fr) L::store(fr + l, v);
+    }
+    return;
+  }
+  const auto f = rf[rec];
+  const T w1 = f.w1, w2 = T(1) - f.w1;
+  const T h1 = T(0.5) * f.ds1, h2 = T(0.5) * f.ds2;
+  const bool two = k2 >= 0;
+  const int64_t b1 = (int64_t)k1 * nl;
+  const int64_t b2 = (int64_t)(two ? k2 : k1) * nl;
+  const T *p1 = t.z >= 0 ? Ich + (int64_t)t.z * nl : Ifr + (int64_t)(-t.z - 1) * nl;
+  const T *p2 = t.w >= 0 ? Ich + (int64_t)t.w * nl : Ifr + (int64_t)(-t.w - 1) * nl;
+  for (int l = l0; l < nl; l += C * V) {
+    const VT ci = L::load(chi + bi + l), si = L::load(S + bi + l);
+    const VT c1 = L::load(chi + b1 + l), s1 = L::load(S + b1 + l), u1 = L::load(p1 + l);
+    VT c2, s2, u2;
+    if (two) {
+      c2 = L::load(chi + b2 + l);
+      s2 = L::load(S + b2 + l);
+      u2 = L::load(p2 + l);
+    }
+    VT out;
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      const T cik = L::get(ci, k), sik = L::get(si, k);
+      T Iv = vrt::seg_line<T>((L::get(c1, k) + cik) * h1, L::get(u1, k), L::get(s1, k), sik);
+      if (two) {
+        const T Ib = vrt::seg_line<T>((L::get(c2, k) + cik) * h2, L::get(u2, k), L::get(s2, k), sik);
+        Iv = vrt::seg_mix<T>(w1, w2, Iv, Ib);
+      }
+      L::set(out, k, Iv);
+    }
+    L::store(own + l, out);
+    if (fr) L::store(fr + l, out);
+  }
+}
+
+template <typename T, int V>
+void launch_ckv(hipStream_t s, const int4 *ri, const typename vrt::RecOf<T>::type *rf, const int4 *ck, int64_t b,
+                int64_t c, int32_t nl, const T *chi, const T *S, const T *Ibot, const T *Itop, T *Ich, T *Ifr) {
+#define VRT_CKC(CC)                                                                                                  \
+  hipLaunchKernelGGL((ck_sweep_kernel<T, CC, V>), dim3((unsigned)(((c + 64 / CC - 1) / (64 / CC) + 3) / 4)),        \
+                     dim3(256), 0, s, ri, rf, ck, b, c, nl, chi, S, Ibot, Itop, Ich, Ifr)
+  switch (vrt::lanes_per_record(nl / V)) {
+    case 64: VRT_CKC(64); break;
+    case 32: VRT_CKC(32); break;
+    case 16: VRT_CKC(16); break;
+    case 8: VRT_CKC(8); break;
+    case 4: VRT_CKC(4); break;
+    case 2: VRT_CKC(2); break;
+    default: VRT_CKC(1); break;
+  }
+#undef VRT_CKC
+}
+
 // 16-byte lane vectors when the row length allows (and rows then stay 16-byte aligned)
 template <typename T> constexpr int kVec = 16 / sizeof(T);
 
@@ -413,6 +506,20 @@ void launch_sweep(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *
                          pipe);
   else
     launch_v<T, 1>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I, xcd_chunks, ray0, xtab, xk, 0);
+  VRT_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_sweep_ck(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *rf, const int4 *ck,
+                     int64_t rec_begin, int64_t rec_count, int32_t nl, const T *chi, const T *S, const T *Ibot,
+                     const T *Itop, T *Ich, T *Ifr) {
+  if (rec_count <= 0) return;
+  const bool aligned =
+      aligned16(chi) && aligned16(S) && aligned16(Ibot) && aligned16(Itop) && aligned16(Ich) && aligned16(Ifr);
+  if (aligned && nl % kVec<T> == 0)
+    launch_ckv<T, kVec<T>>(s, ri, rf, ck, rec_begin, rec_count, nl, chi, S, Ibot, Itop, Ich, Ifr);
+  else
+    launch_ckv<T, 1>(s, ri, rf, ck, rec_begin, rec_count, nl, chi, S, Ibot, Itop, Ich, Ifr);
   VRT_HIP(hipGetLastError());
 }
 
@@ -447,6 +554,12 @@ template void launch_sweep<float>(hipStream_t, const int4 *, const RecF32 *, int
 template void launch_sweep<double>(hipStream_t, const int4 *, const RecF64 *, int64_t, int64_t, int32_t, int64_t,
                                    const double *, const double *, const double *, const double *, double *, int32_t,
                                    int32_t, const int64_t *, int32_t, int32_t, int32_t);
+template void launch_sweep_ck<float>(hipStream_t, const int4 *, const RecF32 *, const int4 *, int64_t, int64_t,
+                                     int32_t, const float *, const float *, const float *, const float *, float *,
+                                     float *);
+template void launch_sweep_ck<double>(hipStream_t, const int4 *, const RecF64 *, const int4 *, int64_t, int64_t,
+                                      int32_t, const double *, const double *, const double *, const double *,
+                                      double *, double *);
 template void launch_jreduce<float>(hipStream_t, const float *, int32_t, int64_t, const double *, float *, bool,
                                     const int32_t *);
 template void launch_jreduce<double>(hipStream_t, const double *, int32_t, int64_t, const double *, double *,

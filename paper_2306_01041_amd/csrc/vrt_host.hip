@@ -493,6 +493,7 @@ void set_rays_voronoi(vrt_grid g) {
   if (g->interleave) build_interleaved(g);
   g->down_built = false;
   if (g->segment) build_downwind(g);
+  g->ck_levels = 0;  // the checkpoint table names record indices
 }
 
 template <typename T> T *intensity_buffer(vrt_grid g, int32_t nl, void *I_rays) {
@@ -838,6 +839,85 @@ void build_dependents(vrt_grid g) {
   g->deps_built = true;
 }
 
+// Checkpoint plan of the reverse sweep for level chunks of K steps (chunk c =
+// steps [cK, cK + K)) and ray groups of `group` rays. Within a group, the
+// records of one chunk get consecutive chunk slots (the chunk buffer holds one
+// chunk's rows at a time), and every (ray, site) whose row is read by a record
+// of a later chunk gets a frontier slot (its row is kept for the rest of the
+// reverse sweep). A record's upwind row lies in the chunk buffer when the
+// upwind site is in the same chunk, else in the frontier buffer (upwind sites
+// sit at lower level steps, so never in a later chunk). Host work O(R n).
+void build_checkpoints(vrt_grid g, int32_t K, int32_t group) {
+  if (g->ck_levels == K && g->ck_group == group) return;
+  const int64_t n = g->n;
+  const int32_t R = g->R, NS = g->n_steps;
+  hipStream_t s = g->ctx->stream;
+  std::vector<int4> ri((size_t)g->n_rec);
+  VRT_HIP(hipMemcpyAsync(ri.data(), g->d_ri.p, ri.size() * sizeof(int4), hipMemcpyDeviceToHost, s));
+  VRT_HIP(hipStreamSynchronize(s));
+  std::vector<int4> tab((size_t)g->n_rec, make_int4(0, -1, 0, 0));
+  std::vector<int64_t> rec_of;
+  std::vector<int32_t> chunk_of, fslot;
+  int64_t max_rows = 0, max_front = 0;
+  for (int32_t r0 = 0; r0 < R; r0 += group) {
+    const int32_t gc = std::min(group, R - r0);
+    const size_t GN = (size_t)gc * (size_t)n;
+    rec_of.assign(GN, -1);
+    chunk_of.assign(GN, 0);
+    fslot.assign(GN, -1);
+    // chunk slots, and the record and chunk of every (ray, site) of the group
+    for (int32_t c0 = 0; c0 < NS; c0 += K) {
+      int64_t slot = 0;
+      for (int32_t st = c0; st < std::min(c0 + K, NS); ++st)
+        for (int32_t r = r0; r < r0 + gc; ++r) {
+          const int64_t b = g->seg_off[(size_t)st * R + r], c = g->seg_cnt[(size_t)st * R + r];
+          for (int64_t rec = b; rec < b + c; ++rec) {
+            const size_t key = (size_t)(r - r0) * (size_t)n + (size_t)ri[(size_t)rec].x;
+            rec_of[key] = rec;
+            chunk_of[key] = c0 / K;
+            tab[(size_t)rec].x = (int32_t)slot++;
+          }
+        }
+      max_rows = std::max(max_rows, slot);
+    }
+    for (size_t key = 0; key < GN; ++key)
+      if (rec_of[key] < 0) fail(VRT_E_STATE, "the schedule misses a site of ray %d", r0 + (int32_t)(key / (size_t)n));
+    // frontier rows: read from a later chunk
+    for (size_t key = 0; key < GN; ++key) {
+      const int4 q = ri[(size_t)rec_of[key]];
+      const size_t base = key - key % (size_t)n;
+      for (int32_t u : {q.y, q.z})
+        if (u >= 0 && chunk_of[base + (size_t)u] < chunk_of[key]) fslot[base + (size_t)u] = 0;
+    }
+    int64_t front = 0;
+    for (size_t key = 0; key < GN; ++key)
+      if (fslot[key] == 0) fslot[key] = (int32_t)(front++) + 1;  // stored + 1 until the table is written
+    max_front = std::max(max_front, front);
+    for (size_t key = 0; key < GN; ++key) {
+      const int64_t rec = rec_of[key];
+      const int4 q = ri[(size_t)rec];
+      const size_t base = key - key % (size_t)n;
+      int4 &t = tab[(size_t)rec];
+      t.y = fslot[key] > 0 ? fslot[key] - 1 : -1;
+      auto loc = [&](int32_t u) -> int32_t {
+        if (u < 0) return 0;
+        const size_t ku = base + (size_t)u;
+        if (chunk_of[ku] == chunk_of[key]) return tab[(size_t)rec_of[ku]].x;
+        return -fslot[ku];  // -(frontier slot + 1)
+      };
+      t.z = loc(q.y);
+      t.w = q.z >= 0 ? loc(q.z) : t.z;
+    }
+  }
+  if (max_rows > INT32_MAX || max_front >= INT32_MAX) fail(VRT_E_ARG, "checkpoint buffers above 2^31 rows");
+  upload(g->d_ck, tab.data(), tab.size(), s);
+  VRT_HIP(hipStreamSynchronize(s));
+  g->ck_levels = K;
+  g->ck_group = group;
+  g->ck_chunk_rows = max_rows;
+  g->ck_front_rows = max_front;
+}
+
 // Wave items of the persistent reverse sweep of rays [r0, r0 + gc) for `spw`
 // records per wave: the (level step, ray) segments in decreasing step order,
 // each cut separately; cnt holds the record count + 256 x (ray - r0).
@@ -879,7 +959,7 @@ template <> const vrt::RecF64 *dep_records<double>(vrt_grid g) { return g->d_dep
 template <typename T>
 void formal_solution_vjp(vrt_grid g, int32_t nl, const T *chi, const T *S, const T *Ib, const T *It,
                          const T *I_rays, const T *gI, const T *gJ, T *o_chi, T *o_S, T *o_Ib, T *o_It,
-                         int32_t group) {
+                         int32_t group, int32_t ckpt) {
   build_dependents(g);
   hipStream_t s = g->ctx->stream;
   const int64_t n = g->n;
@@ -887,7 +967,19 @@ void formal_solution_vjp(vrt_grid g, int32_t nl, const T *chi, const T *S, const
   const int64_t nn = n * nl;
   if (group <= 0 || group > R) group = R;
   const size_t gbytes = (size_t)group * (size_t)nn * sizeof(T);
-  if (!I_rays) g->d_vI.alloc(gbytes);
+  // level-chunk checkpoints replace the group's full forward rows
+  const bool ck = !I_rays && ckpt > 0;
+  T *Ich = nullptr, *Ifr = nullptr;
+  if (ck) {
+    build_checkpoints(g, std::min(ckpt, std::max(g->n_steps, 1)), group);
+    g->d_vI.release();
+    g->d_vIch.alloc((size_t)std::max<int64_t>(g->ck_chunk_rows, 1) * (size_t)nl * sizeof(T));
+    g->d_vIfr.alloc((size_t)std::max<int64_t>(g->ck_front_rows, 1) * (size_t)nl * sizeof(T));
+    Ich = g->d_vIch.as<T>();
+    Ifr = g->d_vIfr.as<T>();
+  } else if (!I_rays) {
+    g->d_vI.alloc(gbytes);
+  }
   g->d_vIbar.alloc(gbytes);
   g->d_vSbar.alloc(gbytes);
   g->d_vCbar.alloc(gbytes);
@@ -906,6 +998,38 @@ void formal_solution_vjp(vrt_grid g, int32_t nl, const T *chi, const T *S, const
       const int32_t rl = r0 + gc - 1;
       c = g->seg_off[(size_t)st * R + rl] + g->seg_cnt[(size_t)st * R + rl] - b;
     };
+    if (ck) {
+      // forward over every step, keeping the frontier rows (and the last
+      // chunk's rows in the chunk buffer); then chunk by chunk downwards:
+      // recompute the chunk's rows from the frontier, then its reverse steps
+      const int4 *tab = g->d_ck.as<int4>();
+      const int32_t K = g->ck_levels;
+      for (int32_t st = 0; st < g->n_steps; ++st) {
+        int64_t b, c;
+        seg(st, b, c);
+        vrt::launch_sweep_ck<T>(s, ri, rf, tab, b, c, nl, chi, S, Ib, It, Ich, Ifr);
+      }
+      const int32_t last = g->n_steps > 0 ? (g->n_steps - 1) / K : 0;
+      for (int32_t cc = last; cc >= 0; --cc) {
+        const int32_t s0 = cc * K, s1 = std::min(s0 + K, g->n_steps);
+        if (cc != last)
+          for (int32_t st = s0; st < s1; ++st) {
+            int64_t b, c;
+            seg(st, b, c);
+            vrt::launch_sweep_ck<T>(s, ri, rf, tab, b, c, nl, chi, S, Ib, It, Ich, Ifr);
+          }
+        for (int32_t st = s1 - 1; st >= s0; --st) {
+          int64_t b, c;
+          seg(st, b, c);
+          vrt::launch_reverse<T>(s, ri, rf, b, c, nl, n, r0, g->d_dep_ptr.as<int64_t>(),
+                                 g->d_dep_site.as<int32_t>(), dep_records<T>(g), chi, S, Ich, gI, gJ,
+                                 g->d_w.as<double>(), Ibar, Sbar, Cbar, tab, Ich, Ifr);
+        }
+      }
+      vrt::launch_reverse_reduce<T>(s, n, nl, r0, gc, g->d_dirs.as<double>(), g->d_wall.as<uint8_t>(), Ibar, Sbar,
+                                    Cbar, acc, acc + nn, acc + 2 * nn, acc + 3 * nn);
+      continue;
+    }
     const T *Ifw;
     if (I_rays) {
       Ifw = I_rays + (size_t)r0 * (size_t)nn;
@@ -1804,10 +1928,11 @@ vrt_status vrt_two_level_solve_batched(vrt_grid g, vrt_prec prec, vrt_exec exec,
 vrt_status vrt_formal_solution_vjp(vrt_grid g, vrt_prec prec, int32_t n_lambda, const void *chi, const void *S,
                                    const void *I_bottom, const void *I_top, const void *I_rays, const void *dL_dI,
                                    const void *dL_dJ, void *dL_dchi, void *dL_dS, void *dL_dIbottom, void *dL_dItop,
-                                   int32_t ray_group) {
+                                   int32_t ray_group, int32_t checkpoint_levels) {
   if (!g) return VRT_E_ARG;
   return guarded(g->ctx, [&] {
-    if (!valid_prec(prec) || n_lambda <= 0 || ray_group < 0) fail(VRT_E_ARG, "bad precision, n_lambda or ray group");
+    if (!valid_prec(prec) || n_lambda <= 0 || ray_group < 0 || checkpoint_levels < 0)
+      fail(VRT_E_ARG, "bad precision, n_lambda, ray group or checkpoint interval");
     if (g->kind != 0) fail(VRT_E_ARG, "the reverse sweep exists for Voronoi grids only");
     if (g->segment) fail(VRT_E_ARG, "the reverse sweep differentiates the linear segment only");
     if (g->R == 0) fail(VRT_E_STATE, "rays not set");
@@ -1819,14 +1944,41 @@ vrt_status vrt_formal_solution_vjp(vrt_grid g, vrt_prec prec, int32_t n_lambda, 
       const T *ib = I_bottom ? (const T *)I_bottom : (const T *)S;
       formal_solution_vjp<T>(g, n_lambda, (const T *)chi, (const T *)S, ib, (const T *)I_top, (const T *)I_rays,
                              (const T *)dL_dI, (const T *)dL_dJ, (T *)dL_dchi, (T *)dL_dS, (T *)dL_dIbottom,
-                             (T *)dL_dItop, ray_group);
+                             (T *)dL_dItop, ray_group, checkpoint_levels);
     } else {
       using T = double;
       const T *ib = I_bottom ? (const T *)I_bottom : (const T *)S;
       formal_solution_vjp<T>(g, n_lambda, (const T *)chi, (const T *)S, ib, (const T *)I_top, (const T *)I_rays,
                              (const T *)dL_dI, (const T *)dL_dJ, (T *)dL_dchi, (T *)dL_dS, (T *)dL_dIbottom,
-                             (T *)dL_dItop, ray_group);
+                             (T *)dL_dItop, ray_group, checkpoint_levels);
     }
+    return VRT_OK;
+  });
+}
+
+vrt_status vrt_formal_solution_vjp_scratch(vrt_grid g, vrt_prec prec, int32_t n_lambda, int32_t keep_intensities,
+                                           int32_t ray_group, int32_t checkpoint_levels, int64_t *bytes) {
+  if (!g) return VRT_E_ARG;
+  return guarded(g->ctx, [&] {
+    if (!valid_prec(prec) || n_lambda <= 0 || ray_group < 0 || checkpoint_levels < 0 || !bytes)
+      fail(VRT_E_ARG, "bad precision, n_lambda, ray group, checkpoint interval or output");
+    if (g->kind != 0) fail(VRT_E_ARG, "the reverse sweep exists for Voronoi grids only");
+    if (g->R == 0) fail(VRT_E_STATE, "rays not set");
+    const int64_t n = g->n, nl = n_lambda;
+    const int64_t el = prec == VRT_F32 ? 4 : 8;
+    const int32_t group = ray_group <= 0 || ray_group > g->R ? g->R : ray_group;
+    int64_t rows = 3 * (int64_t)group * n;  // adjoint, S and chi contributions of a ray group
+    int64_t extra = 4 * n * nl * 8;         // double accumulators
+    if (!keep_intensities) {
+      if (checkpoint_levels > 0 && n > 0) {
+        build_checkpoints(g, std::min(checkpoint_levels, std::max(g->n_steps, 1)), group);
+        rows += std::max<int64_t>(g->ck_chunk_rows, 1) + std::max<int64_t>(g->ck_front_rows, 1);
+        extra += g->n_rec * (int64_t)sizeof(int4);
+      } else {
+        rows += (int64_t)group * n;
+      }
+    }
+    *bytes = rows * nl * el + extra;
     return VRT_OK;
   });
 }

@@ -238,6 +238,13 @@ struct vrt_grid_s {
   vrt::DevBuf d_dep_ptr, d_dep_site, d_dep_rf32, d_dep_rf64;
   bool deps_built = false;
   vrt::DevBuf d_vI, d_vIbar, d_vSbar, d_vCbar, d_vacc;
+  // checkpointed forward intensities of the reverse sweep: per record
+  // {chunk slot, frontier slot or -1, upwind row locations} for level chunks
+  // of ck_levels steps and ray groups of ck_group rays (0 = not built), the
+  // row counts of the chunk and frontier buffers, and the buffers
+  vrt::DevBuf d_ck, d_vIch, d_vIfr;
+  int32_t ck_levels = 0, ck_group = 0;
+  int64_t ck_chunk_rows = 0, ck_front_rows = 0;
 
   // final synthesis on a regular grid: per-point packed line data and the
   // nearest-site walk's error flag
@@ -290,6 +297,14 @@ void launch_sweep(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *
                   int64_t rec_count, int32_t nl, int64_t n, const T *chi, const T *S, const T *Ibot,
                   const T *Itop, T *I, int32_t xcd_chunks, int32_t ray0, const int64_t *xtab = nullptr,
                   int32_t xk = 0, int32_t lane_bytes = 16, int32_t pipe = 0);
+// Forward sweep of records [rec_begin, rec_begin + rec_count) with checkpointed
+// rows: ck[rec] = {chunk slot, frontier slot or -1, upwind location of line 1,
+// of line 2} (location >= 0: chunk slot in Ich; -(f + 1): frontier slot f in
+// Ifr); rows of nl entries. Same arithmetic as launch_sweep.
+template <typename T>
+void launch_sweep_ck(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *rf, const int4 *ck,
+                     int64_t rec_begin, int64_t rec_count, int32_t nl, const T *chi, const T *S, const T *Ibot,
+                     const T *Itop, T *Ich, T *Ifr);
 // abs_rows: I holds sign-encoded rows (read as |I|); then err is the persistent
 // sweep's device error word, and a set word makes the outputs NaN (the rows
 // are not the current epoch's)
@@ -347,7 +362,8 @@ template <typename T>
 void launch_reverse(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *rf, int64_t rec_begin,
                     int64_t rec_count, int32_t nl, int64_t n, int32_t ray0, const int64_t *dep_ptr,
                     const int32_t *dep_site, const typename RecOf<T>::type *dep_rec, const T *chi, const T *S,
-                    const T *I, const T *gI, const T *gJ, const double *ray_w, T *Ibar, T *Sbar, T *Cbar);
+                    const T *I, const T *gI, const T *gJ, const double *ray_w, T *Ibar, T *Sbar, T *Cbar,
+                    const int4 *ck = nullptr, const T *Ich = nullptr, const T *Ifr = nullptr);
 // Every level step of a ray group's reverse sweep in one launch; items from
 // the group's (step, ray) segments in decreasing step order, item_cnt =
 // count + 256 x (ray - ray0); stamps and words as for the persistent sweep.

@@ -114,7 +114,10 @@ vrt_two_level_solve_batched = _sig("vrt_two_level_solve_batched", _st,
                                     ctypes.c_int32, _i64, _d, _i32])
 vrt_formal_solution_vjp = _sig("vrt_formal_solution_vjp", _st, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp,
                                                                 _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
-                                                                ctypes.c_int32])
+                                                                ctypes.c_int32, ctypes.c_int32])
+vrt_formal_solution_vjp_scratch = _sig("vrt_formal_solution_vjp_scratch", _st,
+                                       [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)])
 vrt_emergent_scatter = _sig("vrt_emergent_scatter", _st, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp])
 vrt_lte_continuum_vjp = _sig("vrt_lte_continuum_vjp", _st, [_vp, ctypes.c_int32, ctypes.c_int32, _d, ctypes.c_double,
                                                             _vp, _vp, _vp, _vp, _vp, _vp, _vp])
@@ -488,8 +491,13 @@ def two_level_solve_batched(grid: Grid, atm_ptr, wlam, phi, chi_line, chi_cont, 
 
 
 def formal_solution_vjp(grid: Grid, chi, S, dL_dI=None, dL_dJ=None, I_bottom=None, I_top=None, I_rays=None,
-                        ray_group: int = 0):
-    """(dL/dchi, dL/dS, dL/dI_bottom, dL/dI_top) as new device tensors [n, nl]."""
+                        ray_group: int = 0, checkpoint_levels: int = 0):
+    """(dL/dchi, dL/dS, dL/dI_bottom, dL/dI_top) as new device tensors [n, nl].
+
+    Without I_rays the forward intensities are recomputed ray group by ray
+    group; checkpoint_levels = k > 0 keeps only per-level-chunk checkpoints of
+    them (chunks of k level steps) and recomputes each chunk before its
+    reverse steps: less memory, bit-identical results."""
     import torch
 
     inf = grid.info()
@@ -502,8 +510,20 @@ def formal_solution_vjp(grid: Grid, chi, S, dL_dI=None, dL_dJ=None, I_bottom=Non
     outs = [torch.empty((n, nl), dtype=chi.dtype, device=chi.device) for _ in range(4)]
     grid.ctx.check(vrt_formal_solution_vjp(grid.handle, _prec_of(chi), int(nl), _dev(chi), _dev(S), _dev(I_bottom),
                                            _dev(I_top), _dev(I_rays), _dev(dL_dI), _dev(dL_dJ),
-                                           *[_dev(o) for o in outs], int(ray_group)))
+                                           *[_dev(o) for o in outs], int(ray_group), int(checkpoint_levels)))
     return tuple(outs)
+
+
+def formal_solution_vjp_scratch(grid: Grid, dtype, n_lambda: int, keep_intensities: bool = False,
+                                ray_group: int = 0, checkpoint_levels: int = 0) -> int:
+    """Device bytes of scratch that formal_solution_vjp holds for these settings."""
+    import torch
+
+    out = ctypes.c_int64(0)
+    grid.ctx.check(vrt_formal_solution_vjp_scratch(grid.handle, VRT_F32 if dtype == torch.float32 else VRT_F64,
+                                                   int(n_lambda), 1 if keep_intensities else 0, int(ray_group),
+                                                   int(checkpoint_levels), ctypes.byref(out)))
+    return int(out.value)
 
 
 def emergent_scatter(grid: Grid, dL_dIem, dL_dI):
@@ -546,7 +566,8 @@ def _make_lte_emergent():
         the library's kernels."""
 
         @staticmethod
-        def forward(fctx, T, rho, grid, lam, kappa0, dtype, keep_intensities, ray_group, emergent_dtype):
+        def forward(fctx, T, rho, grid, lam, kappa0, dtype, keep_intensities, ray_group, emergent_dtype,
+                    checkpoint_levels):
             inf = grid.info()
             n, R = inf["n_sites"], inf["n_rays"]
             lam = np.ascontiguousarray(np.atleast_1d(lam), np.float64)
@@ -573,6 +594,7 @@ def _make_lte_emergent():
             else:
                 chi, S = chi_f, S_f
             fctx.grid, fctx.lam, fctx.kappa0, fctx.ray_group = grid, lam, kappa0, ray_group
+            fctx.checkpoint_levels = checkpoint_levels
             fctx.I = I
             fctx.save_for_backward(T, rho, chi, S)
             return em
@@ -585,9 +607,10 @@ def _make_lte_emergent():
             gI = torch.empty((inf["n_rays"], inf["n_sites"], chi.shape[1]), dtype=chi.dtype, device=chi.device)
             emergent_scatter(grid, g_em.contiguous().to(chi.dtype), gI)
             g_chi, g_S, g_Ib, _ = formal_solution_vjp(grid, chi, S, dL_dI=gI, I_rays=fctx.I,
-                                                      ray_group=fctx.ray_group)
+                                                      ray_group=fctx.ray_group,
+                                                      checkpoint_levels=fctx.checkpoint_levels)
             gT, gr = lte_continuum_vjp(grid, fctx.lam, fctx.kappa0, T, rho, g_chi, g_S, g_Ib)
-            return gT, gr, None, None, None, None, None, None, None
+            return gT, gr, None, None, None, None, None, None, None, None
 
     return LTEEmergent
 
@@ -596,7 +619,7 @@ _LTE_EMERGENT = None
 
 
 def lte_emergent(T, rho, grid: Grid, lam, kappa0, dtype=None, keep_intensities=True, ray_group=0,
-                 emergent_dtype=None):
+                 emergent_dtype=None, checkpoint_levels=0):
     """Differentiable emergent intensities [n_emergent, nl] (see LTEEmergent).
 
     dtype is the precision of the sweeps (float32 by default). emergent_dtype
@@ -608,6 +631,11 @@ def lte_emergent(T, rho, grid: Grid, lam, kappa0, dtype=None, keep_intensities=T
     intensities. Pass emergent_dtype=torch.float32 for an all-single-precision
     pipeline (faster forward, gradients good to ~1e-3 of central differences
     in that regime).
+
+    Memory: keep_intensities=False drops the forward intensities after the
+    forward pass (the backward pass recomputes them), ray_group bounds the
+    rays whose adjoint rows are held at once, and checkpoint_levels = k > 0
+    keeps only per-level-chunk checkpoints of the recomputed intensities.
     """
     import torch
 
@@ -617,7 +645,8 @@ def lte_emergent(T, rho, grid: Grid, lam, kappa0, dtype=None, keep_intensities=T
     dtype = torch.float32 if dtype is None else dtype
     if emergent_dtype is None:
         emergent_dtype = torch.float64 if dtype == torch.float32 else dtype
-    return _LTE_EMERGENT.apply(T, rho, grid, lam, kappa0, dtype, keep_intensities, ray_group, emergent_dtype)
+    return _LTE_EMERGENT.apply(T, rho, grid, lam, kappa0, dtype, keep_intensities, ray_group, emergent_dtype,
+                               checkpoint_levels)
 
 
 # ----------------------------------------------------------------------------

@@ -162,6 +162,63 @@ def test_persistent_reverse_matches_level_steps(v, ctx, case, nl, prec):
     G.close()
 
 
+@pytest.mark.parametrize("nl", [8, 64])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_level_chunk_checkpoints_are_bit_identical(v, ctx, case, nl, prec):
+    """Per-level-chunk checkpoints of the recomputed forward intensities (the
+    frontier rows a later chunk reads, and each chunk recomputed just before
+    its reverse steps) give the same bits as keeping every row, for chunks of
+    one step, a few steps and more steps than the sweep has, with and without
+    ray groups; the autograd misfit gradient is the same with and without."""
+    flush(f"vjp checkpoints nl={nl} {prec}")
+    atm, g, dirs, w, sel = case
+    lam = np.linspace(500e-9, 700e-9, nl)
+    chi, S = oracle.lte(lam, atm.kappa0, atm.T, atm.rho)
+    chi = chi * np.random.default_rng(nl + 11).uniform(0.5, 2.0, (1, nl))
+    rng = np.random.default_rng(13)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    gI = to_dev(rng.standard_normal((len(dirs), g.n, nl)), dt)
+    gJ = to_dev(rng.standard_normal((g.n, nl)), dt)
+    G = v.Grid.from_synth(ctx, g)
+    G.set_rays(dirs, w)
+    levels = G.info()["max_levels"]
+    c_d, S_d = to_dev(chi, dt), to_dev(S, dt)
+    for group in (0, 5):
+        ref = [t.cpu().numpy() for t in v.formal_solution_vjp(G, c_d, S_d, dL_dI=gI, dL_dJ=gJ, ray_group=group)]
+        for k in (1, 3, 7, levels - 1, levels, 10 * levels):
+            got = v.formal_solution_vjp(G, c_d, S_d, dL_dI=gI, dL_dJ=gJ, ray_group=group, checkpoint_levels=k)
+            for a, b in zip(got, ref):
+                assert np.array_equal(a.cpu().numpy(), b), (group, k)
+    full = v.formal_solution_vjp_scratch(G, dt, nl, keep_intensities=False, ray_group=5)
+    kept = v.formal_solution_vjp_scratch(G, dt, nl, keep_intensities=True, ray_group=5)
+    part = v.formal_solution_vjp_scratch(G, dt, nl, keep_intensities=False, ray_group=5, checkpoint_levels=7)
+    flush(f"  scratch bytes: kept {kept}, recomputed {full}, checkpointed every 7 steps {part}")
+    # the checkpointed rows (beyond the plan's 16 bytes per sweep record) are
+    # fewer than a ray group's full rows
+    plan = 16 * len(dirs) * g.n
+    assert 0 < part - kept - plan < full - kept
+    # the record order re-packs the sweep records (and so the plan)
+    G.tune(v.VRT_TUNE_RECORD_ORDER, 0)
+    G.set_rays(dirs, w)
+    ref = [t.cpu().numpy() for t in v.formal_solution_vjp(G, c_d, S_d, dL_dI=gI, ray_group=3)]
+    got = v.formal_solution_vjp(G, c_d, S_d, dL_dI=gI, ray_group=3, checkpoint_levels=4)
+    for a, b in zip(got, ref):
+        assert np.array_equal(a.cpu().numpy(), b)
+    with pytest.raises(v.VrtError):
+        v.formal_solution_vjp(G, c_d, S_d, dL_dI=gI, checkpoint_levels=-1)
+    # through autograd, with the forward intensities dropped after the forward pass
+    T0, r0 = to_dev(atm.T, torch.float64), to_dev(atm.rho, torch.float64)
+    grads = []
+    for k in (0, 5):
+        T = T0.clone().requires_grad_(True)
+        rho = r0.clone().requires_grad_(True)
+        v.lte_emergent(T, rho, G, lam, atm.kappa0, dtype=dt, keep_intensities=False, ray_group=4,
+                       checkpoint_levels=k).double().pow(2).sum().backward()
+        grads.append((T.grad.cpu().numpy(), rho.grad.cpu().numpy()))
+    assert np.array_equal(grads[0][0], grads[1][0]) and np.array_equal(grads[0][1], grads[1][1])
+    G.close()
+
+
 def test_lte_chain_rule_matches_oracle(v, ctx, case):
     flush("lte vjp")
     atm, g, dirs, w, sel = case

@@ -69,8 +69,10 @@ typedef enum { VRT_F64 = 0, VRT_F32 = 1 } vrt_prec;
  *             upwind elements it loads carry its epoch's sign; the J quadrature
  *             and vrt_emergent_gather read those rows as |I|. That encoding
  *             needs I >= 0 (S, I_bottom, I_top >= 0); a negative or NaN
- *             intensity is reported as VRT_E_NUMERIC. One ray's intensities must
- *             stay below 4 GiB (else VRT_E_ARG). Check vrt_grid_device_status
+ *             intensity is reported as VRT_E_NUMERIC. Rows pass between
+ *             wavefronts through buffer descriptors; when one ray's rows
+ *             reach 4 GiB, each access uses the descriptor of its 2 GiB window
+ *             (same results, a few more instructions per access). Check vrt_grid_device_status
  *             after synchronising to learn whether a bounded wait gave up
  *             (VRT_E_TIMEOUT) or a value could not be encoded (VRT_E_NUMERIC).
  * AUTO:       the mode vrt_grid_autotune chose for the grid (GRAPH until the
@@ -266,8 +268,8 @@ vrt_status vrt_grid_tune(vrt_grid grid, int32_t knob, int64_t value);
  * persistent sweep; `reps` replays each after one warm-up. Keeps the fastest
  * setting on the grid, including its launch mode for VRT_EXEC_AUTO, and
  * writes a one-line JSON report (host, may be NULL) of every candidate's mean
- * time in ms and the choice. A candidate that fails (e.g. the persistent
- * sweep of a ray above 4 GiB) is reported with "ms": null and skipped.
+ * time in ms and the choice. A candidate that fails (e.g. a device error of
+ * the persistent sweep) is reported with "ms": null and skipped.
  * Re-packs the sweep records when the record order changes. Blocks. */
 vrt_status vrt_grid_autotune(vrt_grid grid, vrt_prec prec, int32_t n_lambda, const void *chi,
                              const void *S, const void *I_bottom, const void *I_top, void *J,

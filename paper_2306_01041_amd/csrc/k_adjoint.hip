@@ -61,13 +61,13 @@ template <typename T, int V> struct PlainRows {
 
 // and device-scope buffer accesses for the persistent kernel (other
 // wavefronts read the rows during the launch)
-template <typename T, int V> struct CoherentRows {
-  __amdgpu_buffer_rsrc_t r;
+template <typename T, int V, bool BIG> struct CoherentRows {
+  vrt_persist::RayBlock<BIG> blk;
   __device__ __forceinline__ typename ALane<T, V>::type load(int64_t e) const {
-    return vrt_persist::row_load<typename ALane<T, V>::type>(r, (uint32_t)(e * (int64_t)sizeof(T)));
+    return blk.template load<typename ALane<T, V>::type>(e * (int64_t)sizeof(T));
   }
   __device__ __forceinline__ void store(int64_t e, const typename ALane<T, V>::type &v) const {
-    vrt_persist::row_store<typename ALane<T, V>::type>(r, (uint32_t)(e * (int64_t)sizeof(T)), v);
+    blk.template store<typename ALane<T, V>::type>(e * (int64_t)sizeof(T), v);
   }
 };
 
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(256) void reverse_kernel(
 // items) carries the epoch stamp; after writing k's adjoint row the wave
 // stamps k. The adjoint rows pass between wavefronts with the device-scope
 // policy; Sbar and Cbar are read only after the launch.
-template <typename T, int C, int V>
+template <typename T, int C, int V, bool BIG>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void persistent_reverse_kernel(
     const int4 *__restrict__ ri, const typename vrt::RecOf<T>::type *__restrict__ rf,
     const int64_t *__restrict__ item_rec, const int32_t *__restrict__ item_cnt, int64_t n_items, int32_t nl,
@@ -231,9 +231,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void pers
       const int64_t d0 = dep_ptr[(int64_t)ray * (n + 1) + k], d1 = dep_ptr[(int64_t)ray * (n + 1) + k + 1];
       bool ok = true;
       for (int64_t t = d0; t < d1 && ok; ++t) ok = vrt_persist::wait_stamp(fr + dep_site[t], epoch, err, spin_cap);
-      // the item's ray's block of the group's adjoint rows (below 4 GiB: checked by the host)
-      const CoherentRows<T, V> rows{__builtin_amdgcn_make_buffer_rsrc(
-          Ibar + (int64_t)(cr >> 8) * nn, 0, (int)(uint32_t)(nn * (int64_t)sizeof(T)), vrt_persist::kRawBufferWord3)};
+      // the item's ray's block of the group's adjoint rows (BIG: 4 GiB or more)
+      const CoherentRows<T, V, BIG> rows{
+          vrt_persist::RayBlock<BIG>(Ibar + (int64_t)(cr >> 8) * nn, nn * (int64_t)sizeof(T))};
       reverse_record<T, C, V>(q, rf, rec, l0, nl, n, ray0, dep_ptr, dep_site, dep_rec, chi, S, I, gI, gJ, ray_w,
                               rows, Sbar, Cbar);
     }
@@ -276,8 +276,8 @@ __global__ __launch_bounds__(256) void reverse_reduce_kernel(int64_t n, int32_t 
 
 template <typename T>
 __global__ void to_prec_kernel(int64_t nn, const double *__restrict__ a, T *__restrict__ out) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < nn) out[t] = (T)a[t];
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nn; t += (int64_t)gridDim.x * blockDim.x)
+    out[t] = (T)a[t];
 }
 
 // adjoint of the emergent gather: dL/dI at the emergent rows, zero elsewhere
@@ -293,8 +293,8 @@ __global__ void emergent_scatter_kernel(int64_t total, int32_t nl, int64_t n, co
 }
 
 template <typename T> __global__ void fill_kernel(int64_t count, T *__restrict__ p) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < count) p[t] = T(0);
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x)
+    p[t] = T(0);
 }
 
 // SI 2019 exact values
@@ -370,7 +370,7 @@ void launch_rv(hipStream_t s, const int4 *ri, const typename vrt::RecOf<T>::type
 #undef VRT_RC
 }
 
-inline unsigned nbk(int64_t work, int bs) { return (unsigned)((work + bs - 1) / bs); }
+inline unsigned nbk(int64_t work, int bs) { return vrt::grid_blocks(work, bs); }
 
 template <typename T, int C, int V>
 void launch_prc(hipStream_t s, const vrt::PersistItems &it, int32_t max_blocks, const int4 *ri,
@@ -379,7 +379,8 @@ void launch_prc(hipStream_t s, const vrt::PersistItems &it, int32_t max_blocks, 
                 const T *gI, const T *gJ, const double *w, T *Ib, T *Sb, T *Cb, int64_t flag_ld, int32_t *flags,
                 int32_t *words, int64_t cap) {
   if (it.spw != 64 / C) throw vrt::Error(VRT_E_STATE, "persistent item table built for another record width");
-  auto kern = persistent_reverse_kernel<T, C, V>;
+  const bool big = n * (int64_t)nl * (int64_t)sizeof(T) >= (int64_t(1) << 32);
+  auto kern = big ? persistent_reverse_kernel<T, C, V, true> : persistent_reverse_kernel<T, C, V, false>;
   int dev = 0, cus = 0, per_cu = 0;
   VRT_HIP(hipGetDevice(&dev));
   VRT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -454,8 +455,6 @@ void launch_persistent_reverse(hipStream_t s, const PersistItems &items, int32_t
                                T *Ibar, T *Sbar, T *Cbar, int64_t flag_ld, int32_t *flags, int32_t *words,
                                int64_t spin_cap) {
   if (items.n_items <= 0) return;
-  if (n * (int64_t)nl * (int64_t)sizeof(T) >= (int64_t(1) << 32))
-    throw Error(VRT_E_ARG, "persistent reverse sweep: one ray's adjoint rows exceed 4 GiB");
   constexpr int VW = 16 / sizeof(T);
   const bool aligned = al16(chi) && al16(S) && al16(I) && al16(Ibar) && al16(Sbar) && al16(Cbar);
   if (aligned && nl % VW == 0)
@@ -481,13 +480,13 @@ void launch_reverse_reduce(hipStream_t s, int64_t n, int32_t nl, int32_t ray0, i
 
 template <typename T> void launch_to_prec(hipStream_t s, int64_t nn, const double *a, T *out) {
   if (nn == 0 || !out) return;
-  hipLaunchKernelGGL(to_prec_kernel<T>, dim3(nbk(nn, 256)), dim3(256), 0, s, nn, a, out);
+  hipLaunchKernelGGL(to_prec_kernel<T>, dim3((unsigned)std::min<int64_t>((nn + 255) / 256, 65536)), dim3(256), 0, s, nn, a, out);
   VRT_HIP(hipGetLastError());
 }
 
 template <typename T> void launch_fill_zero(hipStream_t s, int64_t count, T *p) {
   if (count == 0) return;
-  hipLaunchKernelGGL(fill_kernel<T>, dim3(nbk(count, 256)), dim3(256), 0, s, count, p);
+  hipLaunchKernelGGL(fill_kernel<T>, dim3((unsigned)std::min<int64_t>((count + 255) / 256, 65536)), dim3(256), 0, s, count, p);
   VRT_HIP(hipGetLastError());
 }
 

@@ -146,13 +146,13 @@ template <typename T, int V> struct PlainRows {
     BLane<T, V>::store(base + e, v);
   }
 };
-template <typename T, int V> struct CoherentRows {
-  __amdgpu_buffer_rsrc_t r;
+template <typename T, int V, bool BIG> struct CoherentRows {
+  vrt_persist::RayBlock<BIG> blk;
   __device__ __forceinline__ typename BLane<T, V>::type load(int64_t e) const {
-    return vrt_persist::row_load<typename BLane<T, V>::type>(r, (uint32_t)(e * (int64_t)sizeof(T)));
+    return blk.template load<typename BLane<T, V>::type>(e * (int64_t)sizeof(T));
   }
   __device__ __forceinline__ void store(int64_t e, const typename BLane<T, V>::type &v) const {
-    vrt_persist::row_store<typename BLane<T, V>::type>(r, (uint32_t)(e * (int64_t)sizeof(T)), v);
+    blk.template store<typename BLane<T, V>::type>(e * (int64_t)sizeof(T), v);
   }
 };
 
@@ -277,7 +277,7 @@ __global__ __launch_bounds__(256) void bezier_sweep_kernel(
 // linear sweep. Items: (level step, ray) segments in step order, at most
 // 64 / kLanes records each; item_cnt = record count + 256 x ray. Only the
 // upwind rows pass between wavefronts (the downwind lines read S and chi).
-template <typename T, int V>
+template <typename T, int V, bool BIG>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void persistent_bezier_kernel(
     const int4 *__restrict__ ri, const typename vrt::RecOf<T>::type *__restrict__ rf,
     const int64_t *__restrict__ item_rec, const int32_t *__restrict__ item_cnt, int64_t n_items, int32_t nl,
@@ -307,10 +307,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void pers
         vrt_persist::wait_stamp(fr + k2, epoch, err, spin_cap);
     }
     if (live) {
-      // the item's ray's block of n * nl values (below 4 GiB: checked by the host)
-      const CoherentRows<T, V> rows{__builtin_amdgcn_make_buffer_rsrc(
-          I + (int64_t)(cr >> 8) * n * nl, 0, (int)(uint32_t)(n * nl * (int64_t)sizeof(T)),
-          vrt_persist::kRawBufferWord3)};
+      // the item's ray's block of n * nl values (BIG: 4 GiB or more)
+      const CoherentRows<T, V, BIG> rows{
+          vrt_persist::RayBlock<BIG>(I + (int64_t)(cr >> 8) * n * nl, n * nl * (int64_t)sizeof(T))};
       bezier_record<T, V>(q, rf, rec, l0, nl, n, q1, q2, qw1, qd1, qd2, chi, S, Ibot, Itop, rows);
     }
     // every row store of the wave has completed before any of its stamps
@@ -354,8 +353,6 @@ void launch_persistent_bezier(hipStream_t s, const PersistItems &items, int32_t 
                               int32_t *flags, int32_t *words, int64_t spin_cap) {
   if (items.n_items <= 0) return;
   if (items.spw != 64 / kLanes) throw Error(VRT_E_STATE, "persistent item table built for another record width");
-  if (n * (int64_t)nl * (int64_t)sizeof(T) >= (int64_t(1) << 32))
-    throw Error(VRT_E_ARG, "persistent sweep: one ray's intensities exceed 4 GiB; use the level-step modes");
   constexpr int VW = 16 / (int)sizeof(T);
   auto al = [](const void *p) { return p == nullptr || (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
   const bool vec = nl % VW == 0 && al(chi) && al(S) && al(Ibot) && al(Itop) && al(I);
@@ -375,8 +372,9 @@ void launch_persistent_bezier(hipStream_t s, const PersistItems &items, int32_t 
                        flag_ld, flags, words, spin_cap);
     VRT_HIP(hipGetLastError());
   };
-  if (vec) launch(persistent_bezier_kernel<T, VW>);
-  else launch(persistent_bezier_kernel<T, 1>);
+  const bool big = n * (int64_t)nl * (int64_t)sizeof(T) >= (int64_t(1) << 32);
+  if (vec) big ? launch(persistent_bezier_kernel<T, VW, true>) : launch(persistent_bezier_kernel<T, VW, false>);
+  else big ? launch(persistent_bezier_kernel<T, 1, true>) : launch(persistent_bezier_kernel<T, 1, false>);
 }
 
 template void launch_persistent_bezier<float>(hipStream_t, const PersistItems &, int32_t, const int4 *,

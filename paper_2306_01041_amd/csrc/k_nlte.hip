@@ -224,7 +224,7 @@ __global__ void check_partition_kernel(int64_t n, int32_t R, const int32_t *__re
   if (out) atomicOr(bad, 1);
 }
 
-inline unsigned nb(int64_t work, int bs) { return (unsigned)((work + bs - 1) / bs); }
+inline unsigned nb(int64_t work, int bs) { return vrt::grid_blocks(work, bs); }
 
 }  // namespace
 

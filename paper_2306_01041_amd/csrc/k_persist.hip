@@ -104,9 +104,9 @@ template <typename T> __global__ void sign_fill_kernel(T *__restrict__ p, int64_
 // every element carries the epoch's sign and is returned as |I|; the store
 // writes the epoch's sign and flags a negative or NaN value, which the encoding
 // cannot carry.
-template <typename T, typename VT, typename L, int V, bool SIGN>
-__device__ __forceinline__ VT get_row(__amdgpu_buffer_rsrc_t r, uint32_t off, bool neg, int32_t *err, int64_t cap) {
-  VT u = row_load<VT>(r, off);
+template <typename T, typename VT, typename L, int V, bool SIGN, bool BIG>
+__device__ __forceinline__ VT get_row(const RayBlock<BIG> &r, int64_t off, bool neg, int32_t *err, int64_t cap) {
+  VT u = r.template load<VT>(off);
   if constexpr (SIGN) {
     auto ready = [&](const VT &x) {
       bool ok = true;
@@ -123,7 +123,7 @@ __device__ __forceinline__ VT get_row(__amdgpu_buffer_rsrc_t r, uint32_t off, bo
         break;
       }
       __builtin_amdgcn_s_sleep(1);
-      u = row_load<VT>(r, off);
+      u = r.template load<VT>(off);
     }
 #pragma unroll
     for (int k = 0; k < V; ++k) L::set(u, k, abs_el<T>(L::get(u, k)));
@@ -131,8 +131,8 @@ __device__ __forceinline__ VT get_row(__amdgpu_buffer_rsrc_t r, uint32_t off, bo
   return u;
 }
 
-template <typename T, typename VT, typename L, int V, bool SIGN>
-__device__ __forceinline__ void put_row(__amdgpu_buffer_rsrc_t r, uint32_t off, VT v, bool neg, int32_t *err) {
+template <typename T, typename VT, typename L, int V, bool SIGN, bool BIG>
+__device__ __forceinline__ void put_row(const RayBlock<BIG> &r, int64_t off, VT v, bool neg, int32_t *err) {
   if constexpr (SIGN) {
     bool bad = false;
 #pragma unroll
@@ -144,10 +144,10 @@ __device__ __forceinline__ void put_row(__amdgpu_buffer_rsrc_t r, uint32_t off, 
     }
     if (bad) __hip_atomic_fetch_or(err, 2, __ATOMIC_RELAXED, kXScope);
   }
-  row_store<VT>(r, off, v);
+  r.template store<VT>(off, v);
 }
 
-template <typename T, int C, int V, bool SIGN>
+template <typename T, int C, int V, bool SIGN, bool BIG>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void persistent_sweep_kernel(
     const int4 *__restrict__ ri, const typename vrt::RecOf<T>::type *__restrict__ rf,
     const int64_t *__restrict__ item_rec, const int32_t *__restrict__ item_cnt, int64_t n_items, int32_t nl,
@@ -180,9 +180,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void pers
       if (wait_stamp(fr + k1, epoch, err, spin_cap) && k2 >= 0) wait_stamp(fr + k2, epoch, err, spin_cap);
     }
     if (live) {
-      // the item's ray's block of n * nl values (below 4 GiB: checked by the host)
-      const __amdgpu_buffer_rsrc_t Iray = __builtin_amdgcn_make_buffer_rsrc(
-          I + (int64_t)(cr >> 8) * n * nl, 0, (int)(uint32_t)(n * nl * (int64_t)sizeof(T)), kRawBufferWord3);
+      // the item's ray's block of n * nl values (BIG: 4 GiB or more)
+      const RayBlock<BIG> Iray(I + (int64_t)(cr >> 8) * n * nl, n * nl * (int64_t)sizeof(T));
       const int64_t bi = (int64_t)site * nl;
       if (k1 < 0) {
         for (int l = l0; l < nl; l += C * V) {
@@ -190,7 +189,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void pers
           if (up) v = L::load(Ibot + bi + l);
           else if (Itop) v = L::load(Itop + bi + l);
           else v = VT(T(0));
-          put_row<T, VT, L, V, SIGN>(Iray, (uint32_t)((bi + l) * sizeof(T)), v, neg, err);
+          put_row<T, VT, L, V, SIGN>(Iray, (bi + l) * (int64_t)sizeof(T), v, neg, err);
         }
       } else {
         const auto f = rf[rec];
@@ -202,12 +201,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void pers
         for (int l = l0; l < nl; l += C * V) {
           const VT ci = L::load(chi + bi + l), si = L::load(S + bi + l);
           const VT c1 = L::load(chi + b1 + l), s1 = L::load(S + b1 + l);
-          const VT u1 = get_row<T, VT, L, V, SIGN>(Iray, (uint32_t)((b1 + l) * sizeof(T)), neg, err, spin_cap);
+          const VT u1 = get_row<T, VT, L, V, SIGN>(Iray, (b1 + l) * (int64_t)sizeof(T), neg, err, spin_cap);
           VT c2, s2, u2;
           if (two) {
             c2 = L::load(chi + b2 + l);
             s2 = L::load(S + b2 + l);
-            u2 = get_row<T, VT, L, V, SIGN>(Iray, (uint32_t)((b2 + l) * sizeof(T)), neg, err, spin_cap);
+            u2 = get_row<T, VT, L, V, SIGN>(Iray, (b2 + l) * (int64_t)sizeof(T), neg, err, spin_cap);
           }
           VT out;
 #pragma unroll
@@ -220,7 +219,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void pers
             }
             L::set(out, k, Iv);
           }
-          put_row<T, VT, L, V, SIGN>(Iray, (uint32_t)((bi + l) * sizeof(T)), out, neg, err);
+          put_row<T, VT, L, V, SIGN>(Iray, (bi + l) * (int64_t)sizeof(T), out, neg, err);
         }
       }
     }
@@ -240,7 +239,9 @@ void launch_pc(hipStream_t s, const vrt::PersistItems &it, int32_t max_blocks, c
                const T *S, const T *Ibot, const T *Itop, T *I, int32_t *flags, int32_t *words, int64_t cap,
                bool sign) {
   if (it.spw != 64 / C) throw vrt::Error(VRT_E_STATE, "persistent item table built for another record width");
-  auto kern = sign ? persistent_sweep_kernel<T, C, V, true> : persistent_sweep_kernel<T, C, V, false>;
+  const bool big = n * (int64_t)nl * (int64_t)sizeof(T) >= (int64_t(1) << 32);
+  auto kern = sign ? (big ? persistent_sweep_kernel<T, C, V, true, true> : persistent_sweep_kernel<T, C, V, true, false>)
+                   : (big ? persistent_sweep_kernel<T, C, V, false, true> : persistent_sweep_kernel<T, C, V, false, false>);
   int dev = 0, cus = 0, per_cu = 0;
   VRT_HIP(hipGetDevice(&dev));
   VRT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -309,8 +310,6 @@ void launch_persistent_sweep(hipStream_t s, const PersistItems &items, int32_t m
                              const T *S, const T *Ibot, const T *Itop, T *I, int32_t *flags, int32_t *words,
                              int64_t spin_cap, bool sign) {
   if (items.n_items <= 0) return;
-  if (n * (int64_t)nl * (int64_t)sizeof(T) >= (int64_t(1) << 32))
-    throw Error(VRT_E_ARG, "persistent sweep: one ray's intensities exceed 4 GiB; use the level-step modes");
   constexpr int VW = 16 / sizeof(T);
   const bool aligned = al16(chi) && al16(S) && al16(Ibot) && al16(Itop) && al16(I);
   if (aligned && nl % VW == 0)

@@ -144,7 +144,7 @@ __global__ __launch_bounds__(256) void pack_kernel(int64_t n, int32_t R, int32_t
   rf64[g] = vrt::RecF64{w1[rs], ds1[rs], ds2[rs], 0.0};
 }
 
-inline unsigned nblocks(int64_t total, int bs) { return (unsigned)((total + bs - 1) / bs); }
+inline unsigned nblocks(int64_t total, int bs) { return vrt::grid_blocks(total, bs); }
 
 }  // namespace
 

@@ -435,7 +435,7 @@ __global__ __launch_bounds__(256) void vertical_kernel(int64_t ncol, int32_t nz,
   out[t] = I;
 }
 
-inline unsigned blocks_for(int64_t count, int threads = 256) { return (unsigned)((count + threads - 1) / threads); }
+inline unsigned blocks_for(int64_t count, int threads = 256) { return vrt::grid_blocks(count, threads); }
 
 }  // namespace
 

@@ -42,6 +42,42 @@ template <typename X> __device__ __forceinline__ void row_store(__amdgpu_buffer_
   }
 }
 
+// One ray's block of rows accessed with the device-scope policy, at byte
+// offsets. Below 4 GiB one descriptor covers the whole block, uniform across
+// the wavefront. Above (BIG), every access takes the descriptor of the 2 GiB
+// window holding its offset; the descriptor then differs between lanes, and
+// the compiler issues the access once per distinct window in the wavefront.
+template <bool BIG> struct RayBlock {
+  __amdgpu_buffer_rsrc_t whole;
+  char *base;
+  int64_t bytes;
+  __device__ __forceinline__ RayBlock(const void *p, int64_t nbytes)
+      : base(static_cast<char *>(const_cast<void *>(p))), bytes(nbytes) {
+    if constexpr (!BIG) whole = __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)(uint32_t)nbytes, kRawBufferWord3);
+  }
+  __device__ __forceinline__ __amdgpu_buffer_rsrc_t window(int64_t w) const {
+    const int64_t rest = bytes - (w << 31);
+    const int64_t lim = rest < 0xffffffffLL ? rest : 0xffffffffLL;
+    return __builtin_amdgcn_make_buffer_rsrc(base + (w << 31), 0, (int)(uint32_t)lim, kRawBufferWord3);
+  }
+  template <typename X> __device__ __forceinline__ X load(int64_t off) const {
+    if constexpr (BIG) {
+      const int64_t w = off >> 31;
+      return row_load<X>(window(w), (uint32_t)(off - (w << 31)));
+    } else {
+      return row_load<X>(whole, (uint32_t)off);
+    }
+  }
+  template <typename X> __device__ __forceinline__ void store(int64_t off, const X &v) const {
+    if constexpr (BIG) {
+      const int64_t w = off >> 31;
+      row_store<X>(window(w), (uint32_t)(off - (w << 31)), v);
+    } else {
+      row_store<X>(whole, (uint32_t)off, v);
+    }
+  }
+};
+
 constexpr int32_t kFrozen = 1 << 30;
 
 // Wait until *f == epoch. Returns false if the bound was exceeded or another

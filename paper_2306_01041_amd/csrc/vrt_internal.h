@@ -24,6 +24,17 @@ struct Error : std::runtime_error {
   Error(vrt_status c, const std::string &m) : std::runtime_error(m), code(c) {}
 };
 
+// Blocks of a one-dimensional grid covering `work` threads. One dispatch
+// counts its work-items in 32 bits, so a larger launch is an error here
+// instead of a silently truncated grid.
+inline unsigned grid_blocks(int64_t work, int threads) {
+  const int64_t b = (work + threads - 1) / threads;
+  if (b * (int64_t)threads > (int64_t)0xffffffffLL)
+    throw Error(VRT_E_ARG, "a launch of " + std::to_string(b * (int64_t)threads) +
+                               " work-items exceeds the 2^32 of one dispatch");
+  return (unsigned)b;
+}
+
 #define VRT_HIP(expr)                                                                  \
   do {                                                                                 \
     hipError_t e_ = (expr);                                                            \

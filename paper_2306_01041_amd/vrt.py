@@ -243,8 +243,9 @@ class Context:
             self.handle = None
         _live_contexts.discard(self)
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (bound at definition: module globals may already be gone at exit)
+        if _finalizing() or not self.handle:
             return
         try:
             self.close()
@@ -339,8 +340,8 @@ class Grid:
             vrt_grid_destroy(self.handle)
         self.handle = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing() or not self.handle:
             return
         try:
             self.close()

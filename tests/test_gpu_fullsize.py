@@ -23,7 +23,9 @@ times (FP32 sweeps, graph-launched and persistent, default launch layout):
   256 grid with the 101-point line: the nearest sites of 4,096 sampled points
   bit for bit and the mu = 1 emergent intensity of 64 sampled columns;
 * the quadratic Bezier segment on the 262,144-site grid, 64 wavelengths, FP32
-  graph-launched: J against the oracle's Bezier sweep (1e-5).
+  graph-launched: J against the oracle's Bezier sweep (1e-5);
+* one ray's rows above 4 GiB: the persistent sweeps against the level steps,
+  bit for bit.
 
 Each case prints what it is about to run and the errors it finds.
 """
@@ -451,3 +453,52 @@ def test_c1_bezier_full_size(v, ctx, c1):
     e = relerr(J.cpu().numpy(), Jo)
     flush(f"  FP32 Bezier J vs oracle: {e:.3e}")
     assert e <= 1e-5
+
+
+def test_persistent_sweeps_above_4gib_per_ray(v, ctx):
+    """One ray's rows above 4 GiB (8,487,200 lattice sites x 128 wavelengths
+    in FP32, 4.35 GB per ray, two oblique rays): the persistent forward sweep
+    (linear and Bezier segments) and the persistent reverse sweep address the
+    rows through 2 GiB windows and give the level-step results bit for bit."""
+    nx = ny = 206
+    nz = 200
+    nl = 128
+    z = np.linspace(0.0, 1.0, nz)
+    flush(f"above 4 GiB per ray: lattice {nx}x{ny}x{nz}, {nl} wavelengths")
+    g = synth.lattice_grid(nx, ny, z, dx=1.0 / nx, dy=1.0 / ny)
+    assert g.n * nl * 4 >= 1 << 32
+    th = np.radians(30.0)
+    dirs = np.array([[np.sin(th), 0.0, np.cos(th)], [-np.sin(th), 0.0, -np.cos(th)]])
+    w = np.array([0.5, 0.5])
+    G = v.Grid.from_synth(ctx, g)
+    G.set_rays(dirs, w)
+    rng = torch.Generator(device="cuda:0").manual_seed(7)
+    chi = torch.rand((g.n, nl), generator=rng, device="cuda:0", dtype=torch.float32) * 50.0 + 1.0
+    S = torch.rand((g.n, nl), generator=rng, device="cuda:0", dtype=torch.float32)
+    J = torch.empty_like(chi)
+    for seg in (0, 1):
+        G.tune(v.VRT_TUNE_SEGMENT, seg)
+        v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_GRAPH)
+        ref = J.clone()
+        J.zero_()
+        v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_PERSISTENT)
+        G.device_status()
+        flush(f"  segment {seg}: persistent equals level steps: {bool(torch.equal(J, ref))}")
+        assert torch.equal(J, ref), seg
+        del ref
+    G.tune(v.VRT_TUNE_SEGMENT, 0)
+    # the reverse sweep, one ray at a time (adjoint rows of one ray: 4.35 GB)
+    I = torch.empty((2, g.n, nl), dtype=torch.float32, device="cuda:0")
+    v.formal_solution(G, chi, S, J, I_rays=I, exec_mode=v.VRT_EXEC_GRAPH)
+    del J
+    gJ = torch.rand((g.n, nl), generator=rng, device="cuda:0", dtype=torch.float32) - 0.5
+    ref = [t.cpu() for t in v.formal_solution_vjp(G, chi, S, dL_dJ=gJ, I_rays=I, ray_group=1)[:2]]
+    torch.cuda.empty_cache()
+    G.tune(v.VRT_TUNE_REVERSE_PERSISTENT, 1)
+    got = v.formal_solution_vjp(G, chi, S, dL_dJ=gJ, I_rays=I, ray_group=1)[:2]
+    G.device_status()
+    G.tune(v.VRT_TUNE_REVERSE_PERSISTENT, 0)
+    same = [bool(torch.equal(a.cpu(), b)) for a, b in zip(got, ref)]
+    flush(f"  persistent reverse equals level steps: {same}")
+    assert all(same)
+    G.close()

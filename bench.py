@@ -139,6 +139,9 @@ def main():
                     help="processes that build the c3 batch's atmospheres (1: in this process, e.g. under a profiler)")
     ap.add_argument("--no-accel", action="store_true",
                     help="c2/c3 alone: skip the accelerated iteration to convergence (short profiler runs)")
+    ap.add_argument("--inputs-cache", default=None, metavar="DIR",
+                    help="c2/c3: read the atmospheres from DIR/<workload>.npz, or build and write them there (a "
+                         "run that reads the cache starts no worker processes)")
     ap.add_argument("--no-lambda", action="store_true",
                     help="default run: skip the c2 and c3 two-level iteration blocks")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -463,6 +466,28 @@ def main():
             log(f"regular grid {name}: {ms_r:.2f} ms -> {ur / (ms_r * 1e-3):.3e} updates/s")
             del chr_, Sr, Jr
         regular["speedup_fp32_graph"] = round(regular["fp64_plain"]["ms"] / regular["fp32_graph"]["ms"], 2)
+        # the two plane kernels (LDS-tiled upwind blocks, per-point rows) in both
+        # precisions; the default takes the tiles in FP64 and the rows in FP32
+        kernels = {}
+        for name, dt, mode in (("fp32_graph", torch.float32, v.VRT_EXEC_GRAPH),
+                               ("fp64_plain", torch.float64, v.VRT_EXEC_PLAIN)):
+            chr_ = torch.empty((len(xyz), nl), dtype=dt, device=dev)
+            Sr = torch.empty_like(chr_)
+            Jr = torch.empty_like(chr_)
+            v.lte_continuum(Gr, lam, atr.kappa0, Tr, rr, chr_, Sr)
+            for tiled, key in ((1, "lds_tiles"), (0, "rows")):
+                Gr.tune(v.VRT_TUNE_REGULAR_TILE, tiled)
+                v.formal_solution(Gr, chr_, Sr, Jr, exec_mode=mode)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(2):
+                    v.formal_solution(Gr, chr_, Sr, Jr, exec_mode=mode)
+                torch.cuda.synchronize()
+                kernels.setdefault(name, {})[key] = round((time.perf_counter() - t0) * 1e3 / 2, 3)
+            del chr_, Sr, Jr
+        Gr.tune(v.VRT_TUNE_REGULAR_TILE, 2)
+        regular["plane_kernels_ms"] = kernels
+        log(f"regular grid plane kernels (ms): {kernels}")
         if not args.no_synthesis:
             synthesis = run_synthesis(v, G, Gr, g, atm, atr, nx, ny, zr, stream)
         Gr.close()
@@ -816,29 +841,24 @@ def lambda_counter_traffic(workload, mode, layout):
     return rec["sweep_bytes_per_formal_solution"]["total"]
 
 
-def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", interleave=0, pipeline=0, workers=16):
-    """Two-level Lambda iteration on 1,048,576 sites (c2) or on a batch of 48
-    atmospheres of 32,768-524,288 sites (c3): 101 line wavelengths (rows padded
-    to 104), 24 rays, eps = 1e-4, FP32 sweeps, FP64 line update, graph-captured
-    iterations. Times the formal solution alone in the iteration's layout (the
-    launch mode that is faster of graph and persistent), a bounded number of
-    plain iterations, and the accelerated (Jacobi) iteration to convergence;
-    returns the block's dictionary, with the roofline of the formal solution on
-    two byte bases: the whole-solution model (20 B + 20 B / Nlambda per update:
-    read S and chi, write I, read-modify-write J) over the whole formal
-    solution, and the sweep kernel's own bytes (read S_i and chi_i, write I_i,
-    the record shared by the wavelengths) over the sweep launches alone."""
-    import torch
-
-    import paper_2306_01041_amd
+def lambda_inputs(workload, workers, cache_dir=None):
+    """The seeded atmospheres of a two-level workload as one union grid:
+    (grid, site offsets, T, rho, kappa0, LineSetup). With cache_dir, the grid,
+    T and rho are read from (or written to) <cache_dir>/<workload>.npz and the
+    line data are recomputed from T and rho with threads, so a run that reads
+    the cache starts no worker processes (e.g. under a profiler)."""
     import synth
-    from synth.nlte import LAMBDA0_NM, line_case
+    from synth.nlte import line_case, line_setup
 
-    v = paper_2306_01041_amd.load()
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = "cuda:0"
+    path = os.path.join(cache_dir, f"{workload}.npz") if cache_dir else None
+    if path and os.path.exists(path):
+        z = np.load(path)
+        U = synth.VoronoiGrid(xyz=z["xyz"], nbr_ptr=z["ptr"], nbr_idx=z["idx"], nbr_shift=z["shift"], wall=z["wall"],
+                              lo=z["lo"], hi=z["hi"], periodic_xy=True)
+        off, T, rho, kappa0 = z["off"], z["T"], z["rho"], float(z["kappa0"])
+        log(f"{workload}: inputs read from {path}")
+        return U, off, T, rho, kappa0, line_setup(T, rho, n_lambda=101, workers=16)
     seed = 1041
-    t0 = time.time()
     if workload == "c2":
         jobs = [(1048576, seed)]
     else:
@@ -856,24 +876,60 @@ def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", int
             for k, r in enumerate(pool.imap(line_case, jobs)):
                 made.append(r)
                 log(f"atmosphere {k + 1}/{len(jobs)}: {r[1].n} sites")
-    atms = [m[0] for m in made]
     grids = [m[1] for m in made]
-    lines = [m[2] for m in made]
-    del made
     U, off = synth.concat_grids(grids) if len(grids) > 1 else (grids[0], np.array([0, grids[0].n], np.int64))
-    T = np.concatenate([a.T for a in atms])
-    rho = np.concatenate([a.rho for a in atms])
+    T = np.concatenate([m[0].T for m in made])
+    rho = np.concatenate([m[0].rho for m in made])
+    kappa0 = float(made[0][0].kappa0)
+    if len(made) == 1:
+        line = made[0][2]
+    else:
+        line = made[0][2]
+        line.phi = np.concatenate([m[2].phi for m in made])
+        line.chi_line = np.concatenate([m[2].chi_line for m in made])
+    del made
+    if path:
+        os.makedirs(cache_dir, exist_ok=True)
+        np.savez(path, xyz=U.xyz, ptr=U.nbr_ptr, idx=U.nbr_idx, shift=U.nbr_shift, wall=U.wall, lo=U.lo, hi=U.hi,
+                 off=off, T=T, rho=rho, kappa0=kappa0)
+        log(f"{workload}: inputs written to {path}")
+    return U, off, T, rho, kappa0, line
+
+
+def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", interleave=0, pipeline=0, workers=16,
+                 cache_dir=None):
+    """Two-level Lambda iteration on 1,048,576 sites (c2) or on a batch of 48
+    atmospheres of 32,768-524,288 sites (c3): 101 line wavelengths (rows padded
+    to 104), 24 rays, eps = 1e-4, FP32 sweeps, FP64 line update, graph-captured
+    iterations. Times the formal solution alone in the iteration's layout (the
+    launch mode that is faster of graph and persistent), a bounded number of
+    plain iterations, and the accelerated (Jacobi) iteration to convergence;
+    returns the block's dictionary, with the roofline of the formal solution on
+    two byte bases: the whole-solution model (20 B + 20 B / Nlambda per update:
+    read S and chi, write I, read-modify-write J) over the whole formal
+    solution, and the sweep kernel's own bytes (read S_i and chi_i, write I_i,
+    the record shared by the wavelengths) over the sweep launches alone."""
+    import torch
+
+    import paper_2306_01041_amd
+    import synth
+    from synth.nlte import LAMBDA0_NM
+
+    v = paper_2306_01041_amd.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = "cuda:0"
+    t0 = time.time()
+    U, off, T, rho, kappa0, line = lambda_inputs(workload, workers, cache_dir)
+    n_atm = len(off) - 1
     nl = 101
-    wlam = lines[0].wlam
-    phi = torch.empty((U.n, nl), dtype=torch.float64, device=dev)
-    for j, ln in enumerate(lines):
-        phi[off[j]:off[j + 1]].copy_(torch.as_tensor(ln.phi))
-    chi_L = torch.as_tensor(np.concatenate([ln.chi_line for ln in lines]), device=dev)
-    del lines
+    wlam = line.wlam
+    phi = torch.as_tensor(line.phi, device=dev)
+    chi_L = torch.as_tensor(line.chi_line, device=dev)
+    del line
     dirs, w = synth.gauss_legendre_quadrature()
     R = len(dirs)
     build_s = time.time() - t0
-    log(f"{workload}: {len(grids)} atmosphere(s), {U.n} sites, inputs built in {build_s:.1f} s")
+    log(f"{workload}: {n_atm} atmosphere(s), {U.n} sites, inputs built in {build_s:.1f} s")
 
     ctx = v.Context(0)
     stream = torch.cuda.current_stream()
@@ -888,8 +944,7 @@ def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", int
     # one continuum constant for the batch (a recipe constant)
     chi_c = torch.empty((U.n, 1), dtype=d, device=dev)
     B = torch.empty_like(chi_c)
-    v.lte_continuum(G, lam0, atms[0].kappa0, torch.as_tensor(T, device=dev), torch.as_tensor(rho, device=dev),
-                    chi_c, B)
+    v.lte_continuum(G, lam0, kappa0, torch.as_tensor(T, device=dev), torch.as_tensor(rho, device=dev), chi_c, B)
     chi_c, B = chi_c[:, 0].contiguous(), B[:, 0].contiguous()
     eps = 1e-4
 
@@ -994,9 +1049,9 @@ def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", int
             f"iteration, {total_s:.2f} s")
     out = {
         "workload": (f"two-level Lambda iteration, " +
-                     (f"{U.n} sites" if len(grids) == 1 else f"{len(grids)} atmospheres, {U.n} sites in total") +
+                     (f"{U.n} sites" if n_atm == 1 else f"{n_atm} atmospheres, {U.n} sites in total") +
                      f", {nl} line wavelengths, {R} rays, eps {eps}, FP32 sweeps, FP64 update"),
-        "sites": U.n, "atmospheres": len(grids), "wavelengths": nl, "rays": R, "levels_max": info["max_levels"],
+        "sites": U.n, "atmospheres": n_atm, "wavelengths": nl, "rays": R, "levels_max": info["max_levels"],
         "formal_solution_ms": round(fs_ms, 3), "updates_per_s": upd_s, "launch_mode": mode_name,
         "formal_solution_ms_by_mode": {k: round(t, 3) for k, t in fs_by_mode.items()},
         "tuning": tuning["chosen"] if tuning else None,
@@ -1031,7 +1086,7 @@ def run_lambda(args):
     out = lambda_block(args.workload, max_iter=args.max_iter or (20 if args.workload == "c2" else 10),
                        accel_iter=0 if args.no_accel else (1000 if args.workload == "c2" else 200),
                        mode_pref="auto" if args.mode == "auto" else args.mode, interleave=args.interleave,
-                       pipeline=args.pipeline, workers=args.workers)
+                       pipeline=args.pipeline, workers=args.workers, cache_dir=args.inputs_cache)
     line = {"metric": "site*ray*lambda updates/s of the formal solution inside the two-level Lambda iteration",
             "value": out["updates_per_s"], "unit": "site*ray*lambda updates/s", "n_gpus": 1,
             "higher_is_better": True, "dtype": "f32",

@@ -228,6 +228,18 @@ vrt_status vrt_grid_set_rays(vrt_grid grid, int32_t n_rays, const double *dir, c
  *                           lane-vector per lane; other layouts keep the
  *                           classic kernel). Results are the same bits. */
 #define VRT_TUNE_PIPELINE 14
+/*   VRT_TUNE_REGULAR_TILE   regular grids: 1 = every plane after the first
+ *                           runs the LDS-tiled kernel (a workgroup stages the
+ *                           chi, S and I of the upwind block of an 8 x 8 tile
+ *                           of points once and interpolates all four corners
+ *                           from LDS; needs 16-byte rows), 0 = the row kernel
+ *                           (every point loads its four upwind corners, which
+ *                           neighbouring points share through the caches),
+ *                           2 = tiled in double precision, rows in single
+ *                           (on a 128 x 128 x 256 grid with 64 wavelengths
+ *                           the tiles were 5 % faster in FP64 and 12 % slower
+ *                           in FP32); identical results [2]. */
+#define VRT_TUNE_REGULAR_TILE 15
 /*   VRT_TUNE_SEGMENT        source model along a Delaunay line (Voronoi grids):
  *                           0 = linear (Sect. 2.5) [0]; 1 = quadratic Bezier
  *                           (the higher-order solver Sect. 2.5 points to, de

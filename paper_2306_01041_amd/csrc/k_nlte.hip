@@ -89,9 +89,23 @@ __global__ __launch_bounds__(256) void jbar_kernel(int64_t n, int32_t nl, int32_
       double acc[V];
 #pragma unroll
       for (int e = 0; e < V; ++e) acc[e] = 0.0;
-      for (int32_t r = 0; r < R; ++r) {
-        // each intensity is read once: non-temporal (streaming) loads
-        const VT x = __builtin_nontemporal_load(reinterpret_cast<const VT *>(I + (int64_t)r * nn + site * ld + l));
+      // rays in order, eight loads in flight before their sums (each intensity
+      // is read once: non-temporal streaming loads)
+      const T *Ip = I + site * ld + l;
+      int32_t r = 0;
+      for (; r + 8 <= R; r += 8) {
+        VT x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = __builtin_nontemporal_load(reinterpret_cast<const VT *>(Ip + (int64_t)(r + u) * nn));
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const double wr = w[r + u];
+#pragma unroll
+          for (int e = 0; e < V; ++e) acc[e] += wr * (double)x[u][e];
+        }
+      }
+      for (; r < R; ++r) {
+        const VT x = __builtin_nontemporal_load(reinterpret_cast<const VT *>(Ip + (int64_t)r * nn));
         const double wr = w[r];
 #pragma unroll
         for (int e = 0; e < V; ++e) acc[e] += wr * (double)x[e];

@@ -58,6 +58,14 @@ __device__ __forceinline__ void plane_shift(double q_over_d, int32_t np, int32_t
   shift = (int32_t)m;  // in [0, np)
 }
 
+// Bilinear interpolation with a fixed order of operations, so that the row
+// kernel and the tiled kernel round alike.
+template <typename T>
+__device__ __forceinline__ T bilin(T a00, T a10, T a01, T a11, T v00, T v10, T v01, T v11) {
+#pragma clang fp contract(off)
+  return vrt::seg_fma(a11, v11, vrt::seg_fma(a01, v01, vrt::seg_fma(a10, v10, a00 * v00)));
+}
+
 // C lanes per point, V consecutive wavelengths per lane (nl a multiple of V).
 template <typename T, int C, int V>
 __global__ __launch_bounds__(256) void regular_kernel(int32_t step, int32_t ray_begin, int32_t ray_count, int32_t nx,
@@ -125,13 +133,114 @@ __global__ __launch_bounds__(256) void regular_kernel(int32_t step, int32_t ray_
     VT out;
 #pragma unroll
     for (int e = 0; e < V; ++e) {
-      const T Iu = a00 * el<T, V>(i00, e) + a10 * el<T, V>(i10, e) + a01 * el<T, V>(i01, e) + a11 * el<T, V>(i11, e);
-      const T Su = a00 * el<T, V>(s00, e) + a10 * el<T, V>(s10, e) + a01 * el<T, V>(s01, e) + a11 * el<T, V>(s11, e);
-      const T cu = a00 * el<T, V>(x00, e) + a10 * el<T, V>(x10, e) + a01 * el<T, V>(x01, e) + a11 * el<T, V>(x11, e);
+      const T Iu = bilin<T>(a00, a10, a01, a11, el<T, V>(i00, e), el<T, V>(i10, e), el<T, V>(i01, e), el<T, V>(i11, e));
+      const T Su = bilin<T>(a00, a10, a01, a11, el<T, V>(s00, e), el<T, V>(s10, e), el<T, V>(s01, e), el<T, V>(s11, e));
+      const T cu = bilin<T>(a00, a10, a01, a11, el<T, V>(x00, e), el<T, V>(x10, e), el<T, V>(x01, e), el<T, V>(x11, e));
       set_el<T, V>(out, e, vrt::seg_line<T>((cu + el<T, V>(cm, e)) * h, Iu, Su, el<T, V>(sm, e)));
     }
     L::store(Iray + me + l, out);
   }
+}
+
+// LDS-tiled plane step (planes after the first). A workgroup owns an 8 x 8
+// tile of grid points of one ray and a chunk of 4 lane-vectors (64 bytes) of
+// their wavelengths. Because the upwind offset is the same for the whole
+// plane, the upwind points of the tile form a 9 x 9 block of the previous
+// plane; the workgroup stages chi, S and I of that block in LDS once (each
+// upwind value is used by up to four points) and then updates every point
+// from LDS, reading only its own chi and S from memory. Blocks are handed to
+// the dies in contiguous ranges of tiles, so neighbouring tiles, which share
+// the edge of their blocks, share a die's L2 (and the wavelength chunks of one
+// tile are consecutive blocks). Same arithmetic as the row kernel.
+constexpr int kTile = 8, kTileQ = 4;
+
+template <typename T>
+__global__ __launch_bounds__(256) void regular_tile_kernel(int32_t step, int32_t ray_begin, int32_t ray_count,
+                                                           int32_t nx, int32_t ny, int32_t nz, double dx, double dy,
+                                                           const double *__restrict__ z,
+                                                           const double *__restrict__ dirs, int32_t nl,
+                                                           const T *__restrict__ chi, const T *__restrict__ S, T *I,
+                                                           int32_t xcd_chunks) {
+  constexpr int V = 16 / (int)sizeof(T);
+  using L = RLane<T, V>;
+  using VT = typename L::type;
+  constexpr int RX = kTile + 1, RP = RX * RX, Q = kTileQ;
+  __shared__ VT reg[3][RP][Q];  // chi, S and I of the upwind block
+  const int32_t tiles_x = (nx + kTile - 1) / kTile, tiles_y = (ny + kTile - 1) / kTile;
+  const int64_t ntile = (int64_t)tiles_x * tiles_y;
+  const int32_t nch = (nl + Q * V - 1) / (Q * V);
+  // die-chunked block order (as in the Voronoi sweep)
+  int64_t b = blockIdx.x;
+  {
+    const int64_t nb = gridDim.x, k = xcd_chunks;
+    if (k > 1 && nb >= k) {
+      const int64_t x = b % k, jj = b / k, per = nb / k, rem = nb % k;
+      b = x * per + (x < rem ? x : rem) + jj;
+    }
+  }
+  // wavelength chunks fastest: the chunks of one tile read the same rows
+  const int32_t chunk = (int32_t)(b % nch);
+  const int64_t rest = b / nch;
+  const int64_t tile = rest % ntile;
+  const int32_t rr = (int32_t)(rest / ntile);
+  if (rr >= ray_count) return;  // uniform over the workgroup, before its barrier
+  const int32_t r = ray_begin + rr;
+  const int64_t plane = (int64_t)nx * ny;
+  const double mx = dirs[3 * r + 0], my = dirs[3 * r + 1], mz = dirs[3 * r + 2];
+  const bool up = mz > 0.0;
+  const int32_t k = up ? step : nz - 1 - step;
+  const int32_t ku = up ? k - 1 : k + 1;
+  const int64_t n = plane * nz;
+  T *Iray = I + (int64_t)r * n * nl;
+  const double ds = fabs(z[k] - z[ku]) / fabs(mz);
+  int32_t sx, sy;
+  double tx, ty;
+  plane_shift(-ds * mx / dx, nx, sx, tx);
+  plane_shift(-ds * my / dy, ny, sy, ty);
+  const int32_t x0 = (int32_t)(tile % tiles_x) * kTile, y0 = (int32_t)(tile / tiles_x) * kTile;
+  const int32_t lc = chunk * Q * V;
+  // stage the upwind block: point (a, c) of the block is grid point
+  // (x0 + sx + a, y0 + sy + c) of plane ku, periodic in x and y
+  const int64_t pu0 = (int64_t)ku * plane;
+  for (int e = threadIdx.x; e < 3 * RP * Q; e += blockDim.x) {
+    const int arr = e / (RP * Q), pq = e - arr * (RP * Q);
+    const int p = pq / Q, q = pq - p * Q;
+    const int a = p % RX, c = p / RX;
+    int32_t gx = x0 + sx + a, gy = y0 + sy + c;
+    while (gx >= nx) gx -= nx;
+    while (gy >= ny) gy -= ny;
+    const int32_t l = lc + q * V;
+    VT v = VT(T(0));
+    if (l < nl) {
+      const int64_t off = (pu0 + (int64_t)gy * nx + gx) * nl + l;
+      v = L::load((arr == 0 ? chi : arr == 1 ? S : Iray) + off);
+    }
+    reg[arr][p][q] = v;
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  const int q = t % Q, pt = t / Q;
+  const int px = pt % kTile, py = pt / kTile;
+  const int32_t i = x0 + px, j = y0 + py, l = lc + q * V;
+  if (i >= nx || j >= ny || l >= nl) return;
+  const T a00 = (T)((1.0 - tx) * (1.0 - ty)), a10 = (T)(tx * (1.0 - ty));
+  const T a01 = (T)((1.0 - tx) * ty), a11 = (T)(tx * ty);
+  const T h = (T)(0.5 * ds);
+  const int p00 = py * RX + px, p10 = p00 + 1, p01 = p00 + RX, p11 = p01 + 1;
+  const int64_t me = ((int64_t)k * plane + (int64_t)j * nx + i) * nl + l;
+  const VT cm = L::load(chi + me), sm = L::load(S + me);
+  VT out;
+#pragma unroll
+  for (int e = 0; e < V; ++e) {
+    const T Iu = bilin<T>(a00, a10, a01, a11, el<T, V>(reg[2][p00][q], e), el<T, V>(reg[2][p10][q], e),
+                          el<T, V>(reg[2][p01][q], e), el<T, V>(reg[2][p11][q], e));
+    const T Su = bilin<T>(a00, a10, a01, a11, el<T, V>(reg[1][p00][q], e), el<T, V>(reg[1][p10][q], e),
+                          el<T, V>(reg[1][p01][q], e), el<T, V>(reg[1][p11][q], e));
+    const T cu = bilin<T>(a00, a10, a01, a11, el<T, V>(reg[0][p00][q], e), el<T, V>(reg[0][p10][q], e),
+                          el<T, V>(reg[0][p01][q], e), el<T, V>(reg[0][p11][q], e));
+    set_el<T, V>(out, e, vrt::seg_line<T>((cu + el<T, V>(cm, e)) * h, Iu, Su, el<T, V>(sm, e)));
+  }
+  L::store(Iray + me, out);
 }
 
 template <typename T, int C, int V>
@@ -170,10 +279,19 @@ namespace vrt {
 template <typename T>
 void launch_regular(hipStream_t s, int32_t step, int32_t ray_begin, int32_t ray_count, int32_t nx, int32_t ny,
                     int32_t nz, double dx, double dy, const double *z, const double *dirs, int32_t nl, const T *chi,
-                    const T *S, const T *Ibot, const T *Itop, T *I) {
+                    const T *S, const T *Ibot, const T *Itop, T *I, bool tiled, int32_t xcd_chunks) {
   if (ray_count <= 0 || nx * ny == 0) return;
   constexpr int VW = 16 / sizeof(T);
   const bool aligned = al16r(chi) && al16r(S) && al16r(Ibot) && al16r(Itop) && al16r(I);
+  if (tiled && step > 0 && aligned && nl % VW == 0) {
+    const int64_t tiles = (int64_t)((nx + kTile - 1) / kTile) * ((ny + kTile - 1) / kTile);
+    const int64_t blocks = tiles * ((nl + kTileQ * VW - 1) / (kTileQ * VW)) * ray_count;
+    if (blocks >= (int64_t)1 << 31) throw Error(VRT_E_ARG, "regular grid too large for one plane launch");
+    hipLaunchKernelGGL(regular_tile_kernel<T>, dim3((unsigned)blocks), dim3(kTile * kTile * kTileQ), 0, s, step,
+                       ray_begin, ray_count, nx, ny, nz, dx, dy, z, dirs, nl, chi, S, I, xcd_chunks);
+    VRT_HIP(hipGetLastError());
+    return;
+  }
   if (aligned && nl % VW == 0)
     launch_rv<T, VW>(s, step, ray_begin, ray_count, nx, ny, nz, dx, dy, z, dirs, nl, chi, S, Ibot, Itop, I);
   else
@@ -183,9 +301,9 @@ void launch_regular(hipStream_t s, int32_t step, int32_t ray_begin, int32_t ray_
 
 template void launch_regular<float>(hipStream_t, int32_t, int32_t, int32_t, int32_t, int32_t, int32_t, double, double,
                                     const double *, const double *, int32_t, const float *, const float *,
-                                    const float *, const float *, float *);
+                                    const float *, const float *, float *, bool, int32_t);
 template void launch_regular<double>(hipStream_t, int32_t, int32_t, int32_t, int32_t, int32_t, int32_t, double, double,
                                      const double *, const double *, int32_t, const double *, const double *,
-                                     const double *, const double *, double *);
+                                     const double *, const double *, double *, bool, int32_t);
 
 }  // namespace vrt

@@ -270,13 +270,22 @@ __global__ __launch_bounds__(256) void jreduce_kernel(const T *__restrict__ I, i
     double acc[V];
 #pragma unroll
     for (int k = 0; k < V; ++k) acc[k] = 0.0;
-    for (int32_t r = 0; r < R; ++r) {
-      // each intensity is read once: non-temporal (streaming) loads
-      const VT x = __builtin_nontemporal_load(reinterpret_cast<const VT *>(I + (int64_t)r * nn + t * V));
-      const double wr = w[r];
+    // rays in order, eight loads in flight before their sums (each intensity
+    // is read once: non-temporal streaming loads)
+    auto add = [&](const VT &x, double wr) {
 #pragma unroll
       for (int k = 0; k < V; ++k) acc[k] += wr * (ABS ? __builtin_fabs((double)L::get(x, k)) : (double)L::get(x, k));
+    };
+    int32_t r = 0;
+    for (; r + 8 <= R; r += 8) {
+      VT x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        x[u] = __builtin_nontemporal_load(reinterpret_cast<const VT *>(I + (int64_t)(r + u) * nn + t * V));
+#pragma unroll
+      for (int u = 0; u < 8; ++u) add(x[u], w[r + u]);
     }
+    for (; r < R; ++r) add(__builtin_nontemporal_load(reinterpret_cast<const VT *>(I + (int64_t)r * nn + t * V)), w[r]);
     VT out;
 #pragma unroll
     for (int k = 0; k < V; ++k) L::set(out, k, (T)acc[k]);

@@ -753,7 +753,8 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
     const int64_t plane = (int64_t)g->nx * g->ny;
     auto planes = [&](int32_t st, int32_t rb, int32_t rc) {
       timed_launch(ctx, s, tm, 2, plane * rc * nl, [&] {
-        vrt::launch_regular<T>(s, st, rb, rc, g->nx, g->ny, g->nz, g->dx, g->dy, z, dirs, nl, chi, S, Ib, It, I);
+        vrt::launch_regular<T>(s, st, rb, rc, g->nx, g->ny, g->nz, g->dx, g->dy, z, dirs, nl, chi, S, Ib, It, I,
+                               g->regular_tiled == 1 || (g->regular_tiled == 2 && sizeof(T) == 8), g->xcd_chunks);
       });
     };
     if (ex == VRT_EXEC_PLAIN) {
@@ -1597,6 +1598,9 @@ vrt_status vrt_grid_tune(vrt_grid g, int32_t knob, int64_t value) {
     } else if (knob == VRT_TUNE_PIPELINE) {
       if (value != 0 && value != 2 && value != 4 && value != 8) fail(VRT_E_ARG, "pipeline depth must be 0, 2, 4 or 8");
       g->pipe = (int)value;
+    } else if (knob == VRT_TUNE_REGULAR_TILE) {
+      if (value < 0 || value > 2) fail(VRT_E_ARG, "regular tiling must be 0, 1 or 2");
+      g->regular_tiled = (int)value;
     } else if (knob == VRT_TUNE_LANE_BYTES) {
       if (value != 16 && value != 32) fail(VRT_E_ARG, "lane bytes must be 16 or 32");
       g->lane_bytes = (int)value;

@@ -75,26 +75,33 @@ def test_regular_matches_oracle(v, ctx, prec, mode, nl, shape):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_regular_modes_bitwise_equal(v, ctx, prec):
-    """One launch per ray and plane (plain) and one per plane for all rays (graph)
-    run the same per-point arithmetic, so their intensities agree bit for bit."""
-    flush(f"regular plain vs graph {prec}")
-    nx, ny, nz, nl = 13, 9, 11, 8
+@pytest.mark.parametrize("nl", [8, 24, 64])
+def test_regular_modes_bitwise_equal(v, ctx, prec, nl):
+    """One launch per ray and plane (plain) and one per plane for all rays
+    (graph), with the LDS-tiled plane kernel and with the row kernel, run the
+    same per-point arithmetic, so their intensities agree bit for bit (rows of
+    13 and 9 points: partial 8 x 8 tiles; 24 wavelengths: a partial chunk)."""
+    flush(f"regular plain vs graph, tiled vs rows {prec} nl={nl}")
+    nx, ny, nz = 13, 9, 11
     z, chi, S, Ib = _case(nx, ny, nz, nl, 5)
     dirs, w = synth.gauss_legendre_quadrature()
     G = v.Grid.regular(ctx, nx, ny, z, 0.11, 0.13)
     G.set_rays(dirs, w)
     d = torch.float64 if prec == "f64" else torch.float32
     out = {}
-    for mode in ("PLAIN", "GRAPH"):
-        J = torch.empty((nx * ny * nz, nl), dtype=d, device="cuda:0")
-        I = torch.empty((len(dirs), nx * ny * nz, nl), dtype=d, device="cuda:0")
-        v.formal_solution(G, to_dev(chi, d), to_dev(S, d), J, I_bottom=to_dev(Ib, d), I_rays=I,
-                          exec_mode=getattr(v, "VRT_EXEC_" + mode))
-        out[mode] = (J, I)
+    for tiled in (1, 0, 2):
+        G.tune(v.VRT_TUNE_REGULAR_TILE, tiled)
+        for mode in ("PLAIN", "GRAPH"):
+            J = torch.empty((nx * ny * nz, nl), dtype=d, device="cuda:0")
+            I = torch.empty((len(dirs), nx * ny * nz, nl), dtype=d, device="cuda:0")
+            v.formal_solution(G, to_dev(chi, d), to_dev(S, d), J, I_bottom=to_dev(Ib, d), I_rays=I,
+                              exec_mode=getattr(v, "VRT_EXEC_" + mode))
+            out[(tiled, mode)] = (J, I)
     torch.cuda.synchronize()
-    assert torch.equal(out["PLAIN"][1], out["GRAPH"][1])
-    assert torch.equal(out["PLAIN"][0], out["GRAPH"][0])
+    ref = out[(0, "PLAIN")]
+    for key, (J, I) in out.items():
+        assert torch.equal(I, ref[1]), key
+        assert torch.equal(J, ref[0]), key
     G.close()
 
 

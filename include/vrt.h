@@ -281,7 +281,9 @@ vrt_status vrt_grid_tune(vrt_grid grid, int32_t knob, int64_t value);
  * setting on the grid, including its launch mode for VRT_EXEC_AUTO, and
  * writes a one-line JSON report (host, may be NULL) of every candidate's mean
  * time in ms and the choice. A candidate that fails (e.g. a device error of
- * the persistent sweep) is reported with "ms": null and skipped.
+ * the persistent sweep) is reported with "ms": null and skipped. On a regular
+ * grid the candidates are the graph-launched plane steps with the row kernel
+ * and with the LDS-tiled kernel (VRT_TUNE_REGULAR_TILE 0 and 1).
  * Re-packs the sweep records when the record order changes. Blocks. */
 vrt_status vrt_grid_autotune(vrt_grid grid, vrt_prec prec, int32_t n_lambda, const void *chi,
                              const void *S, const void *I_bottom, const void *I_top, void *J,

@@ -1626,11 +1626,55 @@ vrt_status vrt_grid_autotune(vrt_grid g, vrt_prec prec, int32_t n_lambda, const 
     if (!valid_prec(prec) || n_lambda <= 0 || reps <= 0) fail(VRT_E_ARG, "bad autotune arguments");
     if (g->R == 0) fail(VRT_E_STATE, "rays not set");
     if (g->segment) fail(VRT_E_ARG, "the autotuner times the linear sweep's layouts");
-    if (g->n == 0 || g->kind != 0) return VRT_OK;
+    if (g->n == 0) return VRT_OK;
     hipStream_t s = g->ctx->stream;
     hipEvent_t e0, e1;
     VRT_HIP(hipEventCreate(&e0));
     VRT_HIP(hipEventCreate(&e1));
+    if (g->kind != 0) {
+      // regular grid: the graph-launched plane steps with the row kernel and
+      // with the LDS-tiled kernel
+      std::string rep = "{\"candidates\": [";
+      double best = 1e300;
+      int best_tile = g->regular_tiled == 1 ? 1 : 0;
+      for (int tile = 0; tile <= 1; ++tile) {
+        g->regular_tiled = tile;
+        g->drop_graphs();
+        auto run = [&] {
+          if (prec == VRT_F32)
+            formal_solution<float>(g, VRT_EXEC_GRAPH, n_lambda, chi, S, I_bottom, I_top, J, I_rays);
+          else
+            formal_solution<double>(g, VRT_EXEC_GRAPH, n_lambda, chi, S, I_bottom, I_top, J, I_rays);
+        };
+        run();  // capture + warm-up
+        VRT_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r) run();
+        VRT_HIP(hipEventRecord(e1, s));
+        VRT_HIP(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        VRT_HIP(hipEventElapsedTime(&ms, e0, e1));
+        const double mean = ms / reps;
+        char buf[160];
+        snprintf(buf, sizeof buf, "%s{\"exec\": \"graph\", \"regular_tile\": %d, \"ms\": %.5f}", tile ? ", " : "",
+                 tile, mean);
+        rep += buf;
+        if (mean < best) {
+          best = mean;
+          best_tile = tile;
+        }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      g->regular_tiled = best_tile;
+      g->tuned_exec = VRT_EXEC_GRAPH;
+      g->drop_graphs();
+      char buf[160];
+      snprintf(buf, sizeof buf, "], \"chosen\": {\"exec\": \"graph\", \"regular_tile\": %d, \"ms\": %.5f}}", best_tile,
+               best);
+      rep += buf;
+      if (report && report_len > 0) snprintf(report, (size_t)report_len, "%s", rep.c_str());
+      return VRT_OK;
+    }
     struct Cand {
       int xcd, aff, lb, il, pipe, exec;
     };

@@ -125,3 +125,27 @@ def test_lattice_voronoi_equals_regular_vertical_rays(v, ctx):
     assert relerr(Jv.cpu().numpy(), Jr.cpu().numpy()) <= 1e-13
     Gv.close()
     Gr.close()
+
+
+def test_regular_autotune_picks_a_plane_kernel(v, ctx):
+    """On a regular grid the autotuner times the row and the LDS-tiled plane
+    kernels, keeps the faster, and the results stay bit for bit the same."""
+    flush("regular autotune")
+    nx, ny, nz, nl = 24, 16, 20, 16
+    z, chi, S, Ib = _case(nx, ny, nz, nl, 9)
+    dirs, w = synth.gauss_legendre_quadrature()
+    G = v.Grid.regular(ctx, nx, ny, z, 0.11, 0.13)
+    G.set_rays(dirs, w)
+    d = torch.float32
+    c_d, S_d, Ib_d = to_dev(chi, d), to_dev(S, d), to_dev(Ib, d)
+    J = torch.empty((nx * ny * nz, nl), dtype=d, device="cuda:0")
+    v.formal_solution(G, c_d, S_d, J, I_bottom=Ib_d, exec_mode=v.VRT_EXEC_GRAPH)
+    ref = J.clone()
+    rep = v.autotune(G, c_d, S_d, J, I_bottom=Ib_d, reps=2)
+    assert [c["regular_tile"] for c in rep["candidates"]] == [0, 1]
+    assert rep["chosen"]["ms"] == min(c["ms"] for c in rep["candidates"])
+    for mode in (v.VRT_EXEC_AUTO, v.VRT_EXEC_PLAIN):
+        v.formal_solution(G, c_d, S_d, J, I_bottom=Ib_d, exec_mode=mode)
+        torch.cuda.synchronize()
+        assert torch.equal(J, ref), mode
+    G.close()

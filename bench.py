@@ -72,7 +72,8 @@ def sweep_bytes_per_update(nl: int, fp: int) -> float:
     return 3.0 * fp + (16.0 + 4.0 * fp) / nl
 
 
-LAYOUT_KEYS = ("record_order", "xcd_chunks", "ray_affinity", "chains", "lane_bytes", "interleave", "pipeline")
+LAYOUT_KEYS = ("record_order", "shared_levels", "xcd_chunks", "ray_affinity", "chains", "lane_bytes", "interleave",
+               "pipeline")
 
 
 def counter_traffic(nl, n, mode, layout):
@@ -88,7 +89,10 @@ def counter_traffic(nl, n, mode, layout):
     if nl != 64 or n != 262144 or not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    # the persistent sweep reads the per-ray record order whatever the layout knobs say
+    # the persistent sweep reads the per-ray record order whatever the layout
+    # knobs say, but its work items follow the level steps
+    if persistent and rec.get("layout", {}).get("shared_levels", 0) != layout.get("shared_levels", 0):
+        return None
     if not persistent and ({k: rec.get("layout", {}).get(k) for k in LAYOUT_KEYS}
                            != {k: layout.get(k) for k in LAYOUT_KEYS}):
         return None
@@ -119,6 +123,8 @@ def main():
     ap.add_argument("--interleave", type=int, choices=[0, 1, 2], default=0,
                     help="with a fixed layout (c1: --no-autotune; c2/c3: --mode other than auto): sweep the "
                          "interleaved record copy, in Morton order (1) or in site-index order (2)")
+    ap.add_argument("--shared-levels", type=int, choices=[0, 1], default=0,
+                    help="with a fixed layout: one level schedule for the rays of one azimuth and hemisphere")
     ap.add_argument("--pipeline", type=int, choices=[0, 2, 4, 8], default=0,
                     help="with a fixed layout: interior level steps launch the pipelined sweep kernel with this "
                          "many groups of records in flight per wavefront (0: the plain level-step kernel)")
@@ -214,11 +220,13 @@ def main():
     tuning = None if args.no_autotune else v.autotune(G, chi, S, J, reps=5)
     log(f"autotune: {tuning}")
     if tuning is None:
+        G.tune(v.VRT_TUNE_SHARED_LEVELS, args.shared_levels)
         G.tune(v.VRT_TUNE_INTERLEAVE, args.interleave)
         G.tune(v.VRT_TUNE_PIPELINE, args.pipeline)
-    layout = dict(tuning["chosen"]) if tuning else {"record_order": 1, "xcd_chunks": 8, "ray_affinity": 0,
-                                                    "chains": 1, "lane_bytes": 16,
-                                                    "interleave": args.interleave, "pipeline": args.pipeline}
+    layout = dict(tuning["chosen"]) if tuning else {"record_order": 1, "shared_levels": args.shared_levels,
+                                                    "xcd_chunks": 8, "ray_affinity": 0, "chains": 1,
+                                                    "lane_bytes": 16, "interleave": args.interleave,
+                                                    "pipeline": args.pipeline}
     mode_times = {}
     if args.mode == "auto" and tuning:
         args.mode = tuning["chosen"]["exec"]
@@ -295,9 +303,12 @@ def main():
         f"{achieved:.0f} GB/s algorithmic (counters: {traffic}); J quadrature {jr_one:.3f} ms "
         f"({jr_bytes / (jr_one * 1e-3) / 1e9:.0f} GB/s)")
 
-    # plain FP64 GPU path
+    # plain FP64 GPU path: one launch per (ray, level), on each ray's own level
+    # schedule (levels shared by a group of rays would add launches here)
     fp64 = None
     if not args.no_fp64:
+        if layout.get("shared_levels"):
+            G.tune(v.VRT_TUNE_SHARED_LEVELS, 0)
         f64 = torch.float64
         chi64 = torch.empty((g.n, nl), dtype=f64, device=dev)
         S64 = torch.empty_like(chi64)
@@ -316,8 +327,10 @@ def main():
         jerr = float(((J.double() - J64).abs() / J64.abs()).max().item())
         fp64 = {"ms_per_step": round(ms64, 3), "value": updates / (ms64 * 1e-3),
                 "speedup_fp32_batched": round(ms64 / ms_step, 2), "fp32_vs_fp64_max_rel_err_J": jerr}
-        log(f"FP64 plain step {ms64:.2f} ms; FP32 graph speed-up {ms64 / ms_step:.1f}x; FP32 J err {jerr:.2e}")
+        log(f"FP64 plain step {ms64:.2f} ms; FP32 {args.mode} speed-up {ms64 / ms_step:.1f}x; FP32 J err {jerr:.2e}")
         del chi64, S64, J64
+        if layout.get("shared_levels"):
+            G.tune(v.VRT_TUNE_SHARED_LEVELS, 1)
 
     # the quadratic Bezier segment on the same grid and fields (FP32, graph-launched)
     bezier = None
@@ -807,7 +820,8 @@ def run_design(args):
     print(json.dumps(out))
 
 
-LAMBDA_LAYOUT_KEYS = ("record_order", "xcd_chunks", "ray_affinity", "lane_bytes", "interleave", "pipeline")
+LAMBDA_LAYOUT_KEYS = ("record_order", "shared_levels", "xcd_chunks", "ray_affinity", "lane_bytes", "interleave",
+                      "pipeline")
 
 
 def sweep_kernel_names(mode, layout, c):
@@ -901,7 +915,7 @@ def lambda_inputs(workload, workers, cache_dir=None):
 
 
 def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", interleave=0, pipeline=0, workers=16,
-                 cache_dir=None):
+                 cache_dir=None, shared_levels=0):
     """Two-level Lambda iteration on 1,048,576 sites (c2) or on a batch of 48
     atmospheres of 32,768-524,288 sites (c3): 101 line wavelengths (rows padded
     to 104), 24 rays, eps = 1e-4, FP32 sweeps, FP64 line update, graph-captured
@@ -977,10 +991,11 @@ def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", int
         mode_pref = tuning["chosen"]["exec"]
         layout = dict(tuning["chosen"])
     else:
+        G.tune(v.VRT_TUNE_SHARED_LEVELS, shared_levels)
         G.tune(v.VRT_TUNE_INTERLEAVE, interleave)
         G.tune(v.VRT_TUNE_PIPELINE, pipeline)
-        layout = {"record_order": 1, "xcd_chunks": 8, "ray_affinity": 0, "lane_bytes": 16,
-                  "interleave": interleave, "pipeline": pipeline}
+        layout = {"record_order": 1, "shared_levels": shared_levels, "xcd_chunks": 8, "ray_affinity": 0,
+                  "lane_bytes": 16, "interleave": interleave, "pipeline": pipeline}
     fs_by_mode = {}
     if tuning:
         for c in tuning["candidates"]:
@@ -1090,7 +1105,8 @@ def run_lambda(args):
     out = lambda_block(args.workload, max_iter=args.max_iter or (20 if args.workload == "c2" else 10),
                        accel_iter=0 if args.no_accel else (1000 if args.workload == "c2" else 200),
                        mode_pref="auto" if args.mode == "auto" else args.mode, interleave=args.interleave,
-                       pipeline=args.pipeline, workers=args.workers, cache_dir=args.inputs_cache)
+                       pipeline=args.pipeline, workers=args.workers, cache_dir=args.inputs_cache,
+                       shared_levels=args.shared_levels)
     line = {"metric": "site*ray*lambda updates/s of the formal solution inside the two-level Lambda iteration",
             "value": out["updates_per_s"], "unit": "site*ray*lambda updates/s", "n_gpus": 1,
             "higher_is_better": True, "dtype": "f32",

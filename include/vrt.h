@@ -240,6 +240,18 @@ vrt_status vrt_grid_set_rays(vrt_grid grid, int32_t n_rays, const double *dir, c
  *                           the tiles were 5 % faster in FP64 and 12 % slower
  *                           in FP32); identical results [2]. */
 #define VRT_TUNE_REGULAR_TILE 15
+/*   VRT_TUNE_SHARED_LEVELS  Voronoi grids: 1 = the rays of one hemisphere and
+ *                           one horizontal direction (one azimuth, all
+ *                           inclinations) share one level schedule, the
+ *                           longest path in the union of their dependency
+ *                           graphs (acyclic: every line runs strictly upwind in
+ *                           height), so a site's records of those rays sit in
+ *                           one level step and share its chi and S rows;
+ *                           0 = one schedule per ray [0]. Rebuilds the
+ *                           schedules and records at once when the rays are
+ *                           set; identical results. vrt_grid_schedule then
+ *                           reports the shared levels. */
+#define VRT_TUNE_SHARED_LEVELS 16
 /*   VRT_TUNE_SEGMENT        source model along a Delaunay line (Voronoi grids):
  *                           0 = linear (Sect. 2.5) [0]; 1 = quadratic Bezier
  *                           (the higher-order solver Sect. 2.5 points to, de
@@ -277,7 +289,9 @@ vrt_status vrt_grid_tune(vrt_grid grid, int32_t knob, int64_t value);
  * graph-launched level steps under a fixed list of {die chunks, ray
  * affinity, lane bytes, interleaved record copy (Morton or site order),
  * pipeline depth} settings, and (Voronoi grids, linear segment) the
- * persistent sweep; `reps` replays each after one warm-up. Keeps the fastest
+ * persistent sweep; then, with levels shared by the rays of one azimuth
+ * (VRT_TUNE_SHARED_LEVELS), the layouts that pay with them; `reps` replays
+ * each after one warm-up. Keeps the fastest
  * setting on the grid, including its launch mode for VRT_EXEC_AUTO, and
  * writes a one-line JSON report (host, may be NULL) of every candidate's mean
  * time in ms and the choice. A candidate that fails (e.g. a device error of

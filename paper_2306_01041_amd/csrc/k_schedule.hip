@@ -45,6 +45,43 @@ __global__ __launch_bounds__(256) void level_relax_kernel(int64_t n, int32_t R, 
   }
 }
 
+// Levels shared by a group of rays (peer[r][0..P) lists the rays that share
+// ray r's levels, -1 padded): a site's level is the same for every ray of the
+// group and exceeds the level of every site that any of them reads from, the
+// longest path in the union of their dependency graphs. Starting from zero (or
+// from any lower bound) the relaxation only raises levels, as above.
+__global__ __launch_bounds__(256) void level_share_kernel(int64_t n, int32_t R, int32_t P,
+                                                          const int32_t *__restrict__ peer,
+                                                          const int32_t *__restrict__ k1,
+                                                          const int32_t *__restrict__ k2, int32_t *level,
+                                                          int32_t *changed) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)R * n) return;
+  const int32_t r = (int32_t)(t / n);
+  const int64_t i = t - (int64_t)r * n;
+  int32_t v = __hip_atomic_load(&level[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int32_t p = 0; p < P; ++p) {
+    const int32_t q = peer[(int64_t)r * P + p];
+    if (q < 0) break;
+    const int64_t bq = (int64_t)q * n;
+    const int32_t lq = __hip_atomic_load(&level[bq + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    v = lq > v ? lq : v;
+    const int32_t a = k1[bq + i];
+    if (a < 0) continue;
+    const int32_t va = __hip_atomic_load(&level[bq + a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+    v = va > v ? va : v;
+    const int32_t b = k2[bq + i];
+    if (b >= 0) {
+      const int32_t vb = __hip_atomic_load(&level[bq + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+      v = vb > v ? vb : v;
+    }
+  }
+  if (v != level[t]) {
+    __hip_atomic_store(&level[t], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *changed = 1;
+  }
+}
+
 __global__ void level_max_kernel(int64_t total, const int32_t *__restrict__ level, int32_t *out_max) {
   int32_t m = 0;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x)
@@ -157,10 +194,14 @@ void launch_level_fill(hipStream_t s, int64_t total, int32_t *level) {
 }
 
 void launch_level_relax(hipStream_t s, int64_t n, int32_t R, const int32_t *k1, const int32_t *k2,
-                        int32_t *level, int32_t *changed) {
+                        int32_t *level, int32_t *changed, const int32_t *peer, int32_t P) {
   const int64_t total = (int64_t)R * n;
   if (total == 0) return;
-  hipLaunchKernelGGL(level_relax_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, n, R, k1, k2, level, changed);
+  if (peer)
+    hipLaunchKernelGGL(level_share_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, n, R, P, peer, k1, k2, level,
+                       changed);
+  else
+    hipLaunchKernelGGL(level_relax_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, n, R, k1, k2, level, changed);
   VRT_HIP(hipGetLastError());
 }
 

@@ -358,6 +358,10 @@ void set_rays_voronoi(vrt_grid g) {
   const int64_t n = g->n;
   const int32_t R = g->R;
   const int64_t RN = (int64_t)R * n;
+  // the wave-item tables and captured launches follow the level steps
+  g->drop_graphs();
+  g->persist_items.clear();
+  g->reverse_items.clear();
   g->d_k1.alloc(RN * 4);
   g->d_k2.alloc(RN * 4);
   g->d_w1.alloc(RN * 8);
@@ -391,6 +395,46 @@ void set_rays_voronoi(vrt_grid g) {
   g->n_fallback = 0;
   for (auto v : nfb) g->n_fallback += (int64_t)v;
 
+  // rays that share one level schedule: the same hemisphere and the same
+  // horizontal direction (rays of one azimuth at different inclinations)
+  DevBuf d_peer;
+  int32_t P = 0;
+  if (g->shared_levels) {
+    std::vector<std::vector<int32_t>> groups;
+    std::vector<int32_t> gid((size_t)R, -1);
+    auto hdir = [&](int32_t r, double &hx, double &hy) {
+      const double x = g->h_dirs[3 * (size_t)r], y = g->h_dirs[3 * (size_t)r + 1];
+      const double h = std::sqrt(x * x + y * y);
+      hx = h > 1e-12 ? x / h : 0.0;
+      hy = h > 1e-12 ? y / h : 0.0;
+    };
+    for (int32_t r = 0; r < R; ++r) {
+      double hx, hy;
+      hdir(r, hx, hy);
+      const bool up = g->h_dirs[3 * (size_t)r + 2] > 0.0;
+      for (size_t q = 0; q < groups.size() && gid[(size_t)r] < 0; ++q) {
+        const int32_t o = groups[q][0];
+        double ox, oy;
+        hdir(o, ox, oy);
+        if ((g->h_dirs[3 * (size_t)o + 2] > 0.0) == up && (hx != 0.0 || hy != 0.0) && std::fabs(hx - ox) < 1e-9 &&
+            std::fabs(hy - oy) < 1e-9)
+          gid[(size_t)r] = (int32_t)q;
+      }
+      if (gid[(size_t)r] < 0) {
+        gid[(size_t)r] = (int32_t)groups.size();
+        groups.push_back({});
+      }
+      groups[(size_t)gid[(size_t)r]].push_back(r);
+    }
+    for (const auto &gr : groups) P = std::max<int32_t>(P, (int32_t)gr.size());
+    std::vector<int32_t> peer((size_t)R * P, -1);
+    for (int32_t r = 0; r < R; ++r) {
+      const auto &gr = groups[(size_t)gid[(size_t)r]];
+      for (size_t q = 0; q < gr.size(); ++q) peer[(size_t)r * P + q] = gr[q];
+    }
+    upload(d_peer, peer.data(), peer.size(), s);
+  }
+
   // levels by monotone relaxation, 16 passes between checks
   int32_t *level = g->d_level.as<int32_t>();
   vrt::launch_level_fill(s, RN, level);
@@ -398,7 +442,8 @@ void set_rays_voronoi(vrt_grid g) {
   for (;;) {
     VRT_HIP(hipMemsetAsync(d_flags, 0, 4 * 16, s));
     for (int b = 0; b < 16; ++b)
-      vrt::launch_level_relax(s, n, R, g->d_k1.as<int32_t>(), g->d_k2.as<int32_t>(), level, d_flags + b);
+      vrt::launch_level_relax(s, n, R, g->d_k1.as<int32_t>(), g->d_k2.as<int32_t>(), level, d_flags + b,
+                              P ? d_peer.as<int32_t>() : nullptr, P);
     int32_t flags[16];
     VRT_HIP(hipMemcpyAsync(flags, d_flags, sizeof flags, hipMemcpyDeviceToHost, s));
     VRT_HIP(hipStreamSynchronize(s));
@@ -1598,6 +1643,18 @@ vrt_status vrt_grid_tune(vrt_grid g, int32_t knob, int64_t value) {
     } else if (knob == VRT_TUNE_PIPELINE) {
       if (value != 0 && value != 2 && value != 4 && value != 8) fail(VRT_E_ARG, "pipeline depth must be 0, 2, 4 or 8");
       g->pipe = (int)value;
+    } else if (knob == VRT_TUNE_SHARED_LEVELS) {
+      if (value != 0 && value != 1) fail(VRT_E_ARG, "shared levels must be 0 or 1");
+      if (g->kind == 0 && (int)value != g->shared_levels) {
+        g->shared_levels = (int)value;
+        if (g->R > 0) {
+          // new level steps: the item tables and every schedule-derived table go
+          g->drop_graphs();
+          g->persist_items.clear();
+          g->reverse_items.clear();
+          set_rays_voronoi(g);
+        }
+      }
     } else if (knob == VRT_TUNE_REGULAR_TILE) {
       if (value < 0 || value > 2) fail(VRT_E_ARG, "regular tiling must be 0, 1 or 2");
       g->regular_tiled = (int)value;
@@ -1679,34 +1736,49 @@ vrt_status vrt_grid_autotune(vrt_grid g, vrt_prec prec, int32_t n_lambda, const 
       int xcd, aff, lb, il, pipe, exec;
     };
     struct Setting {
-      int order, xcd, aff, lb, il, pipe, exec;
+      int order, shared, xcd, aff, lb, il, pipe, exec;
     };
     // graph-launched level steps under die chunks x ray affinity x lane bytes
     // x interleaved copy x pipeline depth, and the persistent sweep (whose
-    // launch ignores those knobs). Split chains are not candidates: kernels on
-    // separate queues were measured not to overlap. The interleaved copies
-    // sort every step across rays whatever the record order, so they are timed
-    // under one order only; they are built on the host, up to 2^28 records.
+    // launch ignores those knobs), for each record layout: per-ray levels in
+    // site order and in Morton order, and levels shared by the rays of one
+    // azimuth (Morton order, the layouts that pay there). Split chains are not
+    // candidates: kernels on separate queues were measured not to overlap. The
+    // interleaved copies sort every step across rays whatever the record order,
+    // so they are timed under the Morton order only; they are built on the
+    // host, up to 2^28 records.
     const int G = VRT_EXEC_GRAPH, P = VRT_EXEC_PERSISTENT;
     static const Cand cands[] = {{0, 0, 16, 0, 0, G}, {8, 0, 16, 0, 0, G}, {0, 1, 16, 0, 0, G}, {8, 0, 32, 0, 0, G},
                                  {0, 1, 32, 0, 0, G}, {8, 0, 16, 0, 2, G}, {8, 0, 16, 0, 4, G}, {8, 0, 16, 1, 0, G},
                                  {0, 0, 16, 1, 0, G}, {8, 0, 16, 1, 2, G}, {8, 0, 16, 2, 0, G}, {8, 0, 16, 2, 2, G},
                                  {8, 0, 16, 0, 0, P}};
+    static const Cand shared_cands[] = {{8, 0, 16, 0, 2, G}, {8, 0, 16, 1, 2, G}, {8, 0, 16, 2, 0, G},
+                                        {8, 0, 16, 2, 2, G}, {8, 0, 16, 0, 0, P}};
+    struct Layout {
+      int order, shared;
+      const Cand *c;
+      size_t nc;
+    };
+    const Layout layouts[] = {{0, 0, cands, sizeof cands / sizeof cands[0]},
+                              {1, 0, cands, sizeof cands / sizeof cands[0]},
+                              {1, 1, shared_cands, sizeof shared_cands / sizeof shared_cands[0]}};
     std::string rep = "{\"candidates\": [";
     double best = 1e300;
-    Setting bs{g->record_order, g->xcd_chunks, g->ray_affinity, g->lane_bytes, g->interleave, g->pipe,
-               g->tuned_exec};
+    Setting bs{g->record_order, g->shared_levels, g->xcd_chunks, g->ray_affinity, g->lane_bytes, g->interleave,
+               g->pipe, g->tuned_exec};
     g->chains = 1;
     bool first = true;
     auto fmt = [](int exec) { return exec == VRT_EXEC_PERSISTENT ? "persistent" : "graph"; };
-    for (int order = 0; order <= 1; ++order) {
-      if (order != g->record_order || first) {
-        g->record_order = order;
+    for (const Layout &ly : layouts) {
+      if (ly.order != g->record_order || ly.shared != g->shared_levels || first) {
+        g->record_order = ly.order;
+        g->shared_levels = ly.shared;
         g->interleave = 0;
-        g->drop_graphs();
         set_rays_voronoi(g);
       }
-      for (const auto &cd : cands) {
+      for (size_t ci = 0; ci < ly.nc; ++ci) {
+        const Cand &cd = ly.c[ci];
+        const int order = ly.order;
         if (cd.il && (order != 1 || g->n_rec > (int64_t(1) << 28))) continue;
         if (cd.exec == P && g->segment) continue;
         g->xcd_chunks = cd.xcd;
@@ -1738,18 +1810,18 @@ vrt_status vrt_grid_autotune(vrt_grid g, vrt_prec prec, int32_t n_lambda, const 
           VRT_HIP(hipStreamSynchronize(s));
           take_device_error(g, 0);  // rethrows a pending device error as its own status
         }
-        char buf[256], msb[32];
+        char buf[288], msb[32];
         if (mean >= 0.0) snprintf(msb, sizeof msb, "%.5f", mean);
         else snprintf(msb, sizeof msb, "null");
         snprintf(buf, sizeof buf,
-                 "%s{\"exec\": \"%s\", \"record_order\": %d, \"xcd_chunks\": %d, \"ray_affinity\": %d, "
-                 "\"lane_bytes\": %d, \"interleave\": %d, \"pipeline\": %d, \"ms\": %s}",
-                 first ? "" : ", ", fmt(cd.exec), order, cd.xcd, cd.aff, cd.lb, cd.il, cd.pipe, msb);
+                 "%s{\"exec\": \"%s\", \"record_order\": %d, \"shared_levels\": %d, \"xcd_chunks\": %d, "
+                 "\"ray_affinity\": %d, \"lane_bytes\": %d, \"interleave\": %d, \"pipeline\": %d, \"ms\": %s}",
+                 first ? "" : ", ", fmt(cd.exec), order, ly.shared, cd.xcd, cd.aff, cd.lb, cd.il, cd.pipe, msb);
         rep += buf;
         first = false;
         if (mean >= 0.0 && mean < best) {
           best = mean;
-          bs = Setting{order, cd.xcd, cd.aff, cd.lb, cd.il, cd.pipe, cd.exec};
+          bs = Setting{order, ly.shared, cd.xcd, cd.aff, cd.lb, cd.il, cd.pipe, cd.exec};
         }
       }
     }
@@ -1757,8 +1829,9 @@ vrt_status vrt_grid_autotune(vrt_grid g, vrt_prec prec, int32_t n_lambda, const 
     (void)hipEventDestroy(e1);
     g->chains = 1;  // every candidate was timed with one launch chain
     g->interleave = 0;
-    if (bs.order != g->record_order) {
+    if (bs.order != g->record_order || bs.shared != g->shared_levels) {
       g->record_order = bs.order;
+      g->shared_levels = bs.shared;
       set_rays_voronoi(g);
     }
     g->xcd_chunks = bs.xcd;
@@ -1769,11 +1842,11 @@ vrt_status vrt_grid_autotune(vrt_grid g, vrt_prec prec, int32_t n_lambda, const 
     g->tuned_exec = bs.exec;
     if (bs.il && g->interleaved_built != bs.il) build_interleaved(g);
     g->drop_graphs();
-    char buf[320];
+    char buf[352];
     snprintf(buf, sizeof buf,
-             "], \"chosen\": {\"exec\": \"%s\", \"record_order\": %d, \"xcd_chunks\": %d, \"ray_affinity\": %d, "
-             "\"lane_bytes\": %d, \"interleave\": %d, \"pipeline\": %d, \"ms\": %.5f}}",
-             fmt(bs.exec), bs.order, bs.xcd, bs.aff, bs.lb, bs.il, bs.pipe, best);
+             "], \"chosen\": {\"exec\": \"%s\", \"record_order\": %d, \"shared_levels\": %d, \"xcd_chunks\": %d, "
+             "\"ray_affinity\": %d, \"lane_bytes\": %d, \"interleave\": %d, \"pipeline\": %d, \"ms\": %.5f}}",
+             fmt(bs.exec), bs.order, bs.shared, bs.xcd, bs.aff, bs.lb, bs.il, bs.pipe, best);
     rep += buf;
     if (report && report_len > 0) snprintf(report, (size_t)report_len, "%s", rep.c_str());
     return VRT_OK;

@@ -190,6 +190,7 @@ struct vrt_grid_s {
 
   // tuning knobs
   int record_order = 1;  // 0 site index, 1 Morton (x, y) within a level
+  int shared_levels = 0;  // 1: one level schedule per (hemisphere, azimuth) group of rays
   int xcd_chunks = 8;    // 0 = plain block order
   int ray_affinity = 0;  // 1: each ray's records always run on the same die
   int chains = 1;        // independent launch chains (streams) a sweep is split into
@@ -279,7 +280,7 @@ void launch_select(hipStream_t s, int64_t n, int32_t R, const double *xyz, const
 // ---- k_schedule.hip
 void launch_level_fill(hipStream_t s, int64_t total, int32_t *level);
 void launch_level_relax(hipStream_t s, int64_t n, int32_t R, const int32_t *k1, const int32_t *k2,
-                        int32_t *level, int32_t *changed);
+                        int32_t *level, int32_t *changed, const int32_t *peer = nullptr, int32_t P = 0);
 void launch_level_count(hipStream_t s, int64_t n, int32_t R, int32_t Lmax, int64_t tile,
                         const int32_t *level, int32_t *cnt, const int32_t *visit);
 void launch_level_scan(hipStream_t s, int32_t R, int32_t Lmax, int64_t ntiles, int32_t *cnt,

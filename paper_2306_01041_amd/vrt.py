@@ -50,6 +50,7 @@ VRT_TUNE_SEGMENT = 11
 VRT_TUNE_REVERSE_PERSISTENT = 13
 VRT_TUNE_PIPELINE = 14
 VRT_TUNE_REGULAR_TILE = 15
+VRT_TUNE_SHARED_LEVELS = 16
 
 VRT_F64 = 0
 VRT_F32 = 1

@@ -348,6 +348,19 @@ def test_tuning_knobs_do_not_change_results(v, ctx, quad, grids):
                     ref = out
                 assert np.array_equal(out, ref), (order, xcd, aff, ch, lb, rg, il, pp, mode)
             G.close()
+    for il, pp, ch in ((0, 0, 1), (1, 2, 1), (2, 2, 1), (2, 0, 1), (0, 0, 3)):
+        G = v.Grid.from_synth(ctx, g)
+        G.tune(v.VRT_TUNE_SHARED_LEVELS, 1)
+        G.tune(v.VRT_TUNE_CHAINS, ch)
+        G.set_rays(dirs, w)
+        G.tune(v.VRT_TUNE_INTERLEAVE, il)
+        G.tune(v.VRT_TUNE_PIPELINE, pp)
+        J = torch.empty_like(chi)
+        for mode in (v.VRT_EXEC_GRAPH, v.VRT_EXEC_BATCHED, v.VRT_EXEC_PLAIN, v.VRT_EXEC_PERSISTENT):
+            v.formal_solution(G, chi, S, J, exec_mode=mode)
+            G.device_status()
+            assert np.array_equal(J.cpu().numpy(), ref), ("shared", il, pp, ch, mode)
+        G.close()
     # switched on after the rays are set: the copy is built at once
     G = _gpu_grid(v, ctx, g, dirs, w)
     G.tune(v.VRT_TUNE_INTERLEAVE, 1)
@@ -360,8 +373,10 @@ def test_tuning_knobs_do_not_change_results(v, ctx, quad, grids):
     J = torch.empty_like(chi)
     rep = v.autotune(G, chi, S, J, reps=2)
     # per record order: 7 level-step layouts without the interleaved copies and
-    # the persistent sweep, plus 5 with them under the Morton order
-    assert len(rep["candidates"]) == 21
+    # the persistent sweep, plus 5 with them under the Morton order; then 5
+    # layouts with levels shared by the rays of one azimuth
+    assert len(rep["candidates"]) == 26
+    assert sum(c["shared_levels"] for c in rep["candidates"]) == 5
     assert {c["exec"] for c in rep["candidates"]} == {"graph", "persistent"}
     assert rep["chosen"]["ms"] == min(c["ms"] for c in rep["candidates"] if c["ms"] is not None)
     for mode in (v.VRT_EXEC_AUTO, v.VRT_EXEC_GRAPH, v.VRT_EXEC_PERSISTENT):
@@ -394,6 +409,56 @@ def test_persistent_fp32_matches_graph_bitwise(v, ctx, quad, grids, nl):
         G.device_status()
         assert np.array_equal(J.cpu().numpy(), ref), rep
     G.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_shared_levels_give_identical_results(v, ctx, quad, grids, prec):
+    """One level schedule shared by the rays of one hemisphere and azimuth is a
+    valid schedule for each of them (a site's level is the same for the group
+    and above the level of every site any of them reads from), is at least as
+    deep as each ray's own, and gives the per-ray schedule's intensities, J and
+    adjoint bit for bit in every launch mode."""
+    flush(f"shared levels {prec}")
+    atm, g = grids[16384]
+    dirs, w = quad
+    dt = torch.float32 if prec == "f32" else torch.float64
+    chi_o, S_o = _fields(atm, 8, 13)
+    chi, S = to_dev(chi_o, dt), to_dev(S_o, dt)
+    R = len(dirs)
+    out = {}
+    own = {}
+    for shared in (0, 1):
+        G = v.Grid.from_synth(ctx, g)
+        G.tune(v.VRT_TUNE_SHARED_LEVELS, shared)
+        G.set_rays(dirs, w, 7.0)
+        sch = [G.schedule(r) for r in range(R)]
+        if shared:
+            hz = np.hypot(dirs[:, 0], dirs[:, 1])
+            for r in range(R):
+                k1, k2, lev = sch[r]["k1"], sch[r]["k2"], sch[r]["level"]
+                for k in (k1, k2):
+                    m = k >= 0
+                    assert np.all(lev[m] > lev[k[m]]), r
+                assert np.all(lev[k1 < 0] == 0), r
+                assert sch[r]["n_levels"] >= own[r], r
+                for q in range(R):
+                    if np.sign(dirs[q, 2]) == np.sign(dirs[r, 2]) and np.allclose(dirs[q, :2] / hz[q], dirs[r, :2] / hz[r]):
+                        assert np.array_equal(sch[q]["level"], lev), (r, q)
+        else:
+            own = {r: sch[r]["n_levels"] for r in range(R)}
+        res = []
+        for mode in (v.VRT_EXEC_PLAIN, v.VRT_EXEC_GRAPH, v.VRT_EXEC_PERSISTENT):
+            J = torch.empty_like(chi)
+            I = torch.empty((R, g.n, 8), dtype=dt, device="cuda:0")
+            v.formal_solution(G, chi, S, J, I_rays=I, exec_mode=mode)
+            G.device_status()
+            res += [J.cpu().numpy(), I.cpu().numpy()]
+        gI = torch.ones((R, g.n, 8), dtype=dt, device="cuda:0")
+        res += [t.cpu().numpy() for t in v.formal_solution_vjp(G, chi, S, dL_dI=gI, I_rays=I)]
+        out[shared] = res
+        G.close()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
 
 
 @pytest.mark.parametrize("nl", [64, 101])

@@ -140,7 +140,24 @@ def test_c1_voronoi_full_size(v, ctx, c1):
         assert eI <= tol_I
         for r in range(len(dirs)):
             assert np.array_equal(sites[off[r]:off[r + 1]], em_sites[r])
+        if mode == v.VRT_EXEC_PERSISTENT:
+            ref32 = prev
         del chi, S, J, em
+    # the layout the autotuner picks for the benchmark: the persistent sweep on
+    # level steps shared by the rays of one azimuth (and the graph-launched
+    # level steps with the site-order copy and the pipelined kernel): same bits
+    G.tune(v.VRT_TUNE_SHARED_LEVELS, 1)
+    G.tune(v.VRT_TUNE_INTERLEAVE, 2)
+    G.tune(v.VRT_TUNE_PIPELINE, 2)
+    chi = torch.empty((g.n, nl), dtype=torch.float32, device="cuda:0")
+    S = torch.empty_like(chi)
+    J = torch.empty_like(chi)
+    v.lte_continuum(G, lam, atm.kappa0, T, rho, chi, S)
+    for mode in (v.VRT_EXEC_PERSISTENT, v.VRT_EXEC_GRAPH):
+        v.formal_solution(G, chi, S, J, exec_mode=mode)
+        G.device_status()
+        assert np.array_equal(J.cpu().numpy(), ref32), mode
+    flush("  shared level steps: persistent and graph J bit-identical to the per-ray schedules")
     G.close()
 
 
@@ -299,10 +316,15 @@ def test_c2_one_iteration_full_size(v, ctx):
     v.lte_continuum(G, lam0, atm.kappa0, to_dev(atm.T, d), to_dev(atm.rho, d), chi_c, B)
     chi_c, B = chi_c[:, 0].contiguous(), B[:, 0].contiguous()
     S = B.clone()
+    # the benchmark's layout: shared level steps, site-order copy, pipelined kernel
+    G.tune(v.VRT_TUNE_SHARED_LEVELS, 1)
+    G.tune(v.VRT_TUNE_INTERLEAVE, 2)
+    G.tune(v.VRT_TUNE_PIPELINE, 2)
     st, nit, hist = v.two_level_solve(G, line.wlam, to_dev(line.phi, d), to_dev(line.chi_line, d), chi_c, B, eps, S,
                                       max_iter=1, tol=0.0, sweep_dtype=torch.float32)
     torch.cuda.synchronize()
     sel = oracle.select(g, dirs)
+    G.tune(v.VRT_TUNE_SHARED_LEVELS, 0)  # per-ray schedules, to compare with the oracle's
     _check_schedules(G, g, dirs, sel)
     G.close()
     flush("  oracle FP64 iteration (1,048,576 sites x 24 rays x 101 wavelengths)")
@@ -321,7 +343,7 @@ def test_c2_one_iteration_full_size(v, ctx):
 def test_c3_batch_one_iteration_full_size(v, ctx):
     """The 48-atmosphere batch (32,768-524,288 sites each, log-uniform, seeds
     1042..1089; about 10 million sites in one grid), one plain Lambda iteration
-    with FP32 sweeps in the graph-launched mode the benchmark times, against
+    with FP32 sweeps in the graph-launched mode and layout the benchmark times, against
     standalone oracle iterations of four of its atmospheres (the smallest, the
     largest and two seeded picks): S_line to 1e-5, atmosphere by atmosphere."""
     import multiprocessing as mp
@@ -357,6 +379,10 @@ def test_c3_batch_one_iteration_full_size(v, ctx):
         phi[off[a]:off[a + 1]].copy_(torch.as_tensor(ln.phi))
     chi_L = to_dev(np.concatenate([ln.chi_line for ln in lines]), d)
     S = B.clone()
+    # the benchmark's layout: shared level steps, site-order copy, pipelined kernel
+    G.tune(v.VRT_TUNE_SHARED_LEVELS, 1)
+    G.tune(v.VRT_TUNE_INTERLEAVE, 2)
+    G.tune(v.VRT_TUNE_PIPELINE, 2)
     flush("  GPU: one iteration of the whole batch (FP32 sweeps, graph)")
     st, its, hist = v.two_level_solve_batched(G, off, lines[0].wlam, phi, chi_L, chi_c, B, eps, S, max_iter=1,
                                               tol=0.0, sweep_dtype=torch.float32, exec_mode=v.VRT_EXEC_GRAPH)

@@ -89,9 +89,11 @@ def counter_traffic(nl, n, mode, layout):
     if nl != 64 or n != 262144 or not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    # the persistent sweep reads the per-ray record order whatever the layout
-    # knobs say, but its work items follow the level steps
-    if persistent and rec.get("layout", {}).get("shared_levels", 0) != layout.get("shared_levels", 0):
+    # the persistent sweep reads the per-ray record order or, with an interleaved
+    # copy built, that copy (wave items then mix rays); its work items follow the
+    # level steps
+    if persistent and any(rec.get("layout", {}).get(k, 0) != layout.get(k, 0)
+                          for k in ("shared_levels", "interleave")):
         return None
     if not persistent and ({k: rec.get("layout", {}).get(k) for k in LAYOUT_KEYS}
                            != {k: layout.get(k) for k in LAYOUT_KEYS}):

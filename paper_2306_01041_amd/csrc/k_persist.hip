@@ -152,10 +152,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void pers
     const int4 *__restrict__ ri, const typename vrt::RecOf<T>::type *__restrict__ rf,
     const int64_t *__restrict__ item_rec, const int32_t *__restrict__ item_cnt, int64_t n_items, int32_t nl,
     int64_t n, int64_t flag_ld, const T *__restrict__ chi, const T *__restrict__ S, const T *__restrict__ Ibot,
-    const T *__restrict__ Itop, T *I, int32_t *flags, int32_t *words, int64_t spin_cap) {
+    const T *__restrict__ Itop, T *I, int32_t *flags, int32_t *words, int64_t spin_cap, int64_t mixed_bytes) {
   using L = PLane<T, V>;
   using VT = typename L::type;
   const int32_t epoch = SIGN ? words[5] : words[0];
+  // mixed_bytes > 0: items mix rays (records of one level step in site order
+  // across rays); one descriptor then covers every ray's rows (mixed_bytes of
+  // them, below 4 GiB) and each lane adds its own ray's offset
+  const bool mixed = mixed_bytes > 0;
   int32_t *err = words + 1;
   // a sign-encoded sweep after an unacknowledged error would trust rows of an
   // unknown sign: it does nothing until the host has read and cleared the error
@@ -180,8 +184,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void pers
       if (wait_stamp(fr + k1, epoch, err, spin_cap) && k2 >= 0) wait_stamp(fr + k2, epoch, err, spin_cap);
     }
     if (live) {
-      // the item's ray's block of n * nl values (BIG: 4 GiB or more)
-      const RayBlock<BIG> Iray(I + (int64_t)(cr >> 8) * n * nl, n * nl * (int64_t)sizeof(T));
+      // the item's ray's block of n * nl values (BIG: 4 GiB or more), or every
+      // ray's rows for mixed items
+      const RayBlock<BIG> Iray(mixed ? I : I + (int64_t)(cr >> 8) * n * nl,
+                               mixed ? mixed_bytes : n * nl * (int64_t)sizeof(T));
+      const int64_t rb = mixed ? (int64_t)ray * n * nl : 0;
       const int64_t bi = (int64_t)site * nl;
       if (k1 < 0) {
         for (int l = l0; l < nl; l += C * V) {
@@ -189,7 +196,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void pers
           if (up) v = L::load(Ibot + bi + l);
           else if (Itop) v = L::load(Itop + bi + l);
           else v = VT(T(0));
-          put_row<T, VT, L, V, SIGN>(Iray, (bi + l) * (int64_t)sizeof(T), v, neg, err);
+          put_row<T, VT, L, V, SIGN>(Iray, (rb + bi + l) * (int64_t)sizeof(T), v, neg, err);
         }
       } else {
         const auto f = rf[rec];
@@ -201,12 +208,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void pers
         for (int l = l0; l < nl; l += C * V) {
           const VT ci = L::load(chi + bi + l), si = L::load(S + bi + l);
           const VT c1 = L::load(chi + b1 + l), s1 = L::load(S + b1 + l);
-          const VT u1 = get_row<T, VT, L, V, SIGN>(Iray, (b1 + l) * (int64_t)sizeof(T), neg, err, spin_cap);
+          const VT u1 = get_row<T, VT, L, V, SIGN>(Iray, (rb + b1 + l) * (int64_t)sizeof(T), neg, err, spin_cap);
           VT c2, s2, u2;
           if (two) {
             c2 = L::load(chi + b2 + l);
             s2 = L::load(S + b2 + l);
-            u2 = get_row<T, VT, L, V, SIGN>(Iray, (b2 + l) * (int64_t)sizeof(T), neg, err, spin_cap);
+            u2 = get_row<T, VT, L, V, SIGN>(Iray, (rb + b2 + l) * (int64_t)sizeof(T), neg, err, spin_cap);
           }
           VT out;
 #pragma unroll
@@ -219,7 +226,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void pers
             }
             L::set(out, k, Iv);
           }
-          put_row<T, VT, L, V, SIGN>(Iray, (bi + l) * (int64_t)sizeof(T), out, neg, err);
+          put_row<T, VT, L, V, SIGN>(Iray, (rb + bi + l) * (int64_t)sizeof(T), out, neg, err);
         }
       }
     }
@@ -237,7 +244,7 @@ template <typename T, int C, int V>
 void launch_pc(hipStream_t s, const vrt::PersistItems &it, int32_t max_blocks, const int4 *ri,
                const typename vrt::RecOf<T>::type *rf, int32_t nl, int64_t n, int64_t flag_ld, const T *chi,
                const T *S, const T *Ibot, const T *Itop, T *I, int32_t *flags, int32_t *words, int64_t cap,
-               bool sign) {
+               bool sign, int64_t mixed_bytes) {
   if (it.spw != 64 / C) throw vrt::Error(VRT_E_STATE, "persistent item table built for another record width");
   const bool big = n * (int64_t)nl * (int64_t)sizeof(T) >= (int64_t(1) << 32);
   auto kern = sign ? (big ? persistent_sweep_kernel<T, C, V, true, true> : persistent_sweep_kernel<T, C, V, true, false>)
@@ -258,22 +265,23 @@ void launch_pc(hipStream_t s, const vrt::PersistItems &it, int32_t max_blocks, c
   const int32_t *item_cnt = it.cnt.as<int32_t>();
   const int64_t n_items = it.n_items;
   hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, s, ri, rf, item_rec, item_cnt, n_items, nl, n,
-                     flag_ld, chi, S, Ibot, Itop, I, flags, words, cap);
+                     flag_ld, chi, S, Ibot, Itop, I, flags, words, cap, mixed_bytes);
   VRT_HIP(hipGetLastError());
 }
 
 template <typename T, int V>
 void launch_pv(hipStream_t s, const vrt::PersistItems &it, int32_t mb, const int4 *ri,
                const typename vrt::RecOf<T>::type *rf, int32_t nl, int64_t n, int64_t fl, const T *chi, const T *S,
-               const T *Ibot, const T *Itop, T *I, int32_t *flags, int32_t *words, int64_t cap, bool sg) {
+               const T *Ibot, const T *Itop, T *I, int32_t *flags, int32_t *words, int64_t cap, bool sg,
+               int64_t mx) {
   switch (vrt::lanes_per_record(nl / V)) {
-    case 64: launch_pc<T, 64, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg); break;
-    case 32: launch_pc<T, 32, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg); break;
-    case 16: launch_pc<T, 16, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg); break;
-    case 8: launch_pc<T, 8, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg); break;
-    case 4: launch_pc<T, 4, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg); break;
-    case 2: launch_pc<T, 2, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg); break;
-    default: launch_pc<T, 1, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg); break;
+    case 64: launch_pc<T, 64, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg, mx); break;
+    case 32: launch_pc<T, 32, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg, mx); break;
+    case 16: launch_pc<T, 16, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg, mx); break;
+    case 8: launch_pc<T, 8, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg, mx); break;
+    case 4: launch_pc<T, 4, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg, mx); break;
+    case 2: launch_pc<T, 2, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg, mx); break;
+    default: launch_pc<T, 1, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg, mx); break;
   }
 }
 
@@ -308,24 +316,30 @@ template <typename T>
 void launch_persistent_sweep(hipStream_t s, const PersistItems &items, int32_t max_blocks, const int4 *ri,
                              const typename RecOf<T>::type *rf, int32_t nl, int64_t n, int64_t flag_ld, const T *chi,
                              const T *S, const T *Ibot, const T *Itop, T *I, int32_t *flags, int32_t *words,
-                             int64_t spin_cap, bool sign) {
+                             int64_t spin_cap, bool sign, int32_t mixed_rays) {
   if (items.n_items <= 0) return;
+  int64_t mixed_bytes = 0;
+  if (mixed_rays > 0) {
+    mixed_bytes = (int64_t)mixed_rays * n * (int64_t)nl * (int64_t)sizeof(T);
+    if (mixed_bytes >= (int64_t(1) << 32))
+      throw Error(VRT_E_ARG, "persistent sweep: items that mix rays need all rows below 4 GiB");
+  }
   constexpr int VW = 16 / sizeof(T);
   const bool aligned = al16(chi) && al16(S) && al16(Ibot) && al16(Itop) && al16(I);
   if (aligned && nl % VW == 0)
     launch_pv<T, VW>(s, items, max_blocks, ri, rf, nl, n, flag_ld, chi, S, Ibot, Itop, I, flags, words, spin_cap,
-                     sign);
+                     sign, mixed_bytes);
   else
     launch_pv<T, 1>(s, items, max_blocks, ri, rf, nl, n, flag_ld, chi, S, Ibot, Itop, I, flags, words, spin_cap,
-                    sign);
+                    sign, mixed_bytes);
 }
 
 template void launch_persistent_sweep<float>(hipStream_t, const PersistItems &, int32_t, const int4 *, const RecF32 *,
                                              int32_t, int64_t, int64_t, const float *, const float *, const float *,
-                                             const float *, float *, int32_t *, int32_t *, int64_t, bool);
+                                             const float *, float *, int32_t *, int32_t *, int64_t, bool, int32_t);
 template void launch_persistent_sweep<double>(hipStream_t, const PersistItems &, int32_t, const int4 *,
                                               const RecF64 *, int32_t, int64_t, int64_t, const double *,
                                               const double *, const double *, const double *, double *, int32_t *,
-                                              int32_t *, int64_t, bool);
+                                              int32_t *, int64_t, bool, int32_t);
 
 }  // namespace vrt

@@ -625,17 +625,27 @@ void take_device_error(vrt_grid g, int32_t iter) {
   fail(VRT_E_TIMEOUT, "a bounded wait of the persistent sweep gave up%s (spin cap %lld)", at, (long long)g->spin_cap);
 }
 
-// Wave items of the persistent sweep for `spw` records per wave: every
-// (level step, ray) segment is cut separately, so no item holds two levels
-// of one ray or two rays; cnt holds the record count + 256 x the ray.
-const vrt::PersistItems &persistent_items(vrt_grid g, int32_t spw) {
-  auto it = g->persist_items.find(spw);
+// Wave items of the persistent sweep: the (level step, ray) segments in step
+// order, cut into at most spw records, cnt = record count + 256 x ray; or, with
+// `mixed`, each level step of the interleaved record copy cut into spw
+// records whatever their rays (cnt = record count).
+const vrt::PersistItems &persistent_items(vrt_grid g, int32_t spw, bool mixed = false) {
+  const int key = spw + (mixed ? 1024 : 0);
+  auto it = g->persist_items.find(key);
   if (it != g->persist_items.end()) return *it->second;
   const int32_t R = g->R;
   if (R >= (1 << 23)) fail(VRT_E_ARG, "persistent sweep: too many rays");
   std::vector<int64_t> rec;
   std::vector<int32_t> cnt;
   for (int32_t st = 0; st < g->n_steps; ++st) {
+    if (mixed) {
+      const int64_t b = g->step_ptr[(size_t)st], e = g->step_ptr[(size_t)st + 1];
+      for (int64_t r = b; r < e; r += spw) {
+        rec.push_back(r);
+        cnt.push_back((int32_t)std::min<int64_t>(spw, e - r));
+      }
+      continue;
+    }
     for (int32_t ray = 0; ray < R; ++ray) {
       const int64_t b = g->seg_off[(size_t)st * R + ray], e = b + g->seg_cnt[(size_t)st * R + ray];
       for (int64_t r = b; r < e; r += spw) {
@@ -652,7 +662,7 @@ const vrt::PersistItems &persistent_items(vrt_grid g, int32_t spw) {
   ensure_flags(g);
   VRT_HIP(hipStreamSynchronize(g->ctx->stream));  // host tables are local
   auto &ref = *p;
-  g->persist_items.emplace(spw, std::move(p));
+  g->persist_items.emplace(key, std::move(p));
   return ref;
 }
 
@@ -703,13 +713,21 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
     }
   } else if (g->kind == 0 && ex == VRT_EXEC_PERSISTENT) {
     const bool aligned = vrt::al16(chi) && vrt::al16(S) && vrt::al16(Ib) && vrt::al16(It) && vrt::al16(I);
-    const vrt::PersistItems &items = persistent_items(g, vrt::persistent_records_per_wave(nl, sizeof(T), aligned));
+    // the interleaved record copy, when there is one and every ray's rows fit
+    // one descriptor: wave items then take records of several rays
+    const bool mixed = g->interleave && g->interleaved_built == g->interleave &&
+                       (int64_t)R * n * (int64_t)nl * (int64_t)sizeof(T) < (int64_t(1) << 32);
+    const vrt::PersistItems &items =
+        persistent_items(g, vrt::persistent_records_per_wave(nl, sizeof(T), aligned), mixed);
+    const int4 *rix = mixed ? g->d_ri_x.as<int4>() : g->d_ri.as<int4>();
+    const auto *rfx = records<T>(g);
+    if (mixed)
+      rfx = sizeof(T) == 4 ? reinterpret_cast<decltype(rfx)>(g->d_rf32_x.p) : reinterpret_cast<decltype(rfx)>(g->d_rf64_x.p);
     int32_t *words = g->d_epoch.as<int32_t>();
     vrt::launch_persist_begin(s, words, sign);
     timed_launch(ctx, s, tm, 0, g->n_rec * nl, [&] {
-      vrt::launch_persistent_sweep<T>(s, items, g->persist_max_blocks, g->d_ri.as<int4>(), records<T>(g), nl, n,
-                                      flag_ld(g), chi, S, Ib, It, I, g->d_flags.as<int32_t>(), words, g->spin_cap,
-                                      sign);
+      vrt::launch_persistent_sweep<T>(s, items, g->persist_max_blocks, rix, rfx, nl, n, flag_ld(g), chi, S, Ib, It,
+                                      I, g->d_flags.as<int32_t>(), words, g->spin_cap, sign, mixed ? R : 0);
     });
   } else if (g->kind == 0) {
     const int4 *ri = g->d_ri.as<int4>();
@@ -1753,7 +1771,8 @@ vrt_status vrt_grid_autotune(vrt_grid g, vrt_prec prec, int32_t n_lambda, const 
                                  {0, 0, 16, 1, 0, G}, {8, 0, 16, 1, 2, G}, {8, 0, 16, 2, 0, G}, {8, 0, 16, 2, 2, G},
                                  {8, 0, 16, 0, 0, P}};
     static const Cand shared_cands[] = {{8, 0, 16, 0, 2, G}, {8, 0, 16, 1, 2, G}, {8, 0, 16, 2, 0, G},
-                                        {8, 0, 16, 2, 2, G}, {8, 0, 16, 0, 0, P}};
+                                        {8, 0, 16, 2, 2, G}, {8, 0, 16, 0, 0, P}, {8, 0, 16, 1, 0, P},
+                                        {8, 0, 16, 2, 0, P}};
     struct Layout {
       int order, shared;
       const Cand *c;

@@ -349,7 +349,7 @@ template <typename T>
 void launch_persistent_sweep(hipStream_t s, const PersistItems &items, int32_t max_blocks, const int4 *ri,
                              const typename RecOf<T>::type *rf, int32_t nl, int64_t n, int64_t flag_ld, const T *chi,
                              const T *S, const T *Ibot, const T *Itop, T *I, int32_t *flags, int32_t *words,
-                             int64_t spin_cap, bool sign = false);
+                             int64_t spin_cap, bool sign = false, int32_t mixed_rays = 0);
 
 // ---- k_nlte.hip
 template <typename T>

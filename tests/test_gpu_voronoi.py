@@ -360,6 +360,12 @@ def test_tuning_knobs_do_not_change_results(v, ctx, quad, grids):
             v.formal_solution(G, chi, S, J, exec_mode=mode)
             G.device_status()
             assert np.array_equal(J.cpu().numpy(), ref), ("shared", il, pp, ch, mode)
+        # the persistent sweep into caller rows (epoch stamps; with an interleaved
+        # copy its wave items mix rays)
+        I = torch.empty((len(dirs), g.n, chi.shape[1]), dtype=chi.dtype, device="cuda:0")
+        v.formal_solution(G, chi, S, J, I_rays=I, exec_mode=v.VRT_EXEC_PERSISTENT)
+        G.device_status()
+        assert np.array_equal(J.cpu().numpy(), ref), ("shared, caller rows", il, pp, ch)
         G.close()
     # switched on after the rays are set: the copy is built at once
     G = _gpu_grid(v, ctx, g, dirs, w)
@@ -375,8 +381,8 @@ def test_tuning_knobs_do_not_change_results(v, ctx, quad, grids):
     # per record order: 7 level-step layouts without the interleaved copies and
     # the persistent sweep, plus 5 with them under the Morton order; then 5
     # layouts with levels shared by the rays of one azimuth
-    assert len(rep["candidates"]) == 26
-    assert sum(c["shared_levels"] for c in rep["candidates"]) == 5
+    assert len(rep["candidates"]) == 28
+    assert sum(c["shared_levels"] for c in rep["candidates"]) == 7
     assert {c["exec"] for c in rep["candidates"]} == {"graph", "persistent"}
     assert rep["chosen"]["ms"] == min(c["ms"] for c in rep["candidates"] if c["ms"] is not None)
     for mode in (v.VRT_EXEC_AUTO, v.VRT_EXEC_GRAPH, v.VRT_EXEC_PERSISTENT):

@@ -219,9 +219,8 @@ vrt_status vrt_grid_set_rays(vrt_grid grid, int32_t n_rays, const double *dir, c
  *                           index across rays (for sites numbered along space,
  *                           e.g. a batch of atmospheres, whose Morton codes
  *                           would interleave the atmospheres) [0]. The
-                           persistent sweep into the library's own rows
-                           reads the same copy, so one wave item mixes rays,
-                           when every ray's rows fit one 4 GiB block. */
+                           persistent sweep reads the same copy, so one of
+                           its wave items mixes rays. */
 #define VRT_TUNE_INTERLEAVE 10
 /*   VRT_TUNE_PIPELINE       0 = one group of records per wavefront in the
  *                           level-step sweeps; 2, 4 or 8 = each wavefront

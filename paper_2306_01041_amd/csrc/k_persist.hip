@@ -157,8 +157,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void pers
   using VT = typename L::type;
   const int32_t epoch = SIGN ? words[5] : words[0];
   // mixed_bytes > 0: items mix rays (records of one level step in site order
-  // across rays); one descriptor then covers every ray's rows (mixed_bytes of
-  // them, below 4 GiB) and each lane adds its own ray's offset
+  // across rays); the row block then covers every ray's rows (mixed_bytes of
+  // them; BIG when that is 4 GiB or more) and each lane adds its own ray's
+  // offset
   const bool mixed = mixed_bytes > 0;
   int32_t *err = words + 1;
   // a sign-encoded sweep after an unacknowledged error would trust rows of an
@@ -246,7 +247,8 @@ void launch_pc(hipStream_t s, const vrt::PersistItems &it, int32_t max_blocks, c
                const T *S, const T *Ibot, const T *Itop, T *I, int32_t *flags, int32_t *words, int64_t cap,
                bool sign, int64_t mixed_bytes) {
   if (it.spw != 64 / C) throw vrt::Error(VRT_E_STATE, "persistent item table built for another record width");
-  const bool big = n * (int64_t)nl * (int64_t)sizeof(T) >= (int64_t(1) << 32);
+  const int64_t block = mixed_bytes > 0 ? mixed_bytes : n * (int64_t)nl * (int64_t)sizeof(T);
+  const bool big = block >= (int64_t(1) << 32);
   auto kern = sign ? (big ? persistent_sweep_kernel<T, C, V, true, true> : persistent_sweep_kernel<T, C, V, true, false>)
                    : (big ? persistent_sweep_kernel<T, C, V, false, true> : persistent_sweep_kernel<T, C, V, false, false>);
   int dev = 0, cus = 0, per_cu = 0;
@@ -318,12 +320,7 @@ void launch_persistent_sweep(hipStream_t s, const PersistItems &items, int32_t m
                              const T *S, const T *Ibot, const T *Itop, T *I, int32_t *flags, int32_t *words,
                              int64_t spin_cap, bool sign, int32_t mixed_rays) {
   if (items.n_items <= 0) return;
-  int64_t mixed_bytes = 0;
-  if (mixed_rays > 0) {
-    mixed_bytes = (int64_t)mixed_rays * n * (int64_t)nl * (int64_t)sizeof(T);
-    if (mixed_bytes >= (int64_t(1) << 32))
-      throw Error(VRT_E_ARG, "persistent sweep: items that mix rays need all rows below 4 GiB");
-  }
+  const int64_t mixed_bytes = mixed_rays > 0 ? (int64_t)mixed_rays * n * (int64_t)nl * (int64_t)sizeof(T) : 0;
   constexpr int VW = 16 / sizeof(T);
   const bool aligned = al16(chi) && al16(S) && al16(Ibot) && al16(Itop) && al16(I);
   if (aligned && nl % VW == 0)

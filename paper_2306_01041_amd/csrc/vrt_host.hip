@@ -713,10 +713,9 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
     }
   } else if (g->kind == 0 && ex == VRT_EXEC_PERSISTENT) {
     const bool aligned = vrt::al16(chi) && vrt::al16(S) && vrt::al16(Ib) && vrt::al16(It) && vrt::al16(I);
-    // the interleaved record copy, when there is one and every ray's rows fit
-    // one descriptor: wave items then take records of several rays
-    const bool mixed = g->interleave && g->interleaved_built == g->interleave &&
-                       (int64_t)R * n * (int64_t)nl * (int64_t)sizeof(T) < (int64_t(1) << 32);
+    // the interleaved record copy, when there is one: wave items then take
+    // records of several rays
+    const bool mixed = g->interleave && g->interleaved_built == g->interleave;
     const vrt::PersistItems &items =
         persistent_items(g, vrt::persistent_records_per_wave(nl, sizeof(T), aligned), mixed);
     const int4 *rix = mixed ? g->d_ri_x.as<int4>() : g->d_ri.as<int4>();

@@ -484,8 +484,9 @@ def test_c1_bezier_full_size(v, ctx, c1):
 def test_persistent_sweeps_above_4gib_per_ray(v, ctx):
     """One ray's rows above 4 GiB (8,487,200 lattice sites x 128 wavelengths
     in FP32, 4.35 GB per ray, two oblique rays): the persistent forward sweep
-    (linear and Bezier segments) and the persistent reverse sweep address the
-    rows through 2 GiB windows and give the level-step results bit for bit."""
+    (linear and Bezier segments, and linear with wave items mixing the rays)
+    and the persistent reverse sweep address the rows through 2 GiB windows
+    and give the level-step results bit for bit."""
     nx = ny = 206
     nz = 200
     nl = 128
@@ -511,6 +512,16 @@ def test_persistent_sweeps_above_4gib_per_ray(v, ctx):
         G.device_status()
         flush(f"  segment {seg}: persistent equals level steps: {bool(torch.equal(J, ref))}")
         assert torch.equal(J, ref), seg
+        if seg == 0:
+            # wave items that mix the two rays on the site-order record copy,
+            # addressing one 8.7 GB block of both rays' rows
+            G.tune(v.VRT_TUNE_INTERLEAVE, 2)
+            J.zero_()
+            v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_PERSISTENT)
+            G.device_status()
+            flush(f"  mixed-ray items equal level steps: {bool(torch.equal(J, ref))}")
+            assert torch.equal(J, ref)
+            G.tune(v.VRT_TUNE_INTERLEAVE, 0)
         del ref
     G.tune(v.VRT_TUNE_SEGMENT, 0)
     # the reverse sweep, one ray at a time (adjoint rows of one ray: 4.35 GB)

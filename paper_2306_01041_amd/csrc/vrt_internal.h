@@ -198,8 +198,8 @@ struct vrt_grid_s {
   int ray_groups = 1;    // the rays are swept in this many consecutive passes
   int interleave = 0;    // step-wide sweeps read a copy of the records ordered across rays by the site's
                          // horizontal Morton code (1) or by site index (2); 0 = per-ray order
-  int pipe = 0;
-  int regular_tiled = 2;  // regular grids: LDS-tiled plane kernel (1), row kernel (0), tiled in FP64 only (2)          // > 0: level-step sweeps use the pipelined kernel with this many record groups per wave
+  int pipe = 0;          // > 0: level-step sweeps use the pipelined kernel with this many record groups per wave
+  int regular_tiled = 2;  // regular grids: LDS-tiled plane kernel (1), row kernel (0), tiled in FP64 only (2)
   int segment = 0;       // 0: linear source along a line, 1: quadratic Bezier (needs the downwind lines)
   int reverse_persistent = 0;  // 1: the reverse sweep of a ray group runs as one persistent launch
   std::map<int64_t, std::unique_ptr<vrt::PersistItems>> reverse_items;  // keyed by (spw, first ray, group)

@@ -394,6 +394,42 @@ def test_tuning_knobs_do_not_change_results(v, ctx, quad, grids):
     G.close()
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+@pytest.mark.parametrize("nl", [3, 8])
+def test_persistent_items_across_rays_bitwise(v, ctx, quad, grids, prec, nl):
+    """Wave items cut from an interleaved record copy hold records of several
+    rays (each lane addresses its own ray's rows): in both precisions, with
+    whole 16-byte vectors (8 wavelengths) and single elements (3), into the
+    library's sign-encoded rows and into caller rows with epoch stamps, the
+    persistent sweep gives the level steps' J and intensities bit for bit."""
+    flush(f"persistent mixed items {prec} nl={nl}")
+    atm, g = grids[16384]
+    dirs, w = quad
+    dt = torch.float32 if prec == "f32" else torch.float64
+    chi_o, S_o = _fields(atm, nl, 21)
+    chi, S = to_dev(chi_o, dt), to_dev(S_o, dt)
+    R = len(dirs)
+    G = v.Grid.from_synth(ctx, g)
+    G.tune(v.VRT_TUNE_SHARED_LEVELS, 1)
+    G.set_rays(dirs, w, 7.0)
+    Jg = torch.empty_like(chi)
+    Ig = torch.empty((R, g.n, nl), dtype=dt, device="cuda:0")
+    v.formal_solution(G, chi, S, Jg, I_rays=Ig, exec_mode=v.VRT_EXEC_GRAPH)
+    torch.cuda.synchronize()
+    for il in (1, 2):
+        G.tune(v.VRT_TUNE_INTERLEAVE, il)
+        for _ in range(2):
+            J = torch.full_like(chi, -1.0)
+            v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_PERSISTENT)
+            G.device_status()
+            assert torch.equal(J, Jg), ("own rows", il)
+            I = torch.full_like(Ig, -1.0)
+            v.formal_solution(G, chi, S, J, I_rays=I, exec_mode=v.VRT_EXEC_PERSISTENT)
+            G.device_status()
+            assert torch.equal(J, Jg) and torch.equal(I, Ig), ("caller rows", il)
+    G.close()
+
+
 @pytest.mark.parametrize("nl", [1, 64, 101])
 def test_persistent_fp32_matches_graph_bitwise(v, ctx, quad, grids, nl):
     """The persistent dataflow sweep performs the same arithmetic per record as

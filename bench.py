@@ -89,22 +89,20 @@ def counter_traffic(nl, n, mode, layout):
     if nl != 64 or n != 262144 or not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    # the persistent sweep reads the per-ray record order or, with an interleaved
-    # copy built, that copy (wave items then mix rays); its work items follow the
-    # level steps
-    if persistent and any(rec.get("layout", {}).get(k, 0) != layout.get(k, 0)
-                          for k in ("shared_levels", "interleave")):
-        return None
-    if not persistent and ({k: rec.get("layout", {}).get(k) for k in LAYOUT_KEYS}
-                           != {k: layout.get(k) for k in LAYOUT_KEYS}):
-        return None
     h = hashlib.sha256()
     srcs = ("k_persist.hip", "persist.h", "segment.h") if persistent else ("k_sweep.hip", "segment.h")
     for f in srcs:
         h.update(open(os.path.join(ROOT, "paper_2306_01041_amd", "csrc", f), "rb").read())
     if h.hexdigest()[:16] != rec.get("source_sha256_16"):
         return None
-    return rec["sweep_bytes_per_launch"]["total"]
+    # one entry per measured layout: the persistent sweep reads the per-ray
+    # record order or, with an interleaved copy built, that copy (wave items
+    # then mix rays), and its work items follow the level steps
+    keys = ("shared_levels", "interleave") if persistent else LAYOUT_KEYS
+    for e in rec.get("entries", [rec]):
+        if all(e.get("layout", {}).get(k, 0) == layout.get(k, 0) for k in keys):
+            return e["sweep_bytes_per_launch"]["total"]
+    return None
 
 
 def main():

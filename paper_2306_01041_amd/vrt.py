@@ -584,7 +584,13 @@ def _make_lte_emergent():
             J = torch.empty_like(chi_f)
             I = torch.empty((R, n, nl), dtype=fdt, device=dev) if keep_intensities and not mixed else None
             lte_continuum(grid, lam, kappa0, T, rho, chi_f, S_f)
-            formal_solution(grid, chi_f, S_f, J, I_rays=I, exec_mode=VRT_EXEC_BATCHED)
+            # without rows to keep, on a Voronoi grid, the persistent sweep into
+            # the library's own (sign-encoded) rows; rows kept for the backward
+            # pass are fresh buffers every call, so they take eager level steps
+            # (a captured graph would be rebuilt for each)
+            fast = I is None and grid.kind == "voronoi"
+            formal_solution(grid, chi_f, S_f, J, I_rays=I,
+                            exec_mode=VRT_EXEC_PERSISTENT if fast else VRT_EXEC_BATCHED)
             off, _ = grid.emergent_index()
             em = torch.empty((int(off[-1]), nl), dtype=fdt, device=dev)
             emergent_gather(grid, em, I_rays=I)

@@ -227,6 +227,7 @@ def main():
                                                     "xcd_chunks": 8, "ray_affinity": 0, "chains": 1,
                                                     "lane_bytes": 16, "interleave": args.interleave,
                                                     "pipeline": args.pipeline}
+    layout.setdefault("chains", 1)  # the autotuner times one launch chain
     mode_times = {}
     if args.mode == "auto" and tuning:
         args.mode = tuning["chosen"]["exec"]

@@ -272,6 +272,50 @@ def test_tiny_lattice_and_fallback_grids(v, ctx, quad):
     G.close()
 
 
+@pytest.mark.parametrize("shape", [(1, 1, (0.0, 1.0)), (3, 2, (0.5,)), (1, 2, (0.0, 0.5, 1.0)),
+                                   (2, 3, (0.0, 0.3, 1.0))])
+def test_degenerate_grids_and_quadratures(v, ctx, quad, shape):
+    """Degenerate cases of the method: two sites that are their own periodic
+    neighbours, a single layer (every site on both walls: up rays return
+    I_bottom, down rays 0), one-site-wide columns; with the full quadrature, a
+    single oblique ray and one ray pair; every launch mode and layout, in FP64
+    against the oracle and in FP32 within its tolerance. A wavelength count of
+    zero is an argument error."""
+    nx, ny, z = shape
+    flush(f"degenerate grid {nx}x{ny}x{len(z)}")
+    g = synth.lattice_grid(nx, ny, list(z))
+    th = np.radians(40.0)
+    oblique = np.array([[np.sin(th) * np.cos(0.3), np.sin(th) * np.sin(0.3), np.cos(th)]])
+    pair = np.array([[0.0, np.sin(th), np.cos(th)], [0.0, -np.sin(th), -np.cos(th)]])
+    rng = np.random.default_rng(len(z) + 7 * nx)
+    nl = 3
+    chi = rng.uniform(0.2, 3.0, (g.n, nl))
+    S = rng.uniform(0.5, 2.0, (g.n, nl))
+    for dirs, w in (quad, (oblique, np.array([1.0])), (pair, np.array([0.5, 0.5]))):
+        sel = oracle.select(g, dirs)
+        Jo = oracle.fs_voronoi(g, dirs, w, sel, chi, S, S)
+        for shared, il in ((0, 0), (1, 0), (1, 1), (1, 2)):
+            G = v.Grid.from_synth(ctx, g)
+            G.tune(v.VRT_TUNE_SHARED_LEVELS, shared)
+            G.set_rays(dirs, w, 7.0)
+            G.tune(v.VRT_TUNE_INTERLEAVE, il)
+            for d, tol in ((torch.float64, 1e-12), (torch.float32, 1e-5)):
+                c_d, s_d = to_dev(chi, d), to_dev(S, d)
+                for mode in (v.VRT_EXEC_PLAIN, v.VRT_EXEC_GRAPH, v.VRT_EXEC_PERSISTENT):
+                    for rows in (False, True):
+                        J = torch.full((g.n, nl), -1.0, dtype=d, device="cuda:0")
+                        I = torch.empty((len(dirs), g.n, nl), dtype=d, device="cuda:0") if rows else None
+                        v.formal_solution(G, c_d, s_d, J, I_rays=I, exec_mode=mode)
+                        G.device_status()
+                        e = relerr(J.cpu().numpy(), Jo)
+                        assert e <= tol, (shape, len(dirs), shared, il, d, mode, rows, e)
+            with pytest.raises(v.VrtError) as err:
+                e0 = torch.empty((g.n, 0), dtype=torch.float64, device="cuda:0")
+                v.formal_solution(G, e0, e0, torch.empty_like(e0))
+            assert err.value.status == v.VRT_E_ARG
+            G.close()
+
+
 def test_determinism(v, ctx, quad, grids):
     flush("determinism")
     atm, g = grids[1000]

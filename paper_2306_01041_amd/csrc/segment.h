@@ -74,27 +74,34 @@ __host__ __device__ constexpr double inv_factorial(int m) {
 }
 
 template <> struct Seg<double> {
-  // eighteen terms: truncation below 1e-21 relative for x < 1/2
   static __device__ __forceinline__ void weights(double x, double &E, double &pu, double &p0) {
     double d0;
     weights(x, E, pu, p0, d0);
   }
+  // One exponential for both forms. Below x = 1/2 the forms of the single
+  // precision path with longer series: Psi_0 = x P(x) and Psi_u = x (R(x) - P(x)),
+  // R = sum_{n=0..16} (-1)^n x^n/(n+1)! (= (1 - e^-x)/x) and
+  // P = sum_{n=1..16} (-1)^(n+1) x^(n-1)/(n+1)! (= (1 - R)/x), whose
+  // coefficients are R's shifted by one with the sign changed; the first term
+  // left out is below 1e-19 relative. From x = 1/2 up, 1 - e^-x >= 0.39
+  // carries no cancellation, so r = (1 - e^-x)/x keeps double precision.
   static __device__ __forceinline__ void weights(double x, double &E, double &pu, double &p0, double &d0) {
-    if (x < 0.5) {
-      double s0 = 0.0, su = 0.0;
+    E = exp(-x);
+    double R = inv_factorial(17);  // (-1)^16/17!
+    double P = -inv_factorial(17);  // (-1)^17/17!, the x^15 term of P
 #pragma unroll
-      for (int k = 18; k >= 1; --k) {
-        const double c = ((k & 1) ? 1.0 : -1.0) * inv_factorial(k + 1);  // (-1)^(k+1)/(k+1)!
-        s0 = s0 * x + c;
-        su = su * x + (double)k * c;
-      }
-      p0 = s0 * x;
-      pu = su * x;
-      d0 = su;
-      E = exp(-x);
+    for (int n = 15; n >= 0; --n) {
+      const double b = ((n & 1) ? -1.0 : 1.0) * inv_factorial(n + 1);  // (-1)^n/(n+1)!
+      R = R * x + b;
+      if (n >= 1) P = P * x - b;  // the x^(n-1) term of P is -(x^n term of R)
+    }
+    const double Q = R - P;  // Psi_u / x
+    if (x < 0.5) {
+      p0 = x * P;
+      pu = x * Q;
+      d0 = Q;
     } else {
-      E = exp(-x);
-      const double r = -expm1(-x) / x;
+      const double r = (1.0 - E) / x;
       p0 = 1.0 - r;
       pu = r - E;
       d0 = pu / x;

@@ -116,13 +116,14 @@ __device__ __forceinline__ void reverse_record(const int4 q, const typename vrt:
   const T w1 = two ? (T)f.w1 : T(1), w2 = T(1) - (T)f.w1;
   for (int l = l0; l < nl; l += C * V) {
     const VT ck_ = L::load(chi + bk + l), sk = L::load(S + bk + l), ik = L::load(Iown + l);
-    VT ib, sb, cb;
-    for (int e = 0; e < V; ++e) {
-      T seed = gI ? gI[(int64_t)ray * nn + bk + l + e] : T(0);
-      if (gJ) seed += wr * gJ[bk + l + e];
-      L::set(ib, e, seed);
-      L::set(sb, e, T(0));
-      L::set(cb, e, T(0));
+    // the seed: dL/dI of this (ray, site) plus w_r dL/dJ (whole vectors: the
+    // launch takes V > 1 only when both are 16-byte aligned)
+    VT ib = VT(T(0)), sb = VT(T(0)), cb = VT(T(0));
+    if (gI) ib = L::load(gI + (int64_t)ray * nn + bk + l);
+    if (gJ) {
+      const VT j = L::load(gJ + bk + l);
+#pragma unroll
+      for (int e = 0; e < V; ++e) L::set(ib, e, L::get(ib, e) + wr * L::get(j, e));
     }
     // gather from the dependents
     for (int64_t t = d0; t < d1; ++t) {
@@ -430,8 +431,8 @@ void launch_reverse(hipStream_t s, const int4 *ri, const typename RecOf<T>::type
                     const int4 *ck, const T *Ich, const T *Ifr) {
   if (rec_count <= 0) return;
   constexpr int VW = 16 / sizeof(T);
-  const bool aligned = al16(chi) && al16(S) && al16(I) && al16(Ibar) && al16(Sbar) && al16(Cbar) && al16(Ich) &&
-                       al16(Ifr);
+  const bool aligned = al16(chi) && al16(S) && al16(I) && al16(gI) && al16(gJ) && al16(Ibar) && al16(Sbar) &&
+                       al16(Cbar) && al16(Ich) && al16(Ifr);
   if (aligned && nl % VW == 0)
     launch_rv<T, VW>(s, ri, rf, rec_begin, rec_count, nl, n, ray0, dep_ptr, dep_site, dep_rec, chi, S, I, gI, gJ,
                      ray_w, Ibar, Sbar, Cbar, ck, Ich, Ifr);
@@ -456,7 +457,8 @@ void launch_persistent_reverse(hipStream_t s, const PersistItems &items, int32_t
                                int64_t spin_cap) {
   if (items.n_items <= 0) return;
   constexpr int VW = 16 / sizeof(T);
-  const bool aligned = al16(chi) && al16(S) && al16(I) && al16(Ibar) && al16(Sbar) && al16(Cbar);
+  const bool aligned = al16(chi) && al16(S) && al16(I) && al16(gI) && al16(gJ) && al16(Ibar) && al16(Sbar) &&
+                       al16(Cbar);
   if (aligned && nl % VW == 0)
     launch_prv<T, VW>(s, items, max_blocks, ri, rf, nl, n, ray0, dep_ptr, dep_site, dep_rec, chi, S, I, gI, gJ, ray_w,
                       Ibar, Sbar, Cbar, flag_ld, flags, words, spin_cap);

@@ -1106,8 +1106,8 @@ void formal_solution_vjp(vrt_grid g, int32_t nl, const T *chi, const T *S, const
       Ifw = Iw;
     }
     if (g->reverse_persistent) {
-      const bool aligned = vrt::al16(chi) && vrt::al16(S) && vrt::al16(Ifw) && vrt::al16(Ibar) &&
-                           vrt::al16(Sbar) && vrt::al16(Cbar);
+      const bool aligned = vrt::al16(chi) && vrt::al16(S) && vrt::al16(Ifw) && vrt::al16(gI) && vrt::al16(gJ) &&
+                           vrt::al16(Ibar) && vrt::al16(Sbar) && vrt::al16(Cbar);
       const vrt::PersistItems &items =
           reverse_items(g, vrt::reverse_records_per_wave(nl, sizeof(T), aligned), r0, gc);
       int32_t *words = g->d_epoch.as<int32_t>();

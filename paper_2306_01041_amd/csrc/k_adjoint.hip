@@ -419,6 +419,20 @@ void launch_prv(hipStream_t s, const vrt::PersistItems &it, int32_t mb, const in
 #undef VRT_PRC
 }
 
+// Forward rows of the last solution in the reverse sweep's precision: |src|
+// for sign-encoded rows; NaN everywhere if a persistent sweep raised an error
+// (its rows are then not all of one epoch).
+template <typename Tin, typename Tout>
+__global__ void rows_convert_kernel(const Tin *__restrict__ src, bool abs, Tout *__restrict__ dst, int64_t count,
+                                    const int32_t *err) {
+  const bool bad = err && *err != 0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x) {
+    const Tin x = src[t];
+    // (a float widens to double exactly; a double rounds once to the output)
+    dst[t] = bad ? (Tout)__builtin_nan("") : (Tout)(abs ? __builtin_fabs((double)x) : (double)x);
+  }
+}
+
 }  // namespace
 
 namespace vrt {
@@ -441,6 +455,23 @@ void launch_reverse(hipStream_t s, const int4 *ri, const typename RecOf<T>::type
                     ray_w, Ibar, Sbar, Cbar, ck, Ich, Ifr);
   VRT_HIP(hipGetLastError());
 }
+
+template <typename T>
+void launch_rows_convert(hipStream_t s, const void *src, bool src_f32, bool abs, T *dst, int64_t count,
+                         const int32_t *err) {
+  if (count <= 0) return;
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (src_f32)
+    hipLaunchKernelGGL((rows_convert_kernel<float, T>), dim3((unsigned)blocks), dim3(256), 0, s,
+                       static_cast<const float *>(src), abs, dst, count, err);
+  else
+    hipLaunchKernelGGL((rows_convert_kernel<double, T>), dim3((unsigned)blocks), dim3(256), 0, s,
+                       static_cast<const double *>(src), abs, dst, count, err);
+  VRT_HIP(hipGetLastError());
+}
+template void launch_rows_convert<float>(hipStream_t, const void *, bool, bool, float *, int64_t, const int32_t *);
+template void launch_rows_convert<double>(hipStream_t, const void *, bool, bool, double *, int64_t, const int32_t *);
 
 int32_t reverse_records_per_wave(int32_t nl, int elem_bytes, bool aligned) {
   const int VW = 16 / elem_bytes;

@@ -617,6 +617,7 @@ void take_device_error(vrt_grid g, int32_t iter) {
   if (err == 0) return;
   VRT_HIP(hipMemset(g->d_epoch.as<int32_t>() + 1, 0, 4));
   for (int k = 0; k < 4; ++k) g->sgn_key[k] = 0;
+  ++g->solution_id;  // the last solution's rows may be of no single epoch
   char at[48] = "";
   if (iter > 0) snprintf(at, sizeof at, " at iteration %d", iter);
   if (err & 2)
@@ -1168,6 +1169,7 @@ vrt_status two_level_solve(vrt_grid g, vrt_exec ex, int32_t nl, const double *wl
   constexpr int32_t per16 = 16 / (int32_t)sizeof(T);
   const int32_t ld = (nl + per16 - 1) / per16 * per16;
   const size_t nn = (size_t)g->n * (size_t)ld;
+  ++g->solution_id;  // from here on the last solution's rows may be overwritten
   T *I = intensity_buffer<T>(g, ld, nullptr);
   VRT_HIP(hipStreamSynchronize(s));  // earlier work may still read the buffers replaced below
   g->d_nchi.alloc(nn * sizeof(T));
@@ -1289,6 +1291,8 @@ vrt_status two_level_solve(vrt_grid g, vrt_exec ex, int32_t nl, const double *wl
   g->last_prec = sizeof(T) == 4 ? VRT_F32 : VRT_F64;
   g->last_nl = nl;
   g->last_ld = ld;
+  g->last_own = true;
+  ++g->solution_id;
   return n_active == 0 ? VRT_OK : VRT_W_NOT_CONVERGED;
 }
 
@@ -1300,6 +1304,7 @@ void formal_solution(vrt_grid g, vrt_exec ex, int32_t nl, const void *chi_, cons
   const T *It = static_cast<const T *>(It_);
   T *J = static_cast<T *>(J_);
   vrt_ctx ctx = g->ctx;
+  ++g->solution_id;  // from here on the last solution's rows may be overwritten
   if (ex == VRT_EXEC_PERSISTENT && g->kind != 0) ex = VRT_EXEC_GRAPH;
   // the linear-segment persistent sweep into the library's own rows uses the
   // sign-encoded protocol; rows handed in by the caller keep the stamps
@@ -1341,6 +1346,8 @@ void formal_solution(vrt_grid g, vrt_exec ex, int32_t nl, const void *chi_, cons
   g->last_prec = sizeof(T) == 4 ? VRT_F32 : VRT_F64;
   g->last_nl = nl;
   g->last_ld = nl;
+  g->last_own = Ir_ == nullptr;
+  ++g->solution_id;
 }
 
 bool valid_prec(vrt_prec p) { return p == VRT_F64 || p == VRT_F32; }
@@ -1616,6 +1623,7 @@ vrt_status vrt_grid_set_rays(vrt_grid g, int32_t n_rays, const double *dir, cons
     for (int k = 0; k < 4; ++k) g->sgn_key[k] = 0;
     g->last_I = nullptr;  // the rows it pointed to are gone
     g->last_abs = false;
+    ++g->solution_id;
     if (g->kind == 0) {
       set_rays_voronoi(g);
     } else {
@@ -2000,6 +2008,7 @@ vrt_status vrt_formal_solution_noalloc(vrt_grid g, vrt_prec prec, int32_t n_lamb
     // later gather may read them as this grid's last solution
     g->last_I = nullptr;
     g->last_abs = false;
+    ++g->solution_id;
     return VRT_OK;
   });
 }
@@ -2090,6 +2099,60 @@ vrt_status vrt_formal_solution_vjp(vrt_grid g, vrt_prec prec, int32_t n_lambda, 
       formal_solution_vjp<T>(g, n_lambda, (const T *)chi, (const T *)S, ib, (const T *)I_top, (const T *)I_rays,
                              (const T *)dL_dI, (const T *)dL_dJ, (T *)dL_dchi, (T *)dL_dS, (T *)dL_dIbottom,
                              (T *)dL_dItop, ray_group, checkpoint_levels);
+    }
+    return VRT_OK;
+  });
+}
+
+vrt_status vrt_grid_solution_id(vrt_grid g, int64_t *id) {
+  if (!g || !id) return VRT_E_ARG;
+  *id = g->solution_id;
+  return VRT_OK;
+}
+
+vrt_status vrt_formal_solution_vjp_last(vrt_grid g, vrt_prec prec, int32_t n_lambda, const void *chi, const void *S,
+                                        const void *I_bottom, const void *I_top, const void *dL_dI,
+                                        const void *dL_dJ, void *dL_dchi, void *dL_dS, void *dL_dIbottom,
+                                        void *dL_dItop, int32_t ray_group, int64_t solution_id) {
+  if (!g) return VRT_E_ARG;
+  return guarded(g->ctx, [&] {
+    if (!valid_prec(prec) || n_lambda <= 0 || ray_group < 0)
+      fail(VRT_E_ARG, "bad precision, n_lambda or ray group");
+    if (g->kind != 0) fail(VRT_E_ARG, "the reverse sweep exists for Voronoi grids only");
+    if (g->segment) fail(VRT_E_ARG, "the reverse sweep differentiates the linear segment only");
+    if (g->R == 0) fail(VRT_E_STATE, "rays not set");
+    if (!chi || !S) fail(VRT_E_ARG, "chi and S are required");
+    if (!dL_dI && !dL_dJ) fail(VRT_E_ARG, "give dL_dI, dL_dJ or both");
+    if (solution_id != g->solution_id || !g->last_I || !g->last_own)
+      fail(VRT_E_STATE, "the grid's last formal solution is not solution %lld", (long long)solution_id);
+    if (g->last_nl != n_lambda || g->last_ld != n_lambda)
+      fail(VRT_E_STATE, "the last solution had %d wavelengths in rows of %d", g->last_nl, g->last_ld);
+    if (g->n == 0) return VRT_OK;
+    // the last solution's rows of every ray, in this precision, in the
+    // reverse sweep's own scratch (NaN if its persistent sweep raised an error)
+    const size_t el = prec == VRT_F32 ? 4 : 8;
+    const int64_t count = (int64_t)g->R * g->n * n_lambda;
+    g->d_vIch.release();
+    g->d_vIfr.release();
+    g->d_vI.alloc((size_t)count * el);
+    const int32_t *err = g->last_abs ? g->d_epoch.as<int32_t>() + 1 : nullptr;
+    hipStream_t s = g->ctx->stream;
+    if (prec == VRT_F32) {
+      using T = float;
+      T *Ifw = g->d_vI.as<T>();
+      vrt::launch_rows_convert<T>(s, g->last_I, g->last_prec == VRT_F32, g->last_abs, Ifw, count, err);
+      const T *ib = I_bottom ? (const T *)I_bottom : (const T *)S;
+      formal_solution_vjp<T>(g, n_lambda, (const T *)chi, (const T *)S, ib, (const T *)I_top, Ifw,
+                             (const T *)dL_dI, (const T *)dL_dJ, (T *)dL_dchi, (T *)dL_dS, (T *)dL_dIbottom,
+                             (T *)dL_dItop, ray_group, 0);
+    } else {
+      using T = double;
+      T *Ifw = g->d_vI.as<T>();
+      vrt::launch_rows_convert<T>(s, g->last_I, g->last_prec == VRT_F32, g->last_abs, Ifw, count, err);
+      const T *ib = I_bottom ? (const T *)I_bottom : (const T *)S;
+      formal_solution_vjp<T>(g, n_lambda, (const T *)chi, (const T *)S, ib, (const T *)I_top, Ifw,
+                             (const T *)dL_dI, (const T *)dL_dJ, (T *)dL_dchi, (T *)dL_dS, (T *)dL_dIbottom,
+                             (T *)dL_dItop, ray_group, 0);
     }
     return VRT_OK;
   });

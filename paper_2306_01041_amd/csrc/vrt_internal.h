@@ -226,6 +226,10 @@ struct vrt_grid_s {
   int64_t sgn_key[4] = {0, 0, 0, 0};
   int last_prec = -1;            // their precision, wavelength count and row stride
   int32_t last_nl = 0, last_ld = 0;
+  bool last_own = false;         // last_I is one of the library's own row blocks
+  // identifies the last solution whose rows last_I holds: it grows with every
+  // call that writes or drops the library's rows (or finds a device error)
+  int64_t solution_id = 0;
 
   // persistent sweep state: per-(ray, site) epoch stamps, the epoch, a device
   // error flag (a bounded wait gave up) and wave-item tables by width
@@ -350,6 +354,12 @@ void launch_persistent_sweep(hipStream_t s, const PersistItems &items, int32_t m
                              const typename RecOf<T>::type *rf, int32_t nl, int64_t n, int64_t flag_ld, const T *chi,
                              const T *S, const T *Ibot, const T *Itop, T *I, int32_t *flags, int32_t *words,
                              int64_t spin_cap, bool sign = false, int32_t mixed_rays = 0);
+
+// dst[i] = |src[i]| (abs) or src[i], converted to T; NaN everywhere when the
+// persistent sweeps' error word (err, may be null) is set
+template <typename T>
+void launch_rows_convert(hipStream_t s, const void *src, bool src_f32, bool abs, T *dst, int64_t count,
+                         const int32_t *err);
 
 // ---- k_nlte.hip
 template <typename T>

@@ -117,6 +117,10 @@ vrt_two_level_solve_batched = _sig("vrt_two_level_solve_batched", _st,
 vrt_formal_solution_vjp = _sig("vrt_formal_solution_vjp", _st, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp,
                                                                 _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                                                 ctypes.c_int32, ctypes.c_int32])
+vrt_grid_solution_id = _sig("vrt_grid_solution_id", _st, [_vp, ctypes.POINTER(ctypes.c_int64)])
+vrt_formal_solution_vjp_last = _sig("vrt_formal_solution_vjp_last", _st,
+                                    [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                     _vp, _vp, ctypes.c_int32, ctypes.c_int64])
 vrt_formal_solution_vjp_scratch = _sig("vrt_formal_solution_vjp_scratch", _st,
                                        [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)])
@@ -324,6 +328,12 @@ class Grid:
         return dict(k1=k1, k2=k2, w1=w1, ds1=d1, ds2=d2, level=lev, order=order, level_ptr=lp[: nl.value + 1].copy(),
                     n_levels=nl.value)
 
+    def solution_id(self) -> int:
+        """Identifier of the grid's last solution (see formal_solution_vjp_last)."""
+        out = ctypes.c_int64(0)
+        self.ctx.check(vrt_grid_solution_id(self.handle, ctypes.byref(out)))
+        return int(out.value)
+
     def device_status(self):
         """Synchronise and raise VrtError(VRT_E_TIMEOUT) if a bounded device wait gave up."""
         self.ctx.check(vrt_grid_device_status(self.handle))
@@ -517,6 +527,27 @@ def formal_solution_vjp(grid: Grid, chi, S, dL_dI=None, dL_dJ=None, I_bottom=Non
     return tuple(outs)
 
 
+def formal_solution_vjp_last(grid: Grid, solution_id: int, chi, S, dL_dI=None, dL_dJ=None, I_bottom=None,
+                             I_top=None, ray_group: int = 0):
+    """formal_solution_vjp with the forward intensities of the grid's last formal
+    solution (the one whose Grid.solution_id() was `solution_id`), converted to
+    chi's precision instead of recomputed. Raises VrtError (VRT_E_STATE) when
+    the grid has solved again since, or that solution kept no rows of its own."""
+    import torch
+
+    inf = grid.info()
+    n, R = inf["n_sites"], inf["n_rays"]
+    nl = chi.shape[1]
+    for t, name in ((chi, "chi"), (S, "S"), (dL_dJ, "dL_dJ"), (I_bottom, "I_bottom"), (I_top, "I_top")):
+        _need(t, (n, nl), chi.dtype, name)
+    _need(dL_dI, (R, n, nl), chi.dtype, "dL_dI")
+    outs = [torch.empty((n, nl), dtype=chi.dtype, device=chi.device) for _ in range(4)]
+    grid.ctx.check(vrt_formal_solution_vjp_last(grid.handle, _prec_of(chi), int(nl), _dev(chi), _dev(S),
+                                                _dev(I_bottom), _dev(I_top), _dev(dL_dI), _dev(dL_dJ),
+                                                *[_dev(o) for o in outs], int(ray_group), int(solution_id)))
+    return tuple(outs)
+
+
 def formal_solution_vjp_scratch(grid: Grid, dtype, n_lambda: int, keep_intensities: bool = False,
                                 ray_group: int = 0, checkpoint_levels: int = 0) -> int:
     """Device bytes of scratch that formal_solution_vjp holds for these settings."""
@@ -565,8 +596,10 @@ def _make_lte_emergent():
 
         Forward: chi, S = lte_continuum(T, rho); formal solution; emergent
         gather. Backward: emergent scatter, the hand-written reverse sweep
-        (vrt_formal_solution_vjp) and the LTE chain rule; every step runs in
-        the library's kernels."""
+        (vrt_formal_solution_vjp_last on the forward solution's own rows when
+        nothing has solved on the grid since, else vrt_formal_solution_vjp,
+        which recomputes them) and the LTE chain rule; every step runs in the
+        library's kernels."""
 
         @staticmethod
         def forward(fctx, T, rho, grid, lam, kappa0, dtype, keep_intensities, ray_group, emergent_dtype,
@@ -591,6 +624,11 @@ def _make_lte_emergent():
             fast = I is None and grid.kind == "voronoi"
             formal_solution(grid, chi_f, S_f, J, I_rays=I,
                             exec_mode=VRT_EXEC_PERSISTENT if fast else VRT_EXEC_BATCHED)
+            # the backward pass may take this solution's rows (all rays at once)
+            # instead of recomputing them, if nothing has solved on the grid
+            # since; not when ray groups or checkpoints bound its memory
+            reuse = I is None and checkpoint_levels == 0 and ray_group == 0
+            fctx.solution = grid.solution_id() if reuse else None
             off, _ = grid.emergent_index()
             em = torch.empty((int(off[-1]), nl), dtype=fdt, device=dev)
             emergent_gather(grid, em, I_rays=I)
@@ -615,9 +653,18 @@ def _make_lte_emergent():
             inf = grid.info()
             gI = torch.empty((inf["n_rays"], inf["n_sites"], chi.shape[1]), dtype=chi.dtype, device=chi.device)
             emergent_scatter(grid, g_em.contiguous().to(chi.dtype), gI)
-            g_chi, g_S, g_Ib, _ = formal_solution_vjp(grid, chi, S, dL_dI=gI, I_rays=fctx.I,
-                                                      ray_group=fctx.ray_group,
-                                                      checkpoint_levels=fctx.checkpoint_levels)
+            out = None
+            if fctx.solution is not None:
+                try:
+                    out = formal_solution_vjp_last(grid, fctx.solution, chi, S, dL_dI=gI, ray_group=fctx.ray_group)
+                except VrtError as e:
+                    if e.status != VRT_E_STATE:
+                        raise
+                    # the grid solved again since the forward pass: recompute
+            if out is None:
+                out = formal_solution_vjp(grid, chi, S, dL_dI=gI, I_rays=fctx.I, ray_group=fctx.ray_group,
+                                          checkpoint_levels=fctx.checkpoint_levels)
+            g_chi, g_S, g_Ib, _ = out
             gT, gr = lte_continuum_vjp(grid, fctx.lam, fctx.kappa0, T, rho, g_chi, g_S, g_Ib)
             return gT, gr, None, None, None, None, None, None, None, None
 
@@ -636,15 +683,22 @@ def lte_emergent(T, rho, grid: Grid, lam, kappa0, dtype=None, keep_intensities=T
     default float64 when the sweeps are float32: a misfit's residuals are often
     a fraction of a percent of the intensities, and a single-precision forward
     sweep's ~1e-6 rounding would then reach the gradient at ~1e-4. The reverse
-    sweep still runs in single precision on its own single-precision forward
-    intensities. Pass emergent_dtype=torch.float32 for an all-single-precision
+    sweep still runs in single precision. Pass emergent_dtype=torch.float32 for an all-single-precision
     pipeline (faster forward, gradients good to ~1e-3 of central differences
     in that regime).
 
-    Memory: keep_intensities=False drops the forward intensities after the
-    forward pass (the backward pass recomputes them), ray_group bounds the
+    Without intensities of its own to keep (the default mixed-precision
+    pipeline, or keep_intensities=False) the forward sweep runs into the
+    library's rows, and the backward pass takes its forward intensities from
+    those rows, rounded to the sweep precision, if nothing has solved on the
+    grid in between; otherwise it recomputes them in the sweep precision.
+
+    Memory: keep_intensities=False holds no intensity tensor between the passes
+    (the backward pass takes the library's rows as above, or recomputes them),
+    ray_group bounds the
     rays whose adjoint rows are held at once, and checkpoint_levels = k > 0
-    keeps only per-level-chunk checkpoints of the recomputed intensities.
+    keeps only per-level-chunk checkpoints of the recomputed intensities; with
+    either of the last two the backward pass always recomputes.
     """
     import torch
 

@@ -219,6 +219,80 @@ def test_level_chunk_checkpoints_are_bit_identical(v, ctx, case, nl, prec):
     G.close()
 
 
+@pytest.mark.parametrize("fwd", ["f64 persistent", "f32 graph"])
+def test_reverse_sweep_on_the_last_solutions_rows(v, ctx, case, fwd):
+    """The reverse sweep on the last formal solution's rows kept by the library
+    (sign-encoded rows of the FP64 persistent sweep, or plain FP32 rows),
+    converted to the sweep's precision, equals the reverse sweep handed the
+    same rows bit for bit. Any later solve, or a solution into caller rows,
+    makes the solution unusable (VRT_E_STATE)."""
+    flush(f"vjp on the last solution ({fwd})")
+    atm, g, dirs, w, sel = case
+    nl = 8
+    lam = np.linspace(500e-9, 700e-9, nl)
+    chi, S = oracle.lte(lam, atm.kappa0, atm.T, atm.rho)
+    R = len(dirs)
+    G = v.Grid.from_synth(ctx, g)
+    G.set_rays(dirs, w)
+    dt = torch.float64 if fwd.startswith("f64") else torch.float32
+    mode = v.VRT_EXEC_PERSISTENT if "persistent" in fwd else v.VRT_EXEC_GRAPH
+    c_f, s_f = to_dev(chi, dt), to_dev(S, dt)
+    J = torch.empty_like(c_f)
+    I_ref = torch.empty((R, g.n, nl), dtype=dt, device="cuda:0")
+    v.formal_solution(G, c_f, s_f, J, I_rays=I_ref, exec_mode=v.VRT_EXEC_GRAPH)
+    v.formal_solution(G, c_f, s_f, J, exec_mode=mode)
+    sid = G.solution_id()
+    f32 = torch.float32
+    c32, s32 = to_dev(chi, f32), to_dev(S, f32)
+    gI = to_dev(np.random.default_rng(3).standard_normal((R, g.n, nl)), f32)
+    got = v.formal_solution_vjp_last(G, sid, c32, s32, dL_dI=gI)
+    want = v.formal_solution_vjp(G, c32, s32, dL_dI=gI, I_rays=I_ref.to(f32).contiguous())
+    G.device_status()
+    for a, b in zip(got, want):
+        assert torch.equal(a, b)
+    # a ray group at a time, from the same converted rows
+    got2 = v.formal_solution_vjp_last(G, sid, c32, s32, dL_dI=gI, ray_group=5)
+    want2 = v.formal_solution_vjp(G, c32, s32, dL_dI=gI, I_rays=I_ref.to(f32).contiguous(), ray_group=5)
+    for a, b in zip(got2, want2):
+        assert torch.equal(a, b)
+    v.formal_solution(G, c_f, s_f, J, exec_mode=mode)
+    with pytest.raises(v.VrtError) as e:
+        v.formal_solution_vjp_last(G, sid, c32, s32, dL_dI=gI)
+    assert e.value.status == v.VRT_E_STATE
+    v.formal_solution(G, c_f, s_f, J, I_rays=I_ref, exec_mode=mode)
+    with pytest.raises(v.VrtError) as e:
+        v.formal_solution_vjp_last(G, G.solution_id(), c32, s32, dL_dI=gI)
+    assert e.value.status == v.VRT_E_STATE
+    G.close()
+
+
+def test_autograd_reuses_the_forward_rows_or_recomputes(v, ctx, case):
+    """The differentiable emergent intensity takes its backward pass's forward
+    rows from its own FP64 forward solution, and recomputes them in FP32 when
+    the grid has solved again in between; the two gradients agree to the
+    single-precision rounding of the rows."""
+    flush("autograd reuse or recompute")
+    atm, g, dirs, w, sel = case
+    lam = np.linspace(500e-9, 700e-9, 4)
+    G = v.Grid.from_synth(ctx, g)
+    G.set_rays(dirs, w)
+    off, _ = G.emergent_index()
+    cvec = to_dev(np.random.default_rng(8).standard_normal((int(off[-1]), len(lam))), torch.float64)
+    grads = []
+    for intervene in (False, True):
+        T = to_dev(atm.T, torch.float64).requires_grad_(True)
+        rho = to_dev(atm.rho, torch.float64).requires_grad_(True)
+        L = (v.lte_emergent(T, rho, G, lam, atm.kappa0, dtype=torch.float32).double() * cvec).sum()
+        if intervene:
+            x = torch.ones((g.n, 2), dtype=torch.float32, device="cuda:0")
+            v.formal_solution(G, x, x, torch.empty_like(x))
+        L.backward()
+        grads.append((T.grad.cpu().numpy(), rho.grad.cpu().numpy()))
+    for a, b in zip(grads[0], grads[1]):
+        assert normerr(a, b) <= 1e-5
+    G.close()
+
+
 def test_lte_chain_rule_matches_oracle(v, ctx, case):
     flush("lte vjp")
     atm, g, dirs, w, sel = case

@@ -323,6 +323,17 @@ def test_c2_one_iteration_full_size(v, ctx):
     st, nit, hist = v.two_level_solve(G, line.wlam, to_dev(line.phi, d), to_dev(line.chi_line, d), chi_c, B, eps, S,
                                       max_iter=1, tol=0.0, sweep_dtype=torch.float32)
     torch.cuda.synchronize()
+    # the same iteration with the persistent sweep, whose wave items mix the
+    # rays of the site-order copy and address every ray's rows (10.5 GB)
+    # through 2 GiB windows: the same bits
+    S_p = B.clone()
+    st_p, nit_p, hist_p = v.two_level_solve(G, line.wlam, to_dev(line.phi, d), to_dev(line.chi_line, d), chi_c, B,
+                                            eps, S_p, max_iter=1, tol=0.0, sweep_dtype=torch.float32,
+                                            exec_mode=v.VRT_EXEC_PERSISTENT)
+    G.device_status()
+    flush(f"  persistent iteration equals the graph's: {bool(torch.equal(S_p, S))}")
+    assert torch.equal(S_p, S) and hist_p[0] == hist[0]
+    del S_p
     sel = oracle.select(g, dirs)
     G.tune(v.VRT_TUNE_SHARED_LEVELS, 0)  # per-ray schedules, to compare with the oracle's
     _check_schedules(G, g, dirs, sel)

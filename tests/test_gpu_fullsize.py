@@ -356,7 +356,8 @@ def test_c3_batch_one_iteration_full_size(v, ctx):
     1042..1089; about 10 million sites in one grid), one plain Lambda iteration
     with FP32 sweeps in the graph-launched mode and layout the benchmark times, against
     standalone oracle iterations of four of its atmospheres (the smallest, the
-    largest and two seeded picks): S_line to 1e-5, atmosphere by atmosphere."""
+    largest and two seeded picks): S_line to 1e-5, atmosphere by atmosphere; the
+    same iteration as one persistent sweep gives the graph's bits."""
     import multiprocessing as mp
 
     from synth.nlte import line_case
@@ -398,6 +399,18 @@ def test_c3_batch_one_iteration_full_size(v, ctx):
     st, its, hist = v.two_level_solve_batched(G, off, lines[0].wlam, phi, chi_L, chi_c, B, eps, S, max_iter=1,
                                               tol=0.0, sweep_dtype=torch.float32, exec_mode=v.VRT_EXEC_GRAPH)
     torch.cuda.synchronize()
+    # the whole batch's iteration as one persistent sweep (items mixing the
+    # rays of the site-order copy, 100 GB of rows through 2 GiB windows): the
+    # same bits
+    flush("  GPU: the same iteration with the persistent sweep")
+    S_p = B.clone()
+    st_p, its_p, hist_p = v.two_level_solve_batched(G, off, lines[0].wlam, phi, chi_L, chi_c, B, eps, S_p,
+                                                    max_iter=1, tol=0.0, sweep_dtype=torch.float32,
+                                                    exec_mode=v.VRT_EXEC_PERSISTENT)
+    G.device_status()
+    flush(f"  persistent iteration equals the graph's: {bool(torch.equal(S_p, S))}")
+    assert torch.equal(S_p, S) and np.array_equal(hist_p, hist)
+    del S_p
     S = S.cpu().numpy()
     G.close()
     del phi, chi_L, chi_c, B

@@ -1,10 +1,12 @@
 """Benchmark: site*ray*wavelength updates per second of the formal solution on a
 262,144-site Voronoi grid (64 wavelengths 400-900 nm, 24 rays), one GPU.
 
-One step = grey LTE source assembly (chi = kappa0 rho^2 T^9, S = B_lambda(T))
-+ the FP32 formal solution of all 24 rays, level step by level step, captured
-in a HIP graph + the angle quadrature of J (double accumulation) + the
-emergent-intensity gather. Inputs (T, rho) are resident on the GPU before the
+One step = grey LTE source assembly (chi = kappa0 rho^2 T^9, S = B_lambda(T),
+a site's two rows side by side in one [n][2][64] array unless --rows separate)
++ the FP32 formal solution of all 24 rays in the launch mode and layout the
+library's autotuner picks (the persistent sweep or graph-captured level steps)
++ the angle quadrature of J (double accumulation) + the emergent-intensity
+gather. Inputs (T, rho) are resident on the GPU before the
 timed region. The grid, its quadrature and the per-ray schedules are built
 once, outside the timed region.
 
@@ -73,7 +75,9 @@ def sweep_bytes_per_update(nl: int, fp: int) -> float:
 
 
 LAYOUT_KEYS = ("record_order", "shared_levels", "xcd_chunks", "ray_affinity", "chains", "lane_bytes", "interleave",
-               "pipeline")
+               "pipeline", "rows")
+# layout values of summaries that predate a key
+LAYOUT_DEFAULTS = {"rows": "separate"}
 
 
 def counter_traffic(nl, n, mode, layout):
@@ -98,9 +102,10 @@ def counter_traffic(nl, n, mode, layout):
     # one entry per measured layout: the persistent sweep reads the per-ray
     # record order or, with an interleaved copy built, that copy (wave items
     # then mix rays), and its work items follow the level steps
-    keys = ("shared_levels", "interleave") if persistent else LAYOUT_KEYS
+    keys = ("shared_levels", "interleave", "rows") if persistent else LAYOUT_KEYS
     for e in rec.get("entries", [rec]):
-        if all(e.get("layout", {}).get(k, 0) == layout.get(k, 0) for k in keys):
+        if all(e.get("layout", {}).get(k, LAYOUT_DEFAULTS.get(k, 0)) == layout.get(k, LAYOUT_DEFAULTS.get(k, 0))
+               for k in keys):
             return e["sweep_bytes_per_launch"]["total"]
     return None
 
@@ -128,6 +133,9 @@ def main():
     ap.add_argument("--pipeline", type=int, choices=[0, 2, 4, 8], default=0,
                     help="with a fixed layout: interior level steps launch the pipelined sweep kernel with this "
                          "many groups of records in flight per wavefront (0: the plain level-step kernel)")
+    ap.add_argument("--rows", choices=["paired", "separate"], default="paired",
+                    help="timed formal solutions: chi and S of a site in one [2][n_lambda] row pair "
+                         "(vrt_formal_solution_ld, the layout of the two-level iteration) or in separate arrays")
     ap.add_argument("--workload", choices=["c1", "c2", "c3", "synth", "design"], default="c1",
                     help="c1: the formal solution (default line); c2: the two-level Lambda iteration on 1,048,576 "
                          "sites; c3: 48 atmospheres of 32,768-524,288 sites solved as one batch; synth: only the "
@@ -210,6 +218,13 @@ def main():
     chi = torch.empty((g.n, nl), dtype=f32, device=dev)
     S = torch.empty_like(chi)
     J = torch.empty_like(chi)
+    # the timed steps' opacity and source: a site's two rows side by side
+    # (views of one [n][2][nl] array) or the separate arrays above
+    if args.rows == "paired":
+        cs = torch.empty((g.n, 2, nl), dtype=f32, device=dev)
+        chi_t, S_t = cs[:, 0], cs[:, 1]
+    else:
+        chi_t, S_t = chi, S
     off, _ = G.emergent_index()
     em = torch.empty((int(off[-1]), nl), dtype=f32, device=dev)
 
@@ -217,6 +232,9 @@ def main():
     # the library's autotuner times the launch layouts and the persistent sweep
     # on this workload and keeps the fastest on the grid (its launch mode too)
     v.lte_continuum(G, lam, atm.kappa0, T, rho, chi, S)
+    if chi_t is not chi:
+        v.lte_continuum(G, lam, atm.kappa0, T, rho, chi_t, S_t)
+    # (the autotuner takes arrays of n x n_lambda)
     tuning = None if args.no_autotune else v.autotune(G, chi, S, J, reps=5)
     log(f"autotune: {tuning}")
     if tuning is None:
@@ -228,6 +246,7 @@ def main():
                                                     "lane_bytes": 16, "interleave": args.interleave,
                                                     "pipeline": args.pipeline}
     layout.setdefault("chains", 1)  # the autotuner times one launch chain
+    layout["rows"] = args.rows
     mode_times = {}
     if args.mode == "auto" and tuning:
         args.mode = tuning["chosen"]["exec"]
@@ -239,11 +258,11 @@ def main():
         for name in ("graph", "persistent"):
             try:
                 for _ in range(2):
-                    v.formal_solution(G, chi, S, J, exec_mode=modes[name])
+                    v.formal_solution(G, chi_t, S_t, J, exec_mode=modes[name])
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 for _ in range(5):
-                    v.formal_solution(G, chi, S, J, exec_mode=modes[name])
+                    v.formal_solution(G, chi_t, S_t, J, exec_mode=modes[name])
                 G.device_status()
                 mode_times[name] = (time.perf_counter() - t0) * 1e3 / 5
             except v.VrtError as e:  # a mode that reports an error is not a candidate
@@ -253,8 +272,8 @@ def main():
     mode = modes[args.mode]
 
     def step():
-        v.lte_continuum(G, lam, atm.kappa0, T, rho, chi, S)
-        v.formal_solution(G, chi, S, J, exec_mode=mode)
+        v.lte_continuum(G, lam, atm.kappa0, T, rho, chi_t, S_t)
+        v.formal_solution(G, chi_t, S_t, J, exec_mode=mode)
         v.emergent_gather(G, em)
 
     for _ in range(args.warmup):
@@ -279,14 +298,14 @@ def main():
     nprof = 10
     ev0.record(stream)
     for _ in range(nprof):
-        v.formal_solution(G, chi, S, J, exec_mode=mode)
+        v.formal_solution(G, chi_t, S_t, J, exec_mode=mode)
     ev1.record(stream)
     ev1.synchronize()
     fs_ms = ev0.elapsed_time(ev1) / nprof
     ctx.profile_reset()
     ctx.set_profiling(True)
     for _ in range(3):
-        v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_BATCHED)
+        v.formal_solution(G, chi_t, S_t, J, exec_mode=v.VRT_EXEC_BATCHED)
     sw_ms_ev, sw_launches, sw_units = ctx.profile(0)
     jr_ms, jr_launches, jr_units = ctx.profile(1)
     ctx.set_profiling(False)
@@ -340,12 +359,12 @@ def main():
         ms_by_mode = {}
         for name, m in (("graph", v.VRT_EXEC_GRAPH), ("persistent", v.VRT_EXEC_PERSISTENT)):
             try:
-                v.formal_solution(G, chi, S, J, exec_mode=m)
+                v.formal_solution(G, chi_t, S_t, J, exec_mode=m)
                 torch.cuda.synchronize()
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
                 for _ in range(5):
-                    v.formal_solution(G, chi, S, J, exec_mode=m)
+                    v.formal_solution(G, chi_t, S_t, J, exec_mode=m)
                 e1.record(stream)
                 e1.synchronize()
                 G.device_status()
@@ -452,7 +471,7 @@ def main():
     regular = None
     synthesis = None
     if not args.no_regular:
-        del chi, S, J
+        del chi, S, J, chi_t, S_t
         nx = ny = 128
         nz = 256
         dxr, dyr, zr, xyz = regular_recipe(atm.box, nx, ny, nz)
@@ -574,8 +593,8 @@ def main():
     # the two-level iteration workloads, whose sweeps read more than the 256 MB
     # of the last-level cache holds: 1,048,576 sites, and 48 atmospheres in one batch
     if not args.no_lambda:
-        out["c2"] = lambda_block("c2", max_iter=20, accel_iter=1000, workers=args.workers)
-        out["c3"] = lambda_block("c3", max_iter=5, accel_iter=200, workers=args.workers)
+        out["c2"] = lambda_block("c2", max_iter=20, accel_iter=1000, workers=args.workers, rows=args.rows)
+        out["c3"] = lambda_block("c3", max_iter=5, accel_iter=200, workers=args.workers, rows=args.rows)
     print(json.dumps(out))
 
 
@@ -822,7 +841,7 @@ def run_design(args):
 
 
 LAMBDA_LAYOUT_KEYS = ("record_order", "shared_levels", "xcd_chunks", "ray_affinity", "lane_bytes", "interleave",
-                      "pipeline")
+                      "pipeline", "rows")
 
 
 def sweep_kernel_names(mode, layout, c):
@@ -849,8 +868,10 @@ def lambda_counter_traffic(workload, mode, layout):
     rec = json.load(open(path))
     if rec.get("launch_mode") != mode:
         return None
-    if mode != "persistent" and ({k: rec.get("layout", {}).get(k) for k in LAMBDA_LAYOUT_KEYS}
-                                 != {k: layout.get(k) for k in LAMBDA_LAYOUT_KEYS}):
+    if mode != "persistent" and ({k: rec.get("layout", {}).get(k, LAYOUT_DEFAULTS.get(k)) for k in LAMBDA_LAYOUT_KEYS}
+                                 != {k: layout.get(k, LAYOUT_DEFAULTS.get(k)) for k in LAMBDA_LAYOUT_KEYS}):
+        return None
+    if mode == "persistent" and rec.get("layout", {}).get("rows", "separate") != layout.get("rows", "separate"):
         return None
     h = hashlib.sha256()
     for f in rec.get("sources", []):
@@ -916,7 +937,7 @@ def lambda_inputs(workload, workers, cache_dir=None):
 
 
 def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", interleave=0, pipeline=0, workers=16,
-                 cache_dir=None, shared_levels=0):
+                 cache_dir=None, shared_levels=0, rows="paired"):
     """Two-level Lambda iteration on 1,048,576 sites (c2) or on a batch of 48
     atmospheres of 32,768-524,288 sites (c3): 101 line wavelengths (rows padded
     to 104), 24 rays, eps = 1e-4, FP32 sweeps, FP64 line update, graph-captured
@@ -969,8 +990,9 @@ def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", int
 
     # the formal solution alone, on the fields of the first iteration, in the
     # library's own layout inside the iteration: rows padded to 104 entries
-    # (16-byte multiples) with the continuum in the padding; only the 101 line
-    # wavelengths count as updates
+    # (16-byte multiples) with the continuum in the padding, a site's chi and S
+    # rows side by side (rows="paired"; "separate": two arrays); only the 101
+    # line wavelengths count as updates
     f32 = torch.float32
     ld = (nl + 3) // 4 * 4
     chi = torch.empty((U.n, ld), dtype=f32, device=dev)
@@ -981,13 +1003,20 @@ def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", int
     chi[:, nl:] = chi_c[:, None]
     S[:, nl:] = B[:, None]
     J = torch.empty_like(chi)
+    if rows == "paired":
+        cs = torch.empty((U.n, 2, ld), dtype=f32, device=dev)
+        cs[:, 0] = chi
+        cs[:, 1] = S
+        chi_t, S_t = cs[:, 0], cs[:, 1]
+    else:
+        chi_t, S_t = chi, S
     # launch modes: the autotuner (auto) times the graph of level steps under
     # its layouts and the persistent sweep, and keeps the fastest on the grid
     modes = {"graph": v.VRT_EXEC_GRAPH, "batched": v.VRT_EXEC_BATCHED, "persistent": v.VRT_EXEC_PERSISTENT}
     tuning = None
     if mode_pref == "auto":
         t1 = time.time()
-        tuning = v.autotune(G, chi, S, J, reps=3)
+        tuning = v.autotune(G, chi, S, J, reps=3)  # (on arrays of n x ld)
         log(f"{workload}: autotune in {time.time() - t1:.1f} s, chosen {tuning['chosen']}")
         mode_pref = tuning["chosen"]["exec"]
         layout = dict(tuning["chosen"])
@@ -997,6 +1026,7 @@ def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", int
         G.tune(v.VRT_TUNE_PIPELINE, pipeline)
         layout = {"record_order": 1, "shared_levels": shared_levels, "xcd_chunks": 8, "ray_affinity": 0,
                   "lane_bytes": 16, "interleave": interleave, "pipeline": pipeline}
+    layout["rows"] = rows
     fs_by_mode = {}
     if tuning:
         for c in tuning["candidates"]:
@@ -1005,13 +1035,13 @@ def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", int
     for name in (mode_pref,):
         try:
             for _ in range(2):
-                v.formal_solution(G, chi, S, J, exec_mode=modes[name])
+                v.formal_solution(G, chi_t, S_t, J, exec_mode=modes[name])
             torch.cuda.synchronize()
             k = 5
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
             for _ in range(k):
-                v.formal_solution(G, chi, S, J, exec_mode=modes[name])
+                v.formal_solution(G, chi_t, S_t, J, exec_mode=modes[name])
             e1.record(stream)
             e1.synchronize()
             G.device_status()
@@ -1023,7 +1053,7 @@ def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", int
     # the angle quadrature of J on its own (one eager launch, HIP events on the library stream)
     ctx.profile_reset()
     ctx.set_profiling(True)
-    v.formal_solution(G, chi, S, J, exec_mode=v.VRT_EXEC_BATCHED)
+    v.formal_solution(G, chi_t, S_t, J, exec_mode=v.VRT_EXEC_BATCHED)
     jr_ms, jr_launches, _ = ctx.profile(1)
     sw_ms_b, sw_launches, _ = ctx.profile(0)
     ctx.set_profiling(False)
@@ -1037,7 +1067,9 @@ def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", int
     sweep_bpu = sweep_bytes_per_update(nl, 4) * ld / nl  # the sweep moves ld-entry rows
     sweep_gbs = sweep_bpu * updates / (sweep_ms * 1e-3) / 1e9
     traffic = lambda_counter_traffic(workload, mode_name, layout)
-    del chi, S, J
+    del chi, S, J, chi_t, S_t
+    if rows == "paired":
+        del cs
     log(f"{workload}: formal solution (ms by launch mode): {fs_by_mode} -> {mode_name}: {fs_ms:.3f} ms, "
         f"{upd_s:.3e} updates/s; sweep {sweep_ms:.3f} ms ({sweep_gbs:.0f} GB/s own bytes), J {jr_one:.3f} ms")
 
@@ -1107,7 +1139,7 @@ def run_lambda(args):
                        accel_iter=0 if args.no_accel else (1000 if args.workload == "c2" else 200),
                        mode_pref="auto" if args.mode == "auto" else args.mode, interleave=args.interleave,
                        pipeline=args.pipeline, workers=args.workers, cache_dir=args.inputs_cache,
-                       shared_levels=args.shared_levels)
+                       shared_levels=args.shared_levels, rows=args.rows)
     line = {"metric": "site*ray*lambda updates/s of the formal solution inside the two-level Lambda iteration",
             "value": out["updates_per_s"], "unit": "site*ray*lambda updates/s", "n_gpus": 1,
             "higher_is_better": True, "dtype": "f32",

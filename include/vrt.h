@@ -332,6 +332,16 @@ vrt_status vrt_lte_continuum(vrt_grid grid, vrt_prec prec, int32_t n_lambda,
                              const double *lambda_m, double kappa0, const double *T,
                              const double *rho, void *chi, void *S);
 
+/* vrt_lte_continuum with rows ld_src apart: the chi and S rows of site i start
+ * at chi + i * ld_src and S + i * ld_src (elements; ld_src >= n_lambda, and
+ * ld_src = n_lambda is vrt_lte_continuum). With S = chi + n_lambda and
+ * ld_src = 2 * n_lambda each site's two rows sit side by side, the layout
+ * vrt_formal_solution_ld reads fastest. Entries between the rows are not
+ * written. Errors: VRT_E_ARG for ld_src < n_lambda and as vrt_lte_continuum. */
+vrt_status vrt_lte_continuum_ld(vrt_grid grid, vrt_prec prec, int32_t n_lambda, int64_t ld_src,
+                                const double *lambda_m, double kappa0, const double *T,
+                                const double *rho, void *chi, void *S);
+
 /* Formal solution for every ray and wavelength and the mean intensity
  * J = sum_r w_r I_r (Sect. 2.1, Eq. 2 and 4; Sect. 2.5, Eq. 5).
  *   chi, S     device [n][n_lambda] opacity (m^-1, >= 0) and source function.
@@ -348,6 +358,22 @@ vrt_status vrt_lte_continuum(vrt_grid grid, vrt_prec prec, int32_t n_lambda,
 vrt_status vrt_formal_solution(vrt_grid grid, vrt_prec prec, vrt_exec exec, int32_t n_lambda,
                                const void *chi, const void *S, const void *I_bottom,
                                const void *I_top, void *J, void *I_rays);
+
+/* vrt_formal_solution (Sect. 2.1, Eq. 2 and 4; Sect. 2.5, Eq. 5) with input
+ * rows ld_src elements apart: the rows of site i of chi, S, I_bottom and I_top
+ * start at i * ld_src (ld_src >= n_lambda; ld_src = n_lambda is
+ * vrt_formal_solution). J and I_rays keep rows of n_lambda entries. The
+ * intended use pairs a site's opacity and source rows, S = chi + n_lambda and
+ * ld_src = 2 * n_lambda (one [n][2][n_lambda] array): a sweep reads chi and S
+ * of every upwind site together, and paired rows make that one contiguous
+ * span; the two-level iteration stores its rows this way. The results are
+ * those of vrt_formal_solution on the same values bit for bit. With I_bottom
+ * NULL the bottom boundary reads S at the same stride. Errors: VRT_E_ARG for
+ * ld_src < n_lambda, for ld_src != n_lambda on a regular grid (its plane
+ * kernels read rows of n_lambda entries), and as vrt_formal_solution. */
+vrt_status vrt_formal_solution_ld(vrt_grid grid, vrt_prec prec, vrt_exec exec, int32_t n_lambda,
+                                  int64_t ld_src, const void *chi, const void *S,
+                                  const void *I_bottom, const void *I_top, void *J, void *I_rays);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same

@@ -158,9 +158,10 @@ template <typename T, int V, bool BIG> struct CoherentRows {
 
 // The quadratic-segment update of one record (site of one ray) for the
 // wavelengths l0, l0 + kLanes V, ...; rows: the record's ray's intensities.
+// The input rows of site i (chi, S, boundary intensities) start at i cs (cs >= nl).
 template <typename T, int V, typename Rows>
 __device__ __forceinline__ void bezier_record(const int4 q, const typename vrt::RecOf<T>::type *__restrict__ rf,
-                                              int64_t rec, int l0, int32_t nl, int64_t n,
+                                              int64_t rec, int l0, int32_t nl, int64_t cs, int64_t n,
                                               const int32_t *__restrict__ q1, const int32_t *__restrict__ q2,
                                               const double *__restrict__ qw1, const double *__restrict__ qd1,
                                               const double *__restrict__ qd2, const T *__restrict__ chi,
@@ -170,12 +171,12 @@ __device__ __forceinline__ void bezier_record(const int4 q, const typename vrt::
   using VT = typename L::type;
   const int32_t site = q.x, k1 = q.y, k2 = q.z, ray = q.w >> 1;
   const bool up = (q.w & 1) != 0;
-  const int64_t bi = (int64_t)site * nl;
+  const int64_t bi = (int64_t)site * nl, ei = (int64_t)site * cs;
   if (k1 < 0) {
     for (int l = l0; l < nl; l += kLanes * V) {
       VT v;
-      if (up) v = L::load(Ibot + bi + l);
-      else if (Itop) v = L::load(Itop + bi + l);
+      if (up) v = L::load(Ibot + ei + l);
+      else if (Itop) v = L::load(Itop + ei + l);
       else v = VT(T(0));
       rows.store(bi + l, v);
     }
@@ -191,23 +192,24 @@ __device__ __forceinline__ void bezier_record(const int4 q, const typename vrt::
   const T qa = two_d ? (T)qw1[rs] : T(1);
   const T g1 = T(0.5) * (T)qd1[rs], g2 = T(0.5) * (T)qd2[rs];
   const int64_t bk1 = (int64_t)k1 * nl, bk2 = (int64_t)(two ? k2 : k1) * nl;
-  const int64_t bd1 = (int64_t)(d1 >= 0 ? d1 : site) * nl, bd2 = (int64_t)(two_d ? d2 : site) * nl;
+  const int64_t ek1 = (int64_t)k1 * cs, ek2 = (int64_t)(two ? k2 : k1) * cs;
+  const int64_t ed1 = (int64_t)(d1 >= 0 ? d1 : site) * cs, ed2 = (int64_t)(two_d ? d2 : site) * cs;
   for (int l = l0; l < nl; l += kLanes * V) {
-    const VT ci = L::load(chi + bi + l), si = L::load(S + bi + l);
-    const VT ck1 = L::load(chi + bk1 + l), sk1 = L::load(S + bk1 + l), ik1 = rows.load(bk1 + l);
+    const VT ci = L::load(chi + ei + l), si = L::load(S + ei + l);
+    const VT ck1 = L::load(chi + ek1 + l), sk1 = L::load(S + ek1 + l), ik1 = rows.load(bk1 + l);
     VT ck2 = ck1, sk2 = sk1, ik2 = ik1;
     if (two) {
-      ck2 = L::load(chi + bk2 + l);
-      sk2 = L::load(S + bk2 + l);
+      ck2 = L::load(chi + ek2 + l);
+      sk2 = L::load(S + ek2 + l);
       ik2 = rows.load(bk2 + l);
     }
     VT cq1 = ci, sq1 = si, cq2 = ci, sq2 = si;
     if (d1 >= 0) {
-      cq1 = L::load(chi + bd1 + l);
-      sq1 = L::load(S + bd1 + l);
+      cq1 = L::load(chi + ed1 + l);
+      sq1 = L::load(S + ed1 + l);
       if (two_d) {
-        cq2 = L::load(chi + bd2 + l);
-        sq2 = L::load(S + bd2 + l);
+        cq2 = L::load(chi + ed2 + l);
+        sq2 = L::load(S + ed2 + l);
       }
     }
     VT out;
@@ -258,10 +260,10 @@ __device__ __forceinline__ void bezier_record(const int4 q, const typename vrt::
 template <typename T, int V>
 __global__ __launch_bounds__(256) void bezier_sweep_kernel(
     const int4 *__restrict__ ri, const typename vrt::RecOf<T>::type *__restrict__ rf, int64_t rec_begin,
-    int64_t rec_count, int32_t nl, int64_t n, const int32_t *__restrict__ q1, const int32_t *__restrict__ q2,
-    const double *__restrict__ qw1, const double *__restrict__ qd1, const double *__restrict__ qd2,
-    const T *__restrict__ chi, const T *__restrict__ S, const T *__restrict__ Ibot, const T *__restrict__ Itop,
-    T *I, int32_t xcd_chunks) {
+    int64_t rec_count, int32_t nl, int64_t cs, int64_t n, const int32_t *__restrict__ q1,
+    const int32_t *__restrict__ q2, const double *__restrict__ qw1, const double *__restrict__ qd1,
+    const double *__restrict__ qd2, const T *__restrict__ chi, const T *__restrict__ S, const T *__restrict__ Ibot,
+    const T *__restrict__ Itop, T *I, int32_t xcd_chunks) {
   const int64_t t = die_chunked_block(xcd_chunks) * blockDim.x + threadIdx.x;
   const int64_t r = t / kLanes;
   if (r >= rec_count) return;
@@ -269,7 +271,7 @@ __global__ __launch_bounds__(256) void bezier_sweep_kernel(
   const int64_t rec = rec_begin + r;
   const int4 q = ri[rec];
   const PlainRows<T, V> rows{I + (int64_t)(q.w >> 1) * n * nl};
-  bezier_record<T, V>(q, rf, rec, l0, nl, n, q1, q2, qw1, qd1, qd2, chi, S, Ibot, Itop, rows);
+  bezier_record<T, V>(q, rf, rec, l0, nl, cs, n, q1, q2, qw1, qd1, qd2, chi, S, Ibot, Itop, rows);
 }
 
 // Persistent quadratic-segment sweep: every ray and level in one launch, with
@@ -281,7 +283,7 @@ template <typename T, int V, bool BIG>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void persistent_bezier_kernel(
     const int4 *__restrict__ ri, const typename vrt::RecOf<T>::type *__restrict__ rf,
     const int64_t *__restrict__ item_rec, const int32_t *__restrict__ item_cnt, int64_t n_items, int32_t nl,
-    int64_t n, const int32_t *__restrict__ q1, const int32_t *__restrict__ q2, const double *__restrict__ qw1,
+    int64_t cs, int64_t n, const int32_t *__restrict__ q1, const int32_t *__restrict__ q2, const double *__restrict__ qw1,
     const double *__restrict__ qd1, const double *__restrict__ qd2, const T *__restrict__ chi,
     const T *__restrict__ S, const T *__restrict__ Ibot, const T *__restrict__ Itop, T *I, int64_t flag_ld,
     int32_t *flags, int32_t *words, int64_t spin_cap) {
@@ -310,7 +312,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void pers
       // the item's ray's block of n * nl values (BIG: 4 GiB or more)
       const CoherentRows<T, V, BIG> rows{
           vrt_persist::RayBlock<BIG>(I + (int64_t)(cr >> 8) * n * nl, n * nl * (int64_t)sizeof(T))};
-      bezier_record<T, V>(q, rf, rec, l0, nl, n, q1, q2, qw1, qd1, qd2, chi, S, Ibot, Itop, rows);
+      bezier_record<T, V>(q, rf, rec, l0, nl, cs, n, q1, q2, qw1, qd1, qd2, chi, S, Ibot, Itop, rows);
     }
     // every row store of the wave has completed before any of its stamps
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -327,19 +329,19 @@ namespace vrt {
 
 template <typename T>
 void launch_bezier_sweep(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *rf, int64_t rec_begin,
-                         int64_t rec_count, int32_t nl, int64_t n, const int32_t *q1, const int32_t *q2,
-                         const double *qw1, const double *qd1, const double *qd2, const T *chi, const T *S,
-                         const T *Ibot, const T *Itop, T *I, int32_t xcd_chunks) {
+                         int64_t rec_count, int32_t nl, int64_t cs, int64_t n, const int32_t *q1,
+                         const int32_t *q2, const double *qw1, const double *qd1, const double *qd2, const T *chi,
+                         const T *S, const T *Ibot, const T *Itop, T *I, int32_t xcd_chunks) {
   if (rec_count <= 0) return;
   const unsigned blocks = (unsigned)((rec_count * kLanes + 255) / 256);
   constexpr int V = 16 / (int)sizeof(T);
   auto al = [](const void *p) { return p == nullptr || (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
-  if (nl % V == 0 && al(chi) && al(S) && al(Ibot) && al(Itop) && al(I))
-    bezier_sweep_kernel<T, V><<<blocks, 256, 0, s>>>(ri, rf, rec_begin, rec_count, nl, n, q1, q2, qw1, qd1, qd2, chi,
-                                                     S, Ibot, Itop, I, xcd_chunks);
+  if (nl % V == 0 && cs % V == 0 && al(chi) && al(S) && al(Ibot) && al(Itop) && al(I))
+    bezier_sweep_kernel<T, V><<<blocks, 256, 0, s>>>(ri, rf, rec_begin, rec_count, nl, cs, n, q1, q2, qw1, qd1, qd2,
+                                                     chi, S, Ibot, Itop, I, xcd_chunks);
   else
-    bezier_sweep_kernel<T, 1><<<blocks, 256, 0, s>>>(ri, rf, rec_begin, rec_count, nl, n, q1, q2, qw1, qd1, qd2, chi,
-                                                     S, Ibot, Itop, I, xcd_chunks);
+    bezier_sweep_kernel<T, 1><<<blocks, 256, 0, s>>>(ri, rf, rec_begin, rec_count, nl, cs, n, q1, q2, qw1, qd1, qd2,
+                                                     chi, S, Ibot, Itop, I, xcd_chunks);
   VRT_HIP(hipGetLastError());
 }
 
@@ -347,15 +349,15 @@ int32_t bezier_records_per_wave() { return 64 / kLanes; }
 
 template <typename T>
 void launch_persistent_bezier(hipStream_t s, const PersistItems &items, int32_t max_blocks, const int4 *ri,
-                              const typename RecOf<T>::type *rf, int32_t nl, int64_t n, const int32_t *q1,
-                              const int32_t *q2, const double *qw1, const double *qd1, const double *qd2,
-                              const T *chi, const T *S, const T *Ibot, const T *Itop, T *I, int64_t flag_ld,
-                              int32_t *flags, int32_t *words, int64_t spin_cap) {
+                              const typename RecOf<T>::type *rf, int32_t nl, int64_t cs, int64_t n,
+                              const int32_t *q1, const int32_t *q2, const double *qw1, const double *qd1,
+                              const double *qd2, const T *chi, const T *S, const T *Ibot, const T *Itop, T *I,
+                              int64_t flag_ld, int32_t *flags, int32_t *words, int64_t spin_cap) {
   if (items.n_items <= 0) return;
   if (items.spw != 64 / kLanes) throw Error(VRT_E_STATE, "persistent item table built for another record width");
   constexpr int VW = 16 / (int)sizeof(T);
   auto al = [](const void *p) { return p == nullptr || (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
-  const bool vec = nl % VW == 0 && al(chi) && al(S) && al(Ibot) && al(Itop) && al(I);
+  const bool vec = nl % VW == 0 && cs % VW == 0 && al(chi) && al(S) && al(Ibot) && al(Itop) && al(I);
   auto launch = [&](auto kern) {
     int dev = 0, cus = 0, per_cu = 0;
     VRT_HIP(hipGetDevice(&dev));
@@ -368,8 +370,8 @@ void launch_persistent_bezier(hipStream_t s, const PersistItems &items, int32_t 
     if (max_blocks > 0) blocks = max_blocks;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, s, ri, rf, items.rec.as<int64_t>(),
-                       items.cnt.as<int32_t>(), items.n_items, nl, n, q1, q2, qw1, qd1, qd2, chi, S, Ibot, Itop, I,
-                       flag_ld, flags, words, spin_cap);
+                       items.cnt.as<int32_t>(), items.n_items, nl, cs, n, q1, q2, qw1, qd1, qd2, chi, S, Ibot, Itop,
+                       I, flag_ld, flags, words, spin_cap);
     VRT_HIP(hipGetLastError());
   };
   const bool big = n * (int64_t)nl * (int64_t)sizeof(T) >= (int64_t(1) << 32);
@@ -378,22 +380,22 @@ void launch_persistent_bezier(hipStream_t s, const PersistItems &items, int32_t 
 }
 
 template void launch_persistent_bezier<float>(hipStream_t, const PersistItems &, int32_t, const int4 *,
-                                              const RecF32 *, int32_t, int64_t, const int32_t *, const int32_t *,
+                                              const RecF32 *, int32_t, int64_t, int64_t, const int32_t *, const int32_t *,
                                               const double *, const double *, const double *, const float *,
                                               const float *, const float *, const float *, float *, int64_t,
                                               int32_t *, int32_t *, int64_t);
 template void launch_persistent_bezier<double>(hipStream_t, const PersistItems &, int32_t, const int4 *,
-                                               const RecF64 *, int32_t, int64_t, const int32_t *, const int32_t *,
+                                               const RecF64 *, int32_t, int64_t, int64_t, const int32_t *, const int32_t *,
                                                const double *, const double *, const double *, const double *,
                                                const double *, const double *, const double *, double *, int64_t,
                                                int32_t *, int32_t *, int64_t);
 
 template void launch_bezier_sweep<float>(hipStream_t, const int4 *, const RecF32 *, int64_t, int64_t, int32_t,
-                                         int64_t, const int32_t *, const int32_t *, const double *, const double *,
+                                         int64_t, int64_t, const int32_t *, const int32_t *, const double *, const double *,
                                          const double *, const float *, const float *, const float *, const float *,
                                          float *, int32_t);
 template void launch_bezier_sweep<double>(hipStream_t, const int4 *, const RecF64 *, int64_t, int64_t, int32_t,
-                                          int64_t, const int32_t *, const int32_t *, const double *, const double *,
+                                          int64_t, int64_t, const int32_t *, const int32_t *, const double *, const double *,
                                           const double *, const double *, const double *, const double *,
                                           const double *, double *, int32_t);
 

@@ -17,10 +17,11 @@
 
 namespace {
 
-// Rows of chi and S have ld >= nl entries; the ld - nl padding entries take
-// the continuum alone (finite values the sweep may carry but nothing reads).
+// Rows of chi and S have ld >= nl entries and start cs >= ld apart (the
+// iteration pairs them: S = chi + ld, cs = 2 ld); the ld - nl padding entries
+// take the continuum alone (finite values the sweep may carry but nothing reads).
 template <typename T>
-__global__ __launch_bounds__(256) void nlte_assemble_kernel(int64_t n, int32_t nl, int32_t ld,
+__global__ __launch_bounds__(256) void nlte_assemble_kernel(int64_t n, int32_t nl, int32_t ld, int64_t cs,
                                                             const double *__restrict__ phi,
                                                             const double *__restrict__ chi_L,
                                                             const double *__restrict__ chi_c,
@@ -31,22 +32,26 @@ __global__ __launch_bounds__(256) void nlte_assemble_kernel(int64_t n, int32_t n
   if (t >= n * ld) return;
   const int64_t i = t / ld;
   const int32_t l = (int32_t)(t - i * ld);
+  const int64_t o = i * cs + l;
   if (l >= nl) {
-    chi[t] = (T)chi_c[i];
-    S[t] = (T)B[i];
+    chi[o] = (T)chi_c[i];
+    S[o] = (T)B[i];
     return;
   }
   const double lo = chi_L[i] * phi[i * nl + l];
   const double c = chi_c[i] + lo;
-  chi[t] = (T)c;
-  S[t] = (T)((lo * S_L[i] + chi_c[i] * B[i]) / c);
+  chi[o] = (T)c;
+  S[o] = (T)((lo * S_L[i] + chi_c[i] * B[i]) / c);
 }
 
+// out[i cs + l] = v[i] for l < ld
 template <typename T>
-__global__ void broadcast_kernel(int64_t n, int32_t ld, const double *__restrict__ v, T *__restrict__ out) {
+__global__ void broadcast_kernel(int64_t n, int32_t ld, int64_t cs, const double *__restrict__ v,
+                                 T *__restrict__ out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n * ld) return;
-  out[t] = (T)v[t / ld];
+  const int64_t i = t / ld;
+  out[i * cs + (t - i * ld)] = (T)v[i];
 }
 
 __global__ void zero_u64_array_kernel(int32_t count, unsigned long long *p) {
@@ -245,17 +250,19 @@ inline unsigned nb(int64_t work, int bs) { return vrt::grid_blocks(work, bs); }
 namespace vrt {
 
 template <typename T>
-void launch_nlte_assemble(hipStream_t s, int64_t n, int32_t nl, int32_t ld, const double *phi, const double *chi_L,
-                          const double *chi_c, const double *B, const double *S_L, T *chi, T *S) {
+void launch_nlte_assemble(hipStream_t s, int64_t n, int32_t nl, int32_t ld, int64_t cs, const double *phi,
+                          const double *chi_L, const double *chi_c, const double *B, const double *S_L, T *chi,
+                          T *S) {
   if (n * ld == 0) return;
-  hipLaunchKernelGGL(nlte_assemble_kernel<T>, dim3(nb(n * ld, 256)), dim3(256), 0, s, n, nl, ld, phi, chi_L, chi_c,
-                     B, S_L, chi, S);
+  hipLaunchKernelGGL(nlte_assemble_kernel<T>, dim3(nb(n * ld, 256)), dim3(256), 0, s, n, nl, ld, cs, phi, chi_L,
+                     chi_c, B, S_L, chi, S);
   VRT_HIP(hipGetLastError());
 }
 
-template <typename T> void launch_broadcast(hipStream_t s, int64_t n, int32_t ld, const double *v, T *out) {
+template <typename T>
+void launch_broadcast(hipStream_t s, int64_t n, int32_t ld, int64_t cs, const double *v, T *out) {
   if (n * ld == 0) return;
-  hipLaunchKernelGGL(broadcast_kernel<T>, dim3(nb(n * ld, 256)), dim3(256), 0, s, n, ld, v, out);
+  hipLaunchKernelGGL(broadcast_kernel<T>, dim3(nb(n * ld, 256)), dim3(256), 0, s, n, ld, cs, v, out);
   VRT_HIP(hipGetLastError());
 }
 
@@ -298,12 +305,14 @@ void launch_line_diag(hipStream_t s, int64_t n, int32_t nl, int32_t R, const dou
   VRT_HIP(hipGetLastError());
 }
 
-template void launch_nlte_assemble<float>(hipStream_t, int64_t, int32_t, int32_t, const double *, const double *,
-                                          const double *, const double *, const double *, float *, float *);
-template void launch_nlte_assemble<double>(hipStream_t, int64_t, int32_t, int32_t, const double *, const double *,
-                                           const double *, const double *, const double *, double *, double *);
-template void launch_broadcast<float>(hipStream_t, int64_t, int32_t, const double *, float *);
-template void launch_broadcast<double>(hipStream_t, int64_t, int32_t, const double *, double *);
+template void launch_nlte_assemble<float>(hipStream_t, int64_t, int32_t, int32_t, int64_t, const double *,
+                                          const double *, const double *, const double *, const double *, float *,
+                                          float *);
+template void launch_nlte_assemble<double>(hipStream_t, int64_t, int32_t, int32_t, int64_t, const double *,
+                                           const double *, const double *, const double *, const double *, double *,
+                                           double *);
+template void launch_broadcast<float>(hipStream_t, int64_t, int32_t, int64_t, const double *, float *);
+template void launch_broadcast<double>(hipStream_t, int64_t, int32_t, int64_t, const double *, double *);
 template void launch_line_update<float>(hipStream_t, int64_t, int32_t, int32_t, int32_t, const float *,
                                         const double *, const double *, const double *, const double *, double,
                                         double *, int32_t, const int64_t *, const int32_t *, unsigned long long *,

@@ -151,8 +151,9 @@ template <typename T, int C, int V, bool SIGN, bool BIG>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void persistent_sweep_kernel(
     const int4 *__restrict__ ri, const typename vrt::RecOf<T>::type *__restrict__ rf,
     const int64_t *__restrict__ item_rec, const int32_t *__restrict__ item_cnt, int64_t n_items, int32_t nl,
-    int64_t n, int64_t flag_ld, const T *__restrict__ chi, const T *__restrict__ S, const T *__restrict__ Ibot,
-    const T *__restrict__ Itop, T *I, int32_t *flags, int32_t *words, int64_t spin_cap, int64_t mixed_bytes) {
+    int64_t cs, int64_t n, int64_t flag_ld, const T *__restrict__ chi, const T *__restrict__ S,
+    const T *__restrict__ Ibot, const T *__restrict__ Itop, T *I, int32_t *flags, int32_t *words, int64_t spin_cap,
+    int64_t mixed_bytes) {
   using L = PLane<T, V>;
   using VT = typename L::type;
   const int32_t epoch = SIGN ? words[5] : words[0];
@@ -190,12 +191,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void pers
       const RayBlock<BIG> Iray(mixed ? I : I + (int64_t)(cr >> 8) * n * nl,
                                mixed ? mixed_bytes : n * nl * (int64_t)sizeof(T));
       const int64_t rb = mixed ? (int64_t)ray * n * nl : 0;
-      const int64_t bi = (int64_t)site * nl;
+      // input rows (chi, S, boundary intensities) of site i at i cs (cs >= nl)
+      const int64_t bi = (int64_t)site * nl, ei = (int64_t)site * cs;
       if (k1 < 0) {
         for (int l = l0; l < nl; l += C * V) {
           VT v;
-          if (up) v = L::load(Ibot + bi + l);
-          else if (Itop) v = L::load(Itop + bi + l);
+          if (up) v = L::load(Ibot + ei + l);
+          else if (Itop) v = L::load(Itop + ei + l);
           else v = VT(T(0));
           put_row<T, VT, L, V, SIGN>(Iray, (rb + bi + l) * (int64_t)sizeof(T), v, neg, err);
         }
@@ -206,14 +208,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void pers
         const bool two = k2 >= 0;
         const int64_t b1 = (int64_t)k1 * nl;
         const int64_t b2 = (int64_t)(two ? k2 : k1) * nl;
+        const int64_t e1 = (int64_t)k1 * cs, e2 = (int64_t)(two ? k2 : k1) * cs;
         for (int l = l0; l < nl; l += C * V) {
-          const VT ci = L::load(chi + bi + l), si = L::load(S + bi + l);
-          const VT c1 = L::load(chi + b1 + l), s1 = L::load(S + b1 + l);
+          const VT ci = L::load(chi + ei + l), si = L::load(S + ei + l);
+          const VT c1 = L::load(chi + e1 + l), s1 = L::load(S + e1 + l);
           const VT u1 = get_row<T, VT, L, V, SIGN>(Iray, (rb + b1 + l) * (int64_t)sizeof(T), neg, err, spin_cap);
           VT c2, s2, u2;
           if (two) {
-            c2 = L::load(chi + b2 + l);
-            s2 = L::load(S + b2 + l);
+            c2 = L::load(chi + e2 + l);
+            s2 = L::load(S + e2 + l);
             u2 = get_row<T, VT, L, V, SIGN>(Iray, (rb + b2 + l) * (int64_t)sizeof(T), neg, err, spin_cap);
           }
           VT out;
@@ -243,9 +246,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_num_sgpr(80))) void pers
 
 template <typename T, int C, int V>
 void launch_pc(hipStream_t s, const vrt::PersistItems &it, int32_t max_blocks, const int4 *ri,
-               const typename vrt::RecOf<T>::type *rf, int32_t nl, int64_t n, int64_t flag_ld, const T *chi,
-               const T *S, const T *Ibot, const T *Itop, T *I, int32_t *flags, int32_t *words, int64_t cap,
-               bool sign, int64_t mixed_bytes) {
+               const typename vrt::RecOf<T>::type *rf, int32_t nl, int64_t cs, int64_t n, int64_t flag_ld,
+               const T *chi, const T *S, const T *Ibot, const T *Itop, T *I, int32_t *flags, int32_t *words,
+               int64_t cap, bool sign, int64_t mixed_bytes) {
   if (it.spw != 64 / C) throw vrt::Error(VRT_E_STATE, "persistent item table built for another record width");
   const int64_t block = mixed_bytes > 0 ? mixed_bytes : n * (int64_t)nl * (int64_t)sizeof(T);
   const bool big = block >= (int64_t(1) << 32);
@@ -266,24 +269,24 @@ void launch_pc(hipStream_t s, const vrt::PersistItems &it, int32_t max_blocks, c
   const int64_t *item_rec = it.rec.as<int64_t>();
   const int32_t *item_cnt = it.cnt.as<int32_t>();
   const int64_t n_items = it.n_items;
-  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, s, ri, rf, item_rec, item_cnt, n_items, nl, n,
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), 0, s, ri, rf, item_rec, item_cnt, n_items, nl, cs, n,
                      flag_ld, chi, S, Ibot, Itop, I, flags, words, cap, mixed_bytes);
   VRT_HIP(hipGetLastError());
 }
 
 template <typename T, int V>
 void launch_pv(hipStream_t s, const vrt::PersistItems &it, int32_t mb, const int4 *ri,
-               const typename vrt::RecOf<T>::type *rf, int32_t nl, int64_t n, int64_t fl, const T *chi, const T *S,
-               const T *Ibot, const T *Itop, T *I, int32_t *flags, int32_t *words, int64_t cap, bool sg,
+               const typename vrt::RecOf<T>::type *rf, int32_t nl, int64_t cs, int64_t n, int64_t fl, const T *chi,
+               const T *S, const T *Ibot, const T *Itop, T *I, int32_t *flags, int32_t *words, int64_t cap, bool sg,
                int64_t mx) {
   switch (vrt::lanes_per_record(nl / V)) {
-    case 64: launch_pc<T, 64, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg, mx); break;
-    case 32: launch_pc<T, 32, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg, mx); break;
-    case 16: launch_pc<T, 16, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg, mx); break;
-    case 8: launch_pc<T, 8, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg, mx); break;
-    case 4: launch_pc<T, 4, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg, mx); break;
-    case 2: launch_pc<T, 2, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg, mx); break;
-    default: launch_pc<T, 1, V>(s, it, mb, ri, rf, nl, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg, mx); break;
+    case 64: launch_pc<T, 64, V>(s, it, mb, ri, rf, nl, cs, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg, mx); break;
+    case 32: launch_pc<T, 32, V>(s, it, mb, ri, rf, nl, cs, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg, mx); break;
+    case 16: launch_pc<T, 16, V>(s, it, mb, ri, rf, nl, cs, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg, mx); break;
+    case 8: launch_pc<T, 8, V>(s, it, mb, ri, rf, nl, cs, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg, mx); break;
+    case 4: launch_pc<T, 4, V>(s, it, mb, ri, rf, nl, cs, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg, mx); break;
+    case 2: launch_pc<T, 2, V>(s, it, mb, ri, rf, nl, cs, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg, mx); break;
+    default: launch_pc<T, 1, V>(s, it, mb, ri, rf, nl, cs, n, fl, chi, S, Ibot, Itop, I, flags, words, cap, sg, mx); break;
   }
 }
 
@@ -308,34 +311,35 @@ template <typename T> void launch_sign_fill(hipStream_t s, T *p, int64_t count, 
 template void launch_sign_fill<float>(hipStream_t, float *, int64_t, const int32_t *);
 template void launch_sign_fill<double>(hipStream_t, double *, int64_t, const int32_t *);
 
-int32_t persistent_records_per_wave(int32_t nl, int elem_bytes, bool aligned) {
+int32_t persistent_records_per_wave(int32_t nl, int elem_bytes, bool aligned, int64_t cs) {
   const int VW = 16 / elem_bytes;
-  const int V = (aligned && nl % VW == 0) ? VW : 1;
+  const int V = (aligned && nl % VW == 0 && cs % VW == 0) ? VW : 1;
   return 64 / lanes_per_record(nl / V);
 }
 
 template <typename T>
 void launch_persistent_sweep(hipStream_t s, const PersistItems &items, int32_t max_blocks, const int4 *ri,
-                             const typename RecOf<T>::type *rf, int32_t nl, int64_t n, int64_t flag_ld, const T *chi,
-                             const T *S, const T *Ibot, const T *Itop, T *I, int32_t *flags, int32_t *words,
-                             int64_t spin_cap, bool sign, int32_t mixed_rays) {
+                             const typename RecOf<T>::type *rf, int32_t nl, int64_t cs, int64_t n, int64_t flag_ld,
+                             const T *chi, const T *S, const T *Ibot, const T *Itop, T *I, int32_t *flags,
+                             int32_t *words, int64_t spin_cap, bool sign, int32_t mixed_rays) {
   if (items.n_items <= 0) return;
   const int64_t mixed_bytes = mixed_rays > 0 ? (int64_t)mixed_rays * n * (int64_t)nl * (int64_t)sizeof(T) : 0;
   constexpr int VW = 16 / sizeof(T);
   const bool aligned = al16(chi) && al16(S) && al16(Ibot) && al16(Itop) && al16(I);
-  if (aligned && nl % VW == 0)
-    launch_pv<T, VW>(s, items, max_blocks, ri, rf, nl, n, flag_ld, chi, S, Ibot, Itop, I, flags, words, spin_cap,
+  if (aligned && nl % VW == 0 && cs % VW == 0)
+    launch_pv<T, VW>(s, items, max_blocks, ri, rf, nl, cs, n, flag_ld, chi, S, Ibot, Itop, I, flags, words, spin_cap,
                      sign, mixed_bytes);
   else
-    launch_pv<T, 1>(s, items, max_blocks, ri, rf, nl, n, flag_ld, chi, S, Ibot, Itop, I, flags, words, spin_cap,
+    launch_pv<T, 1>(s, items, max_blocks, ri, rf, nl, cs, n, flag_ld, chi, S, Ibot, Itop, I, flags, words, spin_cap,
                     sign, mixed_bytes);
 }
 
 template void launch_persistent_sweep<float>(hipStream_t, const PersistItems &, int32_t, const int4 *, const RecF32 *,
-                                             int32_t, int64_t, int64_t, const float *, const float *, const float *,
-                                             const float *, float *, int32_t *, int32_t *, int64_t, bool, int32_t);
+                                             int32_t, int64_t, int64_t, int64_t, const float *, const float *,
+                                             const float *, const float *, float *, int32_t *, int32_t *, int64_t,
+                                             bool, int32_t);
 template void launch_persistent_sweep<double>(hipStream_t, const PersistItems &, int32_t, const int4 *,
-                                              const RecF64 *, int32_t, int64_t, int64_t, const double *,
+                                              const RecF64 *, int32_t, int64_t, int64_t, int64_t, const double *,
                                               const double *, const double *, const double *, double *, int32_t *,
                                               int32_t *, int64_t, bool, int32_t);
 

@@ -33,11 +33,13 @@ template <typename T> struct SVec<T, 1> {
 // C lanes per site (a power of two), 64/C sites per wavefront, V consecutive
 // wavelengths per lane (nl a multiple of V): the site's temperature, density
 // and opacity are loaded once per lane group, each lane evaluates the Planck
-// function at its V wavelengths, and a wavefront writes whole rows.
+// function at its V wavelengths, and a wavefront writes whole rows. Rows of
+// site i start at i cs (cs >= nl, a multiple of V).
 template <typename T, int C, int V>
-__global__ __launch_bounds__(256) void lte_kernel(int64_t n, int32_t nl, const double *__restrict__ lam, double kappa0,
-                                                  const double *__restrict__ Tk, const double *__restrict__ rho,
-                                                  T *__restrict__ chi, T *__restrict__ S) {
+__global__ __launch_bounds__(256) void lte_kernel(int64_t n, int32_t nl, int64_t cs, const double *__restrict__ lam,
+                                                  double kappa0, const double *__restrict__ Tk,
+                                                  const double *__restrict__ rho, T *__restrict__ chi,
+                                                  T *__restrict__ S) {
   using VT = typename SVec<T, V>::type;
   constexpr int SPW = 64 / C;
   const int lane = threadIdx.x & 63;
@@ -46,7 +48,7 @@ __global__ __launch_bounds__(256) void lte_kernel(int64_t n, int32_t nl, const d
   const double Ti = Tk[i], ri = rho[i];
   const double T3 = Ti * Ti * Ti;
   const T c = (T)(kappa0 * (ri * ri) * (T3 * T3 * T3));
-  T *crow = chi + i * nl, *srow = S + i * nl;
+  T *crow = chi + i * cs, *srow = S + i * cs;
   for (int32_t l = (lane % C) * V; l < nl; l += C * V) {
     VT cv, sv;
     if constexpr (V == 1) {
@@ -65,25 +67,25 @@ __global__ __launch_bounds__(256) void lte_kernel(int64_t n, int32_t nl, const d
 }
 
 template <typename T, int C, int V>
-void launch_lc(hipStream_t s, int64_t n, int32_t nl, const double *lam, double kappa0, const double *T_,
+void launch_lc(hipStream_t s, int64_t n, int32_t nl, int64_t cs, const double *lam, double kappa0, const double *T_,
                const double *rho, T *chi, T *S) {
   constexpr int SPW = 64 / C;
   const int64_t blocks = (n + 4 * SPW - 1) / (4 * SPW);
-  hipLaunchKernelGGL((lte_kernel<T, C, V>), dim3((unsigned)blocks), dim3(256), 0, s, n, nl, lam, kappa0, T_, rho, chi,
-                     S);
+  hipLaunchKernelGGL((lte_kernel<T, C, V>), dim3((unsigned)blocks), dim3(256), 0, s, n, nl, cs, lam, kappa0, T_, rho,
+                     chi, S);
 }
 
 template <typename T, int V>
-void launch_lv(hipStream_t s, int64_t n, int32_t nl, const double *lam, double kappa0, const double *T_,
+void launch_lv(hipStream_t s, int64_t n, int32_t nl, int64_t cs, const double *lam, double kappa0, const double *T_,
                const double *rho, T *chi, T *S) {
   switch (vrt::lanes_per_record(nl / V)) {
-    case 64: launch_lc<T, 64, V>(s, n, nl, lam, kappa0, T_, rho, chi, S); break;
-    case 32: launch_lc<T, 32, V>(s, n, nl, lam, kappa0, T_, rho, chi, S); break;
-    case 16: launch_lc<T, 16, V>(s, n, nl, lam, kappa0, T_, rho, chi, S); break;
-    case 8: launch_lc<T, 8, V>(s, n, nl, lam, kappa0, T_, rho, chi, S); break;
-    case 4: launch_lc<T, 4, V>(s, n, nl, lam, kappa0, T_, rho, chi, S); break;
-    case 2: launch_lc<T, 2, V>(s, n, nl, lam, kappa0, T_, rho, chi, S); break;
-    default: launch_lc<T, 1, V>(s, n, nl, lam, kappa0, T_, rho, chi, S); break;
+    case 64: launch_lc<T, 64, V>(s, n, nl, cs, lam, kappa0, T_, rho, chi, S); break;
+    case 32: launch_lc<T, 32, V>(s, n, nl, cs, lam, kappa0, T_, rho, chi, S); break;
+    case 16: launch_lc<T, 16, V>(s, n, nl, cs, lam, kappa0, T_, rho, chi, S); break;
+    case 8: launch_lc<T, 8, V>(s, n, nl, cs, lam, kappa0, T_, rho, chi, S); break;
+    case 4: launch_lc<T, 4, V>(s, n, nl, cs, lam, kappa0, T_, rho, chi, S); break;
+    case 2: launch_lc<T, 2, V>(s, n, nl, cs, lam, kappa0, T_, rho, chi, S); break;
+    default: launch_lc<T, 1, V>(s, n, nl, cs, lam, kappa0, T_, rho, chi, S); break;
   }
 }
 
@@ -94,20 +96,20 @@ inline bool al16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) 
 namespace vrt {
 
 template <typename T>
-void launch_lte(hipStream_t s, int64_t n, int32_t nl, const double *lam, double kappa0, const double *T_,
+void launch_lte(hipStream_t s, int64_t n, int32_t nl, int64_t cs, const double *lam, double kappa0, const double *T_,
                 const double *rho, T *chi, T *S) {
   if (n == 0 || nl == 0) return;
   constexpr int VW = 16 / sizeof(T);
-  if (nl % VW == 0 && al16(chi) && al16(S))
-    launch_lv<T, VW>(s, n, nl, lam, kappa0, T_, rho, chi, S);
+  if (nl % VW == 0 && cs % VW == 0 && al16(chi) && al16(S))
+    launch_lv<T, VW>(s, n, nl, cs, lam, kappa0, T_, rho, chi, S);
   else
-    launch_lv<T, 1>(s, n, nl, lam, kappa0, T_, rho, chi, S);
+    launch_lv<T, 1>(s, n, nl, cs, lam, kappa0, T_, rho, chi, S);
   VRT_HIP(hipGetLastError());
 }
 
-template void launch_lte<float>(hipStream_t, int64_t, int32_t, const double *, double, const double *,
+template void launch_lte<float>(hipStream_t, int64_t, int32_t, int64_t, const double *, double, const double *,
                                 const double *, float *, float *);
-template void launch_lte<double>(hipStream_t, int64_t, int32_t, const double *, double, const double *,
+template void launch_lte<double>(hipStream_t, int64_t, int32_t, int64_t, const double *, double, const double *,
                                  const double *, double *, double *);
 
 }  // namespace vrt

@@ -67,12 +67,15 @@ __device__ __forceinline__ int64_t affinity_record(const int64_t *__restrict__ x
   return -1;
 }
 
-// C lanes per record, V consecutive wavelengths per lane (nl is a multiple of V).
+// C lanes per record, V consecutive wavelengths per lane (nl and cs are
+// multiples of V). The input rows of site i (chi, S and the boundary
+// intensities) start at i cs (cs >= nl); intensity rows are nl apart.
 template <typename T, int C, int V>
 __device__ __forceinline__ void sweep_body(const int4 *__restrict__ ri,
                                            const typename vrt::RecOf<T>::type *__restrict__ rf, int64_t rec_begin,
-                                           int64_t rec_count, int32_t nl, int64_t n, const T *__restrict__ chi,
-                                           const T *__restrict__ S, const T *__restrict__ Ibot,
+                                           int64_t rec_count, int32_t nl, int64_t cs, int64_t n,
+                                           const T *__restrict__ chi, const T *__restrict__ S,
+                                           const T *__restrict__ Ibot,
                                            const T *__restrict__ Itop, T *I, int32_t xcd_chunks, int32_t ray0,
                                            const int64_t *__restrict__ xtab, int32_t xk) {
   using L = Lane<T, V>;
@@ -95,12 +98,12 @@ __device__ __forceinline__ void sweep_body(const int4 *__restrict__ ri,
   const int32_t ray = q.w >> 1;
   const bool up = (q.w & 1) != 0;
   T *Iray = I + (int64_t)(ray - ray0) * n * nl;
-  const int64_t bi = (int64_t)site * nl;
+  const int64_t bi = (int64_t)site * nl, ei = (int64_t)site * cs;
   if (k1 < 0) {
     for (int l = l0; l < nl; l += C * V) {
       VT v;
-      if (up) v = L::load(Ibot + bi + l);
-      else if (Itop) v = L::load(Itop + bi + l);
+      if (up) v = L::load(Ibot + ei + l);
+      else if (Itop) v = L::load(Itop + ei + l);
       else v = VT(T(0));
       L::store(Iray + bi + l, v);
     }
@@ -112,13 +115,14 @@ __device__ __forceinline__ void sweep_body(const int4 *__restrict__ ri,
   const bool two = k2 >= 0;
   const int64_t b1 = (int64_t)k1 * nl;
   const int64_t b2 = (int64_t)(two ? k2 : k1) * nl;
+  const int64_t e1 = (int64_t)k1 * cs, e2 = (int64_t)(two ? k2 : k1) * cs;
   for (int l = l0; l < nl; l += C * V) {
-    const VT ci = L::load(chi + bi + l), si = L::load(S + bi + l);
-    const VT c1 = L::load(chi + b1 + l), s1 = L::load(S + b1 + l), u1 = L::load(Iray + b1 + l);
+    const VT ci = L::load(chi + ei + l), si = L::load(S + ei + l);
+    const VT c1 = L::load(chi + e1 + l), s1 = L::load(S + e1 + l), u1 = L::load(Iray + b1 + l);
     VT c2, s2, u2;
     if (two) {
-      c2 = L::load(chi + b2 + l);
-      s2 = L::load(S + b2 + l);
+      c2 = L::load(chi + e2 + l);
+      s2 = L::load(S + e2 + l);
       u2 = L::load(Iray + b2 + l);
     }
     VT out;
@@ -142,10 +146,10 @@ __device__ __forceinline__ void sweep_body(const int4 *__restrict__ ri,
 template <typename T, int C, int V>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void sweep_kernel(
     const int4 *__restrict__ ri, const typename vrt::RecOf<T>::type *__restrict__ rf, int64_t rec_begin,
-    int64_t rec_count, int32_t nl, int64_t n, const T *__restrict__ chi, const T *__restrict__ S,
+    int64_t rec_count, int32_t nl, int64_t cs, int64_t n, const T *__restrict__ chi, const T *__restrict__ S,
     const T *__restrict__ Ibot, const T *__restrict__ Itop, T *I, int32_t xcd_chunks, int32_t ray0,
     const int64_t *__restrict__ xtab, int32_t xk) {
-  sweep_body<T, C, V>(ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I, xcd_chunks, ray0, xtab, xk);
+  sweep_body<T, C, V>(ri, rf, rec_begin, rec_count, nl, cs, n, chi, S, Ibot, Itop, I, xcd_chunks, ray0, xtab, xk);
 }
 
 // Double precision, or 32-byte lanes (twice the records per wavefront): more
@@ -153,10 +157,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
 template <typename T, int C, int V>
 __global__ __launch_bounds__(256) void sweep_kernel_wide(
     const int4 *__restrict__ ri, const typename vrt::RecOf<T>::type *__restrict__ rf, int64_t rec_begin,
-    int64_t rec_count, int32_t nl, int64_t n, const T *__restrict__ chi, const T *__restrict__ S,
+    int64_t rec_count, int32_t nl, int64_t cs, int64_t n, const T *__restrict__ chi, const T *__restrict__ S,
     const T *__restrict__ Ibot, const T *__restrict__ Itop, T *I, int32_t xcd_chunks, int32_t ray0,
     const int64_t *__restrict__ xtab, int32_t xk) {
-  sweep_body<T, C, V>(ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I, xcd_chunks, ray0, xtab, xk);
+  sweep_body<T, C, V>(ri, rf, rec_begin, rec_count, nl, cs, n, chi, S, Ibot, Itop, I, xcd_chunks, ray0, xtab, xk);
 }
 
 // Pipelined form of the same update for interior records (level steps >= 1:
@@ -176,7 +180,7 @@ __global__ __launch_bounds__(256) void sweep_kernel_wide(
 template <typename T, int C, int V, int Q>
 __global__ __launch_bounds__(256) void sweep_pipe_kernel(
     const int4 *__restrict__ ri, const typename vrt::RecOf<T>::type *__restrict__ rf, int64_t rec_begin,
-    int64_t rec_count, int32_t nl, int64_t n, const T *__restrict__ chi, const T *__restrict__ S, T *I,
+    int64_t rec_count, int32_t nl, int64_t cs, int64_t n, const T *__restrict__ chi, const T *__restrict__ S, T *I,
     int32_t xcd_chunks) {
   using L = Lane<T, V>;
   using VT = typename L::type;
@@ -202,14 +206,15 @@ __global__ __launch_bounds__(256) void sweep_pipe_kernel(
     const int32_t k1 = q[j].y > 0 ? q[j].y : 0;
     const int32_t k2 = q[j].z >= 0 ? q[j].z : k1;
     T *Iray = I + (int64_t)(q[j].w >> 1) * n * nl;
-    const int64_t bi = (int64_t)q[j].x * nl + l, b1 = (int64_t)k1 * nl + l, b2 = (int64_t)k2 * nl + l;
-    ci[j] = L::load(chi + bi);
-    si[j] = L::load(S + bi);
-    c1[j] = L::load(chi + b1);
-    s1[j] = L::load(S + b1);
+    const int64_t b1 = (int64_t)k1 * nl + l, b2 = (int64_t)k2 * nl + l;
+    const int64_t ei = (int64_t)q[j].x * cs + l, e1 = (int64_t)k1 * cs + l, e2 = (int64_t)k2 * cs + l;
+    ci[j] = L::load(chi + ei);
+    si[j] = L::load(S + ei);
+    c1[j] = L::load(chi + e1);
+    s1[j] = L::load(S + e1);
     u1[j] = L::load(Iray + b1);
-    c2[j] = L::load(chi + b2);
-    s2[j] = L::load(S + b2);
+    c2[j] = L::load(chi + e2);
+    s2[j] = L::load(S + e2);
     u2[j] = L::load(Iray + b2);
   };
   auto finish = [&](int j) {
@@ -348,52 +353,52 @@ void launch_ev(hipStream_t s, int64_t total, int32_t nl, int32_t ld, int64_t n, 
 // grid holds that many records for every die.
 template <typename T, int C, int V, int Q>
 void launch_pipe(hipStream_t s, const int4 *ri, const typename vrt::RecOf<T>::type *rf, int64_t b, int64_t c,
-                 int32_t nl, int64_t n, const T *chi, const T *S, T *I, int32_t xc) {
+                 int32_t nl, int64_t cs, int64_t n, const T *chi, const T *S, T *I, int32_t xc) {
   constexpr int SPW = 64 / C;
   const int64_t waves = (c + SPW * Q - 1) / (SPW * Q);
   const int64_t blocks = (waves + 3) / 4;
-  hipLaunchKernelGGL((sweep_pipe_kernel<T, C, V, Q>), dim3((unsigned)blocks), dim3(256), 0, s, ri, rf, b, c, nl, n,
-                     chi, S, I, xc);
+  hipLaunchKernelGGL((sweep_pipe_kernel<T, C, V, Q>), dim3((unsigned)blocks), dim3(256), 0, s, ri, rf, b, c, nl, cs,
+                     n, chi, S, I, xc);
 }
 
 template <typename T, int C, int V>
 void launch_c(hipStream_t s, const int4 *ri, const typename vrt::RecOf<T>::type *rf, int64_t b, int64_t c, int32_t nl,
-              int64_t n, const T *chi, const T *S, const T *Ibot, const T *Itop, T *I, int32_t xc, int32_t ray0,
-              const int64_t *xtab, int32_t xk, int32_t pipe) {
+              int64_t cs, int64_t n, const T *chi, const T *S, const T *Ibot, const T *Itop, T *I, int32_t xc,
+              int32_t ray0, const int64_t *xtab, int32_t xk, int32_t pipe) {
   constexpr int SPW = 64 / C;
   if constexpr (V * sizeof(T) == 16) {
     // the pipelined kernel (pipe > 0 is passed only for interior level steps):
     // per-ray rows from I (ray0 = 0), no affinity table, one lane-vector per lane
     if (pipe > 0 && !xtab && ray0 == 0 && nl <= C * V) {
-      if (pipe >= 8) launch_pipe<T, C, V, 8>(s, ri, rf, b, c, nl, n, chi, S, I, xc);
-      else if (pipe >= 4) launch_pipe<T, C, V, 4>(s, ri, rf, b, c, nl, n, chi, S, I, xc);
-      else launch_pipe<T, C, V, 2>(s, ri, rf, b, c, nl, n, chi, S, I, xc);
+      if (pipe >= 8) launch_pipe<T, C, V, 8>(s, ri, rf, b, c, nl, cs, n, chi, S, I, xc);
+      else if (pipe >= 4) launch_pipe<T, C, V, 4>(s, ri, rf, b, c, nl, cs, n, chi, S, I, xc);
+      else launch_pipe<T, C, V, 2>(s, ri, rf, b, c, nl, cs, n, chi, S, I, xc);
       return;
     }
   }
   const int64_t waves = (c + SPW - 1) / SPW;
   const int64_t blocks = xtab ? (int64_t)vrt::kDies * ((waves + 3) / 4) : (waves + 3) / 4;
   if constexpr (sizeof(T) != 4 || V * sizeof(T) > 16)
-    hipLaunchKernelGGL((sweep_kernel_wide<T, C, V>), dim3((unsigned)blocks), dim3(256), 0, s, ri, rf, b, c, nl, n, chi,
-                       S, Ibot, Itop, I, xc, ray0, xtab, xk);
+    hipLaunchKernelGGL((sweep_kernel_wide<T, C, V>), dim3((unsigned)blocks), dim3(256), 0, s, ri, rf, b, c, nl, cs, n,
+                       chi, S, Ibot, Itop, I, xc, ray0, xtab, xk);
   else
-    hipLaunchKernelGGL((sweep_kernel<T, C, V>), dim3((unsigned)blocks), dim3(256), 0, s, ri, rf, b, c, nl, n, chi, S,
-                       Ibot, Itop, I, xc, ray0, xtab, xk);
+    hipLaunchKernelGGL((sweep_kernel<T, C, V>), dim3((unsigned)blocks), dim3(256), 0, s, ri, rf, b, c, nl, cs, n, chi,
+                       S, Ibot, Itop, I, xc, ray0, xtab, xk);
 }
 
 // lanes per record for m lane-vectors per row: the smallest power of two >= m, at most 64
 template <typename T, int V>
 void launch_v(hipStream_t s, const int4 *ri, const typename vrt::RecOf<T>::type *rf, int64_t b, int64_t c, int32_t nl,
-              int64_t n, const T *chi, const T *S, const T *Ibot, const T *Itop, T *I, int32_t xc, int32_t ray0,
-              const int64_t *xtab, int32_t xk, int32_t pp) {
+              int64_t cs, int64_t n, const T *chi, const T *S, const T *Ibot, const T *Itop, T *I, int32_t xc,
+              int32_t ray0, const int64_t *xtab, int32_t xk, int32_t pp) {
   const int32_t m = nl / V;
-  if (m >= 33) launch_c<T, 64, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk, pp);
-  else if (m >= 17) launch_c<T, 32, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk, pp);
-  else if (m >= 9) launch_c<T, 16, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk, pp);
-  else if (m >= 5) launch_c<T, 8, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk, pp);
-  else if (m >= 3) launch_c<T, 4, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk, pp);
-  else if (m == 2) launch_c<T, 2, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk, pp);
-  else launch_c<T, 1, V>(s, ri, rf, b, c, nl, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk, pp);
+  if (m >= 33) launch_c<T, 64, V>(s, ri, rf, b, c, nl, cs, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk, pp);
+  else if (m >= 17) launch_c<T, 32, V>(s, ri, rf, b, c, nl, cs, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk, pp);
+  else if (m >= 9) launch_c<T, 16, V>(s, ri, rf, b, c, nl, cs, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk, pp);
+  else if (m >= 5) launch_c<T, 8, V>(s, ri, rf, b, c, nl, cs, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk, pp);
+  else if (m >= 3) launch_c<T, 4, V>(s, ri, rf, b, c, nl, cs, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk, pp);
+  else if (m == 2) launch_c<T, 2, V>(s, ri, rf, b, c, nl, cs, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk, pp);
+  else launch_c<T, 1, V>(s, ri, rf, b, c, nl, cs, n, chi, S, Ibot, Itop, I, xc, ray0, xtab, xk, pp);
 }
 
 // Forward sweep with checkpointed intensities, for the reverse sweep: the rows
@@ -501,20 +506,22 @@ namespace vrt {
 
 template <typename T>
 void launch_sweep(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *rf, int64_t rec_begin,
-                  int64_t rec_count, int32_t nl, int64_t n, const T *chi, const T *S, const T *Ibot, const T *Itop,
-                  T *I, int32_t xcd_chunks, int32_t ray0, const int64_t *xtab, int32_t xk, int32_t lane_bytes,
-                  int32_t pipe) {
+                  int64_t rec_count, int32_t nl, int64_t cs, int64_t n, const T *chi, const T *S, const T *Ibot,
+                  const T *Itop, T *I, int32_t xcd_chunks, int32_t ray0, const int64_t *xtab, int32_t xk,
+                  int32_t lane_bytes, int32_t pipe) {
   if (rec_count <= 0) return;
+  // a vector lane needs every row it reads to start on its own boundary: the
+  // row lengths and the chi / S row stride are multiples of the vector width
   const bool aligned = aligned16(chi) && aligned16(S) && aligned16(Ibot) && aligned16(Itop) && aligned16(I);
   const bool aligned32 = aligned32p(chi) && aligned32p(S) && aligned32p(Ibot) && aligned32p(Itop) && aligned32p(I);
-  if (lane_bytes == 32 && aligned32 && nl % (2 * kVec<T>) == 0)
-    launch_v<T, 2 * kVec<T>>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I, xcd_chunks, ray0, xtab,
-                             xk, 0);
-  else if (aligned && nl % kVec<T> == 0)
-    launch_v<T, kVec<T>>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I, xcd_chunks, ray0, xtab, xk,
-                         pipe);
+  if (lane_bytes == 32 && aligned32 && nl % (2 * kVec<T>) == 0 && cs % (2 * kVec<T>) == 0)
+    launch_v<T, 2 * kVec<T>>(s, ri, rf, rec_begin, rec_count, nl, cs, n, chi, S, Ibot, Itop, I, xcd_chunks, ray0,
+                             xtab, xk, 0);
+  else if (aligned && nl % kVec<T> == 0 && cs % kVec<T> == 0)
+    launch_v<T, kVec<T>>(s, ri, rf, rec_begin, rec_count, nl, cs, n, chi, S, Ibot, Itop, I, xcd_chunks, ray0, xtab,
+                         xk, pipe);
   else
-    launch_v<T, 1>(s, ri, rf, rec_begin, rec_count, nl, n, chi, S, Ibot, Itop, I, xcd_chunks, ray0, xtab, xk, 0);
+    launch_v<T, 1>(s, ri, rf, rec_begin, rec_count, nl, cs, n, chi, S, Ibot, Itop, I, xcd_chunks, ray0, xtab, xk, 0);
   VRT_HIP(hipGetLastError());
 }
 
@@ -558,11 +565,11 @@ void launch_emergent(hipStream_t s, int64_t total, int32_t nl, int32_t ld, int64
 }
 
 template void launch_sweep<float>(hipStream_t, const int4 *, const RecF32 *, int64_t, int64_t, int32_t, int64_t,
-                                  const float *, const float *, const float *, const float *, float *, int32_t,
-                                  int32_t, const int64_t *, int32_t, int32_t, int32_t);
+                                  int64_t, const float *, const float *, const float *, const float *, float *,
+                                  int32_t, int32_t, const int64_t *, int32_t, int32_t, int32_t);
 template void launch_sweep<double>(hipStream_t, const int4 *, const RecF64 *, int64_t, int64_t, int32_t, int64_t,
-                                   const double *, const double *, const double *, const double *, double *, int32_t,
-                                   int32_t, const int64_t *, int32_t, int32_t, int32_t);
+                                   int64_t, const double *, const double *, const double *, const double *, double *,
+                                   int32_t, int32_t, const int64_t *, int32_t, int32_t, int32_t);
 template void launch_sweep_ck<float>(hipStream_t, const int4 *, const RecF32 *, const int4 *, int64_t, int64_t,
                                      int32_t, const float *, const float *, const float *, const float *, float *,
                                      float *);

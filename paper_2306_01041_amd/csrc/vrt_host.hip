@@ -667,12 +667,16 @@ const vrt::PersistItems &persistent_items(vrt_grid g, int32_t spw, bool mixed = 
   return ref;
 }
 
-// The sweeps of every ray (no angle quadrature).
+// The sweeps of every ray (no angle quadrature). The input rows of site i
+// (chi, S, Ib, It) start at i cs (cs = 0: nl, arrays of n x nl).
 template <typename T>
 void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *chi, const T *S, const T *Ib,
-                   const T *It, T *I, bool sign = false) {
+                   const T *It, T *I, bool sign = false, int64_t cs = 0) {
   const int32_t R = g->R;
   const int64_t n = g->n;
+  if (cs == 0) cs = nl;
+  // the plane kernels of the regular grid read rows of nl entries
+  if (g->kind != 0 && cs != nl) fail(VRT_E_ARG, "a regular grid takes chi and S rows of n_lambda entries");
   vrt_ctx ctx = g->ctx;
   const bool tm = ctx->profiling && ex != VRT_EXEC_GRAPH && s == ctx->stream;
   if (g->kind == 0 && g->segment == 1) {
@@ -681,7 +685,7 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
     auto sweep = [&](const int4 *rix, decltype(rf) rfx, int64_t b, int64_t c) {
       if (c <= 0) return;
       timed_launch(ctx, s, tm, 0, c * nl, [&] {
-        vrt::launch_bezier_sweep<T>(s, rix, rfx, b, c, nl, n, g->d_q1.as<int32_t>(), g->d_q2.as<int32_t>(),
+        vrt::launch_bezier_sweep<T>(s, rix, rfx, b, c, nl, cs, n, g->d_q1.as<int32_t>(), g->d_q2.as<int32_t>(),
                                     g->d_qw1.as<double>(), g->d_qd1.as<double>(), g->d_qd2.as<double>(), chi, S, Ib,
                                     It, I, g->xcd_chunks);
       });
@@ -691,7 +695,7 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
       int32_t *words = g->d_epoch.as<int32_t>();
       vrt::launch_persist_begin(s, words);
       timed_launch(ctx, s, tm, 0, g->n_rec * nl, [&] {
-        vrt::launch_persistent_bezier<T>(s, items, g->persist_max_blocks, ri, rf, nl, n, g->d_q1.as<int32_t>(),
+        vrt::launch_persistent_bezier<T>(s, items, g->persist_max_blocks, ri, rf, nl, cs, n, g->d_q1.as<int32_t>(),
                                          g->d_q2.as<int32_t>(), g->d_qw1.as<double>(), g->d_qd1.as<double>(),
                                          g->d_qd2.as<double>(), chi, S, Ib, It, I, flag_ld(g),
                                          g->d_flags.as<int32_t>(), words, g->spin_cap);
@@ -718,7 +722,7 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
     // records of several rays
     const bool mixed = g->interleave && g->interleaved_built == g->interleave;
     const vrt::PersistItems &items =
-        persistent_items(g, vrt::persistent_records_per_wave(nl, sizeof(T), aligned), mixed);
+        persistent_items(g, vrt::persistent_records_per_wave(nl, sizeof(T), aligned, cs), mixed);
     const int4 *rix = mixed ? g->d_ri_x.as<int4>() : g->d_ri.as<int4>();
     const auto *rfx = records<T>(g);
     if (mixed)
@@ -726,8 +730,8 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
     int32_t *words = g->d_epoch.as<int32_t>();
     vrt::launch_persist_begin(s, words, sign);
     timed_launch(ctx, s, tm, 0, g->n_rec * nl, [&] {
-      vrt::launch_persistent_sweep<T>(s, items, g->persist_max_blocks, rix, rfx, nl, n, flag_ld(g), chi, S, Ib, It,
-                                      I, g->d_flags.as<int32_t>(), words, g->spin_cap, sign, mixed ? R : 0);
+      vrt::launch_persistent_sweep<T>(s, items, g->persist_max_blocks, rix, rfx, nl, cs, n, flag_ld(g), chi, S, Ib,
+                                      It, I, g->d_flags.as<int32_t>(), words, g->spin_cap, sign, mixed ? R : 0);
     });
   } else if (g->kind == 0) {
     const int4 *ri = g->d_ri.as<int4>();
@@ -739,7 +743,7 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
       if (c <= 0) return;
       const int32_t pp = (ex == VRT_EXEC_PLAIN || st == 0) ? 0 : g->pipe;
       timed_launch(ctx, s, tm, 0, c * nl, [&] {
-        vrt::launch_sweep<T>(s, ri, rf, b, c, nl, n, chi, S, Ib, It, I, xc, 0, nullptr, 0, g->lane_bytes, pp);
+        vrt::launch_sweep<T>(s, ri, rf, b, c, nl, cs, n, chi, S, Ib, It, I, xc, 0, nullptr, 0, g->lane_bytes, pp);
       });
     };
     if (ex == VRT_EXEC_PLAIN) {
@@ -754,7 +758,8 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
         if (c <= 0) continue;
         const int64_t units = (g->step_ptr[(size_t)st + 1] - g->step_ptr[(size_t)st]) * nl;
         timed_launch(ctx, s, tm, 0, units, [&] {
-          vrt::launch_sweep<T>(s, ri, rf, 0, c, nl, n, chi, S, Ib, It, I, 0, 0, xt + per * st, g->xk, g->lane_bytes);
+          vrt::launch_sweep<T>(s, ri, rf, 0, c, nl, cs, n, chi, S, Ib, It, I, 0, 0, xt + per * st, g->xk,
+                               g->lane_bytes);
         });
       }
     } else if (g->chains > 1 && R > 1) {
@@ -774,7 +779,7 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
           hipStream_t sc = c == 0 ? s : ctx->aux[(size_t)c - 1];
           timed_launch(ctx, sc, tm, 0, (e - b) * nl,
                        [&] {
-                         vrt::launch_sweep<T>(sc, ri, rf, b, e - b, nl, n, chi, S, Ib, It, I, xc, 0, nullptr, 0,
+                         vrt::launch_sweep<T>(sc, ri, rf, b, e - b, nl, cs, n, chi, S, Ib, It, I, xc, 0, nullptr, 0,
                                               g->lane_bytes, st > 0 ? g->pipe : 0);
                        });
         }
@@ -806,7 +811,7 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
         const int64_t b = g->step_ptr[(size_t)st], c = g->step_ptr[(size_t)st + 1] - b;
         if (c <= 0) continue;
         timed_launch(ctx, s, tm, 0, c * nl, [&] {
-          vrt::launch_sweep<T>(s, rix, rfx, b, c, nl, n, chi, S, Ib, It, I, xc, 0, nullptr, 0, g->lane_bytes,
+          vrt::launch_sweep<T>(s, rix, rfx, b, c, nl, cs, n, chi, S, Ib, It, I, xc, 0, nullptr, 0, g->lane_bytes,
                                st > 0 ? g->pipe : 0);
         });
       }
@@ -831,8 +836,8 @@ void enqueue_sweep(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *
 
 template <typename T>
 void enqueue_fs(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, const T *chi, const T *S, const T *Ib,
-                const T *It, T *J, T *I, bool sign = false) {
-  enqueue_sweep<T>(g, s, ex, nl, chi, S, Ib, It, I, sign);
+                const T *It, T *J, T *I, bool sign = false, int64_t cs = 0) {
+  enqueue_sweep<T>(g, s, ex, nl, chi, S, Ib, It, I, sign, cs);
   vrt_ctx ctx = g->ctx;
   const bool tm = ctx->profiling && ex != VRT_EXEC_GRAPH && s == ctx->stream;
   const int32_t R = g->R;
@@ -1102,7 +1107,7 @@ void formal_solution_vjp(vrt_grid g, int32_t nl, const T *chi, const T *S, const
       for (int32_t st = 0; st < g->n_steps; ++st) {
         int64_t b, c;
         seg(st, b, c);
-        vrt::launch_sweep<T>(s, ri, rf, b, c, nl, n, chi, S, Ib, It, Iw, g->xcd_chunks, r0);
+        vrt::launch_sweep<T>(s, ri, rf, b, c, nl, nl, n, chi, S, Ib, It, Iw, g->xcd_chunks, r0);
       }
       Ifw = Iw;
     }
@@ -1144,11 +1149,14 @@ template <typename T>
 void enqueue_lambda_step(vrt_grid g, hipStream_t s, vrt_exec ex, int32_t nl, int32_t ld, const double *phi,
                          const double *chi_L, const double *chi_c, const double *B, double eps, double *S_L, T *I,
                          int32_t n_atm, const double *Lbar) {
-  T *chi = g->d_nchi.as<T>(), *S = g->d_nS.as<T>(), *Ib = g->d_nIb.as<T>();
+  // a site's chi and S rows side by side (S = chi + ld, rows 2 ld apart): the
+  // sweep's gathers of an upwind site then read one contiguous span
+  const int64_t cs = 2 * (int64_t)ld;
+  T *chi = g->d_nchi.as<T>(), *S = chi + ld, *Ib = g->d_nIb.as<T>();
   auto *dS = g->d_dS.as<unsigned long long>();
   vrt::launch_zero_u64(s, n_atm, dS);
-  vrt::launch_nlte_assemble<T>(s, g->n, nl, ld, phi, chi_L, chi_c, B, S_L, chi, S);
-  enqueue_sweep<T>(g, s, ex == VRT_EXEC_GRAPH ? VRT_EXEC_BATCHED : ex, ld, chi, S, Ib, nullptr, I);
+  vrt::launch_nlte_assemble<T>(s, g->n, nl, ld, cs, phi, chi_L, chi_c, B, S_L, chi, S);
+  enqueue_sweep<T>(g, s, ex == VRT_EXEC_GRAPH ? VRT_EXEC_BATCHED : ex, ld, chi, S, Ib, nullptr, I, false, cs);
   vrt::launch_line_update<T>(s, g->n, nl, ld, g->R, I, g->d_w.as<double>(), g->d_wlam.as<double>(), phi, B, eps,
                              S_L, n_atm, g->d_atm_ptr.as<int64_t>(), g->d_active.as<int32_t>(), dS,
                              g->d_jbar.as<double>(), Lbar);
@@ -1172,9 +1180,9 @@ vrt_status two_level_solve(vrt_grid g, vrt_exec ex, int32_t nl, const double *wl
   ++g->solution_id;  // from here on the last solution's rows may be overwritten
   T *I = intensity_buffer<T>(g, ld, nullptr);
   VRT_HIP(hipStreamSynchronize(s));  // earlier work may still read the buffers replaced below
-  g->d_nchi.alloc(nn * sizeof(T));
-  g->d_nS.alloc(nn * sizeof(T));
-  g->d_nIb.alloc(nn * sizeof(T));
+  // chi and S rows paired, 2 ld apart; the bottom boundary rows (B) at the same stride
+  g->d_nchi.alloc(2 * nn * sizeof(T));
+  g->d_nIb.alloc(2 * nn * sizeof(T));
   g->d_jbar.alloc((size_t)g->n * 8);
   g->d_dS.alloc((size_t)n_atm * 8);
   g->d_atm_ptr.alloc((size_t)(n_atm + 1) * 8);
@@ -1205,7 +1213,7 @@ vrt_status two_level_solve(vrt_grid g, vrt_exec ex, int32_t nl, const double *wl
     VRT_HIP(hipStreamSynchronize(s));
     if (bad) fail(VRT_E_GRID, "a site reads an upwind neighbour in another atmosphere");
   }
-  vrt::launch_broadcast<T>(s, g->n, ld, B, g->d_nIb.as<T>());
+  vrt::launch_broadcast<T>(s, g->n, ld, 2 * (int64_t)ld, B, g->d_nIb.as<T>());
   const double *Lbar = nullptr;
   if (accel) {
     if (g->kind != 0) fail(VRT_E_ARG, "the accelerated iteration needs a Voronoi grid");
@@ -1224,7 +1232,7 @@ vrt_status two_level_solve(vrt_grid g, vrt_exec ex, int32_t nl, const double *wl
                                      (const void *)g->d_dS.p, accel ? 1 : 0);
     // the graph also bakes in the scratch pointers, which the allocations above may have moved
     const bool same = g->nlte_graph && g->nlte_key == key && g->nlte_scratch[0] == g->d_nchi.p &&
-                      g->nlte_scratch[1] == g->d_nS.p && g->nlte_scratch[2] == g->d_nIb.p &&
+                      g->nlte_scratch[2] == g->d_nIb.p &&
                       g->nlte_scratch[3] == (const void *)I && g->nlte_scratch[4] == g->d_wlam.p &&
                       g->nlte_scratch[5] == g->d_jbar.p && g->nlte_scratch[6] == (const void *)Lbar;
     if (!same) {
@@ -1247,7 +1255,7 @@ vrt_status two_level_solve(vrt_grid g, vrt_exec ex, int32_t nl, const double *wl
       VRT_HIP(e);
       g->nlte_key = key;
       g->nlte_scratch[0] = g->d_nchi.p;
-      g->nlte_scratch[1] = g->d_nS.p;
+      g->nlte_scratch[1] = nullptr;
       g->nlte_scratch[2] = g->d_nIb.p;
       g->nlte_scratch[3] = I;
       g->nlte_scratch[4] = g->d_wlam.p;
@@ -1296,9 +1304,10 @@ vrt_status two_level_solve(vrt_grid g, vrt_exec ex, int32_t nl, const double *wl
   return n_active == 0 ? VRT_OK : VRT_W_NOT_CONVERGED;
 }
 
+// cs: the row stride of chi, S, Ib and It in elements (0: nl)
 template <typename T>
 void formal_solution(vrt_grid g, vrt_exec ex, int32_t nl, const void *chi_, const void *S_, const void *Ib_,
-                     const void *It_, void *J_, void *Ir_) {
+                     const void *It_, void *J_, void *Ir_, int64_t cs = 0) {
   const T *chi = static_cast<const T *>(chi_), *S = static_cast<const T *>(S_);
   const T *Ib = Ib_ ? static_cast<const T *>(Ib_) : S;
   const T *It = static_cast<const T *>(It_);
@@ -1310,10 +1319,11 @@ void formal_solution(vrt_grid g, vrt_exec ex, int32_t nl, const void *chi_, cons
   // sign-encoded protocol; rows handed in by the caller keep the stamps
   const bool sign = ex == VRT_EXEC_PERSISTENT && g->segment == 0 && !Ir_;
   T *I = sign ? sign_buffer<T>(g, nl) : intensity_buffer<T>(g, nl, Ir_);
+  if (cs == 0) cs = nl;
   if (ex != VRT_EXEC_GRAPH) {
-    enqueue_fs<T>(g, ctx->stream, ex, nl, chi, S, Ib, It, J, I, sign);
+    enqueue_fs<T>(g, ctx->stream, ex, nl, chi, S, Ib, It, J, I, sign, cs);
   } else {
-    const vrt_grid_s::GraphKey key{sizeof(T), nl, chi, S, Ib, It, J, I};
+    const vrt_grid_s::GraphKey key{sizeof(T), nl, cs, chi, S, Ib, It, J, I};
     auto it = g->graphs.find(key);
     if (it == g->graphs.end() && g->graphs.size() >= 8) {
       // bounded cache: callers that pass fresh buffers every time would otherwise grow it without end
@@ -1322,17 +1332,17 @@ void formal_solution(vrt_grid g, vrt_exec ex, int32_t nl, const void *chi_, cons
     }
     if (it == g->graphs.end()) {
       if (!ctx->capture_stream) VRT_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
-      hipStream_t cs = ctx->capture_stream;
-      VRT_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      hipStream_t cs_ = ctx->capture_stream;
+      VRT_HIP(hipStreamBeginCapture(cs_, hipStreamCaptureModeThreadLocal));
       hipGraph_t graph = nullptr;
       try {
-        enqueue_fs<T>(g, cs, VRT_EXEC_BATCHED, nl, chi, S, Ib, It, J, I);
+        enqueue_fs<T>(g, cs_, VRT_EXEC_BATCHED, nl, chi, S, Ib, It, J, I, false, cs);
       } catch (...) {
-        (void)hipStreamEndCapture(cs, &graph);
+        (void)hipStreamEndCapture(cs_, &graph);
         if (graph) (void)hipGraphDestroy(graph);
         throw;
       }
-      VRT_HIP(hipStreamEndCapture(cs, &graph));
+      VRT_HIP(hipStreamEndCapture(cs_, &graph));
       hipGraphExec_t exec = nullptr;
       hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
@@ -1915,12 +1925,13 @@ vrt_status vrt_grid_schedule(vrt_grid g, int32_t ray, int32_t *k1, int32_t *k2, 
   });
 }
 
-vrt_status vrt_lte_continuum(vrt_grid g, vrt_prec prec, int32_t n_lambda, const double *lambda_m, double kappa0,
-                             const double *T, const double *rho, void *chi, void *S) {
+vrt_status vrt_lte_continuum_ld(vrt_grid g, vrt_prec prec, int32_t n_lambda, int64_t ld_src, const double *lambda_m,
+                                double kappa0, const double *T, const double *rho, void *chi, void *S) {
   if (!g) return VRT_E_ARG;
   return guarded(g->ctx, [&] {
     if (!valid_prec(prec) || n_lambda <= 0 || !lambda_m || !(g->n == 0 || (T && rho && chi && S)))
       fail(VRT_E_ARG, "bad LTE arguments");
+    if (ld_src < n_lambda) fail(VRT_E_ARG, "ld_src %lld is below n_lambda %d", (long long)ld_src, n_lambda);
     for (int32_t l = 0; l < n_lambda; ++l)
       if (!(lambda_m[l] > 0.0)) fail(VRT_E_ARG, "wavelength %d is not positive", l);
     hipStream_t s = g->ctx->stream;
@@ -1933,17 +1944,23 @@ vrt_status vrt_lte_continuum(vrt_grid g, vrt_prec prec, int32_t n_lambda, const 
       g->h_lam.assign(lambda_m, lambda_m + n_lambda);
     }
     if (prec == VRT_F32)
-      vrt::launch_lte<float>(s, g->n, n_lambda, g->d_lam.as<double>(), kappa0, T, rho, static_cast<float *>(chi),
-                             static_cast<float *>(S));
+      vrt::launch_lte<float>(s, g->n, n_lambda, ld_src, g->d_lam.as<double>(), kappa0, T, rho,
+                             static_cast<float *>(chi), static_cast<float *>(S));
     else
-      vrt::launch_lte<double>(s, g->n, n_lambda, g->d_lam.as<double>(), kappa0, T, rho, static_cast<double *>(chi),
-                              static_cast<double *>(S));
+      vrt::launch_lte<double>(s, g->n, n_lambda, ld_src, g->d_lam.as<double>(), kappa0, T, rho,
+                              static_cast<double *>(chi), static_cast<double *>(S));
     return VRT_OK;
   });
 }
 
-vrt_status vrt_formal_solution(vrt_grid g, vrt_prec prec, vrt_exec exec, int32_t n_lambda, const void *chi,
-                               const void *S, const void *I_bottom, const void *I_top, void *J, void *I_rays) {
+vrt_status vrt_lte_continuum(vrt_grid g, vrt_prec prec, int32_t n_lambda, const double *lambda_m, double kappa0,
+                             const double *T, const double *rho, void *chi, void *S) {
+  return vrt_lte_continuum_ld(g, prec, n_lambda, n_lambda, lambda_m, kappa0, T, rho, chi, S);
+}
+
+vrt_status vrt_formal_solution_ld(vrt_grid g, vrt_prec prec, vrt_exec exec, int32_t n_lambda, int64_t ld_src,
+                                  const void *chi, const void *S, const void *I_bottom, const void *I_top, void *J,
+                                  void *I_rays) {
   if (!g) return VRT_E_ARG;
   return guarded(g->ctx, [&] {
     if (exec == VRT_EXEC_AUTO) exec = (vrt_exec)g->tuned_exec;
@@ -1951,15 +1968,23 @@ vrt_status vrt_formal_solution(vrt_grid g, vrt_prec prec, vrt_exec exec, int32_t
                               exec != VRT_EXEC_PERSISTENT))
       fail(VRT_E_ARG, "bad precision or execution mode");
     if (n_lambda <= 0) fail(VRT_E_ARG, "n_lambda must be positive");
+    if (ld_src < n_lambda) fail(VRT_E_ARG, "ld_src %lld is below n_lambda %d", (long long)ld_src, n_lambda);
+    if (g->kind != 0 && ld_src != n_lambda)
+      fail(VRT_E_ARG, "a regular grid takes input rows of n_lambda entries (ld_src = n_lambda)");
     if (g->R == 0) fail(VRT_E_STATE, "rays not set");
     if (g->n > 0 && (!chi || !S || !J)) fail(VRT_E_ARG, "chi, S and J are required");
     if (g->n == 0) return VRT_OK;
     if (prec == VRT_F32)
-      formal_solution<float>(g, exec, n_lambda, chi, S, I_bottom, I_top, J, I_rays);
+      formal_solution<float>(g, exec, n_lambda, chi, S, I_bottom, I_top, J, I_rays, ld_src);
     else
-      formal_solution<double>(g, exec, n_lambda, chi, S, I_bottom, I_top, J, I_rays);
+      formal_solution<double>(g, exec, n_lambda, chi, S, I_bottom, I_top, J, I_rays, ld_src);
     return VRT_OK;
   });
+}
+
+vrt_status vrt_formal_solution(vrt_grid g, vrt_prec prec, vrt_exec exec, int32_t n_lambda, const void *chi,
+                               const void *S, const void *I_bottom, const void *I_top, void *J, void *I_rays) {
+  return vrt_formal_solution_ld(g, prec, exec, n_lambda, n_lambda, chi, S, I_bottom, I_top, J, I_rays);
 }
 
 vrt_status vrt_formal_solution_noalloc(vrt_grid g, vrt_prec prec, int32_t n_lambda, const void *chi, const void *S,

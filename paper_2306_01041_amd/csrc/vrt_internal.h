@@ -240,7 +240,7 @@ struct vrt_grid_s {
 
   // two-level iteration scratch: chi, S, I_bottom in the sweep precision, the
   // profile weights, the max-change word and its pinned host copy
-  vrt::DevBuf d_nchi, d_nS, d_nIb, d_wlam, d_dS, d_atm_ptr, d_active, d_jbar, d_lbar;
+  vrt::DevBuf d_nchi, d_nIb, d_wlam, d_dS, d_atm_ptr, d_active, d_jbar, d_lbar;
   unsigned long long *h_dS = nullptr;  // pinned, [n_atm]
   int32_t *h_active = nullptr;         // pinned, [n_atm]
   int32_t h_dS_cap = 0;
@@ -267,8 +267,9 @@ struct vrt_grid_s {
   // nearest-site walk's error flag
   vrt::DevBuf d_pack, d_walk_bad, d_brute;
 
-  // captured launch sequences, keyed by (prec, n_lambda, pointers)
-  using GraphKey = std::tuple<int, int32_t, const void *, const void *, const void *, const void *, void *, void *>;
+  // captured launch sequences, keyed by (prec, n_lambda, chi / S row stride, pointers)
+  using GraphKey =
+      std::tuple<int, int32_t, int64_t, const void *, const void *, const void *, const void *, void *, void *>;
   std::map<GraphKey, hipGraphExec_t> graphs;
   void drop_graphs();
 };
@@ -309,9 +310,11 @@ void launch_pack(hipStream_t s, int64_t n, int32_t R, int32_t Lmax, const int32_
 // ray0 = 0, no affinity table; otherwise the classic kernel runs). The
 // pipelined kernel updates interior records only: pass pipe > 0 for level
 // steps >= 1 (step 0 holds exactly the boundary sites).
+// The input rows of site i (chi, S, Ibot, Itop) start at i cs (cs >= nl; cs =
+// nl for arrays of n x nl); intensity rows are nl apart.
 template <typename T>
 void launch_sweep(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *rf, int64_t rec_begin,
-                  int64_t rec_count, int32_t nl, int64_t n, const T *chi, const T *S, const T *Ibot,
+                  int64_t rec_count, int32_t nl, int64_t cs, int64_t n, const T *chi, const T *S, const T *Ibot,
                   const T *Itop, T *I, int32_t xcd_chunks, int32_t ray0, const int64_t *xtab = nullptr,
                   int32_t xk = 0, int32_t lane_bytes = 16, int32_t pipe = 0);
 // Forward sweep of records [rec_begin, rec_begin + rec_count) with checkpointed
@@ -334,8 +337,9 @@ void launch_emergent(hipStream_t s, int64_t total, int32_t nl, int32_t ld, int64
                      const int32_t *err = nullptr);
 
 // ---- k_source.hip
+// rows of site i at i cs (cs >= nl)
 template <typename T>
-void launch_lte(hipStream_t s, int64_t n, int32_t nl, const double *lam, double kappa0, const double *T_,
+void launch_lte(hipStream_t s, int64_t n, int32_t nl, int64_t cs, const double *lam, double kappa0, const double *T_,
                 const double *rho, T *chi, T *S);
 
 // ---- k_persist.hip
@@ -347,13 +351,15 @@ void launch_lte(hipStream_t s, int64_t n, int32_t nl, const double *lam, double 
 void launch_persist_begin(hipStream_t s, int32_t *words, bool sign = false);
 // fills count elements with zeros of the current sign-encoded epoch's sign
 template <typename T> void launch_sign_fill(hipStream_t s, T *p, int64_t count, const int32_t *words);
-int32_t persistent_records_per_wave(int32_t nl, int elem_bytes, bool aligned);
+// records per wavefront of the persistent sweep for rows of nl entries and a
+// chi / S row stride cs
+int32_t persistent_records_per_wave(int32_t nl, int elem_bytes, bool aligned, int64_t cs);
 bool al16(const void *p);
 template <typename T>
 void launch_persistent_sweep(hipStream_t s, const PersistItems &items, int32_t max_blocks, const int4 *ri,
-                             const typename RecOf<T>::type *rf, int32_t nl, int64_t n, int64_t flag_ld, const T *chi,
-                             const T *S, const T *Ibot, const T *Itop, T *I, int32_t *flags, int32_t *words,
-                             int64_t spin_cap, bool sign = false, int32_t mixed_rays = 0);
+                             const typename RecOf<T>::type *rf, int32_t nl, int64_t cs, int64_t n, int64_t flag_ld,
+                             const T *chi, const T *S, const T *Ibot, const T *Itop, T *I, int32_t *flags,
+                             int32_t *words, int64_t spin_cap, bool sign = false, int32_t mixed_rays = 0);
 
 // dst[i] = |src[i]| (abs) or src[i], converted to T; NaN everywhere when the
 // persistent sweeps' error word (err, may be null) is set
@@ -362,10 +368,13 @@ void launch_rows_convert(hipStream_t s, const void *src, bool src_f32, bool abs,
                          const int32_t *err);
 
 // ---- k_nlte.hip
+// rows of ld entries, cs apart
 template <typename T>
-void launch_nlte_assemble(hipStream_t s, int64_t n, int32_t nl, int32_t ld, const double *phi, const double *chi_L,
-                          const double *chi_c, const double *B, const double *S_L, T *chi, T *S);
-template <typename T> void launch_broadcast(hipStream_t s, int64_t n, int32_t ld, const double *v, T *out);
+void launch_nlte_assemble(hipStream_t s, int64_t n, int32_t nl, int32_t ld, int64_t cs, const double *phi,
+                          const double *chi_L, const double *chi_c, const double *B, const double *S_L, T *chi,
+                          T *S);
+template <typename T>
+void launch_broadcast(hipStream_t s, int64_t n, int32_t ld, int64_t cs, const double *v, T *out);
 void launch_zero_u64(hipStream_t s, int32_t count, unsigned long long *p);
 // sets *bad to 1 if a selected upwind neighbour of a site lies in another atmosphere
 void launch_check_partition(hipStream_t s, int64_t n, int32_t R, const int32_t *k1, const int32_t *k2, int32_t n_atm,
@@ -427,13 +436,13 @@ void launch_regular(hipStream_t s, int32_t step, int32_t ray_begin, int32_t ray_
 int32_t bezier_records_per_wave();
 template <typename T>
 void launch_persistent_bezier(hipStream_t s, const PersistItems &items, int32_t max_blocks, const int4 *ri,
-                              const typename RecOf<T>::type *rf, int32_t nl, int64_t n, const int32_t *q1,
+                              const typename RecOf<T>::type *rf, int32_t nl, int64_t cs, int64_t n, const int32_t *q1,
                               const int32_t *q2, const double *qw1, const double *qd1, const double *qd2,
                               const T *chi, const T *S, const T *Ibot, const T *Itop, T *I, int64_t flag_ld,
                               int32_t *flags, int32_t *words, int64_t spin_cap);
 template <typename T>
 void launch_bezier_sweep(hipStream_t s, const int4 *ri, const typename RecOf<T>::type *rf, int64_t rec_begin,
-                         int64_t rec_count, int32_t nl, int64_t n, const int32_t *q1, const int32_t *q2,
+                         int64_t rec_count, int32_t nl, int64_t cs, int64_t n, const int32_t *q1, const int32_t *q2,
                          const double *qw1, const double *qd1, const double *qd2, const T *chi, const T *S,
                          const T *Ibot, const T *Itop, T *I, int32_t xcd_chunks);
 

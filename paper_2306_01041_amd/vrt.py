@@ -103,8 +103,12 @@ vrt_grid_schedule = _sig("vrt_grid_schedule", _st, [_vp, ctypes.c_int32, _i32, _
                                                     _i32])
 vrt_lte_continuum = _sig("vrt_lte_continuum", _st, [_vp, ctypes.c_int32, ctypes.c_int32, _d, ctypes.c_double, _vp,
                                                     _vp, _vp, _vp])
+vrt_lte_continuum_ld = _sig("vrt_lte_continuum_ld", _st, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _d,
+                                                          ctypes.c_double, _vp, _vp, _vp, _vp])
 vrt_formal_solution = _sig("vrt_formal_solution", _st, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
                                                         _vp, _vp, _vp, _vp])
+vrt_formal_solution_ld = _sig("vrt_formal_solution_ld", _st, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                              ctypes.c_int64, _vp, _vp, _vp, _vp, _vp, _vp])
 vrt_formal_solution_noalloc = _sig("vrt_formal_solution_noalloc", _st, [_vp, ctypes.c_int32, ctypes.c_int32, _vp,
                                                                         _vp, _vp, _vp, _vp])
 vrt_two_level_solve = _sig("vrt_two_level_solve", _st, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _d, _vp,
@@ -375,32 +379,72 @@ def _need(t, shape, dtype, name):
         raise ValueError(f"{name} must be contiguous")
 
 
+def row_stride(tensors, shape, dtype):
+    """The common row stride (elements) of [n, nl] tensors whose rows are
+    unit-stride and do not overlap (None entries are skipped): views such as
+    cs[:, 0] and cs[:, 1] of one [n, 2, nl] array, whose rows lie 2 nl apart.
+    Raises ValueError for another shape or dtype, a non-unit element stride,
+    overlapping rows or strides that differ between the tensors."""
+    n, nl = shape
+    ld = None
+    for t, name in tensors:
+        if t is None:
+            continue
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+        if t.dtype != dtype:
+            raise ValueError(f"{name} has dtype {t.dtype}, expected {dtype}")
+        if nl > 1 and t.stride(1) != 1:
+            raise ValueError(f"{name}: the entries of a row must be adjacent")
+        r = t.stride(0) if n > 1 else nl
+        if r < nl:
+            raise ValueError(f"{name}: rows {r} apart overlap rows of {nl} entries")
+        if ld is not None and r != ld:
+            raise ValueError(f"{name}: rows {r} apart, the other inputs' rows {ld} apart")
+        ld = r
+    return nl if ld is None else ld
+
+
+def _rows_ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
 def lte_continuum(grid: Grid, lam, kappa0, T, rho, chi, S):
-    """chi = kappa0 rho^2 T^9, S = B_lambda(T) into device tensors chi, S [n, nl] (their dtype sets the precision)."""
+    """chi = kappa0 rho^2 T^9, S = B_lambda(T) into device tensors chi, S [n, nl]
+    (their dtype sets the precision). chi and S may be row-strided views with a
+    common row stride, e.g. cs[:, 0] and cs[:, 1] of one [n, 2, nl] array."""
     import torch
 
     lam = np.ascontiguousarray(np.atleast_1d(lam), np.float64)
     n = grid.info()["n_sites"]
     _need(T, (n,), torch.float64, "T")
     _need(rho, (n,), torch.float64, "rho")
-    _need(chi, (n, len(lam)), chi.dtype, "chi")
-    _need(S, (n, len(lam)), chi.dtype, "S")
-    grid.ctx.check(vrt_lte_continuum(grid.handle, _prec_of(chi), len(lam), _p(lam, _d), float(kappa0), _dev(T),
-                                     _dev(rho), _dev(chi), _dev(S)))
+    ld = row_stride(((chi, "chi"), (S, "S")), (n, len(lam)), chi.dtype)
+    grid.ctx.check(vrt_lte_continuum_ld(grid.handle, _prec_of(chi), len(lam), int(ld), _p(lam, _d), float(kappa0),
+                                        _dev(T), _dev(rho), _rows_ptr(chi), _rows_ptr(S)))
 
 
 def formal_solution(grid: Grid, chi, S, J, I_bottom=None, I_top=None, I_rays=None, exec_mode=VRT_EXEC_BATCHED):
-    """Formal solution of every ray and J (device tensors [n, nl]; I_rays [R, n, nl] optional)."""
+    """Formal solution of every ray and J (device tensors [n, nl]; I_rays [R, n,
+    nl] optional). The inputs chi, S, I_bottom and I_top may be row-strided views
+    with one common row stride (vrt_formal_solution_ld), e.g. chi = cs[:, 0] and
+    S = cs[:, 1] of one [n, 2, nl] array; J and I_rays are contiguous."""
     inf = grid.info()
     n, R = inf["n_sites"], inf["n_rays"]
     if chi.dim() != 2:
         raise ValueError("chi must be [n_sites, n_lambda]")
     nl = chi.shape[1]
-    for t, name in ((chi, "chi"), (S, "S"), (J, "J"), (I_bottom, "I_bottom"), (I_top, "I_top")):
-        _need(t, (n, nl), chi.dtype, name)
+    ld = row_stride(((chi, "chi"), (S, "S"), (I_bottom, "I_bottom"), (I_top, "I_top")), (n, nl), chi.dtype)
+    _need(J, (n, nl), chi.dtype, "J")
     _need(I_rays, (R, n, nl), chi.dtype, "I_rays")
-    grid.ctx.check(vrt_formal_solution(grid.handle, _prec_of(chi), int(exec_mode), int(nl), _dev(chi), _dev(S),
-                                       _dev(I_bottom), _dev(I_top), _dev(J), _dev(I_rays)))
+    if ld == nl:
+        grid.ctx.check(vrt_formal_solution(grid.handle, _prec_of(chi), int(exec_mode), int(nl), _rows_ptr(chi),
+                                           _rows_ptr(S), _rows_ptr(I_bottom), _rows_ptr(I_top), _dev(J),
+                                           _dev(I_rays)))
+    else:
+        grid.ctx.check(vrt_formal_solution_ld(grid.handle, _prec_of(chi), int(exec_mode), int(nl), int(ld),
+                                              _rows_ptr(chi), _rows_ptr(S), _rows_ptr(I_bottom), _rows_ptr(I_top),
+                                              _dev(J), _dev(I_rays)))
 
 
 def formal_solution_noalloc(grid: Grid, chi, S, J, I_bottom=None, I_top=None):

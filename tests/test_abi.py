@@ -115,3 +115,31 @@ def test_empty_grid_is_valid(v):
 def test_null_arguments(v):
     st, _ = v.validate_voronoi(3, None, None, None, None, None, np.zeros(3), np.ones(3), True)
     assert st == v.VRT_E_ARG
+
+
+def test_row_stride_of_strided_views(v):
+    """The binding passes chi / S / boundary views with one common row stride
+    to vrt_formal_solution_ld: paired slots of one [n][2][nl] array give 2 nl,
+    contiguous arrays nl; other element strides, overlapping rows and unequal
+    strides are refused before any call."""
+    torch = pytest.importorskip("torch")
+    n, nl = 5, 6
+    f = torch.float32
+    cs = torch.zeros((n, 2, nl), dtype=f)
+    assert v.row_stride(((cs[:, 0], "chi"), (cs[:, 1], "S"), (None, "I_bottom")), (n, nl), f) == 2 * nl
+    a = torch.zeros((n, nl), dtype=f)
+    assert v.row_stride(((a, "chi"), (a.clone(), "S")), (n, nl), f) == nl
+    wide = torch.zeros((n, nl + 2), dtype=f)
+    assert v.row_stride(((wide[:, :nl], "chi"),), (n, nl), f) == nl + 2
+    # one site: any stride is a valid layout
+    assert v.row_stride(((cs[:1, 0], "chi"),), (1, nl), f) == nl
+    with pytest.raises(ValueError, match="adjacent"):
+        v.row_stride(((a.t().contiguous().t(), "chi"),), (n, nl), f)
+    with pytest.raises(ValueError, match="overlap"):
+        v.row_stride(((torch.zeros(n + nl, dtype=f).as_strided((n, nl), (1, 1)), "chi"),), (n, nl), f)
+    with pytest.raises(ValueError, match="apart"):
+        v.row_stride(((cs[:, 0], "chi"), (a, "S")), (n, nl), f)
+    with pytest.raises(ValueError, match="shape"):
+        v.row_stride(((a[:, :3], "chi"),), (n, nl), f)
+    with pytest.raises(ValueError, match="dtype"):
+        v.row_stride(((a.double(), "chi"),), (n, nl), f)

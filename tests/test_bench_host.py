@@ -46,11 +46,14 @@ def test_persistent_counters_match_layout_and_sources():
         raw = e["raw_kib_per_launch"]
         assert got == pytest.approx(1024 * (raw["fetch"] * rec["fetch_scale"] + raw["write"] * rec["write_scale"]),
                                     rel=1e-4)
-    # another workload, layout or launch mode has no measured traffic
-    assert bench.counter_traffic(64, 262144, "persistent", {"shared_levels": 0, "interleave": 1}) is None
-    assert bench.counter_traffic(64, 262144, "persistent", {"shared_levels": 1, "interleave": 0}) is None
-    assert bench.counter_traffic(32, 262144, "persistent", {"shared_levels": 1, "interleave": 1}) is None
-    assert bench.counter_traffic(64, 1048576, "persistent", {"shared_levels": 1, "interleave": 1}) is None
+    # another workload, layout, row layout or launch mode has no measured traffic
+    lay = dict(rec["entries"][0]["layout"])
+    assert bench.counter_traffic(64, 262144, "persistent", dict(lay, shared_levels=0)) is None
+    assert bench.counter_traffic(64, 262144, "persistent", dict(lay, interleave=0)) is None
+    other_rows = "separate" if lay.get("rows", "separate") == "paired" else "paired"
+    assert bench.counter_traffic(64, 262144, "persistent", dict(lay, rows=other_rows)) is None
+    assert bench.counter_traffic(32, 262144, "persistent", lay) is None
+    assert bench.counter_traffic(64, 1048576, "persistent", lay) is None
 
 
 def test_counters_are_dropped_when_the_sources_change(tmp_path, monkeypatch):
@@ -86,7 +89,8 @@ def test_level_step_counters_match_the_whole_layout(workload):
     if updates:
         alg = bench.sweep_bytes_per_update(101, 4) * 104 / 101 * updates
         assert got > alg
-    for key, other in (("pipeline", 0), ("interleave", 1), ("shared_levels", 0), ("xcd_chunks", 0)):
+    for key, other in (("pipeline", 0), ("interleave", 1), ("shared_levels", 0), ("xcd_chunks", 0),
+                       ("rows", "separate" if lay.get("rows") == "paired" else "paired")):
         changed = dict(lay, **{key: other})
         assert bench.lambda_counter_traffic(workload, "graph", changed) is None, key
     assert bench.lambda_counter_traffic(workload, "persistent", lay) is None

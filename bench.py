@@ -1070,10 +1070,19 @@ def lambda_block(workload, max_iter=None, accel_iter=None, mode_pref="auto", int
     del chi, S, J, chi_t, S_t
     if rows == "paired":
         del cs
+    torch.cuda.empty_cache()  # the library allocates the iteration's scratch itself
     log(f"{workload}: formal solution (ms by launch mode): {fs_by_mode} -> {mode_name}: {fs_ms:.3f} ms, "
         f"{upd_s:.3e} updates/s; sweep {sweep_ms:.3f} ms ({sweep_gbs:.0f} GB/s own bytes), J {jr_one:.3f} ms")
 
-    # plain iterations (timing) and the accelerated iteration to convergence
+    # plain iterations (timing) and the accelerated iteration to convergence,
+    # after one untimed iteration that allocates the iteration's scratch (an
+    # allocation right after large frees can wait while the device clears the
+    # freed memory: a one-time cost that is not an iteration's)
+    S_w = B.clone()
+    v.two_level_solve_batched(G, off, wlam, phi, chi_L, chi_c, B, eps, S_w, max_iter=1, tol=0.0, sweep_dtype=f32,
+                              exec_mode=modes[mode_name])
+    torch.cuda.synchronize()
+    del S_w
     res_it = {}
     for name, acc, cap in (("plain", False, max_iter), ("accelerated", True, accel_iter)):
         if not cap:

@@ -1178,11 +1178,31 @@ vrt_status two_level_solve(vrt_grid g, vrt_exec ex, int32_t nl, const double *wl
   const int32_t ld = (nl + per16 - 1) / per16 * per16;
   const size_t nn = (size_t)g->n * (size_t)ld;
   ++g->solution_id;  // from here on the last solution's rows may be overwritten
-  T *I = intensity_buffer<T>(g, ld, nullptr);
   VRT_HIP(hipStreamSynchronize(s));  // earlier work may still read the buffers replaced below
+  // The sign-encoded rows of persistent formal solutions are neither read nor
+  // written by the iteration, and the last solution's rows are being replaced:
+  // when the device is out of memory for the iteration's scratch, their block
+  // goes back to it (a later persistent solution allocates and refills it).
+  auto fit = [&](auto &&allocate) {
+    try {
+      allocate();
+    } catch (const vrt::Error &e) {
+      if (e.code != VRT_E_NOMEM || !g->d_Isgn.p) throw;
+      (void)hipGetLastError();  // the failed allocation is handled here: later launch checks must not see it
+      g->d_Isgn.release();
+      for (int k = 0; k < 4; ++k) g->sgn_key[k] = 0;
+      if (g->last_abs) {
+        g->last_I = nullptr;  // the rows it pointed to are gone
+        g->last_abs = false;
+      }
+      allocate();
+    }
+  };
+  T *I = nullptr;
+  fit([&] { I = intensity_buffer<T>(g, ld, nullptr); });
   // chi and S rows paired, 2 ld apart; the bottom boundary rows (B) at the same stride
-  g->d_nchi.alloc(2 * nn * sizeof(T));
-  g->d_nIb.alloc(2 * nn * sizeof(T));
+  fit([&] { g->d_nchi.alloc(2 * nn * sizeof(T)); });
+  fit([&] { g->d_nIb.alloc(2 * nn * sizeof(T)); });
   g->d_jbar.alloc((size_t)g->n * 8);
   g->d_dS.alloc((size_t)n_atm * 8);
   g->d_atm_ptr.alloc((size_t)(n_atm + 1) * 8);
@@ -1878,6 +1898,18 @@ vrt_status vrt_grid_autotune(vrt_grid g, vrt_prec prec, int32_t n_lambda, const 
     g->tuned_exec = bs.exec;
     if (bs.il && g->interleaved_built != bs.il) build_interleaved(g);
     g->drop_graphs();
+    // the sign-encoded rows the persistent candidates used: when the persistent
+    // sweep is not the choice, their block goes back to the device (a later
+    // persistent solution allocates and refills it)
+    if (bs.exec != VRT_EXEC_PERSISTENT && g->d_Isgn.p) {
+      VRT_HIP(hipStreamSynchronize(s));
+      g->d_Isgn.release();
+      for (int k = 0; k < 4; ++k) g->sgn_key[k] = 0;
+      if (g->last_abs) {
+        g->last_I = nullptr;  // the rows it pointed to are gone
+        g->last_abs = false;
+      }
+    }
     char buf[352];
     snprintf(buf, sizeof buf,
              "], \"chosen\": {\"exec\": \"%s\", \"record_order\": %d, \"shared_levels\": %d, \"xcd_chunks\": %d, "

@@ -300,7 +300,10 @@ vrt_status vrt_grid_tune(vrt_grid grid, int32_t knob, int64_t value);
  * the persistent sweep) is reported with "ms": null and skipped. On a regular
  * grid the candidates are the graph-launched plane steps with the row kernel
  * and with the LDS-tiled kernel (VRT_TUNE_REGULAR_TILE 0 and 1).
- * Re-packs the sweep records when the record order changes. Blocks. */
+ * Re-packs the sweep records when the record order changes. When the choice
+ * is not the persistent sweep, the library's sign-encoded intensity rows that
+ * its candidates used are freed (n_rays x n x n_lambda elements; a later
+ * persistent solution allocates them again). Blocks. */
 vrt_status vrt_grid_autotune(vrt_grid grid, vrt_prec prec, int32_t n_lambda, const void *chi,
                              const void *S, const void *I_bottom, const void *I_top, void *J,
                              void *I_rays, int32_t reps, char *report, int64_t report_len);
@@ -500,7 +503,10 @@ vrt_status vrt_lte_continuum_vjp(vrt_grid grid, vrt_prec prec, int32_t n_lambda,
  * bottom boundary of upward rays is thermalised (I = B), the top is empty.
  * The formal solutions run in `sweep_prec` with `exec` (VRT_EXEC_GRAPH
  * captures one iteration and replays it); assembly, Jbar, the update and the
- * convergence test are double precision.
+ * convergence test are double precision. The library's scratch holds each
+ * site's chi and S rows side by side (rows of n_lambda rounded up to 16 bytes)
+ * and the per-ray intensities; if the device cannot hold it beside the
+ * sign-encoded rows of earlier persistent formal solutions, those are freed.
  *   wlam      host [n_lambda] quadrature weights of the profile.
  *   phi       device [n][n_lambda] double, profile with sum_l wlam phi = 1.
  *   chi_line, chi_cont, B   device [n] double.

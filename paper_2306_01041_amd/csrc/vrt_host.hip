@@ -1352,17 +1352,17 @@ void formal_solution(vrt_grid g, vrt_exec ex, int32_t nl, const void *chi_, cons
     }
     if (it == g->graphs.end()) {
       if (!ctx->capture_stream) VRT_HIP(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
-      hipStream_t cs_ = ctx->capture_stream;
-      VRT_HIP(hipStreamBeginCapture(cs_, hipStreamCaptureModeThreadLocal));
+      hipStream_t cap_s = ctx->capture_stream;
+      VRT_HIP(hipStreamBeginCapture(cap_s, hipStreamCaptureModeThreadLocal));
       hipGraph_t graph = nullptr;
       try {
-        enqueue_fs<T>(g, cs_, VRT_EXEC_BATCHED, nl, chi, S, Ib, It, J, I, false, cs);
+        enqueue_fs<T>(g, cap_s, VRT_EXEC_BATCHED, nl, chi, S, Ib, It, J, I, false, cs);
       } catch (...) {
-        (void)hipStreamEndCapture(cs_, &graph);
+        (void)hipStreamEndCapture(cap_s, &graph);
         if (graph) (void)hipGraphDestroy(graph);
         throw;
       }
-      VRT_HIP(hipStreamEndCapture(cs_, &graph));
+      VRT_HIP(hipStreamEndCapture(cap_s, &graph));
       hipGraphExec_t exec = nullptr;
       hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
